@@ -1,0 +1,117 @@
+"""Seeded synthetic workloads (no sampler arithmetic lives here).
+
+Shapes and distributions follow the synthetic experiments of Sec. 5 (Gaussian
+mixtures with random means and Wishart covariances; multinomial mixtures with
+Dirichlet topics) at the sizes of the five standard workloads below.  Data
+are drawn with numpy's PCG64 from the given seed, so the oracle and the GPU
+path can be fed identical inputs.
+
+Workloads
+---------
+gauss_d2      N=1e4, d=2, 6 Gaussians, means U[-10,10]^2, covariances
+              Wishart(4, I), equal weights.
+gauss_d32     N=1e6, d=32, 20 Gaussians, means N(0, 25 I), covariances
+              Wishart(d+2, I/d), weights Dirichlet(1).
+mult_v100     N=1e6 count vectors, V=100, 50 topics Dirichlet(0.1), row
+              totals uniform in [50, 200], equal weights.
+gauss_d128    N=1e7, d=128, 100 Gaussians, means N(0, 9 I), covariances
+              Wishart(d+2, I/d), weights Dirichlet(1).
+gauss_d64     N=2e6, d=64, 200 overlapping Gaussians, means N(0, 4 I),
+              covariances Wishart(d+2, I/d), weights Dirichlet(1).
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class GaussianSpec:
+    n: int
+    d: int
+    k: int
+    mean_kind: str      # "uniform" (half-width mean_scale) or "normal" (std mean_scale)
+    mean_scale: float
+    wishart_dof: float  # covariance ~ Wishart(dof, wishart_scale * I)
+    wishart_scale: float
+    weights: str        # "equal" or "dirichlet1"
+
+
+@dataclass
+class MultinomialSpec:
+    n: int
+    v: int
+    k: int
+    topic_conc: float
+    total_lo: int
+    total_hi: int
+
+
+WORKLOADS = {
+    "gauss_d2": GaussianSpec(10_000, 2, 6, "uniform", 10.0, 4.0, 1.0, "equal"),
+    "gauss_d32": GaussianSpec(1_000_000, 32, 20, "normal", 5.0, 34.0, 1.0 / 32, "dirichlet1"),
+    "mult_v100": MultinomialSpec(1_000_000, 100, 50, 0.1, 50, 200),
+    "gauss_d128": GaussianSpec(10_000_000, 128, 100, "normal", 3.0, 130.0, 1.0 / 128, "dirichlet1"),
+    "gauss_d64": GaussianSpec(2_000_000, 64, 200, "normal", 2.0, 66.0, 1.0 / 64, "dirichlet1"),
+}
+
+
+def _wishart(rng, dof, scale, d):
+    """Wishart(dof, scale * I) as a sum of outer products (integer dof) or
+    via Bartlett's factor (any dof > d - 1)."""
+    A = np.zeros((d, d))
+    for i in range(d):
+        A[i, i] = np.sqrt(rng.chisquare(dof - i))
+        A[i, :i] = rng.standard_normal(i)
+    return scale * (A @ A.T)
+
+
+def gaussian_params(spec, seed):
+    """True mixture: weights[k], means[k, d], covariances[k, d, d]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d, k = spec.d, spec.k
+    if spec.mean_kind == "uniform":
+        means = rng.uniform(-spec.mean_scale, spec.mean_scale, size=(k, d))
+    else:
+        means = rng.normal(0.0, spec.mean_scale, size=(k, d))
+    covs = np.stack([_wishart(rng, spec.wishart_dof, spec.wishart_scale, d) for _ in range(k)])
+    if spec.weights == "equal":
+        w = np.full(k, 1.0 / k)
+    else:
+        w = rng.dirichlet(np.ones(k))
+    return w, means, covs
+
+
+def gaussian_data(spec, seed, n=None, dtype=np.float32):
+    """x[n, d] (row-major, point-major) and the true labels."""
+    n = spec.n if n is None else int(n)
+    w, means, covs = gaussian_params(spec, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    labels = rng.choice(spec.k, size=n, p=w)
+    x = np.empty((n, spec.d), dtype=np.float64)
+    for c in range(spec.k):
+        idx = np.nonzero(labels == c)[0]
+        L = np.linalg.cholesky(covs[c])
+        x[idx] = means[c] + rng.standard_normal((idx.size, spec.d)) @ L.T
+    return x.astype(dtype), labels.astype(np.int32)
+
+
+def multinomial_data(spec, seed, n=None):
+    """Counts x[n, V] (int32, row totals in [lo, hi]) and the true labels."""
+    n = spec.n if n is None else int(n)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    topics = rng.dirichlet(np.full(spec.v, spec.topic_conc), size=spec.k)
+    rng2 = np.random.Generator(np.random.PCG64(seed + 1))
+    labels = rng2.integers(0, spec.k, size=n)
+    totals = rng2.integers(spec.total_lo, spec.total_hi + 1, size=n)
+    x = np.empty((n, spec.v), dtype=np.int32)
+    for c in range(spec.k):
+        idx = np.nonzero(labels == c)[0]
+        x[idx] = rng2.multinomial(totals[idx], topics[c])
+    return x, labels.astype(np.int32)
+
+
+def workload(name, seed, n=None):
+    spec = WORKLOADS[name]
+    if isinstance(spec, GaussianSpec):
+        return gaussian_data(spec, seed, n)
+    return multinomial_data(spec, seed, n)
