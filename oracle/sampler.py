@@ -223,9 +223,16 @@ def loglik(model, x, params):
     return lc, ls
 
 
-def gumbels(seed, t, N, K, point_offset=0):
-    """g[i, k] for i < N, k < K: block k // 4, word k % 4 of (i, t, TAG_GUMBEL)."""
-    i = np.arange(N, dtype=np.uint64) + np.uint64(point_offset)
+def _points(N, point_offset, points):
+    if points is not None:
+        return np.asarray(points, dtype=np.uint64)
+    return np.arange(N, dtype=np.uint64) + np.uint64(point_offset)
+
+
+def gumbels(seed, t, N, K, point_offset=0, points=None):
+    """g[i, k] for i < N, k < K: block k // 4, word k % 4 of (i, t, TAG_GUMBEL).
+    `points` gives the point indices (entities) of the rows, if not 0..N-1."""
+    i = _points(N, point_offset, points)
     g = np.zeros((N, K))
     for b in range((K + 3) // 4):
         w = rng.block(seed, t, i, rng.TAG_GUMBEL, b)
@@ -236,28 +243,28 @@ def gumbels(seed, t, N, K, point_offset=0):
     return g
 
 
-def logistics(seed, t, N, point_offset=0):
-    i = np.arange(N, dtype=np.uint64) + np.uint64(point_offset)
+def logistics(seed, t, N, point_offset=0, points=None):
+    i = _points(N, point_offset, points)
     return rng.logistic(rng.block(seed, t, i, rng.TAG_LOGISTIC, 0)[0])
 
 
-def draw_labels(seed, t, lc, ls, point_offset=0):
+def draw_labels(seed, t, lc, ls, point_offset=0, points=None):
     """Gumbel-max draw of z (eq. sample_labels) and the logistic draw of the
     sub-label (eq. sample_sub_labels): z = argmax_k lc + g; sub-label l iff
     ls[z, l] - ls[z, r] + L > 0."""
     N, K = lc.shape
-    g = gumbels(seed, t, N, K, point_offset)
+    g = gumbels(seed, t, N, K, point_offset, points)
     z = np.argmax(lc + g, axis=1)
     idx = np.arange(N)
     delta = ls[idx, z, 0] - ls[idx, z, 1]
-    L = logistics(seed, t, N, point_offset)
+    L = logistics(seed, t, N, point_offset, points)
     zsub = np.where(delta + L > 0, 0, 1)
     return z.astype(np.int64), zsub.astype(np.int64)
 
 
-def sample_labels(model, x, params, t, point_offset=0):
+def sample_labels(model, x, params, t, point_offset=0, points=None):
     lc, ls = loglik(model, x, params)
-    return draw_labels(model.seed, t, lc, ls, point_offset)
+    return draw_labels(model.seed, t, lc, ls, point_offset, points)
 
 
 # ----------------------------------------------------------------------------

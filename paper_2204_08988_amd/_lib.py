@@ -1,0 +1,93 @@
+"""ctypes declarations of the C ABI in include/dpmm.h.
+
+Loads paper_2204_08988_amd/libdpmm.so (built in-tree by build.py).  There is
+no fallback: if the library is missing or does not load, every entry point
+raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpmm.so")
+
+DPMM_OK = 0
+STATUS = {0: "DPMM_OK", -1: "DPMM_E_ARG", -2: "DPMM_E_SHAPE", -3: "DPMM_E_CAPACITY",
+          -4: "DPMM_E_NUMERIC", -5: "DPMM_E_DEVICE", -6: "DPMM_E_OOM", -7: "DPMM_E_STATE"}
+GAUSSIAN, MULTINOMIAL = 0, 1
+FP32, BF16, BF16X3 = 0, 1, 2
+MERGE_PAPER, MERGE_INVERSE_SPLIT = 0, 1
+
+# every symbol include/dpmm.h declares
+EXPORTS = [
+    "dpmm_create", "dpmm_destroy", "dpmm_last_error", "dpmm_status_string", "dpmm_init_labels",
+    "dpmm_set_state", "dpmm_get_state", "dpmm_set_params", "dpmm_get_params", "dpmm_set_stats",
+    "dpmm_get_stats", "dpmm_loglik", "dpmm_sample_labels", "dpmm_suffstats", "dpmm_sample_params",
+    "dpmm_split_merge", "dpmm_step",
+]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("family", ctypes.c_int32), ("d", ctypes.c_int32), ("k_max", ctypes.c_int32),
+        ("burn_out", ctypes.c_int32), ("alpha", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("nu", ctypes.c_double), ("m", ctypes.POINTER(ctypes.c_double)),
+        ("psi", ctypes.POINTER(ctypes.c_double)), ("beta", ctypes.POINTER(ctypes.c_double)),
+        ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32), ("merge_form", ctypes.c_int32),
+    ]
+
+
+class IterInfo(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_int32), ("splits", ctypes.c_int32), ("merges", ctypes.c_int32),
+        ("removed", ctypes.c_int32), ("logpost", ctypes.c_double), ("ms_params", ctypes.c_float),
+        ("ms_labels", ctypes.c_float), ("ms_stats", ctypes.c_float), ("ms_splitmerge", ctypes.c_float),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2204_08988_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "dpmm_create": ([ctypes.POINTER(Config), vp, ctypes.POINTER(vp)], i32),
+        "dpmm_destroy": ([vp], None),
+        "dpmm_last_error": ([vp], ctypes.c_char_p),
+        "dpmm_status_string": ([i32], ctypes.c_char_p),
+        "dpmm_init_labels": ([vp, i64, vp, vp], i32),
+        "dpmm_set_state": ([vp, i32, ctypes.POINTER(i32)], i32),
+        "dpmm_get_state": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "dpmm_set_params": ([vp, i32, dp, dp, dp], i32),
+        "dpmm_get_params": ([vp, dp, dp, dp], i32),
+        "dpmm_set_stats": ([vp, i32, vp], i32),
+        "dpmm_get_stats": ([vp, vp], i32),
+        "dpmm_loglik": ([vp, vp, i64, vp], i32),
+        "dpmm_sample_labels": ([vp, vp, i64, u32, vp, vp], i32),
+        "dpmm_suffstats": ([vp, vp, i64, vp, vp], i32),
+        "dpmm_sample_params": ([vp, u32], i32),
+        "dpmm_split_merge": ([vp, vp, i64, u32, vp, vp, ctypes.POINTER(IterInfo)], i32),
+        "dpmm_step": ([vp, vp, i64, u32, vp, vp, ctypes.POINTER(IterInfo)], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+class DpmmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status

@@ -1,0 +1,772 @@
+// Host runtime of the DPMM HIP library: the C ABI declared in include/dpmm.h.
+//
+// The context owns every device table sized by k_max; the caller owns the
+// data and the labels.  Per iteration the device does all O(N) work (labels,
+// statistics, relabelling) and all float64 linear algebra (posterior draws,
+// marginal likelihoods); the host only runs the O(K^2) accept/reject
+// bookkeeping of splits and merges on a few hundred doubles read back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <memory>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dpmm.h"
+#include "kernels.hpp"
+
+using namespace dpmm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct dpmm_ctx {
+  dpmm_config cfg{};
+  std::vector<double> m, psi, beta, lgamma_beta;
+  double logdet_psi = 0.0, beta_sum = 0.0, lgamma_beta_sum = 0.0;
+  hipStream_t stream = nullptr;
+  int K = 0;
+  std::vector<int> age;
+  bool have_params = false;
+  bool have_stats = false;
+  std::string err;
+  int d = 0, E = 0, stride = 0;
+  std::vector<DevBuf> bufs;
+  // device tables
+  double *d_m = nullptr, *d_psi = nullptr, *d_beta = nullptr, *d_lgamma_beta = nullptr;
+  long long* d_counts = nullptr;  // [2 k_max]
+  double* d_moments = nullptr;    // Gaussian [2 k_max][E]
+  long long* d_sums = nullptr;    // multinomial [2 k_max][V]
+  double *d_log_pi = nullptr, *d_log_pisub = nullptr, *d_tmp = nullptr;
+  double *d_mu = nullptr, *d_sigma = nullptr, *d_log_theta = nullptr, *d_logdet = nullptr;
+  float* d_packed = nullptr;
+  double* d_scratch = nullptr;  // NIW_SCRATCH(d) per workgroup slot
+  int scratch_slots = 0;
+  int* d_err = nullptr;
+  LogmlItem* d_items = nullptr;
+  double* d_logml = nullptr;
+  int items_cap = 0;
+  RelabelEntry* d_table = nullptr;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+
+  dpmm_status fail(dpmm_status s, const std::string& msg) {
+    err = msg;
+    return s;
+  }
+  dpmm_status hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return DPMM_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? DPMM_E_OOM : DPMM_E_DEVICE;
+  }
+  template <typename T>
+  hipError_t alloc(T** p, size_t count) {
+    DevBuf b;
+    b.bytes = std::max<size_t>(count * sizeof(T), 16);
+    hipError_t e = hipMalloc(&b.p, b.bytes);
+    if (e != hipSuccess) return e;
+    bufs.push_back(b);
+    *p = static_cast<T*>(b.p);
+    return hipSuccess;
+  }
+  bool gaussian() const { return cfg.family == DPMM_GAUSSIAN; }
+};
+
+#define DPMM_TRY(expr)                         \
+  do {                                         \
+    dpmm_status _s = (expr);                   \
+    if (_s != DPMM_OK) return _s;              \
+  } while (0)
+#define DPMM_HIP(ctx, expr, what) DPMM_TRY((ctx)->hip((expr), (what)))
+
+namespace {
+
+bool host_cholesky_logdet(std::vector<double> a, int d, double* logdet) {
+  for (int j = 0; j < d; ++j) {
+    double s = a[j * d + j];
+    for (int k = 0; k < j; ++k) s -= a[j * d + k] * a[j * d + k];
+    if (!(s > 0.0) || !std::isfinite(s)) return false;
+    a[j * d + j] = std::sqrt(s);
+    for (int i = j + 1; i < d; ++i) {
+      double t = a[i * d + j];
+      for (int k = 0; k < j; ++k) t -= a[i * d + k] * a[j * d + k];
+      a[i * d + j] = t / a[j * d + j];
+    }
+  }
+  double ld = 0.0;
+  for (int j = 0; j < d; ++j) ld += std::log(a[j * d + j]);
+  *logdet = 2.0 * ld;
+  return true;
+}
+
+inline int tri_index(int a, int b, int d) { return a * d - (a * (a - 1)) / 2 + (b - a); }
+
+dpmm_status check_n(dpmm_ctx* ctx, const void* x, int64_t n) {
+  if (!x && n > 0) return ctx->fail(DPMM_E_ARG, "x is NULL");
+  if (n < 0 || n > (int64_t)0xFFFFFFFFLL) return ctx->fail(DPMM_E_SHAPE, "n must lie in [0, 2^32)");
+  return DPMM_OK;
+}
+
+NiwPriorDev prior_dev(dpmm_ctx* ctx) {
+  NiwPriorDev p;
+  p.kappa = ctx->cfg.kappa;
+  p.nu = ctx->cfg.nu;
+  p.m = ctx->d_m;
+  p.psi = ctx->d_psi;
+  return p;
+}
+
+dpmm_status launch_stats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub) {
+  hipError_t e;
+  if (ctx->gaussian())
+    e = launch_stats_gauss(ctx->d, (const float*)x, n, z, zsub, ctx->K, ctx->d_counts, ctx->d_moments, ctx->stream);
+  else
+    e = launch_stats_mult(ctx->d, (const int*)x, n, z, zsub, ctx->K, ctx->d_counts, ctx->d_sums, ctx->stream);
+  DPMM_HIP(ctx, e, "statistics kernel");
+  ctx->have_stats = true;
+  return DPMM_OK;
+}
+
+// log marginal likelihoods of a list of segment unions (device), read back.
+dpmm_status logml(dpmm_ctx* ctx, const std::vector<LogmlItem>& items, std::vector<double>& out) {
+  out.assign(items.size(), 0.0);
+  size_t done = 0;
+  while (done < items.size()) {
+    const int nb = (int)std::min<size_t>(items.size() - done, (size_t)ctx->items_cap);
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_items, items.data() + done, nb * sizeof(LogmlItem), hipMemcpyHostToDevice,
+                                 ctx->stream), "copy items");
+    hipError_t e;
+    if (ctx->gaussian())
+      e = launch_logml_gauss(nb, ctx->d_items, ctx->d, prior_dev(ctx), ctx->logdet_psi, ctx->d_counts,
+                             ctx->d_moments, ctx->d_scratch, ctx->d_logml, ctx->d_err, ctx->stream);
+    else
+      e = launch_logml_mult(nb, ctx->d_items, ctx->d, ctx->d_beta, ctx->beta_sum, ctx->lgamma_beta_sum,
+                            ctx->d_lgamma_beta, ctx->d_counts, ctx->d_sums, ctx->d_logml, ctx->stream);
+    DPMM_HIP(ctx, e, "log marginal likelihood kernel");
+    DPMM_HIP(ctx, hipMemcpyAsync(out.data() + done, ctx->d_logml, nb * sizeof(double), hipMemcpyDeviceToHost,
+                                 ctx->stream), "copy log marginals");
+    DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    done += nb;
+  }
+  return DPMM_OK;
+}
+
+dpmm_status read_counts(dpmm_ctx* ctx, std::vector<long long>& cnt) {
+  cnt.assign(2 * (size_t)ctx->K, 0);
+  DPMM_HIP(ctx, hipMemcpyAsync(cnt.data(), ctx->d_counts, cnt.size() * sizeof(long long), hipMemcpyDeviceToHost,
+                               ctx->stream), "copy counts");
+  DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  return DPMM_OK;
+}
+
+dpmm_status check_device_error(dpmm_ctx* ctx) {
+  int flag = 0;
+  DPMM_HIP(ctx, hipMemcpyAsync(&flag, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "copy flag");
+  DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  if (flag) {
+    DPMM_HIP(ctx, hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream), "clear flag");
+    return ctx->fail(DPMM_E_NUMERIC, "a float64 Cholesky factorisation met a non-positive pivot (flag " +
+                                         std::to_string(flag) + ")");
+  }
+  return DPMM_OK;
+}
+
+dpmm_status apply_relabel(dpmm_ctx* ctx, const std::vector<RelabelEntry>& table, int64_t n, uint32_t t,
+                          int32_t* z, uint8_t* zsub) {
+  DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_table, table.data(), table.size() * sizeof(RelabelEntry),
+                               hipMemcpyHostToDevice, ctx->stream), "copy relabel table");
+  DPMM_HIP(ctx, launch_relabel(n, ctx->d_table, (int)table.size(), t, ctx->cfg.seed, z, zsub, ctx->stream),
+           "relabel kernel");
+  return DPMM_OK;
+}
+
+double log_posterior(const dpmm_ctx* ctx, const std::vector<long long>& cnt, const std::vector<double>& lml) {
+  const double a = ctx->cfg.alpha;
+  long long N = 0;
+  for (long long c : cnt) N += c;
+  double lp = ctx->K * std::log(a) + std::lgamma(a) - std::lgamma(a + (double)N);
+  for (int k = 0; k < ctx->K; ++k) lp += std::lgamma((double)(cnt[2 * k] + cnt[2 * k + 1])) + lml[k];
+  return lp;
+}
+
+dpmm_status pack_params(dpmm_ctx* ctx) {
+  const int K = ctx->K;
+  if (ctx->gaussian()) {
+    hipLaunchKernelGGL(k_pack_gauss, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->cfg.k_max,
+                       ctx->d_log_pi, ctx->d_log_pisub, ctx->d_mu, ctx->d_sigma, ctx->d_scratch, ctx->d_packed,
+                       ctx->d_logdet, ctx->d_err);
+  } else {
+    hipLaunchKernelGGL(k_pack_mult, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->cfg.k_max,
+                       ctx->d_log_pi, ctx->d_log_pisub, ctx->d_log_theta, ctx->d_packed);
+  }
+  DPMM_HIP(ctx, hipGetLastError(), "pack kernel");
+  ctx->have_params = true;
+  return DPMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dpmm_status_string(dpmm_status s) {
+  switch (s) {
+    case DPMM_OK: return "ok";
+    case DPMM_E_ARG: return "invalid argument";
+    case DPMM_E_SHAPE: return "shape mismatch";
+    case DPMM_E_CAPACITY: return "capacity exceeded";
+    case DPMM_E_NUMERIC: return "numerical error";
+    case DPMM_E_DEVICE: return "device error";
+    case DPMM_E_OOM: return "out of device memory";
+    case DPMM_E_STATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+const char* dpmm_last_error(const dpmm_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return DPMM_E_ARG;
+  }
+  *out = nullptr;
+  auto bad = [](dpmm_status s, const char* msg) {
+    g_create_error = msg;
+    return s;
+  };
+  if (!cfg) return bad(DPMM_E_ARG, "cfg is NULL");
+  if (cfg->family != DPMM_GAUSSIAN && cfg->family != DPMM_MULTINOMIAL) return bad(DPMM_E_ARG, "unknown family");
+  if (cfg->family == DPMM_GAUSSIAN && (cfg->d < 1 || cfg->d > 128))
+    return bad(DPMM_E_ARG, "Gaussian dimension must lie in [1, 128]");
+  if (cfg->family == DPMM_MULTINOMIAL && (cfg->d < 1 || cfg->d > 128))
+    return bad(DPMM_E_ARG, "vocabulary size must lie in [1, 128]");
+  if (cfg->k_max < 1 || cfg->k_max > 4096) return bad(DPMM_E_ARG, "k_max must lie in [1, 4096]");
+  if (cfg->burn_out < 0) return bad(DPMM_E_ARG, "burn_out must be >= 0");
+  if (!(cfg->alpha > 0.0) || !std::isfinite(cfg->alpha)) return bad(DPMM_E_ARG, "alpha must be > 0");
+  if (cfg->precision != DPMM_FP32) return bad(DPMM_E_ARG, "only DPMM_FP32 scoring is available");
+  if (cfg->merge_form != DPMM_MERGE_PAPER && cfg->merge_form != DPMM_MERGE_INVERSE_SPLIT)
+    return bad(DPMM_E_ARG, "unknown merge_form");
+  const int d = cfg->d;
+  std::unique_ptr<dpmm_ctx> ctx(new dpmm_ctx());
+  ctx->cfg = *cfg;
+  ctx->d = d;
+  if (cfg->family == DPMM_GAUSSIAN) {
+    if (!(cfg->kappa > 0.0)) return bad(DPMM_E_ARG, "kappa must be > 0");
+    if (!(cfg->nu > d - 1)) return bad(DPMM_E_ARG, "nu must be > d - 1");
+    if (!cfg->m || !cfg->psi) return bad(DPMM_E_ARG, "m and psi are required");
+    ctx->m.assign(cfg->m, cfg->m + d);
+    ctx->psi.assign(cfg->psi, cfg->psi + (size_t)d * d);
+    for (double v : ctx->m)
+      if (!std::isfinite(v)) return bad(DPMM_E_NUMERIC, "m is not finite");
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j)
+        if (ctx->psi[i * d + j] != ctx->psi[j * d + i]) return bad(DPMM_E_NUMERIC, "psi is not symmetric");
+    if (!host_cholesky_logdet(ctx->psi, d, &ctx->logdet_psi)) return bad(DPMM_E_NUMERIC, "psi is not positive definite");
+    ctx->E = d + d * (d + 1) / 2;
+    ctx->stride = gauss_rec_stride(d);
+  } else {
+    if (!cfg->beta) return bad(DPMM_E_ARG, "beta is required");
+    ctx->beta.assign(cfg->beta, cfg->beta + d);
+    for (double b : ctx->beta) {
+      if (!(b > 0.0) || !std::isfinite(b)) return bad(DPMM_E_ARG, "beta must be > 0");
+      ctx->beta_sum += b;
+      ctx->lgamma_beta.push_back(std::lgamma(b));
+    }
+    ctx->lgamma_beta_sum = std::lgamma(ctx->beta_sum);
+    ctx->E = 0;
+    ctx->stride = mult_rec_stride(d);
+  }
+  ctx->cfg.m = ctx->cfg.psi = ctx->cfg.beta = nullptr;
+  ctx->stream = (hipStream_t)hip_stream;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return bad(DPMM_E_DEVICE, "no HIP device");
+  const int km = cfg->k_max;
+  dpmm_ctx* c = ctx.get();
+  auto chk = [&](hipError_t e) { return e == hipSuccess; };
+  bool ok = true;
+  ok = ok && chk(c->alloc(&c->d_counts, 2 * (size_t)km));
+  ok = ok && chk(c->alloc(&c->d_log_pi, (size_t)km + 1));
+  ok = ok && chk(c->alloc(&c->d_log_pisub, 2 * (size_t)km));
+  ok = ok && chk(c->alloc(&c->d_tmp, (size_t)km + 1));
+  ok = ok && chk(c->alloc(&c->d_logdet, 3 * (size_t)km));
+  ok = ok && chk(c->alloc(&c->d_packed, 3 * (size_t)km * c->stride));
+  ok = ok && chk(c->alloc(&c->d_err, 1));
+  ok = ok && chk(c->alloc(&c->d_table, 4 * (size_t)km));
+  c->items_cap = std::max(3 * km, 256);
+  ok = ok && chk(c->alloc(&c->d_items, (size_t)c->items_cap));
+  ok = ok && chk(c->alloc(&c->d_logml, (size_t)c->items_cap));
+  if (c->gaussian()) {
+    ok = ok && chk(c->alloc(&c->d_m, (size_t)d));
+    ok = ok && chk(c->alloc(&c->d_psi, (size_t)d * d));
+    ok = ok && chk(c->alloc(&c->d_moments, 2 * (size_t)km * c->E));
+    ok = ok && chk(c->alloc(&c->d_mu, 3 * (size_t)km * d));
+    ok = ok && chk(c->alloc(&c->d_sigma, 3 * (size_t)km * d * d));
+    c->scratch_slots = c->items_cap;
+    ok = ok && chk(c->alloc(&c->d_scratch, (size_t)c->scratch_slots * NIW_SCRATCH(d)));
+  } else {
+    ok = ok && chk(c->alloc(&c->d_beta, (size_t)d));
+    ok = ok && chk(c->alloc(&c->d_lgamma_beta, (size_t)d));
+    ok = ok && chk(c->alloc(&c->d_sums, 2 * (size_t)km * d));
+    ok = ok && chk(c->alloc(&c->d_log_theta, 3 * (size_t)km * d));
+  }
+  if (!ok) {
+    for (auto& b : c->bufs) hipFree(b.p);
+    return bad(DPMM_E_OOM, "device allocation failed");
+  }
+  hipError_t e = hipSuccess;
+  if (c->gaussian()) {
+    e = hipMemcpy(c->d_m, c->m.data(), d * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_psi, c->psi.data(), (size_t)d * d * sizeof(double), hipMemcpyHostToDevice);
+  } else {
+    e = hipMemcpy(c->d_beta, c->beta.data(), d * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(c->d_lgamma_beta, c->lgamma_beta.data(), d * sizeof(double), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMemset(c->d_err, 0, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(c->d_packed, 0, 3 * (size_t)km * c->stride * sizeof(float));
+  for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev[i]);
+  if (e != hipSuccess) {
+    for (auto& b : c->bufs) hipFree(b.p);
+    g_create_error = std::string("device setup failed: ") + hipGetErrorString(e);
+    return DPMM_E_DEVICE;
+  }
+  *out = ctx.release();
+  return DPMM_OK;
+}
+
+void dpmm_destroy(dpmm_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  else hipDeviceSynchronize();
+  for (auto& b : ctx->bufs) hipFree(b.p);
+  for (auto& e : ctx->ev)
+    if (e) hipEventDestroy(e);
+  delete ctx;
+}
+
+dpmm_status dpmm_init_labels(dpmm_ctx* ctx, int64_t n, int32_t* z, uint8_t* zsub) {
+  if (!ctx) return DPMM_E_ARG;
+  DPMM_TRY(check_n(ctx, z, n));
+  if (n > 0 && !zsub) return ctx->fail(DPMM_E_ARG, "zsub is NULL");
+  DPMM_HIP(ctx, launch_init_labels(n, ctx->cfg.seed, z, zsub, ctx->stream), "init kernel");
+  ctx->K = 1;
+  ctx->age.assign(1, 0);
+  ctx->have_stats = false;
+  ctx->have_params = false;
+  return DPMM_OK;
+}
+
+dpmm_status dpmm_set_state(dpmm_ctx* ctx, int32_t K, const int32_t* age) {
+  if (!ctx) return DPMM_E_ARG;
+  if (K < 1 || K > ctx->cfg.k_max) return ctx->fail(DPMM_E_CAPACITY, "K must lie in [1, k_max]");
+  ctx->K = K;
+  ctx->age.assign(K, 0);
+  if (age)
+    for (int k = 0; k < K; ++k) ctx->age[k] = age[k];
+  ctx->have_params = false;
+  ctx->have_stats = false;
+  return DPMM_OK;
+}
+
+dpmm_status dpmm_get_state(dpmm_ctx* ctx, int32_t* K, int32_t* age) {
+  if (!ctx || !K) return DPMM_E_ARG;
+  *K = ctx->K;
+  if (age)
+    for (int k = 0; k < ctx->K; ++k) age[k] = ctx->age[k];
+  return DPMM_OK;
+}
+
+dpmm_status dpmm_set_params(dpmm_ctx* ctx, int32_t K, const double* log_pi, const double* log_pisub,
+                            const double* comp) {
+  if (!ctx) return DPMM_E_ARG;
+  if (!log_pi || !log_pisub || !comp) return ctx->fail(DPMM_E_ARG, "parameter array is NULL");
+  if (K < 1 || K > ctx->cfg.k_max) return ctx->fail(DPMM_E_CAPACITY, "K must lie in [1, k_max]");
+  const int d = ctx->d;
+  const size_t P = ctx->gaussian() ? (size_t)d + (size_t)d * d : (size_t)d;
+  for (int k = 0; k < K; ++k)
+    if (std::isnan(log_pi[k]) || std::isnan(log_pisub[2 * k]) || std::isnan(log_pisub[2 * k + 1]))
+      return ctx->fail(DPMM_E_NUMERIC, "weights must not be NaN");
+  for (size_t i = 0; i < (size_t)K * 3 * P; ++i)
+    if (!std::isfinite(comp[i])) return ctx->fail(DPMM_E_NUMERIC, "component parameters must be finite");
+  if (ctx->K != K) ctx->age.assign(K, 0);
+  ctx->K = K;
+  DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_log_pi, log_pi, K * sizeof(double), hipMemcpyHostToDevice, ctx->stream), "copy");
+  DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_log_pisub, log_pisub, 2 * K * sizeof(double), hipMemcpyHostToDevice, ctx->stream),
+           "copy");
+  if (ctx->gaussian()) {
+    std::vector<double> mu((size_t)3 * K * d), sig((size_t)3 * K * d * d);
+    for (int e = 0; e < 3 * K; ++e) {
+      std::memcpy(&mu[(size_t)e * d], comp + e * P, d * sizeof(double));
+      std::memcpy(&sig[(size_t)e * d * d], comp + e * P + d, (size_t)d * d * sizeof(double));
+    }
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_mu, mu.data(), mu.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream),
+             "copy");
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_sigma, sig.data(), sig.size() * sizeof(double), hipMemcpyHostToDevice,
+                                 ctx->stream), "copy");
+    DPMM_TRY(pack_params(ctx));
+    DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    DPMM_TRY(check_device_error(ctx));
+  } else {
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_log_theta, comp, (size_t)3 * K * d * sizeof(double), hipMemcpyHostToDevice,
+                                 ctx->stream), "copy");
+    DPMM_TRY(pack_params(ctx));
+    DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  }
+  return DPMM_OK;
+}
+
+dpmm_status dpmm_get_params(dpmm_ctx* ctx, double* log_pi, double* log_pisub, double* comp) {
+  if (!ctx) return DPMM_E_ARG;
+  if (!log_pi || !log_pisub || !comp) return ctx->fail(DPMM_E_ARG, "parameter array is NULL");
+  if (!ctx->have_params) return ctx->fail(DPMM_E_STATE, "no parameters yet");
+  const int K = ctx->K, d = ctx->d;
+  DPMM_HIP(ctx, hipMemcpyAsync(log_pi, ctx->d_log_pi, K * sizeof(double), hipMemcpyDeviceToHost, ctx->stream), "copy");
+  DPMM_HIP(ctx, hipMemcpyAsync(log_pisub, ctx->d_log_pisub, 2 * K * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+           "copy");
+  if (ctx->gaussian()) {
+    const size_t P = (size_t)d + (size_t)d * d;
+    std::vector<double> mu((size_t)3 * K * d), sig((size_t)3 * K * d * d);
+    DPMM_HIP(ctx, hipMemcpyAsync(mu.data(), ctx->d_mu, mu.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+             "copy");
+    DPMM_HIP(ctx, hipMemcpyAsync(sig.data(), ctx->d_sigma, sig.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                 ctx->stream), "copy");
+    DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    for (int e = 0; e < 3 * K; ++e) {
+      std::memcpy(comp + e * P, &mu[(size_t)e * d], d * sizeof(double));
+      std::memcpy(comp + e * P + d, &sig[(size_t)e * d * d], (size_t)d * d * sizeof(double));
+    }
+  } else {
+    DPMM_HIP(ctx, hipMemcpyAsync(comp, ctx->d_log_theta, (size_t)3 * K * d * sizeof(double), hipMemcpyDeviceToHost,
+                                 ctx->stream), "copy");
+    DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  }
+  return DPMM_OK;
+}
+
+dpmm_status dpmm_set_stats(dpmm_ctx* ctx, int32_t K, const void* stats) {
+  if (!ctx) return DPMM_E_ARG;
+  if (!stats) return ctx->fail(DPMM_E_ARG, "stats is NULL");
+  if (K < 1 || K > ctx->cfg.k_max) return ctx->fail(DPMM_E_CAPACITY, "K must lie in [1, k_max]");
+  const int d = ctx->d;
+  std::vector<long long> cnt(2 * (size_t)K);
+  if (ctx->gaussian()) {
+    const double* s = (const double*)stats;
+    const size_t R = 1 + (size_t)d + (size_t)d * d;
+    std::vector<double> mom(2 * (size_t)K * ctx->E);
+    for (int g = 0; g < 2 * K; ++g) {
+      const double* r = s + g * R;
+      if (!(r[0] >= 0.0) || r[0] != std::floor(r[0])) return ctx->fail(DPMM_E_ARG, "counts must be whole numbers >= 0");
+      cnt[g] = (long long)r[0];
+      double* o = &mom[(size_t)g * ctx->E];
+      for (int i = 0; i < d; ++i) o[i] = r[1 + i];
+      for (int a = 0; a < d; ++a)
+        for (int b = a; b < d; ++b) o[d + tri_index(a, b, d)] = r[1 + d + a * d + b];
+    }
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_moments, mom.data(), mom.size() * sizeof(double), hipMemcpyHostToDevice,
+                                 ctx->stream), "copy");
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_counts, cnt.data(), cnt.size() * sizeof(long long), hipMemcpyHostToDevice,
+                                 ctx->stream), "copy");
+  } else {
+    const long long* s = (const long long*)stats;
+    const size_t R = 1 + (size_t)d;
+    std::vector<long long> sums(2 * (size_t)K * d);
+    for (int g = 0; g < 2 * K; ++g) {
+      if (s[g * R] < 0) return ctx->fail(DPMM_E_ARG, "counts must be >= 0");
+      cnt[g] = s[g * R];
+      for (int v = 0; v < d; ++v) sums[(size_t)g * d + v] = s[g * R + 1 + v];
+    }
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_sums, sums.data(), sums.size() * sizeof(long long), hipMemcpyHostToDevice,
+                                 ctx->stream), "copy");
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_counts, cnt.data(), cnt.size() * sizeof(long long), hipMemcpyHostToDevice,
+                                 ctx->stream), "copy");
+  }
+  DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  if (ctx->K != K) ctx->age.assign(K, 0);
+  ctx->K = K;
+  ctx->have_stats = true;
+  return DPMM_OK;
+}
+
+dpmm_status dpmm_get_stats(dpmm_ctx* ctx, void* stats) {
+  if (!ctx) return DPMM_E_ARG;
+  if (!stats) return ctx->fail(DPMM_E_ARG, "stats is NULL");
+  if (!ctx->have_stats) return ctx->fail(DPMM_E_STATE, "no statistics yet");
+  const int K = ctx->K, d = ctx->d;
+  std::vector<long long> cnt(2 * (size_t)K);
+  DPMM_HIP(ctx, hipMemcpyAsync(cnt.data(), ctx->d_counts, cnt.size() * sizeof(long long), hipMemcpyDeviceToHost,
+                               ctx->stream), "copy");
+  if (ctx->gaussian()) {
+    std::vector<double> mom(2 * (size_t)K * ctx->E);
+    DPMM_HIP(ctx, hipMemcpyAsync(mom.data(), ctx->d_moments, mom.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                 ctx->stream), "copy");
+    DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    double* s = (double*)stats;
+    const size_t R = 1 + (size_t)d + (size_t)d * d;
+    for (int g = 0; g < 2 * K; ++g) {
+      double* r = s + g * R;
+      const double* o = &mom[(size_t)g * ctx->E];
+      r[0] = (double)cnt[g];
+      for (int i = 0; i < d; ++i) r[1 + i] = o[i];
+      for (int a = 0; a < d; ++a)
+        for (int b = a; b < d; ++b) r[1 + d + a * d + b] = r[1 + d + b * d + a] = o[d + tri_index(a, b, d)];
+    }
+  } else {
+    std::vector<long long> sums(2 * (size_t)K * d);
+    DPMM_HIP(ctx, hipMemcpyAsync(sums.data(), ctx->d_sums, sums.size() * sizeof(long long), hipMemcpyDeviceToHost,
+                                 ctx->stream), "copy");
+    DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    long long* s = (long long*)stats;
+    const size_t R = 1 + (size_t)d;
+    for (int g = 0; g < 2 * K; ++g) {
+      s[g * R] = cnt[g];
+      for (int v = 0; v < d; ++v) s[g * R + 1 + v] = sums[(size_t)g * d + v];
+    }
+  }
+  return DPMM_OK;
+}
+
+dpmm_status dpmm_loglik(dpmm_ctx* ctx, const void* x, int64_t n, float* out) {
+  if (!ctx) return DPMM_E_ARG;
+  DPMM_TRY(check_n(ctx, x, n));
+  if (!out && n > 0) return ctx->fail(DPMM_E_ARG, "out is NULL");
+  if (!ctx->have_params) return ctx->fail(DPMM_E_STATE, "no parameters yet");
+  hipError_t e = ctx->gaussian()
+                     ? launch_loglik_gauss(ctx->d, (const float*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max, out, ctx->stream)
+                     : launch_loglik_mult(ctx->d, (const int*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max, out, ctx->stream);
+  DPMM_HIP(ctx, e, "log-likelihood kernel");
+  return DPMM_OK;
+}
+
+dpmm_status dpmm_sample_labels(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32_t* z, uint8_t* zsub) {
+  if (!ctx) return DPMM_E_ARG;
+  DPMM_TRY(check_n(ctx, x, n));
+  if (n > 0 && (!z || !zsub)) return ctx->fail(DPMM_E_ARG, "z / zsub is NULL");
+  if (!ctx->have_params) return ctx->fail(DPMM_E_STATE, "no parameters yet");
+  hipError_t e = ctx->gaussian() ? launch_label_gauss(ctx->d, (const float*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max,
+                                                      t, ctx->cfg.seed, z, zsub, ctx->stream)
+                                 : launch_label_mult(ctx->d, (const int*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max, t,
+                                                     ctx->cfg.seed, z, zsub, ctx->stream);
+  DPMM_HIP(ctx, e, "label kernel");
+  return DPMM_OK;
+}
+
+dpmm_status dpmm_suffstats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub) {
+  if (!ctx) return DPMM_E_ARG;
+  DPMM_TRY(check_n(ctx, x, n));
+  if (n > 0 && (!z || !zsub)) return ctx->fail(DPMM_E_ARG, "z / zsub is NULL");
+  if (ctx->K < 1) return ctx->fail(DPMM_E_STATE, "no clusters yet (call dpmm_init_labels or dpmm_set_state)");
+  return launch_stats(ctx, x, n, z, zsub);
+}
+
+dpmm_status dpmm_sample_params(dpmm_ctx* ctx, uint32_t t) {
+  if (!ctx) return DPMM_E_ARG;
+  if (!ctx->have_stats) return ctx->fail(DPMM_E_STATE, "no statistics yet");
+  const int K = ctx->K;
+  hipLaunchKernelGGL(k_weights, dim3(1), dim3(256), 0, ctx->stream, K, ctx->cfg.alpha, ctx->d_counts, ctx->cfg.seed, t,
+                     ctx->d_log_pi, ctx->d_log_pisub, ctx->d_tmp);
+  DPMM_HIP(ctx, hipGetLastError(), "weights kernel");
+  if (ctx->gaussian()) {
+    hipLaunchKernelGGL(k_niw_draw, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, prior_dev(ctx), ctx->d_counts,
+                       ctx->d_moments, ctx->cfg.seed, t, ctx->d_mu, ctx->d_sigma, ctx->d_scratch, ctx->d_err);
+  } else {
+    hipLaunchKernelGGL(k_dir_draw, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->d_beta, ctx->d_sums,
+                       ctx->cfg.seed, t, ctx->d_log_theta);
+  }
+  DPMM_HIP(ctx, hipGetLastError(), "posterior draw kernel");
+  return pack_params(ctx);
+}
+
+dpmm_status dpmm_split_merge(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32_t* z, uint8_t* zsub,
+                             dpmm_iter_info* info) {
+  if (!ctx) return DPMM_E_ARG;
+  DPMM_TRY(check_n(ctx, x, n));
+  if (n > 0 && (!z || !zsub)) return ctx->fail(DPMM_E_ARG, "z / zsub is NULL");
+  if (!ctx->have_stats) return ctx->fail(DPMM_E_STATE, "no statistics yet");
+  DPMM_TRY(check_device_error(ctx));
+  const double alpha = ctx->cfg.alpha;
+  const uint64_t seed = ctx->cfg.seed;
+  dpmm_iter_info local{};
+  std::vector<long long> cnt;
+  DPMM_TRY(read_counts(ctx, cnt));
+  // 1. delete empty clusters (stable)
+  {
+    int K = ctx->K, kept = 0;
+    std::vector<int> newidx(K, -1);
+    for (int k = 0; k < K; ++k)
+      if (cnt[2 * k] + cnt[2 * k + 1] > 0) newidx[k] = kept++;
+    if (kept == 0) return ctx->fail(DPMM_E_STATE, "every cluster is empty");
+    if (kept < K) {
+      std::vector<RelabelEntry> tab(2 * K);
+      std::vector<int> age;
+      for (int k = 0; k < K; ++k) {
+        tab[2 * k] = RelabelEntry{newidx[k] < 0 ? 0 : newidx[k], 0};
+        tab[2 * k + 1] = tab[2 * k];
+        if (newidx[k] >= 0) age.push_back(ctx->age[k]);
+      }
+      DPMM_TRY(apply_relabel(ctx, tab, n, t, z, zsub));
+      ctx->K = kept;
+      ctx->age = age;
+      local.removed = K - kept;
+      DPMM_TRY(launch_stats(ctx, x, n, z, zsub));
+      DPMM_TRY(read_counts(ctx, cnt));
+    }
+  }
+  const int K = ctx->K;
+  const int burn = ctx->cfg.burn_out;
+  // 2. marginal likelihoods of clusters and sub-clusters
+  std::vector<LogmlItem> items(3 * K);
+  for (int k = 0; k < K; ++k) {
+    items[3 * k] = LogmlItem{{2 * k, 2 * k + 1, -1, -1}};
+    items[3 * k + 1] = LogmlItem{{2 * k, -1, -1, -1}};
+    items[3 * k + 2] = LogmlItem{{2 * k + 1, -1, -1, -1}};
+  }
+  std::vector<double> lml;
+  DPMM_TRY(logml(ctx, items, lml));
+  DPMM_TRY(check_device_error(ctx));
+  std::vector<double> lml_cluster(K);
+  for (int k = 0; k < K; ++k) lml_cluster[k] = lml[3 * k];
+  // 3. splits (Sec. 2.3 eq. HastingsRatioSplit)
+  std::vector<char> touched(K, 0);
+  std::vector<int> split_slot(K, -1);
+  int new_slot = K;
+  for (int k = 0; k < K; ++k) {
+    if (ctx->age[k] < burn) continue;
+    const long long nl = cnt[2 * k], nr = cnt[2 * k + 1];
+    if (nl == 0 || nr == 0) continue;
+    const double lh = std::log(alpha) + std::lgamma((double)nl) + lml[3 * k + 1] + std::lgamma((double)nr) +
+                      lml[3 * k + 2] - std::lgamma((double)(nl + nr)) - lml[3 * k];
+    const double u = uniform_d(rng_block(seed, t, (uint32_t)k, TAG_SPLIT, 0).x);
+    if (std::log(u) < lh) {
+      if (new_slot >= ctx->cfg.k_max) continue;  // capacity: the split is not taken
+      split_slot[k] = new_slot++;
+      touched[k] = 1;
+    }
+  }
+  local.splits = new_slot - K;
+  // 4. merges among clusters not split (Sec. 4.1 eq. sample_merges)
+  std::vector<std::pair<int, int>> pairs;
+  for (int k1 = 0; k1 < K; ++k1) {
+    if (touched[k1] || ctx->age[k1] < burn) continue;
+    for (int k2 = k1 + 1; k2 < K; ++k2) {
+      if (touched[k2] || ctx->age[k2] < burn) continue;
+      pairs.emplace_back(k1, k2);
+    }
+  }
+  std::vector<int> merged_into(K, -1);  // k2 -> k1
+  std::vector<char> is_merge_target(K, 0);
+  if (!pairs.empty()) {
+    std::vector<LogmlItem> pitems(pairs.size());
+    for (size_t p = 0; p < pairs.size(); ++p) {
+      const int k1 = pairs[p].first, k2 = pairs[p].second;
+      pitems[p] = LogmlItem{{2 * k1, 2 * k1 + 1, 2 * k2, 2 * k2 + 1}};
+    }
+    std::vector<double> plml;
+    DPMM_TRY(logml(ctx, pitems, plml));
+    DPMM_TRY(check_device_error(ctx));
+    for (size_t p = 0; p < pairs.size(); ++p) {
+      const int k1 = pairs[p].first, k2 = pairs[p].second;
+      if (touched[k1] || touched[k2]) continue;
+      const double n1 = (double)(cnt[2 * k1] + cnt[2 * k1 + 1]);
+      const double n2 = (double)(cnt[2 * k2] + cnt[2 * k2 + 1]);
+      double lh = std::lgamma(n1 + n2) - std::log(alpha) - std::lgamma(n1) - std::lgamma(n2) + plml[p] -
+                  lml_cluster[k1] - lml_cluster[k2];
+      if (ctx->cfg.merge_form == DPMM_MERGE_PAPER)
+        lh += std::lgamma(alpha) - std::lgamma(alpha + n1 + n2) + std::lgamma(0.5 * alpha + n1) +
+              std::lgamma(0.5 * alpha + n2) - 2.0 * std::lgamma(0.5 * alpha);
+      const double u = uniform_d(rng_block(seed, t, merge_entity(k1, k2), TAG_MERGE, 0).x);
+      if (std::log(u) < lh) {
+        touched[k1] = touched[k2] = 1;
+        merged_into[k2] = k1;
+        is_merge_target[k1] = 1;
+        ++local.merges;
+      }
+    }
+  }
+  // 5. relabel and compact
+  if (local.splits > 0 || local.merges > 0) {
+    const int K2 = new_slot;
+    std::vector<int> final_idx(K2, -1);
+    int kept = 0;
+    for (int s = 0; s < K2; ++s)
+      if (!(s < K && merged_into[s] >= 0)) final_idx[s] = kept++;
+    std::vector<RelabelEntry> tab(2 * K);
+    std::vector<int> age(kept, 0);
+    for (int k = 0; k < K; ++k) {
+      if (split_slot[k] >= 0) {
+        tab[2 * k] = RelabelEntry{final_idx[k], 3};
+        tab[2 * k + 1] = RelabelEntry{final_idx[split_slot[k]], 3};
+      } else if (merged_into[k] >= 0) {
+        tab[2 * k] = tab[2 * k + 1] = RelabelEntry{final_idx[merged_into[k]], 2};
+      } else if (is_merge_target[k]) {
+        tab[2 * k] = tab[2 * k + 1] = RelabelEntry{final_idx[k], 1};
+      } else {
+        tab[2 * k] = RelabelEntry{final_idx[k], 0};
+        tab[2 * k + 1] = RelabelEntry{final_idx[k], 0};
+        age[final_idx[k]] = ctx->age[k];
+      }
+    }
+    DPMM_TRY(apply_relabel(ctx, tab, n, t, z, zsub));
+    ctx->K = kept;
+    ctx->age = age;
+    DPMM_TRY(launch_stats(ctx, x, n, z, zsub));
+    DPMM_TRY(read_counts(ctx, cnt));
+    std::vector<LogmlItem> fitems(kept);
+    for (int k = 0; k < kept; ++k) fitems[k] = LogmlItem{{2 * k, 2 * k + 1, -1, -1}};
+    DPMM_TRY(logml(ctx, fitems, lml_cluster));
+    DPMM_TRY(check_device_error(ctx));
+  }
+  local.K = ctx->K;
+  local.logpost = log_posterior(ctx, cnt, lml_cluster);
+  ctx->have_params = false;  // parameters refer to the clusters before the moves
+  if (info) {
+    info->K = local.K;
+    info->splits = local.splits;
+    info->merges = local.merges;
+    info->removed = local.removed;
+    info->logpost = local.logpost;
+  }
+  return DPMM_OK;
+}
+
+dpmm_status dpmm_step(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32_t* z, uint8_t* zsub,
+                      dpmm_iter_info* info) {
+  if (!ctx) return DPMM_E_ARG;
+  DPMM_TRY(check_n(ctx, x, n));
+  if (n > 0 && (!z || !zsub)) return ctx->fail(DPMM_E_ARG, "z / zsub is NULL");
+  if (ctx->K < 1) return ctx->fail(DPMM_E_STATE, "no clusters yet (call dpmm_init_labels)");
+  if (!ctx->have_stats) DPMM_TRY(launch_stats(ctx, x, n, z, zsub));
+  DPMM_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream), "event");
+  DPMM_TRY(dpmm_sample_params(ctx, t));
+  DPMM_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream), "event");
+  DPMM_TRY(dpmm_sample_labels(ctx, x, n, t, z, zsub));
+  DPMM_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream), "event");
+  DPMM_TRY(launch_stats(ctx, x, n, z, zsub));
+  DPMM_HIP(ctx, hipEventRecord(ctx->ev[3], ctx->stream), "event");
+  dpmm_iter_info local{};
+  DPMM_TRY(dpmm_split_merge(ctx, x, n, t, z, zsub, &local));
+  DPMM_HIP(ctx, hipEventRecord(ctx->ev[4], ctx->stream), "event");
+  for (auto& a : ctx->age) ++a;
+  if (info) {
+    *info = local;
+    DPMM_HIP(ctx, hipEventSynchronize(ctx->ev[4]), "event sync");
+    hipEventElapsedTime(&info->ms_params, ctx->ev[0], ctx->ev[1]);
+    hipEventElapsedTime(&info->ms_labels, ctx->ev[1], ctx->ev[2]);
+    hipEventElapsedTime(&info->ms_stats, ctx->ev[2], ctx->ev[3]);
+    hipEventElapsedTime(&info->ms_splitmerge, ctx->ev[3], ctx->ev[4]);
+  }
+  return DPMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+// Gaussian label step, float32 VALU path: Sec. 4.1 steps (e) and (f).
+//
+// One lane per point, points streamed with a grid-stride loop (x is
+// point-major, so a wave reads 64 consecutive rows).  The cluster loop is
+// uniform across the wave: the component record address depends only on the
+// loop counter, so the compiler fetches means, whitener rows and constants
+// with scalar loads and feeds them to the FMAs as scalar operands.
+//
+// Score of a component: l = c - 1/2 ||W (x - mu)||^2 with W lower triangular
+// (W^T W = Sigma^-1), i.e. d(d+1)/2 FMAs for W (x - mu) and d for the norm.
+//
+// Label draw (eq. sample_labels) as a lazy Gumbel-max: pass 1 keeps the two
+// best scores m1 >= m2.  If m2 < m1 - (G_max - G_min) no other cluster can
+// beat the leader whatever the noise, so z is the leader and no random number
+// is drawn.  Otherwise pass 2 draws the leader's Gumbel first and then the
+// Gumbel of each other cluster k only if l_k + G_max can still exceed the
+// best perturbed score; the result equals argmax_k (l_k + g_k) over all k.
+// Sub-label (eq. sample_sub_labels): the two sub-cluster records of z are
+// gathered per lane; the logistic draw is skipped when the score gap exceeds
+// the logistic's range.
+#include "kernels.hpp"
+
+namespace dpmm {
+
+namespace {
+
+constexpr int BLOCK = 256;
+constexpr float RGAP = GUMBEL_MAX_F - GUMBEL_MIN_F;
+
+template <int D>
+__device__ __forceinline__ float score_rec(const float* __restrict__ p, const float (&x)[D]) {
+  float dx[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) dx[j] = x[j] - p[4 + j];
+  const float* w = p + 4 + D;
+  float q = 0.0f;
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    float y = 0.0f;
+#pragma unroll
+    for (int c = 0; c <= r; ++c) y = fmaf(w[r * (r + 1) / 2 + c], dx[c], y);
+    q = fmaf(y, y, q);
+  }
+  return fmaf(-0.5f, q, p[0]);
+}
+
+// Generic dimension: the centred vector lives in a per-thread LDS column.
+__device__ __forceinline__ float score_rec_dyn(const float* __restrict__ p, const float* __restrict__ x,
+                                               float* dx, int d) {
+  for (int j = 0; j < d; ++j) dx[j * BLOCK] = x[j] - p[4 + j];
+  const float* w = p + 4 + d;
+  float q = 0.0f;
+  for (int r = 0; r < d; ++r) {
+    const float* wr = w + r * (r + 1) / 2;
+    float y = 0.0f;
+    for (int c = 0; c <= r; ++c) y = fmaf(wr[c], dx[c * BLOCK], y);
+    q = fmaf(y, y, q);
+  }
+  return fmaf(-0.5f, q, p[0]);
+}
+
+struct Top2 {
+  float m1, m2;
+  int arg;
+  __device__ __forceinline__ void init() {
+    m1 = -INFINITY;
+    m2 = -INFINITY;
+    arg = 0;
+  }
+  __device__ __forceinline__ void push(float l, int k) {
+    if (l > m1) {
+      m2 = m1;
+      m1 = l;
+      arg = k;
+    } else if (l > m2) {
+      m2 = l;
+    }
+  }
+};
+
+template <typename ScoreFn>
+__device__ __forceinline__ int lazy_gumbel_max(const Top2& t2, int K, uint32_t i, uint32_t t, uint64_t seed,
+                                               ScoreFn score_k) {
+  if (!(t2.m2 > t2.m1 - RGAP)) return t2.arg;
+  int cached = t2.arg >> 2;
+  u32x4 blk = rng_block(seed, t, i, TAG_GUMBEL, (uint32_t)cached);
+  float best = t2.m1 + gumbel_f(word_of(blk, t2.arg & 3));
+  int win = t2.arg;
+  for (int k = 0; k < K; ++k) {
+    if (k == t2.arg) continue;
+    const float l = score_k(k);
+    if (l + GUMBEL_MAX_F > best) {
+      const int b = k >> 2;
+      if (b != cached) {
+        blk = rng_block(seed, t, i, TAG_GUMBEL, (uint32_t)b);
+        cached = b;
+      }
+      const float s = l + gumbel_f(word_of(blk, k & 3));
+      if (s > best || (s == best && k < win)) {
+        best = s;
+        win = k;
+      }
+    }
+  }
+  return win;
+}
+
+__device__ __forceinline__ unsigned char draw_sub(float delta, uint32_t i, uint32_t t, uint64_t seed) {
+  if (delta > LOGISTIC_MAX_F) return 0;
+  if (delta < -LOGISTIC_MAX_F) return 1;
+  const float L = logistic_f(rng_block(seed, t, i, TAG_LOGISTIC, 0).x);
+  return delta + L > 0.0f ? 0 : 1;
+}
+
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_label_gauss(const float* __restrict__ x, long long n,
+                                                       const float* __restrict__ packed, int K, int k_max,
+                                                       uint32_t t, uint64_t seed, int* __restrict__ z,
+                                                       unsigned char* __restrict__ zsub) {
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  const long long stride_pts = (long long)gridDim.x * BLOCK;
+  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride_pts) {
+    float xv[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) xv[j] = x[i * D + j];
+    Top2 t2;
+    t2.init();
+    for (int k = 0; k < K; ++k) t2.push(score_rec<D>(packed + (size_t)k * S, xv), k);
+    const int zi = lazy_gumbel_max(t2, K, (uint32_t)i, t, seed,
+                                   [&](int k) { return score_rec<D>(packed + (size_t)k * S, xv); });
+    const float* ps = packed + (size_t)(k_max + 2 * zi) * S;
+    const float delta = score_rec<D>(ps, xv) - score_rec<D>(ps + S, xv);
+    z[i] = zi;
+    zsub[i] = draw_sub(delta, (uint32_t)i, t, seed);
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_label_gauss_dyn(const float* __restrict__ x, long long n, int d,
+                                                           const float* __restrict__ packed, int K,
+                                                           int k_max, uint32_t t, uint64_t seed,
+                                                           int* __restrict__ z,
+                                                           unsigned char* __restrict__ zsub) {
+  extern __shared__ float lds[];
+  float* dx = lds + threadIdx.x;
+  const int S = gauss_rec_stride(d);
+  const long long stride_pts = (long long)gridDim.x * BLOCK;
+  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride_pts) {
+    const float* xi = x + i * d;
+    Top2 t2;
+    t2.init();
+    for (int k = 0; k < K; ++k) t2.push(score_rec_dyn(packed + (size_t)k * S, xi, dx, d), k);
+    const int zi = lazy_gumbel_max(t2, K, (uint32_t)i, t, seed,
+                                   [&](int k) { return score_rec_dyn(packed + (size_t)k * S, xi, dx, d); });
+    const float* ps = packed + (size_t)(k_max + 2 * zi) * S;
+    const float delta = score_rec_dyn(ps, xi, dx, d) - score_rec_dyn(ps + S, xi, dx, d);
+    z[i] = zi;
+    zsub[i] = draw_sub(delta, (uint32_t)i, t, seed);
+  }
+}
+
+// All 3K weighted log-likelihoods per point (parity / inspection entry).
+__global__ __launch_bounds__(BLOCK) void k_loglik_gauss_dyn(const float* __restrict__ x, long long n, int d,
+                                                            const float* __restrict__ packed, int K,
+                                                            int k_max, float* __restrict__ out) {
+  extern __shared__ float lds[];
+  float* dx = lds + threadIdx.x;
+  const int S = gauss_rec_stride(d);
+  const long long stride_pts = (long long)gridDim.x * BLOCK;
+  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride_pts) {
+    const float* xi = x + i * d;
+    float* o = out + i * 3 * K;
+    for (int k = 0; k < K; ++k) o[k] = score_rec_dyn(packed + (size_t)k * S, xi, dx, d);
+    for (int j = 0; j < 2 * K; ++j) o[K + j] = score_rec_dyn(packed + (size_t)(k_max + j) * S, xi, dx, d);
+  }
+}
+
+int grid_for(long long n) {
+  // enough workgroups to fill 256 CUs several times over, capped so the
+  // grid-stride loop gives each lane a few points at large n
+  long long g = (n + BLOCK - 1) / BLOCK;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_label_gauss(int d, const float* x, long long n, const float* packed, int K, int k_max,
+                              uint32_t t, uint64_t seed, int* z, unsigned char* zsub, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int g = grid_for(n);
+#define DPMM_LABEL_CASE(DD)                                                                          \
+  case DD:                                                                                           \
+    hipLaunchKernelGGL(k_label_gauss<DD>, dim3(g), dim3(BLOCK), 0, s, x, n, packed, K, k_max, t,     \
+                       seed, z, zsub);                                                               \
+    break;
+  switch (d) {
+    DPMM_LABEL_CASE(1)
+    DPMM_LABEL_CASE(2)
+    DPMM_LABEL_CASE(3)
+    DPMM_LABEL_CASE(4)
+    DPMM_LABEL_CASE(8)
+    DPMM_LABEL_CASE(16)
+    DPMM_LABEL_CASE(32)
+    default:
+      hipLaunchKernelGGL(k_label_gauss_dyn, dim3(g), dim3(BLOCK), (size_t)d * BLOCK * sizeof(float), s,
+                         x, n, d, packed, K, k_max, t, seed, z, zsub);
+  }
+#undef DPMM_LABEL_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_loglik_gauss(int d, const float* x, long long n, const float* packed, int K, int k_max,
+                               float* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_loglik_gauss_dyn, dim3(grid_for(n)), dim3(BLOCK), (size_t)d * BLOCK * sizeof(float),
+                     s, x, n, d, packed, K, k_max, out);
+  return hipGetLastError();
+}
+
+}  // namespace dpmm

@@ -1,0 +1,321 @@
+// Parameter kernels (float64 on the device): Sec. 4.1 steps (a)-(d).
+//
+//   k_weights        (a) and (b): Dirichlet cluster and sub-cluster weights
+//                    as normalised Gamma draws.
+//   k_niw_draw       (c) and (d), Gaussian: NIW posterior from the
+//                    sufficient statistics and Bartlett's construction of the
+//                    covariance draw, one workgroup per component.
+//   k_dir_draw       (c) and (d), multinomial: Dirichlet posterior draw.
+//   k_pack_gauss     float32 scoring record per component: Cholesky of Sigma,
+//                    whitener W = L^-1, constant log w - 1/2 log|Sigma| - d/2 log 2pi.
+//   k_pack_mult      float32 record: log w and log theta.
+//
+// Work here is O(K d^3) per iteration; one workgroup per component keeps every
+// matrix of a component on one CU, with the triangular solves and Cholesky
+// columns parallel over rows.
+#include "kernels.hpp"
+
+namespace dpmm {
+
+namespace {
+
+__device__ double block_reduce_max(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_reduce_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// In-place lower Cholesky of the d x d row-major matrix a (global scratch).
+// Returns false (to every thread) if a pivot is not positive and finite.
+__device__ bool block_cholesky(double* a, int d, int* flag) {
+  const int tid = threadIdx.x;
+  if (tid == 0) *flag = 1;
+  __syncthreads();
+  for (int j = 0; j < d; ++j) {
+    if (tid == 0) {
+      double s = a[j * d + j];
+      for (int k = 0; k < j; ++k) s -= a[j * d + k] * a[j * d + k];
+      if (!(s > 0.0) || !isfinite(s)) {
+        *flag = 0;
+        s = 1.0;
+      }
+      a[j * d + j] = sqrt(s);
+    }
+    __syncthreads();
+    const double ljj = a[j * d + j];
+    for (int i = j + 1 + tid; i < d; i += blockDim.x) {
+      double s = a[i * d + j];
+      for (int k = 0; k < j; ++k) s -= a[i * d + k] * a[j * d + k];
+      a[i * d + j] = s / ljj;
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < d * d; idx += blockDim.x) {
+    const int i = idx / d, j = idx % d;
+    if (j > i) a[idx] = 0.0;
+  }
+  __syncthreads();
+  const bool ok = *flag != 0;
+  __syncthreads();
+  return ok;
+}
+
+__device__ __forceinline__ int tri_index(int a, int b, int d) {
+  // packed upper triangle (a <= b), row-major: row a starts at a*d - a(a-1)/2
+  return a * d - (a * (a - 1)) / 2 + (b - a);
+}
+
+}  // namespace
+
+__global__ void k_weights(int K, double alpha, const long long* __restrict__ counts, uint64_t seed,
+                          uint32_t t, double* __restrict__ log_pi, double* __restrict__ log_pisub,
+                          double* __restrict__ tmp) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double mx = -INFINITY;
+  for (int j = tid; j <= K; j += blockDim.x) {
+    const double shape = j < K ? (double)(counts[2 * j] + counts[2 * j + 1]) : alpha;
+    const double lg = log_gamma_draw(seed, t, (uint32_t)j, TAG_WEIGHTS, 0, shape);
+    tmp[j] = lg;
+    mx = fmax(mx, lg);
+  }
+  mx = block_reduce_max(mx, red);
+  double s = 0.0;
+  for (int j = tid; j <= K; j += blockDim.x) s += exp(tmp[j] - mx);
+  s = block_reduce_sum(s, red);
+  const double lse = mx + log(s);
+  for (int j = tid; j < K; j += blockDim.x) log_pi[j] = tmp[j] - lse;
+  for (int k = tid; k < K; k += blockDim.x) {
+    const double a0 = (double)counts[2 * k] + 0.5 * alpha;
+    const double a1 = (double)counts[2 * k + 1] + 0.5 * alpha;
+    const double l0 = log_gamma_draw(seed, t, (uint32_t)k, TAG_SUBWEIGHTS, 0, a0);
+    const double l1 = log_gamma_draw(seed, t, (uint32_t)k, TAG_SUBWEIGHTS, 1, a1);
+    const double m = fmax(l0, l1);
+    const double l = m + log(exp(l0 - m) + exp(l1 - m));
+    log_pisub[2 * k] = l0 - l;
+    log_pisub[2 * k + 1] = l1 - l;
+  }
+}
+
+// One workgroup per component e = 3k + c.  scratch holds NIW_SCRATCH(d)
+// doubles per component (three d x d matrices and a d-vector).  Writes mu[e][d], sigma[e][d][d] (float64).
+__global__ void k_niw_draw(int K, int d, NiwPriorDev prior, const long long* __restrict__ counts,
+                           const double* __restrict__ moments, uint64_t seed, uint32_t t,
+                           double* __restrict__ mu_out, double* __restrict__ sigma_out,
+                           double* __restrict__ scratch, int* __restrict__ err) {
+  __shared__ double red[256];
+  __shared__ int flag;
+  __shared__ double sh_n, sh_kn, sh_nun;
+  const int e = blockIdx.x;
+  if (e >= 3 * K) return;
+  const int k = e / 3, c = e % 3;
+  const int tid = threadIdx.x;
+  const int E = d + d * (d + 1) / 2;
+  double* L = scratch + (size_t)e * NIW_SCRATCH(d);
+  double* A = L + d * d;
+  double* F = A + d * d;
+  double* mn = mu_out + (size_t)e * d;  // m_n staged in the output row
+  // segments feeding this component
+  const int s0 = c == 0 ? 2 * k : 2 * k + (c - 1);
+  const int s1 = c == 0 ? 2 * k + 1 : -1;
+  const double* M0 = moments + (size_t)s0 * E;
+  const double* M1 = s1 >= 0 ? moments + (size_t)s1 * E : nullptr;
+  if (tid == 0) {
+    const double n = (double)counts[s0] + (s1 >= 0 ? (double)counts[s1] : 0.0);
+    sh_n = n;
+    sh_kn = prior.kappa + n;
+    sh_nun = prior.nu + n;
+  }
+  __syncthreads();
+  const double n = sh_n, kn = sh_kn, nun = sh_nun;
+  // m_n = (kappa m + s) / kappa_n
+  for (int i = tid; i < d; i += blockDim.x) {
+    const double s = M0[i] + (M1 ? M1[i] : 0.0);
+    mn[i] = (prior.kappa * prior.m[i] + s) / kn;
+  }
+  // Psi_n = Psi + C + (kappa n / kappa_n)(xbar - m)(xbar - m)^T, C = S - n xbar xbar^T
+  for (int idx = tid; idx < d * d; idx += blockDim.x) {
+    const int i = idx / d, j = idx % d;
+    double v = prior.psi[idx];
+    if (n > 0.0) {
+      const int a = i < j ? i : j, b = i < j ? j : i;
+      const double S = M0[d + tri_index(a, b, d)] + (M1 ? M1[d + tri_index(a, b, d)] : 0.0);
+      const double si = M0[i] + (M1 ? M1[i] : 0.0);
+      const double sj = M0[j] + (M1 ? M1[j] : 0.0);
+      const double xi = si / n, xj = sj / n;
+      v += (S - n * xi * xj) + (prior.kappa * n / kn) * (xi - prior.m[i]) * (xj - prior.m[j]);
+    }
+    L[idx] = v;
+  }
+  __syncthreads();
+  if (!block_cholesky(L, d, &flag)) {
+    if (tid == 0) atomicOr(err, 1);
+  }
+  // Bartlett factor A (lower): A[i][j] ~ N(0,1) for i > j, A[i][i] = sqrt(chi2(nu_n - i))
+  const int nq_off = d * (d - 1) / 2;
+  for (int idx = tid; idx < d * d; idx += blockDim.x) {
+    const int i = idx / d, j = idx % d;
+    double v = 0.0;
+    if (j < i) {
+      v = normal_draw(seed, t, (uint32_t)e, TAG_NIW, (uint32_t)(i * (i - 1) / 2 + j));
+    } else if (j == i) {
+      const double lg = log_gamma_draw(seed, t, (uint32_t)e, TAG_NIW, (uint32_t)(nq_off + i), 0.5 * (nun - i));
+      v = exp(0.5 * (0.69314718055994531 + lg));
+    }
+    A[idx] = v;
+  }
+  __syncthreads();
+  // F = L A^-T: row r solves A f^T = L[r]^T by forward substitution
+  for (int r = tid; r < d; r += blockDim.x) {
+    for (int j = 0; j < d; ++j) {
+      double s = L[r * d + j];
+      for (int q = 0; q < j; ++q) s -= A[j * d + q] * F[r * d + q];
+      F[r * d + j] = s / A[j * d + j];
+    }
+  }
+  __syncthreads();
+  // Sigma = F F^T
+  double* sig = sigma_out + (size_t)e * d * d;
+  for (int idx = tid; idx < d * d; idx += blockDim.x) {
+    const int i = idx / d, j = idx % d;
+    if (j < i) continue;
+    double s = 0.0;
+    for (int q = 0; q < d; ++q) s += F[i * d + q] * F[j * d + q];
+    sig[i * d + j] = s;
+    sig[j * d + i] = s;
+  }
+  // mu = m_n + F eps / sqrt(kappa_n)
+  double* eps = F + d * d;
+  for (int q = tid; q < d; q += blockDim.x)
+    eps[q] = normal_draw(seed, t, (uint32_t)e, TAG_NIW, (uint32_t)(nq_off + d + q));
+  __syncthreads();
+  const double rs = 1.0 / sqrt(kn);
+  for (int r = tid; r < d; r += blockDim.x) {
+    double s = 0.0;
+    for (int q = 0; q < d; ++q) s += F[r * d + q] * eps[q];
+    mn[r] += s * rs;
+  }
+  (void)red;
+}
+
+// One workgroup per component: log theta ~ log Dir(beta + c).
+__global__ void k_dir_draw(int K, int V, const double* __restrict__ beta,
+                           const long long* __restrict__ sums, uint64_t seed, uint32_t t,
+                           double* __restrict__ log_theta) {
+  __shared__ double red[256];
+  const int e = blockIdx.x;
+  if (e >= 3 * K) return;
+  const int k = e / 3, c = e % 3;
+  const int s0 = c == 0 ? 2 * k : 2 * k + (c - 1);
+  const int s1 = c == 0 ? 2 * k + 1 : -1;
+  double* out = log_theta + (size_t)e * V;
+  double mx = -INFINITY;
+  for (int v = threadIdx.x; v < V; v += blockDim.x) {
+    const double cnt = (double)sums[(size_t)s0 * V + v] + (s1 >= 0 ? (double)sums[(size_t)s1 * V + v] : 0.0);
+    const double lg = log_gamma_draw(seed, t, (uint32_t)e, TAG_DIRTHETA, (uint32_t)v, beta[v] + cnt);
+    out[v] = lg;
+    mx = fmax(mx, lg);
+  }
+  mx = block_reduce_max(mx, red);
+  double s = 0.0;
+  for (int v = threadIdx.x; v < V; v += blockDim.x) s += exp(out[v] - mx);
+  s = block_reduce_sum(s, red);
+  const double lse = mx + log(s);
+  __syncthreads();
+  for (int v = threadIdx.x; v < V; v += blockDim.x) out[v] -= lse;
+}
+
+// Pack component e = 3k + c: record slot k (cluster) or k_max + 2k + h (sub).
+__global__ void k_pack_gauss(int K, int d, int k_max, const double* __restrict__ log_pi,
+                             const double* __restrict__ log_pisub, const double* __restrict__ mu,
+                             const double* __restrict__ sigma, double* __restrict__ scratch,
+                             float* __restrict__ packed, double* __restrict__ logdet_out,
+                             int* __restrict__ err) {
+  __shared__ int flag;
+  __shared__ double red[256];
+  const int e = blockIdx.x;
+  if (e >= 3 * K) return;
+  const int k = e / 3, c = e % 3;
+  const int tid = threadIdx.x;
+  double* G = scratch + (size_t)e * NIW_SCRATCH(d);
+  double* W = G + d * d;
+  const double* sig = sigma + (size_t)e * d * d;
+  for (int idx = tid; idx < d * d; idx += blockDim.x) G[idx] = sig[idx];
+  __syncthreads();
+  if (!block_cholesky(G, d, &flag)) {
+    if (tid == 0) atomicOr(err, 2);
+  }
+  // W = G^-1 (lower): column j by forward substitution
+  for (int j = tid; j < d; j += blockDim.x) {
+    for (int i = 0; i < j; ++i) W[i * d + j] = 0.0;
+    W[j * d + j] = 1.0 / G[j * d + j];
+    for (int i = j + 1; i < d; ++i) {
+      double s = 0.0;
+      for (int q = j; q < i; ++q) s += G[i * d + q] * W[q * d + j];
+      W[i * d + j] = -s / G[i * d + i];
+    }
+  }
+  double ld = 0.0;
+  for (int i = tid; i < d; i += blockDim.x) ld += log(G[i * d + i]);
+  ld = 2.0 * block_reduce_sum(ld, red);
+  __syncthreads();
+  const int stride = gauss_rec_stride(d);
+  const int slot = c == 0 ? k : k_max + 2 * k + (c - 1);
+  float* rec = packed + (size_t)slot * stride;
+  const double lw = c == 0 ? log_pi[k] : log_pisub[2 * k + (c - 1)];
+  if (tid == 0) {
+    rec[0] = (float)(lw - 0.5 * ld - 0.5 * d * 1.8378770664093453);
+    rec[1] = rec[2] = rec[3] = 0.0f;
+    logdet_out[e] = ld;
+  }
+  for (int i = tid; i < d; i += blockDim.x) rec[4 + i] = (float)mu[(size_t)e * d + i];
+  for (int idx = tid; idx < d * (d + 1) / 2; idx += blockDim.x) {
+    // row r holds W[r][0..r]; idx = r(r+1)/2 + col
+    int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= idx) ++r;
+    while (r * (r + 1) / 2 > idx) --r;
+    const int col = idx - r * (r + 1) / 2;
+    rec[4 + d + idx] = (float)W[r * d + col];
+  }
+  for (int idx = 4 + d + d * (d + 1) / 2 + tid; idx < stride; idx += blockDim.x) rec[idx] = 0.0f;
+}
+
+__global__ void k_pack_mult(int K, int V, int k_max, const double* __restrict__ log_pi,
+                            const double* __restrict__ log_pisub, const double* __restrict__ log_theta,
+                            float* __restrict__ packed) {
+  const int e = blockIdx.x;
+  if (e >= 3 * K) return;
+  const int k = e / 3, c = e % 3;
+  const int stride = mult_rec_stride(V);
+  const int slot = c == 0 ? k : k_max + 2 * k + (c - 1);
+  float* rec = packed + (size_t)slot * stride;
+  const double lw = c == 0 ? log_pi[k] : log_pisub[2 * k + (c - 1)];
+  if (threadIdx.x == 0) {
+    rec[0] = (float)lw;
+    rec[1] = rec[2] = rec[3] = 0.0f;
+  }
+  for (int v = threadIdx.x; v < V; v += blockDim.x) rec[4 + v] = (float)log_theta[(size_t)e * V + v];
+  for (int idx = 4 + V + threadIdx.x; idx < stride; idx += blockDim.x) rec[idx] = 0.0f;
+}
+
+}  // namespace dpmm

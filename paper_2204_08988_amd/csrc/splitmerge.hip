@@ -1,0 +1,216 @@
+// Split/merge support kernels: Sec. 2.3 (split Hastings ratio, merge) and
+// Sec. 4.1 (eqs. sample_splits, sample_merges), plus label bookkeeping.
+//
+//   k_logml_gauss  log marginal likelihood of the union of up to four
+//                  sub-cluster segments under the NIW prior, one workgroup
+//                  per item (float64 Cholesky of Psi_n for log|Psi_n|);
+//   k_logml_mult   the Dirichlet-multinomial log marginal likelihood;
+//   k_relabel      applies a split/merge/compaction move table to (z, zsub)
+//                  in one O(N) pass;
+//   k_init_labels  the one-cluster initial state.
+// The O(K^2) accept/reject bookkeeping runs on the host from these values.
+#include "kernels.hpp"
+
+namespace dpmm {
+
+namespace {
+
+constexpr int BLOCK = 256;
+
+__device__ __forceinline__ int tri_index(int a, int b, int d) {
+  return a * d - (a * (a - 1)) / 2 + (b - a);
+}
+
+__device__ double reduce_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void k_zero64(unsigned long long* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+__global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, int d, NiwPriorDev prior,
+                              double logdet_psi, const long long* __restrict__ counts,
+                              const double* __restrict__ moments, double* __restrict__ scratch,
+                              double* __restrict__ out, int* __restrict__ err) {
+  __shared__ double red[BLOCK];
+  __shared__ int flag;
+  const int it = blockIdx.x;
+  if (it >= n_items) return;
+  const int tid = threadIdx.x;
+  const int E = d + d * (d + 1) / 2;
+  const LogmlItem item = items[it];
+  double n = 0.0;
+  for (int q = 0; q < 4; ++q)
+    if (item.seg[q] >= 0) n += (double)counts[item.seg[q]];
+  if (n == 0.0) {
+    if (tid == 0) out[it] = 0.0;
+    return;
+  }
+  double* P = scratch + (size_t)it * d * d;
+  const double kn = prior.kappa + n, nun = prior.nu + n;
+  for (int idx = tid; idx < d * d; idx += BLOCK) {
+    const int i = idx / d, j = idx % d;
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    double S = 0.0, si = 0.0, sj = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const int sg = item.seg[q];
+      if (sg < 0) continue;
+      const double* M = moments + (size_t)sg * E;
+      S += M[d + tri_index(a, b, d)];
+      si += M[i];
+      sj += M[j];
+    }
+    const double xi = si / n, xj = sj / n;
+    P[idx] = prior.psi[idx] + (S - n * xi * xj) + (prior.kappa * n / kn) * (xi - prior.m[i]) * (xj - prior.m[j]);
+  }
+  __syncthreads();
+  // Cholesky, column by column
+  if (tid == 0) flag = 1;
+  __syncthreads();
+  for (int j = 0; j < d; ++j) {
+    if (tid == 0) {
+      double s = P[j * d + j];
+      for (int k = 0; k < j; ++k) s -= P[j * d + k] * P[j * d + k];
+      if (!(s > 0.0) || !isfinite(s)) {
+        flag = 0;
+        s = 1.0;
+      }
+      P[j * d + j] = sqrt(s);
+    }
+    __syncthreads();
+    const double ljj = P[j * d + j];
+    for (int i = j + 1 + tid; i < d; i += BLOCK) {
+      double s = P[i * d + j];
+      for (int k = 0; k < j; ++k) s -= P[i * d + k] * P[j * d + k];
+      P[i * d + j] = s / ljj;
+    }
+    __syncthreads();
+  }
+  double ld = 0.0, lg = 0.0;
+  for (int i = tid; i < d; i += BLOCK) {
+    ld += log(P[i * d + i]);
+    // log Gamma_d(nu_n / 2) - log Gamma_d(nu / 2), term j = i + 1
+    lg += lgamma(0.5 * nun - 0.5 * i) - lgamma(0.5 * prior.nu - 0.5 * i);
+  }
+  ld = 2.0 * reduce_sum(ld, red);
+  lg = reduce_sum(lg, red);
+  if (tid == 0) {
+    if (!flag) atomicOr(err, 4);
+    out[it] = -0.5 * n * d * 1.1447298858494002 + lg + 0.5 * prior.nu * logdet_psi - 0.5 * nun * ld +
+              0.5 * d * (log(prior.kappa) - log(kn));
+  }
+}
+
+__global__ void k_logml_mult(int n_items, const LogmlItem* __restrict__ items, int V,
+                             const double* __restrict__ beta, double beta_sum, double lgamma_beta_sum,
+                             const double* __restrict__ lgamma_beta, const long long* __restrict__ counts,
+                             const long long* __restrict__ sums, double* __restrict__ out) {
+  __shared__ double red[BLOCK];
+  const int it = blockIdx.x;
+  if (it >= n_items) return;
+  const LogmlItem item = items[it];
+  long long npts = 0;
+  for (int q = 0; q < 4; ++q)
+    if (item.seg[q] >= 0) npts += counts[item.seg[q]];
+  if (npts == 0) {
+    if (threadIdx.x == 0) out[it] = 0.0;
+    return;
+  }
+  double acc = 0.0, tot = 0.0;
+  for (int v = threadIdx.x; v < V; v += BLOCK) {
+    long long c = 0;
+    for (int q = 0; q < 4; ++q)
+      if (item.seg[q] >= 0) c += sums[(size_t)item.seg[q] * V + v];
+    acc += lgamma(beta[v] + (double)c) - lgamma_beta[v];
+    tot += (double)c;
+  }
+  acc = reduce_sum(acc, red);
+  tot = reduce_sum(tot, red);
+  if (threadIdx.x == 0) out[it] = lgamma_beta_sum - lgamma(beta_sum + tot) + acc;
+}
+
+__global__ void k_relabel(long long n, const RelabelEntry* __restrict__ table, int n_entries, uint32_t t,
+                          uint64_t seed, int* __restrict__ z, unsigned char* __restrict__ zsub) {
+  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK) {
+    const int zi = z[i], zs = zsub[i];
+    const int s = 2 * zi + zs;
+    if (zi < 0 || zs > 1 || s >= n_entries) continue;  // labels outside the table stay as they are
+    const RelabelEntry e = table[s];
+    z[i] = e.new_z;
+    if (e.mode == 1) {
+      zsub[i] = 0;
+    } else if (e.mode == 2) {
+      zsub[i] = 1;
+    } else if (e.mode == 3) {
+      zsub[i] = (unsigned char)(rng_block(seed, t, (uint32_t)i, TAG_SUBINIT, 0).x & 1u);
+    }
+  }
+}
+
+__global__ void k_init_labels(long long n, uint64_t seed, int* __restrict__ z, unsigned char* __restrict__ zsub) {
+  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK) {
+    z[i] = 0;
+    zsub[i] = (unsigned char)(rng_block(seed, 0, (uint32_t)i, TAG_SUBINIT, 0).x & 1u);
+  }
+}
+
+int grid_for(long long n) {
+  long long g = (n + BLOCK - 1) / BLOCK;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_zero64(void* p, size_t n_words, hipStream_t s) {
+  if (n_words == 0) return hipSuccess;
+  size_t g = (n_words + BLOCK - 1) / BLOCK;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_zero64, dim3((unsigned)g), dim3(BLOCK), 0, s, (unsigned long long*)p, n_words);
+  return hipGetLastError();
+}
+
+hipError_t launch_logml_gauss(int n_items, const LogmlItem* items, int d, NiwPriorDev prior, double logdet_psi,
+                              const long long* counts, const double* moments, double* scratch, double* out,
+                              int* err, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_logml_gauss, dim3(n_items), dim3(BLOCK), 0, s, n_items, items, d, prior, logdet_psi,
+                     counts, moments, scratch, out, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_logml_mult(int n_items, const LogmlItem* items, int V, const double* beta, double beta_sum,
+                             double lgamma_beta_sum, const double* lgamma_beta, const long long* counts,
+                             const long long* sums, double* out, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_logml_mult, dim3(n_items), dim3(BLOCK), 0, s, n_items, items, V, beta, beta_sum,
+                     lgamma_beta_sum, lgamma_beta, counts, sums, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_relabel(long long n, const RelabelEntry* table, int n_entries, uint32_t t, uint64_t seed, int* z,
+                          unsigned char* zsub, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_relabel, dim3(grid_for(n)), dim3(BLOCK), 0, s, n, table, n_entries, t, seed, z, zsub);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_labels(long long n, uint64_t seed, int* z, unsigned char* zsub, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_labels, dim3(grid_for(n)), dim3(BLOCK), 0, s, n, seed, z, zsub);
+  return hipGetLastError();
+}
+
+}  // namespace dpmm

@@ -1,0 +1,96 @@
+"""CPU tests of the C ABI: the library loads, exports every function the
+header declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2204_08988_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dpmm.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dpmm_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def _cfg(**kw):
+    d = kw.pop("d", 2)
+    m = np.zeros(d)
+    psi = np.eye(d)
+    cfg = _lib.Config()
+    cfg.family = kw.pop("family", _lib.GAUSSIAN)
+    cfg.d = d
+    cfg.k_max = kw.pop("k_max", 16)
+    cfg.burn_out = kw.pop("burn_out", 0)
+    cfg.alpha = kw.pop("alpha", 1.0)
+    cfg.kappa = kw.pop("kappa", 1.0)
+    cfg.nu = kw.pop("nu", d + 3.0)
+    psi = kw.pop("psi", psi)
+    keep = [m, psi]
+    cfg.m = m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    cfg.psi = psi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if psi is not None else None
+    beta = kw.pop("beta", None)
+    if beta is not None:
+        keep.append(beta)
+        cfg.beta = beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    cfg.seed = 1
+    cfg.precision = kw.pop("precision", _lib.FP32)
+    cfg.merge_form = kw.pop("merge_form", _lib.MERGE_PAPER)
+    assert not kw
+    return cfg, keep
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(family=7), -1),
+    (dict(d=0), -1),
+    (dict(d=129), -1),
+    (dict(k_max=0), -1),
+    (dict(k_max=5000), -1),
+    (dict(burn_out=-1), -1),
+    (dict(alpha=0.0), -1),
+    (dict(alpha=float("nan")), -1),
+    (dict(kappa=-1.0), -1),
+    (dict(nu=0.5), -1),
+    (dict(precision=9), -1),
+    (dict(merge_form=3), -1),
+    (dict(psi=np.array([[1.0, 2.0], [2.0, 1.0]])), -4),
+    (dict(psi=np.array([[1.0, 0.5], [0.4, 1.0]])), -4),
+    (dict(family=_lib.MULTINOMIAL, d=4), -1),
+    (dict(family=_lib.MULTINOMIAL, d=3, beta=np.array([1.0, 0.0, 1.0])), -1),
+])
+def test_create_rejects_bad_config_before_device(kw, status):
+    L = _lib.lib()
+    cfg, keep = _cfg(**kw)
+    ctx = ctypes.c_void_p()
+    s = L.dpmm_create(ctypes.byref(cfg), None, ctypes.byref(ctx))
+    assert s == status, L.dpmm_last_error(None)
+    assert not ctx.value
+    assert len(L.dpmm_last_error(None)) > 0
+
+
+def test_null_arguments():
+    L = _lib.lib()
+    ctx = ctypes.c_void_p()
+    assert L.dpmm_create(None, None, ctypes.byref(ctx)) == -1
+    cfg, keep = _cfg()
+    assert L.dpmm_create(ctypes.byref(cfg), None, None) == -1
+    assert L.dpmm_sample_params(None, 1) == -1
+    assert L.dpmm_step(None, None, 0, 1, None, None, None) == -1
+    L.dpmm_destroy(None)
+    assert L.dpmm_status_string(-3) == b"capacity exceeded"
