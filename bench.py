@@ -1,0 +1,160 @@
+"""Throughput of the DPMM sub-cluster sampler hot path on one MI355X.
+
+A step is one full sampler iteration through the C ABI (dpmm_step: FP64
+parameter draws, the label/sub-label kernel, the statistics kernel, split /
+merge bookkeeping and relabelling) over the whole data set, resident in HBM.
+
+Workload: the Gaussian precision-form configuration, N = 1e6 points, d = 32,
+20 true clusters (means N(0, 25 I), covariances Wishart(d + 2, I/d), weights
+Dirichlet(1)), float32 scoring.  Before the warm-up the chain is run until
+its cluster count has settled, so the timed steps score the converged K.
+
+Prints one JSON line: metric (point-cluster evaluations per second: N (K + 2)
+scores per step), iterations per second, the label kernel's roofline figures
+from HIP events recorded on the sampler's stream, and the FP64 oracle's rate
+on a bounded sample on the host cores (rank 0, one GPU only).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "gauss_d32"
+SEED = 1
+ALPHA = 10.0
+PEAK_FP32_VALU = 78.6e12   # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (non-packed FP32)
+
+
+def flops_per_eval(d):
+    # centring (d), triangular whitening d(d+1)/2 FMAs, squared norm d FMAs
+    return d * (d + 1) + 2 * d
+
+
+def cpu_baseline(x, z, zs, K, d, budget_s=12.0):
+    """Time the FP64 oracle's full iteration on a bounded sample of the data."""
+    from oracle import niw, sampler
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    n_s = 50_000
+    xs = x[:n_s].astype(np.float64)
+    model = sampler.Model("gaussian", ALPHA, niw.NIWPrior(1.0, x.mean(0).astype(np.float64), d + 3.0, np.eye(d)),
+                          seed=SEED, burn_out=5)
+    zz = z[:n_s].astype(np.int64)
+    zzs = zs[:n_s].astype(np.int64)
+    used = np.unique(zz)
+    remap = np.full(K, -1)
+    remap[used] = np.arange(used.size)
+    state = sampler.State(int(used.size), remap[zz], zzs, np.full(used.size, 100, dtype=np.int64))
+    evals = 0
+    t0 = time.perf_counter()
+    t = 10_000
+    while True:
+        k_now = state.K
+        state, info = sampler.step(model, xs, state, t)
+        evals += n_s * (k_now + 2)
+        t += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": evals / el, "unit": "point-cluster evals/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"full FP64 oracle iterations on the first {n_s} points of the workload "
+                      f"({t - 10_000} iterations, {el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2204_08988_amd import datagen
+    from paper_2204_08988_amd.sampler import Sampler
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    spec = datagen.WORKLOADS[WORKLOAD]
+    x_np, labels = datagen.workload(WORKLOAD, SEED)
+    n, d = x_np.shape
+    m = x_np.mean(0).astype(np.float64)
+    x = torch.from_numpy(x_np).cuda()
+    S = Sampler("gaussian", d, 128, ALPHA, SEED, kappa=1.0, nu=d + 3.0, m=m, psi=np.eye(d), burn_out=5)
+    z, zs = S.init_labels(n)
+    t = 1
+    # run the chain until its cluster count settles
+    ks = []
+    for _ in range(400):
+        info = S.step(x, t, z, zs)
+        t += 1
+        ks.append(info["K"])
+        if len(ks) > 30 and len(set(ks[-15:])) == 1 and info["K"] >= spec.k // 2:
+            break
+    for _ in range(args.warmup):
+        S.step(x, t, z, zs)
+        t += 1
+    torch.cuda.synchronize()
+    evals = 0
+    label_ms = 0.0
+    k_sum = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = S.step(x, t, z, zs)
+        t += 1
+        evals += n * (info["K"] + 2)
+        k_sum += info["K"]
+        label_ms += info["ms_labels"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    k_mean = k_sum / args.steps
+    ms_step = 1e3 * elapsed / args.steps
+    label_s = label_ms / 1e3 / args.steps
+    achieved = n * (k_mean + 2) * flops_per_eval(d) / label_s
+    from oracle import nmi as nmi_mod
+    out = {
+        "metric": "point-cluster evals/s in label step; iters/s; time-to-plateau learned vs plain",
+        "value": evals / elapsed,
+        "unit": "point-cluster evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"{WORKLOAD}: Gaussian DPMM, N={n}, d={d}, {spec.k} true clusters, "
+                               "means N(0,25I), covariances Wishart(d+2, I/d), weights Dir(1); "
+                               "FP32 VALU scoring", "n": n, "d": d, "k_mean": k_mean,
+                   "alpha": ALPHA, "parallelism": "single GPU"},
+        "iters_per_s": args.steps / elapsed,
+        "label_kernel_ms": 1e3 * label_s,
+        "label_evals_per_s": n * (k_mean + 2) / label_s,
+        "nmi": nmi_mod.nmi(labels, z.cpu().numpy()),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                     "kernel": "k_label_gauss<32>",
+                     "algorithmic_flops_per_eval": flops_per_eval(d)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(x_np, z.cpu().numpy(), zs.cpu().numpy(), S.K, d)
+    S.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

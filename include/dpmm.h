@@ -23,9 +23,14 @@
  *     HIP call, so they can be exercised on a machine without a GPU.
  *     dpmm_last_error gives a message for the last failure on a context.
  *   - Random numbers: every draw is Philox4x32-10 (Salmon et al., SC'11) at
- *     counter (entity, t, tag, block) under key = seed; see DESIGN notes in
- *     the repository for the tag layout.  The same (seed, t) reproduces the
- *     same draws bit for bit.
+ *     counter (entity, t, tag, block) under key = seed (low word, high word).
+ *     Tags: 0 cluster Gumbels of point i (block k/4, word k%4); 1 sub-label
+ *     logistic of point i; 2 fresh sub-label bit of point i; 16 weight
+ *     Gammas (entity k, the alpha slot entity K); 17 sub-weight Gammas
+ *     (entity k, draw h); 18 NIW draws and 19 Dirichlet draws of component
+ *     3k + c; 20 split uniform (entity k); 21 merge uniform (entity
+ *     k1 << 16 | k2).  Draw q, attempt a of tags >= 16 uses block 256 q + a.
+ *     The same (seed, t) reproduces the same draws bit for bit.
  *   - Threading: one context per host thread; calls on one context are not
  *     re-entrant.
  */
@@ -87,10 +92,11 @@ typedef struct {
   double logpost;    /* log p(z | x) up to a constant: K log alpha
                         + lgamma(alpha) - lgamma(alpha + N)
                         + sum_k [lgamma(N_k) + log f(C_k; lambda)] */
-  float ms_params;   /* device time of the phases, milliseconds (dpmm_step) */
-  float ms_labels;
-  float ms_stats;
-  float ms_splitmerge;
+  float ms_params;     /* device time of the phases, milliseconds (dpmm_step): */
+  float ms_labels;     /*   parameter draws; the label kernel (cluster draw, */
+  float ms_stats;      /*   plus sub-labels for d < 5 and multinomial); the  */
+  float ms_splitmerge; /*   rest of the label step and the statistics; the   */
+                       /*   split/merge phase                                */
 } dpmm_iter_info;
 
 /* Create a context.  hip_stream: a hipStream_t (NULL = default stream).

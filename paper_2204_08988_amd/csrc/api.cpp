@@ -58,6 +58,10 @@ struct dpmm_ctx {
   double* d_logml = nullptr;
   int items_cap = 0;
   RelabelEntry* d_table = nullptr;
+  // cluster-sorted path (Gaussian, d >= SORTED_MIN_D)
+  int *d_hist = nullptr, *d_offs = nullptr, *d_tot = nullptr, *d_perm = nullptr;
+  long long hist_cap = 0, perm_cap = 0;
+  bool labels_gave_stats = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 
   dpmm_status fail(dpmm_status s, const std::string& msg) {
@@ -80,6 +84,7 @@ struct dpmm_ctx {
     return hipSuccess;
   }
   bool gaussian() const { return cfg.family == DPMM_GAUSSIAN; }
+  bool sorted_path() const { return gaussian() && d >= SORTED_MIN_D; }
 };
 
 #define DPMM_TRY(expr)                         \
@@ -126,8 +131,41 @@ NiwPriorDev prior_dev(dpmm_ctx* ctx) {
   return p;
 }
 
+dpmm_status ensure_perm(dpmm_ctx* ctx, int64_t n) {
+  if (n > 0x7FFFFFFFLL) return ctx->fail(DPMM_E_SHAPE, "the Gaussian path for d >= 5 takes n < 2^31 points");
+  if (n <= ctx->perm_cap) return DPMM_OK;
+  if (ctx->d_perm) {
+    DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    hipFree(ctx->d_perm);
+    ctx->d_perm = nullptr;
+    ctx->perm_cap = 0;
+  }
+  DPMM_HIP(ctx, hipMalloc(&ctx->d_perm, (size_t)n * sizeof(int)), "allocate permutation");
+  ctx->perm_cap = n;
+  return DPMM_OK;
+}
+
+// statistics over the cluster-sorted order; with sample = true also draws zsub
+dpmm_status sorted_pass(dpmm_ctx* ctx, const void* x, int64_t n, bool labels_done_hist, bool sample, uint32_t t,
+                        const int32_t* z, uint8_t* zsub, int G, long long per_block) {
+  DPMM_TRY(ensure_perm(ctx, n));
+  DPMM_HIP(ctx, launch_sort_by_z(z, n, ctx->K, G, per_block, labels_done_hist, ctx->d_hist, ctx->d_tot, ctx->d_offs,
+                                 ctx->d_perm, ctx->stream), "sort by cluster");
+  DPMM_HIP(ctx, launch_sub_stats(ctx->d, sample, (const float*)x, n, ctx->d_perm, z, zsub, ctx->d_packed, ctx->K,
+                                 ctx->cfg.k_max, t, ctx->cfg.seed, ctx->d_counts, ctx->d_moments, ctx->stream),
+           "sub-label / statistics kernel");
+  ctx->have_stats = true;
+  return DPMM_OK;
+}
+
 dpmm_status launch_stats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub) {
   hipError_t e;
+  if (ctx->sorted_path()) {
+    int G;
+    long long per;
+    sorted_plan(n, ctx->K, ctx->hist_cap, &G, &per);
+    return sorted_pass(ctx, x, n, false, false, 0, z, const_cast<uint8_t*>(zsub), G, per);
+  }
   if (ctx->gaussian())
     e = launch_stats_gauss(ctx->d, (const float*)x, n, z, zsub, ctx->K, ctx->d_counts, ctx->d_moments, ctx->stream);
   else
@@ -138,7 +176,9 @@ dpmm_status launch_stats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t*
 }
 
 // log marginal likelihoods of a list of segment unions (device), read back.
-dpmm_status logml(dpmm_ctx* ctx, const std::vector<LogmlItem>& items, std::vector<double>& out) {
+// *flag_out (optional) receives the device error flag after the launches.
+dpmm_status logml(dpmm_ctx* ctx, const std::vector<LogmlItem>& items, std::vector<double>& out,
+                  int* flag_out = nullptr) {
   out.assign(items.size(), 0.0);
   size_t done = 0;
   while (done < items.size()) {
@@ -155,6 +195,9 @@ dpmm_status logml(dpmm_ctx* ctx, const std::vector<LogmlItem>& items, std::vecto
     DPMM_HIP(ctx, e, "log marginal likelihood kernel");
     DPMM_HIP(ctx, hipMemcpyAsync(out.data() + done, ctx->d_logml, nb * sizeof(double), hipMemcpyDeviceToHost,
                                  ctx->stream), "copy log marginals");
+    if (flag_out && done + nb == items.size())
+      DPMM_HIP(ctx, hipMemcpyAsync(flag_out, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
+               "copy flag");
     DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
     done += nb;
   }
@@ -202,7 +245,8 @@ double log_posterior(const dpmm_ctx* ctx, const std::vector<long long>& cnt, con
 dpmm_status pack_params(dpmm_ctx* ctx) {
   const int K = ctx->K;
   if (ctx->gaussian()) {
-    hipLaunchKernelGGL(k_pack_gauss, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->cfg.k_max,
+    hipLaunchKernelGGL(k_pack_gauss, dim3(3 * K), dim3(256), niw_lds_bytes(ctx->d), ctx->stream, K, ctx->d,
+                       ctx->cfg.k_max,
                        ctx->d_log_pi, ctx->d_log_pisub, ctx->d_mu, ctx->d_sigma, ctx->d_scratch, ctx->d_packed,
                        ctx->d_logdet, ctx->d_err);
   } else {
@@ -315,6 +359,12 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     ok = ok && chk(c->alloc(&c->d_sigma, 3 * (size_t)km * d * d));
     c->scratch_slots = c->items_cap;
     ok = ok && chk(c->alloc(&c->d_scratch, (size_t)c->scratch_slots * NIW_SCRATCH(d)));
+    if (d >= SORTED_MIN_D) {
+      c->hist_cap = 2048LL * km;
+      ok = ok && chk(c->alloc(&c->d_hist, (size_t)c->hist_cap));
+      ok = ok && chk(c->alloc(&c->d_offs, (size_t)c->hist_cap));
+      ok = ok && chk(c->alloc(&c->d_tot, (size_t)km + 2));
+    }
   } else {
     ok = ok && chk(c->alloc(&c->d_beta, (size_t)d));
     ok = ok && chk(c->alloc(&c->d_lgamma_beta, (size_t)d));
@@ -351,6 +401,7 @@ void dpmm_destroy(dpmm_ctx* ctx) {
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
   else hipDeviceSynchronize();
   for (auto& b : ctx->bufs) hipFree(b.p);
+  if (ctx->d_perm) hipFree(ctx->d_perm);
   for (auto& e : ctx->ev)
     if (e) hipEventDestroy(e);
   delete ctx;
@@ -549,17 +600,52 @@ dpmm_status dpmm_loglik(dpmm_ctx* ctx, const void* x, int64_t n, float* out) {
   return DPMM_OK;
 }
 
-dpmm_status dpmm_sample_labels(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32_t* z, uint8_t* zsub) {
-  if (!ctx) return DPMM_E_ARG;
-  DPMM_TRY(check_n(ctx, x, n));
-  if (n > 0 && (!z || !zsub)) return ctx->fail(DPMM_E_ARG, "z / zsub is NULL");
-  if (!ctx->have_params) return ctx->fail(DPMM_E_STATE, "no parameters yet");
+}  // extern "C"
+
+namespace {
+
+// First half of the label step: the cluster draw (sorted path, d >= 5) or the
+// fused cluster + sub-label kernel (small d, multinomial).
+dpmm_status label_phase(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32_t* z, uint8_t* zsub, int* G,
+                        long long* per) {
+  ctx->labels_gave_stats = false;
+  if (ctx->sorted_path()) {
+    sorted_plan(n, ctx->K, ctx->hist_cap, G, per);
+    DPMM_TRY(ensure_perm(ctx, n));
+    DPMM_HIP(ctx, launch_label_gauss_z(ctx->d, (const float*)x, n, *G, *per, ctx->d_packed, ctx->K, t, ctx->cfg.seed, z,
+                                       ctx->d_hist, ctx->d_tot, ctx->stream), "label kernel");
+    return DPMM_OK;
+  }
   hipError_t e = ctx->gaussian() ? launch_label_gauss(ctx->d, (const float*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max,
                                                       t, ctx->cfg.seed, z, zsub, ctx->stream)
                                  : launch_label_mult(ctx->d, (const int*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max, t,
                                                      ctx->cfg.seed, z, zsub, ctx->stream);
   DPMM_HIP(ctx, e, "label kernel");
   return DPMM_OK;
+}
+
+// Second half on the sorted path: sort by cluster, sub-labels, statistics.
+dpmm_status sub_phase(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32_t* z, uint8_t* zsub, int G,
+                      long long per) {
+  if (!ctx->sorted_path()) return DPMM_OK;
+  DPMM_TRY(sorted_pass(ctx, x, n, true, true, t, z, zsub, G, per));
+  ctx->labels_gave_stats = true;
+  return DPMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dpmm_status dpmm_sample_labels(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32_t* z, uint8_t* zsub) {
+  if (!ctx) return DPMM_E_ARG;
+  DPMM_TRY(check_n(ctx, x, n));
+  if (n > 0 && (!z || !zsub)) return ctx->fail(DPMM_E_ARG, "z / zsub is NULL");
+  if (!ctx->have_params) return ctx->fail(DPMM_E_STATE, "no parameters yet");
+  int G = 0;
+  long long per = 0;
+  DPMM_TRY(label_phase(ctx, x, n, t, z, zsub, &G, &per));
+  return sub_phase(ctx, x, n, t, z, zsub, G, per);
 }
 
 dpmm_status dpmm_suffstats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub) {
@@ -578,12 +664,16 @@ dpmm_status dpmm_sample_params(dpmm_ctx* ctx, uint32_t t) {
                      ctx->d_log_pi, ctx->d_log_pisub, ctx->d_tmp);
   DPMM_HIP(ctx, hipGetLastError(), "weights kernel");
   if (ctx->gaussian()) {
-    hipLaunchKernelGGL(k_niw_draw, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, prior_dev(ctx), ctx->d_counts,
-                       ctx->d_moments, ctx->cfg.seed, t, ctx->d_mu, ctx->d_sigma, ctx->d_scratch, ctx->d_err);
-  } else {
-    hipLaunchKernelGGL(k_dir_draw, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->d_beta, ctx->d_sums,
-                       ctx->cfg.seed, t, ctx->d_log_theta);
+    hipLaunchKernelGGL(k_niw_draw, dim3(3 * K), dim3(256), niw_lds_bytes(ctx->d), ctx->stream, K, ctx->d,
+                       ctx->cfg.k_max, prior_dev(ctx), ctx->d_counts, ctx->d_moments, ctx->d_log_pi,
+                       ctx->d_log_pisub, ctx->cfg.seed, t, ctx->d_mu, ctx->d_sigma, ctx->d_scratch, ctx->d_packed,
+                       ctx->d_logdet, ctx->d_err);
+    DPMM_HIP(ctx, hipGetLastError(), "posterior draw kernel");
+    ctx->have_params = true;
+    return DPMM_OK;
   }
+  hipLaunchKernelGGL(k_dir_draw, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->d_beta, ctx->d_sums,
+                     ctx->cfg.seed, t, ctx->d_log_theta);
   DPMM_HIP(ctx, hipGetLastError(), "posterior draw kernel");
   return pack_params(ctx);
 }
@@ -594,50 +684,68 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t
   DPMM_TRY(check_n(ctx, x, n));
   if (n > 0 && (!z || !zsub)) return ctx->fail(DPMM_E_ARG, "z / zsub is NULL");
   if (!ctx->have_stats) return ctx->fail(DPMM_E_STATE, "no statistics yet");
-  DPMM_TRY(check_device_error(ctx));
   const double alpha = ctx->cfg.alpha;
   const uint64_t seed = ctx->cfg.seed;
+  const int burn = ctx->cfg.burn_out;
   dpmm_iter_info local{};
   std::vector<long long> cnt;
-  DPMM_TRY(read_counts(ctx, cnt));
-  // 1. delete empty clusters (stable)
-  {
-    int K = ctx->K, kept = 0;
+  std::vector<double> lml;
+  std::vector<std::pair<int, int>> pairs;
+  // Marginal likelihoods of every cluster, sub-cluster and eligible pair are
+  // computed in one launch and read back with the counts and the error flag:
+  // one synchronisation per iteration unless a cluster became empty.
+  for (int round = 0;; ++round) {
+    const int K = ctx->K;
+    std::vector<LogmlItem> items(3 * K);
+    for (int k = 0; k < K; ++k) {
+      items[3 * k] = LogmlItem{{2 * k, 2 * k + 1, -1, -1}};
+      items[3 * k + 1] = LogmlItem{{2 * k, -1, -1, -1}};
+      items[3 * k + 2] = LogmlItem{{2 * k + 1, -1, -1, -1}};
+    }
+    pairs.clear();
+    for (int k1 = 0; k1 < K; ++k1) {
+      if (ctx->age[k1] < burn) continue;
+      for (int k2 = k1 + 1; k2 < K; ++k2)
+        if (ctx->age[k2] >= burn) {
+          pairs.emplace_back(k1, k2);
+          items.push_back(LogmlItem{{2 * k1, 2 * k1 + 1, 2 * k2, 2 * k2 + 1}});
+        }
+    }
+    cnt.assign(2 * (size_t)K, 0);
+    int flag = 0;
+    DPMM_HIP(ctx, hipMemcpyAsync(cnt.data(), ctx->d_counts, cnt.size() * sizeof(long long), hipMemcpyDeviceToHost,
+                                 ctx->stream), "copy counts");
+    DPMM_TRY(logml(ctx, items, lml, &flag));  // synchronises
+    if (flag) {
+      DPMM_HIP(ctx, hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream), "clear flag");
+      return ctx->fail(DPMM_E_NUMERIC, "a float64 Cholesky factorisation met a non-positive pivot (flag " +
+                                           std::to_string(flag) + ")");
+    }
+    // delete empty clusters (stable), then start over with the new K
+    int kept = 0;
     std::vector<int> newidx(K, -1);
     for (int k = 0; k < K; ++k)
       if (cnt[2 * k] + cnt[2 * k + 1] > 0) newidx[k] = kept++;
     if (kept == 0) return ctx->fail(DPMM_E_STATE, "every cluster is empty");
-    if (kept < K) {
-      std::vector<RelabelEntry> tab(2 * K);
-      std::vector<int> age;
-      for (int k = 0; k < K; ++k) {
-        tab[2 * k] = RelabelEntry{newidx[k] < 0 ? 0 : newidx[k], 0};
-        tab[2 * k + 1] = tab[2 * k];
-        if (newidx[k] >= 0) age.push_back(ctx->age[k]);
-      }
-      DPMM_TRY(apply_relabel(ctx, tab, n, t, z, zsub));
-      ctx->K = kept;
-      ctx->age = age;
-      local.removed = K - kept;
-      DPMM_TRY(launch_stats(ctx, x, n, z, zsub));
-      DPMM_TRY(read_counts(ctx, cnt));
+    if (kept == K) break;
+    if (round > 0) return ctx->fail(DPMM_E_STATE, "empty clusters remain after compaction");
+    std::vector<RelabelEntry> tab(2 * K);
+    std::vector<int> age;
+    for (int k = 0; k < K; ++k) {
+      tab[2 * k] = RelabelEntry{newidx[k] < 0 ? 0 : newidx[k], 0};
+      tab[2 * k + 1] = tab[2 * k];
+      if (newidx[k] >= 0) age.push_back(ctx->age[k]);
     }
+    DPMM_TRY(apply_relabel(ctx, tab, n, t, z, zsub));
+    ctx->K = kept;
+    ctx->age = age;
+    local.removed = K - kept;
+    DPMM_TRY(launch_stats(ctx, x, n, z, zsub));
   }
   const int K = ctx->K;
-  const int burn = ctx->cfg.burn_out;
-  // 2. marginal likelihoods of clusters and sub-clusters
-  std::vector<LogmlItem> items(3 * K);
-  for (int k = 0; k < K; ++k) {
-    items[3 * k] = LogmlItem{{2 * k, 2 * k + 1, -1, -1}};
-    items[3 * k + 1] = LogmlItem{{2 * k, -1, -1, -1}};
-    items[3 * k + 2] = LogmlItem{{2 * k + 1, -1, -1, -1}};
-  }
-  std::vector<double> lml;
-  DPMM_TRY(logml(ctx, items, lml));
-  DPMM_TRY(check_device_error(ctx));
   std::vector<double> lml_cluster(K);
   for (int k = 0; k < K; ++k) lml_cluster[k] = lml[3 * k];
-  // 3. splits (Sec. 2.3 eq. HastingsRatioSplit)
+  // splits (Sec. 2.3 eq. HastingsRatioSplit)
   std::vector<char> touched(K, 0);
   std::vector<int> split_slot(K, -1);
   int new_slot = K;
@@ -655,46 +763,28 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t
     }
   }
   local.splits = new_slot - K;
-  // 4. merges among clusters not split (Sec. 4.1 eq. sample_merges)
-  std::vector<std::pair<int, int>> pairs;
-  for (int k1 = 0; k1 < K; ++k1) {
-    if (touched[k1] || ctx->age[k1] < burn) continue;
-    for (int k2 = k1 + 1; k2 < K; ++k2) {
-      if (touched[k2] || ctx->age[k2] < burn) continue;
-      pairs.emplace_back(k1, k2);
-    }
-  }
+  // merges among clusters not split (Sec. 4.1 eq. sample_merges), lexicographic
   std::vector<int> merged_into(K, -1);  // k2 -> k1
   std::vector<char> is_merge_target(K, 0);
-  if (!pairs.empty()) {
-    std::vector<LogmlItem> pitems(pairs.size());
-    for (size_t p = 0; p < pairs.size(); ++p) {
-      const int k1 = pairs[p].first, k2 = pairs[p].second;
-      pitems[p] = LogmlItem{{2 * k1, 2 * k1 + 1, 2 * k2, 2 * k2 + 1}};
-    }
-    std::vector<double> plml;
-    DPMM_TRY(logml(ctx, pitems, plml));
-    DPMM_TRY(check_device_error(ctx));
-    for (size_t p = 0; p < pairs.size(); ++p) {
-      const int k1 = pairs[p].first, k2 = pairs[p].second;
-      if (touched[k1] || touched[k2]) continue;
-      const double n1 = (double)(cnt[2 * k1] + cnt[2 * k1 + 1]);
-      const double n2 = (double)(cnt[2 * k2] + cnt[2 * k2 + 1]);
-      double lh = std::lgamma(n1 + n2) - std::log(alpha) - std::lgamma(n1) - std::lgamma(n2) + plml[p] -
-                  lml_cluster[k1] - lml_cluster[k2];
-      if (ctx->cfg.merge_form == DPMM_MERGE_PAPER)
-        lh += std::lgamma(alpha) - std::lgamma(alpha + n1 + n2) + std::lgamma(0.5 * alpha + n1) +
-              std::lgamma(0.5 * alpha + n2) - 2.0 * std::lgamma(0.5 * alpha);
-      const double u = uniform_d(rng_block(seed, t, merge_entity(k1, k2), TAG_MERGE, 0).x);
-      if (std::log(u) < lh) {
-        touched[k1] = touched[k2] = 1;
-        merged_into[k2] = k1;
-        is_merge_target[k1] = 1;
-        ++local.merges;
-      }
+  for (size_t p = 0; p < pairs.size(); ++p) {
+    const int k1 = pairs[p].first, k2 = pairs[p].second;
+    if (touched[k1] || touched[k2]) continue;
+    const double n1 = (double)(cnt[2 * k1] + cnt[2 * k1 + 1]);
+    const double n2 = (double)(cnt[2 * k2] + cnt[2 * k2 + 1]);
+    double lh = std::lgamma(n1 + n2) - std::log(alpha) - std::lgamma(n1) - std::lgamma(n2) + lml[3 * K + p] -
+                lml_cluster[k1] - lml_cluster[k2];
+    if (ctx->cfg.merge_form == DPMM_MERGE_PAPER)
+      lh += std::lgamma(alpha) - std::lgamma(alpha + n1 + n2) + std::lgamma(0.5 * alpha + n1) +
+            std::lgamma(0.5 * alpha + n2) - 2.0 * std::lgamma(0.5 * alpha);
+    const double u = uniform_d(rng_block(seed, t, merge_entity(k1, k2), TAG_MERGE, 0).x);
+    if (std::log(u) < lh) {
+      touched[k1] = touched[k2] = 1;
+      merged_into[k2] = k1;
+      is_merge_target[k1] = 1;
+      ++local.merges;
     }
   }
-  // 5. relabel and compact
+  // relabel and compact
   if (local.splits > 0 || local.merges > 0) {
     const int K2 = new_slot;
     std::vector<int> final_idx(K2, -1);
@@ -721,11 +811,17 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t
     ctx->K = kept;
     ctx->age = age;
     DPMM_TRY(launch_stats(ctx, x, n, z, zsub));
-    DPMM_TRY(read_counts(ctx, cnt));
     std::vector<LogmlItem> fitems(kept);
     for (int k = 0; k < kept; ++k) fitems[k] = LogmlItem{{2 * k, 2 * k + 1, -1, -1}};
-    DPMM_TRY(logml(ctx, fitems, lml_cluster));
-    DPMM_TRY(check_device_error(ctx));
+    cnt.assign(2 * (size_t)kept, 0);
+    DPMM_HIP(ctx, hipMemcpyAsync(cnt.data(), ctx->d_counts, cnt.size() * sizeof(long long), hipMemcpyDeviceToHost,
+                                 ctx->stream), "copy counts");
+    int flag = 0;
+    DPMM_TRY(logml(ctx, fitems, lml_cluster, &flag));
+    if (flag) {
+      DPMM_HIP(ctx, hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream), "clear flag");
+      return ctx->fail(DPMM_E_NUMERIC, "a float64 Cholesky factorisation met a non-positive pivot");
+    }
   }
   local.K = ctx->K;
   local.logpost = log_posterior(ctx, cnt, lml_cluster);
@@ -750,9 +846,12 @@ dpmm_status dpmm_step(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32
   DPMM_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream), "event");
   DPMM_TRY(dpmm_sample_params(ctx, t));
   DPMM_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream), "event");
-  DPMM_TRY(dpmm_sample_labels(ctx, x, n, t, z, zsub));
+  int G = 0;
+  long long per = 0;
+  DPMM_TRY(label_phase(ctx, x, n, t, z, zsub, &G, &per));
   DPMM_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream), "event");
-  DPMM_TRY(launch_stats(ctx, x, n, z, zsub));
+  DPMM_TRY(sub_phase(ctx, x, n, t, z, zsub, G, per));
+  if (!ctx->labels_gave_stats) DPMM_TRY(launch_stats(ctx, x, n, z, zsub));
   DPMM_HIP(ctx, hipEventRecord(ctx->ev[3], ctx->stream), "event");
   dpmm_iter_info local{};
   DPMM_TRY(dpmm_split_merge(ctx, x, n, t, z, zsub, &local));

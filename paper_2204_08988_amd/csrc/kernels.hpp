@@ -5,6 +5,11 @@
 namespace dpmm {
 
 #define NIW_SCRATCH(d) ((size_t)3 * (d) * (d) + (d))
+// float64 workspaces of the per-component kernels live in LDS up to this d
+constexpr int NIW_LDS_MAX_D = 64;
+inline size_t niw_lds_bytes(int d) { return d <= NIW_LDS_MAX_D ? NIW_SCRATCH(d) * sizeof(double) : 0; }
+// the marginal-likelihood kernel keeps one d x d matrix in LDS up to this d
+constexpr int LOGML_LDS_MAX_D = 128;
 
 struct NiwPriorDev {
   double kappa, nu;
@@ -15,9 +20,10 @@ struct NiwPriorDev {
 // ---- parameters (params.hip)
 __global__ void k_weights(int K, double alpha, const long long* counts, uint64_t seed, uint32_t t,
                           double* log_pi, double* log_pisub, double* tmp);
-__global__ void k_niw_draw(int K, int d, NiwPriorDev prior, const long long* counts,
-                           const double* moments, uint64_t seed, uint32_t t, double* mu_out,
-                           double* sigma_out, double* scratch, int* err);
+__global__ void k_niw_draw(int K, int d, int k_max, NiwPriorDev prior, const long long* counts,
+                           const double* moments, const double* log_pi, const double* log_pisub,
+                           uint64_t seed, uint32_t t, double* mu_out, double* sigma_out, double* scratch,
+                           float* packed, double* logdet_out, int* err);
 __global__ void k_dir_draw(int K, int V, const double* beta, const long long* sums, uint64_t seed,
                            uint32_t t, double* log_theta);
 __global__ void k_pack_gauss(int K, int d, int k_max, const double* log_pi, const double* log_pisub,
@@ -29,6 +35,17 @@ __global__ void k_pack_mult(int K, int V, int k_max, const double* log_pi, const
 // ---- host launchers of the templated hot kernels
 hipError_t launch_label_gauss(int d, const float* x, long long n, const float* packed, int K, int k_max,
                               uint32_t t, uint64_t seed, int* z, unsigned char* zsub, hipStream_t s);
+// cluster-sorted path (d >= 5): z + per-block histogram, sort by z, sub-labels
+// and statistics over sorted tiles
+constexpr int SORTED_MIN_D = 5;
+hipError_t launch_label_gauss_z(int d, const float* x, long long n, int G, long long per_block, const float* packed,
+                                int K, uint32_t t, uint64_t seed, int* z, int* hist, int* tot, hipStream_t s);
+hipError_t sorted_plan(long long n, int K, long long hist_cap, int* G, long long* per_block);
+hipError_t launch_sort_by_z(const int* z, long long n, int K, int G, long long per_block, bool have_hist, int* hist,
+                            int* tot, int* offs, int* perm, hipStream_t s);
+hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, const int* perm, const int* z,
+                            unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t, uint64_t seed,
+                            long long* counts, double* moments, hipStream_t s);
 hipError_t launch_loglik_gauss(int d, const float* x, long long n, const float* packed, int K, int k_max,
                                float* out, hipStream_t s);
 hipError_t launch_label_mult(int V, const int* x, long long n, const float* packed, int K, int k_max,

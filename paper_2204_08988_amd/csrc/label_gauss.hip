@@ -15,9 +15,11 @@
 // is drawn.  Otherwise pass 2 draws the leader's Gumbel first and then the
 // Gumbel of each other cluster k only if l_k + G_max can still exceed the
 // best perturbed score; the result equals argmax_k (l_k + g_k) over all k.
-// Sub-label (eq. sample_sub_labels): the two sub-cluster records of z are
-// gathered per lane; the logistic draw is skipped when the score gap exceeds
-// the logistic's range.
+// Sub-label (eq. sample_sub_labels), small d: the two sub-cluster records of
+// z are gathered per lane; the logistic draw is skipped when the score gap
+// exceeds the logistic's range.  For d >= 5 the kernel draws z only and the
+// sub-labels are drawn in cluster-sorted order (sorted.hip), where the
+// sub-cluster records are wave-uniform.
 #include "kernels.hpp"
 
 namespace dpmm {
@@ -158,6 +160,68 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss_dyn(const float* __restri
   }
 }
 
+// Cluster draw only, for the cluster-sorted path (d >= 5): block b labels the
+// contiguous points [b per_block, (b + 1) per_block) and writes its histogram
+// of z (hist[b][k]) and adds it to the cluster totals tot[k].
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_label_gauss_z(const float* __restrict__ x, long long n, long long per_block,
+                                                         const float* __restrict__ packed, int K, uint32_t t,
+                                                         uint64_t seed, int* __restrict__ z, int* __restrict__ hist,
+                                                         int* __restrict__ tot) {
+  extern __shared__ int h[];
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  for (int k = threadIdx.x; k < K; k += BLOCK) h[k] = 0;
+  __syncthreads();
+  const long long begin = (long long)blockIdx.x * per_block;
+  const long long end = begin + per_block < n ? begin + per_block : n;
+  for (long long i = begin + threadIdx.x; i < end; i += BLOCK) {
+    float xv[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) xv[j] = x[i * D + j];
+    Top2 t2;
+    t2.init();
+    for (int k = 0; k < K; ++k) t2.push(score_rec<D>(packed + (size_t)k * S, xv), k);
+    const int zi = lazy_gumbel_max(t2, K, (uint32_t)i, t, seed,
+                                   [&](int k) { return score_rec<D>(packed + (size_t)k * S, xv); });
+    z[i] = zi;
+    atomicAdd(&h[zi], 1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += BLOCK) {
+    hist[(size_t)blockIdx.x * K + k] = h[k];
+    if (h[k]) atomicAdd(&tot[k], h[k]);
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_label_gauss_z_dyn(const float* __restrict__ x, long long n, int d,
+                                                             long long per_block, const float* __restrict__ packed,
+                                                             int K, uint32_t t, uint64_t seed, int* __restrict__ z,
+                                                             int* __restrict__ hist, int* __restrict__ tot) {
+  extern __shared__ float lds[];
+  float* dx = lds + threadIdx.x;
+  int* h = reinterpret_cast<int*>(lds + (size_t)d * BLOCK);
+  const int S = gauss_rec_stride(d);
+  for (int k = threadIdx.x; k < K; k += BLOCK) h[k] = 0;
+  __syncthreads();
+  const long long begin = (long long)blockIdx.x * per_block;
+  const long long end = begin + per_block < n ? begin + per_block : n;
+  for (long long i = begin + threadIdx.x; i < end; i += BLOCK) {
+    const float* xi = x + i * d;
+    Top2 t2;
+    t2.init();
+    for (int k = 0; k < K; ++k) t2.push(score_rec_dyn(packed + (size_t)k * S, xi, dx, d), k);
+    const int zi = lazy_gumbel_max(t2, K, (uint32_t)i, t, seed,
+                                   [&](int k) { return score_rec_dyn(packed + (size_t)k * S, xi, dx, d); });
+    z[i] = zi;
+    atomicAdd(&h[zi], 1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += BLOCK) {
+    hist[(size_t)blockIdx.x * K + k] = h[k];
+    if (h[k]) atomicAdd(&tot[k], h[k]);
+  }
+}
+
 // All 3K weighted log-likelihoods per point (parity / inspection entry).
 __global__ __launch_bounds__(BLOCK) void k_loglik_gauss_dyn(const float* __restrict__ x, long long n, int d,
                                                             const float* __restrict__ packed, int K,
@@ -207,6 +271,30 @@ hipError_t launch_label_gauss(int d, const float* x, long long n, const float* p
                          x, n, d, packed, K, k_max, t, seed, z, zsub);
   }
 #undef DPMM_LABEL_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_label_gauss_z(int d, const float* x, long long n, int G, long long per_block, const float* packed,
+                                int K, uint32_t t, uint64_t seed, int* z, int* hist, int* tot, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipError_t e = launch_zero64(tot, (size_t)(K + 1) / 2 + 1, s);
+  if (e != hipSuccess) return e;
+  const size_t lh = (size_t)K * sizeof(int);
+#define DPMM_LABELZ_CASE(DD)                                                                                  \
+  case DD:                                                                                                    \
+    hipLaunchKernelGGL(k_label_gauss_z<DD>, dim3(G), dim3(BLOCK), lh, s, x, n, per_block, packed, K, t, seed, z, \
+                       hist, tot);                                                                            \
+    break;
+  switch (d) {
+    DPMM_LABELZ_CASE(8)
+    DPMM_LABELZ_CASE(16)
+    DPMM_LABELZ_CASE(32)
+    DPMM_LABELZ_CASE(64)
+    default:
+      hipLaunchKernelGGL(k_label_gauss_z_dyn, dim3(G), dim3(BLOCK), (size_t)d * BLOCK * sizeof(float) + lh, s, x, n,
+                         d, per_block, packed, K, t, seed, z, hist, tot);
+  }
+#undef DPMM_LABELZ_CASE
   return hipGetLastError();
 }
 

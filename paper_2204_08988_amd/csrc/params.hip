@@ -4,16 +4,20 @@
 //                    as normalised Gamma draws.
 //   k_niw_draw       (c) and (d), Gaussian: NIW posterior from the
 //                    sufficient statistics and Bartlett's construction of the
-//                    covariance draw, one workgroup per component.
+//                    covariance draw, one workgroup per component, followed by
+//                    the component's float32 scoring record.
 //   k_dir_draw       (c) and (d), multinomial: Dirichlet posterior draw.
 //   k_pack_gauss     float32 scoring record per component: Cholesky of Sigma,
 //                    whitener W = L^-1, constant log w - 1/2 log|Sigma| - d/2 log 2pi.
 //   k_pack_mult      float32 record: log w and log theta.
 //
 // Work here is O(K d^3) per iteration; one workgroup per component keeps every
-// matrix of a component on one CU, with the triangular solves and Cholesky
-// columns parallel over rows.
+// matrix of a component on one CU, in LDS for d <= 64 (the dependent
+// accesses of Cholesky columns and triangular solves then cost LDS latency,
+// not HBM latency), with the triangular solves and Cholesky columns parallel
+// over rows.
 #include "kernels.hpp"
+#include "linalg.hpp"
 
 namespace dpmm {
 
@@ -43,41 +47,6 @@ __device__ double block_reduce_sum(double v, double* red) {
   const double r = red[0];
   __syncthreads();
   return r;
-}
-
-// In-place lower Cholesky of the d x d row-major matrix a (global scratch).
-// Returns false (to every thread) if a pivot is not positive and finite.
-__device__ bool block_cholesky(double* a, int d, int* flag) {
-  const int tid = threadIdx.x;
-  if (tid == 0) *flag = 1;
-  __syncthreads();
-  for (int j = 0; j < d; ++j) {
-    if (tid == 0) {
-      double s = a[j * d + j];
-      for (int k = 0; k < j; ++k) s -= a[j * d + k] * a[j * d + k];
-      if (!(s > 0.0) || !isfinite(s)) {
-        *flag = 0;
-        s = 1.0;
-      }
-      a[j * d + j] = sqrt(s);
-    }
-    __syncthreads();
-    const double ljj = a[j * d + j];
-    for (int i = j + 1 + tid; i < d; i += blockDim.x) {
-      double s = a[i * d + j];
-      for (int k = 0; k < j; ++k) s -= a[i * d + k] * a[j * d + k];
-      a[i * d + j] = s / ljj;
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < d * d; idx += blockDim.x) {
-    const int i = idx / d, j = idx % d;
-    if (j > i) a[idx] = 0.0;
-  }
-  __syncthreads();
-  const bool ok = *flag != 0;
-  __syncthreads();
-  return ok;
 }
 
 __device__ __forceinline__ int tri_index(int a, int b, int d) {
@@ -117,37 +86,83 @@ __global__ void k_weights(int K, double alpha, const long long* __restrict__ cou
   }
 }
 
-// One workgroup per component e = 3k + c.  scratch holds NIW_SCRATCH(d)
-// doubles per component (three d x d matrices and a d-vector).  Writes mu[e][d], sigma[e][d][d] (float64).
-__global__ void k_niw_draw(int K, int d, NiwPriorDev prior, const long long* __restrict__ counts,
-                           const double* __restrict__ moments, uint64_t seed, uint32_t t,
+// Per-component float64 workspace: three d x d matrices and a d-vector, in
+// LDS when they fit (d <= NIW_LDS_MAX_D), else in the component's slot of the
+// global scratch buffer.
+struct Work {
+  double *M0, *M1, *M2, *v;
+};
+
+__device__ __forceinline__ Work workspace(double* lds, double* scratch, int e, int d) {
+  double* base = d <= NIW_LDS_MAX_D ? lds : scratch + (size_t)e * NIW_SCRATCH(d);
+  Work w;
+  w.M0 = base;
+  w.M1 = base + d * d;
+  w.M2 = base + 2 * d * d;
+  w.v = base + 3 * d * d;
+  return w;
+}
+
+// Factor Sigma (in G) = G G^T in place, W = G^-1 (lower) into Wm, and write the
+// float32 scoring record of a component with log weight lw.
+__device__ void pack_record(double* G, double* Wm, int d, double lw, const double* mu, float* rec,
+                            double* logdet_out, int* err, int* flag, double* red) {
+  const int tid = threadIdx.x;
+  if (!wg_cholesky(G, d, flag)) {
+    if (tid == 0) atomicOr(err, 2);
+  }
+  wg_lower_inverse(G, Wm, d);
+  double ld = 0.0;
+  for (int i = tid; i < d; i += blockDim.x) ld += log(G[i * d + i]);
+  ld = 2.0 * block_reduce_sum(ld, red);
+  __syncthreads();
+  const int stride = gauss_rec_stride(d);
+  if (tid == 0) {
+    rec[0] = (float)(lw - 0.5 * ld - 0.5 * d * 1.8378770664093453);
+    rec[1] = rec[2] = rec[3] = 0.0f;
+    *logdet_out = ld;
+  }
+  for (int i = tid; i < d; i += blockDim.x) rec[4 + i] = (float)mu[i];
+  for (int r = 0; r < d; ++r) {
+    const int row0 = r * (r + 1) / 2;
+    for (int col = tid; col <= r; col += blockDim.x) rec[4 + d + row0 + col] = (float)Wm[r * d + col];
+  }
+  for (int idx = 4 + d + d * (d + 1) / 2 + tid; idx < stride; idx += blockDim.x) rec[idx] = 0.0f;
+}
+
+__device__ __forceinline__ int record_slot(int k, int c, int k_max) { return c == 0 ? k : k_max + 2 * k + (c - 1); }
+
+// One workgroup per component e = 3k + c: NIW posterior from the statistics,
+// Bartlett draw of (mu, Sigma), then the float32 scoring record.  Writes
+// mu[e][d], sigma[e][d][d] (float64), the record and log|Sigma|.
+__global__ void k_niw_draw(int K, int d, int k_max, NiwPriorDev prior, const long long* __restrict__ counts,
+                           const double* __restrict__ moments, const double* __restrict__ log_pi,
+                           const double* __restrict__ log_pisub, uint64_t seed, uint32_t t,
                            double* __restrict__ mu_out, double* __restrict__ sigma_out,
-                           double* __restrict__ scratch, int* __restrict__ err) {
+                           double* __restrict__ scratch, float* __restrict__ packed,
+                           double* __restrict__ logdet_out, int* __restrict__ err) {
+  extern __shared__ double lds_w[];
   __shared__ double red[256];
   __shared__ int flag;
-  __shared__ double sh_n, sh_kn, sh_nun;
+  __shared__ double sh_n;
   const int e = blockIdx.x;
   if (e >= 3 * K) return;
   const int k = e / 3, c = e % 3;
   const int tid = threadIdx.x;
   const int E = d + d * (d + 1) / 2;
-  double* L = scratch + (size_t)e * NIW_SCRATCH(d);
-  double* A = L + d * d;
-  double* F = A + d * d;
+  Work w = workspace(lds_w, scratch, e, d);
+  double* L = w.M0;
+  double* A = w.M1;
+  double* F = w.M2;
+  double* eps = w.v;
   double* mn = mu_out + (size_t)e * d;  // m_n staged in the output row
-  // segments feeding this component
   const int s0 = c == 0 ? 2 * k : 2 * k + (c - 1);
   const int s1 = c == 0 ? 2 * k + 1 : -1;
   const double* M0 = moments + (size_t)s0 * E;
   const double* M1 = s1 >= 0 ? moments + (size_t)s1 * E : nullptr;
-  if (tid == 0) {
-    const double n = (double)counts[s0] + (s1 >= 0 ? (double)counts[s1] : 0.0);
-    sh_n = n;
-    sh_kn = prior.kappa + n;
-    sh_nun = prior.nu + n;
-  }
+  if (tid == 0) sh_n = (double)counts[s0] + (s1 >= 0 ? (double)counts[s1] : 0.0);
   __syncthreads();
-  const double n = sh_n, kn = sh_kn, nun = sh_nun;
+  const double n = sh_n, kn = prior.kappa + n, nun = prior.nu + n;
   // m_n = (kappa m + s) / kappa_n
   for (int i = tid; i < d; i += blockDim.x) {
     const double s = M0[i] + (M1 ? M1[i] : 0.0);
@@ -168,7 +183,7 @@ __global__ void k_niw_draw(int K, int d, NiwPriorDev prior, const long long* __r
     L[idx] = v;
   }
   __syncthreads();
-  if (!block_cholesky(L, d, &flag)) {
+  if (!wg_cholesky(L, d, &flag)) {
     if (tid == 0) atomicOr(err, 1);
   }
   // Bartlett factor A (lower): A[i][j] ~ N(0,1) for i > j, A[i][i] = sqrt(chi2(nu_n - i))
@@ -184,17 +199,21 @@ __global__ void k_niw_draw(int K, int d, NiwPriorDev prior, const long long* __r
     }
     A[idx] = v;
   }
+  for (int q = tid; q < d; q += blockDim.x)
+    eps[q] = normal_draw(seed, t, (uint32_t)e, TAG_NIW, (uint32_t)(nq_off + d + q));
   __syncthreads();
-  // F = L A^-T: row r solves A f^T = L[r]^T by forward substitution
+  // F = L A^-T
+  for (int idx = tid; idx < d * d; idx += blockDim.x) F[idx] = L[idx];
+  __syncthreads();
+  wg_right_solve_lower_t(F, A, d);
+  // mu = m_n + F eps / sqrt(kappa_n)
+  const double rs = 1.0 / sqrt(kn);
   for (int r = tid; r < d; r += blockDim.x) {
-    for (int j = 0; j < d; ++j) {
-      double s = L[r * d + j];
-      for (int q = 0; q < j; ++q) s -= A[j * d + q] * F[r * d + q];
-      F[r * d + j] = s / A[j * d + j];
-    }
+    double s = 0.0;
+    for (int q = 0; q < d; ++q) s += F[r * d + q] * eps[q];
+    mn[r] += s * rs;
   }
-  __syncthreads();
-  // Sigma = F F^T
+  // Sigma = F F^T (into L's storage and the output)
   double* sig = sigma_out + (size_t)e * d * d;
   for (int idx = tid; idx < d * d; idx += blockDim.x) {
     const int i = idx / d, j = idx % d;
@@ -203,19 +222,13 @@ __global__ void k_niw_draw(int K, int d, NiwPriorDev prior, const long long* __r
     for (int q = 0; q < d; ++q) s += F[i * d + q] * F[j * d + q];
     sig[i * d + j] = s;
     sig[j * d + i] = s;
+    L[i * d + j] = s;
+    L[j * d + i] = s;
   }
-  // mu = m_n + F eps / sqrt(kappa_n)
-  double* eps = F + d * d;
-  for (int q = tid; q < d; q += blockDim.x)
-    eps[q] = normal_draw(seed, t, (uint32_t)e, TAG_NIW, (uint32_t)(nq_off + d + q));
   __syncthreads();
-  const double rs = 1.0 / sqrt(kn);
-  for (int r = tid; r < d; r += blockDim.x) {
-    double s = 0.0;
-    for (int q = 0; q < d; ++q) s += F[r * d + q] * eps[q];
-    mn[r] += s * rs;
-  }
-  (void)red;
+  const double lw = c == 0 ? log_pi[k] : log_pisub[2 * k + (c - 1)];
+  pack_record(L, A, d, lw, mn, packed + (size_t)record_slot(k, c, k_max) * gauss_rec_stride(d),
+              logdet_out + e, err, &flag, red);
 }
 
 // One workgroup per component: log theta ~ log Dir(beta + c).
@@ -245,59 +258,26 @@ __global__ void k_dir_draw(int K, int V, const double* __restrict__ beta,
   for (int v = threadIdx.x; v < V; v += blockDim.x) out[v] -= lse;
 }
 
-// Pack component e = 3k + c: record slot k (cluster) or k_max + 2k + h (sub).
+// Pack component e = 3k + c from its float64 (mu, Sigma): record slot k
+// (cluster) or k_max + 2k + h (sub-cluster).
 __global__ void k_pack_gauss(int K, int d, int k_max, const double* __restrict__ log_pi,
                              const double* __restrict__ log_pisub, const double* __restrict__ mu,
                              const double* __restrict__ sigma, double* __restrict__ scratch,
                              float* __restrict__ packed, double* __restrict__ logdet_out,
                              int* __restrict__ err) {
+  extern __shared__ double lds_w[];
   __shared__ int flag;
   __shared__ double red[256];
   const int e = blockIdx.x;
   if (e >= 3 * K) return;
   const int k = e / 3, c = e % 3;
-  const int tid = threadIdx.x;
-  double* G = scratch + (size_t)e * NIW_SCRATCH(d);
-  double* W = G + d * d;
+  Work w = workspace(lds_w, scratch, e, d);
   const double* sig = sigma + (size_t)e * d * d;
-  for (int idx = tid; idx < d * d; idx += blockDim.x) G[idx] = sig[idx];
+  for (int idx = threadIdx.x; idx < d * d; idx += blockDim.x) w.M0[idx] = sig[idx];
   __syncthreads();
-  if (!block_cholesky(G, d, &flag)) {
-    if (tid == 0) atomicOr(err, 2);
-  }
-  // W = G^-1 (lower): column j by forward substitution
-  for (int j = tid; j < d; j += blockDim.x) {
-    for (int i = 0; i < j; ++i) W[i * d + j] = 0.0;
-    W[j * d + j] = 1.0 / G[j * d + j];
-    for (int i = j + 1; i < d; ++i) {
-      double s = 0.0;
-      for (int q = j; q < i; ++q) s += G[i * d + q] * W[q * d + j];
-      W[i * d + j] = -s / G[i * d + i];
-    }
-  }
-  double ld = 0.0;
-  for (int i = tid; i < d; i += blockDim.x) ld += log(G[i * d + i]);
-  ld = 2.0 * block_reduce_sum(ld, red);
-  __syncthreads();
-  const int stride = gauss_rec_stride(d);
-  const int slot = c == 0 ? k : k_max + 2 * k + (c - 1);
-  float* rec = packed + (size_t)slot * stride;
   const double lw = c == 0 ? log_pi[k] : log_pisub[2 * k + (c - 1)];
-  if (tid == 0) {
-    rec[0] = (float)(lw - 0.5 * ld - 0.5 * d * 1.8378770664093453);
-    rec[1] = rec[2] = rec[3] = 0.0f;
-    logdet_out[e] = ld;
-  }
-  for (int i = tid; i < d; i += blockDim.x) rec[4 + i] = (float)mu[(size_t)e * d + i];
-  for (int idx = tid; idx < d * (d + 1) / 2; idx += blockDim.x) {
-    // row r holds W[r][0..r]; idx = r(r+1)/2 + col
-    int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-    while ((r + 1) * (r + 2) / 2 <= idx) ++r;
-    while (r * (r + 1) / 2 > idx) --r;
-    const int col = idx - r * (r + 1) / 2;
-    rec[4 + d + idx] = (float)W[r * d + col];
-  }
-  for (int idx = 4 + d + d * (d + 1) / 2 + tid; idx < stride; idx += blockDim.x) rec[idx] = 0.0f;
+  pack_record(w.M0, w.M1, d, lw, mu + (size_t)e * d, packed + (size_t)record_slot(k, c, k_max) * gauss_rec_stride(d),
+              logdet_out + e, err, &flag, red);
 }
 
 __global__ void k_pack_mult(int K, int V, int k_max, const double* __restrict__ log_pi,

@@ -1,0 +1,475 @@
+// Cluster-sorted second half of the Gaussian label step, for d >= 5:
+// Sec. 4.1 step (f) (sub-labels) and the statistics update of Sec. 4.4.
+//
+// After the cluster draw, points are counting-sorted by z:
+//   k_hist_z     per-block histogram of z over contiguous point ranges (only
+//                when the label kernel did not produce it);
+//   k_scan_hist  per-(block, cluster) output offsets;
+//   k_scatter_z  perm[offset] = i.
+// Then k_sub_stats walks the sorted order in tiles of TR rows.  A tile holds
+// one or a few clusters, so sub-cluster scoring reads the two sub-cluster
+// records of a cluster with wave-uniform (scalar) loads instead of per-lane
+// gathers.  The tile's rows are then placed in LDS grouped by segment
+// s = 2 z + zsub, and every lane accumulates a 2x2 block of sum x x^T (or two
+// entries of sum x) in float64 registers over each segment's rows, with one
+// global atomic per entry, segment and tile.
+#include "kernels.hpp"
+
+namespace dpmm {
+
+namespace {
+
+constexpr int BLOCK = 256;
+constexpr int IPT_MAX = 9;  // 2x2 work items per lane for d <= 128
+
+template <int D>
+__device__ __forceinline__ float score_rec(const float* __restrict__ p, const float (&x)[D]) {
+  float dx[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) dx[j] = x[j] - p[4 + j];
+  const float* w = p + 4 + D;
+  float q = 0.0f;
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    float y = 0.0f;
+#pragma unroll
+    for (int c = 0; c <= r; ++c) y = fmaf(w[r * (r + 1) / 2 + c], dx[c], y);
+    q = fmaf(y, y, q);
+  }
+  return fmaf(-0.5f, q, p[0]);
+}
+
+// Generic d: x read from the lane's LDS row, the centred vector kept in a
+// per-lane LDS column (stride BLOCK).
+__device__ __forceinline__ float score_rec_lds(const float* __restrict__ p, const float* xr, float* dx, int d) {
+  for (int j = 0; j < d; ++j) dx[j * BLOCK] = xr[j] - p[4 + j];
+  const float* w = p + 4 + d;
+  float q = 0.0f;
+  for (int r = 0; r < d; ++r) {
+    const float* wr = w + r * (r + 1) / 2;
+    float y = 0.0f;
+    for (int c = 0; c <= r; ++c) y = fmaf(wr[c], dx[c * BLOCK], y);
+    q = fmaf(y, y, q);
+  }
+  return fmaf(-0.5f, q, p[0]);
+}
+
+__device__ __forceinline__ int block_inclusive_scan(int v, int* buf) {
+  const int tid = threadIdx.x;
+  buf[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < BLOCK; off <<= 1) {
+    const int add = tid >= off ? buf[tid - off] : 0;
+    __syncthreads();
+    buf[tid] += add;
+    __syncthreads();
+  }
+  const int r = buf[tid];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(BLOCK) void k_hist_z(const int* __restrict__ z, long long n, long long per_block, int K,
+                                                  int* __restrict__ hist, int* __restrict__ tot) {
+  extern __shared__ int h[];
+  for (int k = threadIdx.x; k < K; k += BLOCK) h[k] = 0;
+  __syncthreads();
+  const long long begin = (long long)blockIdx.x * per_block;
+  const long long end = begin + per_block < n ? begin + per_block : n;
+  for (long long i = begin + threadIdx.x; i < end; i += BLOCK) {
+    const int zi = z[i];
+    if ((unsigned)zi < (unsigned)K) atomicAdd(&h[zi], 1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += BLOCK) {
+    hist[(size_t)blockIdx.x * K + k] = h[k];
+    if (h[k]) atomicAdd(&tot[k], h[k]);
+  }
+}
+
+// One workgroup per cluster k: offs[b][k] = sum_{k' < k} tot[k'] + sum_{b' < b} hist[b'][k].
+__global__ __launch_bounds__(BLOCK) void k_scan_hist(const int* __restrict__ hist, int G, int K,
+                                                     const int* __restrict__ tot, int* __restrict__ offs) {
+  __shared__ int buf[BLOCK];
+  __shared__ long long base_sh;
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x;
+  long long b0 = 0;
+  for (int q = tid; q < k; q += BLOCK) b0 += tot[q];
+  // reduce b0 over the block
+  buf[tid] = (int)b0;  // cluster totals are below 2^31 (n < 2^31 for this path)
+  __syncthreads();
+  if (tid == 0) {
+    long long s = 0;
+    for (int q = 0; q < BLOCK; ++q) s += buf[q];
+    base_sh = s;
+  }
+  __syncthreads();
+  const int per = (G + BLOCK - 1) / BLOCK;
+  const int g0 = tid * per;
+  int local = 0;
+  for (int g = g0; g < g0 + per && g < G; ++g) local += hist[(size_t)g * K + k];
+  const int incl = block_inclusive_scan(local, buf);
+  int run = (int)base_sh + incl - local;
+  for (int g = g0; g < g0 + per && g < G; ++g) {
+    offs[(size_t)g * K + k] = run;
+    run += hist[(size_t)g * K + k];
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scatter_z(const int* __restrict__ z, long long n, long long per_block,
+                                                     int K, const int* __restrict__ offs, int* __restrict__ perm) {
+  extern __shared__ int cur[];
+  for (int k = threadIdx.x; k < K; k += BLOCK) cur[k] = offs[(size_t)blockIdx.x * K + k];
+  __syncthreads();
+  const long long begin = (long long)blockIdx.x * per_block;
+  const long long end = begin + per_block < n ? begin + per_block : n;
+  for (long long i = begin + threadIdx.x; i < end; i += BLOCK) {
+    const int zi = z[i];
+    if ((unsigned)zi < (unsigned)K) perm[atomicAdd(&cur[zi], 1)] = (int)i;
+  }
+}
+
+// 2x2 work items of one lane for dimension D (0: the generic bound, d <= 128)
+__host__ __device__ constexpr int items_per_lane(int D) {
+  return D == 0 ? IPT_MAX : ((((D + 1) / 2) * ((D + 1) / 2 + 1) / 2 + (D + 1) / 2) + 255) / 256;
+}
+
+// D > 0: a lane's row stays in registers for sub-cluster scoring and is then
+// stored straight to its segment-sorted LDS position; D == 0 (generic d): rows
+// are staged in LDS and reached through an index list.  SAMPLE: draw zsub
+// (else read it).  Workgroup g walks the tiles [g tpw, (g + 1) tpw) of TR
+// sorted rows each (TR <= BLOCK: one row per lane).  Clusters are contiguous
+// in sorted order, so the lanes keep float64 accumulators of the current
+// cluster's two segments across tiles and flush them with global atomics only
+// when the cluster changes or the range ends.
+template <int D, bool SAMPLE>
+__global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x, int d, int TR, int tpw,
+                                                     long long n_sorted, const int* __restrict__ perm,
+                                                     const int* __restrict__ z, unsigned char* __restrict__ zsub,
+                                                     const float* __restrict__ packed, int k_max, uint32_t t,
+                                                     uint64_t seed, long long* __restrict__ counts,
+                                                     double* __restrict__ moments) {
+  constexpr int IPT = items_per_lane(D);
+  extern __shared__ float lds[];
+  const int tid = threadIdx.x;
+  const int dp = (d + 1) & ~1;  // even, padded with a zero column
+  const int ld = dp + 1;        // odd row stride: lanes touching their own rows hit distinct banks
+  float* xs = lds;                                         // [TR][ld]
+  int* rk = reinterpret_cast<int*>(xs + (size_t)TR * ld);  // [TR] cluster of the row
+  int* order = rk + TR;                                    // [TR] (generic d) row of each sorted slot
+  int* lcount = order + TR;                                // [2 TR]
+  int* lstart = lcount + 2 * TR;                           // [2 TR]
+  int* lseg = lstart + 2 * TR;                             // [2 TR]
+  int* buf = lseg + 2 * TR;                                // [BLOCK]
+  float* dxc = reinterpret_cast<float*>(buf + BLOCK);      // [d][BLOCK] (generic d only)
+  const int S = gauss_rec_stride(d);
+  const int E = d + d * (d + 1) / 2;
+  // this lane's 2x2 work items: blocks (I, J), I <= J, of sum x x^T over the
+  // even-padded dimension, then pairs I of sum x (J = -2)
+  const int hb = dp / 2;
+  const int n_tri = hb * (hb + 1) / 2;
+  const int n_items = n_tri + hb;
+  short iI[IPT], iJ[IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const int it = tid + j * BLOCK;
+    iI[j] = -1;
+    iJ[j] = -1;
+    if (it < n_tri) {
+      int u = it, a = 0;
+      while (u >= hb - a) {
+        u -= hb - a;
+        ++a;
+      }
+      iI[j] = (short)a;
+      iJ[j] = (short)(a + u);
+    } else if (it < n_items) {
+      iI[j] = (short)(it - n_tri);
+      iJ[j] = -2;
+    }
+  }
+  // running sums of the current cluster's left (accL) and right (accR)
+  // segments; indexed statically so they stay in registers
+  double accL[IPT][4], accR[IPT][4];
+  long long cntL = 0, cntR = 0;
+  int cur_k = -1;
+  auto zero_acc = [&]() {
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      accL[j][0] = accL[j][1] = accL[j][2] = accL[j][3] = 0.0;
+      accR[j][0] = accR[j][1] = accR[j][2] = accR[j][3] = 0.0;
+    }
+    cntL = cntR = 0;
+  };
+  auto flush_one = [&](double (&acc)[IPT][4], long long cnt, int seg) {
+    if (cnt == 0) return;
+    double* M = moments + (size_t)seg * E;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const int I = iI[j], J = iJ[j];
+      if (I < 0) continue;
+      if (J == -2) {
+        if (2 * I < d) atomicAdd(&M[2 * I], acc[j][0]);
+        if (2 * I + 1 < d) atomicAdd(&M[2 * I + 1], acc[j][1]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            const int a = 2 * I + u, b = 2 * J + v;
+            if (a < d && b < d && a <= b) atomicAdd(&M[d + a * d - (a * (a - 1)) / 2 + (b - a)], acc[j][2 * u + v]);
+          }
+      }
+    }
+    if (tid == 0) atomicAdd((unsigned long long*)&counts[seg], (unsigned long long)cnt);
+  };
+  auto flush = [&]() {
+    if (cur_k < 0) return;
+    flush_one(accL, cntL, 2 * cur_k);
+    flush_one(accR, cntR, 2 * cur_k + 1);
+  };
+  auto accumulate = [&](double (&acc)[IPT][4], int st, int cnt) {
+#pragma unroll 4
+    for (int p = st; p < st + cnt; ++p) {
+      const float* xr = xs + (size_t)(D > 0 ? p : order[p]) * ld;
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const int I = iI[j], J = iJ[j];
+        if (I < 0) continue;
+        const double a0 = xr[2 * I], a1 = xr[2 * I + 1];
+        if (J == -2) {
+          acc[j][0] += a0;
+          acc[j][1] += a1;
+        } else {
+          const double b0 = xr[2 * J], b1 = xr[2 * J + 1];
+          acc[j][0] = fma(a0, b0, acc[j][0]);
+          acc[j][1] = fma(a0, b1, acc[j][1]);
+          acc[j][2] = fma(a1, b0, acc[j][2]);
+          acc[j][3] = fma(a1, b1, acc[j][3]);
+        }
+      }
+    }
+  };
+  zero_acc();
+  const long long tiles = (n_sorted + TR - 1) / TR;
+  const long long tile_end = ((long long)blockIdx.x + 1) * tpw < tiles ? ((long long)blockIdx.x + 1) * tpw : tiles;
+  for (long long tile = (long long)blockIdx.x * tpw; tile < tile_end; ++tile) {
+    const long long tile0 = tile * TR;
+    const int rows = (int)((n_sorted - tile0) < TR ? (n_sorted - tile0) : TR);
+    const int r = tid;
+    const bool valid = r < rows;
+    // ---- phase A: load the row, draw or read its sub-label
+    long long i = 0;
+    int k = -1;
+    float xv[D > 0 ? D : 1];
+    if (valid) {
+      i = perm[tile0 + r];
+      k = z[i];
+      rk[r] = k;
+      if constexpr (D > 0) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) xv[j] = x[i * D + j];
+      } else {
+        float* xr = xs + (size_t)r * ld;
+        for (int j = 0; j < d; ++j) xr[j] = x[i * d + j];
+        for (int j = d; j < dp; ++j) xr[j] = 0.0f;
+      }
+    }
+    for (int q = tid; q < 2 * TR; q += BLOCK) lcount[q] = 0;
+    int zs = 0;
+    if (SAMPLE) {
+      float delta = 0.0f;
+      unsigned long long pending = __ballot(valid);
+      while (pending) {
+        const int lane0 = __ffsll((long long)pending) - 1;
+        const int kk = __shfl(k, lane0);
+        const bool mine = valid && k == kk;
+        if (mine) {
+          const float* ps = packed + (size_t)(k_max + 2 * kk) * S;
+          if constexpr (D > 0) {
+            delta = score_rec<D>(ps, xv) - score_rec<D>(ps + S, xv);
+          } else {
+            const float* xr = xs + (size_t)r * ld;
+            delta = score_rec_lds(ps, xr, dxc + tid, d) - score_rec_lds(ps + S, xr, dxc + tid, d);
+          }
+        }
+        pending &= ~__ballot(mine);
+      }
+      if (valid) {
+        if (delta > LOGISTIC_MAX_F) {
+          zs = 0;
+        } else if (delta < -LOGISTIC_MAX_F) {
+          zs = 1;
+        } else {
+          const float L = logistic_f(rng_block(seed, t, (uint32_t)i, TAG_LOGISTIC, 0).x);
+          zs = delta + L > 0.0f ? 0 : 1;
+        }
+        zsub[i] = (unsigned char)zs;
+      }
+    } else if (valid) {
+      zs = zsub[i] ? 1 : 0;
+    }
+    __syncthreads();
+    // ---- group rows by segment: run id of the cluster (rows are sorted by
+    // z), local id 2 run + zsub
+    const int flag = (valid && (r == 0 || rk[r] != rk[r - 1])) ? 1 : 0;
+    const int incl = block_inclusive_scan(flag, buf);
+    const int nl = 2 * buf[BLOCK - 1];
+    int lid = 0;
+    if (valid) {
+      lid = 2 * (incl - 1) + zs;
+      atomicAdd(&lcount[lid], 1);
+      lseg[lid] = 2 * k + zs;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int a = 0;
+      for (int q = 0; q < nl; ++q) {
+        lstart[q] = a;
+        a += lcount[q];
+      }
+    }
+    __syncthreads();
+    // slot within the segment (any order; the sums are float64): the high
+    // half of lcount serves as the cursor, the low half keeps the count
+    if (valid) {
+      const int pos = lstart[lid] + atomicAdd(&lcount[lid], 0x10000) / 0x10000;
+      if constexpr (D > 0) {
+        float* xr = xs + (size_t)pos * ld;
+#pragma unroll
+        for (int j = 0; j < D; ++j) xr[j] = xv[j];
+        if (D & 1) xr[D] = 0.0f;
+      } else {
+        order[pos] = r;
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < nl; q += BLOCK) lcount[q] &= 0xFFFF;
+    __syncthreads();
+    // ---- phase B: accumulate each segment's rows into the running sums
+    for (int q = 0; q < nl; ++q) {
+      const int cnt = lcount[q];
+      if (cnt == 0) continue;
+      const int seg = lseg[q];
+      const int kq = seg >> 1, h = seg & 1;
+      if (kq != cur_k) {
+        flush();
+        zero_acc();
+        cur_k = kq;
+      }
+      const int st = lstart[q];
+      if (h == 0) {
+        cntL += cnt;
+        accumulate(accL, st, cnt);
+      } else {
+        cntR += cnt;
+        accumulate(accR, st, cnt);
+      }
+    }
+    __syncthreads();
+  }
+  flush();
+}
+
+namespace {
+
+struct SortedPlan {
+  int G;
+  long long per_block;
+};
+
+SortedPlan plan_blocks(long long n, int K, long long hist_cap) {
+  long long G = (n + 511) / 512;
+  if (G > 2048) G = 2048;
+  while (G > 1 && G * K > hist_cap) G = (G + 1) / 2;
+  if (G < 1) G = 1;
+  long long per = (n + G - 1) / G;
+  per = ((per + BLOCK - 1) / BLOCK) * BLOCK;
+  G = (n + per - 1) / per;
+  if (G < 1) G = 1;
+  return SortedPlan{(int)G, per};
+}
+
+int tile_rows(int d) {
+  if (d <= 32) return 256;
+  if (d <= 64) return 128;
+  return 32;  // generic d up to 128: the per-lane centred columns take d x 1 KB of LDS
+}
+
+size_t sub_stats_lds(int d, int TR, bool generic) {
+  const int dp = (d + 1) & ~1;
+  size_t b = (size_t)TR * (dp + 1) * sizeof(float) + (size_t)(2 * TR + 6 * TR + BLOCK) * sizeof(int);
+  if (generic) b += (size_t)d * BLOCK * sizeof(float);
+  return b;
+}
+
+template <bool SAMPLE>
+hipError_t launch_sub_stats_t(int d, const float* x, long long n, const int* perm, const int* z, unsigned char* zsub,
+                              const float* packed, int k_max, uint32_t t, uint64_t seed, long long* counts,
+                              double* moments, hipStream_t s) {
+  const int TR = tile_rows(d);
+  // contiguous tile ranges, about four workgroups per CU
+  const long long tiles = (n + TR - 1) / TR;
+  long long g = tiles < 1024 ? tiles : 1024;
+  const int tpw = (int)((tiles + g - 1) / g);
+  const unsigned grid = (unsigned)((tiles + tpw - 1) / tpw);
+#define DPMM_SUB_CASE(DD)                                                                                 \
+  case DD:                                                                                                \
+    hipLaunchKernelGGL((k_sub_stats<DD, SAMPLE>), dim3(grid), dim3(BLOCK), sub_stats_lds(d, TR, false), s, x, d, \
+                       TR, tpw, n, perm, z, zsub, packed, k_max, t, seed, counts, moments);              \
+    break;
+  switch (d) {
+    DPMM_SUB_CASE(8)
+    DPMM_SUB_CASE(16)
+    DPMM_SUB_CASE(32)
+    DPMM_SUB_CASE(64)
+    default:
+      hipLaunchKernelGGL((k_sub_stats<0, SAMPLE>), dim3(grid), dim3(BLOCK), sub_stats_lds(d, TR, SAMPLE), s, x, d,
+                         TR, tpw, n, perm, z, zsub, packed, k_max, t, seed, counts, moments);
+  }
+#undef DPMM_SUB_CASE
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t sorted_plan(long long n, int K, long long hist_cap, int* G, long long* per_block) {
+  const SortedPlan p = plan_blocks(n, K, hist_cap);
+  *G = p.G;
+  *per_block = p.per_block;
+  return hipSuccess;
+}
+
+hipError_t launch_sort_by_z(const int* z, long long n, int K, int G, long long per_block, bool have_hist, int* hist,
+                            int* tot, int* offs, int* perm, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipError_t e;
+  if (!have_hist) {
+    e = launch_zero64(tot, (size_t)(K + 1) / 2 + 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hist_z, dim3(G), dim3(BLOCK), (size_t)K * sizeof(int), s, z, n, per_block, K, hist, tot);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_scan_hist, dim3(K), dim3(BLOCK), 0, s, hist, G, K, tot, offs);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scatter_z, dim3(G), dim3(BLOCK), (size_t)K * sizeof(int), s, z, n, per_block, K, offs, perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, const int* perm, const int* z,
+                            unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t, uint64_t seed,
+                            long long* counts, double* moments, hipStream_t s) {
+  const int E = d + d * (d + 1) / 2;
+  hipError_t e = launch_zero64(counts, (size_t)2 * K, s);
+  if (e != hipSuccess) return e;
+  e = launch_zero64(moments, (size_t)2 * K * E, s);
+  if (e != hipSuccess) return e;
+  if (n == 0) return hipSuccess;
+  return sample ? launch_sub_stats_t<true>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, s)
+                : launch_sub_stats_t<false>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, s);
+}
+
+}  // namespace dpmm

@@ -3,13 +3,14 @@
 //
 //   k_logml_gauss  log marginal likelihood of the union of up to four
 //                  sub-cluster segments under the NIW prior, one workgroup
-//                  per item (float64 Cholesky of Psi_n for log|Psi_n|);
+//                  per item (float64 Cholesky of Psi_n in LDS for log|Psi_n|);
 //   k_logml_mult   the Dirichlet-multinomial log marginal likelihood;
 //   k_relabel      applies a split/merge/compaction move table to (z, zsub)
 //                  in one O(N) pass;
 //   k_init_labels  the one-cluster initial state.
 // The O(K^2) accept/reject bookkeeping runs on the host from these values.
 #include "kernels.hpp"
+#include "linalg.hpp"
 
 namespace dpmm {
 
@@ -43,6 +44,7 @@ __global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, 
                               double logdet_psi, const long long* __restrict__ counts,
                               const double* __restrict__ moments, double* __restrict__ scratch,
                               double* __restrict__ out, int* __restrict__ err) {
+  extern __shared__ double lds_p[];
   __shared__ double red[BLOCK];
   __shared__ int flag;
   const int it = blockIdx.x;
@@ -57,7 +59,7 @@ __global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, 
     if (tid == 0) out[it] = 0.0;
     return;
   }
-  double* P = scratch + (size_t)it * d * d;
+  double* P = d <= LOGML_LDS_MAX_D ? lds_p : scratch + (size_t)it * d * d;
   const double kn = prior.kappa + n, nun = prior.nu + n;
   for (int idx = tid; idx < d * d; idx += BLOCK) {
     const int i = idx / d, j = idx % d;
@@ -75,28 +77,7 @@ __global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, 
     P[idx] = prior.psi[idx] + (S - n * xi * xj) + (prior.kappa * n / kn) * (xi - prior.m[i]) * (xj - prior.m[j]);
   }
   __syncthreads();
-  // Cholesky, column by column
-  if (tid == 0) flag = 1;
-  __syncthreads();
-  for (int j = 0; j < d; ++j) {
-    if (tid == 0) {
-      double s = P[j * d + j];
-      for (int k = 0; k < j; ++k) s -= P[j * d + k] * P[j * d + k];
-      if (!(s > 0.0) || !isfinite(s)) {
-        flag = 0;
-        s = 1.0;
-      }
-      P[j * d + j] = sqrt(s);
-    }
-    __syncthreads();
-    const double ljj = P[j * d + j];
-    for (int i = j + 1 + tid; i < d; i += BLOCK) {
-      double s = P[i * d + j];
-      for (int k = 0; k < j; ++k) s -= P[i * d + k] * P[j * d + k];
-      P[i * d + j] = s / ljj;
-    }
-    __syncthreads();
-  }
+  const bool ok = wg_cholesky(P, d, &flag);
   double ld = 0.0, lg = 0.0;
   for (int i = tid; i < d; i += BLOCK) {
     ld += log(P[i * d + i]);
@@ -106,7 +87,7 @@ __global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, 
   ld = 2.0 * reduce_sum(ld, red);
   lg = reduce_sum(lg, red);
   if (tid == 0) {
-    if (!flag) atomicOr(err, 4);
+    if (!ok) atomicOr(err, 4);
     out[it] = -0.5 * n * d * 1.1447298858494002 + lg + 0.5 * prior.nu * logdet_psi - 0.5 * nun * ld +
               0.5 * d * (log(prior.kappa) - log(kn));
   }
@@ -186,7 +167,8 @@ hipError_t launch_logml_gauss(int n_items, const LogmlItem* items, int d, NiwPri
                               const long long* counts, const double* moments, double* scratch, double* out,
                               int* err, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_logml_gauss, dim3(n_items), dim3(BLOCK), 0, s, n_items, items, d, prior, logdet_psi,
+  const size_t lds = d <= LOGML_LDS_MAX_D ? (size_t)d * d * sizeof(double) : 0;
+  hipLaunchKernelGGL(k_logml_gauss, dim3(n_items), dim3(BLOCK), lds, s, n_items, items, d, prior, logdet_psi,
                      counts, moments, scratch, out, err);
   return hipGetLastError();
 }

@@ -22,7 +22,21 @@ def _gauss_sampler(d, k_max, seed, **kw):
 
 
 GAUSS_CASES = [(1, 1, 777), (2, 6, 10000), (3, 4, 5000), (8, 12, 4099), (5, 7, 2049),
-               (16, 9, 2000), (32, 20, 3001), (2, 70, 1500), (12, 3, 1300)]
+               (16, 9, 2000), (32, 20, 3001), (2, 70, 1500), (12, 3, 1300), (8, 300, 5000),
+               (64, 5, 700), (33, 4, 900), (128, 3, 300)]
+
+
+def _check_stats(got, x, z, zs, K, d):
+    model = sampler.Model("gaussian", 1.0, niw.NIWPrior(1.0, np.zeros(d), d + 3, np.eye(d)), seed=5)
+    ref = pu.stats_array(sampler.suffstats(model, x, z, zs, K), "gaussian")
+    assert np.array_equal(got[..., 0], ref[..., 0])
+    xa = np.abs(x.astype(np.float64))
+    seg = 2 * z.astype(np.int64) + zs
+    for s_ in range(2 * K):
+        xs = xa[seg == s_]
+        k, h = divmod(s_, 2)
+        assert np.all(np.abs(got[k, h, 1:1 + d] - ref[k, h, 1:1 + d]) <= 1e-6 * xs.sum(0) + 1e-300)
+        assert np.all(np.abs(got[k, h, 1 + d:] - ref[k, h, 1 + d:]).reshape(d, d) <= 1e-6 * (xs.T @ xs) + 1e-300)
 
 
 @pytest.mark.parametrize("d,K,n", GAUSS_CASES)
@@ -46,11 +60,16 @@ def test_gauss_loglik_and_labels(d, K, n):
         assert bad_c.size == 0, (bad_c[:10], tie_c)
         assert bad_s.size == 0, (bad_s[:10], tie_s)
         assert tie_c <= max(2, n // 1000) and tie_s <= max(2, n // 1000)
+        if d < 5:
+            S.suffstats(xt, z, zs)
+        # d >= 5: the statistics are a by-product of the sorted sub-label pass
+        _check_stats(S.get_stats(), x, z.cpu().numpy(), zs.cpu().numpy(), K, d)
     S.close()
 
 
 @pytest.mark.parametrize("d,K,n", [(1, 2, 1000), (2, 6, 10000), (3, 5, 3001), (5, 4, 2500),
-                                   (32, 20, 9000), (20, 3, 70000), (2, 300, 5000), (0, 1, 0)])
+                                   (32, 20, 9000), (20, 3, 70000), (2, 300, 5000), (0, 1, 0),
+                                   (8, 500, 3000), (64, 7, 5000), (128, 2, 700), (32, 1, 1)])
 def test_gauss_suffstats(d, K, n):
     torch = _torch()
     d = max(d, 1)
@@ -61,19 +80,7 @@ def test_gauss_suffstats(d, K, n):
     S = _gauss_sampler(d, K, 5)
     S.set_state(K)
     S.suffstats(torch.from_numpy(x).cuda(), torch.from_numpy(z).cuda(), torch.from_numpy(zs).cuda())
-    got = S.get_stats()
-    model = sampler.Model("gaussian", 1.0, niw.NIWPrior(1.0, np.zeros(d), d + 3, np.eye(d)), seed=5)
-    ref = pu.stats_array(sampler.suffstats(model, x, z, zs, K), "gaussian")
-    assert np.array_equal(got[..., 0], ref[..., 0])
-    xa = np.abs(x.astype(np.float64))
-    seg = 2 * z.astype(np.int64) + zs
-    for s_ in range(2 * K):
-        xs = xa[seg == s_]
-        bound_s = 1e-6 * xs.sum(0) + 1e-300
-        bound_S = 1e-6 * (xs.T @ xs) + 1e-300
-        k, h = divmod(s_, 2)
-        assert np.all(np.abs(got[k, h, 1:1 + d] - ref[k, h, 1:1 + d]) <= bound_s)
-        assert np.all(np.abs(got[k, h, 1 + d:] - ref[k, h, 1 + d:]).reshape(d, d) <= bound_S)
+    _check_stats(S.get_stats(), x, z, zs, K, d)
     S.close()
 
 
