@@ -6,7 +6,8 @@ merge bookkeeping and relabelling) over the whole data set, resident in HBM.
 
 Workload: the Gaussian precision-form configuration, N = 1e6 points, d = 32,
 20 true clusters (means N(0, 25 I), covariances Wishart(d + 2, I/d), weights
-Dirichlet(1)), float32 scoring.  Before the warm-up the chain is run until
+Dirichlet(1)).  `value` is the BF16 matrix-core form by default; the FP32 and
+bf16x3 forms are timed beside it.  Before the warm-up each chain is run until
 its cluster count has settled, so the timed steps score the converged K.
 
 Prints one JSON line: metric (point-cluster evaluations per second: N (K + 2)
@@ -29,6 +30,7 @@ WORKLOAD = "gauss_d32"
 SEED = 1
 ALPHA = 10.0
 PEAK_FP32_VALU = 78.6e12   # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (non-packed FP32)
+PEAK_BF16_MFMA = 2.5e15    # dense BF16 matrix-core peak
 
 
 def flops_per_eval(d):
@@ -70,12 +72,60 @@ def cpu_baseline(x, z, zs, K, d, budget_s=12.0):
                       f"({t - 10_000} iterations, {el:.1f} s)"}
 
 
+def run_form(torch, x, n, d, m, precision, steps, warmup, k_true):
+    """Converge the chain, then time `steps` full iterations of one precision form."""
+    from paper_2204_08988_amd.sampler import Sampler
+    S = Sampler("gaussian", d, 128, ALPHA, SEED, kappa=1.0, nu=d + 3.0, m=m, psi=np.eye(d), burn_out=5,
+                precision=precision)
+    z, zs = S.init_labels(n)
+    t = 1
+    ks = []
+    for _ in range(400):
+        info = S.step(x, t, z, zs)
+        t += 1
+        ks.append(info["K"])
+        if len(ks) > 30 and len(set(ks[-15:])) == 1 and info["K"] >= k_true // 2:
+            break
+    for _ in range(warmup):
+        S.step(x, t, z, zs)
+        t += 1
+    torch.cuda.synchronize()
+    evals = 0
+    ms = {"params": 0.0, "labels": 0.0, "stats": 0.0, "splitmerge": 0.0}
+    k_sum = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = S.step(x, t, z, zs)
+        t += 1
+        evals += n * (info["K"] + 2)
+        k_sum += info["K"]
+        for key in ms:
+            ms[key] += info["ms_" + key]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    k_mean = k_sum / steps
+    res = {
+        "precision": precision,
+        "value": evals / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "iters_per_s": steps / elapsed,
+        "k_mean": k_mean,
+        "phase_ms": {key: v / steps for key, v in ms.items()},
+        "label_kernel_ms": ms["labels"] / steps,
+        "label_evals_per_s": n * (k_mean + 2) / (ms["labels"] / steps / 1e3),
+    }
+    return S, z, zs, res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "bf16x3"],
+                    help="form reported as `value` (the other forms are reported beside it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", action="store_true", help="time only the --precision form")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -84,7 +134,7 @@ def main():
 
     import torch
     from paper_2204_08988_amd import datagen
-    from paper_2204_08988_amd.sampler import Sampler
+    from oracle import nmi as nmi_mod
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     spec = datagen.WORKLOADS[WORKLOAD]
@@ -92,67 +142,60 @@ def main():
     n, d = x_np.shape
     m = x_np.mean(0).astype(np.float64)
     x = torch.from_numpy(x_np).cuda()
-    S = Sampler("gaussian", d, 128, ALPHA, SEED, kappa=1.0, nu=d + 3.0, m=m, psi=np.eye(d), burn_out=5)
-    z, zs = S.init_labels(n)
-    t = 1
-    # run the chain until its cluster count settles
-    ks = []
-    for _ in range(400):
-        info = S.step(x, t, z, zs)
-        t += 1
-        ks.append(info["K"])
-        if len(ks) > 30 and len(set(ks[-15:])) == 1 and info["K"] >= spec.k // 2:
-            break
-    for _ in range(args.warmup):
-        S.step(x, t, z, zs)
-        t += 1
-    torch.cuda.synchronize()
-    evals = 0
-    label_ms = 0.0
-    k_sum = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        info = S.step(x, t, z, zs)
-        t += 1
-        evals += n * (info["K"] + 2)
-        k_sum += info["K"]
-        label_ms += info["ms_labels"]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    k_mean = k_sum / args.steps
-    ms_step = 1e3 * elapsed / args.steps
-    label_s = label_ms / 1e3 / args.steps
-    achieved = n * (k_mean + 2) * flops_per_eval(d) / label_s
-    from oracle import nmi as nmi_mod
+    forms = [args.precision] if args.only else [args.precision] + [f for f in ("fp32", "bf16", "bf16x3")
+                                                                     if f != args.precision]
+    results = {}
+    main_state = None
+    for f in forms:
+        S, z, zs, res = run_form(torch, x, n, d, m, f, args.steps, args.warmup, spec.k)
+        res["nmi"] = nmi_mod.nmi(labels, z.cpu().numpy())
+        results[f] = res
+        if f == args.precision:
+            main_state = (z.cpu().numpy(), zs.cpu().numpy(), S.K)
+        S.close()
+    r = results[args.precision]
+    label_s = r["label_kernel_ms"] / 1e3
+    algo = n * (r["k_mean"] + 2) * flops_per_eval(d)
+    if args.precision == "fp32":
+        roof = {"bound": "alu", "achieved": algo / label_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                "unit": "TFLOP/s", "frac": algo / label_s / PEAK_FP32_VALU, "traffic": None,
+                "kernel": "k_label_gauss_z<32> (FP32 VALU cluster draw)"}
+    else:
+        roof = {"bound": "mfma", "achieved": algo / label_s / 1e12, "peak": PEAK_BF16_MFMA / 1e12,
+                "unit": "TFLOP/s", "frac": algo / label_s / PEAK_BF16_MFMA, "traffic": None,
+                "kernel": f"k_label_gauss_mfma<32,{'true' if args.precision == 'bf16x3' else 'false'}> "
+                          "(BF16 matrix-core cluster draw)"}
+    roof["algorithmic_flops_per_eval"] = flops_per_eval(d)
     out = {
         "metric": "point-cluster evals/s in label step; iters/s; time-to-plateau learned vs plain",
-        "value": evals / elapsed,
+        "value": r["value"],
         "unit": "point-cluster evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32",
+        "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": f"{WORKLOAD}: Gaussian DPMM, N={n}, d={d}, {spec.k} true clusters, "
                                "means N(0,25I), covariances Wishart(d+2, I/d), weights Dir(1); "
-                               "FP32 VALU scoring", "n": n, "d": d, "k_mean": k_mean,
+                               f"cluster scoring {args.precision}, sub-labels FP32, statistics and "
+                               "parameters FP64", "n": n, "d": d, "k_mean": r["k_mean"],
                    "alpha": ALPHA, "parallelism": "single GPU"},
-        "iters_per_s": args.steps / elapsed,
-        "label_kernel_ms": 1e3 * label_s,
-        "label_evals_per_s": n * (k_mean + 2) / label_s,
-        "nmi": nmi_mod.nmi(labels, z.cpu().numpy()),
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
-                     "kernel": "k_label_gauss<32>",
-                     "algorithmic_flops_per_eval": flops_per_eval(d)},
+        "iters_per_s": r["iters_per_s"],
+        "phase_ms": r["phase_ms"],
+        "label_kernel_ms": r["label_kernel_ms"],
+        "label_evals_per_s": r["label_evals_per_s"],
+        "nmi": r["nmi"],
+        "forms": {f: {k: v for k, v in res.items() if k != "precision"} for f, res in results.items()
+                  if f != args.precision},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(x_np, z.cpu().numpy(), zs.cpu().numpy(), S.K, d)
-    S.close()
+        z_np, zs_np, K = main_state
+        out["cpu_baseline"] = cpu_baseline(x_np, z_np, zs_np, K, d)
     print(json.dumps(out), flush=True)
 
 

@@ -76,8 +76,13 @@ typedef struct {
   const double* psi;  /* host [d*d]: NIW scale, row-major SPD (Gaussian; copied) */
   const double* beta; /* host [V]: Dirichlet prior, > 0 (multinomial; copied) */
   uint64_t seed;      /* Philox key */
-  int32_t precision;  /* DPMM_FP32 (the only form of this release; others ->
-                         DPMM_E_ARG) */
+  int32_t precision;  /* cluster scoring of the label step: DPMM_FP32 (vector
+                         ALUs, any d); DPMM_BF16 or DPMM_BF16X3 (matrix cores,
+                         Gaussian with d = 32 or 64 only, else DPMM_E_ARG):
+                         BF16 inputs with FP32 accumulation, X3 adding the
+                         hi/lo cross terms; points whose BF16 top-2 gap leaves
+                         any doubt are re-scored in FP32.  Sub-labels,
+                         statistics and parameters are FP32/FP64 in every form */
   int32_t merge_form; /* DPMM_MERGE_PAPER: ratio of Sec. 4.1 eq. sample_merges;
                          DPMM_MERGE_INVERSE_SPLIT: H_merge = 1 / H_split of
                          Sec. 2.3 */

@@ -62,6 +62,8 @@ struct dpmm_ctx {
   int *d_hist = nullptr, *d_offs = nullptr, *d_tot = nullptr, *d_perm = nullptr;
   long long hist_cap = 0, perm_cap = 0;
   bool labels_gave_stats = false;
+  // BF16 whitener fragments of the cluster components (precision != FP32)
+  uint16_t *d_whi = nullptr, *d_wlo = nullptr;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 
   dpmm_status fail(dpmm_status s, const std::string& msg) {
@@ -254,6 +256,9 @@ dpmm_status pack_params(dpmm_ctx* ctx) {
                        ctx->d_log_pi, ctx->d_log_pisub, ctx->d_log_theta, ctx->d_packed);
   }
   DPMM_HIP(ctx, hipGetLastError(), "pack kernel");
+  if (ctx->d_whi)
+    DPMM_HIP(ctx, launch_pack_wfrag(K, ctx->d, ctx->cfg.k_max, ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->stream),
+             "fragment pack kernel");
   ctx->have_params = true;
   return DPMM_OK;
 }
@@ -299,7 +304,10 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
   if (cfg->k_max < 1 || cfg->k_max > 4096) return bad(DPMM_E_ARG, "k_max must lie in [1, 4096]");
   if (cfg->burn_out < 0) return bad(DPMM_E_ARG, "burn_out must be >= 0");
   if (!(cfg->alpha > 0.0) || !std::isfinite(cfg->alpha)) return bad(DPMM_E_ARG, "alpha must be > 0");
-  if (cfg->precision != DPMM_FP32) return bad(DPMM_E_ARG, "only DPMM_FP32 scoring is available");
+  if (cfg->precision != DPMM_FP32 && cfg->precision != DPMM_BF16 && cfg->precision != DPMM_BF16X3)
+    return bad(DPMM_E_ARG, "unknown precision");
+  if (cfg->precision != DPMM_FP32 && !(cfg->family == DPMM_GAUSSIAN && mfma_supported(cfg->d)))
+    return bad(DPMM_E_ARG, "BF16 matrix-core scoring needs the Gaussian family with d = 32 or 64");
   if (cfg->merge_form != DPMM_MERGE_PAPER && cfg->merge_form != DPMM_MERGE_INVERSE_SPLIT)
     return bad(DPMM_E_ARG, "unknown merge_form");
   const int d = cfg->d;
@@ -359,6 +367,10 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     ok = ok && chk(c->alloc(&c->d_sigma, 3 * (size_t)km * d * d));
     c->scratch_slots = c->items_cap;
     ok = ok && chk(c->alloc(&c->d_scratch, (size_t)c->scratch_slots * NIW_SCRATCH(d)));
+    if (cfg->precision != DPMM_FP32) {
+      ok = ok && chk(c->alloc(&c->d_whi, (size_t)km * d * d));
+      if (cfg->precision == DPMM_BF16X3) ok = ok && chk(c->alloc(&c->d_wlo, (size_t)km * d * d));
+    }
     if (d >= SORTED_MIN_D) {
       c->hist_cap = 2048LL * km;
       ok = ok && chk(c->alloc(&c->d_hist, (size_t)c->hist_cap));
@@ -612,6 +624,12 @@ dpmm_status label_phase(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int
   if (ctx->sorted_path()) {
     sorted_plan(n, ctx->K, ctx->hist_cap, G, per);
     DPMM_TRY(ensure_perm(ctx, n));
+    if (ctx->d_whi) {
+      DPMM_HIP(ctx, launch_label_gauss_mfma(ctx->d, ctx->cfg.precision == DPMM_BF16X3, (const float*)x, n, *G, *per,
+                                            ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->K, t, ctx->cfg.seed, z,
+                                            ctx->d_hist, ctx->d_tot, ctx->stream), "matrix-core label kernel");
+      return DPMM_OK;
+    }
     DPMM_HIP(ctx, launch_label_gauss_z(ctx->d, (const float*)x, n, *G, *per, ctx->d_packed, ctx->K, t, ctx->cfg.seed, z,
                                        ctx->d_hist, ctx->d_tot, ctx->stream), "label kernel");
     return DPMM_OK;
@@ -669,6 +687,9 @@ dpmm_status dpmm_sample_params(dpmm_ctx* ctx, uint32_t t) {
                        ctx->d_log_pisub, ctx->cfg.seed, t, ctx->d_mu, ctx->d_sigma, ctx->d_scratch, ctx->d_packed,
                        ctx->d_logdet, ctx->d_err);
     DPMM_HIP(ctx, hipGetLastError(), "posterior draw kernel");
+    if (ctx->d_whi)
+      DPMM_HIP(ctx, launch_pack_wfrag(K, ctx->d, ctx->cfg.k_max, ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->stream),
+               "fragment pack kernel");
     ctx->have_params = true;
     return DPMM_OK;
   }

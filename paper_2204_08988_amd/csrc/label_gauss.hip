@@ -21,98 +21,13 @@
 // sub-labels are drawn in cluster-sorted order (sorted.hip), where the
 // sub-cluster records are wave-uniform.
 #include "kernels.hpp"
+#include "score.hpp"
 
 namespace dpmm {
 
 namespace {
 
-constexpr int BLOCK = 256;
-constexpr float RGAP = GUMBEL_MAX_F - GUMBEL_MIN_F;
-
-template <int D>
-__device__ __forceinline__ float score_rec(const float* __restrict__ p, const float (&x)[D]) {
-  float dx[D];
-#pragma unroll
-  for (int j = 0; j < D; ++j) dx[j] = x[j] - p[4 + j];
-  const float* w = p + 4 + D;
-  float q = 0.0f;
-#pragma unroll
-  for (int r = 0; r < D; ++r) {
-    float y = 0.0f;
-#pragma unroll
-    for (int c = 0; c <= r; ++c) y = fmaf(w[r * (r + 1) / 2 + c], dx[c], y);
-    q = fmaf(y, y, q);
-  }
-  return fmaf(-0.5f, q, p[0]);
-}
-
-// Generic dimension: the centred vector lives in a per-thread LDS column.
-__device__ __forceinline__ float score_rec_dyn(const float* __restrict__ p, const float* __restrict__ x,
-                                               float* dx, int d) {
-  for (int j = 0; j < d; ++j) dx[j * BLOCK] = x[j] - p[4 + j];
-  const float* w = p + 4 + d;
-  float q = 0.0f;
-  for (int r = 0; r < d; ++r) {
-    const float* wr = w + r * (r + 1) / 2;
-    float y = 0.0f;
-    for (int c = 0; c <= r; ++c) y = fmaf(wr[c], dx[c * BLOCK], y);
-    q = fmaf(y, y, q);
-  }
-  return fmaf(-0.5f, q, p[0]);
-}
-
-struct Top2 {
-  float m1, m2;
-  int arg;
-  __device__ __forceinline__ void init() {
-    m1 = -INFINITY;
-    m2 = -INFINITY;
-    arg = 0;
-  }
-  __device__ __forceinline__ void push(float l, int k) {
-    if (l > m1) {
-      m2 = m1;
-      m1 = l;
-      arg = k;
-    } else if (l > m2) {
-      m2 = l;
-    }
-  }
-};
-
-template <typename ScoreFn>
-__device__ __forceinline__ int lazy_gumbel_max(const Top2& t2, int K, uint32_t i, uint32_t t, uint64_t seed,
-                                               ScoreFn score_k) {
-  if (!(t2.m2 > t2.m1 - RGAP)) return t2.arg;
-  int cached = t2.arg >> 2;
-  u32x4 blk = rng_block(seed, t, i, TAG_GUMBEL, (uint32_t)cached);
-  float best = t2.m1 + gumbel_f(word_of(blk, t2.arg & 3));
-  int win = t2.arg;
-  for (int k = 0; k < K; ++k) {
-    if (k == t2.arg) continue;
-    const float l = score_k(k);
-    if (l + GUMBEL_MAX_F > best) {
-      const int b = k >> 2;
-      if (b != cached) {
-        blk = rng_block(seed, t, i, TAG_GUMBEL, (uint32_t)b);
-        cached = b;
-      }
-      const float s = l + gumbel_f(word_of(blk, k & 3));
-      if (s > best || (s == best && k < win)) {
-        best = s;
-        win = k;
-      }
-    }
-  }
-  return win;
-}
-
-__device__ __forceinline__ unsigned char draw_sub(float delta, uint32_t i, uint32_t t, uint64_t seed) {
-  if (delta > LOGISTIC_MAX_F) return 0;
-  if (delta < -LOGISTIC_MAX_F) return 1;
-  const float L = logistic_f(rng_block(seed, t, i, TAG_LOGISTIC, 0).x);
-  return delta + L > 0.0f ? 0 : 1;
-}
+using namespace score;
 
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_label_gauss(const float* __restrict__ x, long long n,

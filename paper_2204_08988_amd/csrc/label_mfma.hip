@@ -1,0 +1,205 @@
+// Gaussian cluster draw on the matrix cores (BF16 inputs, FP32 accumulation):
+// Sec. 4.1 step (e), eq. sample_labels, for d in {32, 64}.
+//
+// For cluster k the whitened, centred points of a tile are Y^T = W_k (X - mu_k)^T
+// with W_k lower triangular (W^T W = Sigma^-1).  W_k is the MFMA A operand
+// (pre-packed BF16 fragments, identical for every wave), the per-cluster centred
+// points (x - mu_k) rounded to BF16 are the B operand, so after
+// v_mfma_f32_32x32x16_bf16 a lane holds 16 whitened coordinates of one point
+// and the squared norm needs one cross-lane add.  A wave scores 64 points (two
+// 32-point tiles) and each lane ends up owning one point for the draw.
+//
+// BF16X3 adds the two cross terms of the hi/lo split, W_hi dx_lo + W_lo dx_hi,
+// for about 16 mantissa bits.
+//
+// Precision guard: if the runner-up is within the Gumbel range of the leader,
+// widened by an allowance for the BF16 rounding of both scores, the point is
+// re-scored in FP32 on the vector ALUs and drawn exactly as the FP32 kernel
+// draws it; otherwise no other cluster can win and the leader is the label.
+#include "kernels.hpp"
+#include "score.hpp"
+
+namespace dpmm {
+
+using namespace score;
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+namespace {
+
+// allowance on |l_bf16 - l_fp32| of a score with squared norm q
+constexpr float BF16_TOL_REL = 1.0f / 32.0f;
+constexpr float BF16X3_TOL_REL = 1.0f / 4096.0f;
+constexpr float TOL_ABS = 0.05f;
+
+template <int D, bool X3>
+__global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma(const float* __restrict__ x, long long n,
+                                                            long long per_block, const float* __restrict__ packed,
+                                                            const bf16x8* __restrict__ whi,
+                                                            const bf16x8* __restrict__ wlo, int K, uint32_t t,
+                                                            uint64_t seed, int* __restrict__ z,
+                                                            int* __restrict__ hist, int* __restrict__ tot) {
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  constexpr int MT = D / 32, KS = D / 16;
+  extern __shared__ int h[];
+  for (int k = threadIdx.x; k < K; k += BLOCK) h[k] = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  const long long begin = (long long)blockIdx.x * per_block;
+  const long long end = begin + per_block < n ? begin + per_block : n;
+  for (long long base = begin + wave * 64; base < end; base += BLOCK) {
+    // this lane's k-slices of the two tiles' points: dims 16 ks + 8 half + q
+    const long long pA = base + col, pB = base + 32 + col;
+    float xa[KS][8], xb[KS][8];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = 16 * ks + 8 * half + q;
+        xa[ks][q] = pA < end ? x[pA * D + j] : 0.0f;
+        xb[ks][q] = pB < end ? x[pB * D + j] : 0.0f;
+      }
+    float m1 = -INFINITY, m2 = -INFINITY, q1 = 0.0f, q2 = 0.0f;
+    int arg = 0;
+    for (int k = 0; k < K; ++k) {
+      const float* rec = packed + (size_t)k * S;
+      bf16x8 ba[KS], bb[KS], bal[KS], bbl[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float mu = rec[4 + 16 * ks + 8 * half + q];
+          const float da = xa[ks][q] - mu, db = xb[ks][q] - mu;
+          ba[ks][q] = (__bf16)da;
+          bb[ks][q] = (__bf16)db;
+          if (X3) {
+            bal[ks][q] = (__bf16)(da - (float)ba[ks][q]);
+            bbl[ks][q] = (__bf16)(db - (float)bb[ks][q]);
+          }
+        }
+      float qa = 0.0f, qb = 0.0f;
+      const bf16x8* wk = whi + (size_t)k * MT * KS * 64;
+      const bf16x8* wkl = X3 ? wlo + (size_t)k * MT * KS * 64 : nullptr;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f32x16 acca = {0}, accb = {0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const bf16x8 a = wk[(mt * KS + ks) * 64 + lane];
+          acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, ba[ks], acca, 0, 0, 0);
+          accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb[ks], accb, 0, 0, 0);
+          if (X3) {
+            const bf16x8 al = wkl[(mt * KS + ks) * 64 + lane];
+            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, ba[ks], acca, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bb[ks], accb, 0, 0, 0);
+            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bal[ks], acca, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbl[ks], accb, 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          qa = fmaf(acca[r], acca[r], qa);
+          qb = fmaf(accb[r], accb[r], qb);
+        }
+      }
+      qa += __shfl_xor(qa, 32);
+      qb += __shfl_xor(qb, 32);
+      // lane l owns point base + l: tile A for l < 32, tile B for l >= 32
+      const float qm = half ? qb : qa;
+      const float l = fmaf(-0.5f, qm, rec[0]);
+      if (l > m1) {
+        m2 = m1;
+        q2 = q1;
+        m1 = l;
+        q1 = qm;
+        arg = k;
+      } else if (l > m2) {
+        m2 = l;
+        q2 = qm;
+      }
+    }
+    const long long p = base + lane;
+    const bool valid = p < end;
+    const float tol = (X3 ? BF16X3_TOL_REL : BF16_TOL_REL) * (q1 + q2) + TOL_ABS;
+    int zi = arg;
+    if (valid && m2 > m1 - RGAP - tol) {
+      // FP32 re-score of this point, then the FP32 lazy Gumbel-max
+      float xv[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) xv[j] = x[p * D + j];
+      Top2 f;
+      f.init();
+      for (int k = 0; k < K; ++k) f.push(score_rec<D>(packed + (size_t)k * S, xv), k);
+      zi = lazy_gumbel_max(f, K, (uint32_t)p, t, seed,
+                           [&](int k) { return score_rec<D>(packed + (size_t)k * S, xv); });
+    }
+    if (valid) {
+      z[p] = zi;
+      atomicAdd(&h[zi], 1);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += BLOCK) {
+    hist[(size_t)blockIdx.x * K + k] = h[k];
+    if (h[k]) atomicAdd(&tot[k], h[k]);
+  }
+}
+
+// Fragment table of cluster k's whitener: element (mt, ks, lane, q) =
+// W[32 mt + lane % 32][16 ks + 8 (lane / 32) + q] (zero above the diagonal).
+__global__ void k_pack_wfrag(int K, int d, int k_max, const float* __restrict__ packed, __bf16* __restrict__ whi,
+                             __bf16* __restrict__ wlo) {
+  const int k = blockIdx.x;
+  if (k >= K) return;
+  const int S = gauss_rec_stride(d);
+  const float* w = packed + (size_t)k * S + 4 + d;
+  const int KS = d / 16;
+  for (int idx = threadIdx.x; idx < d * d; idx += blockDim.x) {
+    const int q = idx & 7, lane = (idx >> 3) & 63, f = idx >> 9;
+    const int ks = f % KS, mt = f / KS;
+    const int r = 32 * mt + (lane & 31), c = 16 * ks + 8 * (lane >> 5) + q;
+    const float v = c <= r ? w[r * (r + 1) / 2 + c] : 0.0f;
+    const __bf16 hi = (__bf16)v;
+    whi[(size_t)k * d * d + idx] = hi;
+    if (wlo) wlo[(size_t)k * d * d + idx] = (__bf16)(v - (float)hi);
+  }
+}
+
+}  // namespace
+
+bool mfma_supported(int d) { return d == 32 || d == 64; }
+
+hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void* whi, void* wlo, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_wfrag, dim3(K), dim3(256), 0, s, K, d, k_max, packed, (__bf16*)whi, (__bf16*)wlo);
+  return hipGetLastError();
+}
+
+hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, int G, long long per_block,
+                                   const float* packed, const void* whi, const void* wlo, int K, uint32_t t,
+                                   uint64_t seed, int* z, int* hist, int* tot, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipError_t e = launch_zero64(tot, (size_t)(K + 1) / 2 + 1, s);
+  if (e != hipSuccess) return e;
+  const size_t lh = (size_t)K * sizeof(int);
+  const bf16x8* hi = (const bf16x8*)whi;
+  const bf16x8* lo = (const bf16x8*)wlo;
+  if (d == 32 && !x3)
+    hipLaunchKernelGGL((k_label_gauss_mfma<32, false>), dim3(G), dim3(BLOCK), lh, s, x, n, per_block, packed, hi, lo, K,
+                       t, seed, z, hist, tot);
+  else if (d == 32)
+    hipLaunchKernelGGL((k_label_gauss_mfma<32, true>), dim3(G), dim3(BLOCK), lh, s, x, n, per_block, packed, hi, lo, K,
+                       t, seed, z, hist, tot);
+  else if (d == 64 && !x3)
+    hipLaunchKernelGGL((k_label_gauss_mfma<64, false>), dim3(G), dim3(BLOCK), lh, s, x, n, per_block, packed, hi, lo, K,
+                       t, seed, z, hist, tot);
+  else if (d == 64)
+    hipLaunchKernelGGL((k_label_gauss_mfma<64, true>), dim3(G), dim3(BLOCK), lh, s, x, n, per_block, packed, hi, lo, K,
+                       t, seed, z, hist, tot);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace dpmm

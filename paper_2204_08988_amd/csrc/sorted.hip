@@ -14,45 +14,16 @@
 // entries of sum x) in float64 registers over each segment's rows, with one
 // global atomic per entry, segment and tile.
 #include "kernels.hpp"
+#include "score.hpp"
 
 namespace dpmm {
 
 namespace {
 
-constexpr int BLOCK = 256;
+using score::BLOCK;
+using score::score_rec;
+using score::score_rec_dyn;
 constexpr int IPT_MAX = 9;  // 2x2 work items per lane for d <= 128
-
-template <int D>
-__device__ __forceinline__ float score_rec(const float* __restrict__ p, const float (&x)[D]) {
-  float dx[D];
-#pragma unroll
-  for (int j = 0; j < D; ++j) dx[j] = x[j] - p[4 + j];
-  const float* w = p + 4 + D;
-  float q = 0.0f;
-#pragma unroll
-  for (int r = 0; r < D; ++r) {
-    float y = 0.0f;
-#pragma unroll
-    for (int c = 0; c <= r; ++c) y = fmaf(w[r * (r + 1) / 2 + c], dx[c], y);
-    q = fmaf(y, y, q);
-  }
-  return fmaf(-0.5f, q, p[0]);
-}
-
-// Generic d: x read from the lane's LDS row, the centred vector kept in a
-// per-lane LDS column (stride BLOCK).
-__device__ __forceinline__ float score_rec_lds(const float* __restrict__ p, const float* xr, float* dx, int d) {
-  for (int j = 0; j < d; ++j) dx[j * BLOCK] = xr[j] - p[4 + j];
-  const float* w = p + 4 + d;
-  float q = 0.0f;
-  for (int r = 0; r < d; ++r) {
-    const float* wr = w + r * (r + 1) / 2;
-    float y = 0.0f;
-    for (int c = 0; c <= r; ++c) y = fmaf(wr[c], dx[c * BLOCK], y);
-    q = fmaf(y, y, q);
-  }
-  return fmaf(-0.5f, q, p[0]);
-}
 
 __device__ __forceinline__ int block_inclusive_scan(int v, int* buf) {
   const int tid = threadIdx.x;
@@ -293,7 +264,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
             delta = score_rec<D>(ps, xv) - score_rec<D>(ps + S, xv);
           } else {
             const float* xr = xs + (size_t)r * ld;
-            delta = score_rec_lds(ps, xr, dxc + tid, d) - score_rec_lds(ps + S, xr, dxc + tid, d);
+            delta = score_rec_dyn(ps, xr, dxc + tid, d) - score_rec_dyn(ps + S, xr, dxc + tid, d);
           }
         }
         pending &= ~__ballot(mine);
@@ -372,6 +343,172 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
     __syncthreads();
   }
   flush();
+}
+
+// Wave-independent variant for D in {8, 16, 32}: each wave walks its own
+// contiguous range of sorted rows in chunks of 64 (one row per lane), with no
+// workgroup barriers.  The chunk's segments are found with ballots (rows are
+// sorted by z, so each cluster is a run of lanes); for every segment the wave
+// loops over its rows with a wave-uniform row index, and lane j accumulates
+// the 4x4 block (I, J) of sum x x^T (or a group of four entries of sum x)
+// from broadcast LDS reads.  The current cluster's two segments are carried
+// across chunks and flushed with global atomics when the cluster changes.
+template <int D, bool SAMPLE>
+__global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__ x, long long n_sorted,
+                                                       long long rows_per_wave, const int* __restrict__ perm,
+                                                       const int* __restrict__ z, unsigned char* __restrict__ zsub,
+                                                       const float* __restrict__ packed, int k_max, uint32_t t,
+                                                       uint64_t seed, long long* __restrict__ counts,
+                                                       double* __restrict__ moments) {
+  constexpr int LDW = D + 1;  // odd row stride
+  constexpr int HB = D / 4;
+  constexpr int N_TRI = HB * (HB + 1) / 2;
+  constexpr int N_ITEMS = N_TRI + HB;
+  static_assert(N_ITEMS <= 64, "one 4x4 item per lane");
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  constexpr int E = D + D * (D + 1) / 2;
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float* xs = lds + wave * 64 * LDW;
+  // this lane's item
+  int I = -1, J = -1;
+  if (lane < N_TRI) {
+    int u = lane, a = 0;
+    while (u >= HB - a) {
+      u -= HB - a;
+      ++a;
+    }
+    I = a;
+    J = a + u;
+  } else if (lane < N_ITEMS) {
+    I = lane - N_TRI;
+    J = -2;
+  }
+  double aL[16], aR[16];
+  long long cL = 0, cR = 0;
+  int cur_k = -1;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) aL[q] = aR[q] = 0.0;
+  auto flush_one = [&](double (&acc)[16], long long cnt, int seg) {
+    if (cnt == 0) return;
+    double* M = moments + (size_t)seg * E;
+    if (J == -2) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) atomicAdd(&M[4 * I + u], acc[u]);
+    } else if (I >= 0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 4 * I + u, b = 4 * J + v;
+          if (a <= b) atomicAdd(&M[D + a * D - (a * (a - 1)) / 2 + (b - a)], acc[4 * u + v]);
+        }
+    }
+    if (lane == 0) atomicAdd((unsigned long long*)&counts[seg], (unsigned long long)cnt);
+  };
+  auto accumulate = [&](double (&acc)[16], unsigned long long mask) {
+    while (mask) {
+      const int rr = __ffsll((long long)mask) - 1;
+      mask &= mask - 1;
+      const float* row = xs + rr * LDW;
+      if (J == -2) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += (double)row[4 * I + u];
+      } else if (I >= 0) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          av[u] = row[4 * I + u];
+          bv[u] = row[4 * J + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[4 * u + v] = fma(av[u], bv[v], acc[4 * u + v]);
+      }
+    }
+  };
+  const long long gw = (long long)blockIdx.x * (BLOCK / 64) + wave;
+  const long long w_begin = gw * rows_per_wave;
+  const long long w_end = w_begin + rows_per_wave < n_sorted ? w_begin + rows_per_wave : n_sorted;
+  for (long long c0 = w_begin; c0 < w_end; c0 += 64) {
+    const long long r = c0 + lane;
+    const bool valid = r < w_end;
+    long long i = 0;
+    int k = -1;
+    float xv[D];
+    if (valid) {
+      i = perm[r];
+      k = z[i];
+#pragma unroll
+      for (int j = 0; j < D; ++j) xv[j] = x[i * D + j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < D; ++j) xv[j] = 0.0f;
+    }
+    // the previous chunk's reads of xs are done: same wave, in order
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int j = 0; j < D; ++j) xs[lane * LDW + j] = xv[j];
+    int zs = 0;
+    if (SAMPLE) {
+      float delta = 0.0f;
+      unsigned long long pending = __ballot(valid);
+      while (pending) {
+        const int lane0 = __ffsll((long long)pending) - 1;
+        const int kk = __shfl(k, lane0);
+        const bool mine = valid && k == kk;
+        if (mine) {
+          const float* ps = packed + (size_t)(k_max + 2 * kk) * S;
+          delta = score_rec<D>(ps, xv) - score_rec<D>(ps + S, xv);
+        }
+        pending &= ~__ballot(mine);
+      }
+      if (valid) {
+        if (delta > LOGISTIC_MAX_F) {
+          zs = 0;
+        } else if (delta < -LOGISTIC_MAX_F) {
+          zs = 1;
+        } else {
+          const float L = logistic_f(rng_block(seed, t, (uint32_t)i, TAG_LOGISTIC, 0).x);
+          zs = delta + L > 0.0f ? 0 : 1;
+        }
+        zsub[i] = (unsigned char)zs;
+      }
+    } else if (valid) {
+      zs = zsub[i] ? 1 : 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const unsigned long long right = __ballot(valid && zs == 1);
+    unsigned long long rem = __ballot(valid);
+    while (rem) {
+      const int lane0 = __ffsll((long long)rem) - 1;
+      const int kk = __shfl(k, lane0);
+      const unsigned long long mk = __ballot(valid && k == kk);
+      if (kk != cur_k) {
+        if (cur_k >= 0) {
+          flush_one(aL, cL, 2 * cur_k);
+          flush_one(aR, cR, 2 * cur_k + 1);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) aL[q] = aR[q] = 0.0;
+        cL = cR = 0;
+        cur_k = kk;
+      }
+      const unsigned long long mR = mk & right, mL = mk & ~right;
+      cL += __popcll(mL);
+      cR += __popcll(mR);
+      accumulate(aL, mL);
+      accumulate(aR, mR);
+      rem &= ~mk;
+    }
+  }
+  if (cur_k >= 0) {
+    flush_one(aL, cL, 2 * cur_k);
+    flush_one(aR, cR, 2 * cur_k + 1);
+  }
 }
 
 namespace {
@@ -468,6 +605,31 @@ hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, con
   e = launch_zero64(moments, (size_t)2 * K * E, s);
   if (e != hipSuccess) return e;
   if (n == 0) return hipSuccess;
+  if (d == 8 || d == 16 || d == 32) {
+    // about eight waves per CU, each on a contiguous range of whole 64-row chunks
+    const long long waves = 2048;
+    long long rpw = (n + waves - 1) / waves;
+    rpw = ((rpw + 63) / 64) * 64;
+    const long long nw = (n + rpw - 1) / rpw;
+    const unsigned grid = (unsigned)((nw + 3) / 4);
+    const size_t lds = (size_t)4 * 64 * (d + 1) * sizeof(float);
+#define DPMM_SUBW_CASE(DD)                                                                                    \
+  case DD:                                                                                                    \
+    if (sample)                                                                                               \
+      hipLaunchKernelGGL((k_sub_stats_w<DD, true>), dim3(grid), dim3(BLOCK), lds, s, x, n, rpw, perm, z, zsub, \
+                         packed, k_max, t, seed, counts, moments);                                            \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_sub_stats_w<DD, false>), dim3(grid), dim3(BLOCK), lds, s, x, n, rpw, perm, z,     \
+                         zsub, packed, k_max, t, seed, counts, moments);                                      \
+    break;
+    switch (d) {
+      DPMM_SUBW_CASE(8)
+      DPMM_SUBW_CASE(16)
+      DPMM_SUBW_CASE(32)
+    }
+#undef DPMM_SUBW_CASE
+    return hipGetLastError();
+  }
   return sample ? launch_sub_stats_t<true>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, s)
                 : launch_sub_stats_t<false>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, s);
 }

@@ -68,6 +68,8 @@ def _cfg(**kw):
     (dict(kappa=-1.0), -1),
     (dict(nu=0.5), -1),
     (dict(precision=9), -1),
+    (dict(precision=1, d=2), -1),
+    (dict(precision=2, d=48), -1),
     (dict(merge_form=3), -1),
     (dict(psi=np.array([[1.0, 2.0], [2.0, 1.0]])), -4),
     (dict(psi=np.array([[1.0, 0.5], [0.4, 1.0]])), -4),

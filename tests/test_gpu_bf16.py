@@ -1,0 +1,67 @@
+"""GPU parity of the BF16 / bf16x3 matrix-core cluster scoring (d = 32, 64).
+
+The labels must meet the FP32 comparison rule against the FP64 oracle: the
+precision guard re-scores in FP32 every point whose BF16 top-2 gap leaves the
+draw in doubt, so no label may differ where the oracle's margin is clear.
+Covariances are Wishart(d + 2, I/d) draws, the ill-conditioned shape of the
+d = 32 workload."""
+import numpy as np
+import pytest
+
+from oracle import niw, nmi, sampler
+from tests import parity_util as pu
+
+pytestmark = pytest.mark.gpu
+
+
+def _wishart_params(K, d, seed, mean_scale=5.0):
+    g = np.random.Generator(np.random.PCG64(seed))
+    mu = g.normal(0, mean_scale, size=(K, 3, d))
+    mu[:, 1:] = mu[:, :1] + g.normal(0, 0.3, size=(K, 2, d))
+    sigma = np.empty((K, 3, d, d))
+    for k in range(K):
+        for c in range(3):
+            A = np.tril(g.standard_normal((d, d)), -1) + np.diag(np.sqrt(g.chisquare(d + 2 - np.arange(d))))
+            sigma[k, c] = (A @ A.T) / d
+    return sampler.Params(np.log(g.dirichlet(np.ones(K))), np.log(g.dirichlet(np.ones(2), size=K)), mu=mu,
+                          sigma=sigma)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("d,K,n", [(32, 20, 20000), (32, 3, 4097), (64, 8, 6000), (64, 1, 333)])
+def test_bf16_labels_meet_fp32_rule(precision, d, K, n):
+    import torch
+    from paper_2204_08988_amd.sampler import Sampler
+    seed = 4000 + d + K
+    params = _wishart_params(K, d, seed)
+    x = pu.gauss_points(params, n, seed + 1)
+    S = Sampler("gaussian", d, K + 2, 2.0, seed, m=np.zeros(d), psi=np.eye(d), precision=precision)
+    S.set_params(params.log_pi, params.log_pisub, pu.comp_array(params))
+    xt = torch.from_numpy(x).cuda()
+    model = sampler.Model("gaussian", 2.0, niw.NIWPrior(1.0, np.zeros(d), d + 3, np.eye(d)), seed=seed)
+    lc, ls = sampler.loglik(model, x.astype(np.float64), params)
+    Mc, Ms = pu.gauss_scale(x, params)
+    for t in (2, 5):
+        z, zs = S.sample_labels(xt, t)
+        bad_c, bad_s, tie_c, tie_s = pu.label_mismatches(seed, t, z.cpu().numpy(), zs.cpu().numpy(), lc, ls, Mc, Ms)
+        assert bad_c.size == 0, (bad_c[:10], tie_c)
+        assert bad_s.size == 0, (bad_s[:10], tie_s)
+        assert tie_c + tie_s <= max(2, n // 1000)
+    S.close()
+
+
+def test_bf16_chain_recovers_clusters():
+    import torch
+    from paper_2204_08988_amd import datagen
+    from paper_2204_08988_amd.sampler import Sampler
+    x, lab = datagen.workload("gauss_d32", 3, n=60000)
+    d = 32
+    S = Sampler("gaussian", d, 64, 10.0, 3, m=x.mean(0).astype(np.float64), psi=np.eye(d), burn_out=5,
+                precision="bf16")
+    xt = torch.from_numpy(x).cuda()
+    z, zs = S.init_labels(x.shape[0])
+    for t in range(1, 121):
+        info = S.step(xt, t, z, zs)
+    assert 15 <= info["K"] <= 26
+    assert nmi.nmi(lab, z.cpu().numpy()) > 0.95
+    S.close()
