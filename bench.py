@@ -31,6 +31,10 @@ SEED = 1
 ALPHA = 10.0
 PEAK_FP32_VALU = 78.6e12   # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (non-packed FP32)
 PEAK_BF16_MFMA = 2.5e15    # dense BF16 matrix-core peak
+# HBM bytes per launch of the sorted sub-label/statistics kernel at this
+# workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a device copy of
+# known size (profiles/traffic_gauss_d32_n1e6.md); None once the kernel changes
+MEASURED_TRAFFIC = {"k_sub_stats_w<32,true>": 252.0e6}
 
 
 def flops_per_eval(d):
@@ -91,7 +95,7 @@ def run_form(torch, x, n, d, m, precision, steps, warmup, k_true):
         t += 1
     torch.cuda.synchronize()
     evals = 0
-    ms = {"params": 0.0, "labels": 0.0, "stats": 0.0, "splitmerge": 0.0}
+    ms = {"params": 0.0, "labels": 0.0, "sort": 0.0, "stats": 0.0, "splitmerge": 0.0}
     k_sum = 0
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -112,6 +116,7 @@ def run_form(torch, x, n, d, m, precision, steps, warmup, k_true):
         "k_mean": k_mean,
         "phase_ms": {key: v / steps for key, v in ms.items()},
         "label_kernel_ms": ms["labels"] / steps,
+        "stats_kernel_ms": ms["stats"] / steps,
         "label_evals_per_s": n * (k_mean + 2) / (ms["labels"] / steps / 1e3),
     }
     return S, z, zs, res
@@ -126,7 +131,18 @@ def main():
                     help="form reported as `value` (the other forms are reported beside it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", action="store_true", help="time only the --precision form")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy a device buffer of BYTES five times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.empty(args.copy_probe // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        c = torch.empty_like(a)
+        for _ in range(5):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
@@ -155,17 +171,29 @@ def main():
         S.close()
     r = results[args.precision]
     label_s = r["label_kernel_ms"] / 1e3
-    algo = n * (r["k_mean"] + 2) * flops_per_eval(d)
+    stats_s = r["stats_kernel_ms"] / 1e3
+    algo_label = n * (r["k_mean"] + 2) * flops_per_eval(d)
     if args.precision == "fp32":
-        roof = {"bound": "alu", "achieved": algo / label_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                "unit": "TFLOP/s", "frac": algo / label_s / PEAK_FP32_VALU, "traffic": None,
-                "kernel": "k_label_gauss_z<32> (FP32 VALU cluster draw)"}
+        label_roof = {"bound": "alu", "achieved": algo_label / label_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                      "unit": "TFLOP/s", "frac": algo_label / label_s / PEAK_FP32_VALU,
+                      "kernel": "k_label_gauss_z<32> (FP32 VALU cluster draw)"}
     else:
-        roof = {"bound": "mfma", "achieved": algo / label_s / 1e12, "peak": PEAK_BF16_MFMA / 1e12,
-                "unit": "TFLOP/s", "frac": algo / label_s / PEAK_BF16_MFMA, "traffic": None,
-                "kernel": f"k_label_gauss_mfma<32,{'true' if args.precision == 'bf16x3' else 'false'}> "
-                          "(BF16 matrix-core cluster draw)"}
-    roof["algorithmic_flops_per_eval"] = flops_per_eval(d)
+        label_roof = {"bound": "mfma", "achieved": algo_label / label_s / 1e12, "peak": PEAK_BF16_MFMA / 1e12,
+                      "unit": "TFLOP/s", "frac": algo_label / label_s / PEAK_BF16_MFMA,
+                      "kernel": f"k_label_gauss_mfma<32,{'true' if args.precision == 'bf16x3' else 'false'}> "
+                                "(BF16 matrix-core cluster draw)"}
+    label_roof["algorithmic_flops_per_eval"] = flops_per_eval(d)
+    # sub-label draw + statistics over the cluster-sorted order: two FP32
+    # sub-cluster scores and the FP64 moments (sum x, upper triangle of x x^T)
+    stats_flops = 2 * flops_per_eval(d) + d + d * (d + 1)
+    stats_roof = {"bound": "alu", "achieved": n * stats_flops / stats_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                  "unit": "TFLOP/s", "frac": n * stats_flops / stats_s / PEAK_FP32_VALU,
+                  "kernel": "k_sub_stats_w<32,true> (sub-label draw and FP64 statistics, sorted order)",
+                  "algorithmic_flops_per_point": stats_flops,
+                  "hbm_bytes_per_point": 4 * d + 4 + 4 + 1}
+    stats_roof["traffic"] = MEASURED_TRAFFIC.get("k_sub_stats_w<32,true>")
+    label_roof["traffic"] = None
+    roof, other = (stats_roof, label_roof) if stats_s > label_s else (label_roof, stats_roof)
     out = {
         "metric": "point-cluster evals/s in label step; iters/s; time-to-plateau learned vs plain",
         "value": r["value"],
@@ -192,6 +220,7 @@ def main():
         "forms": {f: {k: v for k, v in res.items() if k != "precision"} for f, res in results.items()
                   if f != args.precision},
         "roofline": roof,
+        "roofline_other_kernel": other,
     }
     if not args.no_cpu_baseline:
         z_np, zs_np, K = main_state

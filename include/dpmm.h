@@ -97,11 +97,15 @@ typedef struct {
   double logpost;    /* log p(z | x) up to a constant: K log alpha
                         + lgamma(alpha) - lgamma(alpha + N)
                         + sum_k [lgamma(N_k) + log f(C_k; lambda)] */
-  float ms_params;     /* device time of the phases, milliseconds (dpmm_step): */
-  float ms_labels;     /*   parameter draws; the label kernel (cluster draw, */
-  float ms_stats;      /*   plus sub-labels for d < 5 and multinomial); the  */
-  float ms_splitmerge; /*   rest of the label step and the statistics; the   */
-                       /*   split/merge phase                                */
+  /* device time of the phases of dpmm_step, milliseconds (HIP events on the
+   * context's stream): */
+  float ms_params;     /* parameter draws and packing */
+  float ms_labels;     /* the label kernel: cluster draw (plus the sub-label
+                          draw for d < 5 and the multinomial family) */
+  float ms_sort;       /* counting sort by cluster (Gaussian d >= 5) */
+  float ms_stats;      /* the statistics kernel (for d >= 5 also the
+                          sub-label draw, over the sorted order) */
+  float ms_splitmerge; /* split / merge phase */
 } dpmm_iter_info;
 
 /* Create a context.  hip_stream: a hipStream_t (NULL = default stream).

@@ -40,7 +40,8 @@ class IterInfo(ctypes.Structure):
     _fields_ = [
         ("K", ctypes.c_int32), ("splits", ctypes.c_int32), ("merges", ctypes.c_int32),
         ("removed", ctypes.c_int32), ("logpost", ctypes.c_double), ("ms_params", ctypes.c_float),
-        ("ms_labels", ctypes.c_float), ("ms_stats", ctypes.c_float), ("ms_splitmerge", ctypes.c_float),
+        ("ms_labels", ctypes.c_float), ("ms_sort", ctypes.c_float), ("ms_stats", ctypes.c_float),
+        ("ms_splitmerge", ctypes.c_float),
     ]
 
     def as_dict(self):

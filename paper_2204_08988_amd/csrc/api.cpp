@@ -64,7 +64,8 @@ struct dpmm_ctx {
   bool labels_gave_stats = false;
   // BF16 whitener fragments of the cluster components (precision != FP32)
   uint16_t *d_whi = nullptr, *d_wlo = nullptr;
-  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool timing = false;  // record ev[3] between the sort and the statistics kernel
 
   dpmm_status fail(dpmm_status s, const std::string& msg) {
     err = msg;
@@ -153,6 +154,7 @@ dpmm_status sorted_pass(dpmm_ctx* ctx, const void* x, int64_t n, bool labels_don
   DPMM_TRY(ensure_perm(ctx, n));
   DPMM_HIP(ctx, launch_sort_by_z(z, n, ctx->K, G, per_block, labels_done_hist, ctx->d_hist, ctx->d_tot, ctx->d_offs,
                                  ctx->d_perm, ctx->stream), "sort by cluster");
+  if (ctx->timing) DPMM_HIP(ctx, hipEventRecord(ctx->ev[3], ctx->stream), "event");
   DPMM_HIP(ctx, launch_sub_stats(ctx->d, sample, (const float*)x, n, ctx->d_perm, z, zsub, ctx->d_packed, ctx->K,
                                  ctx->cfg.k_max, t, ctx->cfg.seed, ctx->d_counts, ctx->d_moments, ctx->stream),
            "sub-label / statistics kernel");
@@ -398,7 +400,7 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
   }
   if (e == hipSuccess) e = hipMemset(c->d_err, 0, sizeof(int));
   if (e == hipSuccess) e = hipMemset(c->d_packed, 0, 3 * (size_t)km * c->stride * sizeof(float));
-  for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev[i]);
+  for (int i = 0; i < 6 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev[i]);
   if (e != hipSuccess) {
     for (auto& b : c->bufs) hipFree(b.p);
     g_create_error = std::string("device setup failed: ") + hipGetErrorString(e);
@@ -871,20 +873,26 @@ dpmm_status dpmm_step(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32
   long long per = 0;
   DPMM_TRY(label_phase(ctx, x, n, t, z, zsub, &G, &per));
   DPMM_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream), "event");
-  DPMM_TRY(sub_phase(ctx, x, n, t, z, zsub, G, per));
+  // the sorted path records ev[3] between its sort and its statistics kernel
+  ctx->timing = ctx->sorted_path();
+  const dpmm_status sp = sub_phase(ctx, x, n, t, z, zsub, G, per);
+  ctx->timing = false;
+  DPMM_TRY(sp);
+  if (!ctx->sorted_path()) DPMM_HIP(ctx, hipEventRecord(ctx->ev[3], ctx->stream), "event");
   if (!ctx->labels_gave_stats) DPMM_TRY(launch_stats(ctx, x, n, z, zsub));
-  DPMM_HIP(ctx, hipEventRecord(ctx->ev[3], ctx->stream), "event");
+  DPMM_HIP(ctx, hipEventRecord(ctx->ev[4], ctx->stream), "event");
   dpmm_iter_info local{};
   DPMM_TRY(dpmm_split_merge(ctx, x, n, t, z, zsub, &local));
-  DPMM_HIP(ctx, hipEventRecord(ctx->ev[4], ctx->stream), "event");
+  DPMM_HIP(ctx, hipEventRecord(ctx->ev[5], ctx->stream), "event");
   for (auto& a : ctx->age) ++a;
   if (info) {
     *info = local;
-    DPMM_HIP(ctx, hipEventSynchronize(ctx->ev[4]), "event sync");
+    DPMM_HIP(ctx, hipEventSynchronize(ctx->ev[5]), "event sync");
     hipEventElapsedTime(&info->ms_params, ctx->ev[0], ctx->ev[1]);
     hipEventElapsedTime(&info->ms_labels, ctx->ev[1], ctx->ev[2]);
-    hipEventElapsedTime(&info->ms_stats, ctx->ev[2], ctx->ev[3]);
-    hipEventElapsedTime(&info->ms_splitmerge, ctx->ev[3], ctx->ev[4]);
+    hipEventElapsedTime(&info->ms_sort, ctx->ev[2], ctx->ev[3]);
+    hipEventElapsedTime(&info->ms_stats, ctx->ev[3], ctx->ev[4]);
+    hipEventElapsedTime(&info->ms_splitmerge, ctx->ev[4], ctx->ev[5]);
   }
   return DPMM_OK;
 }
