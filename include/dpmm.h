@@ -30,6 +30,12 @@
  *     (entity k, draw h); 18 NIW draws and 19 Dirichlet draws of component
  *     3k + c; 20 split uniform (entity k); 21 merge uniform (entity
  *     k1 << 16 | k2).  Draw q, attempt a of tags >= 16 uses block 256 q + a.
+ *     The learned split proposal (an added form, not in the paper) uses tag
+ *     3 (Bernoulli side of point i, word 0), 4 (fresh sub-label of point i
+ *     after an accepted learned split, bit 0 of word 0), 5 (training batch
+ *     row j, entity j, t = the training step counter), 22 (move selection:
+ *     entity 0, words 0 type / 1 target / 2 acceptance) and 23 (initial
+ *     weight q: entity q, t = 0).
  *     The same (seed, t) reproduces the same draws bit for bit.
  *   - Threading: one context per host thread; calls on one context are not
  *     re-entrant.
@@ -86,6 +92,12 @@ typedef struct {
   int32_t merge_form; /* DPMM_MERGE_PAPER: ratio of Sec. 4.1 eq. sample_merges;
                          DPMM_MERGE_INVERSE_SPLIT: H_merge = 1 / H_split of
                          Sec. 2.3 */
+  int32_t learned;    /* learned split proposal (an added form; the paper has
+                         none): 0 = off; m > 0 = number of principal axes of
+                         the set features, 1 <= m <= min(d, 32), Gaussian
+                         family only.  F = 2m network inputs.  When on,
+                         dpmm_step makes one learned move after the split /
+                         merge phase */
 } dpmm_config;
 
 /* What one iteration did (filled by dpmm_split_merge and dpmm_step). */
@@ -106,7 +118,26 @@ typedef struct {
   float ms_stats;      /* the statistics kernel (for d >= 5 also the
                           sub-label draw, over the sorted order) */
   float ms_splitmerge; /* split / merge phase */
+  int32_t learned_kind;     /* learned move of dpmm_step: 0 none, 1 split, 2 merge */
+  int32_t learned_accepted; /* 1 if it was accepted */
+  float ms_learned;         /* its device-side time span, milliseconds */
 } dpmm_iter_info;
+
+/* What one learned move did (dpmm_learned_move). */
+typedef struct {
+  int32_t kind;       /* 1 split, 2 merge */
+  int32_t k1, k2;     /* split: k1 = the cluster, k2 = -1; merge: k1 < k2 */
+  int32_t accepted;   /* 1 if the labels were changed */
+  int32_t skipped;    /* 0 the MH test decided; 1 a side of the split proposal
+                         was empty; 2 a split would exceed k_max */
+  int32_t reserved;
+  int64_t n_a, n_b;   /* side sizes (split: Bernoulli sides; merge: k1, k2) */
+  double log_target;  /* split orientation: log alpha + lgamma(n_a) + log f(A)
+                         + lgamma(n_b) + log f(B) - lgamma(n_a + n_b) - log f(A u B) */
+  double log_q_part;  /* log (q(s) + q(not s)): probability of the unordered
+                         partition {A, B} under the per-point Bernoulli proposal */
+  double log_h;       /* log Hastings ratio of the move made (split or merge) */
+} dpmm_learned_info;
 
 /* Create a context.  hip_stream: a hipStream_t (NULL = default stream).
  * Allocates the device tables for k_max clusters.  On failure *out is NULL. */
@@ -183,6 +214,80 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t
  * statistics, dpmm_split_merge, then every cluster's age grows by one. */
 dpmm_status dpmm_step(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32_t* z, uint8_t* zsub,
                       dpmm_iter_info* info);
+
+/* ---- Learned split proposal (an added form; the paper has no learned
+ * component).  A network F -> 128 -> 128 -> 1 (ReLU hidden layers) maps the
+ * set features of a point to the logit of its probability b of going to side
+ * A of a proposed 2-way partition of the set; b = clip(sigmoid(logit), 1e-6,
+ * 1 - 1e-6).  Forward and backward products run on the matrix cores in BF16
+ * with FP32 accumulation; the master weights and Adam state are FP32.
+ * Parameter vector layout (n_params = F*128 + 128 + 128*128 + 128 + 128 + 1):
+ * W1[F][128], b1[128], W2[128][128], b2[128], w3[128], b3, layer k computing
+ * a_k = a_(k-1) W_k + b_k.  Every call below needs cfg.learned > 0
+ * (DPMM_E_STATE otherwise). */
+
+/* Number of network parameters (0 when the learned proposal is off). */
+int64_t dpmm_mlp_n_params(const dpmm_ctx* ctx);
+
+/* Replace (set) or read (get) the FP32 master weights: host double[n_params].
+ * Setting also resets the Adam state.  dpmm_create initialises the weights
+ * He-uniform: W1, W2, w3 entries (2u - 1) sqrt(6 / fan_in) with u the uniform
+ * of Philox word 0 at (entity q, t = 0, tag 23), q = the parameter's index in
+ * the vector; biases 0. */
+dpmm_status dpmm_mlp_set_weights(dpmm_ctx* ctx, const double* params);
+dpmm_status dpmm_mlp_get_weights(dpmm_ctx* ctx, double* params);
+
+/* Logits of n feature rows.  X: device float[n][F] (rounded to BF16 on the
+ * way in); logits: device float[n]. */
+dpmm_status dpmm_mlp_forward(dpmm_ctx* ctx, const float* X, int64_t n, float* logits);
+
+/* Gradient of the summed binary cross-entropy
+ *   L = sum_i [softplus(o_i) - y_i o_i]
+ * with respect to the parameter vector.  X: device float[n][F]; y: device
+ * float[n] in [0, 1]; grad: host double[n_params] (may be NULL); loss: host
+ * (may be NULL).  dpmm_mlp_adam_step then applies one Adam step (Kingma & Ba,
+ * betas 0.9 / 0.999, eps 1e-8, bias-corrected) with that gradient. */
+dpmm_status dpmm_mlp_grad(dpmm_ctx* ctx, const float* X, const float* y, int64_t n, double* grad, double* loss);
+dpmm_status dpmm_mlp_adam_step(dpmm_ctx* ctx, const float* X, const float* y, int64_t n, float lr, double* loss);
+
+/* Set features of the points of cluster k1 (k2 < 0) or of the union of
+ * clusters k1 and k2, from the context's statistics: mean mu and covariance
+ * Sigma (plus 1e-9 (1 + tr Sigma / d) I) of the set, eigenvalues in
+ * decreasing order, each eigenvector's largest-magnitude entry positive;
+ * features of point x: v_j^T (x - mu) / sqrt(lambda_j) and lambda_j / sum
+ * lambda for j < m.  Points in increasing index order.  feats: device
+ * float[n_set][F]; idx: device int32[n_set]; n_set: host.  feats / idx may be
+ * NULL to ask for n_set only; capacity: rows the buffers hold
+ * (DPMM_E_SHAPE if fewer than n_set). */
+dpmm_status dpmm_set_features(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, int32_t k1, int32_t k2,
+                              float* feats, int32_t* idx, int64_t capacity, int64_t* n_set);
+
+/* One learned Metropolis-Hastings move in the collapsed space of partitions
+ * (Hastings 1970; Jain & Neal 2004): split with probability 1 if K = 1 else
+ * 1/2, of the cluster floor(u K); else merge of the floor(u K(K-1)/2)-th pair
+ * in lexicographic order.  Split proposal: point i of the cluster goes to
+ * side A iff uniform(i, t, tag 3) < b_i; merge: A = k1, B = k2.  Target:
+ * alpha^K prod_B Gamma(|B|) f(x_B) (f: the NIW marginal likelihood).  The
+ * reverse move's probability uses the same per-point network on the merged
+ * set, so the move leaves the posterior invariant for any weights.  An
+ * accepted split appends cluster K (side A) with age 0, resets cluster k1's
+ * age and draws fresh sub-labels (tag 4) for its points; an accepted merge
+ * moves k2 into k1 (sub-labels l = old k1, r = old k2), deletes k2 (stable)
+ * and resets k1's age.  The statistics are then recomputed.  Needs current
+ * statistics and non-empty clusters.  side_out: optional device uint8[n]
+ * receiving 1 (side A) / 0 for the points of the set; info: host, optional. */
+dpmm_status dpmm_learned_move(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32_t* z, uint8_t* zsub,
+                              uint8_t* side_out, dpmm_learned_info* info);
+
+/* Train the network on the sampler's own sub-labels: rows are the points of
+ * clusters with age >= burn_out and two non-empty sub-clusters, target 1 for
+ * sub-label l, flipped per cluster so that side l has the larger mean first
+ * principal coordinate.  Each of `steps` Adam steps draws `batch` rows
+ * uniformly with replacement (tag 5).  loss: host, the mean loss of the last
+ * step (may be NULL).  Returns DPMM_OK without a step when no cluster
+ * qualifies (loss = NaN). */
+dpmm_status dpmm_mlp_train(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub,
+                           int32_t steps, int32_t batch, float lr, double* loss);
 
 #ifdef __cplusplus
 }

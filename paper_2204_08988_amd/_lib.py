@@ -22,7 +22,9 @@ EXPORTS = [
     "dpmm_create", "dpmm_destroy", "dpmm_last_error", "dpmm_status_string", "dpmm_init_labels",
     "dpmm_set_state", "dpmm_get_state", "dpmm_set_params", "dpmm_get_params", "dpmm_set_stats",
     "dpmm_get_stats", "dpmm_loglik", "dpmm_sample_labels", "dpmm_suffstats", "dpmm_sample_params",
-    "dpmm_split_merge", "dpmm_step",
+    "dpmm_split_merge", "dpmm_step", "dpmm_mlp_n_params", "dpmm_mlp_set_weights", "dpmm_mlp_get_weights",
+    "dpmm_mlp_forward", "dpmm_mlp_grad", "dpmm_mlp_adam_step", "dpmm_set_features", "dpmm_learned_move",
+    "dpmm_mlp_train",
 ]
 
 
@@ -33,6 +35,7 @@ class Config(ctypes.Structure):
         ("nu", ctypes.c_double), ("m", ctypes.POINTER(ctypes.c_double)),
         ("psi", ctypes.POINTER(ctypes.c_double)), ("beta", ctypes.POINTER(ctypes.c_double)),
         ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32), ("merge_form", ctypes.c_int32),
+        ("learned", ctypes.c_int32),
     ]
 
 
@@ -41,11 +44,24 @@ class IterInfo(ctypes.Structure):
         ("K", ctypes.c_int32), ("splits", ctypes.c_int32), ("merges", ctypes.c_int32),
         ("removed", ctypes.c_int32), ("logpost", ctypes.c_double), ("ms_params", ctypes.c_float),
         ("ms_labels", ctypes.c_float), ("ms_sort", ctypes.c_float), ("ms_stats", ctypes.c_float),
-        ("ms_splitmerge", ctypes.c_float),
+        ("ms_splitmerge", ctypes.c_float), ("learned_kind", ctypes.c_int32),
+        ("learned_accepted", ctypes.c_int32), ("ms_learned", ctypes.c_float),
     ]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class LearnedInfo(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("k1", ctypes.c_int32), ("k2", ctypes.c_int32),
+        ("accepted", ctypes.c_int32), ("skipped", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_a", ctypes.c_int64), ("n_b", ctypes.c_int64), ("log_target", ctypes.c_double),
+        ("log_q_part", ctypes.c_double), ("log_h", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 _lib = None
@@ -79,6 +95,15 @@ def lib():
         "dpmm_sample_params": ([vp, u32], i32),
         "dpmm_split_merge": ([vp, vp, i64, u32, vp, vp, ctypes.POINTER(IterInfo)], i32),
         "dpmm_step": ([vp, vp, i64, u32, vp, vp, ctypes.POINTER(IterInfo)], i32),
+        "dpmm_mlp_n_params": ([vp], i64),
+        "dpmm_mlp_set_weights": ([vp, dp], i32),
+        "dpmm_mlp_get_weights": ([vp, dp], i32),
+        "dpmm_mlp_forward": ([vp, vp, i64, vp], i32),
+        "dpmm_mlp_grad": ([vp, vp, vp, i64, dp, dp], i32),
+        "dpmm_mlp_adam_step": ([vp, vp, vp, i64, ctypes.c_float, dp], i32),
+        "dpmm_set_features": ([vp, vp, i64, vp, i32, i32, vp, vp, i64, ctypes.POINTER(i64)], i32),
+        "dpmm_learned_move": ([vp, vp, i64, u32, vp, vp, vp, ctypes.POINTER(LearnedInfo)], i32),
+        "dpmm_mlp_train": ([vp, vp, i64, vp, vp, i32, i32, ctypes.c_float, dp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

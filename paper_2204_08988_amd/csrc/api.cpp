@@ -15,87 +15,17 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dpmm.h"
-#include "kernels.hpp"
+#include "ctx.hpp"
 
 using namespace dpmm;
+using namespace dpmm::host;
 
 namespace {
 
 thread_local std::string g_create_error;
 
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
-
 }  // namespace
 
-struct dpmm_ctx {
-  dpmm_config cfg{};
-  std::vector<double> m, psi, beta, lgamma_beta;
-  double logdet_psi = 0.0, beta_sum = 0.0, lgamma_beta_sum = 0.0;
-  hipStream_t stream = nullptr;
-  int K = 0;
-  std::vector<int> age;
-  bool have_params = false;
-  bool have_stats = false;
-  std::string err;
-  int d = 0, E = 0, stride = 0;
-  std::vector<DevBuf> bufs;
-  // device tables
-  double *d_m = nullptr, *d_psi = nullptr, *d_beta = nullptr, *d_lgamma_beta = nullptr;
-  long long* d_counts = nullptr;  // [2 k_max]
-  double* d_moments = nullptr;    // Gaussian [2 k_max][E]
-  long long* d_sums = nullptr;    // multinomial [2 k_max][V]
-  double *d_log_pi = nullptr, *d_log_pisub = nullptr, *d_tmp = nullptr;
-  double *d_mu = nullptr, *d_sigma = nullptr, *d_log_theta = nullptr, *d_logdet = nullptr;
-  float* d_packed = nullptr;
-  double* d_scratch = nullptr;  // NIW_SCRATCH(d) per workgroup slot
-  int scratch_slots = 0;
-  int* d_err = nullptr;
-  LogmlItem* d_items = nullptr;
-  double* d_logml = nullptr;
-  int items_cap = 0;
-  RelabelEntry* d_table = nullptr;
-  // cluster-sorted path (Gaussian, d >= SORTED_MIN_D)
-  int *d_hist = nullptr, *d_offs = nullptr, *d_tot = nullptr, *d_perm = nullptr;
-  long long hist_cap = 0, perm_cap = 0;
-  bool labels_gave_stats = false;
-  // BF16 whitener fragments of the cluster components (precision != FP32)
-  uint16_t *d_whi = nullptr, *d_wlo = nullptr;
-  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  bool timing = false;  // record ev[3] between the sort and the statistics kernel
-
-  dpmm_status fail(dpmm_status s, const std::string& msg) {
-    err = msg;
-    return s;
-  }
-  dpmm_status hip(hipError_t e, const char* what) {
-    if (e == hipSuccess) return DPMM_OK;
-    err = std::string(what) + ": " + hipGetErrorString(e);
-    return e == hipErrorOutOfMemory ? DPMM_E_OOM : DPMM_E_DEVICE;
-  }
-  template <typename T>
-  hipError_t alloc(T** p, size_t count) {
-    DevBuf b;
-    b.bytes = std::max<size_t>(count * sizeof(T), 16);
-    hipError_t e = hipMalloc(&b.p, b.bytes);
-    if (e != hipSuccess) return e;
-    bufs.push_back(b);
-    *p = static_cast<T*>(b.p);
-    return hipSuccess;
-  }
-  bool gaussian() const { return cfg.family == DPMM_GAUSSIAN; }
-  bool sorted_path() const { return gaussian() && d >= SORTED_MIN_D; }
-};
-
-#define DPMM_TRY(expr)                         \
-  do {                                         \
-    dpmm_status _s = (expr);                   \
-    if (_s != DPMM_OK) return _s;              \
-  } while (0)
-#define DPMM_HIP(ctx, expr, what) DPMM_TRY((ctx)->hip((expr), (what)))
 
 namespace {
 
@@ -117,7 +47,9 @@ bool host_cholesky_logdet(std::vector<double> a, int d, double* logdet) {
   return true;
 }
 
-inline int tri_index(int a, int b, int d) { return a * d - (a * (a - 1)) / 2 + (b - a); }
+}  // namespace
+
+namespace dpmm::host {
 
 dpmm_status check_n(dpmm_ctx* ctx, const void* x, int64_t n) {
   if (!x && n > 0) return ctx->fail(DPMM_E_ARG, "x is NULL");
@@ -181,8 +113,7 @@ dpmm_status launch_stats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t*
 
 // log marginal likelihoods of a list of segment unions (device), read back.
 // *flag_out (optional) receives the device error flag after the launches.
-dpmm_status logml(dpmm_ctx* ctx, const std::vector<LogmlItem>& items, std::vector<double>& out,
-                  int* flag_out = nullptr) {
+dpmm_status logml(dpmm_ctx* ctx, const std::vector<LogmlItem>& items, std::vector<double>& out, int* flag_out) {
   out.assign(items.size(), 0.0);
   size_t done = 0;
   while (done < items.size()) {
@@ -265,7 +196,7 @@ dpmm_status pack_params(dpmm_ctx* ctx) {
   return DPMM_OK;
 }
 
-}  // namespace
+}  // namespace dpmm::host
 
 extern "C" {
 
@@ -312,6 +243,11 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     return bad(DPMM_E_ARG, "BF16 matrix-core scoring needs the Gaussian family with d = 32 or 64");
   if (cfg->merge_form != DPMM_MERGE_PAPER && cfg->merge_form != DPMM_MERGE_INVERSE_SPLIT)
     return bad(DPMM_E_ARG, "unknown merge_form");
+  if (cfg->learned < 0) return bad(DPMM_E_ARG, "learned must be >= 0");
+  if (cfg->learned > 0 && cfg->family != DPMM_GAUSSIAN)
+    return bad(DPMM_E_ARG, "the learned proposal needs the Gaussian family");
+  if (cfg->learned > 0 && (cfg->learned > cfg->d || cfg->learned > 32))
+    return bad(DPMM_E_ARG, "learned (principal axes) must lie in [1, min(d, 32)]");
   const int d = cfg->d;
   std::unique_ptr<dpmm_ctx> ctx(new dpmm_ctx());
   ctx->cfg = *cfg;
@@ -389,6 +325,11 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     for (auto& b : c->bufs) hipFree(b.p);
     return bad(DPMM_E_OOM, "device allocation failed");
   }
+  if (cfg->learned > 0 && learned_alloc(c) != DPMM_OK) {
+    for (auto& b : c->bufs) hipFree(b.p);
+    g_create_error = c->err;
+    return DPMM_E_OOM;
+  }
   hipError_t e = hipSuccess;
   if (c->gaussian()) {
     e = hipMemcpy(c->d_m, c->m.data(), d * sizeof(double), hipMemcpyHostToDevice);
@@ -400,7 +341,7 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
   }
   if (e == hipSuccess) e = hipMemset(c->d_err, 0, sizeof(int));
   if (e == hipSuccess) e = hipMemset(c->d_packed, 0, 3 * (size_t)km * c->stride * sizeof(float));
-  for (int i = 0; i < 6 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev[i]);
+  for (int i = 0; i < 7 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev[i]);
   if (e != hipSuccess) {
     for (auto& b : c->bufs) hipFree(b.p);
     g_create_error = std::string("device setup failed: ") + hipGetErrorString(e);
@@ -416,6 +357,8 @@ void dpmm_destroy(dpmm_ctx* ctx) {
   else hipDeviceSynchronize();
   for (auto& b : ctx->bufs) hipFree(b.p);
   if (ctx->d_perm) hipFree(ctx->d_perm);
+  if (ctx->d_sel) hipFree(ctx->d_sel);
+  if (ctx->d_side) hipFree(ctx->d_side);
   for (auto& e : ctx->ev)
     if (e) hipEventDestroy(e);
   delete ctx;
@@ -884,10 +827,19 @@ dpmm_status dpmm_step(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32
   dpmm_iter_info local{};
   DPMM_TRY(dpmm_split_merge(ctx, x, n, t, z, zsub, &local));
   DPMM_HIP(ctx, hipEventRecord(ctx->ev[5], ctx->stream), "event");
+  dpmm_learned_info li{};
+  if (ctx->lm > 0) {
+    DPMM_TRY(learned_move(ctx, x, n, t, z, zsub, nullptr, &li));
+    local.K = ctx->K;
+  }
+  DPMM_HIP(ctx, hipEventRecord(ctx->ev[6], ctx->stream), "event");
   for (auto& a : ctx->age) ++a;
   if (info) {
     *info = local;
-    DPMM_HIP(ctx, hipEventSynchronize(ctx->ev[5]), "event sync");
+    info->learned_kind = li.kind;
+    info->learned_accepted = li.accepted;
+    DPMM_HIP(ctx, hipEventSynchronize(ctx->ev[6]), "event sync");
+    hipEventElapsedTime(&info->ms_learned, ctx->ev[5], ctx->ev[6]);
     hipEventElapsedTime(&info->ms_params, ctx->ev[0], ctx->ev[1]);
     hipEventElapsedTime(&info->ms_labels, ctx->ev[1], ctx->ev[2]);
     hipEventElapsedTime(&info->ms_sort, ctx->ev[2], ctx->ev[3]);

@@ -1,0 +1,128 @@
+// Private definition of the library context and the host helpers shared by
+// the C ABI translation units (api.cpp: the sampler; learned.cpp: the learned
+// split proposal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dpmm.h"
+#include "kernels.hpp"
+
+using dpmm::LogmlItem;
+using dpmm::NiwPriorDev;
+using dpmm::RelabelEntry;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct dpmm_ctx {
+  dpmm_config cfg{};
+  std::vector<double> m, psi, beta, lgamma_beta;
+  double logdet_psi = 0.0, beta_sum = 0.0, lgamma_beta_sum = 0.0;
+  hipStream_t stream = nullptr;
+  int K = 0;
+  std::vector<int> age;
+  bool have_params = false;
+  bool have_stats = false;
+  std::string err;
+  int d = 0, E = 0, stride = 0;
+  std::vector<DevBuf> bufs;
+  // device tables
+  double *d_m = nullptr, *d_psi = nullptr, *d_beta = nullptr, *d_lgamma_beta = nullptr;
+  long long* d_counts = nullptr;  // [2 k_max]
+  double* d_moments = nullptr;    // Gaussian [2 k_max][E]
+  long long* d_sums = nullptr;    // multinomial [2 k_max][V]
+  double *d_log_pi = nullptr, *d_log_pisub = nullptr, *d_tmp = nullptr;
+  double *d_mu = nullptr, *d_sigma = nullptr, *d_log_theta = nullptr, *d_logdet = nullptr;
+  float* d_packed = nullptr;
+  double* d_scratch = nullptr;  // NIW_SCRATCH(d) per workgroup slot
+  int scratch_slots = 0;
+  int* d_err = nullptr;
+  LogmlItem* d_items = nullptr;
+  double* d_logml = nullptr;
+  int items_cap = 0;
+  RelabelEntry* d_table = nullptr;
+  // cluster-sorted path (Gaussian, d >= dpmm::SORTED_MIN_D)
+  int *d_hist = nullptr, *d_offs = nullptr, *d_tot = nullptr, *d_perm = nullptr;
+  long long hist_cap = 0, perm_cap = 0;
+  bool labels_gave_stats = false;
+  // BF16 whitener fragments of the cluster components (precision != FP32)
+  uint16_t *d_whi = nullptr, *d_wlo = nullptr;
+  hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool timing = false;  // record ev[3] between the sort and the statistics kernel
+  // learned split proposal (cfg.learned = m > 0 principal axes, F = 2m features)
+  int lm = 0, F = 0, Fp = 0, n_mlp = 0;
+  float *d_p = nullptr, *d_g = nullptr, *d_am = nullptr, *d_av = nullptr;  // FP32 master weights, gradient, Adam
+  int adam_t = 0;
+  uint32_t train_counter = 0;
+  uint16_t *d_w1t = nullptr, *d_w2t = nullptr, *d_w2 = nullptr;  // BF16 operand copies
+  bool weights_fresh = false;
+  // per-chunk activations (MLP_CHUNK rows)
+  uint16_t *d_x16 = nullptr, *d_x16t = nullptr, *d_h1 = nullptr, *d_h1t = nullptr;
+  uint16_t *d_d2 = nullptr, *d_d2t = nullptr, *d_d1 = nullptr, *d_d1t = nullptr;
+  float *d_h2 = nullptr, *d_o = nullptr, *d_y = nullptr;
+  int *d_bidx = nullptr, *d_bcl = nullptr;
+  float* d_frames = nullptr;  // [k_max][d + m d + m]
+  int *d_flip = nullptr, *d_elig = nullptr;
+  double* d_lsums = nullptr;     // proposal sums [4], loss [1]
+  double* d_setpart = nullptr;   // set-statistics partials [SET_STATS_BLOCKS][2][E + 1]
+  int* d_selcnt = nullptr;       // selection block counts [SELECT_BLOCKS + 1]
+  int* d_sel = nullptr;          // selected point indices [sel_cap]
+  unsigned char* d_side = nullptr;  // side of each point [sel_cap]
+  long long sel_cap = 0;
+
+  dpmm_status fail(dpmm_status s, const std::string& msg) {
+    err = msg;
+    return s;
+  }
+  dpmm_status hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return DPMM_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? DPMM_E_OOM : DPMM_E_DEVICE;
+  }
+  template <typename T>
+  hipError_t alloc(T** p, size_t count) {
+    DevBuf b;
+    b.bytes = std::max<size_t>(count * sizeof(T), 16);
+    hipError_t e = hipMalloc(&b.p, b.bytes);
+    if (e != hipSuccess) return e;
+    bufs.push_back(b);
+    *p = static_cast<T*>(b.p);
+    return hipSuccess;
+  }
+  bool gaussian() const { return cfg.family == DPMM_GAUSSIAN; }
+  bool sorted_path() const { return gaussian() && d >= dpmm::SORTED_MIN_D; }
+};
+
+#define DPMM_TRY(expr)                         \
+  do {                                         \
+    dpmm_status _s = (expr);                   \
+    if (_s != DPMM_OK) return _s;              \
+  } while (0)
+#define DPMM_HIP(ctx, expr, what) DPMM_TRY((ctx)->hip((expr), (what)))
+
+namespace dpmm::host {
+
+inline int tri_index(int a, int b, int d) { return a * d - (a * (a - 1)) / 2 + (b - a); }
+dpmm_status check_n(dpmm_ctx* ctx, const void* x, int64_t n);
+NiwPriorDev prior_dev(dpmm_ctx* ctx);
+dpmm_status launch_stats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub);
+// log marginal likelihoods of segment unions, read back (synchronises);
+// *flag_out (optional) receives the device error flag
+dpmm_status logml(dpmm_ctx* ctx, const std::vector<LogmlItem>& items, std::vector<double>& out,
+                  int* flag_out = nullptr);
+dpmm_status check_device_error(dpmm_ctx* ctx);
+dpmm_status apply_relabel(dpmm_ctx* ctx, const std::vector<RelabelEntry>& table, int64_t n, uint32_t t, int32_t* z,
+                          uint8_t* zsub);
+// learned.cpp: buffers of the learned proposal (called by dpmm_create)
+dpmm_status learned_alloc(dpmm_ctx* ctx);
+dpmm_status learned_move(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32_t* z, uint8_t* zsub,
+                         uint8_t* side_out, dpmm_learned_info* info);
+
+}  // namespace dpmm::host

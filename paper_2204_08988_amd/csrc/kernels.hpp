@@ -32,6 +32,46 @@ __global__ void k_pack_gauss(int K, int d, int k_max, const double* log_pi, cons
 __global__ void k_pack_mult(int K, int V, int k_max, const double* log_pi, const double* log_pisub,
                             const double* log_theta, float* packed);
 
+// ---- learned split proposal (mlp.hip)
+constexpr int MLP_HIDDEN = 128;
+constexpr float MLP_CLIP = 1e-6f;
+constexpr int MLP_CHUNK = 65536;      // rows per forward / backward pass
+constexpr int SELECT_BLOCKS = 1024;   // blocks of the stable selection
+constexpr int SET_STATS_BLOCKS = 128; // blocks of the partition statistics
+constexpr uint32_t TAG_LEARNSUB = 4;
+constexpr uint32_t TAG_TRAIN = 5;
+constexpr uint32_t TAG_MLPINIT = 23;
+hipError_t launch_gemm_nt(const void* A, int lda, const void* Bt, int ldb, int M, int N, int K, const float* bias,
+                          bool relu, const void* mask, int ldm, float* out32, int ld32, bool accumulate, void* out16,
+                          int ld16, void* out16t, int ld16t, hipStream_t s);
+hipError_t launch_out_layer(const float* H2, int n, const float* w3, const float* b3, float* o, hipStream_t s);
+hipError_t launch_out_backward(const float* o, const float* y, const float* H2, int n, int npad, const float* w3,
+                               void* D2, void* D2t, float* gw3, float* gb3, double* loss, hipStream_t s);
+hipError_t launch_colsum(const void* A, int lda, int n, int ncol, float* out, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s);
+hipError_t launch_refresh_weights(const float* p, int F, int Fp, void* w1t, void* w2t, void* w2, hipStream_t s);
+hipError_t launch_features(const float* x, int d, const int* idx, const int* cl, int n, const float* frames, int m,
+                           int F, int Fp, void* X16, void* X16t, int npad, float* X32, hipStream_t s);
+hipError_t launch_convert(const float* X32, int n, int F, int Fp, void* X16, void* X16t, int npad, hipStream_t s);
+hipError_t launch_targets(const int* idx, const int* cl, int n, const unsigned char* zsub, const int* flip, float* y,
+                          hipStream_t s);
+hipError_t launch_proposal(const float* o, const int* idx, int n, int merge_k1, const int* z, uint64_t seed,
+                           uint32_t t, unsigned char* side, double* sums, hipStream_t s);
+hipError_t launch_apply_split(const int* idx, int n, const unsigned char* side, int k_new, uint64_t seed, uint32_t t,
+                              int* z, unsigned char* zsub, hipStream_t s);
+// stable selection of {i : z_i in {k1, k2}} (elig == nullptr) or {i : elig[z_i]};
+// cnt: int[SELECT_BLOCKS + 1], the count lands in cnt[SELECT_BLOCKS]
+hipError_t launch_select(const int* z, long long n, int k1, int k2, const int* elig, int K, int* cnt, int* out,
+                         hipStream_t s);
+// float64 statistics of the sides (side[i] = 1: A, 0: B) of the points idx[0..n)
+// into counts / moments slots slot (A) and slot + 1 (B); part: double
+// [SET_STATS_BLOCKS][2][1 + d + d(d+1)/2]
+hipError_t launch_set_stats(const float* x, int d, const int* idx, int n, const unsigned char* side, double* part,
+                            int slot, long long* counts, double* moments, hipStream_t s);
+hipError_t launch_batch_pick(const int* sel, long long n_sel, int batch, uint64_t seed, uint32_t counter, const int* z,
+                             int* bidx, int* bcl, hipStream_t s);
+
 // ---- host launchers of the templated hot kernels
 hipError_t launch_label_gauss(int d, const float* x, long long n, const float* packed, int K, int k_max,
                               uint32_t t, uint64_t seed, int* z, unsigned char* zsub, hipStream_t s);

@@ -29,7 +29,7 @@ class Sampler:
     """One sampler context on the current HIP device and torch stream."""
 
     def __init__(self, family, d, k_max, alpha, seed, kappa=1.0, nu=None, m=None, psi=None,
-                 beta=None, burn_out=15, merge_form="paper", precision="fp32", stream=None):
+                 beta=None, burn_out=15, merge_form="paper", precision="fp32", learned=0, stream=None):
         import torch
         self.torch = torch
         L = _lib.lib()
@@ -56,6 +56,8 @@ class Sampler:
         cfg.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
         cfg.precision = {"fp32": _lib.FP32, "bf16": _lib.BF16, "bf16x3": _lib.BF16X3}[precision]
         cfg.merge_form = {"paper": _lib.MERGE_PAPER, "inverse_split": _lib.MERGE_INVERSE_SPLIT}[merge_form]
+        cfg.learned = int(learned)
+        self.learned = int(learned)
         self._L = L
         self._ctx = ctypes.c_void_p()
         st = stream if stream is not None else _stream(torch)
@@ -180,3 +182,60 @@ class Sampler:
         self._check(self._L.dpmm_step(self._ctx, _tptr(x), x.shape[0], int(t), _tptr(z), _tptr(zsub),
                                       ctypes.byref(info)))
         return info.as_dict()
+
+    # ------------------------------------------------------------------ learned proposal
+    @property
+    def n_mlp_params(self):
+        return int(self._L.dpmm_mlp_n_params(self._ctx))
+
+    def mlp_set_weights(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        if p.shape != (self.n_mlp_params,):
+            raise ValueError("parameter vector length mismatch")
+        self._check(self._L.dpmm_mlp_set_weights(self._ctx, _dptr(p)))
+
+    def mlp_get_weights(self):
+        p = np.zeros(self.n_mlp_params)
+        self._check(self._L.dpmm_mlp_get_weights(self._ctx, _dptr(p)))
+        return p
+
+    def mlp_forward(self, X):
+        out = self.torch.empty(X.shape[0], dtype=self.torch.float32, device=X.device)
+        self._check(self._L.dpmm_mlp_forward(self._ctx, _tptr(X), X.shape[0], _tptr(out)))
+        return out
+
+    def mlp_grad(self, X, y):
+        g = np.zeros(self.n_mlp_params)
+        loss = ctypes.c_double()
+        self._check(self._L.dpmm_mlp_grad(self._ctx, _tptr(X), _tptr(y), X.shape[0], _dptr(g), ctypes.byref(loss)))
+        return g, loss.value
+
+    def mlp_adam_step(self, X, y, lr):
+        loss = ctypes.c_double()
+        self._check(self._L.dpmm_mlp_adam_step(self._ctx, _tptr(X), _tptr(y), X.shape[0], float(lr),
+                                               ctypes.byref(loss)))
+        return loss.value
+
+    def set_features(self, x, z, k1, k2=-1):
+        """(features float32 [n_set][F], point indices int32 [n_set]) of the set."""
+        n_set = ctypes.c_int64()
+        self._check(self._L.dpmm_set_features(self._ctx, _tptr(x), x.shape[0], _tptr(z), int(k1), int(k2), None,
+                                              None, 0, ctypes.byref(n_set)))
+        F = 2 * self.learned
+        feats = self.torch.empty((n_set.value, F), dtype=self.torch.float32, device=x.device)
+        idx = self.torch.empty(n_set.value, dtype=self.torch.int32, device=x.device)
+        self._check(self._L.dpmm_set_features(self._ctx, _tptr(x), x.shape[0], _tptr(z), int(k1), int(k2),
+                                              _tptr(feats), _tptr(idx), n_set.value, ctypes.byref(n_set)))
+        return feats, idx
+
+    def learned_move(self, x, t, z, zsub, side=None):
+        info = _lib.LearnedInfo()
+        self._check(self._L.dpmm_learned_move(self._ctx, _tptr(x), x.shape[0], int(t), _tptr(z), _tptr(zsub),
+                                              _tptr(side), ctypes.byref(info)))
+        return info.as_dict()
+
+    def mlp_train(self, x, z, zsub, steps, batch, lr):
+        loss = ctypes.c_double()
+        self._check(self._L.dpmm_mlp_train(self._ctx, _tptr(x), x.shape[0], _tptr(z), _tptr(zsub), int(steps),
+                                           int(batch), float(lr), ctypes.byref(loss)))
+        return loss.value

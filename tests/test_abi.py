@@ -52,6 +52,7 @@ def _cfg(**kw):
     cfg.seed = 1
     cfg.precision = kw.pop("precision", _lib.FP32)
     cfg.merge_form = kw.pop("merge_form", _lib.MERGE_PAPER)
+    cfg.learned = kw.pop("learned", 0)
     assert not kw
     return cfg, keep
 
@@ -71,6 +72,10 @@ def _cfg(**kw):
     (dict(precision=1, d=2), -1),
     (dict(precision=2, d=48), -1),
     (dict(merge_form=3), -1),
+    (dict(learned=-1), -1),
+    (dict(learned=3, d=2), -1),
+    (dict(learned=33, d=64), -1),
+    (dict(learned=1, family=_lib.MULTINOMIAL, d=4, beta=np.ones(4)), -1),
     (dict(psi=np.array([[1.0, 2.0], [2.0, 1.0]])), -4),
     (dict(psi=np.array([[1.0, 0.5], [0.4, 1.0]])), -4),
     (dict(family=_lib.MULTINOMIAL, d=4), -1),
@@ -96,3 +101,10 @@ def test_null_arguments():
     assert L.dpmm_step(None, None, 0, 1, None, None, None) == -1
     L.dpmm_destroy(None)
     assert L.dpmm_status_string(-3) == b"capacity exceeded"
+    assert L.dpmm_mlp_n_params(None) == 0
+    assert L.dpmm_mlp_set_weights(None, None) == -1
+    assert L.dpmm_mlp_forward(None, None, 0, None) == -1
+    assert L.dpmm_mlp_grad(None, None, None, 0, None, None) == -1
+    assert L.dpmm_learned_move(None, None, 0, 1, None, None, None, None) == -1
+    assert L.dpmm_mlp_train(None, None, 0, None, None, 1, 1, 1e-3, None) == -1
+    assert L.dpmm_set_features(None, None, 0, None, 0, -1, None, None, 0, None) == -1
