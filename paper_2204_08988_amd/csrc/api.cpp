@@ -327,6 +327,8 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
   }
   if (cfg->learned > 0 && learned_alloc(c) != DPMM_OK) {
     for (auto& b : c->bufs) hipFree(b.p);
+    if (c->h_frame) hipHostFree(c->h_frame);
+    if (c->h_back) hipHostFree(c->h_back);
     g_create_error = c->err;
     return DPMM_E_OOM;
   }
@@ -359,6 +361,8 @@ void dpmm_destroy(dpmm_ctx* ctx) {
   if (ctx->d_perm) hipFree(ctx->d_perm);
   if (ctx->d_sel) hipFree(ctx->d_sel);
   if (ctx->d_side) hipFree(ctx->d_side);
+  if (ctx->h_frame) hipHostFree(ctx->h_frame);
+  if (ctx->h_back) hipHostFree(ctx->h_back);
   for (auto& e : ctx->ev)
     if (e) hipEventDestroy(e);
   delete ctx;

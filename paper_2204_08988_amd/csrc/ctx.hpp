@@ -16,6 +16,14 @@ using dpmm::LogmlItem;
 using dpmm::NiwPriorDev;
 using dpmm::RelabelEntry;
 
+// pinned read-back slots of the learned move
+struct LearnedBack {
+  int sel_count;
+  int pad;
+  long long side_cnt[2];
+  double sums[4];
+};
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -76,6 +84,8 @@ struct dpmm_ctx {
   int* d_sel = nullptr;          // selected point indices [sel_cap]
   unsigned char* d_side = nullptr;  // side of each point [sel_cap]
   long long sel_cap = 0;
+  float* h_frame = nullptr;       // pinned staging of one set frame
+  LearnedBack* h_back = nullptr;  // pinned read-back slots
 
   dpmm_status fail(dpmm_status s, const std::string& msg) {
     err = msg;

@@ -51,15 +51,17 @@ hipError_t launch_colsum(const void* A, int lda, int n, int ncol, float* out, hi
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
                        int step, hipStream_t s);
 hipError_t launch_refresh_weights(const float* p, int F, int Fp, void* w1t, void* w2t, void* w2, hipStream_t s);
-hipError_t launch_features(const float* x, int d, const int* idx, const int* cl, int n, const float* frames, int m,
-                           int F, int Fp, void* X16, void* X16t, int npad, float* X32, hipStream_t s);
+// rows whose idx is outside [0, npts) are zero / skipped by the set kernels
+hipError_t launch_features(const float* x, int d, long long npts, const int* idx, const int* cl, int n,
+                           const float* frames, int m, int F, int Fp, void* X16, void* X16t, int npad, float* X32,
+                           hipStream_t s);
 hipError_t launch_convert(const float* X32, int n, int F, int Fp, void* X16, void* X16t, int npad, hipStream_t s);
 hipError_t launch_targets(const int* idx, const int* cl, int n, const unsigned char* zsub, const int* flip, float* y,
                           hipStream_t s);
-hipError_t launch_proposal(const float* o, const int* idx, int n, int merge_k1, const int* z, uint64_t seed,
-                           uint32_t t, unsigned char* side, double* sums, hipStream_t s);
-hipError_t launch_apply_split(const int* idx, int n, const unsigned char* side, int k_new, uint64_t seed, uint32_t t,
-                              int* z, unsigned char* zsub, hipStream_t s);
+hipError_t launch_proposal(const float* o, long long npts, const int* idx, int n, int merge_k1, const int* z,
+                           uint64_t seed, uint32_t t, unsigned char* side, double* sums, hipStream_t s);
+hipError_t launch_apply_split(long long npts, const int* idx, int n, const unsigned char* side, int k_new,
+                              uint64_t seed, uint32_t t, int* z, unsigned char* zsub, hipStream_t s);
 // stable selection of {i : z_i in {k1, k2}} (elig == nullptr) or {i : elig[z_i]};
 // cnt: int[SELECT_BLOCKS + 1], the count lands in cnt[SELECT_BLOCKS]
 hipError_t launch_select(const int* z, long long n, int k1, int k2, const int* elig, int K, int* cnt, int* out,
@@ -67,8 +69,8 @@ hipError_t launch_select(const int* z, long long n, int k1, int k2, const int* e
 // float64 statistics of the sides (side[i] = 1: A, 0: B) of the points idx[0..n)
 // into counts / moments slots slot (A) and slot + 1 (B); part: double
 // [SET_STATS_BLOCKS][2][1 + d + d(d+1)/2]
-hipError_t launch_set_stats(const float* x, int d, const int* idx, int n, const unsigned char* side, double* part,
-                            int slot, long long* counts, double* moments, hipStream_t s);
+hipError_t launch_set_stats(const float* x, int d, long long npts, const int* idx, int n, const unsigned char* side,
+                            double* part, int slot, long long* counts, double* moments, hipStream_t s);
 hipError_t launch_batch_pick(const int* sel, long long n_sel, int batch, uint64_t seed, uint32_t counter, const int* z,
                              int* bidx, int* bcl, hipStream_t s);
 

@@ -6,13 +6,16 @@
 // backward passes (matrix cores), the per-point Bernoulli sides and their
 // log-probability sums, the float64 statistics of the proposed sides, the
 // marginal likelihoods and the relabelling.  Host work per move: one
-// symmetric eigendecomposition of the set's d x d covariance (cyclic Jacobi,
-// float64) and the O(1) accept / reject arithmetic on values read back.
+// symmetric eigendecomposition of the set's d x d covariance (Householder
+// tridiagonalisation and implicit QR, float64) and the O(1) accept / reject
+// arithmetic on values read back; two synchronisations per move.
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "ctx.hpp"
+#include "eigen.hpp"
 
 using namespace dpmm;
 using namespace dpmm::host;
@@ -39,58 +42,14 @@ Offsets offsets(int F) {
 
 int frame_size(const dpmm_ctx* ctx) { return ctx->d + ctx->lm * ctx->d + ctx->lm; }
 
-// Cyclic Jacobi eigendecomposition of a symmetric matrix (Golub & Van Loan,
-// Matrix Computations, Sec. 8.5): A (row-major d x d) is overwritten; w gets
-// the eigenvalues, the columns of V the eigenvectors.
-void jacobi_eigen(std::vector<double>& A, int d, std::vector<double>& w, std::vector<double>& V) {
-  V.assign((size_t)d * d, 0.0);
-  for (int i = 0; i < d; ++i) V[(size_t)i * d + i] = 1.0;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < d; ++i)
-      for (int j = 0; j < d; ++j) {
-        const double v = A[(size_t)i * d + j] * A[(size_t)i * d + j];
-        tot += v;
-        if (i != j) off += v;
-      }
-    if (!(off > 1e-32 * tot)) break;
-    for (int p = 0; p < d; ++p)
-      for (int q = p + 1; q < d; ++q) {
-        const double apq = A[(size_t)p * d + q];
-        if (apq == 0.0) continue;
-        // rotation in the (p, q) plane that zeroes A[p][q]
-        const double theta = (A[(size_t)q * d + q] - A[(size_t)p * d + p]) / (2.0 * apq);
-        const double tn = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(tn * tn + 1.0), s = tn * c;
-        for (int k = 0; k < d; ++k) {
-          const double akp = A[(size_t)k * d + p], akq = A[(size_t)k * d + q];
-          A[(size_t)k * d + p] = c * akp - s * akq;
-          A[(size_t)k * d + q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < d; ++k) {
-          const double apk = A[(size_t)p * d + k], aqk = A[(size_t)q * d + k];
-          A[(size_t)p * d + k] = c * apk - s * aqk;
-          A[(size_t)q * d + k] = s * apk + c * aqk;
-        }
-        A[(size_t)p * d + q] = A[(size_t)q * d + p] = 0.0;
-        for (int k = 0; k < d; ++k) {
-          const double vkp = V[(size_t)k * d + p], vkq = V[(size_t)k * d + q];
-          V[(size_t)k * d + p] = c * vkp - s * vkq;
-          V[(size_t)k * d + q] = s * vkp + c * vkq;
-        }
-      }
-  }
-  w.resize(d);
-  for (int i = 0; i < d; ++i) w[i] = A[(size_t)i * d + i];
-}
-
 // Frame of a set with statistics (n, s, upper triangle U of sum x x^T):
 // out = [mu (d), P (m x d), ratios (m)] as float32, with mu the mean, Sigma
 // the covariance plus 1e-9 (1 + tr Sigma / d) I, eigenpairs by decreasing
 // eigenvalue with each eigenvector's largest-magnitude entry positive,
 // P_j = v_j / sqrt(lambda_j) and ratios_j = lambda_j / sum lambda.  Also
-// returns P_0 in float64 (for the training targets' orientation).
-void set_frame(double n, const double* s, const double* U, int d, int m, float* out, std::vector<double>* p0) {
+// returns P_0 in float64 (for the training targets' orientation).  False if
+// the eigen-iteration did not converge.
+bool set_frame(double n, const double* s, const double* U, int d, int m, float* out, std::vector<double>* p0) {
   std::vector<double> mu(d), A((size_t)d * d);
   for (int i = 0; i < d; ++i) mu[i] = s[i] / n;
   for (int a = 0; a < d; ++a)
@@ -103,7 +62,7 @@ void set_frame(double n, const double* s, const double* U, int d, int m, float* 
   const double reg = 1e-9 * (1.0 + tr / d);
   for (int i = 0; i < d; ++i) A[(size_t)i * d + i] += reg;
   std::vector<double> w, V;
-  jacobi_eigen(A, d, w, V);
+  if (!eig::sym_eigen(A, d, w, V)) return false;
   std::vector<int> order(d);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w[a] > w[b]; });
@@ -115,19 +74,19 @@ void set_frame(double n, const double* s, const double* U, int d, int m, float* 
   }
   for (int i = 0; i < d; ++i) out[i] = (float)mu[i];
   for (int j = 0; j < m; ++j) {
-    const int col = order[j];
+    const double* vec = &V[(size_t)order[j] * d];
     int amax = 0;
     for (int i = 1; i < d; ++i)
-      if (std::fabs(V[(size_t)i * d + col]) > std::fabs(V[(size_t)amax * d + col])) amax = i;
-    const double sign = V[(size_t)amax * d + col] < 0.0 ? -1.0 : 1.0;
-    const double scale = sign / std::sqrt(lam[j]);
-    for (int i = 0; i < d; ++i) out[d + j * d + i] = (float)(V[(size_t)i * d + col] * scale);
+      if (std::fabs(vec[i]) > std::fabs(vec[amax])) amax = i;
+    const double scale = (vec[amax] < 0.0 ? -1.0 : 1.0) / std::sqrt(lam[j]);
+    for (int i = 0; i < d; ++i) out[d + j * d + i] = (float)(vec[i] * scale);
     if (j == 0 && p0) {
       p0->resize(d);
-      for (int i = 0; i < d; ++i) (*p0)[i] = V[(size_t)i * d + col] * scale;
+      for (int i = 0; i < d; ++i) (*p0)[i] = vec[i] * scale;
     }
     out[d + m * d + j] = (float)(lam[j] / total);
   }
+  return true;
 }
 
 dpmm_status need_learned(dpmm_ctx* ctx) {
@@ -220,6 +179,7 @@ dpmm_status adam_update(dpmm_ctx* ctx, float lr) {
 }
 
 // read back the counts of every cluster and the moments of the given slots
+// (one copy per run of consecutive slots)
 dpmm_status read_set_stats(dpmm_ctx* ctx, const std::vector<int>& slots, std::vector<long long>& cnt,
                            std::vector<double>& mom) {
   const int K = ctx->K, E = ctx->E;
@@ -227,16 +187,22 @@ dpmm_status read_set_stats(dpmm_ctx* ctx, const std::vector<int>& slots, std::ve
   mom.assign(slots.size() * (size_t)E, 0.0);
   DPMM_HIP(ctx, hipMemcpyAsync(cnt.data(), ctx->d_counts, cnt.size() * sizeof(long long), hipMemcpyDeviceToHost,
                                ctx->stream), "copy counts");
-  for (size_t j = 0; j < slots.size(); ++j)
-    DPMM_HIP(ctx, hipMemcpyAsync(mom.data() + j * E, ctx->d_moments + (size_t)slots[j] * E, E * sizeof(double),
+  for (size_t j = 0; j < slots.size();) {
+    size_t r = j + 1;
+    while (r < slots.size() && slots[r] == slots[r - 1] + 1) ++r;
+    DPMM_HIP(ctx, hipMemcpyAsync(mom.data() + j * E, ctx->d_moments + (size_t)slots[j] * E, (r - j) * E * sizeof(double),
                                  hipMemcpyDeviceToHost, ctx->stream), "copy moments");
+    j = r;
+  }
   DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
   return DPMM_OK;
 }
 
-// frame of the union of the given slots' statistics, uploaded to frame row `row`
+// frame of the union of the given slots' statistics, staged in the pinned
+// buffer h_frame and copied to frame row 0 (asynchronously: the caller
+// synchronises before h_frame is written again)
 dpmm_status upload_set_frame(dpmm_ctx* ctx, const std::vector<int>& slots, const std::vector<long long>& cnt,
-                             const std::vector<double>& mom, int row, long long* n_set) {
+                             const std::vector<double>& mom, long long* n_set) {
   const int d = ctx->d, E = ctx->E;
   std::vector<double> sum(E, 0.0);
   long long nn = 0;
@@ -246,25 +212,28 @@ dpmm_status upload_set_frame(dpmm_ctx* ctx, const std::vector<int>& slots, const
   }
   *n_set = nn;
   if (nn == 0) return ctx->fail(DPMM_E_STATE, "the set is empty");
-  std::vector<float> fr(frame_size(ctx));
-  set_frame((double)nn, sum.data(), sum.data() + d, d, ctx->lm, fr.data(), nullptr);
-  // the copy is synchronised by the caller's next read-back before fr dies
-  DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_frames + (size_t)row * fr.size(), fr.data(), fr.size() * sizeof(float),
-                               hipMemcpyHostToDevice, ctx->stream), "copy frame");
-  DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  if (!set_frame((double)nn, sum.data(), sum.data() + d, d, ctx->lm, ctx->h_frame, nullptr))
+    return ctx->fail(DPMM_E_NUMERIC, "the eigen-iteration of the set covariance did not converge");
+  DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_frames, ctx->h_frame, frame_size(ctx) * sizeof(float), hipMemcpyHostToDevice,
+                               ctx->stream), "copy frame");
   return DPMM_OK;
 }
 
-// stable list of the points of clusters k1 (and k2 >= 0) in d_sel; checks
-// that it has n_expect entries
-dpmm_status select_set(dpmm_ctx* ctx, const int32_t* z, int64_t n, int k1, int k2, long long n_expect) {
+// stable list of the points of clusters k1 (and k2 >= 0) in d_sel; the
+// number found lands in the pinned h_back->sel_count after the next
+// synchronisation (check_selected compares it with the statistics)
+
+dpmm_status select_set(dpmm_ctx* ctx, const int32_t* z, int64_t n, int k1, int k2) {
   DPMM_TRY(ensure_sel(ctx, n));
   DPMM_HIP(ctx, launch_select(z, n, k1, k2, nullptr, ctx->K, ctx->d_selcnt, ctx->d_sel, ctx->stream),
            "selection kernels");
-  int got = 0;
-  DPMM_HIP(ctx, hipMemcpyAsync(&got, ctx->d_selcnt + SELECT_BLOCKS, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
-           "copy count");
-  DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  DPMM_HIP(ctx, hipMemcpyAsync(&ctx->h_back->sel_count, ctx->d_selcnt + SELECT_BLOCKS, sizeof(int),
+                               hipMemcpyDeviceToHost, ctx->stream), "copy count");
+  return DPMM_OK;
+}
+
+dpmm_status check_selected(dpmm_ctx* ctx, long long n_expect) {
+  const int got = ctx->h_back->sel_count;
   if (got != n_expect)
     return ctx->fail(DPMM_E_STATE, "the statistics do not match z (" + std::to_string(got) + " labelled points, " +
                                        std::to_string(n_expect) + " counted); recompute them with dpmm_suffstats");
@@ -330,6 +299,8 @@ dpmm_status learned_alloc(dpmm_ctx* ctx) {
   A(&c->d_lsums, 8);
   A(&c->d_setpart, (size_t)SET_STATS_BLOCKS * 2 * (1 + c->E));
   A(&c->d_selcnt, SELECT_BLOCKS + 1);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_frame, frame_size(c) * sizeof(float), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_back, sizeof(LearnedBack), hipHostMallocDefault);
   if (e != hipSuccess) return c->hip(e, "allocate learned-proposal buffers");
   // He-uniform initial weights from Philox (tag TAG_MLPINIT), biases zero
   std::vector<float> p(np, 0.0f);
@@ -396,38 +367,35 @@ dpmm_status learned_move(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, in
     if (cnt[2 * k] + cnt[2 * k + 1] == 0)
       return ctx->fail(DPMM_E_STATE, "cluster " + std::to_string(k) + " is empty (run dpmm_split_merge first)");
   long long nC = 0;
-  DPMM_TRY(upload_set_frame(ctx, slots, cnt, mom, 0, &nC));
-  DPMM_TRY(select_set(ctx, z, n, k1, k2, nC));
+  DPMM_TRY(upload_set_frame(ctx, slots, cnt, mom, &nC));
+  DPMM_TRY(select_set(ctx, z, n, k1, k2));
   unsigned char* side = side_out ? side_out : ctx->d_side;
   DPMM_TRY(ensure_weights(ctx));
   hipStream_t s = ctx->stream;
+  LearnedBack* back = ctx->h_back;
   DPMM_HIP(ctx, launch_zero64(ctx->d_lsums, 8, s), "zero kernel");
   for (long long off = 0; off < nC; off += MLP_CHUNK) {
     const int c = (int)std::min<long long>(MLP_CHUNK, nC - off);
-    DPMM_HIP(ctx, launch_features((const float*)x, ctx->d, ctx->d_sel + off, nullptr, c, ctx->d_frames, ctx->lm,
+    DPMM_HIP(ctx, launch_features((const float*)x, ctx->d, n, ctx->d_sel + off, nullptr, c, ctx->d_frames, ctx->lm,
                                   ctx->F, ctx->Fp, ctx->d_x16, nullptr, 0, nullptr, s), "features kernel");
     DPMM_TRY(forward_chunk(ctx, c, false, ctx->d_o));
-    DPMM_HIP(ctx, launch_proposal(ctx->d_o, ctx->d_sel + off, c, split ? -1 : k1, z, seed, t, side, ctx->d_lsums, s),
-             "proposal kernel");
+    DPMM_HIP(ctx, launch_proposal(ctx->d_o, n, ctx->d_sel + off, c, split ? -1 : k1, z, seed, t, side, ctx->d_lsums,
+                                  s), "proposal kernel");
   }
   std::vector<LogmlItem> items;
-  long long side_cnt[2] = {0, 0};
   if (split) {
     const int slot = 2 * K;
-    DPMM_HIP(ctx, launch_set_stats((const float*)x, ctx->d, ctx->d_sel, (int)nC, side, ctx->d_setpart, slot,
+    DPMM_HIP(ctx, launch_set_stats((const float*)x, ctx->d, n, ctx->d_sel, (int)nC, side, ctx->d_setpart, slot,
                                    ctx->d_counts, ctx->d_moments, s), "partition statistics kernels");
-    DPMM_HIP(ctx, hipMemcpyAsync(side_cnt, ctx->d_counts + slot, 2 * sizeof(long long), hipMemcpyDeviceToHost, s),
-             "copy counts");
+    DPMM_HIP(ctx, hipMemcpyAsync(back->side_cnt, ctx->d_counts + slot, 2 * sizeof(long long), hipMemcpyDeviceToHost,
+                                 s), "copy counts");
     items = {LogmlItem{{slot, -1, -1, -1}}, LogmlItem{{slot + 1, -1, -1, -1}},
              LogmlItem{{2 * k1, 2 * k1 + 1, -1, -1}}};
   } else {
-    side_cnt[0] = cnt[2 * k1] + cnt[2 * k1 + 1];
-    side_cnt[1] = cnt[2 * k2] + cnt[2 * k2 + 1];
     items = {LogmlItem{{2 * k1, 2 * k1 + 1, -1, -1}}, LogmlItem{{2 * k2, 2 * k2 + 1, -1, -1}},
              LogmlItem{{2 * k1, 2 * k1 + 1, 2 * k2, 2 * k2 + 1}}};
   }
-  double sums[4] = {0, 0, 0, 0};
-  DPMM_HIP(ctx, hipMemcpyAsync(sums, ctx->d_lsums, 4 * sizeof(double), hipMemcpyDeviceToHost, s), "copy sums");
+  DPMM_HIP(ctx, hipMemcpyAsync(back->sums, ctx->d_lsums, 4 * sizeof(double), hipMemcpyDeviceToHost, s), "copy sums");
   std::vector<double> lml;
   int flag = 0;
   DPMM_TRY(logml(ctx, items, lml, &flag));  // synchronises
@@ -435,10 +403,13 @@ dpmm_status learned_move(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, in
     DPMM_HIP(ctx, hipMemsetAsync(ctx->d_err, 0, sizeof(int), s), "clear flag");
     return ctx->fail(DPMM_E_NUMERIC, "a float64 Cholesky factorisation met a non-positive pivot");
   }
-  const long long nA = side_cnt[0], nB = side_cnt[1];
+  DPMM_TRY(check_selected(ctx, nC));
+  const long long nA = split ? back->side_cnt[0] : cnt[2 * k1] + cnt[2 * k1 + 1];
+  const long long nB = split ? back->side_cnt[1] : cnt[2 * k2] + cnt[2 * k2 + 1];
   li.n_a = nA;
   li.n_b = nB;
   // q(s): side-A points take log b, side-B points log(1 - b); q(not s) swaps them
+  const double* sums = back->sums;
   li.log_q_part = logaddexp(sums[0] + sums[3], sums[1] + sums[2]);
   if (nA == 0 || nB == 0) {
     li.skipped = 1;
@@ -459,7 +430,7 @@ dpmm_status learned_move(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, in
   if (!(std::log(u_acc) < li.log_h)) return finish();
   li.accepted = 1;
   if (split) {
-    DPMM_HIP(ctx, launch_apply_split(ctx->d_sel, (int)nC, side, K, seed, t, z, zsub, s), "apply kernel");
+    DPMM_HIP(ctx, launch_apply_split(n, ctx->d_sel, (int)nC, side, K, seed, t, z, zsub, s), "apply kernel");
     ctx->age[k1] = 0;
     ctx->age.push_back(0);
     ctx->K = K + 1;
@@ -590,17 +561,20 @@ dpmm_status dpmm_set_features(dpmm_ctx* ctx, const void* x, int64_t n, const int
   std::vector<double> mom;
   DPMM_TRY(read_set_stats(ctx, slots, cnt, mom));
   long long nC = 0;
-  DPMM_TRY(upload_set_frame(ctx, slots, cnt, mom, 0, &nC));
+  DPMM_TRY(upload_set_frame(ctx, slots, cnt, mom, &nC));
   *n_set = nC;
-  if (!feats && !idx) return DPMM_OK;
-  if (capacity < nC) return ctx->fail(DPMM_E_SHAPE, "capacity is below the set size");
-  DPMM_TRY(select_set(ctx, z, n, k1, k2, nC));
-  if (feats)
-    DPMM_HIP(ctx, launch_features((const float*)x, ctx->d, ctx->d_sel, nullptr, (int)nC, ctx->d_frames, ctx->lm,
-                                  ctx->F, ctx->Fp, nullptr, nullptr, 0, feats, ctx->stream), "features kernel");
-  if (idx)
-    DPMM_HIP(ctx, hipMemcpyAsync(idx, ctx->d_sel, (size_t)nC * sizeof(int), hipMemcpyDeviceToDevice, ctx->stream),
-             "copy indices");
+  if (feats || idx) {
+    if (capacity < nC) return ctx->fail(DPMM_E_SHAPE, "capacity is below the set size");
+    DPMM_TRY(select_set(ctx, z, n, k1, k2));
+    if (feats)
+      DPMM_HIP(ctx, launch_features((const float*)x, ctx->d, n, ctx->d_sel, nullptr, (int)nC, ctx->d_frames, ctx->lm,
+                                    ctx->F, ctx->Fp, nullptr, nullptr, 0, feats, ctx->stream), "features kernel");
+    if (idx)
+      DPMM_HIP(ctx, hipMemcpyAsync(idx, ctx->d_sel, (size_t)nC * sizeof(int), hipMemcpyDeviceToDevice, ctx->stream),
+               "copy indices");
+  }
+  DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");  // h_frame / h_back are reused
+  if (feats || idx) DPMM_TRY(check_selected(ctx, nC));
   return DPMM_OK;
 }
 
@@ -629,23 +603,43 @@ dpmm_status dpmm_mlp_train(dpmm_ctx* ctx, const void* x, int64_t n, const int32_
   DPMM_TRY(read_set_stats(ctx, slots, cnt, mom));
   std::vector<float> frames((size_t)K * fs, 0.0f);
   std::vector<int> elig(K, 0), flip(K, 0);
-  int n_elig_clusters = 0;
-  std::vector<double> sum(E), p0;
-  for (int k = 0; k < K; ++k) {
-    const long long nl = cnt[2 * k], nr = cnt[2 * k + 1];
-    if (ctx->age[k] < ctx->cfg.burn_out || nl == 0 || nr == 0) continue;
-    for (int e = 0; e < E; ++e) sum[e] = mom[(size_t)(2 * k) * E + e] + mom[(size_t)(2 * k + 1) * E + e];
-    set_frame((double)(nl + nr), sum.data(), sum.data() + d, d, ctx->lm, frames.data() + (size_t)k * fs, &p0);
-    // orientation: side l must have the larger mean first principal coordinate
-    double pl = 0.0, pr = 0.0;
-    for (int i = 0; i < d; ++i) {
-      pl += p0[i] * mom[(size_t)(2 * k) * E + i] / (double)nl;
-      pr += p0[i] * mom[(size_t)(2 * k + 1) * E + i] / (double)nr;
+  std::vector<int> todo;
+  for (int k = 0; k < K; ++k)
+    if (ctx->age[k] >= ctx->cfg.burn_out && cnt[2 * k] > 0 && cnt[2 * k + 1] > 0) todo.push_back(k);
+  // frames of the eligible clusters, spread over host threads
+  std::vector<char> ok(todo.size(), 1);
+  auto work = [&](size_t j0, size_t step) {
+    std::vector<double> sum(E), p0;
+    for (size_t j = j0; j < todo.size(); j += step) {
+      const int k = todo[j];
+      const long long nl = cnt[2 * k], nr = cnt[2 * k + 1];
+      for (int e = 0; e < E; ++e) sum[e] = mom[(size_t)(2 * k) * E + e] + mom[(size_t)(2 * k + 1) * E + e];
+      if (!set_frame((double)(nl + nr), sum.data(), sum.data() + d, d, ctx->lm, frames.data() + (size_t)k * fs,
+                     &p0)) {
+        ok[j] = 0;
+        continue;
+      }
+      // orientation: side l must have the larger mean first principal coordinate
+      double pl = 0.0, pr = 0.0;
+      for (int i = 0; i < d; ++i) {
+        pl += p0[i] * mom[(size_t)(2 * k) * E + i] / (double)nl;
+        pr += p0[i] * mom[(size_t)(2 * k + 1) * E + i] / (double)nr;
+      }
+      flip[k] = pl < pr ? 1 : 0;
+      elig[k] = 1;
     }
-    flip[k] = pl < pr ? 1 : 0;
-    elig[k] = 1;
-    ++n_elig_clusters;
+  };
+  const size_t nthreads = std::min<size_t>(todo.size(), std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+  if (nthreads <= 1 || (size_t)d * d * todo.size() < 200000) {
+    work(0, 1);
+  } else {
+    std::vector<std::thread> pool;
+    for (size_t i = 0; i < nthreads; ++i) pool.emplace_back(work, i, nthreads);
+    for (auto& th : pool) th.join();
   }
+  for (char o : ok)
+    if (!o) return ctx->fail(DPMM_E_NUMERIC, "the eigen-iteration of a cluster covariance did not converge");
+  const int n_elig_clusters = (int)todo.size();
   if (n_elig_clusters == 0 || steps == 0) return DPMM_OK;
   hipStream_t s = ctx->stream;
   DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_frames, frames.data(), frames.size() * sizeof(float), hipMemcpyHostToDevice, s),
@@ -663,7 +657,7 @@ dpmm_status dpmm_mlp_train(dpmm_ctx* ctx, const void* x, int64_t n, const int32_
   for (int st = 0; st < steps; ++st) {
     DPMM_HIP(ctx, launch_batch_pick(ctx->d_sel, n_sel, batch, ctx->cfg.seed, ctx->train_counter++, z, ctx->d_bidx,
                                     ctx->d_bcl, s), "batch kernel");
-    DPMM_HIP(ctx, launch_features((const float*)x, d, ctx->d_bidx, ctx->d_bcl, batch, ctx->d_frames, ctx->lm, ctx->F,
+    DPMM_HIP(ctx, launch_features((const float*)x, d, n, ctx->d_bidx, ctx->d_bcl, batch, ctx->d_frames, ctx->lm, ctx->F,
                                   ctx->Fp, ctx->d_x16, ctx->d_x16t, MLP_CHUNK, nullptr, s), "features kernel");
     DPMM_HIP(ctx, launch_targets(ctx->d_bidx, ctx->d_bcl, batch, zsub, ctx->d_flip, ctx->d_y, s), "targets kernel");
     DPMM_TRY(zero_grad(ctx));

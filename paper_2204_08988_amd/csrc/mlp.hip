@@ -168,19 +168,22 @@ __global__ void k_refresh_weights(const float* __restrict__ p, int F, int Fp, __
 
 // Set features of the points idx[0..n) under the frame fr = [mu (d),
 // P (m x d), ratios (m)] of cluster cl[q] (cl == nullptr: frame 0):
-// row q = [P (x - mu), ratios, 0 ...] of width Fp.  Outputs (each optional):
-// X16 BF16 [n][Fp], X16t BF16 [Fp][npad], X32 FP32 [n][F].
-__global__ void k_features(const float* __restrict__ x, int d, const int* __restrict__ idx, const int* __restrict__ cl,
-                           int n, const float* __restrict__ frames, int m, int F, int Fp, __bf16* __restrict__ X16,
-                           __bf16* __restrict__ X16t, int npad, float* __restrict__ X32) {
+// row q = [P (x - mu), ratios, 0 ...] of width Fp (all zero when idx[q] does
+// not name one of the npts points).  Outputs (each optional): X16 BF16
+// [n][Fp], X16t BF16 [Fp][npad], X32 FP32 [n][F].
+__global__ void k_features(const float* __restrict__ x, int d, long long npts, const int* __restrict__ idx,
+                           const int* __restrict__ cl, int n, const float* __restrict__ frames, int m, int F, int Fp,
+                           __bf16* __restrict__ X16, __bf16* __restrict__ X16t, int npad, float* __restrict__ X32) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const int fs = d + m * d + m;
   const float* fr = frames + (size_t)(cl ? cl[q] : 0) * fs;
-  const float* xi = x + (size_t)idx[q] * d;
+  const bool valid = (unsigned long long)idx[q] < (unsigned long long)npts;  // rows past a short selection
+  const float* xi = x + (size_t)(valid ? idx[q] : 0) * d;
   for (int f = 0; f < Fp; ++f) {
     float v = 0.0f;
-    if (f < m) {
+    if (!valid) {
+    } else if (f < m) {
       const float* pr = fr + d + f * d;
       for (int c = 0; c < d; ++c) v = fmaf(pr[c], xi[c] - fr[c], v);
     } else if (f < 2 * m) {
@@ -217,13 +220,14 @@ __global__ void k_targets(const int* __restrict__ idx, const int* __restrict__ c
 // u(i, t, TAG_BERN) < b (split) or z_i == merge_k1 (merge).  side[i] = 1 on
 // side A, else 0; sums[0..3] += sum_A log b, sum_A log(1-b), sum_B log b,
 // sum_B log(1-b).
-__global__ __launch_bounds__(BLOCK) void k_proposal(const float* __restrict__ o, const int* __restrict__ idx, int n,
-                                                    int merge_k1, const int* __restrict__ z, uint64_t seed, uint32_t t,
+__global__ __launch_bounds__(BLOCK) void k_proposal(const float* __restrict__ o, long long npts,
+                                                    const int* __restrict__ idx, int n, int merge_k1,
+                                                    const int* __restrict__ z, uint64_t seed, uint32_t t,
                                                     unsigned char* __restrict__ side, double* __restrict__ sums) {
   __shared__ double red[4][BLOCK];
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  if (q < n) {
+  if (q < n && (unsigned long long)idx[q] < (unsigned long long)npts) {
     const int i = idx[q];
     float b = 1.0f / (1.0f + expf(-o[q]));
     b = fminf(fmaxf(b, MLP_CLIP), 1.0f - MLP_CLIP);
@@ -245,11 +249,13 @@ __global__ __launch_bounds__(BLOCK) void k_proposal(const float* __restrict__ o,
 
 // Accepted learned split: side-A points of the set go to cluster k_new, every
 // point of the set gets a fresh sub-label (TAG_LEARNSUB).
-__global__ void k_apply_split(const int* __restrict__ idx, int n, const unsigned char* __restrict__ side, int k_new,
-                              uint64_t seed, uint32_t t, int* __restrict__ z, unsigned char* __restrict__ zsub) {
+__global__ void k_apply_split(long long npts, const int* __restrict__ idx, int n,
+                              const unsigned char* __restrict__ side, int k_new, uint64_t seed, uint32_t t,
+                              int* __restrict__ z, unsigned char* __restrict__ zsub) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const int i = idx[q];
+  if ((unsigned long long)i >= (unsigned long long)npts) return;
   if (side[i]) z[i] = k_new;
   zsub[i] = (unsigned char)(rng_block(seed, t, (uint32_t)i, TAG_LEARNSUB, 0).x & 1u);
 }
@@ -327,8 +333,9 @@ __global__ __launch_bounds__(BLOCK) void k_select_write(SelectPred pred, long lo
 constexpr int SS_ROWS = 64;
 constexpr int SS_EPT = 4;
 
-__global__ __launch_bounds__(BLOCK) void k_set_stats(const float* __restrict__ x, int d, const int* __restrict__ idx,
-                                                     int n, int per, const unsigned char* __restrict__ side,
+__global__ __launch_bounds__(BLOCK) void k_set_stats(const float* __restrict__ x, int d, long long npts,
+                                                     const int* __restrict__ idx, int n, int per,
+                                                     const unsigned char* __restrict__ side,
                                                      double* __restrict__ part) {
   extern __shared__ float xs[];  // [SS_ROWS][d]
   __shared__ unsigned char sd[SS_ROWS];
@@ -363,11 +370,13 @@ __global__ __launch_bounds__(BLOCK) void k_set_stats(const float* __restrict__ x
       for (int id = threadIdx.x; id < SS_ROWS * d; id += BLOCK) {
         const int rr = id / d, c = id % d;
         const int q = r0 + rr;
-        xs[id] = q < end ? x[(size_t)idx[q] * d + c] : 0.0f;
+        const bool ok = q < end && (unsigned long long)idx[q] < (unsigned long long)npts;
+        xs[id] = ok ? x[(size_t)idx[q] * d + c] : 0.0f;
       }
       if (threadIdx.x < SS_ROWS) {
         const int q = r0 + threadIdx.x;
-        sd[threadIdx.x] = q < end ? side[idx[q]] : 2;
+        const bool ok = q < end && (unsigned long long)idx[q] < (unsigned long long)npts;
+        sd[threadIdx.x] = ok ? side[idx[q]] : 2;
       }
       __syncthreads();
       const int rows = end - r0 < SS_ROWS ? end - r0 : SS_ROWS;
@@ -470,10 +479,11 @@ hipError_t launch_refresh_weights(const float* p, int F, int Fp, void* w1t, void
   return hipGetLastError();
 }
 
-hipError_t launch_features(const float* x, int d, const int* idx, const int* cl, int n, const float* frames, int m,
-                           int F, int Fp, void* X16, void* X16t, int npad, float* X32, hipStream_t s) {
+hipError_t launch_features(const float* x, int d, long long npts, const int* idx, const int* cl, int n,
+                           const float* frames, int m, int F, int Fp, void* X16, void* X16t, int npad, float* X32,
+                           hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_features, dim3(cdiv(n, BLOCK)), dim3(BLOCK), 0, s, x, d, idx, cl, n, frames, m, F, Fp,
+  hipLaunchKernelGGL(k_features, dim3(cdiv(n, BLOCK)), dim3(BLOCK), 0, s, x, d, npts, idx, cl, n, frames, m, F, Fp,
                      (__bf16*)X16, (__bf16*)X16t, npad, X32);
   return hipGetLastError();
 }
@@ -492,18 +502,19 @@ hipError_t launch_targets(const int* idx, const int* cl, int n, const unsigned c
   return hipGetLastError();
 }
 
-hipError_t launch_proposal(const float* o, const int* idx, int n, int merge_k1, const int* z, uint64_t seed,
-                           uint32_t t, unsigned char* side, double* sums, hipStream_t s) {
+hipError_t launch_proposal(const float* o, long long npts, const int* idx, int n, int merge_k1, const int* z,
+                           uint64_t seed, uint32_t t, unsigned char* side, double* sums, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_proposal, dim3(cdiv(n, BLOCK)), dim3(BLOCK), 0, s, o, idx, n, merge_k1, z, seed, t, side,
+  hipLaunchKernelGGL(k_proposal, dim3(cdiv(n, BLOCK)), dim3(BLOCK), 0, s, o, npts, idx, n, merge_k1, z, seed, t, side,
                      sums);
   return hipGetLastError();
 }
 
-hipError_t launch_apply_split(const int* idx, int n, const unsigned char* side, int k_new, uint64_t seed, uint32_t t,
-                              int* z, unsigned char* zsub, hipStream_t s) {
+hipError_t launch_apply_split(long long npts, const int* idx, int n, const unsigned char* side, int k_new,
+                              uint64_t seed, uint32_t t, int* z, unsigned char* zsub, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_apply_split, dim3(cdiv(n, BLOCK)), dim3(BLOCK), 0, s, idx, n, side, k_new, seed, t, z, zsub);
+  hipLaunchKernelGGL(k_apply_split, dim3(cdiv(n, BLOCK)), dim3(BLOCK), 0, s, npts, idx, n, side, k_new, seed, t, z,
+                     zsub);
   return hipGetLastError();
 }
 
@@ -522,14 +533,14 @@ hipError_t launch_select(const int* z, long long n, int k1, int k2, const int* e
   return hipGetLastError();
 }
 
-hipError_t launch_set_stats(const float* x, int d, const int* idx, int n, const unsigned char* side, double* part,
-                            int slot, long long* counts, double* moments, hipStream_t s) {
+hipError_t launch_set_stats(const float* x, int d, long long npts, const int* idx, int n, const unsigned char* side,
+                            double* part, int slot, long long* counts, double* moments, hipStream_t s) {
   int G = cdiv(n, 1024);
   if (G < 1) G = 1;
   if (G > SET_STATS_BLOCKS) G = SET_STATS_BLOCKS;
   const int per = n > 0 ? cdiv(n, G) : 0;
-  hipLaunchKernelGGL(k_set_stats, dim3(G), dim3(BLOCK), (size_t)SS_ROWS * d * sizeof(float), s, x, d, idx, n, per,
-                     side, part);
+  hipLaunchKernelGGL(k_set_stats, dim3(G), dim3(BLOCK), (size_t)SS_ROWS * d * sizeof(float), s, x, d, npts, idx, n,
+                     per, side, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int E1 = 1 + d + d * (d + 1) / 2;

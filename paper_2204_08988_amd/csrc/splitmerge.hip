@@ -4,6 +4,8 @@
 //   k_logml_gauss  log marginal likelihood of the union of up to four
 //                  sub-cluster segments under the NIW prior, one workgroup
 //                  per item (float64 Cholesky of Psi_n in LDS for log|Psi_n|);
+//   k_logml_gauss_wave  the same for d <= 64, one wave per item with the
+//                  matrix in registers (lane i holds row i);
 //   k_logml_mult   the Dirichlet-multinomial log marginal likelihood;
 //   k_relabel      applies a split/merge/compaction move table to (z, zsub)
 //                  in one O(N) pass;
@@ -93,6 +95,88 @@ __global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, 
   }
 }
 
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// One wave per item, D >= d rows padded with an identity block (whose
+// pivots are 1 and add nothing to log|Psi_n|).  Lane i builds row i of Psi_n
+// (entries k <= i) and the right-looking Cholesky broadcasts column j with
+// v_readlane: no LDS and no barrier.  Entries above the diagonal start at 0
+// and stay 0 under the unmasked updates.
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const LogmlItem* __restrict__ items, int d,
+                                                            NiwPriorDev prior, double logdet_psi,
+                                                            const long long* __restrict__ counts,
+                                                            const double* __restrict__ moments,
+                                                            double* __restrict__ out, int* __restrict__ err) {
+  const int lane = threadIdx.x & 63;
+  const int it = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+  if (it >= n_items) return;
+  const int E = d + d * (d + 1) / 2;
+  const LogmlItem item = items[it];
+  double n = 0.0;
+  for (int q = 0; q < 4; ++q)
+    if (item.seg[q] >= 0) n += (double)counts[item.seg[q]];
+  if (n == 0.0) {
+    if (lane == 0) out[it] = 0.0;
+    return;
+  }
+  const double kn = prior.kappa + n, nun = prior.nu + n, cm = prior.kappa * n / kn;
+  const bool live = lane < d;
+  double si = 0.0;
+  for (int q = 0; q < 4; ++q)
+    if (item.seg[q] >= 0 && live) si += moments[(size_t)item.seg[q] * E + lane];
+  const double xi = si / n;
+  const double dmi = live ? xi - prior.m[lane] : 0.0;
+  double r[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double xk = readlane_d(xi, k), dmk = readlane_d(dmi, k);
+    double v = k == lane ? 1.0 : 0.0;
+    if (k < d && live && k <= lane) {
+      const int tk = d + k * d - (k * (k - 1)) / 2 + (lane - k);  // packed (k, lane), k <= lane
+      double S = 0.0;
+      for (int q = 0; q < 4; ++q)
+        if (item.seg[q] >= 0) S += moments[(size_t)item.seg[q] * E + tk];
+      v = prior.psi[lane * d + k] + (S - n * xi * xk) + cm * dmi * dmk;
+    }
+    r[k] = v;
+  }
+  bool ok = true;
+  double mydiag = 1.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double djj = readlane_d(r[j], j);
+    if (!(djj > 0.0) || !isfinite(djj)) {
+      ok = false;
+      djj = 1.0;
+    }
+    const double ljj = sqrt(djj), inv = 1.0 / ljj;
+    if (lane == j) mydiag = ljj;
+    r[j] = lane == j ? ljj : r[j] * inv;
+#pragma unroll
+    for (int k = j + 1; k < D; ++k) r[k] = fma(-r[j], readlane_d(r[j], k), r[k]);
+  }
+  // log|Psi_n| = 2 sum log L_ii; log Gamma_d(nu_n / 2) - log Gamma_d(nu / 2)
+  const double ld = 2.0 * wave_sum(live ? log(mydiag) : 0.0);
+  const double lg = wave_sum(live ? lgamma(0.5 * nun - 0.5 * lane) - lgamma(0.5 * prior.nu - 0.5 * lane) : 0.0);
+  if (lane == 0) {
+    if (!ok) atomicOr(err, 4);
+    out[it] = -0.5 * n * d * 1.1447298858494002 + lg + 0.5 * prior.nu * logdet_psi - 0.5 * nun * ld +
+              0.5 * d * (log(prior.kappa) - log(kn));
+  }
+}
+
 __global__ void k_logml_mult(int n_items, const LogmlItem* __restrict__ items, int V,
                              const double* __restrict__ beta, double beta_sum, double lgamma_beta_sum,
                              const double* __restrict__ lgamma_beta, const long long* __restrict__ counts,
@@ -167,6 +251,22 @@ hipError_t launch_logml_gauss(int n_items, const LogmlItem* items, int d, NiwPri
                               const long long* counts, const double* moments, double* scratch, double* out,
                               int* err, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
+  const dim3 wg((n_items + BLOCK / 64 - 1) / (BLOCK / 64));
+  if (d <= 16) {
+    hipLaunchKernelGGL(k_logml_gauss_wave<16>, wg, dim3(BLOCK), 0, s, n_items, items, d, prior, logdet_psi, counts,
+                       moments, out, err);
+    return hipGetLastError();
+  }
+  if (d <= 32) {
+    hipLaunchKernelGGL(k_logml_gauss_wave<32>, wg, dim3(BLOCK), 0, s, n_items, items, d, prior, logdet_psi, counts,
+                       moments, out, err);
+    return hipGetLastError();
+  }
+  if (d <= 64) {
+    hipLaunchKernelGGL(k_logml_gauss_wave<64>, wg, dim3(BLOCK), 0, s, n_items, items, d, prior, logdet_psi, counts,
+                       moments, out, err);
+    return hipGetLastError();
+  }
   const size_t lds = d <= LOGML_LDS_MAX_D ? (size_t)d * d * sizeof(double) : 0;
   hipLaunchKernelGGL(k_logml_gauss, dim3(n_items), dim3(BLOCK), lds, s, n_items, items, d, prior, logdet_psi,
                      counts, moments, scratch, out, err);

@@ -183,7 +183,7 @@ def _move_case(d, m, seed):
     return torch, x, z, model, S, theta
 
 
-@pytest.mark.parametrize("d,m", [(2, 2), (8, 3)])
+@pytest.mark.parametrize("d,m", [(2, 2), (8, 3), (40, 4)])
 def test_learned_move_pieces_match_oracle_given_gpu_sides(d, m):
     torch, x, z, model, S, theta = _move_case(d, m, 60 + d)
     xd = x.astype(np.float64)
@@ -213,8 +213,16 @@ def test_learned_move_pieces_match_oracle_given_gpu_sides(d, m):
         side = side_t.cpu().numpy()
         assert np.all(side[np.setdiff1d(np.arange(z.size), C)] == 7)
         sa = side[C] == 1
-        # the GPU's probabilities, from the same features and network
-        feats, idx = S.set_features(xt, zt, info["k1"], info["k2"])
+        zn = zt.cpu().numpy()
+        zs_after = zst.cpu().numpy()
+        K_after = S.K
+        assert K_after == K + (1 if split else -1) * info["accepted"]
+        # the GPU's probabilities, from the same features and network, on the
+        # state before the move
+        z0 = torch.tensor(z.astype(np.int32)).cuda()
+        S.set_state(K)
+        S.suffstats(xt, z0, torch.zeros(z.size, dtype=torch.uint8).cuda())
+        feats, idx = S.set_features(xt, z0, info["k1"], info["k2"])
         assert np.array_equal(idx.cpu().numpy(), C)
         o = S.mlp_forward(feats).cpu().numpy().astype(np.float64)
         b = np.clip(1.0 / (1.0 + np.exp(-o)), learned.CLIP, 1 - learned.CLIP)
@@ -250,23 +258,19 @@ def test_learned_move_pieces_match_oracle_given_gpu_sides(d, m):
         # the oracle's Hastings ratio for the same sides, given the GPU's
         # probabilities, is the same number
         assert info["accepted"] == int(np.log(u_acc) < info["log_h"])
-        zn = zt.cpu().numpy()
         if info["accepted"]:
             if split:
                 exp = z.copy()
                 exp[A] = K
                 assert np.array_equal(zn, exp)
-                assert S.K == K + 1
                 fresh = rng.block(model.seed, t, C.astype(np.uint64), learned.TAG_LEARNSUB, 0)[0] & np.uint32(1)
-                assert np.array_equal(zst.cpu().numpy()[C], fresh.astype(np.uint8))
+                assert np.array_equal(zs_after[C], fresh.astype(np.uint8))
             else:
                 exp = z.copy()
                 exp[z == info["k2"]] = info["k1"]
                 exp[exp > info["k2"]] -= 1
                 assert np.array_equal(zn, exp)
-                zs_n = zst.cpu().numpy()
-                assert np.all(zs_n[z == info["k1"]] == 0) and np.all(zs_n[z == info["k2"]] == 1)
-                assert S.K == K - 1
+                assert np.all(zs_after[z == info["k1"]] == 0) and np.all(zs_after[z == info["k2"]] == 1)
             z = zn.astype(np.int64)
         else:
             assert np.array_equal(zn, z)

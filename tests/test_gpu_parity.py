@@ -156,6 +156,34 @@ def test_gauss_split_merge(merge_form):
     S.close()
 
 
+@pytest.mark.parametrize("d", [3, 16, 17, 32, 33, 64, 65, 100])
+def test_gauss_log_marginals_across_dimensions(d):
+    """Cluster log marginal likelihoods (through the log posterior that the
+    split/merge phase reports when no cluster is old enough to move) against
+    the oracle, on both sides of every register-tile boundary of the
+    marginal-likelihood kernels."""
+    torch = _torch()
+    g = np.random.Generator(np.random.PCG64(70 + d))
+    K, n = 3, 400
+    z = np.repeat(np.arange(K), n // K + 1)[:n]
+    x = (g.standard_normal((n, d)) * np.linspace(0.5, 2.0, d) + 3.0 * z[:, None]).astype(np.float32)
+    zs = g.integers(0, 2, n)
+    psi = np.eye(d) * 0.5 + 0.1
+    model = sampler.Model("gaussian", 2.0, niw.NIWPrior(0.7, np.full(d, 0.3), d + 4.0, psi), seed=1, burn_out=5)
+    ref = sampler.suffstats(model, x.astype(np.float64), z, zs, K)
+    from paper_2204_08988_amd.sampler import Sampler
+    S = Sampler("gaussian", d, 8, 2.0, 1, kappa=0.7, nu=d + 4.0, m=np.full(d, 0.3), psi=psi, burn_out=5)
+    S.set_state(K, [0] * K)
+    S.set_stats(pu.stats_array(ref, "gaussian"))
+    xt = torch.from_numpy(x).cuda()
+    info = S.split_merge(xt, 1, torch.from_numpy(z.astype(np.int32)).cuda(),
+                         torch.from_numpy(zs.astype(np.uint8)).cuda())
+    assert info["K"] == K and info["splits"] == 0 and info["merges"] == 0
+    assert np.isclose(info["logpost"], sampler.log_posterior(model, ref), rtol=1e-10), (info["logpost"],
+                                                                                         sampler.log_posterior(model, ref))
+    S.close()
+
+
 def test_gauss_chain_matches_oracle_then_converges():
     torch = _torch()
     from paper_2204_08988_amd import datagen
