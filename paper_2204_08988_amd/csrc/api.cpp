@@ -111,31 +111,67 @@ dpmm_status launch_stats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t*
   return DPMM_OK;
 }
 
-// log marginal likelihoods of a list of segment unions (device), read back.
-// *flag_out (optional) receives the device error flag after the launches.
+// capacity of the item lists and their pinned staging (synchronises when it grows)
+dpmm_status ensure_items(dpmm_ctx* ctx, size_t count) {
+  if (count <= ctx->items_cap) return DPMM_OK;
+  const size_t cap = std::max(count, 2 * ctx->items_cap);
+  if (ctx->items_cap) DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  hipFree(ctx->d_items);
+  hipFree(ctx->d_logml);
+  hipFree(ctx->d_mflag);
+  hipHostFree(ctx->h_items);
+  hipHostFree(ctx->h_lml);
+  hipHostFree(ctx->h_mflag);
+  ctx->d_items = nullptr;
+  ctx->d_logml = nullptr;
+  ctx->d_mflag = nullptr;
+  ctx->h_items = nullptr;
+  ctx->h_lml = nullptr;
+  ctx->h_mflag = nullptr;
+  ctx->items_cap = 0;
+  DPMM_HIP(ctx, hipMalloc(&ctx->d_items, cap * sizeof(LogmlItem)), "allocate items");
+  DPMM_HIP(ctx, hipMalloc(&ctx->d_logml, cap * sizeof(double)), "allocate items");
+  DPMM_HIP(ctx, hipMalloc(&ctx->d_mflag, cap), "allocate items");
+  DPMM_HIP(ctx, hipHostMalloc((void**)&ctx->h_items, cap * sizeof(LogmlItem), hipHostMallocDefault), "pin items");
+  DPMM_HIP(ctx, hipHostMalloc((void**)&ctx->h_lml, cap * sizeof(double), hipHostMallocDefault), "pin items");
+  DPMM_HIP(ctx, hipHostMalloc((void**)&ctx->h_mflag, cap, hipHostMallocDefault), "pin items");
+  ctx->items_cap = cap;
+  return DPMM_OK;
+}
+
+// enqueue the log marginal likelihoods of items (copied through pinned staging)
+dpmm_status logml_launch(dpmm_ctx* ctx, const LogmlItem* items, size_t count) {
+  DPMM_TRY(ensure_items(ctx, count));
+  if (count == 0) return DPMM_OK;
+  std::memcpy(ctx->h_items, items, count * sizeof(LogmlItem));
+  DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_items, ctx->h_items, count * sizeof(LogmlItem), hipMemcpyHostToDevice,
+                               ctx->stream), "copy items");
+  hipError_t e;
+  if (ctx->gaussian())
+    e = launch_logml_gauss((int)count, ctx->d_items, ctx->d, prior_dev(ctx), ctx->logdet_psi, ctx->d_counts,
+                           ctx->d_moments, ctx->d_scratch, ctx->d_logml, ctx->d_err, ctx->stream);
+  else
+    e = launch_logml_mult((int)count, ctx->d_items, ctx->d, ctx->d_beta, ctx->beta_sum, ctx->lgamma_beta_sum,
+                          ctx->d_lgamma_beta, ctx->d_counts, ctx->d_sums, ctx->d_logml, ctx->stream);
+  DPMM_HIP(ctx, e, "log marginal likelihood kernel");
+  return DPMM_OK;
+}
+
+// log marginal likelihoods of a list of segment unions (device), read back
+// with one synchronisation.  *flag_out (optional) receives the device error
+// flag after the launch.
 dpmm_status logml(dpmm_ctx* ctx, const std::vector<LogmlItem>& items, std::vector<double>& out, int* flag_out) {
   out.assign(items.size(), 0.0);
-  size_t done = 0;
-  while (done < items.size()) {
-    const int nb = (int)std::min<size_t>(items.size() - done, (size_t)ctx->items_cap);
-    DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_items, items.data() + done, nb * sizeof(LogmlItem), hipMemcpyHostToDevice,
-                                 ctx->stream), "copy items");
-    hipError_t e;
-    if (ctx->gaussian())
-      e = launch_logml_gauss(nb, ctx->d_items, ctx->d, prior_dev(ctx), ctx->logdet_psi, ctx->d_counts,
-                             ctx->d_moments, ctx->d_scratch, ctx->d_logml, ctx->d_err, ctx->stream);
-    else
-      e = launch_logml_mult(nb, ctx->d_items, ctx->d, ctx->d_beta, ctx->beta_sum, ctx->lgamma_beta_sum,
-                            ctx->d_lgamma_beta, ctx->d_counts, ctx->d_sums, ctx->d_logml, ctx->stream);
-    DPMM_HIP(ctx, e, "log marginal likelihood kernel");
-    DPMM_HIP(ctx, hipMemcpyAsync(out.data() + done, ctx->d_logml, nb * sizeof(double), hipMemcpyDeviceToHost,
+  DPMM_TRY(logml_launch(ctx, items.data(), items.size()));
+  if (!items.empty())
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->h_lml, ctx->d_logml, items.size() * sizeof(double), hipMemcpyDeviceToHost,
                                  ctx->stream), "copy log marginals");
-    if (flag_out && done + nb == items.size())
-      DPMM_HIP(ctx, hipMemcpyAsync(flag_out, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
-               "copy flag");
-    DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
-    done += nb;
-  }
+  if (flag_out)
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
+             "copy flag");
+  DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  std::memcpy(out.data(), ctx->h_lml, items.size() * sizeof(double));
+  if (flag_out) *flag_out = *ctx->h_flag;
   return DPMM_OK;
 }
 
@@ -294,16 +330,13 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
   ok = ok && chk(c->alloc(&c->d_packed, 3 * (size_t)km * c->stride));
   ok = ok && chk(c->alloc(&c->d_err, 1));
   ok = ok && chk(c->alloc(&c->d_table, 4 * (size_t)km));
-  c->items_cap = std::max(3 * km, 256);
-  ok = ok && chk(c->alloc(&c->d_items, (size_t)c->items_cap));
-  ok = ok && chk(c->alloc(&c->d_logml, (size_t)c->items_cap));
   if (c->gaussian()) {
     ok = ok && chk(c->alloc(&c->d_m, (size_t)d));
     ok = ok && chk(c->alloc(&c->d_psi, (size_t)d * d));
     ok = ok && chk(c->alloc(&c->d_moments, 2 * (size_t)km * c->E));
     ok = ok && chk(c->alloc(&c->d_mu, 3 * (size_t)km * d));
     ok = ok && chk(c->alloc(&c->d_sigma, 3 * (size_t)km * d * d));
-    c->scratch_slots = c->items_cap;
+    c->scratch_slots = std::max(3 * km, 256);
     ok = ok && chk(c->alloc(&c->d_scratch, (size_t)c->scratch_slots * NIW_SCRATCH(d)));
     if (cfg->precision != DPMM_FP32) {
       ok = ok && chk(c->alloc(&c->d_whi, (size_t)km * d * d));
@@ -321,15 +354,14 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     ok = ok && chk(c->alloc(&c->d_sums, 2 * (size_t)km * d));
     ok = ok && chk(c->alloc(&c->d_log_theta, 3 * (size_t)km * d));
   }
+  // every failure below releases what was allocated through dpmm_destroy
   if (!ok) {
-    for (auto& b : c->bufs) hipFree(b.p);
+    dpmm_destroy(ctx.release());
     return bad(DPMM_E_OOM, "device allocation failed");
   }
   if (cfg->learned > 0 && learned_alloc(c) != DPMM_OK) {
-    for (auto& b : c->bufs) hipFree(b.p);
-    if (c->h_frame) hipHostFree(c->h_frame);
-    if (c->h_back) hipHostFree(c->h_back);
     g_create_error = c->err;
+    dpmm_destroy(ctx.release());
     return DPMM_E_OOM;
   }
   hipError_t e = hipSuccess;
@@ -342,11 +374,14 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
       e = hipMemcpy(c->d_lgamma_beta, c->lgamma_beta.data(), d * sizeof(double), hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = hipMemset(c->d_err, 0, sizeof(int));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_cnt, 2 * (size_t)km * sizeof(long long), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_flag, sizeof(int), hipHostMallocDefault);
+  if (e == hipSuccess && ensure_items(c, (size_t)std::max(3 * km, 256)) != DPMM_OK) e = hipErrorOutOfMemory;
   if (e == hipSuccess) e = hipMemset(c->d_packed, 0, 3 * (size_t)km * c->stride * sizeof(float));
   for (int i = 0; i < 7 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev[i]);
   if (e != hipSuccess) {
-    for (auto& b : c->bufs) hipFree(b.p);
     g_create_error = std::string("device setup failed: ") + hipGetErrorString(e);
+    dpmm_destroy(ctx.release());
     return DPMM_E_DEVICE;
   }
   *out = ctx.release();
@@ -363,6 +398,14 @@ void dpmm_destroy(dpmm_ctx* ctx) {
   if (ctx->d_side) hipFree(ctx->d_side);
   if (ctx->h_frame) hipHostFree(ctx->h_frame);
   if (ctx->h_back) hipHostFree(ctx->h_back);
+  hipFree(ctx->d_items);
+  hipFree(ctx->d_logml);
+  hipFree(ctx->d_mflag);
+  hipHostFree(ctx->h_items);
+  hipHostFree(ctx->h_lml);
+  hipHostFree(ctx->h_mflag);
+  hipHostFree(ctx->h_cnt);
+  hipHostFree(ctx->h_flag);
   for (auto& e : ctx->ev)
     if (e) hipEventDestroy(e);
   delete ctx;
@@ -661,6 +704,7 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t
   std::vector<long long> cnt;
   std::vector<double> lml;
   std::vector<std::pair<int, int>> pairs;
+  std::vector<unsigned char> merge_ok;
   // Marginal likelihoods of every cluster, sub-cluster and eligible pair are
   // computed in one launch and read back with the counts and the error flag:
   // one synchronisation per iteration unless a cluster became empty.
@@ -681,11 +725,27 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t
           items.push_back(LogmlItem{{2 * k1, 2 * k1 + 1, 2 * k2, 2 * k2 + 1}});
         }
     }
-    cnt.assign(2 * (size_t)K, 0);
-    int flag = 0;
-    DPMM_HIP(ctx, hipMemcpyAsync(cnt.data(), ctx->d_counts, cnt.size() * sizeof(long long), hipMemcpyDeviceToHost,
+    // one launch for every marginal, the merge tests on the device, one
+    // read-back: counts, the 3K cluster / sub-cluster marginals, the pair
+    // decisions and the error flag
+    DPMM_TRY(logml_launch(ctx, items.data(), items.size()));
+    DPMM_HIP(ctx, launch_merge_decide((int)pairs.size(), ctx->d_items + 3 * K, ctx->d_counts, ctx->d_logml,
+                                      ctx->d_logml + 3 * K, alpha, ctx->cfg.merge_form == DPMM_MERGE_PAPER, seed, t,
+                                      ctx->d_mflag, ctx->stream), "merge test kernel");
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->h_cnt, ctx->d_counts, 2 * (size_t)K * sizeof(long long), hipMemcpyDeviceToHost,
                                  ctx->stream), "copy counts");
-    DPMM_TRY(logml(ctx, items, lml, &flag));  // synchronises
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->h_lml, ctx->d_logml, 3 * (size_t)K * sizeof(double), hipMemcpyDeviceToHost,
+                                 ctx->stream), "copy log marginals");
+    if (!pairs.empty())
+      DPMM_HIP(ctx, hipMemcpyAsync(ctx->h_mflag, ctx->d_mflag, pairs.size(), hipMemcpyDeviceToHost, ctx->stream),
+               "copy merge tests");
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
+             "copy flag");
+    DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    cnt.assign(ctx->h_cnt, ctx->h_cnt + 2 * (size_t)K);
+    lml.assign(ctx->h_lml, ctx->h_lml + 3 * (size_t)K);
+    merge_ok.assign(ctx->h_mflag, ctx->h_mflag + pairs.size());
+    const int flag = *ctx->h_flag;
     if (flag) {
       DPMM_HIP(ctx, hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream), "clear flag");
       return ctx->fail(DPMM_E_NUMERIC, "a float64 Cholesky factorisation met a non-positive pivot (flag " +
@@ -739,15 +799,7 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t
   for (size_t p = 0; p < pairs.size(); ++p) {
     const int k1 = pairs[p].first, k2 = pairs[p].second;
     if (touched[k1] || touched[k2]) continue;
-    const double n1 = (double)(cnt[2 * k1] + cnt[2 * k1 + 1]);
-    const double n2 = (double)(cnt[2 * k2] + cnt[2 * k2 + 1]);
-    double lh = std::lgamma(n1 + n2) - std::log(alpha) - std::lgamma(n1) - std::lgamma(n2) + lml[3 * K + p] -
-                lml_cluster[k1] - lml_cluster[k2];
-    if (ctx->cfg.merge_form == DPMM_MERGE_PAPER)
-      lh += std::lgamma(alpha) - std::lgamma(alpha + n1 + n2) + std::lgamma(0.5 * alpha + n1) +
-            std::lgamma(0.5 * alpha + n2) - 2.0 * std::lgamma(0.5 * alpha);
-    const double u = uniform_d(rng_block(seed, t, merge_entity(k1, k2), TAG_MERGE, 0).x);
-    if (std::log(u) < lh) {
+    if (merge_ok[p]) {  // the test of k_merge_decide
       touched[k1] = touched[k2] = 1;
       merged_into[k2] = k1;
       is_merge_target[k1] = 1;

@@ -52,9 +52,17 @@ struct dpmm_ctx {
   double* d_scratch = nullptr;  // NIW_SCRATCH(d) per workgroup slot
   int scratch_slots = 0;
   int* d_err = nullptr;
+  // marginal-likelihood items: device lists and pinned staging, grown by
+  // ensure_items (outside bufs)
   LogmlItem* d_items = nullptr;
   double* d_logml = nullptr;
-  int items_cap = 0;
+  unsigned char* d_mflag = nullptr;
+  LogmlItem* h_items = nullptr;
+  double* h_lml = nullptr;
+  unsigned char* h_mflag = nullptr;
+  size_t items_cap = 0;
+  long long* h_cnt = nullptr;  // pinned [2 k_max]
+  int* h_flag = nullptr;       // pinned
   RelabelEntry* d_table = nullptr;
   // cluster-sorted path (Gaussian, d >= dpmm::SORTED_MIN_D)
   int *d_hist = nullptr, *d_offs = nullptr, *d_tot = nullptr, *d_perm = nullptr;
@@ -128,6 +136,7 @@ dpmm_status launch_stats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t*
 dpmm_status logml(dpmm_ctx* ctx, const std::vector<LogmlItem>& items, std::vector<double>& out,
                   int* flag_out = nullptr);
 dpmm_status check_device_error(dpmm_ctx* ctx);
+dpmm_status ensure_items(dpmm_ctx* ctx, size_t count);
 dpmm_status apply_relabel(dpmm_ctx* ctx, const std::vector<RelabelEntry>& table, int64_t n, uint32_t t, int32_t* z,
                           uint8_t* zsub);
 // learned.cpp: buffers of the learned proposal (called by dpmm_create)

@@ -112,6 +112,10 @@ struct LogmlItem {
 hipError_t launch_logml_gauss(int n_items, const LogmlItem* items, int d, NiwPriorDev prior,
                               double logdet_psi, const long long* counts, const double* moments,
                               double* scratch, double* out, int* err, hipStream_t s);
+// accept[p] = merge test of pair item pairs[p] (see k_merge_decide)
+hipError_t launch_merge_decide(int n_pairs, const LogmlItem* pairs, const long long* counts, const double* lml_cluster,
+                               const double* lml_pair, double alpha, bool paper_form, uint64_t seed, uint32_t t,
+                               unsigned char* accept, hipStream_t s);
 hipError_t launch_logml_mult(int n_items, const LogmlItem* items, int V, const double* beta,
                              double beta_sum, double lgamma_beta_sum, const double* lgamma_beta,
                              const long long* counts, const long long* sums, double* out, hipStream_t s);

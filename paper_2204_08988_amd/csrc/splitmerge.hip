@@ -177,6 +177,30 @@ __global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const L
   }
 }
 
+// Merge test of every listed pair (Sec. 4.1 eq. sample_merges; with
+// paper_form = 0 the reciprocal of the split ratio of Sec. 2.3): pair p is the
+// item pairs[p] = (2 k1, 2 k1 + 1, 2 k2, 2 k2 + 1) with union marginal
+// lml_pair[p]; lml_cluster[3 k] is cluster k's marginal.  accept[p] = 1 when
+// log u < log H_merge with u the merge uniform of (k1, k2).
+__global__ void k_merge_decide(int n_pairs, const LogmlItem* __restrict__ pairs, const long long* __restrict__ counts,
+                               const double* __restrict__ lml_cluster, const double* __restrict__ lml_pair,
+                               double alpha, int paper_form, uint64_t seed, uint32_t t,
+                               unsigned char* __restrict__ accept) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  const LogmlItem it = pairs[p];
+  const int k1 = it.seg[0] >> 1, k2 = it.seg[2] >> 1;
+  const double n1 = (double)(counts[2 * k1] + counts[2 * k1 + 1]);
+  const double n2 = (double)(counts[2 * k2] + counts[2 * k2 + 1]);
+  double lh = lgamma(n1 + n2) - log(alpha) - lgamma(n1) - lgamma(n2) + lml_pair[p] - lml_cluster[3 * k1] -
+              lml_cluster[3 * k2];
+  if (paper_form)
+    lh += lgamma(alpha) - lgamma(alpha + n1 + n2) + lgamma(0.5 * alpha + n1) + lgamma(0.5 * alpha + n2) -
+          2.0 * lgamma(0.5 * alpha);
+  const double u = uniform_d(rng_block(seed, t, merge_entity(k1, k2), TAG_MERGE, 0).x);
+  accept[p] = log(u) < lh ? 1 : 0;
+}
+
 __global__ void k_logml_mult(int n_items, const LogmlItem* __restrict__ items, int V,
                              const double* __restrict__ beta, double beta_sum, double lgamma_beta_sum,
                              const double* __restrict__ lgamma_beta, const long long* __restrict__ counts,
@@ -279,6 +303,15 @@ hipError_t launch_logml_mult(int n_items, const LogmlItem* items, int V, const d
   if (n_items == 0) return hipSuccess;
   hipLaunchKernelGGL(k_logml_mult, dim3(n_items), dim3(BLOCK), 0, s, n_items, items, V, beta, beta_sum,
                      lgamma_beta_sum, lgamma_beta, counts, sums, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_decide(int n_pairs, const LogmlItem* pairs, const long long* counts, const double* lml_cluster,
+                               const double* lml_pair, double alpha, bool paper_form, uint64_t seed, uint32_t t,
+                               unsigned char* accept, hipStream_t s) {
+  if (n_pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_merge_decide, dim3((n_pairs + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, n_pairs, pairs, counts,
+                     lml_cluster, lml_pair, alpha, paper_form ? 1 : 0, seed, t, accept);
   return hipGetLastError();
 }
 
