@@ -122,6 +122,76 @@ def run_form(torch, x, n, d, m, precision, steps, warmup, k_true):
     return S, z, zs, res
 
 
+AB_WORKLOAD = "gauss_d64"
+
+
+def run_chain(torch, x, n, d, m, iters, learned, train_every, train_steps, batch, lr):
+    """One chain from K = 1 with the BF16 form: per iteration (t, seconds since
+    the start, K, log posterior, learned move accepted).  Training time of the
+    learned chain is inside the clock."""
+    from paper_2204_08988_amd.sampler import Sampler
+    S = Sampler("gaussian", d, 512, ALPHA, SEED, kappa=1.0, nu=d + 3.0, m=m, psi=np.eye(d), burn_out=5,
+                precision="bf16", learned=learned)
+    z, zs = S.init_labels(n)
+    torch.cuda.synchronize()
+    rec, tries, acc, t_train = [], 0, 0, 0.0
+    t0 = time.perf_counter()
+    for t in range(1, iters + 1):
+        info = S.step(x, t, z, zs)
+        if learned:
+            tries += 1
+            acc += info["learned_accepted"]
+            if t % train_every == 0:
+                a = time.perf_counter()
+                S.mlp_train(x, z, zs, train_steps, batch, lr)
+                t_train += time.perf_counter() - a
+        rec.append((t, time.perf_counter() - t0, info["K"], info["logpost"]))
+    return S, z, rec, {"learned_moves": tries, "learned_accepted": acc, "train_s": t_train}
+
+
+def learned_ab(args):
+    """Time to the plain chain's log-posterior plateau, learned vs plain."""
+    import torch
+    from paper_2204_08988_amd import datagen
+    from oracle import nmi as nmi_mod
+    spec = datagen.WORKLOADS[AB_WORKLOAD]
+    x_np, labels = datagen.workload(AB_WORKLOAD, 3)
+    n, d = x_np.shape
+    m = x_np.mean(0).astype(np.float64)
+    x = torch.from_numpy(x_np).cuda()
+    chains = {}
+    for form, learned in (("plain", 0), ("learned", args.ab_axes)):
+        S, z, rec, extra = run_chain(torch, x, n, d, m, args.ab_iters, learned, args.ab_train_every,
+                                     args.ab_train_steps, args.ab_batch, args.ab_lr)
+        chains[form] = (rec, extra, nmi_mod.nmi(labels, z.cpu().numpy()), S.K)
+        S.close()
+    # the plateau: mean log posterior of the plain chain's last quarter, with a
+    # tolerance of three of its standard deviations (at least 1e-6 relative)
+    tail = np.array([r[3] for r in chains["plain"][0][-max(1, args.ab_iters // 4):]])
+    level = float(tail.mean())
+    tol = max(3.0 * float(tail.std()), 1e-6 * abs(level))
+    out = {"metric": "time-to-plateau learned vs plain", "unit": "s", "higher_is_better": False,
+           "workload": f"{AB_WORKLOAD}: Gaussian DPMM, N={n}, d={d}, {spec.k} true clusters, means N(0,4I), "
+                       "covariances Wishart(d+2, I/d), weights Dir(1); start K=1; BF16 cluster scoring",
+           "plateau_logpost": level, "plateau_tol": tol,
+           "learned_config": {"axes": args.ab_axes, "features": 2 * args.ab_axes, "hidden": [128, 128],
+                              "train_every": args.ab_train_every, "train_steps": args.ab_train_steps,
+                              "batch": args.ab_batch, "lr": args.ab_lr}}
+    for form, (rec, extra, nmi, K) in chains.items():
+        hit = next((r for r in rec if r[3] >= level - tol), None)
+        out[form] = {"time_to_plateau_s": None if hit is None else hit[1],
+                     "iters_to_plateau": None if hit is None else hit[0],
+                     "total_s": rec[-1][1], "final_K": K, "final_logpost": rec[-1][3], "nmi": nmi,
+                     "trace": [[r[0], round(r[1], 4), r[2], r[3]] for r in rec if r[0] % 5 == 0], **extra}
+    p, l = out["plain"], out["learned"]
+    out["speedup_wall"] = (p["time_to_plateau_s"] / l["time_to_plateau_s"]
+                           if p["time_to_plateau_s"] and l["time_to_plateau_s"] else None)
+    out["speedup_iters"] = (p["iters_to_plateau"] / l["iters_to_plateau"]
+                            if p["iters_to_plateau"] and l["iters_to_plateau"] else None)
+    out["nmi_diff"] = l["nmi"] - p["nmi"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,7 +203,19 @@ def main():
     ap.add_argument("--only", action="store_true", help="time only the --precision form")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a device buffer of BYTES five times (calibrates HBM byte counters)")
+    ap.add_argument("--learned-ab", action="store_true",
+                    help="instead of the throughput line: time to the plain chain's log-posterior plateau, "
+                         "learned proposal vs plain, on the learned-proposal workload")
+    ap.add_argument("--ab-iters", type=int, default=200)
+    ap.add_argument("--ab-axes", type=int, default=8)
+    ap.add_argument("--ab-train-every", type=int, default=10)
+    ap.add_argument("--ab-train-steps", type=int, default=40)
+    ap.add_argument("--ab-batch", type=int, default=4096)
+    ap.add_argument("--ab-lr", type=float, default=1e-3)
     args = ap.parse_args()
+    if args.gpus == 1 and args.learned_ab:
+        learned_ab(args)
+        return
     if args.copy_probe:
         import torch
         a = torch.empty(args.copy_probe // 4, dtype=torch.float32, device="cuda").fill_(1.0)
