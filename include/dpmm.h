@@ -84,7 +84,7 @@ typedef struct {
   uint64_t seed;      /* Philox key */
   int32_t precision;  /* cluster scoring of the label step: DPMM_FP32 (vector
                          ALUs, any d); DPMM_BF16 or DPMM_BF16X3 (matrix cores,
-                         Gaussian with d = 32 or 64 only, else DPMM_E_ARG):
+                         Gaussian with d = 32, 64 or 128 only, else DPMM_E_ARG):
                          BF16 inputs with FP32 accumulation, X3 adding the
                          hi/lo cross terms; points whose BF16 top-2 gap leaves
                          any doubt are re-scored in FP32.  Sub-labels,

@@ -276,7 +276,7 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
   if (cfg->precision != DPMM_FP32 && cfg->precision != DPMM_BF16 && cfg->precision != DPMM_BF16X3)
     return bad(DPMM_E_ARG, "unknown precision");
   if (cfg->precision != DPMM_FP32 && !(cfg->family == DPMM_GAUSSIAN && mfma_supported(cfg->d)))
-    return bad(DPMM_E_ARG, "BF16 matrix-core scoring needs the Gaussian family with d = 32 or 64");
+    return bad(DPMM_E_ARG, "BF16 matrix-core scoring needs the Gaussian family with d = 32, 64 or 128");
   if (cfg->merge_form != DPMM_MERGE_PAPER && cfg->merge_form != DPMM_MERGE_INVERSE_SPLIT)
     return bad(DPMM_E_ARG, "unknown merge_form");
   if (cfg->learned < 0) return bad(DPMM_E_ARG, "learned must be >= 0");
@@ -340,6 +340,7 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     ok = ok && chk(c->alloc(&c->d_scratch, (size_t)c->scratch_slots * NIW_SCRATCH(d)));
     if (cfg->precision != DPMM_FP32) {
       ok = ok && chk(c->alloc(&c->d_whi, (size_t)km * d * d));
+      ok = ok && chk(c->alloc(&c->d_nflag, 2));
       if (cfg->precision == DPMM_BF16X3) ok = ok && chk(c->alloc(&c->d_wlo, (size_t)km * d * d));
     }
     if (d >= SORTED_MIN_D) {
@@ -619,7 +620,8 @@ dpmm_status label_phase(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int
     if (ctx->d_whi) {
       DPMM_HIP(ctx, launch_label_gauss_mfma(ctx->d, ctx->cfg.precision == DPMM_BF16X3, (const float*)x, n, *G, *per,
                                             ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->K, t, ctx->cfg.seed, z,
-                                            ctx->d_hist, ctx->d_tot, ctx->stream), "matrix-core label kernel");
+                                            ctx->d_hist, ctx->d_tot, ctx->d_perm, ctx->d_nflag, ctx->stream),
+               "matrix-core label kernel");
       return DPMM_OK;
     }
     DPMM_HIP(ctx, launch_label_gauss_z(ctx->d, (const float*)x, n, *G, *per, ctx->d_packed, ctx->K, t, ctx->cfg.seed, z,

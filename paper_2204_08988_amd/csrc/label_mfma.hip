@@ -1,5 +1,5 @@
 // Gaussian cluster draw on the matrix cores (BF16 inputs, FP32 accumulation):
-// Sec. 4.1 step (e), eq. sample_labels, for d in {32, 64}.
+// Sec. 4.1 step (e), eq. sample_labels, for d in {32, 64, 128}.
 //
 // For cluster k the whitened, centred points of a tile are Y^T = W_k (X - mu_k)^T
 // with W_k lower triangular (W^T W = Sigma^-1).  W_k is the MFMA A operand
@@ -147,6 +147,204 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma(const float* __restr
   }
 }
 
+// d = 128: the cluster's whitener fragments (and mu, c) are staged in LDS once
+// per workgroup and shared by its four waves, double-buffered: cluster k + 1 is
+// fetched into registers while cluster k computes; MFMA tiles entirely above the
+// diagonal of W (16 ks > 32 mt + 31) are skipped, so the matrix cores execute
+// 1.25 d^2 instead of 2 d^2 flops per point-cluster.  Points whose top-2 gap
+// leaves any doubt are not drawn here: they are appended to `flagged` (z = -1,
+// not in the histogram) and drawn by k_rescore_flagged in FP32.
+template <int D, bool X3>
+__global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma_lds(const float* __restrict__ x, long long n,
+                                                                long long per_block, const float* __restrict__ packed,
+                                                                const bf16x8* __restrict__ whi,
+                                                                const bf16x8* __restrict__ wlo, int K,
+                                                                int* __restrict__ z, int* __restrict__ hist,
+                                                                int* __restrict__ tot, int* __restrict__ flagged,
+                                                                int* __restrict__ n_flagged) {
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  constexpr int MT = D / 32, KS = D / 16, NF = MT * KS * 64;
+  constexpr int PF = NF / BLOCK;  // fragments each thread stages per cluster
+  constexpr int NB = X3 ? 2 : 1;  // fragment tables per cluster (hi, lo)
+  constexpr int MUS = D + 4;      // mu[D], c
+  static_assert(NF % BLOCK == 0 && D < BLOCK, "staging layout");
+  // two staging buffers: [buf][NB][NF] fragments, then [buf][MUS] floats, then the histogram
+  extern __shared__ __align__(16) unsigned char smem[];
+  bf16x8* s_w = reinterpret_cast<bf16x8*>(smem);
+  float* s_mu = reinterpret_cast<float*>(s_w + 2 * NB * NF);
+  int* h = reinterpret_cast<int*>(s_mu + 2 * MUS);
+  for (int k = threadIdx.x; k < K; k += BLOCK) h[k] = 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  const long long begin = (long long)blockIdx.x * per_block;
+  const long long end = begin + per_block < n ? begin + per_block : n;
+  // staging of cluster k into buffer b: global -> registers (pf*), registers -> LDS
+  bf16x8 pf[NB][PF];
+  float pfmu = 0.0f;
+  auto fetch = [&](int k) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      pf[0][j] = whi[(size_t)k * NF + threadIdx.x + j * BLOCK];
+      if (X3) pf[NB - 1][j] = wlo[(size_t)k * NF + threadIdx.x + j * BLOCK];
+    }
+    const float* rec = packed + (size_t)k * S;
+    pfmu = threadIdx.x < D ? rec[4 + threadIdx.x] : (threadIdx.x == D ? rec[0] : 0.0f);
+  };
+  auto store = [&](int b) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      s_w[(b * NB) * NF + threadIdx.x + j * BLOCK] = pf[0][j];
+      if (X3) s_w[(b * NB + NB - 1) * NF + threadIdx.x + j * BLOCK] = pf[NB - 1][j];
+    }
+    if (threadIdx.x <= D) s_mu[b * MUS + threadIdx.x] = pfmu;
+  };
+  const bool any = begin < end;
+  if (any) {
+    fetch(0);
+    store(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  // every wave runs the same number of chunks and clusters: one barrier per cluster
+  for (long long chunk = begin; chunk < end; chunk += BLOCK) {
+    const long long base = chunk + wave * 64;
+    const long long pA = base + col, pB = base + 32 + col;
+    float xa[KS][8], xb[KS][8];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = 16 * ks + 8 * half + q;
+        xa[ks][q] = pA < end ? x[pA * D + j] : 0.0f;
+        xb[ks][q] = pB < end ? x[pB * D + j] : 0.0f;
+      }
+    const bool more = chunk + BLOCK < end;
+    float m1 = -INFINITY, m2 = -INFINITY, q1 = 0.0f, q2 = 0.0f;
+    int arg = 0;
+    for (int k = 0; k < K; ++k) {
+      // the next cluster (or the next chunk's first) is fetched while this one computes
+      const bool next = k + 1 < K || more;
+      if (next) fetch(k + 1 < K ? k + 1 : 0);
+      const bf16x8* cw = s_w + (buf * NB) * NF;
+      const bf16x8* cwl = s_w + (buf * NB + NB - 1) * NF;
+      const float* cmu = s_mu + buf * MUS;
+      bf16x8 ba[KS], bb[KS], bal[KS], bbl[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float mu = cmu[16 * ks + 8 * half + q];
+          const float da = xa[ks][q] - mu, db = xb[ks][q] - mu;
+          ba[ks][q] = (__bf16)da;
+          bb[ks][q] = (__bf16)db;
+          if (X3) {
+            bal[ks][q] = (__bf16)(da - (float)ba[ks][q]);
+            bbl[ks][q] = (__bf16)(db - (float)bb[ks][q]);
+          }
+        }
+      float qa = 0.0f, qb = 0.0f;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f32x16 acca = {0}, accb = {0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          if (16 * ks > 32 * mt + 31) continue;  // W is lower triangular: an all-zero tile
+          const bf16x8 a = cw[(mt * KS + ks) * 64 + lane];
+          acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, ba[ks], acca, 0, 0, 0);
+          accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb[ks], accb, 0, 0, 0);
+          if (X3) {
+            const bf16x8 al = cwl[(mt * KS + ks) * 64 + lane];
+            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, ba[ks], acca, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bb[ks], accb, 0, 0, 0);
+            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bal[ks], acca, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbl[ks], accb, 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          qa = fmaf(acca[r], acca[r], qa);
+          qb = fmaf(accb[r], accb[r], qb);
+        }
+      }
+      qa += __shfl_xor(qa, 32);
+      qb += __shfl_xor(qb, 32);
+      const float qm = half ? qb : qa;
+      const float l = fmaf(-0.5f, qm, cmu[D]);
+      if (l > m1) {
+        m2 = m1;
+        q2 = q1;
+        m1 = l;
+        q1 = qm;
+        arg = k;
+      } else if (l > m2) {
+        m2 = l;
+        q2 = qm;
+      }
+      // the other buffer was last read before the previous barrier
+      if (next) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+    const long long p = base + lane;
+    if (p < end) {
+      const float tol = (X3 ? BF16X3_TOL_REL : BF16_TOL_REL) * (q1 + q2) + TOL_ABS;
+      if (m2 > m1 - RGAP - tol) {
+        flagged[atomicAdd(n_flagged, 1)] = (int)p;
+        z[p] = -1;
+      } else {
+        z[p] = arg;
+        atomicAdd(&h[arg], 1);
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += BLOCK) {
+    hist[(size_t)blockIdx.x * K + k] = h[k];
+    if (h[k]) atomicAdd(&tot[k], h[k]);
+  }
+}
+
+constexpr int RS_BLOCK = 64;
+
+// FP32 re-score and lazy Gumbel-max draw of the deferred points (exactly the
+// FP32 kernel's draw); the centred vector of a thread lives in an LDS column.
+// Adds each drawn point to the histogram of the label-kernel block that owns it.
+__global__ __launch_bounds__(RS_BLOCK) void k_rescore_flagged(const float* __restrict__ x, int d,
+                                                              const int* __restrict__ flagged,
+                                                              const int* __restrict__ n_flagged, long long per_block,
+                                                              const float* __restrict__ packed, int K, uint32_t t,
+                                                              uint64_t seed, int* __restrict__ z,
+                                                              int* __restrict__ hist, int* __restrict__ tot) {
+  extern __shared__ float dxs[];  // [d][RS_BLOCK]
+  float* dx = dxs + threadIdx.x;
+  const int S = gauss_rec_stride(d);
+  const int cnt = *n_flagged;
+  for (int q = blockIdx.x * RS_BLOCK + threadIdx.x; q < cnt; q += gridDim.x * RS_BLOCK) {
+    const long long p = flagged[q];
+    const float* xp = x + p * d;
+    auto score = [&](int k) {
+      const float* rp = packed + (size_t)k * S;
+      for (int j = 0; j < d; ++j) dx[j * RS_BLOCK] = xp[j] - rp[4 + j];
+      const float* w = rp + 4 + d;
+      float qq = 0.0f;
+      for (int r = 0; r < d; ++r) {
+        const float* wr = w + r * (r + 1) / 2;
+        float y = 0.0f;
+        for (int c = 0; c <= r; ++c) y = fmaf(wr[c], dx[c * RS_BLOCK], y);
+        qq = fmaf(y, y, qq);
+      }
+      return fmaf(-0.5f, qq, rp[0]);
+    };
+    Top2 f;
+    f.init();
+    for (int k = 0; k < K; ++k) f.push(score(k), k);
+    const int zi = lazy_gumbel_max(f, K, (uint32_t)p, t, seed, score);
+    z[p] = zi;
+    atomicAdd(&hist[(size_t)(p / per_block) * K + zi], 1);
+    atomicAdd(&tot[zi], 1);
+  }
+}
+
 // Fragment table of cluster k's whitener: element (mt, ks, lane, q) =
 // W[32 mt + lane % 32][16 ks + 8 (lane / 32) + q] (zero above the diagonal).
 __global__ void k_pack_wfrag(int K, int d, int k_max, const float* __restrict__ packed, __bf16* __restrict__ whi,
@@ -169,7 +367,7 @@ __global__ void k_pack_wfrag(int K, int d, int k_max, const float* __restrict__ 
 
 }  // namespace
 
-bool mfma_supported(int d) { return d == 32 || d == 64; }
+bool mfma_supported(int d) { return d == 32 || d == 64 || d == 128; }
 
 hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void* whi, void* wlo, hipStream_t s) {
   hipLaunchKernelGGL(k_pack_wfrag, dim3(K), dim3(256), 0, s, K, d, k_max, packed, (__bf16*)whi, (__bf16*)wlo);
@@ -178,13 +376,40 @@ hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void*
 
 hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, int G, long long per_block,
                                    const float* packed, const void* whi, const void* wlo, int K, uint32_t t,
-                                   uint64_t seed, int* z, int* hist, int* tot, hipStream_t s) {
+                                   uint64_t seed, int* z, int* hist, int* tot, int* flagged, int* n_flagged,
+                                   hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipError_t e = launch_zero64(tot, (size_t)(K + 1) / 2 + 1, s);
   if (e != hipSuccess) return e;
   const size_t lh = (size_t)K * sizeof(int);
   const bf16x8* hi = (const bf16x8*)whi;
   const bf16x8* lo = (const bf16x8*)wlo;
+  if (d == 128) {
+    e = launch_zero64(n_flagged, 1, s);
+    if (e != hipSuccess) return e;
+    constexpr int NF = 4 * 8 * 64;
+    const size_t lds = 2 * ((size_t)(x3 ? 2 : 1) * NF * sizeof(bf16x8) + (128 + 4) * sizeof(float)) + lh;
+    static bool attr_set = false;
+    if (!attr_set) {  // more than 64 KB of dynamic LDS (160 KB per CU on gfx950)
+      e = hipFuncSetAttribute((const void*)k_label_gauss_mfma_lds<128, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_label_gauss_mfma_lds<128, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+    if (x3)
+      hipLaunchKernelGGL((k_label_gauss_mfma_lds<128, true>), dim3(G), dim3(BLOCK), lds, s, x, n, per_block, packed,
+                         hi, lo, K, z, hist, tot, flagged, n_flagged);
+    else
+      hipLaunchKernelGGL((k_label_gauss_mfma_lds<128, false>), dim3(G), dim3(BLOCK), lds, s, x, n, per_block, packed,
+                         hi, lo, K, z, hist, tot, flagged, n_flagged);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rescore_flagged, dim3(1024), dim3(RS_BLOCK), (size_t)d * RS_BLOCK * sizeof(float), s, x, d,
+                       flagged, n_flagged, per_block, packed, K, t, seed, z, hist, tot);
+    return hipGetLastError();
+  }
   if (d == 32 && !x3)
     hipLaunchKernelGGL((k_label_gauss_mfma<32, false>), dim3(G), dim3(BLOCK), lh, s, x, n, per_block, packed, hi, lo, K,
                        t, seed, z, hist, tot);

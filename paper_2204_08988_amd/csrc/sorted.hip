@@ -543,6 +543,276 @@ size_t sub_stats_lds(int d, int TR, bool generic) {
   return b;
 }
 
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
+
+// FP32 score c - 1/2 |W (x - mu)|^2 of a row held in LDS under the record p
+// (wave-uniform: its loads are scalar); the centred row lives in registers.
+template <int D>
+__device__ __forceinline__ float score_lds(const float* __restrict__ p, const float* __restrict__ xr) {
+  float dx[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) dx[j] = xr[j] - p[4 + j];
+  const float* w = p + 4 + D;
+  float q = 0.0f;
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    float y = 0.0f;
+#pragma unroll
+    for (int c = 0; c <= r; ++c) y = fmaf(w[r * (r + 1) / 2 + c], dx[c], y);
+    q = fmaf(y, y, q);
+  }
+  return fmaf(-0.5f, q, p[0]);
+}
+
+constexpr int BIG_THREADS = 512;  // 8 waves: 0-3 own the left segment, 4-7 the right
+constexpr int BIG_ROWS = 256;     // sorted rows per tile
+
+__device__ __forceinline__ int block_inclusive_scan_big(int v, int* buf) {
+  const int tid = threadIdx.x;
+  buf[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < BIG_THREADS; off <<= 1) {
+    const int add = tid >= off ? buf[tid - off] : 0;
+    __syncthreads();
+    buf[tid] += add;
+    __syncthreads();
+  }
+  const int r = buf[tid];
+  __syncthreads();
+  return r;
+}
+
+// Sub-label draw of sorted rows, one row per thread (d = 128): the FP32
+// scores of the two sub-clusters of the row's cluster with wave-uniform
+// (scalar-loaded) parameters and the centred row in registers.
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_sub_labels_big(const float* __restrict__ x, long long n_sorted,
+                                                          const int* __restrict__ perm, const int* __restrict__ z,
+                                                          unsigned char* __restrict__ zsub,
+                                                          const float* __restrict__ packed, int k_max, uint32_t t,
+                                                          uint64_t seed) {
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  const bool valid = g < n_sorted;
+  const int i = valid ? perm[g] : 0;
+  const int k = valid ? z[i] : -1;
+  float delta = 0.0f;
+  unsigned long long pending = __ballot(valid);
+  while (pending) {
+    const int lane0 = __ffsll((long long)pending) - 1;
+    const int kk = __builtin_amdgcn_readfirstlane(__shfl(k, lane0));
+    const bool mine = valid && k == kk;
+    if (mine) {
+      const float* ps = packed + (size_t)(k_max + 2 * kk) * S;
+      float sc[2];
+#pragma clang loop unroll(disable)
+      for (int h = 0; h < 2; ++h) sc[h] = score_lds<D>(ps + h * S, x + (size_t)i * D);
+      delta = sc[0] - sc[1];
+    }
+    pending &= ~__ballot(mine);
+  }
+  if (!valid) return;
+  int zs;
+  if (delta > LOGISTIC_MAX_F) {
+    zs = 0;
+  } else if (delta < -LOGISTIC_MAX_F) {
+    zs = 1;
+  } else {
+    const float L = logistic_f(rng_block(seed, t, (uint32_t)i, TAG_LOGISTIC, 0).x);
+    zs = delta + L > 0.0f ? 0 : 1;
+  }
+  zsub[i] = (unsigned char)zs;
+}
+
+// Sub-labels (d = 64, SAMPLE) and statistics for d in {64, 128} over the
+// cluster-sorted order, with sum x x^T on the FP64 matrix cores.  A workgroup
+// of 8 waves walks a contiguous range of tiles of BIG_ROWS sorted rows:
+//   (1) the tile's rows are gathered into LDS (coalesced row reads);
+//   (2) with SAMPLE, thread r < BIG_ROWS draws row r's sub-label from the
+//       FP32 scores of the two sub-clusters of its cluster (wave-uniform
+//       parameters: scalar loads); otherwise the sub-label is read;
+//   (3) rows are grouped by segment (run of a cluster, sub-label);
+//   (4) per segment, four rows at a time, v_mfma_f64_16x16x4_f64 adds
+//       X_I^T X_J to the upper 16 x 16 blocks (I, J) of sum x x^T: the left
+//       segment belongs to waves 0-3, the right to waves 4-7, and a wave owns
+//       blocks w, w + 4, ... (FP32 inputs are exact in FP64); each wave also
+//       sums a quarter of sum x in FP64 on the vector ALUs.
+// Each wave carries its segment of the current cluster across tiles and
+// flushes it with global atomics when the cluster changes or the range ends.
+template <int D, bool SAMPLE>
+__global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __restrict__ x, long long n_sorted,
+                                                               int tpb, const int* __restrict__ perm,
+                                                               const int* __restrict__ z,
+                                                               unsigned char* __restrict__ zsub,
+                                                               const float* __restrict__ packed, int k_max,
+                                                               uint32_t t, uint64_t seed,
+                                                               long long* __restrict__ counts,
+                                                               double* __restrict__ moments) {
+  constexpr int LD = D + 1;  // odd row stride
+  constexpr int NB = D / 16, NT = NB * (NB + 1) / 2, TPW = (NT + 3) / 4;
+  constexpr int E = D + D * (D + 1) / 2;
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  constexpr int DW = D / 4;  // dimensions of sum x per wave
+  extern __shared__ float xs[];  // [BIG_ROWS][LD]
+  __shared__ int order[BIG_ROWS], rk[BIG_ROWS], buf[BIG_THREADS];
+  __shared__ int lcount[2 * BIG_ROWS], lstart[2 * BIG_ROWS], lseg[2 * BIG_ROWS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int side = wave >> 2, wq = wave & 3;  // segment (0 left, 1 right), quarter
+  int bI[TPW], bJ[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) {
+    int u = wq + 4 * j, a = 0;
+    bI[j] = -1;
+    bJ[j] = -1;
+    if (u < NT) {
+      while (u >= NB - a) {
+        u -= NB - a;
+        ++a;
+      }
+      bI[j] = a;
+      bJ[j] = a + u;
+    }
+  }
+  f64x4 acc[TPW];
+  double sx = 0.0;
+  long long cnt_seg = 0;
+  int cur_k = -1;
+  auto zero_acc = [&]() {
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    sx = 0.0;
+    cnt_seg = 0;
+  };
+  auto flush = [&]() {
+    if (cur_k < 0 || cnt_seg == 0) return;
+    const int seg = 2 * cur_k + side;
+    double* M = moments + (size_t)seg * E;
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+      if (bI[j] < 0) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        // accumulator element e of lane l is row l / 16 + 4 e, column l % 16
+        const int a = 16 * bI[j] + (lane >> 4) + 4 * e, b = 16 * bJ[j] + (lane & 15);
+        if (a <= b) atomicAdd(&M[D + a * D - (a * (a - 1)) / 2 + (b - a)], acc[j][e]);
+      }
+    }
+    if (lane < DW) atomicAdd(&M[wq * DW + lane], sx);
+    if (wq == 0 && lane == 0) atomicAdd((unsigned long long*)&counts[seg], (unsigned long long)cnt_seg);
+  };
+  zero_acc();
+  const long long tiles = (n_sorted + BIG_ROWS - 1) / BIG_ROWS;
+  const long long tb = (long long)blockIdx.x * tpb;
+  const long long te = tb + tpb < tiles ? tb + tpb : tiles;
+  for (long long tile = tb; tile < te; ++tile) {
+    const long long base = tile * BIG_ROWS;
+    const int rows = (int)(n_sorted - base < BIG_ROWS ? n_sorted - base : BIG_ROWS);
+    const bool valid = tid < rows;
+    __syncthreads();  // the previous tile's LDS reads are done
+    // ---- (1) gather the rows
+    int my_i = 0, k = -1;
+    if (valid) {
+      my_i = perm[base + tid];
+      k = z[my_i];
+      rk[tid] = k;
+      order[tid] = my_i;
+    }
+    for (int q = tid; q < 2 * BIG_ROWS; q += BIG_THREADS) lcount[q] = 0;
+    __syncthreads();
+    for (int e = tid; e < rows * D; e += BIG_THREADS) {
+      const int r = e / D, c = e - r * D;
+      xs[r * LD + c] = x[(size_t)order[r] * D + c];
+    }
+    __syncthreads();
+    // ---- (2) sub-label of row tid
+    int zs = 0;
+    if (SAMPLE) {
+      float delta = 0.0f;
+      unsigned long long pending = __ballot(valid);
+      while (pending) {
+        const int lane0 = __ffsll((long long)pending) - 1;
+        const int kk = __builtin_amdgcn_readfirstlane(__shfl(k, lane0));
+        const bool mine = valid && k == kk;
+        if (mine) {
+          const float* ps = packed + (size_t)(k_max + 2 * kk) * S;
+          float sc[2];
+#pragma clang loop unroll(disable)
+          for (int h = 0; h < 2; ++h) sc[h] = score_lds<D>(ps + h * S, xs + tid * LD);
+          delta = sc[0] - sc[1];
+        }
+        pending &= ~__ballot(mine);
+      }
+      if (valid) {
+        if (delta > LOGISTIC_MAX_F) {
+          zs = 0;
+        } else if (delta < -LOGISTIC_MAX_F) {
+          zs = 1;
+        } else {
+          const float L = logistic_f(rng_block(seed, t, (uint32_t)my_i, TAG_LOGISTIC, 0).x);
+          zs = delta + L > 0.0f ? 0 : 1;
+        }
+        zsub[my_i] = (unsigned char)zs;
+      }
+    } else if (valid) {
+      zs = zsub[my_i] ? 1 : 0;
+    }
+    // ---- (3) group rows by segment: run of the cluster (rows are sorted by
+    // z), then sub-label
+    const int flag = (valid && (tid == 0 || rk[tid] != rk[tid - 1])) ? 1 : 0;
+    const int incl = block_inclusive_scan_big(flag, buf);
+    const int nl = 2 * buf[BIG_THREADS - 1];
+    int lid = 0;
+    if (valid) {
+      lid = 2 * (incl - 1) + zs;
+      atomicAdd(&lcount[lid], 1);
+      lseg[lid] = 2 * k + zs;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int a = 0;
+      for (int q = 0; q < nl; ++q) {
+        lstart[q] = a;
+        a += lcount[q];
+      }
+    }
+    __syncthreads();
+    if (valid) order[lstart[lid] + atomicAdd(&lcount[lid], 0x10000) / 0x10000] = tid;
+    __syncthreads();
+    for (int q = tid; q < nl; q += BIG_THREADS) lcount[q] &= 0xFFFF;
+    __syncthreads();
+    // ---- (4) this wave's segments: runs q with sub-label `side`
+    for (int q = side; q < nl; q += 2) {
+      const int cnt = lcount[q];
+      if (cnt == 0) continue;
+      const int kq = lseg[q] >> 1;
+      if (kq != cur_k) {
+        flush();
+        zero_acc();
+        cur_k = kq;
+      }
+      cnt_seg += cnt;
+      const int st = lstart[q];
+      for (int g = 0; g < cnt; g += 4) {
+        const int p = g + (lane >> 4);
+        const bool ok = p < cnt;
+        const float* xr = xs + (size_t)(ok ? order[st + p] : 0) * LD;
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+          if (bI[j] < 0) continue;
+          const double av = ok ? (double)xr[16 * bI[j] + (lane & 15)] : 0.0;
+          const double bv = ok ? (double)xr[16 * bJ[j] + (lane & 15)] : 0.0;
+          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[j], 0, 0, 0);
+        }
+      }
+      if (lane < DW) {
+        const int dim = wq * DW + lane;
+        for (int p = 0; p < cnt; ++p) sx += (double)xs[(size_t)order[st + p] * LD + dim];
+      }
+    }
+  }
+  flush();
+}
+
 template <bool SAMPLE>
 hipError_t launch_sub_stats_t(int d, const float* x, long long n, const int* perm, const int* z, unsigned char* zsub,
                               const float* packed, int k_max, uint32_t t, uint64_t seed, long long* counts,
@@ -605,6 +875,41 @@ hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, con
   e = launch_zero64(moments, (size_t)2 * K * E, s);
   if (e != hipSuccess) return e;
   if (n == 0) return hipSuccess;
+  if (d == 64 || d == 128) {
+    // d = 128 draws the sub-labels in their own pass (registers), then counts
+    if (sample && d == 128) {
+      const unsigned lg = (unsigned)((n + BLOCK - 1) / BLOCK);
+      hipLaunchKernelGGL(k_sub_labels_big<128>, dim3(lg), dim3(BLOCK), 0, s, x, n, perm, z, zsub, packed, k_max, t,
+                         seed);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const long long tiles = (n + BIG_ROWS - 1) / BIG_ROWS;
+    const long long gmax = d == 128 ? 256 : 512;
+    const long long g = tiles < gmax ? tiles : gmax;
+    const int tpb = (int)((tiles + g - 1) / g);
+    const unsigned grid = (unsigned)((tiles + tpb - 1) / tpb);
+    const size_t lds = (size_t)BIG_ROWS * (d + 1) * sizeof(float);  // above 64 KB: raise the limit once
+    static bool attr_set = false;
+    if (!attr_set) {
+      const void* fns[3] = {(const void*)k_sub_stats_big<64, true>, (const void*)k_sub_stats_big<64, false>,
+                            (const void*)k_sub_stats_big<128, false>};
+      for (const void* f : fns) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 144 * 1024);
+        if (e != hipSuccess) return e;
+      }
+      attr_set = true;
+    }
+    if (d == 64 && sample)
+      hipLaunchKernelGGL((k_sub_stats_big<64, true>), dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z,
+                         zsub, packed, k_max, t, seed, counts, moments);
+    else if (d == 64)
+      hipLaunchKernelGGL((k_sub_stats_big<64, false>), dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z,
+                         zsub, packed, k_max, t, seed, counts, moments);
+    else
+      hipLaunchKernelGGL((k_sub_stats_big<128, false>), dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z,
+                         zsub, packed, k_max, t, seed, counts, moments);
+    return hipGetLastError();
+  }
   if (d == 8 || d == 16 || d == 32) {
     // about eight waves per CU, each on a contiguous range of whole 64-row chunks
     const long long waves = 2048;

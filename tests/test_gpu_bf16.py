@@ -1,10 +1,12 @@
-"""GPU parity of the BF16 / bf16x3 matrix-core cluster scoring (d = 32, 64).
+"""GPU parity of the BF16 / bf16x3 matrix-core cluster scoring (d = 32, 64, 128).
 
 The labels must meet the FP32 comparison rule against the FP64 oracle: the
 precision guard re-scores in FP32 every point whose BF16 top-2 gap leaves the
 draw in doubt, so no label may differ where the oracle's margin is clear.
 Covariances are Wishart(d + 2, I/d) draws, the ill-conditioned shape of the
-d = 32 workload."""
+d = 32 workload.  At d = 128 the doubtful points are drawn by a separate FP32
+pass after the matrix-core pass; close cluster means (mean_scale 0.4) force
+many of them."""
 import numpy as np
 import pytest
 
@@ -28,12 +30,14 @@ def _wishart_params(K, d, seed, mean_scale=5.0):
 
 
 @pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
-@pytest.mark.parametrize("d,K,n", [(32, 20, 20000), (32, 3, 4097), (64, 8, 6000), (64, 1, 333)])
-def test_bf16_labels_meet_fp32_rule(precision, d, K, n):
+@pytest.mark.parametrize("d,K,n,scale", [(32, 20, 20000, 5.0), (32, 3, 4097, 5.0), (64, 8, 6000, 5.0),
+                                         (64, 1, 333, 5.0), (128, 6, 3000, 5.0), (128, 1, 257, 5.0),
+                                         (128, 5, 2000, 0.4)])
+def test_bf16_labels_meet_fp32_rule(precision, d, K, n, scale):
     import torch
     from paper_2204_08988_amd.sampler import Sampler
     seed = 4000 + d + K
-    params = _wishart_params(K, d, seed)
+    params = _wishart_params(K, d, seed, mean_scale=scale)
     x = pu.gauss_points(params, n, seed + 1)
     S = Sampler("gaussian", d, K + 2, 2.0, seed, m=np.zeros(d), psi=np.eye(d), precision=precision)
     S.set_params(params.log_pi, params.log_pisub, pu.comp_array(params))
@@ -47,6 +51,9 @@ def test_bf16_labels_meet_fp32_rule(precision, d, K, n):
         assert bad_c.size == 0, (bad_c[:10], tie_c)
         assert bad_s.size == 0, (bad_s[:10], tie_s)
         assert tie_c + tie_s <= max(2, n // 1000)
+        # the sorted statistics pass used the label pass's histograms
+        counts = S.get_stats()[:, :, 0].sum(axis=1)
+        assert np.array_equal(counts, np.bincount(z.cpu().numpy(), minlength=K))
     S.close()
 
 
