@@ -81,6 +81,18 @@ __device__ __forceinline__ float logistic_f(uint32_t w) {
   return logf(u) - log1pf(-u);
 }
 
+// Sub-label draw (eq. sample_sub_labels) from the score gap delta = l_l - l_r:
+// l (0) iff delta + L > 0 for the logistic L = log u - log(1 - u) of point i's
+// word; since the logit is increasing this is u > 1 / (1 + e^delta), one exp
+// instead of two logs.  A gap beyond the logistic's range decides without a
+// draw.
+__device__ __forceinline__ int sub_label_draw(float delta, uint64_t seed, uint32_t t, uint32_t i) {
+  if (delta > LOGISTIC_MAX_F) return 0;
+  if (delta < -LOGISTIC_MAX_F) return 1;
+  const float u = uniform_f(rng_block(seed, t, i, TAG_LOGISTIC, 0).x);
+  return u > 1.0f / (1.0f + expf(delta)) ? 0 : 1;
+}
+
 __host__ __device__ __forceinline__ double box_muller_d(uint32_t w0, uint32_t w1) {
   const double u0 = uniform_d(w0), u1 = uniform_d(w1);
   return sqrt(-2.0 * log(u0)) * cos(6.283185307179586 * u1);

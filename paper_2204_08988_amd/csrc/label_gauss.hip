@@ -29,12 +29,25 @@ namespace {
 
 using namespace score;
 
-template <int D>
+template <int D, bool STAGED>
 __global__ __launch_bounds__(BLOCK) void k_label_gauss(const float* __restrict__ x, long long n,
                                                        const float* __restrict__ packed, int K, int k_max,
                                                        uint32_t t, uint64_t seed, int* __restrict__ z,
                                                        unsigned char* __restrict__ zsub) {
   constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  // STAGED: the K cluster records, then the 2K sub-cluster records, copied to
+  // LDS once per workgroup (broadcast reads instead of a scalar load per
+  // cluster and a per-lane global gather per point)
+  extern __shared__ float recs[];
+  const float* cl = packed;
+  const float* sub = packed + (size_t)k_max * S;
+  if constexpr (STAGED) {
+    for (int q = threadIdx.x; q < K * S; q += BLOCK) recs[q] = packed[q];
+    for (int q = threadIdx.x; q < 2 * K * S; q += BLOCK) recs[K * S + q] = packed[(size_t)k_max * S + q];
+    __syncthreads();
+    cl = recs;
+    sub = recs + K * S;
+  }
   const long long stride_pts = (long long)gridDim.x * BLOCK;
   for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride_pts) {
     float xv[D];
@@ -42,10 +55,10 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss(const float* __restrict__
     for (int j = 0; j < D; ++j) xv[j] = x[i * D + j];
     Top2 t2;
     t2.init();
-    for (int k = 0; k < K; ++k) t2.push(score_rec<D>(packed + (size_t)k * S, xv), k);
+    for (int k = 0; k < K; ++k) t2.push(score_rec<D>(cl + (size_t)k * S, xv), k);
     const int zi = lazy_gumbel_max(t2, K, (uint32_t)i, t, seed,
-                                   [&](int k) { return score_rec<D>(packed + (size_t)k * S, xv); });
-    const float* ps = packed + (size_t)(k_max + 2 * zi) * S;
+                                   [&](int k) { return score_rec<D>(cl + (size_t)k * S, xv); });
+    const float* ps = sub + (size_t)(2 * zi) * S;
     const float delta = score_rec<D>(ps, xv) - score_rec<D>(ps + S, xv);
     z[i] = zi;
     zsub[i] = draw_sub(delta, (uint32_t)i, t, seed);
@@ -168,10 +181,17 @@ hipError_t launch_label_gauss(int d, const float* x, long long n, const float* p
                               uint32_t t, uint64_t seed, int* z, unsigned char* zsub, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int g = grid_for(n);
+  // the 3K score records go to LDS when they fit in 48 KB
+  const size_t rec_bytes = (size_t)3 * K * gauss_rec_stride(d) * sizeof(float);
+  const bool staged = rec_bytes <= 48 * 1024;
 #define DPMM_LABEL_CASE(DD)                                                                          \
   case DD:                                                                                           \
-    hipLaunchKernelGGL(k_label_gauss<DD>, dim3(g), dim3(BLOCK), 0, s, x, n, packed, K, k_max, t,     \
-                       seed, z, zsub);                                                               \
+    if (staged)                                                                                      \
+      hipLaunchKernelGGL((k_label_gauss<DD, true>), dim3(g), dim3(BLOCK), rec_bytes, s, x, n, packed, \
+                         K, k_max, t, seed, z, zsub);                                                \
+    else                                                                                             \
+      hipLaunchKernelGGL((k_label_gauss<DD, false>), dim3(g), dim3(BLOCK), 0, s, x, n, packed, K,    \
+                         k_max, t, seed, z, zsub);                                                   \
     break;
   switch (d) {
     DPMM_LABEL_CASE(1)

@@ -75,14 +75,7 @@ __global__ __launch_bounds__(BLOCK) void k_label_mult(const int* __restrict__ x,
     const float* ps = packed + (size_t)(k_max + 2 * zi) * S;
     const float delta = score_mult<VT>(ps, xv) - score_mult<VT>(ps + S, xv);
     unsigned char zs;
-    if (delta > LOGISTIC_MAX_F) {
-      zs = 0;
-    } else if (delta < -LOGISTIC_MAX_F) {
-      zs = 1;
-    } else {
-      const float L = logistic_f(rng_block(seed, t, (uint32_t)i, TAG_LOGISTIC, 0).x);
-      zs = delta + L > 0.0f ? 0 : 1;
-    }
+    zs = sub_label_draw(delta, seed, t, (uint32_t)i);
     z[i] = zi;
     zsub[i] = zs;
   }

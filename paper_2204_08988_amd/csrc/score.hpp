@@ -89,10 +89,7 @@ __device__ __forceinline__ int lazy_gumbel_max(const Top2& t2, int K, uint32_t i
 }
 
 __device__ __forceinline__ unsigned char draw_sub(float delta, uint32_t i, uint32_t t, uint64_t seed) {
-  if (delta > LOGISTIC_MAX_F) return 0;
-  if (delta < -LOGISTIC_MAX_F) return 1;
-  const float L = logistic_f(rng_block(seed, t, i, TAG_LOGISTIC, 0).x);
-  return delta + L > 0.0f ? 0 : 1;
+  return (unsigned char)sub_label_draw(delta, seed, t, i);
 }
 
 }  // namespace score

@@ -270,14 +270,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
         pending &= ~__ballot(mine);
       }
       if (valid) {
-        if (delta > LOGISTIC_MAX_F) {
-          zs = 0;
-        } else if (delta < -LOGISTIC_MAX_F) {
-          zs = 1;
-        } else {
-          const float L = logistic_f(rng_block(seed, t, (uint32_t)i, TAG_LOGISTIC, 0).x);
-          zs = delta + L > 0.0f ? 0 : 1;
-        }
+        zs = sub_label_draw(delta, seed, t, (uint32_t)i);
         zsub[i] = (unsigned char)zs;
       }
     } else if (valid) {
@@ -465,14 +458,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
         pending &= ~__ballot(mine);
       }
       if (valid) {
-        if (delta > LOGISTIC_MAX_F) {
-          zs = 0;
-        } else if (delta < -LOGISTIC_MAX_F) {
-          zs = 1;
-        } else {
-          const float L = logistic_f(rng_block(seed, t, (uint32_t)i, TAG_LOGISTIC, 0).x);
-          zs = delta + L > 0.0f ? 0 : 1;
-        }
+        zs = sub_label_draw(delta, seed, t, (uint32_t)i);
         zsub[i] = (unsigned char)zs;
       }
     } else if (valid) {
@@ -613,14 +599,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_labels_big(const float* __restric
   }
   if (!valid) return;
   int zs;
-  if (delta > LOGISTIC_MAX_F) {
-    zs = 0;
-  } else if (delta < -LOGISTIC_MAX_F) {
-    zs = 1;
-  } else {
-    const float L = logistic_f(rng_block(seed, t, (uint32_t)i, TAG_LOGISTIC, 0).x);
-    zs = delta + L > 0.0f ? 0 : 1;
-  }
+  zs = sub_label_draw(delta, seed, t, (uint32_t)i);
   zsub[i] = (unsigned char)zs;
 }
 
@@ -743,14 +722,7 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
         pending &= ~__ballot(mine);
       }
       if (valid) {
-        if (delta > LOGISTIC_MAX_F) {
-          zs = 0;
-        } else if (delta < -LOGISTIC_MAX_F) {
-          zs = 1;
-        } else {
-          const float L = logistic_f(rng_block(seed, t, (uint32_t)my_i, TAG_LOGISTIC, 0).x);
-          zs = delta + L > 0.0f ? 0 : 1;
-        }
+        zs = sub_label_draw(delta, seed, t, (uint32_t)my_i);
         zsub[my_i] = (unsigned char)zs;
       }
     } else if (valid) {
