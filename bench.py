@@ -125,10 +125,12 @@ def run_form(torch, x, n, d, m, precision, steps, warmup, k_true):
 AB_WORKLOAD = "gauss_d64"
 
 
-def run_chain(torch, x, n, d, m, iters, learned, train_every, train_steps, batch, lr):
+def run_chain(torch, x, n, d, m, iters, learned, train_every, train_until, train_steps, batch, lr):
     """One chain from K = 1 with the BF16 form: per iteration (t, seconds since
-    the start, K, log posterior, learned move accepted).  Training time of the
-    learned chain is inside the clock."""
+    the start, K, log posterior).  The learned chain trains every `train_every`
+    iterations up to iteration `train_until` (the growth phase, while clusters
+    still hold several components and their sub-labels carry a signal); its
+    training time is inside the clock."""
     from paper_2204_08988_amd.sampler import Sampler
     S = Sampler("gaussian", d, 512, ALPHA, SEED, kappa=1.0, nu=d + 3.0, m=m, psi=np.eye(d), burn_out=5,
                 precision="bf16", learned=learned)
@@ -141,7 +143,7 @@ def run_chain(torch, x, n, d, m, iters, learned, train_every, train_steps, batch
         if learned:
             tries += 1
             acc += info["learned_accepted"]
-            if t % train_every == 0:
+            if t % train_every == 0 and t <= train_until:
                 a = time.perf_counter()
                 S.mlp_train(x, z, zs, train_steps, batch, lr)
                 t_train += time.perf_counter() - a
@@ -162,20 +164,23 @@ def learned_ab(args):
     chains = {}
     for form, learned in (("plain", 0), ("learned", args.ab_axes)):
         S, z, rec, extra = run_chain(torch, x, n, d, m, args.ab_iters, learned, args.ab_train_every,
-                                     args.ab_train_steps, args.ab_batch, args.ab_lr)
+                                     args.ab_train_until, args.ab_train_steps, args.ab_batch, args.ab_lr)
         chains[form] = (rec, extra, nmi_mod.nmi(labels, z.cpu().numpy()), S.K)
         S.close()
-    # the plateau: mean log posterior of the plain chain's last quarter, with a
-    # tolerance of three of its standard deviations (at least 1e-6 relative)
+    # the plateau: mean log posterior of the plain chain's last quarter; a chain
+    # has reached it once within max(3 standard deviations of that tail, 1e-5 of
+    # the level) -- converged chains can settle in modes a few hundred nats
+    # apart (one cluster more or less), far below 1e-5 of the level
     tail = np.array([r[3] for r in chains["plain"][0][-max(1, args.ab_iters // 4):]])
     level = float(tail.mean())
-    tol = max(3.0 * float(tail.std()), 1e-6 * abs(level))
+    tol = max(3.0 * float(tail.std()), 1e-5 * abs(level))
     out = {"metric": "time-to-plateau learned vs plain", "unit": "s", "higher_is_better": False,
            "workload": f"{AB_WORKLOAD}: Gaussian DPMM, N={n}, d={d}, {spec.k} true clusters, means N(0,4I), "
                        "covariances Wishart(d+2, I/d), weights Dir(1); start K=1; BF16 cluster scoring",
            "plateau_logpost": level, "plateau_tol": tol,
            "learned_config": {"axes": args.ab_axes, "features": 2 * args.ab_axes, "hidden": [128, 128],
-                              "train_every": args.ab_train_every, "train_steps": args.ab_train_steps,
+                              "train_every": args.ab_train_every, "train_until": args.ab_train_until,
+                              "train_steps": args.ab_train_steps,
                               "batch": args.ab_batch, "lr": args.ab_lr}}
     for form, (rec, extra, nmi, K) in chains.items():
         hit = next((r for r in rec if r[3] >= level - tol), None)
@@ -209,7 +214,8 @@ def main():
     ap.add_argument("--ab-iters", type=int, default=200)
     ap.add_argument("--ab-axes", type=int, default=8)
     ap.add_argument("--ab-train-every", type=int, default=10)
-    ap.add_argument("--ab-train-steps", type=int, default=40)
+    ap.add_argument("--ab-train-until", type=int, default=60)
+    ap.add_argument("--ab-train-steps", type=int, default=20)
     ap.add_argument("--ab-batch", type=int, default=4096)
     ap.add_argument("--ab-lr", type=float, default=1e-3)
     args = ap.parse_args()

@@ -384,27 +384,31 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
   const size_t lh = (size_t)K * sizeof(int);
   const bf16x8* hi = (const bf16x8*)whi;
   const bf16x8* lo = (const bf16x8*)wlo;
-  if (d == 128) {
+  if (d == 64 || d == 128) {
     e = launch_zero64(n_flagged, 1, s);
     if (e != hipSuccess) return e;
-    constexpr int NF = 4 * 8 * 64;
-    const size_t lds = 2 * ((size_t)(x3 ? 2 : 1) * NF * sizeof(bf16x8) + (128 + 4) * sizeof(float)) + lh;
+    const int NF = (d / 32) * (d / 16) * 64;
+    const size_t lds = 2 * ((size_t)(x3 ? 2 : 1) * NF * sizeof(bf16x8) + (d + 4) * sizeof(float)) + lh;
     static bool attr_set = false;
     if (!attr_set) {  // more than 64 KB of dynamic LDS (160 KB per CU on gfx950)
-      e = hipFuncSetAttribute((const void*)k_label_gauss_mfma_lds<128, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_label_gauss_mfma_lds<128, false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      if (e != hipSuccess) return e;
+      const void* fns[4] = {(const void*)k_label_gauss_mfma_lds<128, true>,
+                            (const void*)k_label_gauss_mfma_lds<128, false>,
+                            (const void*)k_label_gauss_mfma_lds<64, true>,
+                            (const void*)k_label_gauss_mfma_lds<64, false>};
+      for (const void* f : fns) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+      }
       attr_set = true;
     }
-    if (x3)
-      hipLaunchKernelGGL((k_label_gauss_mfma_lds<128, true>), dim3(G), dim3(BLOCK), lds, s, x, n, per_block, packed,
-                         hi, lo, K, z, hist, tot, flagged, n_flagged);
-    else
-      hipLaunchKernelGGL((k_label_gauss_mfma_lds<128, false>), dim3(G), dim3(BLOCK), lds, s, x, n, per_block, packed,
-                         hi, lo, K, z, hist, tot, flagged, n_flagged);
+#define DPMM_MFMA_LDS(DD, XX)                                                                             \
+  hipLaunchKernelGGL((k_label_gauss_mfma_lds<DD, XX>), dim3(G), dim3(BLOCK), lds, s, x, n, per_block, packed, \
+                     hi, lo, K, z, hist, tot, flagged, n_flagged)
+    if (d == 128 && x3) DPMM_MFMA_LDS(128, true);
+    else if (d == 128) DPMM_MFMA_LDS(128, false);
+    else if (x3) DPMM_MFMA_LDS(64, true);
+    else DPMM_MFMA_LDS(64, false);
+#undef DPMM_MFMA_LDS
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rescore_flagged, dim3(1024), dim3(RS_BLOCK), (size_t)d * RS_BLOCK * sizeof(float), s, x, d,
                        flagged, n_flagged, per_block, packed, K, t, seed, z, hist, tot);
