@@ -117,12 +117,75 @@ def run_form(torch, x, n, d, m, precision, steps, warmup, k_true):
         "phase_ms": {key: v / steps for key, v in ms.items()},
         "label_kernel_ms": ms["labels"] / steps,
         "stats_kernel_ms": ms["stats"] / steps,
-        "label_evals_per_s": n * (k_mean + 2) / (ms["labels"] / steps / 1e3),
+        "label_evals_per_s": n * k_mean / (ms["labels"] / steps / 1e3),
     }
     return S, z, zs, res
 
 
 AB_WORKLOAD = "gauss_d64"
+
+
+def label_step(args):
+    """Label-step throughput at a workload's true mixture: the statistics come
+    from the generating labels, nothing splits or merges (burn_out beyond the
+    run), and each timed iteration redraws the parameters and the labels."""
+    import torch
+    from paper_2204_08988_amd import datagen
+    from paper_2204_08988_amd.sampler import Sampler
+    name = args.label_step
+    spec = datagen.WORKLOADS[name]
+    gauss = isinstance(spec, datagen.GaussianSpec)
+    n = int(float(args.n)) if args.n else None
+    x_np, labels = datagen.workload(name, 5, n)
+    n, d = x_np.shape
+    K = int(labels.max()) + 1
+    x = torch.from_numpy(x_np).cuda()
+    del x_np
+    prec = args.precision if gauss and d in (32, 64, 128) else "fp32"  # matrix-core forms: d = 32, 64, 128
+    if gauss:
+        S = Sampler("gaussian", d, max(2 * K, 16), ALPHA, SEED, kappa=1.0, nu=d + 3.0, m=np.zeros(d), psi=np.eye(d),
+                    burn_out=10 ** 9, precision=prec)
+    else:
+        S = Sampler("multinomial", d, max(2 * K, 16), ALPHA, SEED, beta=np.ones(d), burn_out=10 ** 9)
+    z = torch.from_numpy(labels.astype(np.int32)).cuda()
+    zs = torch.from_numpy((np.arange(n) % 2).astype(np.uint8)).cuda()
+    S.set_state(K, [0] * K)
+    S.suffstats(x, z, zs)
+    ms = {"params": 0.0, "labels": 0.0, "sort": 0.0, "stats": 0.0, "splitmerge": 0.0}
+    for t in range(1, args.warmup + 1):
+        S.step(x, t, z, zs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.warmup + 1, args.warmup + args.steps + 1):
+        info = S.step(x, t, z, zs)
+        for key in ms:
+            ms[key] += info["ms_" + key]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = {k: v / args.steps for k, v in ms.items()}
+    lab_s = ms["labels"] / 1e3
+    evals = n * K / lab_s
+    fpe = flops_per_eval(d) if gauss else 2 * d  # multinomial: sum_v x_v log theta_kv
+    flops = n * K * fpe / lab_s
+    fused = d <= 4 or not gauss  # these label kernels also draw the sub-labels
+    bpp = 4 * d + 4 + (1 if fused else 0)  # x read, z (and zsub) written
+    hbm = bpp * n / lab_s
+    if prec == "fp32":
+        roof = {"bound": "alu", "achieved": flops / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                "frac": flops / PEAK_FP32_VALU}
+    else:
+        roof = {"bound": "mfma", "achieved": flops / 1e12, "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
+                "frac": flops / PEAK_BF16_MFMA}
+    roof.update({"hbm_achieved_GBs": hbm / 1e9, "hbm_frac": hbm / 8e12, "algorithmic_flops_per_eval": fpe,
+                 "hbm_bytes_per_point": bpp})
+    out = {"metric": "point-cluster evals/s in label step", "value": evals, "unit": "point-cluster evals/s",
+           "higher_is_better": True, "dtype": prec if gauss else "fp32 (int32 counts)",
+           "data": "synthetic",
+           "config": {"workload": f"{name}: N={n}, d={d}, {spec.k} true clusters at the generating mixture "
+                                  "(statistics from the true labels, no split or merge)", "n": n, "d": d, "K": K},
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "phase_ms": ms,
+           "label_kernel": roof}
+    print(json.dumps(out), flush=True)
 
 
 def run_chain(torch, x, n, d, m, iters, learned, train_every, train_until, train_steps, batch, lr):
@@ -208,6 +271,9 @@ def main():
     ap.add_argument("--only", action="store_true", help="time only the --precision form")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a device buffer of BYTES five times (calibrates HBM byte counters)")
+    ap.add_argument("--label-step", metavar="WORKLOAD",
+                    help="instead of the throughput line: label-step throughput at WORKLOAD's true mixture")
+    ap.add_argument("--n", default=None, help="points for --label-step (default: the workload's N)")
     ap.add_argument("--learned-ab", action="store_true",
                     help="instead of the throughput line: time to the plain chain's log-posterior plateau, "
                          "learned proposal vs plain, on the learned-proposal workload")
@@ -221,6 +287,9 @@ def main():
     args = ap.parse_args()
     if args.gpus == 1 and args.learned_ab:
         learned_ab(args)
+        return
+    if args.gpus == 1 and args.label_step:
+        label_step(args)
         return
     if args.copy_probe:
         import torch
@@ -260,7 +329,7 @@ def main():
     r = results[args.precision]
     label_s = r["label_kernel_ms"] / 1e3
     stats_s = r["stats_kernel_ms"] / 1e3
-    algo_label = n * (r["k_mean"] + 2) * flops_per_eval(d)
+    algo_label = n * r["k_mean"] * flops_per_eval(d)  # the cluster draw scores K clusters per point
     if args.precision == "fp32":
         label_roof = {"bound": "alu", "achieved": algo_label / label_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                       "unit": "TFLOP/s", "frac": algo_label / label_s / PEAK_FP32_VALU,

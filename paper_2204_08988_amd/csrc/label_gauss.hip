@@ -209,6 +209,66 @@ hipError_t launch_label_gauss(int d, const float* x, long long n, const float* p
   return hipGetLastError();
 }
 
+// d = 128, FP32: a workgroup walks its point range in chunks of BLOCK rows,
+// gathered coalesced into LDS columns (stride BLOCK + 1); each thread centres
+// its column in registers and scores the clusters with wave-uniform records.
+// The Gumbel-max runs as one streaming pass: cluster k's Gumbel is drawn only
+// while l_k + G_max can still beat the running best perturbed score, which
+// gives the argmax of l_k + g_k over all k with the same counter-based g_k.
+constexpr int COL_LD = BLOCK + 1;
+
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_label_gauss_z_col(const float* __restrict__ x, long long n,
+                                                             long long per_block, const float* __restrict__ packed,
+                                                             int K, uint32_t t, uint64_t seed, int* __restrict__ z,
+                                                             int* __restrict__ hist, int* __restrict__ tot) {
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  extern __shared__ float xs[];  // [D][COL_LD], then the histogram
+  int* h = reinterpret_cast<int*>(xs + D * COL_LD);
+  for (int k = threadIdx.x; k < K; k += BLOCK) h[k] = 0;
+  const long long begin = (long long)blockIdx.x * per_block;
+  const long long end = begin + per_block < n ? begin + per_block : n;
+  for (long long chunk = begin; chunk < end; chunk += BLOCK) {
+    const int rows = (int)(end - chunk < BLOCK ? end - chunk : BLOCK);
+    __syncthreads();  // the previous chunk's columns are read
+    for (int e = threadIdx.x; e < rows * D; e += BLOCK) {
+      const int r = e / D, c = e - r * D;
+      xs[c * COL_LD + r] = x[(size_t)(chunk + r) * D + c];
+    }
+    __syncthreads();
+    const int r = threadIdx.x;
+    if (r < rows) {
+      const long long i = chunk + r;
+      const float* xc = xs + r;
+      float best = -INFINITY;
+      int win = 0, cached = -1;
+      u32x4 blk{0u, 0u, 0u, 0u};
+      for (int k = 0; k < K; ++k) {
+        const float l = score_col<D, COL_LD>(packed + (size_t)k * S, xc);
+        if (l + GUMBEL_MAX_F > best) {
+          const int b = k >> 2;
+          if (b != cached) {
+            blk = rng_block(seed, t, (uint32_t)i, TAG_GUMBEL, (uint32_t)b);
+            cached = b;
+          }
+          const float v = l + gumbel_f(word_of(blk, k & 3));
+          if (v > best) {
+            best = v;
+            win = k;
+          }
+        }
+      }
+      z[i] = win;
+      atomicAdd(&h[win], 1);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += BLOCK) {
+    hist[(size_t)blockIdx.x * K + k] = h[k];
+    if (h[k]) atomicAdd(&tot[k], h[k]);
+  }
+}
+
 hipError_t launch_label_gauss_z(int d, const float* x, long long n, int G, long long per_block, const float* packed,
                                 int K, uint32_t t, uint64_t seed, int* z, int* hist, int* tot, hipStream_t s) {
   if (n == 0) return hipSuccess;
@@ -225,6 +285,18 @@ hipError_t launch_label_gauss_z(int d, const float* x, long long n, int G, long 
     DPMM_LABELZ_CASE(16)
     DPMM_LABELZ_CASE(32)
     DPMM_LABELZ_CASE(64)
+    case 128: {
+      static bool attr_set = false;
+      if (!attr_set) {  // the row block takes more than 64 KB of LDS
+        e = hipFuncSetAttribute((const void*)k_label_gauss_z_col<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+      }
+      hipLaunchKernelGGL(k_label_gauss_z_col<128>, dim3(G), dim3(BLOCK), (size_t)128 * COL_LD * sizeof(float) + lh, s,
+                         x, n, per_block, packed, K, t, seed, z, hist, tot);
+      break;
+    }
     default:
       hipLaunchKernelGGL(k_label_gauss_z_dyn, dim3(G), dim3(BLOCK), (size_t)d * BLOCK * sizeof(float) + lh, s, x, n,
                          d, per_block, packed, K, t, seed, z, hist, tot);

@@ -42,6 +42,26 @@ __device__ __forceinline__ float score_rec_dyn(const float* __restrict__ p, cons
   return fmaf(-0.5f, q, p[0]);
 }
 
+// FP32 score of a row stored as an LDS column (element j at xc[j * LDC]) under
+// the record p; the centred row is held in registers.  With a wave-uniform p
+// the record's loads are scalar.
+template <int D, int LDC>
+__device__ __forceinline__ float score_col(const float* __restrict__ p, const float* __restrict__ xc) {
+  float dx[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) dx[j] = xc[j * LDC] - p[4 + j];
+  const float* w = p + 4 + D;
+  float q = 0.0f;
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    float y = 0.0f;
+#pragma unroll
+    for (int c = 0; c <= r; ++c) y = fmaf(w[r * (r + 1) / 2 + c], dx[c], y);
+    q = fmaf(y, y, q);
+  }
+  return fmaf(-0.5f, q, p[0]);
+}
+
 struct Top2 {
   float m1, m2;
   int arg;

@@ -598,9 +598,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_labels_big(const float* __restric
     pending &= ~__ballot(mine);
   }
   if (!valid) return;
-  int zs;
-  zs = sub_label_draw(delta, seed, t, (uint32_t)i);
-  zsub[i] = (unsigned char)zs;
+  zsub[i] = (unsigned char)sub_label_draw(delta, seed, t, (uint32_t)i);
 }
 
 // Sub-labels (d = 64, SAMPLE) and statistics for d in {64, 128} over the
