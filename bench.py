@@ -34,7 +34,7 @@ PEAK_BF16_MFMA = 2.5e15    # dense BF16 matrix-core peak
 # HBM bytes per launch of the sorted sub-label/statistics kernel at this
 # workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a device copy of
 # known size (profiles/traffic_gauss_d32_n1e6.md); None once the kernel changes
-MEASURED_TRAFFIC = {"k_sub_stats_w<32,true>": 252.0e6}
+MEASURED_TRAFFIC = {"k_sub_stats_w<32,true>": None}
 
 
 def flops_per_eval(d):
@@ -341,7 +341,9 @@ def main():
                                 "(BF16 matrix-core cluster draw)"}
     label_roof["algorithmic_flops_per_eval"] = flops_per_eval(d)
     # sub-label draw + statistics over the cluster-sorted order: two FP32
-    # sub-cluster scores and the FP64 moments (sum x, upper triangle of x x^T)
+    # sub-cluster scores (VALU) and the FP64 moments (sum x, upper triangle of
+    # x x^T; FP64 matrix cores).  Both units peak at 78.6 TFLOP/s on this chip,
+    # so their summed flops over that peak bound the kernel from below.
     stats_flops = 2 * flops_per_eval(d) + d + d * (d + 1)
     stats_roof = {"bound": "alu", "achieved": n * stats_flops / stats_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                   "unit": "TFLOP/s", "frac": n * stats_flops / stats_s / PEAK_FP32_VALU,

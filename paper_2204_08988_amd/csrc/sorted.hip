@@ -24,6 +24,7 @@ using score::BLOCK;
 using score::score_rec;
 using score::score_rec_dyn;
 constexpr int IPT_MAX = 9;  // 2x2 work items per lane for d <= 128
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
 
 __device__ __forceinline__ int block_inclusive_scan(int v, int* buf) {
   const int tid = threadIdx.x;
@@ -338,124 +339,131 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
   flush();
 }
 
-// Wave-independent variant for D in {8, 16, 32}: each wave walks its own
+// Wave-independent kernel for D in {8, 16, 32}: each wave walks its own
 // contiguous range of sorted rows in chunks of 64 (one row per lane), with no
-// workgroup barriers.  The chunk's segments are found with ballots (rows are
-// sorted by z, so each cluster is a run of lanes); for every segment the wave
-// loops over its rows with a wave-uniform row index, and lane j accumulates
-// the 4x4 block (I, J) of sum x x^T (or a group of four entries of sum x)
-// from broadcast LDS reads.  The current cluster's two segments are carried
-// across chunks and flushed with global atomics when the cluster changes.
+// workgroup barriers.  Per chunk:
+//   (1) sub-cluster scores: for each run of lanes with the same cluster (rows
+//       are sorted by z, so a cluster is a run of lanes) every lane scores the
+//       run's two sub-cluster records; control flow stays wave-uniform, so the
+//       records are read with scalar loads, and each lane keeps the result of
+//       its own run;
+//   (2) each row is stored to LDS at its segment-sorted slot: within a run the
+//       left rows first, then the right rows;
+//   (3) per segment, four rows at a time, v_mfma_f64_16x16x4_f64 adds the
+//       16x16 blocks (I <= J) of sum x x^T (dimensions padded to a multiple
+//       of 16 with zeros); the same operands give sum x.
+// The current cluster's two segments are carried across chunks and flushed
+// with global atomics when the cluster changes or the range ends.
 template <int D, bool SAMPLE>
 __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__ x, long long n_sorted,
                                                        long long rows_per_wave, const int* __restrict__ perm,
                                                        const int* __restrict__ z, unsigned char* __restrict__ zsub,
-                                                       const float* __restrict__ packed, int k_max, uint32_t t,
+                                                       const float* __restrict__ packed, int K, int k_max, uint32_t t,
                                                        uint64_t seed, long long* __restrict__ counts,
                                                        double* __restrict__ moments) {
+  constexpr int NB = (D + 15) / 16;  // 16-wide blocks of dimensions
+  constexpr int NBLK = NB * (NB + 1) / 2;
   constexpr int LDW = D + 1;  // odd row stride
-  constexpr int HB = D / 4;
-  constexpr int N_TRI = HB * (HB + 1) / 2;
-  constexpr int N_ITEMS = N_TRI + HB;
-  static_assert(N_ITEMS <= 64, "one 4x4 item per lane");
   constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
   constexpr int E = D + D * (D + 1) / 2;
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float* xs = lds + wave * 64 * LDW;
-  // this lane's item
-  int I = -1, J = -1;
-  if (lane < N_TRI) {
-    int u = lane, a = 0;
-    while (u >= HB - a) {
-      u -= HB - a;
-      ++a;
-    }
-    I = a;
-    J = a + u;
-  } else if (lane < N_ITEMS) {
-    I = lane - N_TRI;
-    J = -2;
-  }
-  double aL[16], aR[16];
-  long long cL = 0, cR = 0;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int col = lane & 15;
+  f64x4 cL[NBLK], cR[NBLK];
+  double sL[NB], sR[NB];
+  long long nL = 0, nR = 0;
   int cur_k = -1;
+  auto zero_acc = [&]() {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) aL[q] = aR[q] = 0.0;
-  auto flush_one = [&](double (&acc)[16], long long cnt, int seg) {
-    if (cnt == 0) return;
+    for (int b = 0; b < NBLK; ++b) cL[b] = cR[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int b = 0; b < NB; ++b) sL[b] = sR[b] = 0.0;
+    nL = nR = 0;
+  };
+  // lane l holds element j of block (I, J) at row 16 I + l / 16 + 4 j, column 16 J + l % 16
+  auto flush_one = [&](f64x4 (&c)[NBLK], double (&sx)[NB], long long cnt, int seg) {
     double* M = moments + (size_t)seg * E;
-    if (J == -2) {
+    int blk = 0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) atomicAdd(&M[4 * I + u], acc[u]);
-    } else if (I >= 0) {
+    for (int I = 0; I < NB; ++I)
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int J = I; J < NB; ++J, ++blk)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int a = 4 * I + u, b = 4 * J + v;
-          if (a <= b) atomicAdd(&M[D + a * D - (a * (a - 1)) / 2 + (b - a)], acc[4 * u + v]);
+        for (int j = 0; j < 4; ++j) {
+          const int a = 16 * I + (lane >> 4) + 4 * j, b = 16 * J + col;
+          if (a <= b && b < D) atomicAdd(&M[D + a * D - (a * (a - 1)) / 2 + (b - a)], c[blk][j]);
         }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      double v = sx[b];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (lane < 16 && 16 * b + lane < D) atomicAdd(&M[16 * b + lane], v);
     }
     if (lane == 0) atomicAdd((unsigned long long*)&counts[seg], (unsigned long long)cnt);
   };
-  auto accumulate = [&](double (&acc)[16], unsigned long long mask) {
-    while (mask) {
-      const int rr = __ffsll((long long)mask) - 1;
-      mask &= mask - 1;
-      const float* row = xs + rr * LDW;
-      if (J == -2) {
+  auto flush = [&]() {
+    if (cur_k < 0) return;
+    if (nL) flush_one(cL, sL, nL, 2 * cur_k);
+    if (nR) flush_one(cR, sR, nR, 2 * cur_k + 1);
+  };
+  // rows [s0, e0) of the wave's LDS tile, four at a time: A = B = the rows' block of dimensions
+  auto mfma_rows = [&](f64x4 (&c)[NBLK], double (&sx)[NB], int s0, int e0) {
+    for (int g = s0; g < e0; g += 4) {
+      const int rr = g + (lane >> 4);
+      const bool ok = rr < e0;
+      double a[NB];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] += (double)row[4 * I + u];
-      } else if (I >= 0) {
-        double av[4], bv[4];
+      for (int b = 0; b < NB; ++b) a[b] = (ok && 16 * b + col < D) ? (double)xs[rr * LDW + 16 * b + col] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          av[u] = row[4 * I + u];
-          bv[u] = row[4 * J + u];
-        }
+      for (int b = 0; b < NB; ++b) sx[b] += a[b];
+      int blk = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+      for (int I = 0; I < NB; ++I)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[4 * u + v] = fma(av[u], bv[v], acc[4 * u + v]);
-      }
+        for (int J = I; J < NB; ++J, ++blk) c[blk] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], a[J], c[blk], 0, 0, 0);
     }
   };
+  zero_acc();
   const long long gw = (long long)blockIdx.x * (BLOCK / 64) + wave;
   const long long w_begin = gw * rows_per_wave;
   const long long w_end = w_begin + rows_per_wave < n_sorted ? w_begin + rows_per_wave : n_sorted;
   for (long long c0 = w_begin; c0 < w_end; c0 += 64) {
     const long long r = c0 + lane;
-    const bool valid = r < w_end;
+    bool valid = r < w_end;
     long long i = 0;
     int k = -1;
     float xv[D];
     if (valid) {
       i = perm[r];
-      k = z[i];
+      // a label outside [0, K) leaves its row out (and never reaches memory)
+      valid = (unsigned long long)i < (unsigned long long)n_sorted;
+      if (valid) k = z[i];
+      valid = valid && (unsigned)k < (unsigned)K;
+    }
+    if (valid) {
 #pragma unroll
       for (int j = 0; j < D; ++j) xv[j] = x[i * D + j];
     } else {
+      i = 0;
 #pragma unroll
       for (int j = 0; j < D; ++j) xv[j] = 0.0f;
     }
-    // the previous chunk's reads of xs are done: same wave, in order
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int j = 0; j < D; ++j) xs[lane * LDW + j] = xv[j];
+    // ---- (1) sub-labels
     int zs = 0;
     if (SAMPLE) {
       float delta = 0.0f;
-      unsigned long long pending = __ballot(valid);
-      while (pending) {
-        const int lane0 = __ffsll((long long)pending) - 1;
-        const int kk = __shfl(k, lane0);
+      unsigned long long pend = __ballot(valid);
+      while (pend) {
+        const int lane0 = __ffsll((long long)pend) - 1;
+        const int kk = __builtin_amdgcn_readlane(k, lane0);
         const bool mine = valid && k == kk;
-        if (mine) {
-          const float* ps = packed + (size_t)(k_max + 2 * kk) * S;
-          delta = score_rec<D>(ps, xv) - score_rec<D>(ps + S, xv);
-        }
-        pending &= ~__ballot(mine);
+        const float* ps = packed + (size_t)(k_max + 2 * kk) * S;
+        const float dl = score_rec<D>(ps, xv) - score_rec<D>(ps + S, xv);
+        if (mine) delta = dl;
+        pend &= ~__ballot(mine);
       }
       if (valid) {
         zs = sub_label_draw(delta, seed, t, (uint32_t)i);
@@ -464,37 +472,48 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
     } else if (valid) {
       zs = zsub[i] ? 1 : 0;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // ---- (2) segment-sorted slot of each row
     const unsigned long long right = __ballot(valid && zs == 1);
+    int pos = 0;
     unsigned long long rem = __ballot(valid);
     while (rem) {
       const int lane0 = __ffsll((long long)rem) - 1;
-      const int kk = __shfl(k, lane0);
+      const int kk = __builtin_amdgcn_readlane(k, lane0);
+      const bool mine = valid && k == kk;
+      const unsigned long long mk = __ballot(mine);
+      const unsigned long long mR = mk & right, mL = mk & ~right;
+      if (mine) pos = lane0 + (zs ? __popcll(mL) + __popcll(mR & below) : __popcll(mL & below));
+      rem &= ~mk;
+    }
+    // the previous chunk's reads of xs are done: same wave, in order
+    __builtin_amdgcn_wave_barrier();
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) xs[pos * LDW + j] = xv[j];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // ---- (3) each run's two segments into the running sums
+    rem = __ballot(valid);
+    while (rem) {
+      const int lane0 = __ffsll((long long)rem) - 1;
+      const int kk = __builtin_amdgcn_readlane(k, lane0);
       const unsigned long long mk = __ballot(valid && k == kk);
       if (kk != cur_k) {
-        if (cur_k >= 0) {
-          flush_one(aL, cL, 2 * cur_k);
-          flush_one(aR, cR, 2 * cur_k + 1);
-        }
-#pragma unroll
-        for (int q = 0; q < 16; ++q) aL[q] = aR[q] = 0.0;
-        cL = cR = 0;
+        flush();
+        zero_acc();
         cur_k = kk;
       }
-      const unsigned long long mR = mk & right, mL = mk & ~right;
-      cL += __popcll(mL);
-      cR += __popcll(mR);
-      accumulate(aL, mL);
-      accumulate(aR, mR);
+      const int cl = __popcll(mk & ~right), cr = __popcll(mk & right);
+      nL += cl;
+      nR += cr;
+      mfma_rows(cL, sL, lane0, lane0 + cl);
+      mfma_rows(cR, sR, lane0 + cl, lane0 + cl + cr);
       rem &= ~mk;
     }
   }
-  if (cur_k >= 0) {
-    flush_one(aL, cL, 2 * cur_k);
-    flush_one(aR, cR, 2 * cur_k + 1);
-  }
+  flush();
 }
 
 namespace {
@@ -529,7 +548,6 @@ size_t sub_stats_lds(int d, int TR, bool generic) {
   return b;
 }
 
-typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
 
 // FP32 score c - 1/2 |W (x - mu)|^2 of a row held in LDS under the record p
 // (wave-uniform: its loads are scalar); the centred row lives in registers.
@@ -892,10 +910,10 @@ hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, con
   case DD:                                                                                                    \
     if (sample)                                                                                               \
       hipLaunchKernelGGL((k_sub_stats_w<DD, true>), dim3(grid), dim3(BLOCK), lds, s, x, n, rpw, perm, z, zsub, \
-                         packed, k_max, t, seed, counts, moments);                                            \
+                         packed, K, k_max, t, seed, counts, moments);                                         \
     else                                                                                                      \
       hipLaunchKernelGGL((k_sub_stats_w<DD, false>), dim3(grid), dim3(BLOCK), lds, s, x, n, rpw, perm, z,     \
-                         zsub, packed, k_max, t, seed, counts, moments);                                      \
+                         zsub, packed, K, k_max, t, seed, counts, moments);                                   \
     break;
     switch (d) {
       DPMM_SUBW_CASE(8)
