@@ -23,6 +23,9 @@ COMMON = [
     # packed FP32 instructions stay off: they are not used by this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # matrix-core accumulators in ordinary VGPRs (the epilogues read them with
+    # VALU instructions; no accvgpr moves), AGPRs only as overflow
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-I", os.path.join(ROOT, "include"),
 ]
 
