@@ -337,7 +337,7 @@ def main():
     else:
         label_roof = {"bound": "mfma", "achieved": algo_label / label_s / 1e12, "peak": PEAK_BF16_MFMA / 1e12,
                       "unit": "TFLOP/s", "frac": algo_label / label_s / PEAK_BF16_MFMA,
-                      "kernel": f"k_label_gauss_mfma<32,{'true' if args.precision == 'bf16x3' else 'false'}> "
+                      "kernel": f"k_label_gauss_mfma32<{'true' if args.precision == 'bf16x3' else 'false'}> "
                                 "(BF16 matrix-core cluster draw)"}
     label_roof["algorithmic_flops_per_eval"] = flops_per_eval(d)
     # sub-label draw + statistics over the cluster-sorted order: two FP32

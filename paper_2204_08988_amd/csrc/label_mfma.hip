@@ -14,8 +14,9 @@
 //
 // Precision guard: if the runner-up is within the Gumbel range of the leader,
 // widened by an allowance for the BF16 rounding of both scores, the point is
-// re-scored in FP32 on the vector ALUs and drawn exactly as the FP32 kernel
-// draws it; otherwise no other cluster can win and the leader is the label.
+// deferred to k_rescore_flagged, which re-scores it in FP32 on the vector ALUs
+// and draws it exactly as the FP32 kernel draws it; otherwise no other cluster
+// can win and the leader is the label.
 #include "kernels.hpp"
 #include "score.hpp"
 
@@ -33,115 +34,152 @@ constexpr float BF16_TOL_REL = 1.0f / 32.0f;
 constexpr float BF16X3_TOL_REL = 1.0f / 4096.0f;
 constexpr float TOL_ABS = 0.05f;
 
-template <int D, bool X3>
-__global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma(const float* __restrict__ x, long long n,
-                                                            long long per_block, const float* __restrict__ packed,
-                                                            const bf16x8* __restrict__ whi,
-                                                            const bf16x8* __restrict__ wlo, int K, uint32_t t,
-                                                            uint64_t seed, int* __restrict__ z,
-                                                            int* __restrict__ hist, int* __restrict__ tot) {
+constexpr int BLOCK32 = 512;  // threads per workgroup of the d = 32 kernel
+
+// d = 32: the whitener fragments, means and constants of a group of up to CG
+// clusters are staged in LDS once and shared by the workgroup's eight waves
+// (when K <= CG, once per workgroup).  A wave scores 64 points (two 32-point
+// tiles) against each cluster of the group: the per-cluster centring in FP32,
+// the BF16 B operand, v_mfma_f32_32x32x16_bf16 with the W_k fragment as A, and
+// the squared norm; the top-2 update is branch-free so that two clusters'
+// work interleaves.  Points whose top-2 gap leaves any doubt are appended to
+// `flagged` (z = -1, not in the histogram) for k_rescore_flagged.
+template <bool X3>
+__global__ __launch_bounds__(BLOCK32) void k_label_gauss_mfma32(const float* __restrict__ x, long long n,
+                                                                long long per_block, const float* __restrict__ packed,
+                                                                const bf16x8* __restrict__ whi,
+                                                                const bf16x8* __restrict__ wlo, int K,
+                                                                int* __restrict__ z, int* __restrict__ hist,
+                                                                int* __restrict__ tot, int* __restrict__ flagged,
+                                                                int* __restrict__ n_flagged) {
+  constexpr int D = 32, KS = 2, NF = KS * 64;  // 16-byte fragments per cluster and table
+  constexpr int NB = X3 ? 2 : 1;               // tables per cluster (hi, lo)
+  constexpr int CG = X3 ? 16 : 32;             // clusters per LDS stage (64 KB of fragments)
+  constexpr int MUS = D + 4;                   // mu[D], c, padding
   constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
-  constexpr int MT = D / 32, KS = D / 16;
-  extern __shared__ int h[];
-  for (int k = threadIdx.x; k < K; k += BLOCK) h[k] = 0;
-  __syncthreads();
+  extern __shared__ __align__(16) unsigned char smem[];
+  bf16x8* s_w = reinterpret_cast<bf16x8*>(smem);              // [CG][NB][NF]
+  float* s_mu = reinterpret_cast<float*>(s_w + CG * NB * NF);  // [CG][MUS]
+  int* h = reinterpret_cast<int*>(s_mu + CG * MUS);            // [K]
+  for (int k = threadIdx.x; k < K; k += BLOCK32) h[k] = 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int half = lane >> 5, col = lane & 31;
+  const unsigned long long below = (1ull << lane) - 1ull;
   const long long begin = (long long)blockIdx.x * per_block;
   const long long end = begin + per_block < n ? begin + per_block : n;
-  for (long long base = begin + wave * 64; base < end; base += BLOCK) {
-    // this lane's k-slices of the two tiles' points: dims 16 ks + 8 half + q
+  auto stage = [&](int g0, int cnt) {
+    for (int e = threadIdx.x; e < cnt * NB * NF; e += BLOCK32) {
+      const int c = e / (NB * NF), r = e - c * (NB * NF);
+      const int tb = r / NF, f = r - tb * NF;
+      s_w[e] = (X3 && tb ? wlo : whi)[(size_t)(g0 + c) * NF + f];
+    }
+    for (int e = threadIdx.x; e < cnt * MUS; e += BLOCK32) {
+      const int c = e / MUS, j = e - c * MUS;
+      const float* rec = packed + (size_t)(g0 + c) * S;
+      s_mu[e] = j < D ? rec[4 + j] : (j == D ? rec[0] : 0.0f);
+    }
+  };
+  const bool single = K <= CG;
+  if (single && begin < end) stage(0, K);
+  __syncthreads();
+  for (long long chunk = begin; chunk < end; chunk += BLOCK32) {
+    const long long base = chunk + wave * 64;
     const long long pA = base + col, pB = base + 32 + col;
+    // this lane's k-slices of the two tiles' points: dims 16 ks + 8 half + q
     float xa[KS][8], xb[KS][8];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int j = 16 * ks + 8 * half + q;
-        xa[ks][q] = pA < end ? x[pA * D + j] : 0.0f;
-        xb[ks][q] = pB < end ? x[pB * D + j] : 0.0f;
-      }
+    for (int ks = 0; ks < KS; ++ks) {
+      const float4* ra = reinterpret_cast<const float4*>(x + pA * D + 16 * ks + 8 * half);
+      const float4* rb = reinterpret_cast<const float4*>(x + pB * D + 16 * ks + 8 * half);
+      const float4 a0 = pA < end ? ra[0] : float4{0.f, 0.f, 0.f, 0.f};
+      const float4 a1 = pA < end ? ra[1] : float4{0.f, 0.f, 0.f, 0.f};
+      const float4 b0 = pB < end ? rb[0] : float4{0.f, 0.f, 0.f, 0.f};
+      const float4 b1 = pB < end ? rb[1] : float4{0.f, 0.f, 0.f, 0.f};
+      xa[ks][0] = a0.x; xa[ks][1] = a0.y; xa[ks][2] = a0.z; xa[ks][3] = a0.w;
+      xa[ks][4] = a1.x; xa[ks][5] = a1.y; xa[ks][6] = a1.z; xa[ks][7] = a1.w;
+      xb[ks][0] = b0.x; xb[ks][1] = b0.y; xb[ks][2] = b0.z; xb[ks][3] = b0.w;
+      xb[ks][4] = b1.x; xb[ks][5] = b1.y; xb[ks][6] = b1.z; xb[ks][7] = b1.w;
+    }
     float m1 = -INFINITY, m2 = -INFINITY, q1 = 0.0f, q2 = 0.0f;
     int arg = 0;
-    for (int k = 0; k < K; ++k) {
-      const float* rec = packed + (size_t)k * S;
-      bf16x8 ba[KS], bb[KS], bal[KS], bbl[KS];
+    for (int g0 = 0; g0 < K; g0 += CG) {
+      const int cnt = K - g0 < CG ? K - g0 : CG;
+      if (!single) {
+        __syncthreads();  // every wave is done with the previous group
+        stage(g0, cnt);
+        __syncthreads();
+      }
+#pragma unroll 2
+      for (int c = 0; c < cnt; ++c) {
+        const bf16x8* cw = s_w + c * NB * NF;
+        const float* cmu = s_mu + c * MUS;
+        bf16x8 ba[KS], bb[KS], bal[KS], bbl[KS];
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
+        for (int ks = 0; ks < KS; ++ks) {
+          const float4 u0 = *reinterpret_cast<const float4*>(cmu + 16 * ks + 8 * half);
+          const float4 u1 = *reinterpret_cast<const float4*>(cmu + 16 * ks + 8 * half + 4);
+          const float mu[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const float mu = rec[4 + 16 * ks + 8 * half + q];
-          const float da = xa[ks][q] - mu, db = xb[ks][q] - mu;
-          ba[ks][q] = (__bf16)da;
-          bb[ks][q] = (__bf16)db;
-          if (X3) {
-            bal[ks][q] = (__bf16)(da - (float)ba[ks][q]);
-            bbl[ks][q] = (__bf16)(db - (float)bb[ks][q]);
+          for (int q = 0; q < 8; ++q) {
+            const float da = xa[ks][q] - mu[q], db = xb[ks][q] - mu[q];
+            ba[ks][q] = (__bf16)da;
+            bb[ks][q] = (__bf16)db;
+            if (X3) {
+              bal[ks][q] = (__bf16)(da - (float)ba[ks][q]);
+              bbl[ks][q] = (__bf16)(db - (float)bb[ks][q]);
+            }
           }
         }
-      float qa = 0.0f, qb = 0.0f;
-      const bf16x8* wk = whi + (size_t)k * MT * KS * 64;
-      const bf16x8* wkl = X3 ? wlo + (size_t)k * MT * KS * 64 : nullptr;
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
         f32x16 acca = {0}, accb = {0};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-          const bf16x8 a = wk[(mt * KS + ks) * 64 + lane];
-          acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, ba[ks], acca, 0, 0, 0);
-          accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb[ks], accb, 0, 0, 0);
+          const bf16x8 w = cw[ks * 64 + lane];
+          acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, ba[ks], acca, 0, 0, 0);
+          accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, bb[ks], accb, 0, 0, 0);
           if (X3) {
-            const bf16x8 al = wkl[(mt * KS + ks) * 64 + lane];
-            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, ba[ks], acca, 0, 0, 0);
-            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bb[ks], accb, 0, 0, 0);
-            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bal[ks], acca, 0, 0, 0);
-            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbl[ks], accb, 0, 0, 0);
+            const bf16x8 wl = cw[NF + ks * 64 + lane];
+            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, ba[ks], acca, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, bb[ks], accb, 0, 0, 0);
+            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, bal[ks], acca, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, bbl[ks], accb, 0, 0, 0);
           }
         }
+        float qa = 0.0f, qb = 0.0f;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           qa = fmaf(acca[r], acca[r], qa);
           qb = fmaf(accb[r], accb[r], qb);
         }
-      }
-      qa += __shfl_xor(qa, 32);
-      qb += __shfl_xor(qb, 32);
-      // lane l owns point base + l: tile A for l < 32, tile B for l >= 32
-      const float qm = half ? qb : qa;
-      const float l = fmaf(-0.5f, qm, rec[0]);
-      if (l > m1) {
-        m2 = m1;
-        q2 = q1;
-        m1 = l;
-        q1 = qm;
-        arg = k;
-      } else if (l > m2) {
-        m2 = l;
-        q2 = qm;
+        // lane l owns point base + l (tile A for l < 32, tile B for l >= 32):
+        // it keeps its own tile's half-sum and receives the partner's
+        const float qm = (half ? qb : qa) + __shfl_xor(half ? qa : qb, 32);
+        const float l = fmaf(-0.5f, qm, cmu[D]);
+        const bool gt1 = l > m1, gt2 = l > m2;
+        m2 = gt1 ? m1 : (gt2 ? l : m2);
+        q2 = gt1 ? q1 : (gt2 ? qm : q2);
+        m1 = gt1 ? l : m1;
+        q1 = gt1 ? qm : q1;
+        arg = gt1 ? g0 + c : arg;
       }
     }
     const long long p = base + lane;
     const bool valid = p < end;
     const float tol = (X3 ? BF16X3_TOL_REL : BF16_TOL_REL) * (q1 + q2) + TOL_ABS;
-    int zi = arg;
-    if (valid && m2 > m1 - RGAP - tol) {
-      // FP32 re-score of this point, then the FP32 lazy Gumbel-max
-      float xv[D];
-#pragma unroll
-      for (int j = 0; j < D; ++j) xv[j] = x[p * D + j];
-      Top2 f;
-      f.init();
-      for (int k = 0; k < K; ++k) f.push(score_rec<D>(packed + (size_t)k * S, xv), k);
-      zi = lazy_gumbel_max(f, K, (uint32_t)p, t, seed,
-                           [&](int k) { return score_rec<D>(packed + (size_t)k * S, xv); });
+    const bool doubt = valid && m2 > m1 - RGAP - tol;
+    const unsigned long long dm = __ballot(doubt);
+    if (dm) {
+      int slot0 = 0;
+      if (lane == __ffsll((long long)dm) - 1) slot0 = atomicAdd(n_flagged, __popcll(dm));
+      slot0 = __shfl(slot0, __ffsll((long long)dm) - 1);
+      if (doubt) flagged[slot0 + __popcll(dm & below)] = (int)p;
     }
     if (valid) {
-      z[p] = zi;
-      atomicAdd(&h[zi], 1);
+      z[p] = doubt ? -1 : arg;
+      if (!doubt) atomicAdd(&h[arg], 1);
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < K; k += BLOCK) {
+  for (int k = threadIdx.x; k < K; k += BLOCK32) {
     hist[(size_t)blockIdx.x * K + k] = h[k];
     if (h[k]) atomicAdd(&tot[k], h[k]);
   }
@@ -384,23 +422,22 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
   const size_t lh = (size_t)K * sizeof(int);
   const bf16x8* hi = (const bf16x8*)whi;
   const bf16x8* lo = (const bf16x8*)wlo;
+  e = launch_zero64(n_flagged, 1, s);
+  if (e != hipSuccess) return e;
+  static bool attr_set = false;
+  if (!attr_set) {  // more than 64 KB of dynamic LDS (160 KB per CU on gfx950)
+    const void* fns[6] = {(const void*)k_label_gauss_mfma_lds<128, true>, (const void*)k_label_gauss_mfma_lds<128, false>,
+                          (const void*)k_label_gauss_mfma_lds<64, true>,  (const void*)k_label_gauss_mfma_lds<64, false>,
+                          (const void*)k_label_gauss_mfma32<true>,        (const void*)k_label_gauss_mfma32<false>};
+    for (const void* f : fns) {
+      e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      if (e != hipSuccess) return e;
+    }
+    attr_set = true;
+  }
   if (d == 64 || d == 128) {
-    e = launch_zero64(n_flagged, 1, s);
-    if (e != hipSuccess) return e;
     const int NF = (d / 32) * (d / 16) * 64;
     const size_t lds = 2 * ((size_t)(x3 ? 2 : 1) * NF * sizeof(bf16x8) + (d + 4) * sizeof(float)) + lh;
-    static bool attr_set = false;
-    if (!attr_set) {  // more than 64 KB of dynamic LDS (160 KB per CU on gfx950)
-      const void* fns[4] = {(const void*)k_label_gauss_mfma_lds<128, true>,
-                            (const void*)k_label_gauss_mfma_lds<128, false>,
-                            (const void*)k_label_gauss_mfma_lds<64, true>,
-                            (const void*)k_label_gauss_mfma_lds<64, false>};
-      for (const void* f : fns) {
-        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-      }
-      attr_set = true;
-    }
 #define DPMM_MFMA_LDS(DD, XX)                                                                             \
   hipLaunchKernelGGL((k_label_gauss_mfma_lds<DD, XX>), dim3(G), dim3(BLOCK), lds, s, x, n, per_block, packed, \
                      hi, lo, K, z, hist, tot, flagged, n_flagged)
@@ -409,25 +446,21 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
     else if (x3) DPMM_MFMA_LDS(64, true);
     else DPMM_MFMA_LDS(64, false);
 #undef DPMM_MFMA_LDS
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rescore_flagged, dim3(1024), dim3(RS_BLOCK), (size_t)d * RS_BLOCK * sizeof(float), s, x, d,
-                       flagged, n_flagged, per_block, packed, K, t, seed, z, hist, tot);
-    return hipGetLastError();
-  }
-  if (d == 32 && !x3)
-    hipLaunchKernelGGL((k_label_gauss_mfma<32, false>), dim3(G), dim3(BLOCK), lh, s, x, n, per_block, packed, hi, lo, K,
-                       t, seed, z, hist, tot);
-  else if (d == 32)
-    hipLaunchKernelGGL((k_label_gauss_mfma<32, true>), dim3(G), dim3(BLOCK), lh, s, x, n, per_block, packed, hi, lo, K,
-                       t, seed, z, hist, tot);
-  else if (d == 64 && !x3)
-    hipLaunchKernelGGL((k_label_gauss_mfma<64, false>), dim3(G), dim3(BLOCK), lh, s, x, n, per_block, packed, hi, lo, K,
-                       t, seed, z, hist, tot);
-  else if (d == 64)
-    hipLaunchKernelGGL((k_label_gauss_mfma<64, true>), dim3(G), dim3(BLOCK), lh, s, x, n, per_block, packed, hi, lo, K,
-                       t, seed, z, hist, tot);
-  else
+  } else if (d == 32) {
+    // [CG][NB][NF] fragments (64 KB), [CG][d + 4] means and constants, the histogram
+    const size_t lds = (size_t)65536 + (size_t)(x3 ? 16 : 32) * (d + 4) * sizeof(float) + lh;
+    if (x3)
+      hipLaunchKernelGGL((k_label_gauss_mfma32<true>), dim3(G), dim3(BLOCK32), lds, s, x, n, per_block, packed, hi, lo,
+                         K, z, hist, tot, flagged, n_flagged);
+    else
+      hipLaunchKernelGGL((k_label_gauss_mfma32<false>), dim3(G), dim3(BLOCK32), lds, s, x, n, per_block, packed, hi,
+                         lo, K, z, hist, tot, flagged, n_flagged);
+  } else {
     return hipErrorInvalidValue;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rescore_flagged, dim3(1024), dim3(RS_BLOCK), (size_t)d * RS_BLOCK * sizeof(float), s, x, d,
+                     flagged, n_flagged, per_block, packed, K, t, seed, z, hist, tot);
   return hipGetLastError();
 }
 
