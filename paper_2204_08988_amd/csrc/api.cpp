@@ -676,11 +676,10 @@ dpmm_status dpmm_sample_params(dpmm_ctx* ctx, uint32_t t) {
                      ctx->d_log_pi, ctx->d_log_pisub, ctx->d_tmp);
   DPMM_HIP(ctx, hipGetLastError(), "weights kernel");
   if (ctx->gaussian()) {
-    hipLaunchKernelGGL(k_niw_draw, dim3(3 * K), dim3(256), niw_lds_bytes(ctx->d), ctx->stream, K, ctx->d,
-                       ctx->cfg.k_max, prior_dev(ctx), ctx->d_counts, ctx->d_moments, ctx->d_log_pi,
-                       ctx->d_log_pisub, ctx->cfg.seed, t, ctx->d_mu, ctx->d_sigma, ctx->d_scratch, ctx->d_packed,
-                       ctx->d_logdet, ctx->d_err);
-    DPMM_HIP(ctx, hipGetLastError(), "posterior draw kernel");
+    DPMM_HIP(ctx, launch_niw_draw(K, ctx->d, ctx->cfg.k_max, prior_dev(ctx), ctx->d_counts, ctx->d_moments,
+                                  ctx->d_log_pi, ctx->d_log_pisub, ctx->cfg.seed, t, ctx->d_mu, ctx->d_sigma,
+                                  ctx->d_scratch, ctx->d_packed, ctx->d_logdet, ctx->d_err, ctx->stream),
+             "posterior draw kernel");
     if (ctx->d_whi)
       DPMM_HIP(ctx, launch_pack_wfrag(K, ctx->d, ctx->cfg.k_max, ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->stream),
                "fragment pack kernel");

@@ -24,6 +24,11 @@ __global__ void k_niw_draw(int K, int d, int k_max, NiwPriorDev prior, const lon
                            const double* moments, const double* log_pi, const double* log_pisub,
                            uint64_t seed, uint32_t t, double* mu_out, double* sigma_out, double* scratch,
                            float* packed, double* logdet_out, int* err);
+// k_niw_draw, with one wave per component for d <= 64
+hipError_t launch_niw_draw(int K, int d, int k_max, NiwPriorDev prior, const long long* counts,
+                           const double* moments, const double* log_pi, const double* log_pisub, uint64_t seed,
+                           uint32_t t, double* mu_out, double* sigma_out, double* scratch, float* packed,
+                           double* logdet_out, int* err, hipStream_t s);
 __global__ void k_dir_draw(int K, int V, const double* beta, const long long* sums, uint64_t seed,
                            uint32_t t, double* log_theta);
 __global__ void k_pack_gauss(int K, int d, int k_max, const double* log_pi, const double* log_pisub,

@@ -231,6 +231,262 @@ __global__ void k_niw_draw(int K, int d, int k_max, NiwPriorDev prior, const lon
               logdet_out + e, err, &flag, red);
 }
 
+namespace {
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Keeps the compiler from hoisting the next rows' LDS reads above this point
+// (a whole triangle of broadcast reads in flight would not fit in registers).
+__device__ __forceinline__ void issue_fence() { __asm__ volatile("" ::: "memory"); }
+
+// LDS writes of one lane made visible to the wave's other lanes
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 1 / sqrt(s) from the hardware estimate and two Newton steps (within an ulp
+// or two of the correctly rounded value)
+__device__ __forceinline__ double rsqrt_refined(double s) {
+  double y = __builtin_amdgcn_rsq(s);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-s * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+// Right-looking Cholesky of the matrix whose row `lane` is r (D x D): the
+// pivot comes by v_readlane, the scaled column j is broadcast through `col`
+// (LDS, D doubles) for the trailing update a_ik -= a_ij a_kj.  Afterwards r is
+// row `lane` of L (zero above the diagonal) and diag its pivot.  A pivot that
+// is not positive and finite is replaced by 1 and reported by the
+// (wave-uniform) return value.  Entries right of the diagonal are scratch
+// during the loop and are cleared at the end.
+template <int D>
+__device__ __forceinline__ bool wave_cholesky(double (&r)[D], int lane, double& diag, double* col) {
+  bool ok = true;
+  diag = 1.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double s = readlane_d(r[j], j);
+    if (!(s > 0.0) || !isfinite(s)) {
+      ok = false;
+      s = 1.0;
+    }
+    const double inv = rsqrt_refined(s), ljj = s * inv;
+    if (lane == j) diag = ljj;
+    r[j] = lane == j ? ljj : r[j] * inv;
+    if (j + 1 < D) {
+      // (a wave's LDS operations complete in order: the next step's write
+      // cannot overtake these reads)
+      if (lane < D) col[lane] = r[j];
+      wave_sync();
+#pragma unroll
+      for (int k = j + 1; k < D; ++k) r[k] = fma(-r[j], col[k], r[k]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+    if (j > lane) r[j] = 0.0;
+  return ok;
+}
+
+}  // namespace
+
+// k_niw_draw for d <= D (D in {16, 32, 64}) with two waves per component and
+// a single workgroup barrier.  Wave 0 owns the matrices: lane i holds row i of
+// each d x d matrix of the draw, padded to D rows with an identity block
+// (pivots 1, no coupling to the d x d block), in registers; pivots travel by
+// v_readlane and broadcast columns and rows through LDS.  Wave 1 meanwhile
+// draws the Bartlett factor, its diagonal reciprocals and the mean's normals
+// into LDS.  The random draws are those of k_niw_draw; the float64 arithmetic
+// follows it except for the pivots (refined reciprocal square roots), the
+// reciprocals taken ahead of the triangular solves and the order of the sums
+// in Sigma = F F^T and log|Sigma|.
+template <int D>
+__global__ __launch_bounds__(128) void k_niw_draw_wave(int K, int d, int k_max, NiwPriorDev prior,
+                                                       const long long* __restrict__ counts,
+                                                       const double* __restrict__ moments,
+                                                       const double* __restrict__ log_pi,
+                                                       const double* __restrict__ log_pisub, uint64_t seed,
+                                                       uint32_t t, double* __restrict__ mu_out,
+                                                       double* __restrict__ sigma_out, float* __restrict__ packed,
+                                                       double* __restrict__ logdet_out, int* __restrict__ err) {
+  constexpr int LD = D + 1;
+  __shared__ double sm[D * LD];  // Bartlett factor A, then F, then G
+  __shared__ double col[D];      // Cholesky column broadcast
+  __shared__ double rdiag[D];    // 1 / A[j][j], then 1 / G[j][j]
+  __shared__ double seps[D];     // the mean's normals
+  const int e = blockIdx.x;
+  if (e >= 3 * K) return;
+  const int k = e / 3, c = e % 3;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool live = lane < d;
+  const int E = d + d * (d + 1) / 2;
+  const int s0 = c == 0 ? 2 * k : 2 * k + (c - 1);
+  const int s1 = c == 0 ? 2 * k + 1 : -1;
+  const double n = (double)counts[s0] + (s1 >= 0 ? (double)counts[s1] : 0.0);
+  const double kn = prior.kappa + n, nun = prior.nu + n;
+  const int nq_off = d * (d - 1) / 2;
+  if (wave == 1) {
+    // Bartlett factor A (lower): A[i][j] ~ N(0,1) for i > j,
+    // A[i][i] = sqrt(chi2(nu_n - i)); identity in the padding
+    if (lane < D)
+      for (int row = 0; row < D; ++row) sm[row * LD + lane] = row == lane ? 1.0 : 0.0;
+    wave_sync();
+    for (int q = lane; q < nq_off; q += 64) {
+      int i = (int)((1.0 + sqrt(1.0 + 8.0 * (double)q)) * 0.5);  // q = i (i - 1) / 2 + j, 0 <= j < i
+      while (i * (i - 1) / 2 > q) --i;
+      while ((i + 1) * i / 2 <= q) ++i;
+      const int j = q - i * (i - 1) / 2;
+      sm[i * LD + j] = normal_draw(seed, t, (uint32_t)e, TAG_NIW, (uint32_t)q);
+    }
+    double a = 1.0;
+    if (live) {
+      const double lg =
+          log_gamma_draw(seed, t, (uint32_t)e, TAG_NIW, (uint32_t)(nq_off + lane), 0.5 * (nun - lane));
+      a = exp(0.5 * (0.69314718055994531 + lg));
+      sm[lane * LD + lane] = a;
+    }
+    if (lane < D) {
+      rdiag[lane] = 1.0 / a;
+      seps[lane] = live ? normal_draw(seed, t, (uint32_t)e, TAG_NIW, (uint32_t)(nq_off + d + lane)) : 0.0;
+    }
+  }
+  double r[D];
+  double diag = 1.0, mu_i = 0.0;
+  if (wave == 0) {
+    const double* M0 = moments + (size_t)s0 * E;
+    const double* M1 = s1 >= 0 ? moments + (size_t)s1 * E : M0;
+    double si = 0.0, mi = 0.0;
+    if (live) {
+      si = M0[lane] + (s1 >= 0 ? M1[lane] : 0.0);
+      mi = prior.m[lane];
+    }
+    const double mni = (prior.kappa * mi + si) / kn;
+    const double xi = n > 0.0 ? si / n : 0.0;
+    const double cm = prior.kappa * n / kn;
+    // row of Psi_n = Psi + C + (kappa n / kappa_n)(xbar - m)(xbar - m)^T; the
+    // loads of a group of 16 columns are issued together
+#pragma unroll
+    for (int j0 = 0; j0 < D; j0 += 16) {
+      issue_fence();
+#pragma unroll
+      for (int j = j0; j < j0 + 16; ++j) {
+        const double xj = readlane_d(xi, j), mj = readlane_d(mi, j);
+        const bool in = live && j < d;
+        const int a = lane < j ? lane : j, b = lane < j ? j : lane;
+        const int ti = in ? d + tri_index(a, b, d) : 0;
+        const double S = M0[ti] + (s1 >= 0 ? M1[ti] : 0.0);
+        const double ps = prior.psi[in ? lane * d + j : 0];
+        const double v = n > 0.0 ? ps + ((S - n * xi * xj) + cm * (xi - mi) * (xj - mj)) : ps;
+        r[j] = in ? v : (j == lane ? 1.0 : 0.0);
+      }
+    }
+    if (!wave_cholesky<D>(r, lane, diag, col) && lane == 0) atomicOr(err, 1);
+    __syncthreads();
+    // F = L A^-T, row by row: F[i][j] *= 1 / A[j][j], then F[i][q] -= F[i][j] A[q][j] (q > j)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      issue_fence();
+      r[j] *= rdiag[j];
+#pragma unroll
+      for (int q = j + 1; q < D; ++q) r[q] = fma(-r[j], sm[q * LD + j], r[q]);
+    }
+    // mu = m_n + F eps / sqrt(kappa_n)
+    {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) acc = fma(r[q], seps[q], acc);
+      mu_i = mni + acc * (1.0 / sqrt(kn));
+      if (live) mu_out[(size_t)e * d + lane] = mu_i;
+    }
+    // Sigma = F F^T: row `lane` against every row of F (in LDS), four rows at a time
+    wave_sync();
+    if (lane < D) {
+#pragma unroll
+      for (int q = 0; q < D; ++q) sm[lane * LD + q] = r[q];
+    }
+    wave_sync();
+    double* sig = sigma_out + (size_t)e * d * d;
+    for (int j = 0; j < d; j += 4) {
+      issue_fence();
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      const int j1 = j + 1 < D ? j + 1 : j, j2 = j + 2 < D ? j + 2 : j, j3 = j + 3 < D ? j + 3 : j;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        a0 = fma(r[q], sm[j * LD + q], a0);
+        a1 = fma(r[q], sm[j1 * LD + q], a1);
+        a2 = fma(r[q], sm[j2 * LD + q], a2);
+        a3 = fma(r[q], sm[j3 * LD + q], a3);
+      }
+      if (live) {
+        sig[lane * d + j] = a0;
+        if (j + 1 < d) sig[lane * d + j + 1] = a1;
+        if (j + 2 < d) sig[lane * d + j + 2] = a2;
+        if (j + 3 < d) sig[lane * d + j + 3] = a3;
+      }
+    }
+    // the scoring record: Sigma = G G^T, W = G^-1, log|Sigma|
+#pragma unroll
+    for (int j = 0; j < D; ++j) r[j] = (live && j < d) ? sig[lane * d + j] : (j == lane ? 1.0 : 0.0);
+    if (!wave_cholesky<D>(r, lane, diag, col) && lane == 0) atomicOr(err, 2);
+    wave_sync();
+    if (lane < D) {
+#pragma unroll
+      for (int q = 0; q < D; ++q) sm[lane * LD + q] = r[q];
+      rdiag[lane] = 1.0 / diag;
+    }
+    wave_sync();
+    // W = G^-1 by columns: lane c owns column c and runs the forward
+    // substitution w[r] = (delta_rc - sum_{k<r} G[r][k] w[k]) / G[r][r] with the
+    // rows of G read as LDS broadcasts (w[k] = 0 for k < c adds nothing)
+#pragma unroll
+    for (int rr = 0; rr < D; ++rr) {
+      issue_fence();
+      double acc = rr == lane ? 1.0 : 0.0;
+#pragma unroll
+      for (int kk = 0; kk < rr; ++kk) acc = fma(-sm[rr * LD + kk], r[kk], acc);
+      r[rr] = acc * rdiag[rr];
+    }
+  } else {
+    __syncthreads();
+  }
+  if (wave != 0) return;
+  const double ld = 2.0 * wave_sum(live ? log(diag) : 0.0);
+  const double lw = c == 0 ? log_pi[k] : log_pisub[2 * k + (c - 1)];
+  const int stride = gauss_rec_stride(d);
+  float* rec = packed + (size_t)record_slot(k, c, k_max) * stride;
+  if (lane == 0) {
+    rec[0] = (float)(lw - 0.5 * ld - 0.5 * d * 1.8378770664093453);
+    rec[1] = rec[2] = rec[3] = 0.0f;
+    logdet_out[e] = ld;
+  }
+  if (live) {
+    rec[4 + lane] = (float)mu_i;
+    // column `lane` of W: W[i][lane] for lane <= i < d
+    float* wc = rec + 4 + d + lane;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+      if (i >= lane && i < d) wc[i * (i + 1) / 2] = (float)r[i];
+  }
+  for (int idx = 4 + d + d * (d + 1) / 2 + lane; idx < stride; idx += 64) rec[idx] = 0.0f;
+}
+
 // One workgroup per component: log theta ~ log Dir(beta + c).
 __global__ void k_dir_draw(int K, int V, const double* __restrict__ beta,
                            const long long* __restrict__ sums, uint64_t seed, uint32_t t,
@@ -296,6 +552,27 @@ __global__ void k_pack_mult(int K, int V, int k_max, const double* __restrict__ 
   }
   for (int v = threadIdx.x; v < V; v += blockDim.x) rec[4 + v] = (float)log_theta[(size_t)e * V + v];
   for (int idx = 4 + V + threadIdx.x; idx < stride; idx += blockDim.x) rec[idx] = 0.0f;
+}
+
+hipError_t launch_niw_draw(int K, int d, int k_max, NiwPriorDev prior, const long long* counts,
+                           const double* moments, const double* log_pi, const double* log_pisub, uint64_t seed,
+                           uint32_t t, double* mu_out, double* sigma_out, double* scratch, float* packed,
+                           double* logdet_out, int* err, hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+#define DPMM_NIW_WAVE(DD)                                                                                    \
+  hipLaunchKernelGGL(k_niw_draw_wave<DD>, dim3(3 * K), dim3(128), 0, s, K, d, k_max, prior, counts, moments,  \
+                     log_pi, log_pisub, seed, t, mu_out, sigma_out, packed, logdet_out, err)
+  if (d <= 16)
+    DPMM_NIW_WAVE(16);
+  else if (d <= 32)
+    DPMM_NIW_WAVE(32);
+  else if (d <= 64)
+    DPMM_NIW_WAVE(64);
+  else
+    hipLaunchKernelGGL(k_niw_draw, dim3(3 * K), dim3(256), niw_lds_bytes(d), s, K, d, k_max, prior, counts, moments,
+                       log_pi, log_pisub, seed, t, mu_out, sigma_out, scratch, packed, logdet_out, err);
+#undef DPMM_NIW_WAVE
+  return hipGetLastError();
 }
 
 }  // namespace dpmm
