@@ -12,9 +12,12 @@
 //   k_init_labels  the one-cluster initial state.
 // The O(K^2) accept/reject bookkeeping runs on the host from these values.
 #include "kernels.hpp"
+#include "wave64.hpp"
 #include "linalg.hpp"
 
 namespace dpmm {
+
+using namespace wave64;
 
 namespace {
 
@@ -95,32 +98,20 @@ __global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, 
   }
 }
 
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
 // One wave per item, D >= d rows padded with an identity block (whose
 // pivots are 1 and add nothing to log|Psi_n|).  Lane i builds row i of Psi_n
-// (entries k <= i) and the right-looking Cholesky broadcasts column j with
-// v_readlane: no LDS and no barrier.  Entries above the diagonal start at 0
-// and stay 0 under the unmasked updates.
+// (entries k <= i; the loads of 16 columns at a time are issued together) and
+// factors it with the wave Cholesky (pivots by v_readlane, columns broadcast
+// through a per-wave LDS buffer): no workgroup barrier.
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const LogmlItem* __restrict__ items, int d,
                                                             NiwPriorDev prior, double logdet_psi,
                                                             const long long* __restrict__ counts,
                                                             const double* __restrict__ moments,
                                                             double* __restrict__ out, int* __restrict__ err) {
-  const int lane = threadIdx.x & 63;
-  const int it = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+  __shared__ double cols[BLOCK / 64][D];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int it = blockIdx.x * (BLOCK / 64) + wave;
   if (it >= n_items) return;
   const int E = d + d * (d + 1) / 2;
   const LogmlItem item = items[it];
@@ -133,40 +124,38 @@ __global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const L
   }
   const double kn = prior.kappa + n, nun = prior.nu + n, cm = prior.kappa * n / kn;
   const bool live = lane < d;
+  // the item's segments (unused slots read segment 0 with weight 0)
+  const double* Mq[4];
+  double wq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    wq[q] = item.seg[q] >= 0 ? 1.0 : 0.0;
+    Mq[q] = moments + (size_t)(item.seg[q] >= 0 ? item.seg[q] : 0) * E;
+  }
   double si = 0.0;
   for (int q = 0; q < 4; ++q)
-    if (item.seg[q] >= 0 && live) si += moments[(size_t)item.seg[q] * E + lane];
+    if (item.seg[q] >= 0 && live) si += Mq[q][lane];
   const double xi = si / n;
   const double dmi = live ? xi - prior.m[lane] : 0.0;
   double r[D];
 #pragma unroll
-  for (int k = 0; k < D; ++k) {
-    const double xk = readlane_d(xi, k), dmk = readlane_d(dmi, k);
-    double v = k == lane ? 1.0 : 0.0;
-    if (k < d && live && k <= lane) {
-      const int tk = d + k * d - (k * (k - 1)) / 2 + (lane - k);  // packed (k, lane), k <= lane
+  for (int k0 = 0; k0 < D; k0 += 16) {
+    issue_fence();
+#pragma unroll
+    for (int k = k0; k < k0 + 16 && k < D; ++k) {
+      const double xk = readlane_d(xi, k), dmk = readlane_d(dmi, k);
+      const bool in = k < d && live && k <= lane;
+      const int tk = in ? d + k * d - (k * (k - 1)) / 2 + (lane - k) : 0;  // packed (k, lane), k <= lane
       double S = 0.0;
+#pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (item.seg[q] >= 0) S += moments[(size_t)item.seg[q] * E + tk];
-      v = prior.psi[lane * d + k] + (S - n * xi * xk) + cm * dmi * dmk;
+        if (wq[q] != 0.0) S += Mq[q][tk];
+      const double v = prior.psi[in ? lane * d + k : 0] + (S - n * xi * xk) + cm * dmi * dmk;
+      r[k] = in ? v : (k == lane ? 1.0 : 0.0);
     }
-    r[k] = v;
   }
-  bool ok = true;
-  double mydiag = 1.0;
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    double djj = readlane_d(r[j], j);
-    if (!(djj > 0.0) || !isfinite(djj)) {
-      ok = false;
-      djj = 1.0;
-    }
-    const double ljj = sqrt(djj), inv = 1.0 / ljj;
-    if (lane == j) mydiag = ljj;
-    r[j] = lane == j ? ljj : r[j] * inv;
-#pragma unroll
-    for (int k = j + 1; k < D; ++k) r[k] = fma(-r[j], readlane_d(r[j], k), r[k]);
-  }
+  double mydiag;
+  const bool ok = wave_cholesky<D>(r, lane, mydiag, cols[wave]);
   // log|Psi_n| = 2 sum log L_ii; log Gamma_d(nu_n / 2) - log Gamma_d(nu / 2)
   const double ld = 2.0 * wave_sum(live ? log(mydiag) : 0.0);
   const double lg = wave_sum(live ? lgamma(0.5 * nun - 0.5 * lane) - lgamma(0.5 * prior.nu - 0.5 * lane) : 0.0);
