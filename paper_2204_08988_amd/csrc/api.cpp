@@ -72,10 +72,15 @@ dpmm_status ensure_perm(dpmm_ctx* ctx, int64_t n) {
   if (ctx->d_perm) {
     DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
     hipFree(ctx->d_perm);
+    hipFree(ctx->d_cand);
     ctx->d_perm = nullptr;
+    ctx->d_cand = nullptr;
     ctx->perm_cap = 0;
   }
   DPMM_HIP(ctx, hipMalloc(&ctx->d_perm, (size_t)n * sizeof(int)), "allocate permutation");
+  // candidate lists of the points the matrix-core label kernels defer
+  if (ctx->d_nflag)
+    DPMM_HIP(ctx, hipMalloc(&ctx->d_cand, (size_t)n * RESCORE_CAND * sizeof(int)), "allocate candidate lists");
   ctx->perm_cap = n;
   return DPMM_OK;
 }
@@ -395,6 +400,7 @@ void dpmm_destroy(dpmm_ctx* ctx) {
   else hipDeviceSynchronize();
   for (auto& b : ctx->bufs) hipFree(b.p);
   if (ctx->d_perm) hipFree(ctx->d_perm);
+  if (ctx->d_cand) hipFree(ctx->d_cand);
   if (ctx->d_sel) hipFree(ctx->d_sel);
   if (ctx->d_side) hipFree(ctx->d_side);
   if (ctx->h_frame) hipHostFree(ctx->h_frame);
@@ -620,7 +626,8 @@ dpmm_status label_phase(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int
     if (ctx->d_whi) {
       DPMM_HIP(ctx, launch_label_gauss_mfma(ctx->d, ctx->cfg.precision == DPMM_BF16X3, (const float*)x, n, *G, *per,
                                             ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->K, t, ctx->cfg.seed, z,
-                                            ctx->d_hist, ctx->d_tot, ctx->d_perm, ctx->d_nflag, ctx->stream),
+                                            ctx->d_hist, ctx->d_tot, ctx->d_perm, ctx->d_cand, ctx->d_nflag,
+                                            ctx->stream),
                "matrix-core label kernel");
       return DPMM_OK;
     }

@@ -70,7 +70,8 @@ struct dpmm_ctx {
   bool labels_gave_stats = false;
   // BF16 whitener fragments of the cluster components (precision != FP32)
   uint16_t *d_whi = nullptr, *d_wlo = nullptr;
-  int* d_nflag = nullptr;  // count of the points deferred to FP32 (d = 128)
+  int* d_nflag = nullptr;  // count of the points deferred to FP32 (matrix-core label kernels)
+  int* d_cand = nullptr;   // [perm_cap][RESCORE_CAND] their candidate clusters
   hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool timing = false;  // record ev[3] between the sort and the statistics kernel
   // learned split proposal (cfg.learned = m > 0 principal axes, F = 2m features)

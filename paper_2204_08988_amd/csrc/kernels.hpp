@@ -6,6 +6,8 @@ namespace dpmm {
 
 #define NIW_SCRATCH(d) ((size_t)3 * (d) * (d) + (d))
 // float64 workspaces of the per-component kernels live in LDS up to this d
+// candidate clusters kept per point by the matrix-core label kernels
+constexpr int RESCORE_CAND = 8;
 constexpr int NIW_LDS_MAX_D = 64;
 inline size_t niw_lds_bytes(int d) { return d <= NIW_LDS_MAX_D ? NIW_SCRATCH(d) * sizeof(double) : 0; }
 // the marginal-likelihood kernel keeps one d x d matrix in LDS up to this d
@@ -96,12 +98,13 @@ hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, con
 // BF16 matrix-core cluster draw (d in {32, 64}) and its whitener fragments
 bool mfma_supported(int d);
 hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void* whi, void* wlo, hipStream_t s);
-// flagged: int[n] (the points whose draw is deferred to FP32, d = 128 only);
-// n_flagged: one device int
+// flagged: int[n] (the points whose draw is deferred to FP32); cand:
+// int[n][RESCORE_CAND], each deferred point's candidate clusters (-1: empty
+// slot, -2 in slot 0: all clusters); n_flagged: one device int
 hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, int G, long long per_block,
                                    const float* packed, const void* whi, const void* wlo, int K, uint32_t t,
-                                   uint64_t seed, int* z, int* hist, int* tot, int* flagged, int* n_flagged,
-                                   hipStream_t s);
+                                   uint64_t seed, int* z, int* hist, int* tot, int* flagged, int* cand,
+                                   int* n_flagged, hipStream_t s);
 hipError_t launch_loglik_gauss(int d, const float* x, long long n, const float* packed, int K, int k_max,
                                float* out, hipStream_t s);
 hipError_t launch_label_mult(int V, const int* x, long long n, const float* packed, int K, int k_max,

@@ -33,6 +33,102 @@ namespace {
 constexpr float BF16_TOL_REL = 1.0f / 32.0f;
 constexpr float BF16X3_TOL_REL = 1.0f / 4096.0f;
 constexpr float TOL_ABS = 0.05f;
+constexpr int NCAND = RESCORE_CAND;
+
+// Candidate clusters of one point for the FP32 re-score.  A BF16 score l with
+// squared norm q stands for an FP32 score within rel q + TOL_ABS / 2 of it, so
+// the FP32 maximum is at least lo_max - TOL_ABS / 2, lo_max = max (l - rel q),
+// and a cluster can only win the FP32 Gumbel-max if its bound u = l + rel q
+// exceeds T = lo_max - RGAP - TOL_ABS.  T only grows as clusters are scored,
+// so a cluster at or below the running T never becomes a candidate: only the
+// others enter the list (the NCAND largest u, in decreasing order), and the
+// largest bound ever pushed out of it tells whether the list is complete.
+struct Cands {
+  float u[NCAND];
+  int k[NCAND];
+  float lo_max, ev_max;
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int j = 0; j < NCAND; ++j) {
+      u[j] = -INFINITY;
+      k[j] = -1;
+    }
+    lo_max = -INFINITY;
+    ev_max = -INFINITY;
+  }
+  __device__ __forceinline__ float threshold() const { return lo_max - RGAP - TOL_ABS; }
+  __device__ __forceinline__ void push(float l, float q, float rel, int kk) {
+    lo_max = fmaxf(lo_max, fmaf(-rel, q, l));
+    const float uu = fmaf(rel, q, l);
+    if (uu > threshold() && uu > u[NCAND - 1]) {
+      ev_max = fmaxf(ev_max, u[NCAND - 1]);
+      float cu = uu;
+      int ck = kk;
+#pragma unroll
+      for (int j = 0; j < NCAND; ++j) {
+        const bool sw = cu > u[j];
+        const float tu = u[j];
+        const int tk = k[j];
+        u[j] = sw ? cu : tu;
+        k[j] = sw ? ck : tk;
+        cu = sw ? tu : cu;
+        ck = sw ? tk : ck;
+      }
+    } else if (uu > threshold()) {
+      ev_max = fmaxf(ev_max, uu);  // a bound inside the window that the full list has no room for
+    }
+  }
+};
+
+// The main pass keeps, per point, the two largest bounds u1 >= u2 (cluster k1)
+// and lo_max: exactly one cluster can win in FP32 unless u2 > T.
+struct Top2U {
+  float u1, u2, lo_max;
+  int k1;
+  __device__ __forceinline__ void init() {
+    u1 = u2 = lo_max = -INFINITY;
+    k1 = 0;
+  }
+  __device__ __forceinline__ void push(float l, float q, float rel, int kk) {
+    lo_max = fmaxf(lo_max, fmaf(-rel, q, l));
+    const float u = fmaf(rel, q, l);
+    const bool gt1 = u > u1, gt2 = u > u2;
+    u2 = gt1 ? u1 : (gt2 ? u : u2);
+    u1 = gt1 ? u : u1;
+    k1 = gt1 ? kk : k1;
+  }
+};
+
+// Main pass, point p: certain (z = k1, the only cluster that can win) unless
+// another bound reaches T; then appended to `flagged` (z = -1, not in the
+// histogram) for the candidate pass and k_rescore_flagged.
+__device__ __forceinline__ void finish_main(bool valid, long long p, const Top2U& t2, int* z, int* h, int* flagged,
+                                            int* n_flagged, int lane) {
+  const bool doubt = valid && t2.u2 > t2.lo_max - RGAP - TOL_ABS;
+  const unsigned long long dm = __ballot(doubt);
+  if (dm) {
+    const int leader = __ffsll((long long)dm) - 1;
+    int slot0 = 0;
+    if (lane == leader) slot0 = atomicAdd(n_flagged, __popcll(dm));
+    slot0 = __shfl(slot0, leader);
+    if (doubt) flagged[slot0 + __popcll(dm & ((1ull << lane) - 1ull))] = (int)p;
+  }
+  if (valid) {
+    z[p] = doubt ? -1 : t2.k1;
+    if (!doubt) atomicAdd(&h[t2.k1], 1);
+  }
+}
+
+// Candidate pass, deferred slot r: the listed clusters above T, -1 elsewhere,
+// or -2 in slot 0 when a cluster above T may be missing from the list.
+__device__ __forceinline__ void finish_cands(bool valid, long long r, const Cands& cd, int* cand) {
+  if (!valid) return;
+  const float T = cd.threshold();
+  const bool complete = !(cd.ev_max > T);
+  int* cs = cand + (size_t)r * NCAND;
+#pragma unroll
+  for (int j = 0; j < NCAND; ++j) cs[j] = complete ? (cd.u[j] > T ? cd.k[j] : -1) : (j == 0 ? -2 : -1);
+}
 
 constexpr int BLOCK32 = 512;  // threads per workgroup of the d = 32 kernel
 
@@ -44,15 +140,16 @@ constexpr int BLOCK32 = 512;  // threads per workgroup of the d = 32 kernel
 // the squared norm; the top-2 update is branch-free so that two clusters'
 // work interleaves.  Points whose top-2 gap leaves any doubt are appended to
 // `flagged` (z = -1, not in the histogram) for k_rescore_flagged.
-template <bool X3>
+template <bool X3, bool CANDS>
 __global__ __launch_bounds__(BLOCK32) void k_label_gauss_mfma32(const float* __restrict__ x, long long n,
                                                                 long long per_block, const float* __restrict__ packed,
                                                                 const bf16x8* __restrict__ whi,
                                                                 const bf16x8* __restrict__ wlo, int K,
                                                                 int* __restrict__ z, int* __restrict__ hist,
                                                                 int* __restrict__ tot, int* __restrict__ flagged,
-                                                                int* __restrict__ n_flagged) {
+                                                                int* __restrict__ cand, int* __restrict__ n_flagged) {
   constexpr int D = 32, KS = 2, NF = KS * 64;  // 16-byte fragments per cluster and table
+  constexpr float REL = X3 ? BF16X3_TOL_REL : BF16_TOL_REL;
   constexpr int NB = X3 ? 2 : 1;               // tables per cluster (hi, lo)
   constexpr int CG = X3 ? 16 : 32;             // clusters per LDS stage (64 KB of fragments)
   constexpr int MUS = D + 4;                   // mu[D], c, padding
@@ -64,9 +161,11 @@ __global__ __launch_bounds__(BLOCK32) void k_label_gauss_mfma32(const float* __r
   for (int k = threadIdx.x; k < K; k += BLOCK32) h[k] = 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int half = lane >> 5, col = lane & 31;
-  const unsigned long long below = (1ull << lane) - 1ull;
-  const long long begin = (long long)blockIdx.x * per_block;
-  const long long end = begin + per_block < n ? begin + per_block : n;
+  // main pass: the workgroup's points; candidate pass: the deferred slots, grid-strided
+  const long long nf = CANDS ? (long long)*n_flagged : 0;
+  const long long begin = CANDS ? (long long)blockIdx.x * BLOCK32 : (long long)blockIdx.x * per_block;
+  const long long end = CANDS ? nf : (begin + per_block < n ? begin + per_block : n);
+  const long long step = CANDS ? (long long)gridDim.x * BLOCK32 : BLOCK32;
   auto stage = [&](int g0, int cnt) {
     for (int e = threadIdx.x; e < cnt * NB * NF; e += BLOCK32) {
       const int c = e / (NB * NF), r = e - c * (NB * NF);
@@ -82,26 +181,32 @@ __global__ __launch_bounds__(BLOCK32) void k_label_gauss_mfma32(const float* __r
   const bool single = K <= CG;
   if (single && begin < end) stage(0, K);
   __syncthreads();
-  for (long long chunk = begin; chunk < end; chunk += BLOCK32) {
+  for (long long chunk = begin; chunk < end; chunk += step) {
     const long long base = chunk + wave * 64;
-    const long long pA = base + col, pB = base + 32 + col;
+    const long long rA = base + col, rB = base + 32 + col;
+    const long long pA = rA < end ? (CANDS ? (long long)flagged[rA] : rA) : 0;
+    const long long pB = rB < end ? (CANDS ? (long long)flagged[rB] : rB) : 0;
     // this lane's k-slices of the two tiles' points: dims 16 ks + 8 half + q
     float xa[KS][8], xb[KS][8];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const float4* ra = reinterpret_cast<const float4*>(x + pA * D + 16 * ks + 8 * half);
       const float4* rb = reinterpret_cast<const float4*>(x + pB * D + 16 * ks + 8 * half);
-      const float4 a0 = pA < end ? ra[0] : float4{0.f, 0.f, 0.f, 0.f};
-      const float4 a1 = pA < end ? ra[1] : float4{0.f, 0.f, 0.f, 0.f};
-      const float4 b0 = pB < end ? rb[0] : float4{0.f, 0.f, 0.f, 0.f};
-      const float4 b1 = pB < end ? rb[1] : float4{0.f, 0.f, 0.f, 0.f};
+      const float4 a0 = rA < end ? ra[0] : float4{0.f, 0.f, 0.f, 0.f};
+      const float4 a1 = rA < end ? ra[1] : float4{0.f, 0.f, 0.f, 0.f};
+      const float4 b0 = rB < end ? rb[0] : float4{0.f, 0.f, 0.f, 0.f};
+      const float4 b1 = rB < end ? rb[1] : float4{0.f, 0.f, 0.f, 0.f};
       xa[ks][0] = a0.x; xa[ks][1] = a0.y; xa[ks][2] = a0.z; xa[ks][3] = a0.w;
       xa[ks][4] = a1.x; xa[ks][5] = a1.y; xa[ks][6] = a1.z; xa[ks][7] = a1.w;
       xb[ks][0] = b0.x; xb[ks][1] = b0.y; xb[ks][2] = b0.z; xb[ks][3] = b0.w;
       xb[ks][4] = b1.x; xb[ks][5] = b1.y; xb[ks][6] = b1.z; xb[ks][7] = b1.w;
     }
-    float m1 = -INFINITY, m2 = -INFINITY, q1 = 0.0f, q2 = 0.0f;
-    int arg = 0;
+    Top2U t2;
+    Cands cd;
+    if (CANDS)
+      cd.init();
+    else
+      t2.init();
     for (int g0 = 0; g0 < K; g0 += CG) {
       const int cnt = K - g0 < CG ? K - g0 : CG;
       if (!single) {
@@ -154,30 +259,19 @@ __global__ __launch_bounds__(BLOCK32) void k_label_gauss_mfma32(const float* __r
         // it keeps its own tile's half-sum and receives the partner's
         const float qm = (half ? qb : qa) + __shfl_xor(half ? qa : qb, 32);
         const float l = fmaf(-0.5f, qm, cmu[D]);
-        const bool gt1 = l > m1, gt2 = l > m2;
-        m2 = gt1 ? m1 : (gt2 ? l : m2);
-        q2 = gt1 ? q1 : (gt2 ? qm : q2);
-        m1 = gt1 ? l : m1;
-        q1 = gt1 ? qm : q1;
-        arg = gt1 ? g0 + c : arg;
+        if (CANDS)
+          cd.push(l, qm, REL, g0 + c);
+        else
+          t2.push(l, qm, REL, g0 + c);
       }
     }
-    const long long p = base + lane;
-    const bool valid = p < end;
-    const float tol = (X3 ? BF16X3_TOL_REL : BF16_TOL_REL) * (q1 + q2) + TOL_ABS;
-    const bool doubt = valid && m2 > m1 - RGAP - tol;
-    const unsigned long long dm = __ballot(doubt);
-    if (dm) {
-      int slot0 = 0;
-      if (lane == __ffsll((long long)dm) - 1) slot0 = atomicAdd(n_flagged, __popcll(dm));
-      slot0 = __shfl(slot0, __ffsll((long long)dm) - 1);
-      if (doubt) flagged[slot0 + __popcll(dm & below)] = (int)p;
-    }
-    if (valid) {
-      z[p] = doubt ? -1 : arg;
-      if (!doubt) atomicAdd(&h[arg], 1);
-    }
+    const long long r = base + lane;
+    if (CANDS)
+      finish_cands(r < end, r, cd, cand);
+    else
+      finish_main(r < end, r, t2, z, h, flagged, n_flagged, lane);
   }
+  if (CANDS) return;
   __syncthreads();
   for (int k = threadIdx.x; k < K; k += BLOCK32) {
     hist[(size_t)blockIdx.x * K + k] = h[k];
@@ -192,16 +286,17 @@ __global__ __launch_bounds__(BLOCK32) void k_label_gauss_mfma32(const float* __r
 // 1.25 d^2 instead of 2 d^2 flops per point-cluster.  Points whose top-2 gap
 // leaves any doubt are not drawn here: they are appended to `flagged` (z = -1,
 // not in the histogram) and drawn by k_rescore_flagged in FP32.
-template <int D, bool X3>
+template <int D, bool X3, bool CANDS>
 __global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma_lds(const float* __restrict__ x, long long n,
                                                                 long long per_block, const float* __restrict__ packed,
                                                                 const bf16x8* __restrict__ whi,
                                                                 const bf16x8* __restrict__ wlo, int K,
                                                                 int* __restrict__ z, int* __restrict__ hist,
                                                                 int* __restrict__ tot, int* __restrict__ flagged,
-                                                                int* __restrict__ n_flagged) {
+                                                                int* __restrict__ cand, int* __restrict__ n_flagged) {
   constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
   constexpr int MT = D / 32, KS = D / 16, NF = MT * KS * 64;
+  constexpr float REL = X3 ? BF16X3_TOL_REL : BF16_TOL_REL;
   constexpr int PF = NF / BLOCK;  // fragments each thread stages per cluster
   constexpr int NB = X3 ? 2 : 1;  // fragment tables per cluster (hi, lo)
   constexpr int MUS = D + 4;      // mu[D], c
@@ -214,8 +309,11 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma_lds(const float* __r
   for (int k = threadIdx.x; k < K; k += BLOCK) h[k] = 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int half = lane >> 5, col = lane & 31;
-  const long long begin = (long long)blockIdx.x * per_block;
-  const long long end = begin + per_block < n ? begin + per_block : n;
+  // main pass: the workgroup's points; candidate pass: the deferred slots, grid-strided
+  const long long nf = CANDS ? (long long)*n_flagged : 0;
+  const long long begin = CANDS ? (long long)blockIdx.x * BLOCK : (long long)blockIdx.x * per_block;
+  const long long end = CANDS ? nf : (begin + per_block < n ? begin + per_block : n);
+  const long long step = CANDS ? (long long)gridDim.x * BLOCK : BLOCK;
   // staging of cluster k into buffer b: global -> registers (pf*), registers -> LDS
   bf16x8 pf[NB][PF];
   float pfmu = 0.0f;
@@ -244,21 +342,27 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma_lds(const float* __r
   __syncthreads();
   int buf = 0;
   // every wave runs the same number of chunks and clusters: one barrier per cluster
-  for (long long chunk = begin; chunk < end; chunk += BLOCK) {
+  for (long long chunk = begin; chunk < end; chunk += step) {
     const long long base = chunk + wave * 64;
-    const long long pA = base + col, pB = base + 32 + col;
+    const long long rA = base + col, rB = base + 32 + col;
+    const long long pA = rA < end ? (CANDS ? (long long)flagged[rA] : rA) : 0;
+    const long long pB = rB < end ? (CANDS ? (long long)flagged[rB] : rB) : 0;
     float xa[KS][8], xb[KS][8];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int j = 16 * ks + 8 * half + q;
-        xa[ks][q] = pA < end ? x[pA * D + j] : 0.0f;
-        xb[ks][q] = pB < end ? x[pB * D + j] : 0.0f;
+        xa[ks][q] = rA < end ? x[pA * D + j] : 0.0f;
+        xb[ks][q] = rB < end ? x[pB * D + j] : 0.0f;
       }
-    const bool more = chunk + BLOCK < end;
-    float m1 = -INFINITY, m2 = -INFINITY, q1 = 0.0f, q2 = 0.0f;
-    int arg = 0;
+    const bool more = chunk + step < end;
+    Top2U t2;
+    Cands cd;
+    if (CANDS)
+      cd.init();
+    else
+      t2.init();
     for (int k = 0; k < K; ++k) {
       // the next cluster (or the next chunk's first) is fetched while this one computes
       const bool next = k + 1 < K || more;
@@ -308,33 +412,22 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma_lds(const float* __r
       qb += __shfl_xor(qb, 32);
       const float qm = half ? qb : qa;
       const float l = fmaf(-0.5f, qm, cmu[D]);
-      if (l > m1) {
-        m2 = m1;
-        q2 = q1;
-        m1 = l;
-        q1 = qm;
-        arg = k;
-      } else if (l > m2) {
-        m2 = l;
-        q2 = qm;
-      }
+      if (CANDS)
+        cd.push(l, qm, REL, k);
+      else
+        t2.push(l, qm, REL, k);
       // the other buffer was last read before the previous barrier
       if (next) store(buf ^ 1);
       __syncthreads();
       buf ^= 1;
     }
-    const long long p = base + lane;
-    if (p < end) {
-      const float tol = (X3 ? BF16X3_TOL_REL : BF16_TOL_REL) * (q1 + q2) + TOL_ABS;
-      if (m2 > m1 - RGAP - tol) {
-        flagged[atomicAdd(n_flagged, 1)] = (int)p;
-        z[p] = -1;
-      } else {
-        z[p] = arg;
-        atomicAdd(&h[arg], 1);
-      }
-    }
+    const long long r = base + lane;
+    if (CANDS)
+      finish_cands(r < end, r, cd, cand);
+    else
+      finish_main(r < end, r, t2, z, h, flagged, n_flagged, lane);
   }
+  if (CANDS) return;
   __syncthreads();
   for (int k = threadIdx.x; k < K; k += BLOCK) {
     hist[(size_t)blockIdx.x * K + k] = h[k];
@@ -344,11 +437,16 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma_lds(const float* __r
 
 constexpr int RS_BLOCK = 64;
 
-// FP32 re-score and lazy Gumbel-max draw of the deferred points (exactly the
-// FP32 kernel's draw); the centred vector of a thread lives in an LDS column.
-// Adds each drawn point to the histogram of the label-kernel block that owns it.
+// FP32 re-score and lazy Gumbel-max draw of the deferred points, exactly the
+// FP32 kernel's draw; the centred vector of a thread lives in an LDS column.
+// With a complete candidate list only the candidates are scored (in
+// increasing k, the order of the full draw): every other cluster's FP32 score
+// is below the leader's by more than the Gumbel range, so the full draw skips
+// it too.  Adds each drawn point to the histogram of the label-kernel block
+// that owns it.
 __global__ __launch_bounds__(RS_BLOCK) void k_rescore_flagged(const float* __restrict__ x, int d,
                                                               const int* __restrict__ flagged,
+                                                              const int* __restrict__ cand,
                                                               const int* __restrict__ n_flagged, long long per_block,
                                                               const float* __restrict__ packed, int K, uint32_t t,
                                                               uint64_t seed, int* __restrict__ z,
@@ -373,10 +471,57 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rescore_flagged(const float* __res
       }
       return fmaf(-0.5f, qq, rp[0]);
     };
-    Top2 f;
-    f.init();
-    for (int k = 0; k < K; ++k) f.push(score(k), k);
-    const int zi = lazy_gumbel_max(f, K, (uint32_t)p, t, seed, score);
+    int ids[NCAND];
+#pragma unroll
+    for (int j = 0; j < NCAND; ++j) ids[j] = cand[(size_t)q * NCAND + j];
+    int zi;
+    if (ids[0] == -2) {
+      Top2 f;
+      f.init();
+      for (int k = 0; k < K; ++k) f.push(score(k), k);
+      zi = lazy_gumbel_max(f, K, (uint32_t)p, t, seed, score);
+    } else {
+      // candidates in increasing k (empty slots last)
+#pragma unroll
+      for (int a = 0; a < NCAND; ++a)
+#pragma unroll
+        for (int b = 0; b + 1 < NCAND - a; ++b) {
+          const unsigned ka = (unsigned)ids[b], kb = (unsigned)ids[b + 1];
+          ids[b] = ka < kb ? (int)ka : (int)kb;
+          ids[b + 1] = ka < kb ? (int)kb : (int)ka;
+        }
+      float sc[NCAND];
+      Top2 f;
+      f.init();
+#pragma unroll
+      for (int j = 0; j < NCAND; ++j) {
+        sc[j] = ids[j] >= 0 ? score(ids[j]) : -INFINITY;
+        if (ids[j] >= 0) f.push(sc[j], ids[j]);
+      }
+      zi = f.arg;
+      if (f.m2 > f.m1 - RGAP) {
+        int cached = f.arg >> 2;
+        u32x4 blk = rng_block(seed, t, (uint32_t)p, TAG_GUMBEL, (uint32_t)cached);
+        float best = f.m1 + gumbel_f(word_of(blk, f.arg & 3));
+#pragma unroll
+        for (int j = 0; j < NCAND; ++j) {
+          const int k = ids[j];
+          if (k < 0 || k == f.arg) continue;
+          if (sc[j] + GUMBEL_MAX_F > best) {
+            const int b = k >> 2;
+            if (b != cached) {
+              blk = rng_block(seed, t, (uint32_t)p, TAG_GUMBEL, (uint32_t)b);
+              cached = b;
+            }
+            const float s = sc[j] + gumbel_f(word_of(blk, k & 3));
+            if (s > best || (s == best && k < zi)) {
+              best = s;
+              zi = k;
+            }
+          }
+        }
+      }
+    }
     z[p] = zi;
     atomicAdd(&hist[(size_t)(p / per_block) * K + zi], 1);
     atomicAdd(&tot[zi], 1);
@@ -414,8 +559,8 @@ hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void*
 
 hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, int G, long long per_block,
                                    const float* packed, const void* whi, const void* wlo, int K, uint32_t t,
-                                   uint64_t seed, int* z, int* hist, int* tot, int* flagged, int* n_flagged,
-                                   hipStream_t s) {
+                                   uint64_t seed, int* z, int* hist, int* tot, int* flagged, int* cand,
+                                   int* n_flagged, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipError_t e = launch_zero64(tot, (size_t)(K + 1) / 2 + 1, s);
   if (e != hipSuccess) return e;
@@ -426,41 +571,57 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
   if (e != hipSuccess) return e;
   static bool attr_set = false;
   if (!attr_set) {  // more than 64 KB of dynamic LDS (160 KB per CU on gfx950)
-    const void* fns[6] = {(const void*)k_label_gauss_mfma_lds<128, true>, (const void*)k_label_gauss_mfma_lds<128, false>,
-                          (const void*)k_label_gauss_mfma_lds<64, true>,  (const void*)k_label_gauss_mfma_lds<64, false>,
-                          (const void*)k_label_gauss_mfma32<true>,        (const void*)k_label_gauss_mfma32<false>};
+    const void* fns[12] = {
+        (const void*)k_label_gauss_mfma_lds<128, true, false>, (const void*)k_label_gauss_mfma_lds<128, false, false>,
+        (const void*)k_label_gauss_mfma_lds<64, true, false>,  (const void*)k_label_gauss_mfma_lds<64, false, false>,
+        (const void*)k_label_gauss_mfma32<true, false>,        (const void*)k_label_gauss_mfma32<false, false>,
+        (const void*)k_label_gauss_mfma_lds<128, true, true>,  (const void*)k_label_gauss_mfma_lds<128, false, true>,
+        (const void*)k_label_gauss_mfma_lds<64, true, true>,   (const void*)k_label_gauss_mfma_lds<64, false, true>,
+        (const void*)k_label_gauss_mfma32<true, true>,         (const void*)k_label_gauss_mfma32<false, true>};
     for (const void* f : fns) {
       e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       if (e != hipSuccess) return e;
     }
     attr_set = true;
   }
-  if (d == 64 || d == 128) {
-    const int NF = (d / 32) * (d / 16) * 64;
-    const size_t lds = 2 * ((size_t)(x3 ? 2 : 1) * NF * sizeof(bf16x8) + (d + 4) * sizeof(float)) + lh;
-#define DPMM_MFMA_LDS(DD, XX)                                                                             \
-  hipLaunchKernelGGL((k_label_gauss_mfma_lds<DD, XX>), dim3(G), dim3(BLOCK), lds, s, x, n, per_block, packed, \
-                     hi, lo, K, z, hist, tot, flagged, n_flagged)
-    if (d == 128 && x3) DPMM_MFMA_LDS(128, true);
-    else if (d == 128) DPMM_MFMA_LDS(128, false);
-    else if (x3) DPMM_MFMA_LDS(64, true);
-    else DPMM_MFMA_LDS(64, false);
+  // the main pass, then the candidate pass over the points it deferred (same grid)
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool cands = pass == 1;
+    if (d == 64 || d == 128) {
+      const int NF = (d / 32) * (d / 16) * 64;
+      const size_t lds = 2 * ((size_t)(x3 ? 2 : 1) * NF * sizeof(bf16x8) + (d + 4) * sizeof(float)) + lh;
+#define DPMM_MFMA_LDS(DD, XX, CC)                                                                           \
+  hipLaunchKernelGGL((k_label_gauss_mfma_lds<DD, XX, CC>), dim3(G), dim3(BLOCK), lds, s, x, n, per_block, packed, \
+                     hi, lo, K, z, hist, tot, flagged, cand, n_flagged)
+      if (d == 128 && x3) {
+        if (cands) DPMM_MFMA_LDS(128, true, true); else DPMM_MFMA_LDS(128, true, false);
+      } else if (d == 128) {
+        if (cands) DPMM_MFMA_LDS(128, false, true); else DPMM_MFMA_LDS(128, false, false);
+      } else if (x3) {
+        if (cands) DPMM_MFMA_LDS(64, true, true); else DPMM_MFMA_LDS(64, true, false);
+      } else {
+        if (cands) DPMM_MFMA_LDS(64, false, true); else DPMM_MFMA_LDS(64, false, false);
+      }
 #undef DPMM_MFMA_LDS
-  } else if (d == 32) {
-    // [CG][NB][NF] fragments (64 KB), [CG][d + 4] means and constants, the histogram
-    const size_t lds = (size_t)65536 + (size_t)(x3 ? 16 : 32) * (d + 4) * sizeof(float) + lh;
-    if (x3)
-      hipLaunchKernelGGL((k_label_gauss_mfma32<true>), dim3(G), dim3(BLOCK32), lds, s, x, n, per_block, packed, hi, lo,
-                         K, z, hist, tot, flagged, n_flagged);
-    else
-      hipLaunchKernelGGL((k_label_gauss_mfma32<false>), dim3(G), dim3(BLOCK32), lds, s, x, n, per_block, packed, hi,
-                         lo, K, z, hist, tot, flagged, n_flagged);
-  } else {
-    return hipErrorInvalidValue;
+    } else if (d == 32) {
+      // [CG][NB][NF] fragments (64 KB), [CG][d + 4] means and constants, the histogram
+      const size_t lds = (size_t)65536 + (size_t)(x3 ? 16 : 32) * (d + 4) * sizeof(float) + lh;
+#define DPMM_MFMA32(XX, CC)                                                                                 \
+  hipLaunchKernelGGL((k_label_gauss_mfma32<XX, CC>), dim3(G), dim3(BLOCK32), lds, s, x, n, per_block, packed, hi, \
+                     lo, K, z, hist, tot, flagged, cand, n_flagged)
+      if (x3) {
+        if (cands) DPMM_MFMA32(true, true); else DPMM_MFMA32(true, false);
+      } else {
+        if (cands) DPMM_MFMA32(false, true); else DPMM_MFMA32(false, false);
+      }
+#undef DPMM_MFMA32
+    } else {
+      return hipErrorInvalidValue;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_rescore_flagged, dim3(1024), dim3(RS_BLOCK), (size_t)d * RS_BLOCK * sizeof(float), s, x, d,
-                     flagged, n_flagged, per_block, packed, K, t, seed, z, hist, tot);
+                     flagged, cand, n_flagged, per_block, packed, K, t, seed, z, hist, tot);
   return hipGetLastError();
 }
 
