@@ -346,7 +346,8 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     if (cfg->precision != DPMM_FP32) {
       ok = ok && chk(c->alloc(&c->d_whi, (size_t)km * d * d));
       ok = ok && chk(c->alloc(&c->d_nflag, 2));
-      if (cfg->precision == DPMM_BF16X3) ok = ok && chk(c->alloc(&c->d_wlo, (size_t)km * d * d));
+      // low parts: the bf16x3 form, and the candidate pass of either matrix-core form
+      ok = ok && chk(c->alloc(&c->d_wlo, (size_t)km * d * d));
     }
     if (d >= SORTED_MIN_D) {
       c->hist_cap = 2048LL * km;

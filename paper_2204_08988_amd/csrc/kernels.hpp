@@ -95,6 +95,12 @@ hipError_t launch_sort_by_z(const int* z, long long n, int K, int G, long long p
 hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, const int* perm, const int* z,
                             unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t, uint64_t seed,
                             long long* counts, double* moments, hipStream_t s);
+// statistics of a listed set of cluster k1's points split by side[i] into
+// segments slot, slot + 1 (slot >= 2 k1; d in {8, 16, 32, 64, 128})
+bool partition_stats_supported(int d);
+hipError_t launch_partition_stats(int d, const float* x, long long npts, const int* idx, long long nsel,
+                                  const int* z, int k1, int K, const unsigned char* side, int slot,
+                                  long long* counts, double* moments, hipStream_t s);
 // BF16 matrix-core cluster draw (d in {32, 64}) and its whitener fragments
 bool mfma_supported(int d);
 hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void* whi, void* wlo, hipStream_t s);

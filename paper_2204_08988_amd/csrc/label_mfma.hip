@@ -17,6 +17,8 @@
 // deferred to k_rescore_flagged, which re-scores it in FP32 on the vector ALUs
 // and draws it exactly as the FP32 kernel draws it; otherwise no other cluster
 // can win and the leader is the label.
+#include <climits>
+
 #include "kernels.hpp"
 #include "score.hpp"
 
@@ -35,6 +37,21 @@ constexpr float BF16X3_TOL_REL = 1.0f / 4096.0f;
 constexpr float TOL_ABS = 0.05f;
 constexpr int NCAND = RESCORE_CAND;
 
+// arr[bucket] += 1 for every active lane, as one atomic per distinct bucket of
+// the wave (deferred points pile onto few clusters; per-lane atomics on a
+// handful of addresses serialise).  Call with every lane of the wave.
+__device__ __forceinline__ void wave_count_add(bool active, long long bucket, int* arr) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long pend = __ballot(active);
+  while (pend) {
+    const int l0 = __ffsll((long long)pend) - 1;
+    const long long b0 = __shfl(bucket, l0);
+    const unsigned long long m = __ballot(active && bucket == b0);
+    if (lane == l0) atomicAdd(&arr[b0], __popcll(m));
+    pend &= ~m;
+  }
+}
+
 // Candidate clusters of one point for the FP32 re-score.  A BF16 score l with
 // squared norm q stands for an FP32 score within rel q + TOL_ABS / 2 of it, so
 // the FP32 maximum is at least lo_max - TOL_ABS / 2, lo_max = max (l - rel q),
@@ -44,13 +61,14 @@ constexpr int NCAND = RESCORE_CAND;
 // others enter the list (the NCAND largest u, in decreasing order), and the
 // largest bound ever pushed out of it tells whether the list is complete.
 struct Cands {
-  float u[NCAND];
+  float u[NCAND], q[NCAND];
   int k[NCAND];
   float lo_max, ev_max;
   __device__ __forceinline__ void init() {
 #pragma unroll
     for (int j = 0; j < NCAND; ++j) {
       u[j] = -INFINITY;
+      q[j] = 0.0f;
       k[j] = -1;
     }
     lo_max = -INFINITY;
@@ -62,16 +80,18 @@ struct Cands {
     const float uu = fmaf(rel, q, l);
     if (uu > threshold() && uu > u[NCAND - 1]) {
       ev_max = fmaxf(ev_max, u[NCAND - 1]);
-      float cu = uu;
+      float cu = uu, cq = q;
       int ck = kk;
 #pragma unroll
       for (int j = 0; j < NCAND; ++j) {
         const bool sw = cu > u[j];
-        const float tu = u[j];
+        const float tu = u[j], tq = this->q[j];
         const int tk = k[j];
         u[j] = sw ? cu : tu;
+        this->q[j] = sw ? cq : tq;
         k[j] = sw ? ck : tk;
         cu = sw ? tu : cu;
+        cq = sw ? tq : cq;
         ck = sw ? tk : ck;
       }
     } else if (uu > threshold()) {
@@ -119,15 +139,57 @@ __device__ __forceinline__ void finish_main(bool valid, long long p, const Top2U
   }
 }
 
-// Candidate pass, deferred slot r: the listed clusters above T, -1 elsewhere,
-// or -2 in slot 0 when a cluster above T may be missing from the list.
-__device__ __forceinline__ void finish_cands(bool valid, long long r, const Cands& cd, int* cand) {
-  if (!valid) return;
+// Candidate pass (bf16x3 scores, allowance rel q + TOL_ABS / 2 each), deferred
+// slot r of point p: with a complete list the candidates' Gumbel values are
+// drawn here (the same words as the FP32 draw).  If the perturbed leader's
+// lower bound beats every other candidate's upper bound, the FP32 draw picks
+// the same cluster: z[p] is written and the point counted, and slot 0 of the
+// list becomes -3.  Otherwise the list holds the candidates (-1 elsewhere) or
+// -2 in slot 0 when a cluster above T may be missing, for k_rescore_flagged.
+__device__ __forceinline__ void finish_cands(bool valid, long long r, long long p, const Cands& cd, float rel,
+                                             int K, long long per_block, uint32_t t, uint64_t seed, int* z,
+                                             int* hist, int* tot, int* cand) {
   const float T = cd.threshold();
   const bool complete = !(cd.ev_max > T);
-  int* cs = cand + (size_t)r * NCAND;
+  bool sure = false;
+  int kb = -1;
+  if (valid && complete) {
+    float pb = -INFINITY, tb = 0.0f;
+    float pv[NCAND], tv[NCAND];
 #pragma unroll
-  for (int j = 0; j < NCAND; ++j) cs[j] = complete ? (cd.u[j] > T ? cd.k[j] : -1) : (j == 0 ? -2 : -1);
+    for (int j = 0; j < NCAND; ++j) {
+      pv[j] = -INFINITY;
+      tv[j] = 0.0f;
+      if (cd.k[j] >= 0 && cd.u[j] > T) {
+        const int k = cd.k[j];
+        const float l = fmaf(-rel, cd.q[j], cd.u[j]);
+        const u32x4 blk = rng_block(seed, t, (uint32_t)p, TAG_GUMBEL, (uint32_t)(k >> 2));
+        pv[j] = l + gumbel_f(word_of(blk, k & 3));
+        tv[j] = fmaf(rel, cd.q[j], 0.5f * TOL_ABS);
+        if (pv[j] > pb || (pv[j] == pb && k < kb)) {
+          pb = pv[j];
+          tb = tv[j];
+          kb = k;
+        }
+      }
+    }
+    sure = kb >= 0;
+#pragma unroll
+    for (int j = 0; j < NCAND; ++j)
+      if (cd.k[j] >= 0 && cd.k[j] != kb && cd.u[j] > T) sure = sure && (pb - tb > pv[j] + tv[j]);
+  }
+  if (valid) {
+    int* cs = cand + (size_t)r * NCAND;
+    if (sure) {
+      z[p] = kb;
+      cs[0] = -3;
+    } else {
+#pragma unroll
+      for (int j = 0; j < NCAND; ++j) cs[j] = complete ? (cd.u[j] > T ? cd.k[j] : -1) : (j == 0 ? -2 : -1);
+    }
+  }
+  wave_count_add(sure, sure ? (p / per_block) * K + kb : 0, hist);
+  wave_count_add(sure, sure ? kb : 0, tot);
 }
 
 constexpr int BLOCK32 = 512;  // threads per workgroup of the d = 32 kernel
@@ -144,8 +206,8 @@ template <bool X3, bool CANDS>
 __global__ __launch_bounds__(BLOCK32) void k_label_gauss_mfma32(const float* __restrict__ x, long long n,
                                                                 long long per_block, const float* __restrict__ packed,
                                                                 const bf16x8* __restrict__ whi,
-                                                                const bf16x8* __restrict__ wlo, int K,
-                                                                int* __restrict__ z, int* __restrict__ hist,
+                                                                const bf16x8* __restrict__ wlo, int K, uint32_t t,
+                                                                uint64_t seed, int* __restrict__ z, int* __restrict__ hist,
                                                                 int* __restrict__ tot, int* __restrict__ flagged,
                                                                 int* __restrict__ cand, int* __restrict__ n_flagged) {
   constexpr int D = 32, KS = 2, NF = KS * 64;  // 16-byte fragments per cluster and table
@@ -267,7 +329,8 @@ __global__ __launch_bounds__(BLOCK32) void k_label_gauss_mfma32(const float* __r
     }
     const long long r = base + lane;
     if (CANDS)
-      finish_cands(r < end, r, cd, cand);
+      finish_cands(r < end, r, r < end ? (long long)flagged[r] : 0, cd, REL, K, per_block, t, seed, z, hist, tot,
+                   cand);
     else
       finish_main(r < end, r, t2, z, h, flagged, n_flagged, lane);
   }
@@ -290,8 +353,8 @@ template <int D, bool X3, bool CANDS>
 __global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma_lds(const float* __restrict__ x, long long n,
                                                                 long long per_block, const float* __restrict__ packed,
                                                                 const bf16x8* __restrict__ whi,
-                                                                const bf16x8* __restrict__ wlo, int K,
-                                                                int* __restrict__ z, int* __restrict__ hist,
+                                                                const bf16x8* __restrict__ wlo, int K, uint32_t t,
+                                                                uint64_t seed, int* __restrict__ z, int* __restrict__ hist,
                                                                 int* __restrict__ tot, int* __restrict__ flagged,
                                                                 int* __restrict__ cand, int* __restrict__ n_flagged) {
   constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
@@ -423,7 +486,8 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma_lds(const float* __r
     }
     const long long r = base + lane;
     if (CANDS)
-      finish_cands(r < end, r, cd, cand);
+      finish_cands(r < end, r, r < end ? (long long)flagged[r] : 0, cd, REL, K, per_block, t, seed, z, hist, tot,
+                   cand);
     else
       finish_main(r < end, r, t2, z, h, flagged, n_flagged, lane);
   }
@@ -435,96 +499,119 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma_lds(const float* __r
   }
 }
 
-constexpr int RS_BLOCK = 64;
+constexpr int RS_BLOCK = 256;
 
-// FP32 re-score and lazy Gumbel-max draw of the deferred points, exactly the
-// FP32 kernel's draw; the centred vector of a thread lives in an LDS column.
-// With a complete candidate list only the candidates are scored (in
-// increasing k, the order of the full draw): every other cluster's FP32 score
-// is below the leader's by more than the Gumbel range, so the full draw skips
-// it too.  Adds each drawn point to the histogram of the label-kernel block
-// that owns it.
-__global__ __launch_bounds__(RS_BLOCK) void k_rescore_flagged(const float* __restrict__ x, int d,
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
+// FP32 draw of the deferred points, exactly the FP32 kernel's draw: the
+// winner of max_k (l_k + g_k) with the smaller k on ties, here as a streaming
+// lazy Gumbel-max over the point's candidates in increasing k (or over all K
+// when its list is incomplete).  Each candidate k that is not already beaten
+// by more than the Gumbel range gets its Gumbel value, so the result equals
+// the full draw.  A wave takes 64 deferred points and walks the union of their
+// cluster sequences in increasing k: at each step every lane scores the same
+// cluster (the record comes through scalar loads) and the lanes whose next
+// cluster it is use the score.  Adds each drawn point to the histogram of the
+// label-kernel block that owns it.
+template <int D>
+__global__ __launch_bounds__(RS_BLOCK) void k_rescore_flagged(const float* __restrict__ x,
                                                               const int* __restrict__ flagged,
                                                               const int* __restrict__ cand,
                                                               const int* __restrict__ n_flagged, long long per_block,
                                                               const float* __restrict__ packed, int K, uint32_t t,
                                                               uint64_t seed, int* __restrict__ z,
                                                               int* __restrict__ hist, int* __restrict__ tot) {
-  extern __shared__ float dxs[];  // [d][RS_BLOCK]
-  float* dx = dxs + threadIdx.x;
-  const int S = gauss_rec_stride(d);
-  const int cnt = *n_flagged;
-  for (int q = blockIdx.x * RS_BLOCK + threadIdx.x; q < cnt; q += gridDim.x * RS_BLOCK) {
-    const long long p = flagged[q];
-    const float* xp = x + p * d;
-    auto score = [&](int k) {
-      const float* rp = packed + (size_t)k * S;
-      for (int j = 0; j < d; ++j) dx[j * RS_BLOCK] = xp[j] - rp[4 + j];
-      const float* w = rp + 4 + d;
-      float qq = 0.0f;
-      for (int r = 0; r < d; ++r) {
-        const float* wr = w + r * (r + 1) / 2;
-        float y = 0.0f;
-        for (int c = 0; c <= r; ++c) y = fmaf(wr[c], dx[c * RS_BLOCK], y);
-        qq = fmaf(y, y, qq);
-      }
-      return fmaf(-0.5f, qq, rp[0]);
-    };
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nf = *n_flagged;
+  for (int base = (blockIdx.x * (RS_BLOCK / 64) + wave) * 64; base < nf; base += gridDim.x * RS_BLOCK) {
+    const int q = base + lane;
+    const bool valid = q < nf;
+    const long long p = valid ? flagged[q] : 0;
+    // the row is re-read (from cache) for every cluster: only the centred copy stays in registers
+    const float4* xr = reinterpret_cast<const float4*>(x + p * D);
     int ids[NCAND];
 #pragma unroll
-    for (int j = 0; j < NCAND; ++j) ids[j] = cand[(size_t)q * NCAND + j];
-    int zi;
-    if (ids[0] == -2) {
-      Top2 f;
-      f.init();
-      for (int k = 0; k < K; ++k) f.push(score(k), k);
-      zi = lazy_gumbel_max(f, K, (uint32_t)p, t, seed, score);
-    } else {
-      // candidates in increasing k (empty slots last)
+    for (int j = 0; j < NCAND; ++j) ids[j] = valid ? cand[(size_t)q * NCAND + j] : -1;
+    const bool done = valid && ids[0] == -3;  // drawn by the candidate pass
+    const bool all = valid && ids[0] == -2;
+    // candidates in increasing k, empty slots (-1) last
 #pragma unroll
-      for (int a = 0; a < NCAND; ++a)
+    for (int a = 0; a < NCAND; ++a)
 #pragma unroll
-        for (int b = 0; b + 1 < NCAND - a; ++b) {
-          const unsigned ka = (unsigned)ids[b], kb = (unsigned)ids[b + 1];
-          ids[b] = ka < kb ? (int)ka : (int)kb;
-          ids[b + 1] = ka < kb ? (int)kb : (int)ka;
-        }
-      float sc[NCAND];
-      Top2 f;
-      f.init();
-#pragma unroll
-      for (int j = 0; j < NCAND; ++j) {
-        sc[j] = ids[j] >= 0 ? score(ids[j]) : -INFINITY;
-        if (ids[j] >= 0) f.push(sc[j], ids[j]);
+      for (int b = 0; b + 1 < NCAND - a; ++b) {
+        const unsigned ka = (unsigned)ids[b], kb = (unsigned)ids[b + 1];
+        ids[b] = ka < kb ? (int)ka : (int)kb;
+        ids[b + 1] = ka < kb ? (int)kb : (int)ka;
       }
-      zi = f.arg;
-      if (f.m2 > f.m1 - RGAP) {
-        int cached = f.arg >> 2;
-        u32x4 blk = rng_block(seed, t, (uint32_t)p, TAG_GUMBEL, (uint32_t)cached);
-        float best = f.m1 + gumbel_f(word_of(blk, f.arg & 3));
+    if (done) ids[0] = -1;
+    int pos = 0;                  // next candidate slot (list lanes)
+    int nxt_all = all ? 0 : K;    // next cluster (all-K lanes)
+    float best = -INFINITY;
+    int win = -1, cached = -1;
+    u32x4 blk = {0u, 0u, 0u, 0u};
+    for (;;) {
+      int mine_k = INT_MAX;
+      if (all) {
+        mine_k = nxt_all < K ? nxt_all : INT_MAX;
+      } else if (valid) {
 #pragma unroll
-        for (int j = 0; j < NCAND; ++j) {
-          const int k = ids[j];
-          if (k < 0 || k == f.arg) continue;
-          if (sc[j] + GUMBEL_MAX_F > best) {
-            const int b = k >> 2;
-            if (b != cached) {
-              blk = rng_block(seed, t, (uint32_t)p, TAG_GUMBEL, (uint32_t)b);
-              cached = b;
-            }
-            const float s = sc[j] + gumbel_f(word_of(blk, k & 3));
-            if (s > best || (s == best && k < zi)) {
-              best = s;
-              zi = k;
-            }
+        for (int j = 0; j < NCAND; ++j)
+          if (j == pos && ids[j] >= 0) mine_k = ids[j];
+      }
+      // uniform by construction; readfirstlane lets the compiler see it (scalar record loads)
+      const int kk = __builtin_amdgcn_readfirstlane(wave_min_i(mine_k));
+      if (kk == INT_MAX) break;
+      float l;
+      {
+        const float* rec = packed + (size_t)kk * S;
+        float dx[D];
+#pragma unroll
+        for (int j = 0; j < D / 4; ++j) {
+          const float4 v = xr[j];
+          dx[4 * j] = v.x - rec[4 + 4 * j];
+          dx[4 * j + 1] = v.y - rec[5 + 4 * j];
+          dx[4 * j + 2] = v.z - rec[6 + 4 * j];
+          dx[4 * j + 3] = v.w - rec[7 + 4 * j];
+        }
+        const float* w = rec + 4 + D;
+        float qq = 0.0f;
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          float y = 0.0f;
+#pragma unroll
+          for (int c = 0; c <= r; ++c) y = fmaf(w[r * (r + 1) / 2 + c], dx[c], y);
+          qq = fmaf(y, y, qq);
+        }
+        l = fmaf(-0.5f, qq, rec[0]);
+      }
+      if (mine_k == kk) {
+        if (l + GUMBEL_MAX_F > best) {
+          const int b = kk >> 2;
+          if (b != cached) {
+            blk = rng_block(seed, t, (uint32_t)p, TAG_GUMBEL, (uint32_t)b);
+            cached = b;
+          }
+          const float sv = l + gumbel_f(word_of(blk, kk & 3));
+          if (sv > best) {
+            best = sv;
+            win = kk;
           }
         }
+        if (all)
+          ++nxt_all;
+        else
+          ++pos;
       }
     }
-    z[p] = zi;
-    atomicAdd(&hist[(size_t)(p / per_block) * K + zi], 1);
-    atomicAdd(&tot[zi], 1);
+    const bool drew = valid && !done;
+    if (drew) z[p] = win;
+    wave_count_add(drew, drew ? (p / per_block) * K + win : 0, hist);
+    wave_count_add(drew, drew ? win : 0, tot);
   }
 }
 
@@ -571,13 +658,12 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
   if (e != hipSuccess) return e;
   static bool attr_set = false;
   if (!attr_set) {  // more than 64 KB of dynamic LDS (160 KB per CU on gfx950)
-    const void* fns[12] = {
+    const void* fns[9] = {
         (const void*)k_label_gauss_mfma_lds<128, true, false>, (const void*)k_label_gauss_mfma_lds<128, false, false>,
         (const void*)k_label_gauss_mfma_lds<64, true, false>,  (const void*)k_label_gauss_mfma_lds<64, false, false>,
         (const void*)k_label_gauss_mfma32<true, false>,        (const void*)k_label_gauss_mfma32<false, false>,
-        (const void*)k_label_gauss_mfma_lds<128, true, true>,  (const void*)k_label_gauss_mfma_lds<128, false, true>,
-        (const void*)k_label_gauss_mfma_lds<64, true, true>,   (const void*)k_label_gauss_mfma_lds<64, false, true>,
-        (const void*)k_label_gauss_mfma32<true, true>,         (const void*)k_label_gauss_mfma32<false, true>};
+        (const void*)k_label_gauss_mfma_lds<128, true, true>,  (const void*)k_label_gauss_mfma_lds<64, true, true>,
+        (const void*)k_label_gauss_mfma32<true, true>};
     for (const void* f : fns) {
       e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       if (e != hipSuccess) return e;
@@ -592,36 +678,49 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
       const size_t lds = 2 * ((size_t)(x3 ? 2 : 1) * NF * sizeof(bf16x8) + (d + 4) * sizeof(float)) + lh;
 #define DPMM_MFMA_LDS(DD, XX, CC)                                                                           \
   hipLaunchKernelGGL((k_label_gauss_mfma_lds<DD, XX, CC>), dim3(G), dim3(BLOCK), lds, s, x, n, per_block, packed, \
-                     hi, lo, K, z, hist, tot, flagged, cand, n_flagged)
-      if (d == 128 && x3) {
-        if (cands) DPMM_MFMA_LDS(128, true, true); else DPMM_MFMA_LDS(128, true, false);
-      } else if (d == 128) {
-        if (cands) DPMM_MFMA_LDS(128, false, true); else DPMM_MFMA_LDS(128, false, false);
-      } else if (x3) {
-        if (cands) DPMM_MFMA_LDS(64, true, true); else DPMM_MFMA_LDS(64, true, false);
+                     hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
+#define DPMM_MFMA_LDS_C(DD)                                                                                   \
+  hipLaunchKernelGGL((k_label_gauss_mfma_lds<DD, true, true>), dim3(G), dim3(BLOCK), lds_c, s, x, n, per_block,  \
+                     packed, hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
+      // the candidate pass scores in bf16x3 whatever the main pass's form
+      const size_t lds_c = 2 * ((size_t)2 * NF * sizeof(bf16x8) + (d + 4) * sizeof(float)) + lh;
+      if (d == 128) {
+        if (cands) DPMM_MFMA_LDS_C(128); else if (x3) DPMM_MFMA_LDS(128, true, false); else DPMM_MFMA_LDS(128, false, false);
       } else {
-        if (cands) DPMM_MFMA_LDS(64, false, true); else DPMM_MFMA_LDS(64, false, false);
+        if (cands) DPMM_MFMA_LDS_C(64); else if (x3) DPMM_MFMA_LDS(64, true, false); else DPMM_MFMA_LDS(64, false, false);
       }
 #undef DPMM_MFMA_LDS
+#undef DPMM_MFMA_LDS_C
     } else if (d == 32) {
-      // [CG][NB][NF] fragments (64 KB), [CG][d + 4] means and constants, the histogram
-      const size_t lds = (size_t)65536 + (size_t)(x3 ? 16 : 32) * (d + 4) * sizeof(float) + lh;
+      // [CG][NB][NF] fragments (64 KB), [CG][d + 4] means and constants, the histogram;
+      // the candidate pass scores in bf16x3
+      const size_t lds = (size_t)65536 + (size_t)(x3 || cands ? 16 : 32) * (d + 4) * sizeof(float) + lh;
 #define DPMM_MFMA32(XX, CC)                                                                                 \
   hipLaunchKernelGGL((k_label_gauss_mfma32<XX, CC>), dim3(G), dim3(BLOCK32), lds, s, x, n, per_block, packed, hi, \
-                     lo, K, z, hist, tot, flagged, cand, n_flagged)
-      if (x3) {
-        if (cands) DPMM_MFMA32(true, true); else DPMM_MFMA32(true, false);
-      } else {
-        if (cands) DPMM_MFMA32(false, true); else DPMM_MFMA32(false, false);
-      }
+                     lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
+      if (cands)
+        DPMM_MFMA32(true, true);
+      else if (x3)
+        DPMM_MFMA32(true, false);
+      else
+        DPMM_MFMA32(false, false);
 #undef DPMM_MFMA32
     } else {
       return hipErrorInvalidValue;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_rescore_flagged, dim3(1024), dim3(RS_BLOCK), (size_t)d * RS_BLOCK * sizeof(float), s, x, d,
-                     flagged, cand, n_flagged, per_block, packed, K, t, seed, z, hist, tot);
+  // the deferred points in FP32 (grid-strided; the count stays on the device)
+#define DPMM_RESCORE(DD)                                                                                 \
+  hipLaunchKernelGGL(k_rescore_flagged<DD>, dim3(512), dim3(RS_BLOCK), 0, s, x, flagged, cand, n_flagged, \
+                     per_block, packed, K, t, seed, z, hist, tot)
+  if (d == 32)
+    DPMM_RESCORE(32);
+  else if (d == 64)
+    DPMM_RESCORE(64);
+  else
+    DPMM_RESCORE(128);
+#undef DPMM_RESCORE
   return hipGetLastError();
 }
 

@@ -383,13 +383,20 @@ dpmm_status learned_move(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, in
                                   s), "proposal kernel");
   }
   std::vector<LogmlItem> items;
+  int a_off = 0;  // segment of side A (side == 1) within slot, slot + 1
   if (split) {
     const int slot = 2 * K;
-    DPMM_HIP(ctx, launch_set_stats((const float*)x, ctx->d, n, ctx->d_sel, (int)nC, side, ctx->d_setpart, slot,
-                                   ctx->d_counts, ctx->d_moments, s), "partition statistics kernels");
+    // the sorted-order kernels keep side h in segment slot + h; the generic one puts side A first
+    a_off = partition_stats_supported(ctx->d) ? 1 : 0;
+    if (partition_stats_supported(ctx->d))
+      DPMM_HIP(ctx, launch_partition_stats(ctx->d, (const float*)x, n, ctx->d_sel, nC, z, k1, K, side, slot,
+                                           ctx->d_counts, ctx->d_moments, s), "partition statistics kernels");
+    else
+      DPMM_HIP(ctx, launch_set_stats((const float*)x, ctx->d, n, ctx->d_sel, (int)nC, side, ctx->d_setpart, slot,
+                                     ctx->d_counts, ctx->d_moments, s), "partition statistics kernels");
     DPMM_HIP(ctx, hipMemcpyAsync(back->side_cnt, ctx->d_counts + slot, 2 * sizeof(long long), hipMemcpyDeviceToHost,
                                  s), "copy counts");
-    items = {LogmlItem{{slot, -1, -1, -1}}, LogmlItem{{slot + 1, -1, -1, -1}},
+    items = {LogmlItem{{slot + a_off, -1, -1, -1}}, LogmlItem{{slot + 1 - a_off, -1, -1, -1}},
              LogmlItem{{2 * k1, 2 * k1 + 1, -1, -1}}};
   } else {
     items = {LogmlItem{{2 * k1, 2 * k1 + 1, -1, -1}}, LogmlItem{{2 * k2, 2 * k2 + 1, -1, -1}},
@@ -404,8 +411,8 @@ dpmm_status learned_move(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, in
     return ctx->fail(DPMM_E_NUMERIC, "a float64 Cholesky factorisation met a non-positive pivot");
   }
   DPMM_TRY(check_selected(ctx, nC));
-  const long long nA = split ? back->side_cnt[0] : cnt[2 * k1] + cnt[2 * k1 + 1];
-  const long long nB = split ? back->side_cnt[1] : cnt[2 * k2] + cnt[2 * k2 + 1];
+  const long long nA = split ? back->side_cnt[a_off] : cnt[2 * k1] + cnt[2 * k1 + 1];
+  const long long nB = split ? back->side_cnt[1 - a_off] : cnt[2 * k2] + cnt[2 * k2 + 1];
   li.n_a = nA;
   li.n_b = nB;
   // q(s): side-A points take log b, side-B points log(1 - b); q(not s) swaps them

@@ -355,7 +355,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
 // The current cluster's two segments are carried across chunks and flushed
 // with global atomics when the cluster changes or the range ends.
 template <int D, bool SAMPLE>
-__global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__ x, long long n_sorted,
+__global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__ x, long long npts, long long n_sorted,
                                                        long long rows_per_wave, const int* __restrict__ perm,
                                                        const int* __restrict__ z, unsigned char* __restrict__ zsub,
                                                        const float* __restrict__ packed, int K, int k_max, uint32_t t,
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
     if (valid) {
       i = perm[r];
       // a label outside [0, K) leaves its row out (and never reaches memory)
-      valid = (unsigned long long)i < (unsigned long long)n_sorted;
+      valid = (unsigned long long)i < (unsigned long long)npts;
       if (valid) k = z[i];
       valid = valid && (unsigned)k < (unsigned)K;
     }
@@ -854,14 +854,14 @@ hipError_t launch_sort_by_z(const int* z, long long n, int K, int G, long long p
   return hipGetLastError();
 }
 
-hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, const int* perm, const int* z,
-                            unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t, uint64_t seed,
-                            long long* counts, double* moments, hipStream_t s) {
-  const int E = d + d * (d + 1) / 2;
-  hipError_t e = launch_zero64(counts, (size_t)2 * K, s);
-  if (e != hipSuccess) return e;
-  e = launch_zero64(moments, (size_t)2 * K * E, s);
-  if (e != hipSuccess) return e;
+namespace {
+
+// The statistics kernels over rows perm[0, n) (point indices below npts),
+// accumulating into counts / moments (which the caller has zeroed).
+hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts, long long n, const int* perm,
+                             const int* z, unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t,
+                             uint64_t seed, long long* counts, double* moments, hipStream_t s) {
+  hipError_t e;
   if (n == 0) return hipSuccess;
   if (d == 64 || d == 128) {
     // d = 128 draws the sub-labels in their own pass (registers), then counts
@@ -906,14 +906,14 @@ hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, con
     const long long nw = (n + rpw - 1) / rpw;
     const unsigned grid = (unsigned)((nw + 3) / 4);
     const size_t lds = (size_t)4 * 64 * (d + 1) * sizeof(float);
-#define DPMM_SUBW_CASE(DD)                                                                                    \
-  case DD:                                                                                                    \
-    if (sample)                                                                                               \
-      hipLaunchKernelGGL((k_sub_stats_w<DD, true>), dim3(grid), dim3(BLOCK), lds, s, x, n, rpw, perm, z, zsub, \
-                         packed, K, k_max, t, seed, counts, moments);                                         \
-    else                                                                                                      \
-      hipLaunchKernelGGL((k_sub_stats_w<DD, false>), dim3(grid), dim3(BLOCK), lds, s, x, n, rpw, perm, z,     \
-                         zsub, packed, K, k_max, t, seed, counts, moments);                                   \
+#define DPMM_SUBW_CASE(DD)                                                                                      \
+  case DD:                                                                                                      \
+    if (sample)                                                                                                 \
+      hipLaunchKernelGGL((k_sub_stats_w<DD, true>), dim3(grid), dim3(BLOCK), lds, s, x, npts, n, rpw, perm, z,  \
+                         zsub, packed, K, k_max, t, seed, counts, moments);                                     \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_sub_stats_w<DD, false>), dim3(grid), dim3(BLOCK), lds, s, x, npts, n, rpw, perm, z, \
+                         zsub, packed, K, k_max, t, seed, counts, moments);                                     \
     break;
     switch (d) {
       DPMM_SUBW_CASE(8)
@@ -925,6 +925,40 @@ hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, con
   }
   return sample ? launch_sub_stats_t<true>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, s)
                 : launch_sub_stats_t<false>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, s);
+}
+
+}  // namespace
+
+hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, const int* perm, const int* z,
+                            unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t, uint64_t seed,
+                            long long* counts, double* moments, hipStream_t s) {
+  const int E = d + d * (d + 1) / 2;
+  hipError_t e = launch_zero64(counts, (size_t)2 * K, s);
+  if (e != hipSuccess) return e;
+  e = launch_zero64(moments, (size_t)2 * K * E, s);
+  if (e != hipSuccess) return e;
+  return sub_stats_kernels(d, sample, x, n, n, perm, z, zsub, packed, K, k_max, t, seed, counts, moments, s);
+}
+
+bool partition_stats_supported(int d) { return d == 8 || d == 16 || d == 32 || d == 64 || d == 128; }
+
+// The listed points idx[0, nsel) all belong to cluster k1; side[i] in {0, 1}
+// plays the sub-label, so the sorted-order kernels leave the statistics of
+// side h in segment 2 k1 + h of the arrays they are given.  Shifting the base
+// pointers by slot - 2 k1 segments puts them in counts[slot + h] and
+// moments[(slot + h) E] and touches nothing else.
+hipError_t launch_partition_stats(int d, const float* x, long long npts, const int* idx, long long nsel,
+                                  const int* z, int k1, int K, const unsigned char* side, int slot,
+                                  long long* counts, double* moments, hipStream_t s) {
+  if (!partition_stats_supported(d) || k1 < 0 || k1 >= K || slot < 2 * k1) return hipErrorInvalidValue;
+  const int E = d + d * (d + 1) / 2;
+  hipError_t e = launch_zero64(counts + slot, 2, s);
+  if (e != hipSuccess) return e;
+  e = launch_zero64(moments + (size_t)slot * E, (size_t)2 * E, s);
+  if (e != hipSuccess) return e;
+  const long long shift = (long long)slot - 2 * k1;
+  return sub_stats_kernels(d, false, x, npts, nsel, idx, z, const_cast<unsigned char*>(side), nullptr, K, 0, 0, 0,
+                           counts + shift, moments + shift * E, s);
 }
 
 }  // namespace dpmm
