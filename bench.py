@@ -34,7 +34,7 @@ PEAK_BF16_MFMA = 2.5e15    # dense BF16 matrix-core peak
 # HBM bytes per launch of the sorted sub-label/statistics kernel at this
 # workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a device copy of
 # known size (profiles/traffic_gauss_d32_n1e6.md); None once the kernel changes
-MEASURED_TRAFFIC = {"k_sub_stats_w<32,true>": None}
+MEASURED_TRAFFIC = {"k_sub_stats_w<32,true>": 203.2e6, "k_label_gauss_mfma32<false,false>": 133.2e6}
 
 
 def flops_per_eval(d):
@@ -351,7 +351,8 @@ def main():
                   "algorithmic_flops_per_point": stats_flops,
                   "hbm_bytes_per_point": 4 * d + 4 + 4 + 1}
     stats_roof["traffic"] = MEASURED_TRAFFIC.get("k_sub_stats_w<32,true>")
-    label_roof["traffic"] = None
+    label_roof["traffic"] = (MEASURED_TRAFFIC.get("k_label_gauss_mfma32<false,false>")
+                             if args.precision == "bf16" else None)
     roof, other = (stats_roof, label_roof) if stats_s > label_s else (label_roof, stats_roof)
     out = {
         "metric": "point-cluster evals/s in label step; iters/s; time-to-plateau learned vs plain",

@@ -670,17 +670,19 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
     }
     attr_set = true;
   }
-  // the main pass, then the candidate pass over the points it deferred (same grid)
+  // the main pass, then the candidate pass over the points it deferred (grid-strided,
+  // about 2048 waves: usually it finds none)
   for (int pass = 0; pass < 2; ++pass) {
     const bool cands = pass == 1;
+    const int Gp = cands ? (d == 32 ? (G < 256 ? G : 256) : (G < 512 ? G : 512)) : G;
     if (d == 64 || d == 128) {
       const int NF = (d / 32) * (d / 16) * 64;
       const size_t lds = 2 * ((size_t)(x3 ? 2 : 1) * NF * sizeof(bf16x8) + (d + 4) * sizeof(float)) + lh;
 #define DPMM_MFMA_LDS(DD, XX, CC)                                                                           \
-  hipLaunchKernelGGL((k_label_gauss_mfma_lds<DD, XX, CC>), dim3(G), dim3(BLOCK), lds, s, x, n, per_block, packed, \
+  hipLaunchKernelGGL((k_label_gauss_mfma_lds<DD, XX, CC>), dim3(Gp), dim3(BLOCK), lds, s, x, n, per_block, packed, \
                      hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
 #define DPMM_MFMA_LDS_C(DD)                                                                                   \
-  hipLaunchKernelGGL((k_label_gauss_mfma_lds<DD, true, true>), dim3(G), dim3(BLOCK), lds_c, s, x, n, per_block,  \
+  hipLaunchKernelGGL((k_label_gauss_mfma_lds<DD, true, true>), dim3(Gp), dim3(BLOCK), lds_c, s, x, n, per_block, \
                      packed, hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
       // the candidate pass scores in bf16x3 whatever the main pass's form
       const size_t lds_c = 2 * ((size_t)2 * NF * sizeof(bf16x8) + (d + 4) * sizeof(float)) + lh;
@@ -696,7 +698,7 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
       // the candidate pass scores in bf16x3
       const size_t lds = (size_t)65536 + (size_t)(x3 || cands ? 16 : 32) * (d + 4) * sizeof(float) + lh;
 #define DPMM_MFMA32(XX, CC)                                                                                 \
-  hipLaunchKernelGGL((k_label_gauss_mfma32<XX, CC>), dim3(G), dim3(BLOCK32), lds, s, x, n, per_block, packed, hi, \
+  hipLaunchKernelGGL((k_label_gauss_mfma32<XX, CC>), dim3(Gp), dim3(BLOCK32), lds, s, x, n, per_block, packed, hi, \
                      lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
       if (cands)
         DPMM_MFMA32(true, true);
