@@ -72,12 +72,18 @@ dpmm_status ensure_perm(dpmm_ctx* ctx, int64_t n) {
   if (ctx->d_perm) {
     DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
     hipFree(ctx->d_perm);
+    hipFree(ctx->d_zsort);
     hipFree(ctx->d_cand);
     ctx->d_perm = nullptr;
+    ctx->d_zsort = nullptr;
     ctx->d_cand = nullptr;
     ctx->perm_cap = 0;
   }
   DPMM_HIP(ctx, hipMalloc(&ctx->d_perm, (size_t)n * sizeof(int)), "allocate permutation");
+  DPMM_HIP(ctx, hipMalloc(&ctx->d_zsort, (size_t)n * sizeof(int)), "allocate sorted labels");
+  if (!ctx->d_part && sub_stats_part_doubles(ctx->d) > 0)
+    DPMM_HIP(ctx, hipMalloc(&ctx->d_part, sub_stats_part_doubles(ctx->d) * sizeof(double)),
+             "allocate partial statistics");
   // candidate lists of the points the matrix-core label kernels defer
   if (ctx->d_nflag)
     DPMM_HIP(ctx, hipMalloc(&ctx->d_cand, (size_t)n * RESCORE_CAND * sizeof(int)), "allocate candidate lists");
@@ -90,10 +96,11 @@ dpmm_status sorted_pass(dpmm_ctx* ctx, const void* x, int64_t n, bool labels_don
                         const int32_t* z, uint8_t* zsub, int G, long long per_block) {
   DPMM_TRY(ensure_perm(ctx, n));
   DPMM_HIP(ctx, launch_sort_by_z(z, n, ctx->K, G, per_block, labels_done_hist, ctx->d_hist, ctx->d_tot, ctx->d_offs,
-                                 ctx->d_perm, ctx->stream), "sort by cluster");
+                                 ctx->d_perm, ctx->d_zsort, ctx->stream), "sort by cluster");
   if (ctx->timing) DPMM_HIP(ctx, hipEventRecord(ctx->ev[3], ctx->stream), "event");
-  DPMM_HIP(ctx, launch_sub_stats(ctx->d, sample, (const float*)x, n, ctx->d_perm, z, zsub, ctx->d_packed, ctx->K,
-                                 ctx->cfg.k_max, t, ctx->cfg.seed, ctx->d_counts, ctx->d_moments, ctx->stream),
+  DPMM_HIP(ctx, launch_sub_stats(ctx->d, sample, (const float*)x, n, ctx->d_perm, z, ctx->d_zsort, zsub, ctx->d_packed,
+                                 ctx->K, ctx->cfg.k_max, t, ctx->cfg.seed, ctx->d_counts, ctx->d_moments, ctx->d_offs,
+                                 ctx->d_tot, ctx->d_part, ctx->stream),
            "sub-label / statistics kernel");
   ctx->have_stats = true;
   return DPMM_OK;
@@ -401,6 +408,8 @@ void dpmm_destroy(dpmm_ctx* ctx) {
   else hipDeviceSynchronize();
   for (auto& b : ctx->bufs) hipFree(b.p);
   if (ctx->d_perm) hipFree(ctx->d_perm);
+  if (ctx->d_zsort) hipFree(ctx->d_zsort);
+  if (ctx->d_part) hipFree(ctx->d_part);
   if (ctx->d_cand) hipFree(ctx->d_cand);
   if (ctx->d_sel) hipFree(ctx->d_sel);
   if (ctx->d_side) hipFree(ctx->d_side);

@@ -66,6 +66,8 @@ struct dpmm_ctx {
   RelabelEntry* d_table = nullptr;
   // cluster-sorted path (Gaussian, d >= dpmm::SORTED_MIN_D)
   int *d_hist = nullptr, *d_offs = nullptr, *d_tot = nullptr, *d_perm = nullptr;
+  int* d_zsort = nullptr;  // [perm_cap] the cluster of each row of the sorted order
+  double* d_part = nullptr;  // partial statistics slots of the d <= 32 statistics kernel
   long long hist_cap = 0, perm_cap = 0;
   bool labels_gave_stats = false;
   // BF16 whitener fragments of the cluster components (precision != FP32)

@@ -91,10 +91,17 @@ hipError_t launch_label_gauss_z(int d, const float* x, long long n, int G, long 
                                 int K, uint32_t t, uint64_t seed, int* z, int* hist, int* tot, hipStream_t s);
 hipError_t sorted_plan(long long n, int K, long long hist_cap, int* G, long long* per_block);
 hipError_t launch_sort_by_z(const int* z, long long n, int K, int G, long long per_block, bool have_hist, int* hist,
-                            int* tot, int* offs, int* perm, hipStream_t s);
+                            int* tot, int* offs, int* perm, int* zsort, hipStream_t s);
+// waves of the d <= 32 statistics kernel; in slot mode (cstart = the clusters'
+// first sorted rows, ctot their sizes, part = sub_stats_part_doubles(d)
+// doubles) every cluster's statistics are written, with no atomics
+constexpr int SUBW_WAVES = 2048;
+bool sub_stats_slot_mode(int d);
+size_t sub_stats_part_doubles(int d);
 hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, const int* perm, const int* z,
-                            unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t, uint64_t seed,
-                            long long* counts, double* moments, hipStream_t s);
+                            const int* zrow, unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t,
+                            uint64_t seed, long long* counts, double* moments, const int* cstart, const int* ctot,
+                            double* part, hipStream_t s);
 // statistics of a listed set of cluster k1's points split by side[i] into
 // segments slot, slot + 1 (slot >= 2 k1; d in {8, 16, 32, 64, 128})
 bool partition_stats_supported(int d);

@@ -5,7 +5,8 @@
 //   k_hist_z     per-block histogram of z over contiguous point ranges (only
 //                when the label kernel did not produce it);
 //   k_scan_hist  per-(block, cluster) output offsets;
-//   k_scatter_z  perm[offset] = i.
+//   k_scatter_z  perm[offset] = i, zsort[offset] = z_i (the cluster of each
+//                sorted row, read coalesced by the kernels below).
 // Then k_sub_stats walks the sorted order in tiles of TR rows.  A tile holds
 // one or a few clusters, so sub-cluster scoring reads the two sub-cluster
 // records of a cluster with wave-uniform (scalar) loads instead of per-lane
@@ -92,7 +93,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_hist(const int* __restrict__ his
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scatter_z(const int* __restrict__ z, long long n, long long per_block,
-                                                     int K, const int* __restrict__ offs, int* __restrict__ perm) {
+                                                     int K, const int* __restrict__ offs, int* __restrict__ perm,
+                                                     int* __restrict__ zsort) {
   extern __shared__ int cur[];
   for (int k = threadIdx.x; k < K; k += BLOCK) cur[k] = offs[(size_t)blockIdx.x * K + k];
   __syncthreads();
@@ -100,7 +102,11 @@ __global__ __launch_bounds__(BLOCK) void k_scatter_z(const int* __restrict__ z, 
   const long long end = begin + per_block < n ? begin + per_block : n;
   for (long long i = begin + threadIdx.x; i < end; i += BLOCK) {
     const int zi = z[i];
-    if ((unsigned)zi < (unsigned)K) perm[atomicAdd(&cur[zi], 1)] = (int)i;
+    if ((unsigned)zi < (unsigned)K) {
+      const int pos = atomicAdd(&cur[zi], 1);
+      perm[pos] = (int)i;
+      zsort[pos] = zi;
+    }
   }
 }
 
@@ -357,10 +363,12 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
 template <int D, bool SAMPLE>
 __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__ x, long long npts, long long n_sorted,
                                                        long long rows_per_wave, const int* __restrict__ perm,
-                                                       const int* __restrict__ z, unsigned char* __restrict__ zsub,
+                                                       const int* __restrict__ z, const int* __restrict__ zrow,
+                                                       unsigned char* __restrict__ zsub,
                                                        const float* __restrict__ packed, int K, int k_max, uint32_t t,
                                                        uint64_t seed, long long* __restrict__ counts,
-                                                       double* __restrict__ moments) {
+                                                       double* __restrict__ moments, const int* __restrict__ cstart,
+                                                       const int* __restrict__ ctot, double* __restrict__ part) {
   constexpr int NB = (D + 15) / 16;  // 16-wide blocks of dimensions
   constexpr int NBLK = NB * (NB + 1) / 2;
   constexpr int LDW = D + 1;  // odd row stride
@@ -382,9 +390,16 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
     for (int b = 0; b < NB; ++b) sL[b] = sR[b] = 0.0;
     nL = nR = 0;
   };
-  // lane l holds element j of block (I, J) at row 16 I + l / 16 + 4 j, column 16 J + l % 16
-  auto flush_one = [&](f64x4 (&c)[NBLK], double (&sx)[NB], long long cnt, int seg) {
-    double* M = moments + (size_t)seg * E;
+  const long long gw = (long long)blockIdx.x * (BLOCK / 64) + wave;
+  const long long w_begin = gw * rows_per_wave;
+  const long long w_end = w_begin + rows_per_wave < n_sorted ? w_begin + rows_per_wave : n_sorted;
+  int k_first = -1;  // cluster of the wave's first row (partial-slot mode)
+  // lane l holds element j of block (I, J) at row 16 I + l / 16 + 4 j, column 16 J + l % 16.
+  // Atomic mode (part == nullptr): added to counts[seg], moments[seg].  Slot mode:
+  // stored to M (moments layout) and *cnt_out, either the final arrays (the
+  // cluster lies in this wave's rows) or a partial slot that k_sub_stats_fix sums.
+  auto flush_one = [&](f64x4 (&c)[NBLK], double (&sx)[NB], long long cnt, double* M, long long* cnt_out,
+                       double* cnt_d, bool atomic) {
     int blk = 0;
 #pragma unroll
     for (int I = 0; I < NB; ++I)
@@ -393,21 +408,53 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int a = 16 * I + (lane >> 4) + 4 * j, b = 16 * J + col;
-          if (a <= b && b < D) atomicAdd(&M[D + a * D - (a * (a - 1)) / 2 + (b - a)], c[blk][j]);
+          if (a <= b && b < D) {
+            double* dst = &M[D + a * D - (a * (a - 1)) / 2 + (b - a)];
+            if (atomic)
+              atomicAdd(dst, c[blk][j]);
+            else
+              *dst = c[blk][j];
+          }
         }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       double v = sx[b];
       v += __shfl_xor(v, 16);
       v += __shfl_xor(v, 32);
-      if (lane < 16 && 16 * b + lane < D) atomicAdd(&M[16 * b + lane], v);
+      if (lane < 16 && 16 * b + lane < D) {
+        if (atomic)
+          atomicAdd(&M[16 * b + lane], v);
+        else
+          M[16 * b + lane] = v;
+      }
     }
-    if (lane == 0) atomicAdd((unsigned long long*)&counts[seg], (unsigned long long)cnt);
+    if (lane == 0) {
+      if (atomic)
+        atomicAdd((unsigned long long*)cnt_out, (unsigned long long)cnt);
+      else if (cnt_out)
+        *cnt_out = cnt;
+      else
+        *cnt_d = (double)cnt;
+    }
   };
   auto flush = [&]() {
     if (cur_k < 0) return;
-    if (nL) flush_one(cL, sL, nL, 2 * cur_k);
-    if (nR) flush_one(cR, sR, nR, 2 * cur_k + 1);
+    if (!part) {
+      if (nL) flush_one(cL, sL, nL, moments + (size_t)(2 * cur_k) * E, &counts[2 * cur_k], nullptr, true);
+      if (nR) flush_one(cR, sR, nR, moments + (size_t)(2 * cur_k + 1) * E, &counts[2 * cur_k + 1], nullptr, true);
+      return;
+    }
+    const long long cs = cstart[cur_k], ce = cs + ctot[cur_k];
+    if (cs >= w_begin && ce <= w_end) {
+      // the whole cluster is this wave's: final values, both segments
+      flush_one(cL, sL, nL, moments + (size_t)(2 * cur_k) * E, &counts[2 * cur_k], nullptr, false);
+      flush_one(cR, sR, nR, moments + (size_t)(2 * cur_k + 1) * E, &counts[2 * cur_k + 1], nullptr, false);
+    } else {
+      // slot 2 gw: the wave's first cluster; 2 gw + 1: its last (when different); each [2][1 + E]
+      double* P = part + (size_t)(2 * gw + (cur_k == k_first ? 0 : 1)) * 2 * (E + 1);
+      flush_one(cL, sL, nL, P + 1, nullptr, P, false);
+      flush_one(cR, sR, nR, P + (E + 1) + 1, nullptr, P + (E + 1), false);
+    }
   };
   // rows [s0, e0) of the wave's LDS tile, four at a time: A = B = the rows' block of dimensions
   auto mfma_rows = [&](f64x4 (&c)[NBLK], double (&sx)[NB], int s0, int e0) {
@@ -427,9 +474,6 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
     }
   };
   zero_acc();
-  const long long gw = (long long)blockIdx.x * (BLOCK / 64) + wave;
-  const long long w_begin = gw * rows_per_wave;
-  const long long w_end = w_begin + rows_per_wave < n_sorted ? w_begin + rows_per_wave : n_sorted;
   for (long long c0 = w_begin; c0 < w_end; c0 += 64) {
     const long long r = c0 + lane;
     bool valid = r < w_end;
@@ -440,7 +484,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
       i = perm[r];
       // a label outside [0, K) leaves its row out (and never reaches memory)
       valid = (unsigned long long)i < (unsigned long long)npts;
-      if (valid) k = z[i];
+      if (valid) k = zrow ? zrow[r] : z[i];
       valid = valid && (unsigned)k < (unsigned)K;
     }
     if (valid) {
@@ -503,6 +547,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
       if (kk != cur_k) {
         flush();
         zero_acc();
+        if (cur_k < 0) k_first = kk;
         cur_k = kk;
       }
       const int cl = __popcll(mk & ~right), cr = __popcll(mk & right);
@@ -514,6 +559,44 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
     }
   }
   flush();
+}
+
+// Slot mode of k_sub_stats_w: the counts and moments of every cluster whose
+// rows span several waves are the sums of those waves' partial slots (2 g for
+// the wave's first cluster, 2 g + 1 for its last); empty clusters get zeros;
+// a cluster inside one wave was written by it.  Grid (entries / FIX_EN, K):
+// FIX_PH phases of threads take every FIX_PH-th slot of FIX_EN entries, and
+// their sums are added in a fixed order (the result does not depend on timing).
+constexpr int FIX_PH = 16, FIX_EN = 16;
+__global__ __launch_bounds__(FIX_PH * FIX_EN) void k_sub_stats_fix(int E, long long rpw, const int* __restrict__ cstart,
+                                                                 const int* __restrict__ ctot,
+                                                                 const double* __restrict__ part,
+                                                                 long long* __restrict__ counts,
+                                                                 double* __restrict__ moments) {
+  __shared__ double red[FIX_PH][FIX_EN];
+  const int k = blockIdx.y;
+  const int W = 2 * (E + 1);
+  const int el = threadIdx.x % FIX_EN, ph = threadIdx.x / FIX_EN;
+  const int e = blockIdx.x * FIX_EN + el;
+  const long long cs = cstart[k], cnt = ctot[k];
+  const long long ga = cnt > 0 ? cs / rpw : 0, gb = cnt > 0 ? (cs + cnt - 1) / rpw : -1;
+  if (cnt > 0 && ga == gb) return;  // written by the wave that holds it (uniform over the block)
+  double v = 0.0;
+  if (e < W) {
+#pragma unroll 4
+    for (long long g = ga + ph; g <= gb; g += FIX_PH)
+      v += part[(size_t)(2 * g + (g == ga && cs != g * rpw ? 1 : 0)) * W + e];
+  }
+  red[ph][el] = v;
+  __syncthreads();
+  if (ph != 0 || e >= W) return;
+  double sum = 0.0;
+  for (int q = 0; q < FIX_PH; ++q) sum += red[q][el];
+  const int h = e / (E + 1), f = e - h * (E + 1);
+  if (f == 0)
+    counts[2 * k + h] = (long long)sum;  // a sum of integer counts below 2^53: exact
+  else
+    moments[(size_t)(2 * k + h) * E + (f - 1)] = sum;
 }
 
 namespace {
@@ -592,6 +675,7 @@ __device__ __forceinline__ int block_inclusive_scan_big(int v, int* buf) {
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_sub_labels_big(const float* __restrict__ x, long long n_sorted,
                                                           const int* __restrict__ perm, const int* __restrict__ z,
+                                                          const int* __restrict__ zrow,
                                                           unsigned char* __restrict__ zsub,
                                                           const float* __restrict__ packed, int k_max, uint32_t t,
                                                           uint64_t seed) {
@@ -599,7 +683,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_labels_big(const float* __restric
   const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
   const bool valid = g < n_sorted;
   const int i = valid ? perm[g] : 0;
-  const int k = valid ? z[i] : -1;
+  const int k = valid ? (zrow ? zrow[g] : z[i]) : -1;
   float delta = 0.0f;
   unsigned long long pending = __ballot(valid);
   while (pending) {
@@ -638,6 +722,7 @@ template <int D, bool SAMPLE>
 __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __restrict__ x, long long n_sorted,
                                                                int tpb, const int* __restrict__ perm,
                                                                const int* __restrict__ z,
+                                                               const int* __restrict__ zrow,
                                                                unsigned char* __restrict__ zsub,
                                                                const float* __restrict__ packed, int k_max,
                                                                uint32_t t, uint64_t seed,
@@ -708,7 +793,7 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
     int my_i = 0, k = -1;
     if (valid) {
       my_i = perm[base + tid];
-      k = z[my_i];
+      k = zrow ? zrow[base + tid] : z[my_i];
       rk[tid] = k;
       order[tid] = my_i;
     }
@@ -839,7 +924,7 @@ hipError_t sorted_plan(long long n, int K, long long hist_cap, int* G, long long
 }
 
 hipError_t launch_sort_by_z(const int* z, long long n, int K, int G, long long per_block, bool have_hist, int* hist,
-                            int* tot, int* offs, int* perm, hipStream_t s) {
+                            int* tot, int* offs, int* perm, int* zsort, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipError_t e;
   if (!have_hist) {
@@ -850,7 +935,8 @@ hipError_t launch_sort_by_z(const int* z, long long n, int K, int G, long long p
   }
   hipLaunchKernelGGL(k_scan_hist, dim3(K), dim3(BLOCK), 0, s, hist, G, K, tot, offs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scatter_z, dim3(G), dim3(BLOCK), (size_t)K * sizeof(int), s, z, n, per_block, K, offs, perm);
+  hipLaunchKernelGGL(k_scatter_z, dim3(G), dim3(BLOCK), (size_t)K * sizeof(int), s, z, n, per_block, K, offs, perm,
+                     zsort);
   return hipGetLastError();
 }
 
@@ -859,16 +945,17 @@ namespace {
 // The statistics kernels over rows perm[0, n) (point indices below npts),
 // accumulating into counts / moments (which the caller has zeroed).
 hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts, long long n, const int* perm,
-                             const int* z, unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t,
-                             uint64_t seed, long long* counts, double* moments, hipStream_t s) {
+                             const int* z, const int* zrow, unsigned char* zsub, const float* packed, int K, int k_max,
+                             uint32_t t, uint64_t seed, long long* counts, double* moments, const int* cstart,
+                             const int* ctot, double* part, hipStream_t s) {
   hipError_t e;
   if (n == 0) return hipSuccess;
   if (d == 64 || d == 128) {
     // d = 128 draws the sub-labels in their own pass (registers), then counts
     if (sample && d == 128) {
       const unsigned lg = (unsigned)((n + BLOCK - 1) / BLOCK);
-      hipLaunchKernelGGL(k_sub_labels_big<128>, dim3(lg), dim3(BLOCK), 0, s, x, n, perm, z, zsub, packed, k_max, t,
-                         seed);
+      hipLaunchKernelGGL(k_sub_labels_big<128>, dim3(lg), dim3(BLOCK), 0, s, x, n, perm, z, zrow, zsub, packed, k_max,
+                         t, seed);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const long long tiles = (n + BIG_ROWS - 1) / BIG_ROWS;
@@ -889,18 +976,18 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
     }
     if (d == 64 && sample)
       hipLaunchKernelGGL((k_sub_stats_big<64, true>), dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z,
-                         zsub, packed, k_max, t, seed, counts, moments);
+                         zrow, zsub, packed, k_max, t, seed, counts, moments);
     else if (d == 64)
       hipLaunchKernelGGL((k_sub_stats_big<64, false>), dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z,
-                         zsub, packed, k_max, t, seed, counts, moments);
+                         zrow, zsub, packed, k_max, t, seed, counts, moments);
     else
       hipLaunchKernelGGL((k_sub_stats_big<128, false>), dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z,
-                         zsub, packed, k_max, t, seed, counts, moments);
+                         zrow, zsub, packed, k_max, t, seed, counts, moments);
     return hipGetLastError();
   }
   if (d == 8 || d == 16 || d == 32) {
     // about eight waves per CU, each on a contiguous range of whole 64-row chunks
-    const long long waves = 2048;
+    const long long waves = SUBW_WAVES;
     long long rpw = (n + waves - 1) / waves;
     rpw = ((rpw + 63) / 64) * 64;
     const long long nw = (n + rpw - 1) / rpw;
@@ -910,10 +997,10 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
   case DD:                                                                                                      \
     if (sample)                                                                                                 \
       hipLaunchKernelGGL((k_sub_stats_w<DD, true>), dim3(grid), dim3(BLOCK), lds, s, x, npts, n, rpw, perm, z,  \
-                         zsub, packed, K, k_max, t, seed, counts, moments);                                     \
+                         zrow, zsub, packed, K, k_max, t, seed, counts, moments, cstart, ctot, part);           \
     else                                                                                                        \
       hipLaunchKernelGGL((k_sub_stats_w<DD, false>), dim3(grid), dim3(BLOCK), lds, s, x, npts, n, rpw, perm, z, \
-                         zsub, packed, K, k_max, t, seed, counts, moments);                                     \
+                         zrow, zsub, packed, K, k_max, t, seed, counts, moments, cstart, ctot, part);           \
     break;
     switch (d) {
       DPMM_SUBW_CASE(8)
@@ -921,7 +1008,14 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
       DPMM_SUBW_CASE(32)
     }
 #undef DPMM_SUBW_CASE
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (part) {
+      const int E = d + d * (d + 1) / 2;
+      hipLaunchKernelGGL(k_sub_stats_fix, dim3((2 * (E + 1) + FIX_EN - 1) / FIX_EN, K), dim3(FIX_PH * FIX_EN), 0, s, E,
+                         rpw, cstart, ctot, part, counts, moments);
+      return hipGetLastError();
+    }
+    return hipSuccess;
   }
   return sample ? launch_sub_stats_t<true>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, s)
                 : launch_sub_stats_t<false>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, s);
@@ -929,15 +1023,27 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
 
 }  // namespace
 
-hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, const int* perm, const int* z,
-                            unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t, uint64_t seed,
-                            long long* counts, double* moments, hipStream_t s) {
+bool sub_stats_slot_mode(int d) { return d == 8 || d == 16 || d == 32; }
+
+size_t sub_stats_part_doubles(int d) {
   const int E = d + d * (d + 1) / 2;
+  return sub_stats_slot_mode(d) ? (size_t)2 * SUBW_WAVES * 2 * (E + 1) : 0;
+}
+
+hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, const int* perm, const int* z,
+                            const int* zrow, unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t,
+                            uint64_t seed, long long* counts, double* moments, const int* cstart, const int* ctot,
+                            double* part, hipStream_t s) {
+  const int E = d + d * (d + 1) / 2;
+  if (n > 0 && part && sub_stats_slot_mode(d))  // every cluster's entries are written: no zeroing
+    return sub_stats_kernels(d, sample, x, n, n, perm, z, zrow, zsub, packed, K, k_max, t, seed, counts, moments,
+                             cstart, ctot, part, s);
   hipError_t e = launch_zero64(counts, (size_t)2 * K, s);
   if (e != hipSuccess) return e;
   e = launch_zero64(moments, (size_t)2 * K * E, s);
   if (e != hipSuccess) return e;
-  return sub_stats_kernels(d, sample, x, n, n, perm, z, zsub, packed, K, k_max, t, seed, counts, moments, s);
+  return sub_stats_kernels(d, sample, x, n, n, perm, z, zrow, zsub, packed, K, k_max, t, seed, counts, moments,
+                           nullptr, nullptr, nullptr, s);
 }
 
 bool partition_stats_supported(int d) { return d == 8 || d == 16 || d == 32 || d == 64 || d == 128; }
@@ -957,8 +1063,8 @@ hipError_t launch_partition_stats(int d, const float* x, long long npts, const i
   e = launch_zero64(moments + (size_t)slot * E, (size_t)2 * E, s);
   if (e != hipSuccess) return e;
   const long long shift = (long long)slot - 2 * k1;
-  return sub_stats_kernels(d, false, x, npts, nsel, idx, z, const_cast<unsigned char*>(side), nullptr, K, 0, 0, 0,
-                           counts + shift, moments + shift * E, s);
+  return sub_stats_kernels(d, false, x, npts, nsel, idx, z, nullptr, const_cast<unsigned char*>(side), nullptr, K, 0,
+                           0, 0, counts + shift, moments + shift * E, nullptr, nullptr, nullptr, s);
 }
 
 }  // namespace dpmm
