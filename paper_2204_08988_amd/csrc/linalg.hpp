@@ -2,6 +2,10 @@
 // LDS (or global scratch), row-major.  All are right-looking: at step j the
 // whole workgroup updates the trailing part in parallel, so every step costs a
 // few barriers and independent LDS accesses instead of a serial dot product.
+// Threads form rows of 32 (tx = column lane, ty = row lane), so the loops over
+// a block of the matrix need no integer division (the workgroup size is a
+// multiple of 32).  Every element receives the same sequence of updates as in
+// a serial right-looking loop.
 #pragma once
 #include "common.hpp"
 
@@ -11,6 +15,7 @@ namespace dpmm {
 // Returns false (on every thread) if a pivot is not positive and finite.
 __device__ inline bool wg_cholesky(double* a, int d, int* flag) {
   const int tid = threadIdx.x, nt = blockDim.x;
+  const int tx = tid & 31, ty = tid >> 5, nty = nt >> 5;
   if (tid == 0) *flag = 1;
   __syncthreads();
   for (int j = 0; j < d; ++j) {
@@ -27,17 +32,14 @@ __device__ inline bool wg_cholesky(double* a, int d, int* flag) {
     for (int i = j + 1 + tid; i < d; i += nt) a[i * d + j] *= inv;
     __syncthreads();
     // trailing update of the lower triangle: a_ik -= a_ij a_kj, j < k <= i
-    const int m = d - j - 1;
-    for (int idx = tid; idx < m * m; idx += nt) {
-      const int i = j + 1 + idx / m, k = j + 1 + idx % m;
-      if (k <= i) a[i * d + k] -= a[i * d + j] * a[k * d + j];
+    for (int i = j + 1 + ty; i < d; i += nty) {
+      const double aij = a[i * d + j];
+      for (int k = j + 1 + tx; k <= i; k += 32) a[i * d + k] -= aij * a[k * d + j];
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < d * d; idx += nt) {
-    const int i = idx / d, j = idx % d;
-    if (j > i) a[idx] = 0.0;
-  }
+  for (int i = ty; i < d; i += nty)
+    for (int j = i + 1 + tx; j < d; j += 32) a[i * d + j] = 0.0;
   __syncthreads();
   const bool ok = *flag != 0;
   __syncthreads();
@@ -47,7 +49,9 @@ __device__ inline bool wg_cholesky(double* a, int d, int* flag) {
 // W = G^-1 for lower-triangular G (W lower triangular), W must not alias G.
 __device__ inline void wg_lower_inverse(const double* G, double* W, int d) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int idx = tid; idx < d * d; idx += nt) W[idx] = (idx / d == idx % d) ? 1.0 : 0.0;
+  const int tx = tid & 31, ty = tid >> 5, nty = nt >> 5;
+  for (int i = ty; i < d; i += nty)
+    for (int c = tx; c < d; c += 32) W[i * d + c] = i == c ? 1.0 : 0.0;
   __syncthreads();
   // forward elimination on [G | I] one row at a time: row j of W is final
   // after dividing by G_jj; it is then eliminated from the rows below.
@@ -55,10 +59,9 @@ __device__ inline void wg_lower_inverse(const double* G, double* W, int d) {
     const double inv = 1.0 / G[j * d + j];
     for (int c = tid; c <= j; c += nt) W[j * d + c] *= inv;
     __syncthreads();
-    const int m = d - j - 1;
-    for (int idx = tid; idx < m * (j + 1); idx += nt) {
-      const int i = j + 1 + idx / (j + 1), c = idx % (j + 1);
-      W[i * d + c] -= G[i * d + j] * W[j * d + c];
+    for (int i = j + 1 + ty; i < d; i += nty) {
+      const double gij = G[i * d + j];
+      for (int c = tx; c <= j; c += 32) W[i * d + c] -= gij * W[j * d + c];
     }
     __syncthreads();
   }
@@ -69,14 +72,14 @@ __device__ inline void wg_lower_inverse(const double* G, double* W, int d) {
 // columns, F[:, q] -= F[:, j] A[q][j] for q > j.
 __device__ inline void wg_right_solve_lower_t(double* F, const double* A, int d) {
   const int tid = threadIdx.x, nt = blockDim.x;
+  const int tx = tid & 31, ty = tid >> 5, nty = nt >> 5;
   for (int j = 0; j < d; ++j) {
     const double inv = 1.0 / A[j * d + j];
     for (int r = tid; r < d; r += nt) F[r * d + j] *= inv;
     __syncthreads();
-    const int m = d - j - 1;
-    for (int idx = tid; idx < d * m; idx += nt) {
-      const int r = idx / m, q = j + 1 + idx % m;
-      F[r * d + q] -= F[r * d + j] * A[q * d + j];
+    for (int r = ty; r < d; r += nty) {
+      const double frj = F[r * d + j];
+      for (int q = j + 1 + tx; q < d; q += 32) F[r * d + q] -= frj * A[q * d + j];
     }
     __syncthreads();
   }
