@@ -34,7 +34,7 @@ PEAK_BF16_MFMA = 2.5e15    # dense BF16 matrix-core peak
 # HBM bytes per launch of the sorted sub-label/statistics kernel at this
 # workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a device copy of
 # known size (profiles/traffic_gauss_d32_n1e6.md); None once the kernel changes
-MEASURED_TRAFFIC = {"k_sub_stats_w<32,true>": 203.2e6, "k_label_gauss_mfma32<false,false>": 133.2e6}
+MEASURED_TRAFFIC = {"k_sub_stats_w<32,true>": 162.5e6, "k_label_gauss_mfma32<false,false>": 133.3e6}
 
 
 def flops_per_eval(d):
