@@ -669,38 +669,155 @@ __device__ __forceinline__ int block_inclusive_scan_big(int v, int* buf) {
   return r;
 }
 
-// Sub-label draw of sorted rows, one row per thread (d = 128): the FP32
-// scores of the two sub-clusters of the row's cluster with wave-uniform
-// (scalar-loaded) parameters and the centred row in registers.
+// Sub-label draw of sorted rows on the FP32 matrix cores (d = 128), Sec. 4.1
+// step (f): the scores of the two sub-clusters of the row's cluster, from
+// Y = W_h (x - mu_h) with v_mfma_f32_32x32x2_f32 (A = W_h, B = the centred
+// rows).  A workgroup walks a contiguous range of sorted rows; the two records
+// of the current cluster are staged in LDS whenever the cluster changes.  A
+// wave scores 64 rows (two 32-row tiles): a lane holds half the coordinates of
+// one row, k = 2s + h at MFMA step s (h = lane / 32).  The rows are centred
+// once on mu_0; sub-cluster 1 starts its accumulators at W_1 (mu_0 - mu_1), so
+// that both products read the same centred rows.  Row blocks of W above the
+// diagonal are skipped (k <= 32 mt + 31 for output rows 32 mt ... 32 mt + 31)
+// and the entries above the diagonal inside a block are read as zero.
+constexpr int SUBL_BLOCK = 256;
+
 template <int D>
-__global__ __launch_bounds__(BLOCK) void k_sub_labels_big(const float* __restrict__ x, long long n_sorted,
-                                                          const int* __restrict__ perm, const int* __restrict__ z,
-                                                          const int* __restrict__ zrow,
-                                                          unsigned char* __restrict__ zsub,
-                                                          const float* __restrict__ packed, int k_max, uint32_t t,
-                                                          uint64_t seed) {
+__global__ __launch_bounds__(SUBL_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sub_labels_mfma(
+    const float* __restrict__ x, long long n_sorted, long long per_block, const int* __restrict__ perm,
+    const int* __restrict__ z, const int* __restrict__ zrow, unsigned char* __restrict__ zsub,
+    const float* __restrict__ packed, int k_max, uint32_t t, uint64_t seed) {
   constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
-  const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  const bool valid = g < n_sorted;
-  const int i = valid ? perm[g] : 0;
-  const int k = valid ? (zrow ? zrow[g] : z[i]) : -1;
-  float delta = 0.0f;
-  unsigned long long pending = __ballot(valid);
-  while (pending) {
-    const int lane0 = __ffsll((long long)pending) - 1;
-    const int kk = __builtin_amdgcn_readfirstlane(__shfl(k, lane0));
-    const bool mine = valid && k == kk;
-    if (mine) {
-      const float* ps = packed + (size_t)(k_max + 2 * kk) * S;
-      float sc[2];
-#pragma clang loop unroll(disable)
-      for (int h = 0; h < 2; ++h) sc[h] = score_lds<D>(ps + h * S, x + (size_t)i * D);
-      delta = sc[0] - sc[1];
+  constexpr int MT = D / 32, HALF = D / 2, QTR = D / 4;
+  static_assert(D % 64 == 0 && D <= SUBL_BLOCK, "layout");
+  typedef float f32x16 __attribute__((ext_vector_type(16)));
+  extern __shared__ __align__(16) float s_rec[];  // records of sub-clusters 0 and 1, then W_1 (mu_0 - mu_1), mu_0 - mu_1
+  float* s_corr = s_rec + 2 * S;
+  float* s_dmu = s_corr + D;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, col = lane & 31;
+  const long long begin = (long long)blockIdx.x * per_block;
+  const long long end = begin + per_block < n_sorted ? begin + per_block : n_sorted;
+  auto kof = [&](long long g) { return __builtin_amdgcn_readfirstlane(zrow ? zrow[g] : z[perm[g]]); };
+  int staged = -1;
+  for (long long chunk = begin; chunk < end; chunk += SUBL_BLOCK) {
+    const long long cend = chunk + SUBL_BLOCK < end ? chunk + SUBL_BLOCK : end;
+    const long long base = chunk + wave * 64;
+    const long long rA = base + col, rB = base + 32 + col;
+    const bool vA = rA < cend, vB = rB < cend;
+    const long long iA = vA ? perm[rA] : 0, iB = vB ? perm[rB] : 0;
+    const int kA = vA ? (zrow ? zrow[rA] : z[iA]) : -1, kB = vB ? (zrow ? zrow[rB] : z[iB]) : -1;
+    const int kmine = h ? kB : kA;
+    float delta = 0.0f;
+    int cur = kof(chunk);
+    const int last = kof(cend - 1);
+    for (;;) {
+      if (cur != staged) {
+        __syncthreads();  // every wave is done with the previous records
+        const float4* src = reinterpret_cast<const float4*>(packed + (size_t)(k_max + 2 * cur) * S);
+        float4* dst = reinterpret_cast<float4*>(s_rec);
+        for (int j = threadIdx.x; j < 2 * S / 4; j += SUBL_BLOCK) dst[j] = src[j];
+        __syncthreads();
+        if (threadIdx.x < D) s_dmu[threadIdx.x] = s_rec[4 + threadIdx.x] - s_rec[S + 4 + threadIdx.x];
+        __syncthreads();
+        if (threadIdx.x < D) {
+          const int i = threadIdx.x;
+          const float* w1 = s_rec + S + 4 + D + i * (i + 1) / 2;
+          float c = 0.0f;
+          for (int k = 0; k <= i; ++k) c = fmaf(w1[k], s_dmu[k], c);
+          s_corr[i] = c;
+        }
+        __syncthreads();
+        staged = cur;
+      }
+      if (__ballot(kA == cur || kB == cur)) {
+        // rows of the two tiles: lane h loads coordinates [HALF h, HALF h + HALF) and the two halves
+        // trade so that ra[2j] = x[2j + h], ra[2j + 1] = x[HALF + 2j + h], centred on mu_0
+        float ra[HALF], rb[HALF];
+        const float4* pa = reinterpret_cast<const float4*>(x + (size_t)iA * D + HALF * h);
+        const float4* pb = reinterpret_cast<const float4*>(x + (size_t)iB * D + HALF * h);
+#pragma unroll
+        for (int q = 0; q < HALF / 4; ++q) {
+          const float4 va = vA ? pa[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float4 vb = vB ? pb[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+          ra[4 * q] = va.x, ra[4 * q + 1] = va.y, ra[4 * q + 2] = va.z, ra[4 * q + 3] = va.w;
+          rb[4 * q] = vb.x, rb[4 * q + 1] = vb.y, rb[4 * q + 2] = vb.z, rb[4 * q + 3] = vb.w;
+        }
+#pragma unroll
+        for (int j = 0; j < QTR; ++j) {
+          const float sa = __shfl_xor(h ? ra[2 * j] : ra[2 * j + 1], 32);
+          const float sb = __shfl_xor(h ? rb[2 * j] : rb[2 * j + 1], 32);
+          if (h) {
+            ra[2 * j] = sa;
+            rb[2 * j] = sb;
+          } else {
+            ra[2 * j + 1] = sa;
+            rb[2 * j + 1] = sb;
+          }
+          const float m0 = s_rec[4 + 2 * j + h], m1 = s_rec[4 + HALF + 2 * j + h];
+          ra[2 * j] -= m0;
+          rb[2 * j] -= m0;
+          ra[2 * j + 1] -= m1;
+          rb[2 * j + 1] -= m1;
+        }
+        float sc[2];
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+          const float* rec = s_rec + sub * S;
+          float qa = 0.0f, qb = 0.0f;
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            f32x16 acca, accb;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const float c0 = sub ? s_corr[32 * mt + 8 * (r >> 2) + 4 * h + (r & 3)] : 0.0f;
+              acca[r] = c0;
+              accb[r] = c0;
+            }
+            const int i = 32 * mt + col;
+            const float* wr = rec + 4 + D + i * (i + 1) / 2 + h;
+#pragma unroll
+            for (int st = 0; st < 16 * (mt + 1); ++st) {
+              float a = wr[2 * st];
+              if (st >= 16 * mt && 2 * st + h > i) a = 0.0f;  // above the diagonal
+              const int reg = st < QTR ? 2 * st : 2 * (st - QTR) + 1;
+              acca = __builtin_amdgcn_mfma_f32_32x32x2f32(a, ra[reg], acca, 0, 0, 0);
+              accb = __builtin_amdgcn_mfma_f32_32x32x2f32(a, rb[reg], accb, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              qa = fmaf(acca[r], acca[r], qa);
+              qb = fmaf(accb[r], accb[r], qb);
+            }
+          }
+          qa += __shfl_xor(qa, 32);
+          qb += __shfl_xor(qb, 32);
+          sc[sub] = fmaf(-0.5f, h ? qb : qa, rec[0]);
+        }
+        if (kmine == cur) delta = sc[0] - sc[1];
+      }
+      if (cur == last) break;
+      // the next cluster: the first row of the chunk above cur (rows are sorted by cluster)
+      long long lo = chunk, hi = cend - 1;
+      while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if (kof(mid) > cur)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      cur = kof(lo);
     }
-    pending &= ~__ballot(mine);
+    const long long rme = base + lane;
+    if (rme < cend) {
+      const int i = (int)(h ? iB : iA);
+      zsub[i] = (unsigned char)sub_label_draw(delta, seed, t, (uint32_t)i);
+    }
   }
-  if (!valid) return;
-  zsub[i] = (unsigned char)sub_label_draw(delta, seed, t, (uint32_t)i);
+}
+
+size_t sub_labels_mfma_lds(int d) {
+  const int S = (4 + d + d * (d + 1) / 2 + 3) & ~3;
+  return (size_t)(2 * S + 2 * d) * sizeof(float);
 }
 
 // Sub-labels (d = 64, SAMPLE) and statistics for d in {64, 128} over the
@@ -953,9 +1070,21 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
   if (d == 64 || d == 128) {
     // d = 128 draws the sub-labels in their own pass (registers), then counts
     if (sample && d == 128) {
-      const unsigned lg = (unsigned)((n + BLOCK - 1) / BLOCK);
-      hipLaunchKernelGGL(k_sub_labels_big<128>, dim3(lg), dim3(BLOCK), 0, s, x, n, perm, z, zrow, zsub, packed, k_max,
-                         t, seed);
+      // two workgroups per CU (the staged records take 66 KB), each on a contiguous range of rows
+      static bool lattr = false;
+      const size_t llds = sub_labels_mfma_lds(128);
+      if (!lattr) {
+        e = hipFuncSetAttribute((const void*)k_sub_labels_mfma<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)llds);
+        if (e != hipSuccess) return e;
+        lattr = true;
+      }
+      const long long chunks = (n + SUBL_BLOCK - 1) / SUBL_BLOCK;
+      const long long gl = chunks < 512 ? chunks : 512;
+      const long long lper = ((chunks + gl - 1) / gl) * SUBL_BLOCK;
+      const unsigned lg = (unsigned)((n + lper - 1) / lper);
+      hipLaunchKernelGGL(k_sub_labels_mfma<128>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, perm, z, zrow, zsub,
+                         packed, k_max, t, seed);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const long long tiles = (n + BIG_ROWS - 1) / BIG_ROWS;
