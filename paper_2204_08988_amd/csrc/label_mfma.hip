@@ -342,11 +342,194 @@ __global__ __launch_bounds__(BLOCK32) void k_label_gauss_mfma32(const float* __r
   }
 }
 
-// d = 128: the cluster's whitener fragments (and mu, c) are staged in LDS once
+typedef __attribute__((address_space(3))) void lds_void;
+
+// The 32 x 16 tiles of a lower-triangular D x D whitener that are not all
+// zero: row block mt (rows 32 mt ... 32 mt + 31) needs ks <= 2 mt + 1.
+template <int D>
+struct TriTiles {
+  static constexpr int MT = D / 32, KS = D / 16;
+  static constexpr int tiles(int m) { return 2 * m + 2 < KS ? 2 * m + 2 : KS; }
+  static constexpr int off(int m) { return m == 0 ? 0 : off(m - 1) + tiles(m - 1); }
+  static constexpr int NT = off(MT);
+};
+
+// d = 128: the whitener fragments of a cluster (only the tiles on or
+// below the diagonal), its mean and its constant are copied from global memory
+// straight into LDS (global_load_lds, no registers), into one of two
+// statically allocated buffers, while the workgroup's four waves score their
+// points against the previous cluster from the other: one barrier per cluster.
+// The matrix cores execute 1.25 d^2 instead of 2 d^2 flops per point-cluster
+// at d = 128.  Points whose top-2 gap leaves any doubt are not drawn here:
+// they are appended to `flagged` (z = -1, not in the histogram) for the
+// candidate pass and k_rescore_flagged.
+template <int D, bool X3, bool CANDS>
+__global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma_dma(const float* __restrict__ x, long long n,
+                                                                long long per_block, const float* __restrict__ packed,
+                                                                const bf16x8* __restrict__ whi,
+                                                                const bf16x8* __restrict__ wlo, int K, uint32_t t,
+                                                                uint64_t seed, int* __restrict__ z, int* __restrict__ hist,
+                                                                int* __restrict__ tot, int* __restrict__ flagged,
+                                                                int* __restrict__ cand, int* __restrict__ n_flagged) {
+  using TT = TriTiles<D>;
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  constexpr int MT = TT::MT, KS = TT::KS, NF = MT * KS * 64;  // fragments per cluster in global memory
+  constexpr int NFZ = TT::NT * 64;  // fragments per cluster staged: the non-zero tiles (20 of 32 at d = 128)
+  constexpr int NJ = (NFZ + BLOCK - 1) / BLOCK;
+  constexpr float REL = X3 ? BF16X3_TOL_REL : BF16_TOL_REL;
+  constexpr int NB = X3 ? 2 : 1;  // fragment tables per cluster (hi, lo)
+  constexpr int MUS = D + 4;      // mu[D], c
+  static_assert(D < BLOCK, "staging layout");
+  // two staging buffers as distinct objects, so that the reads of one need no
+  // wait for the copies in flight into the other
+  __shared__ __align__(16) bf16x8 s_w0[NB * NFZ], s_w1[NB * NFZ];
+  __shared__ __align__(16) float s_mu0[MUS], s_mu1[MUS];
+  extern __shared__ int h[];  // K counters
+  for (int k = threadIdx.x; k < K; k += BLOCK) h[k] = 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  const int wbase = threadIdx.x & ~63;
+  // main pass: the workgroup's points; candidate pass: the deferred slots, grid-strided
+  const long long nf = CANDS ? (long long)*n_flagged : 0;
+  const long long begin = CANDS ? (long long)blockIdx.x * BLOCK : (long long)blockIdx.x * per_block;
+  const long long end = CANDS ? nf : (begin + per_block < n ? begin + per_block : n);
+  const long long step = CANDS ? (long long)gridDim.x * BLOCK : BLOCK;
+  // copies of cluster k into (dw, dmu): fragment f of the staged table is tile f / 64 in
+  // (row block, ks) order, lane f % 64; each wave fills 64 consecutive entries
+  auto stage = [&](bf16x8* dw, float* dmu, int k) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int f = j * BLOCK + threadIdx.x;
+      if (f < NFZ) {
+        const int tt = f >> 6;
+        int mt = 0, o = 0;
+#pragma unroll
+        for (int m = 1; m < MT; ++m)
+          if (tt >= TT::off(m)) mt = m, o = TT::off(m);
+        const size_t g = (size_t)k * NF + (size_t)(mt * KS + tt - o) * 64 + (f & 63);
+        __builtin_amdgcn_global_load_lds((const void*)(whi + g), (lds_void*)(dw + j * BLOCK + wbase), 16, 0, 0);
+        if (X3)
+          __builtin_amdgcn_global_load_lds((const void*)(wlo + g), (lds_void*)(dw + NFZ + j * BLOCK + wbase), 16, 0,
+                                           0);
+      }
+    }
+    if (threadIdx.x <= D) {
+      const float* rec = packed + (size_t)k * S;
+      __builtin_amdgcn_global_load_lds((const void*)(threadIdx.x < D ? rec + 4 + threadIdx.x : rec),
+                                       (lds_void*)(dmu + wbase), 4, 0, 0);
+    }
+  };
+  const bool any = begin < end;
+  if (any) stage(s_w0, s_mu0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int buf = 0;
+  // every wave runs the same number of chunks and clusters: one barrier per cluster
+  for (long long chunk = begin; chunk < end; chunk += step) {
+    const long long base = chunk + wave * 64;
+    const long long rA = base + col, rB = base + 32 + col;
+    const long long pA = rA < end ? (CANDS ? (long long)flagged[rA] : rA) : 0;
+    const long long pB = rB < end ? (CANDS ? (long long)flagged[rB] : rB) : 0;
+    float xa[KS][8], xb[KS][8];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = 16 * ks + 8 * half + q;
+        xa[ks][q] = rA < end ? x[pA * D + j] : 0.0f;
+        xb[ks][q] = rB < end ? x[pB * D + j] : 0.0f;
+      }
+    const bool more = chunk + step < end;
+    Top2U t2;
+    Cands cd;
+    if (CANDS)
+      cd.init();
+    else
+      t2.init();
+    // score cluster k from (cw, cmu) while cluster kn is copied into (nw, nmu)
+    auto cluster = [&](const bf16x8* cw, const float* cmu, bf16x8* nw, float* nmu, int k, bool next, int kn) {
+      if (next) stage(nw, nmu, kn);
+      const bf16x8* cwl = cw + (NB - 1) * NFZ;
+      bf16x8 ba[KS], bb[KS], bal[KS], bbl[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float mu = cmu[16 * ks + 8 * half + q];
+          const float da = xa[ks][q] - mu, db = xb[ks][q] - mu;
+          ba[ks][q] = (__bf16)da;
+          bb[ks][q] = (__bf16)db;
+          if (X3) {
+            bal[ks][q] = (__bf16)(da - (float)ba[ks][q]);
+            bbl[ks][q] = (__bf16)(db - (float)bb[ks][q]);
+          }
+        }
+      float qa = 0.0f, qb = 0.0f;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f32x16 acca = {0}, accb = {0};
+#pragma unroll
+        for (int ks = 0; ks < TT::tiles(mt); ++ks) {
+          const int tile = TT::off(mt) + ks;
+          const bf16x8 a = cw[tile * 64 + lane];
+          acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, ba[ks], acca, 0, 0, 0);
+          accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb[ks], accb, 0, 0, 0);
+          if (X3) {
+            const bf16x8 al = cwl[tile * 64 + lane];
+            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, ba[ks], acca, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bb[ks], accb, 0, 0, 0);
+            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bal[ks], acca, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbl[ks], accb, 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          qa = fmaf(acca[r], acca[r], qa);
+          qb = fmaf(accb[r], accb[r], qb);
+        }
+      }
+      qa += __shfl_xor(qa, 32);
+      qb += __shfl_xor(qb, 32);
+      const float qm = half ? qb : qa;
+      const float l = fmaf(-0.5f, qm, cmu[D]);
+      if (CANDS)
+        cd.push(l, qm, REL, k);
+      else
+        t2.push(l, qm, REL, k);
+      // this wave's copies into the other buffer have landed; after the barrier all have
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    };
+    for (int k = 0; k < K; ++k) {
+      // the next cluster (or the next chunk's first) is copied while this one computes
+      const bool next = k + 1 < K || more;
+      const int kn = k + 1 < K ? k + 1 : 0;
+      if (buf == 0)
+        cluster(s_w0, s_mu0, s_w1, s_mu1, k, next, kn);
+      else
+        cluster(s_w1, s_mu1, s_w0, s_mu0, k, next, kn);
+      buf ^= 1;
+    }
+    const long long r = base + lane;
+    if (CANDS)
+      finish_cands(r < end, r, r < end ? (long long)flagged[r] : 0, cd, REL, K, per_block, t, seed, z, hist, tot,
+                   cand);
+    else
+      finish_main(r < end, r, t2, z, h, flagged, n_flagged, lane);
+  }
+  if (CANDS) return;
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += BLOCK) {
+    hist[(size_t)blockIdx.x * K + k] = h[k];
+    if (h[k]) atomicAdd(&tot[k], h[k]);
+  }
+}
+
+// d = 64: the cluster's whitener fragments (and mu, c) are staged in LDS once
 // per workgroup and shared by its four waves, double-buffered: cluster k + 1 is
-// fetched into registers while cluster k computes; MFMA tiles entirely above the
-// diagonal of W (16 ks > 32 mt + 31) are skipped, so the matrix cores execute
-// 1.25 d^2 instead of 2 d^2 flops per point-cluster.  Points whose top-2 gap
+// fetched into registers while cluster k computes (at d = 64 the prefetch fits
+// in three waves per SIMD; copies straight into LDS cost registers here); MFMA
+// tiles entirely above the diagonal of W (16 ks > 32 mt + 31) are skipped.  Points whose top-2 gap
 // leaves any doubt are not drawn here: they are appended to `flagged` (z = -1,
 // not in the histogram) and drawn by k_rescore_flagged in FP32.
 template <int D, bool X3, bool CANDS>
@@ -657,13 +840,9 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
   e = launch_zero64(n_flagged, 1, s);
   if (e != hipSuccess) return e;
   static bool attr_set = false;
-  if (!attr_set) {  // more than 64 KB of dynamic LDS (160 KB per CU on gfx950)
-    const void* fns[9] = {
-        (const void*)k_label_gauss_mfma_lds<128, true, false>, (const void*)k_label_gauss_mfma_lds<128, false, false>,
-        (const void*)k_label_gauss_mfma_lds<64, true, false>,  (const void*)k_label_gauss_mfma_lds<64, false, false>,
-        (const void*)k_label_gauss_mfma32<true, false>,        (const void*)k_label_gauss_mfma32<false, false>,
-        (const void*)k_label_gauss_mfma_lds<128, true, true>,  (const void*)k_label_gauss_mfma_lds<64, true, true>,
-        (const void*)k_label_gauss_mfma32<true, true>};
+  if (!attr_set) {  // d = 32: more than 64 KB of dynamic LDS (160 KB per CU on gfx950)
+    const void* fns[3] = {(const void*)k_label_gauss_mfma32<true, false>, (const void*)k_label_gauss_mfma32<false, false>,
+                          (const void*)k_label_gauss_mfma32<true, true>};
     for (const void* f : fns) {
       e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       if (e != hipSuccess) return e;
@@ -676,23 +855,30 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
     const bool cands = pass == 1;
     const int Gp = cands ? (d == 32 ? (G < 256 ? G : 256) : (G < 512 ? G : 512)) : G;
     if (d == 64 || d == 128) {
-      const int NF = (d / 32) * (d / 16) * 64;
-      const size_t lds = 2 * ((size_t)(x3 ? 2 : 1) * NF * sizeof(bf16x8) + (d + 4) * sizeof(float)) + lh;
-#define DPMM_MFMA_LDS(DD, XX, CC)                                                                           \
-  hipLaunchKernelGGL((k_label_gauss_mfma_lds<DD, XX, CC>), dim3(Gp), dim3(BLOCK), lds, s, x, n, per_block, packed, \
-                     hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
-#define DPMM_MFMA_LDS_C(DD)                                                                                   \
-  hipLaunchKernelGGL((k_label_gauss_mfma_lds<DD, true, true>), dim3(Gp), dim3(BLOCK), lds_c, s, x, n, per_block, \
-                     packed, hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
-      // the candidate pass scores in bf16x3 whatever the main pass's form
-      const size_t lds_c = 2 * ((size_t)2 * NF * sizeof(bf16x8) + (d + 4) * sizeof(float)) + lh;
+      // d = 128: static staging buffers, only the histogram is dynamic; d = 64: two staging
+      // buffers of [NB][NF] fragments and [d + 4] floats, then the histogram
+#define DPMM_MFMA_LDS(KER, DD, XX, CC, L)                                                                 \
+  hipLaunchKernelGGL((KER<DD, XX, CC>), dim3(Gp), dim3(BLOCK), L, s, x, n, per_block, packed, hi, lo, K, t, seed, \
+                     z, hist, tot, flagged, cand, n_flagged)
       if (d == 128) {
-        if (cands) DPMM_MFMA_LDS_C(128); else if (x3) DPMM_MFMA_LDS(128, true, false); else DPMM_MFMA_LDS(128, false, false);
+        // the candidate pass scores in bf16x3 whatever the main pass's form
+        if (cands)
+          DPMM_MFMA_LDS(k_label_gauss_mfma_dma, 128, true, true, lh);
+        else if (x3)
+          DPMM_MFMA_LDS(k_label_gauss_mfma_dma, 128, true, false, lh);
+        else
+          DPMM_MFMA_LDS(k_label_gauss_mfma_dma, 128, false, false, lh);
       } else {
-        if (cands) DPMM_MFMA_LDS_C(64); else if (x3) DPMM_MFMA_LDS(64, true, false); else DPMM_MFMA_LDS(64, false, false);
+        const int NF = (d / 32) * (d / 16) * 64;
+        const size_t lds = 2 * ((size_t)(x3 || cands ? 2 : 1) * NF * sizeof(bf16x8) + (d + 4) * sizeof(float)) + lh;
+        if (cands)
+          DPMM_MFMA_LDS(k_label_gauss_mfma_lds, 64, true, true, lds);
+        else if (x3)
+          DPMM_MFMA_LDS(k_label_gauss_mfma_lds, 64, true, false, lds);
+        else
+          DPMM_MFMA_LDS(k_label_gauss_mfma_lds, 64, false, false, lds);
       }
 #undef DPMM_MFMA_LDS
-#undef DPMM_MFMA_LDS_C
     } else if (d == 32) {
       // [CG][NB][NF] fragments (64 KB), [CG][d + 4] means and constants, the histogram;
       // the candidate pass scores in bf16x3
