@@ -251,8 +251,16 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
 #pragma unroll
         for (int j = 0; j < D; ++j) xv[j] = x[i * D + j];
       } else {
+        // eight loads in flight at a time (d is not known at compile time)
         float* xr = xs + (size_t)r * ld;
-        for (int j = 0; j < d; ++j) xr[j] = x[i * d + j];
+        for (int j0 = 0; j0 < d; j0 += 8) {
+          float tv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) tv[u] = j0 + u < d ? x[i * d + j0 + u] : 0.0f;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (j0 + u < d) xr[j0 + u] = tv[u];
+        }
         for (int j = d; j < dp; ++j) xr[j] = 0.0f;
       }
     }
@@ -916,9 +924,30 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
     }
     for (int q = tid; q < 2 * BIG_ROWS; q += BIG_THREADS) lcount[q] = 0;
     __syncthreads();
-    for (int e = tid; e < rows * D; e += BIG_THREADS) {
-      const int r = e / D, c = e - r * D;
-      xs[r * LD + c] = x[(size_t)order[r] * D + c];
+    {
+      // D / 4 lanes read a row in 16-byte pieces; all of a thread's loads are in
+      // flight before the first LDS store
+      // (in two batches where the sub-label registers leave less room)
+      constexpr int C4 = D / 4, RPP = BIG_THREADS / C4, NP = BIG_ROWS / RPP, NBAT = SAMPLE ? 2 : 1;
+      const int c4 = tid % C4, r0 = tid / C4;
+#pragma unroll
+      for (int bt = 0; bt < NBAT; ++bt) {
+        float4 v[NP / NBAT];
+#pragma unroll
+        for (int j = 0; j < NP / NBAT; ++j) {
+          const int r = r0 + (bt * (NP / NBAT) + j) * RPP;
+          v[j] = r < rows ? reinterpret_cast<const float4*>(x + (size_t)order[r] * D)[c4]
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int j = 0; j < NP / NBAT; ++j) {
+          float* dst = xs + (r0 + (bt * (NP / NBAT) + j) * RPP) * LD + 4 * c4;
+          dst[0] = v[j].x;
+          dst[1] = v[j].y;
+          dst[2] = v[j].z;
+          dst[3] = v[j].w;
+        }
+      }
     }
     __syncthreads();
     // ---- (2) sub-label of row tid
