@@ -1012,20 +1012,30 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
       cnt_seg += cnt;
       const int st = lstart[q];
       for (int g = 0; g < cnt; g += 4) {
+        // unconditional LDS reads (a lane past the segment reads row 0 and zeroes its
+        // A operand), so that the reads of a step overlap and need no branches
         const int p = g + (lane >> 4);
         const bool ok = p < cnt;
-        const float* xr = xs + (size_t)(ok ? order[st + p] : 0) * LD;
+        const int ro = order[st + (ok ? p : 0)] * LD + (lane & 15);
 #pragma unroll
         for (int j = 0; j < TPW; ++j) {
           if (bI[j] < 0) continue;
-          const double av = ok ? (double)xr[16 * bI[j] + (lane & 15)] : 0.0;
-          const double bv = ok ? (double)xr[16 * bJ[j] + (lane & 15)] : 0.0;
+          const float fa = xs[ro + 16 * bI[j]], fb = xs[ro + 16 * bJ[j]];
+          const double av = ok ? (double)fa : 0.0, bv = (double)fb;
           acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[j], 0, 0, 0);
         }
       }
       if (lane < DW) {
+        // four independent partial sums, each in row order, added at the end
         const int dim = wq * DW + lane;
-        for (int p = 0; p < cnt; ++p) sx += (double)xs[(size_t)order[st + p] * LD + dim];
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        int p = 0;
+        for (; p + 4 <= cnt; p += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) s4[u] += (double)xs[order[st + p + u] * LD + dim];
+        }
+        for (; p < cnt; ++p) s4[0] += (double)xs[order[st + p] * LD + dim];
+        sx += (s4[0] + s4[1]) + (s4[2] + s4[3]);
       }
     }
   }
