@@ -467,11 +467,19 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
   // rows [s0, e0) of the wave's LDS tile, four at a time: A = B = the rows' block of dimensions
   auto mfma_rows = [&](f64x4 (&c)[NBLK], double (&sx)[NB], int s0, int e0) {
     for (int g = s0; g < e0; g += 4) {
+      // unconditional LDS reads of an element inside the tile (row s0, column 0 for a
+      // lane past the rows or the dimensions), then zeroed: no branches, so the reads
+      // of the next step can overlap the matrix-core work of this one
       const int rr = g + (lane >> 4);
       const bool ok = rr < e0;
+      const int rs = ok ? rr : s0;
       double a[NB];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) a[b] = (ok && 16 * b + col < D) ? (double)xs[rr * LDW + 16 * b + col] : 0.0;
+      for (int b = 0; b < NB; ++b) {
+        const int cc = 16 * b + col;
+        const float v = xs[rs * LDW + (cc < D ? cc : 0)];
+        a[b] = (ok && cc < D) ? (double)v : 0.0;
+      }
 #pragma unroll
       for (int b = 0; b < NB; ++b) sx[b] += a[b];
       int blk = 0;
