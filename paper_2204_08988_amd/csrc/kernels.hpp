@@ -9,6 +9,8 @@ namespace dpmm {
 // candidate clusters kept per point by the matrix-core label kernels
 constexpr int RESCORE_CAND = 8;
 constexpr int NIW_LDS_MAX_D = 64;
+// above that and up to this d the draw keeps one d x (d + 1) float64 matrix in LDS
+constexpr int NIW_BIG_MAX_D = 128;
 inline size_t niw_lds_bytes(int d) { return d <= NIW_LDS_MAX_D ? NIW_SCRATCH(d) * sizeof(double) : 0; }
 // the marginal-likelihood kernel keeps one d x d matrix in LDS up to this d
 constexpr int LOGML_LDS_MAX_D = 128;

@@ -234,6 +234,189 @@ __global__ void k_niw_draw(int K, int d, int k_max, NiwPriorDev prior, const lon
               logdet_out + e, err, &flag, red);
 }
 
+constexpr int NIW_BIG_THREADS = 512;
+
+// k_niw_draw for 64 < d <= NIW_BIG_MAX_D: one workgroup of 512 threads per
+// component with one d x d float64 matrix resident in LDS (row stride d + 1),
+// reused in place by every stage: Psi_n -> L = chol(Psi_n) -> F = L A^-T (the
+// columns of the Bartlett factor A come from the component's global scratch,
+// one column ahead) -> Sigma = F F^T (4 x 4 register tiles) -> G = chol(Sigma)
+// -> W = G^-1.  Same random draws and outputs as k_niw_draw.
+__global__ __launch_bounds__(NIW_BIG_THREADS) void k_niw_draw_lds(
+    int K, int d, int k_max, NiwPriorDev prior, const long long* __restrict__ counts,
+    const double* __restrict__ moments, const double* __restrict__ log_pi, const double* __restrict__ log_pisub,
+    uint64_t seed, uint32_t t, double* __restrict__ mu_out, double* __restrict__ sigma_out,
+    double* __restrict__ scratch, float* __restrict__ packed, double* __restrict__ logdet_out, int* __restrict__ err) {
+  extern __shared__ double M[];  // [d][d + 1]
+  __shared__ double colbuf[2][NIW_BIG_MAX_D], eps[NIW_BIG_MAX_D], red[NIW_BIG_THREADS];
+  __shared__ int flag;
+  __shared__ double sh_n;
+  const int e = blockIdx.x;
+  if (e >= 3 * K) return;
+  const int k = e / 3, c = e % 3;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tx = tid & 31, ty = tid >> 5, nty = nt >> 5;
+  const int ld = d + 1;
+  const int E = d + d * (d + 1) / 2;
+  double* At = scratch + (size_t)e * NIW_SCRATCH(d);  // A^T: row j holds column j of A
+  double* mn = mu_out + (size_t)e * d;                // m_n staged in the output row
+  const int s0 = c == 0 ? 2 * k : 2 * k + (c - 1);
+  const int s1 = c == 0 ? 2 * k + 1 : -1;
+  const double* M0 = moments + (size_t)s0 * E;
+  const double* M1 = s1 >= 0 ? moments + (size_t)s1 * E : nullptr;
+  if (tid == 0) sh_n = (double)counts[s0] + (s1 >= 0 ? (double)counts[s1] : 0.0);
+  __syncthreads();
+  const double n = sh_n, kn = prior.kappa + n, nun = prior.nu + n;
+  // m_n = (kappa m + s) / kappa_n
+  for (int i = tid; i < d; i += nt) {
+    const double sv = M0[i] + (M1 ? M1[i] : 0.0);
+    mn[i] = (prior.kappa * prior.m[i] + sv) / kn;
+  }
+  // Psi_n = Psi + C + (kappa n / kappa_n)(xbar - m)(xbar - m)^T, C = S - n xbar xbar^T
+  for (int idx = tid; idx < d * d; idx += nt) {
+    const int i = idx / d, j = idx % d;
+    double v = prior.psi[idx];
+    if (n > 0.0) {
+      const int a = i < j ? i : j, b = i < j ? j : i;
+      const double S = M0[d + tri_index(a, b, d)] + (M1 ? M1[d + tri_index(a, b, d)] : 0.0);
+      const double si = M0[i] + (M1 ? M1[i] : 0.0);
+      const double sj = M0[j] + (M1 ? M1[j] : 0.0);
+      const double xi = si / n, xj = sj / n;
+      v += (S - n * xi * xj) + (prior.kappa * n / kn) * (xi - prior.m[i]) * (xj - prior.m[j]);
+    }
+    M[i * ld + j] = v;
+  }
+  // Bartlett factor (A[i][j] ~ N(0,1) for i > j, A[i][i] = sqrt(chi2(nu_n - i))), stored transposed
+  const int nq_off = d * (d - 1) / 2;
+  for (int idx = tid; idx < d * d; idx += nt) {
+    const int j = idx / d, i = idx % d;  // At[j][i] = A[i][j]
+    double v = 0.0;
+    if (j < i) {
+      v = normal_draw(seed, t, (uint32_t)e, TAG_NIW, (uint32_t)(i * (i - 1) / 2 + j));
+    } else if (j == i) {
+      const double lg = log_gamma_draw(seed, t, (uint32_t)e, TAG_NIW, (uint32_t)(nq_off + i), 0.5 * (nun - i));
+      v = exp(0.5 * (0.69314718055994531 + lg));
+    }
+    At[idx] = v;
+  }
+  for (int q = tid; q < d; q += nt) eps[q] = normal_draw(seed, t, (uint32_t)e, TAG_NIW, (uint32_t)(nq_off + d + q));
+  __threadfence_block();
+  __syncthreads();
+  if (!wg_cholesky(M, d, &flag, ld)) {
+    if (tid == 0) atomicOr(err, 1);
+  }
+  // F = L A^-T in place: column j of F is final after dividing by A_jj, then
+  // F[:, q] -= F[:, j] A[q][j] for q > j; column j + 1 of A is read while step j runs
+  if (tid < d) colbuf[0][tid] = At[tid];
+  __syncthreads();
+  for (int j = 0; j < d; ++j) {
+    const double* cur = colbuf[j & 1];
+    double* nxt = colbuf[(j + 1) & 1];
+    const double pre = (j + 1 < d && tid < d) ? At[(size_t)(j + 1) * d + tid] : 0.0;
+    const double inv = 1.0 / cur[j];
+    for (int r = tid; r < d; r += nt) M[r * ld + j] *= inv;
+    __syncthreads();
+    for (int r = ty; r < d; r += nty) {
+      const double frj = M[r * ld + j];
+      for (int q = j + 1 + tx; q < d; q += 32) M[r * ld + q] -= frj * cur[q];
+    }
+    if (j + 1 < d && tid < d) nxt[tid] = pre;  // last read in step j - 1
+    __syncthreads();
+  }
+  // mu = m_n + F eps / sqrt(kappa_n)
+  const double rs = 1.0 / sqrt(kn);
+  for (int r = tid; r < d; r += nt) {
+    double sv = 0.0;
+    for (int q = 0; q < d; ++q) sv += M[r * ld + q] * eps[q];
+    mn[r] += sv * rs;
+  }
+  // Sigma = F F^T: thread u owns the 4 x 4 tiles u and u + nt of the upper block triangle
+  const int nb = (d + 3) / 4, ntile = nb * (nb + 1) / 2;
+  double acc[2][4][4];
+  int tI[2], tJ[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    int u = tid + h * nt, a = 0;
+    tI[h] = tJ[h] = -1;
+    if (u < ntile) {
+      while (u >= nb - a) {
+        u -= nb - a;
+        ++a;
+      }
+      tI[h] = a;
+      tJ[h] = a + u;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[h][i][j] = 0.0;
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (tI[h] < 0) continue;
+    int ra[4], rb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ra[i] = min(4 * tI[h] + i, d - 1) * ld;
+      rb[i] = min(4 * tJ[h] + i, d - 1) * ld;
+    }
+    for (int q = 0; q < d; ++q) {
+      double fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        fa[i] = M[ra[i] + q];
+        fb[i] = M[rb[i] + q];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[h][i][j] = fma(fa[i], fb[j], acc[h][i][j]);
+    }
+  }
+  __syncthreads();  // every read of F is done
+  double* sig = sigma_out + (size_t)e * d * d;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (tI[h] < 0) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int a = 4 * tI[h] + i, b = 4 * tJ[h] + j;
+        if (a < d && b < d && (tI[h] < tJ[h] || i <= j)) {
+          const double v = acc[h][i][j];
+          sig[a * d + b] = v;
+          sig[b * d + a] = v;
+          M[a * ld + b] = v;
+          M[b * ld + a] = v;
+        }
+      }
+  }
+  __syncthreads();
+  // G = chol(Sigma), log|Sigma|, W = G^-1, the float32 record
+  if (!wg_cholesky(M, d, &flag, ld)) {
+    if (tid == 0) atomicOr(err, 2);
+  }
+  double lds = 0.0;
+  for (int i = tid; i < d; i += nt) lds += log(M[i * ld + i]);
+  lds = 2.0 * block_reduce_sum(lds, red);
+  wg_lower_inverse_inplace(M, d, ld, colbuf[0]);
+  const double lw = c == 0 ? log_pi[k] : log_pisub[2 * k + (c - 1)];
+  float* rec = packed + (size_t)record_slot(k, c, k_max) * gauss_rec_stride(d);
+  const int stride = gauss_rec_stride(d);
+  if (tid == 0) {
+    rec[0] = (float)(lw - 0.5 * lds - 0.5 * d * 1.8378770664093453);
+    rec[1] = rec[2] = rec[3] = 0.0f;
+    logdet_out[e] = lds;
+  }
+  for (int i = tid; i < d; i += nt) rec[4 + i] = (float)mn[i];
+  for (int r = ty; r < d; r += nty) {
+    const int row0 = r * (r + 1) / 2;
+    for (int cc = tx; cc <= r; cc += 32) rec[4 + d + row0 + cc] = (float)M[r * ld + cc];
+  }
+  for (int idx = 4 + d + d * (d + 1) / 2 + tid; idx < stride; idx += nt) rec[idx] = 0.0f;
+}
+
 // k_niw_draw for d <= D (D in {16, 32, 64}) with two waves per component and
 // a single workgroup barrier.  Wave 0 owns the matrices: lane i holds row i of
 // each d x d matrix of the draw, padded to D rows with an identity block
@@ -495,7 +678,20 @@ hipError_t launch_niw_draw(int K, int d, int k_max, NiwPriorDev prior, const lon
     DPMM_NIW_WAVE(32);
   else if (d <= 64)
     DPMM_NIW_WAVE(64);
-  else
+  else if (d <= NIW_BIG_MAX_D) {
+    // one d x (d + 1) float64 matrix in LDS: above 64 KB, raise the limit once
+    static bool attr_set = false;
+    const size_t lds = (size_t)d * (d + 1) * sizeof(double);
+    if (!attr_set) {
+      const hipError_t e = hipFuncSetAttribute((const void*)k_niw_draw_lds,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)((size_t)NIW_BIG_MAX_D * (NIW_BIG_MAX_D + 1) * sizeof(double)));
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(k_niw_draw_lds, dim3(3 * K), dim3(NIW_BIG_THREADS), lds, s, K, d, k_max, prior, counts,
+                       moments, log_pi, log_pisub, seed, t, mu_out, sigma_out, scratch, packed, logdet_out, err);
+  } else
     hipLaunchKernelGGL(k_niw_draw, dim3(3 * K), dim3(256), niw_lds_bytes(d), s, K, d, k_max, prior, counts, moments,
                        log_pi, log_pisub, seed, t, mu_out, sigma_out, scratch, packed, logdet_out, err);
 #undef DPMM_NIW_WAVE

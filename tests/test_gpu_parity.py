@@ -84,9 +84,9 @@ def test_gauss_suffstats(d, K, n):
     S.close()
 
 
-@pytest.mark.parametrize("d,K", [(1, 1), (2, 6), (3, 4), (8, 5), (32, 3)])
+@pytest.mark.parametrize("d,K", [(1, 1), (2, 6), (3, 4), (8, 5), (32, 3), (64, 2), (100, 2), (128, 3)])
 def test_gauss_sample_params(d, K):
-    _torch()
+    torch = _torch()
     seed = 77 + d
     g = np.random.Generator(np.random.PCG64(seed))
     n = 400 * K
@@ -110,6 +110,11 @@ def test_gauss_sample_params(d, K):
         sig = comp[:, :, d:].reshape(K, 3, d, d)
         scale = np.sqrt(np.einsum("kcii,kcjj->kcij", ref.sigma, ref.sigma))
         assert np.all(np.abs(sig - ref.sigma) <= 1e-9 * scale)
+        # the float32 scoring records written by the draw (whitener, constant, mean)
+        lc, ls = sampler.loglik(model, x.astype(np.float64), ref)
+        Mc, Ms = pu.gauss_scale(x, ref)
+        ll = S.loglik(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
+        assert pu.check_loglik(ll, lc, ls, Mc, Ms) <= 1e-5
     S.close()
 
 
