@@ -134,6 +134,10 @@ dpmm_status ensure_items(dpmm_ctx* ctx, size_t count) {
   hipHostFree(ctx->h_items);
   hipHostFree(ctx->h_lml);
   hipHostFree(ctx->h_mflag);
+  hipFree(ctx->d_rb);
+  hipHostFree(ctx->h_rb);
+  ctx->d_rb = nullptr;
+  ctx->h_rb = nullptr;
   ctx->d_items = nullptr;
   ctx->d_logml = nullptr;
   ctx->d_mflag = nullptr;
@@ -147,6 +151,9 @@ dpmm_status ensure_items(dpmm_ctx* ctx, size_t count) {
   DPMM_HIP(ctx, hipHostMalloc((void**)&ctx->h_items, cap * sizeof(LogmlItem), hipHostMallocDefault), "pin items");
   DPMM_HIP(ctx, hipHostMalloc((void**)&ctx->h_lml, cap * sizeof(double), hipHostMallocDefault), "pin items");
   DPMM_HIP(ctx, hipHostMalloc((void**)&ctx->h_mflag, cap, hipHostMallocDefault), "pin items");
+  const size_t rb = readback_bytes(ctx->cfg.k_max, (int)cap);
+  DPMM_HIP(ctx, hipMalloc(&ctx->d_rb, rb), "allocate read-back");
+  DPMM_HIP(ctx, hipHostMalloc((void**)&ctx->h_rb, rb, hipHostMallocDefault), "pin read-back");
   ctx->items_cap = cap;
   return DPMM_OK;
 }
@@ -421,6 +428,8 @@ void dpmm_destroy(dpmm_ctx* ctx) {
   hipHostFree(ctx->h_items);
   hipHostFree(ctx->h_lml);
   hipHostFree(ctx->h_mflag);
+  hipFree(ctx->d_rb);
+  hipHostFree(ctx->h_rb);
   hipHostFree(ctx->h_cnt);
   hipHostFree(ctx->h_flag);
   for (auto& e : ctx->ev)
@@ -750,20 +759,19 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t
     DPMM_HIP(ctx, launch_merge_decide((int)pairs.size(), ctx->d_items + 3 * K, ctx->d_counts, ctx->d_logml,
                                       ctx->d_logml + 3 * K, alpha, ctx->cfg.merge_form == DPMM_MERGE_PAPER, seed, t,
                                       ctx->d_mflag, ctx->stream), "merge test kernel");
-    DPMM_HIP(ctx, hipMemcpyAsync(ctx->h_cnt, ctx->d_counts, 2 * (size_t)K * sizeof(long long), hipMemcpyDeviceToHost,
-                                 ctx->stream), "copy counts");
-    DPMM_HIP(ctx, hipMemcpyAsync(ctx->h_lml, ctx->d_logml, 3 * (size_t)K * sizeof(double), hipMemcpyDeviceToHost,
-                                 ctx->stream), "copy log marginals");
-    if (!pairs.empty())
-      DPMM_HIP(ctx, hipMemcpyAsync(ctx->h_mflag, ctx->d_mflag, pairs.size(), hipMemcpyDeviceToHost, ctx->stream),
-               "copy merge tests");
-    DPMM_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
-             "copy flag");
+    const int P = (int)pairs.size();
+    DPMM_HIP(ctx, launch_pack_readback(K, P, ctx->d_counts, ctx->d_logml, ctx->d_mflag, ctx->d_err, ctx->d_rb,
+                                       ctx->stream), "read-back kernel");
+    DPMM_HIP(ctx, hipMemcpyAsync(ctx->h_rb, ctx->d_rb, readback_bytes(K, P), hipMemcpyDeviceToHost, ctx->stream),
+             "copy read-back");
     DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
-    cnt.assign(ctx->h_cnt, ctx->h_cnt + 2 * (size_t)K);
-    lml.assign(ctx->h_lml, ctx->h_lml + 3 * (size_t)K);
-    merge_ok.assign(ctx->h_mflag, ctx->h_mflag + pairs.size());
-    const int flag = *ctx->h_flag;
+    const long long* rb_cnt = reinterpret_cast<const long long*>(ctx->h_rb + 8);
+    const double* rb_lml = reinterpret_cast<const double*>(ctx->h_rb + 8 + 16 * (size_t)K);
+    const unsigned char* rb_m = ctx->h_rb + 8 + 40 * (size_t)K;
+    cnt.assign(rb_cnt, rb_cnt + 2 * (size_t)K);
+    lml.assign(rb_lml, rb_lml + 3 * (size_t)K);
+    merge_ok.assign(rb_m, rb_m + P);
+    const int flag = (int)*reinterpret_cast<const long long*>(ctx->h_rb);
     if (flag) {
       DPMM_HIP(ctx, hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream), "clear flag");
       return ctx->fail(DPMM_E_NUMERIC, "a float64 Cholesky factorisation met a non-positive pivot (flag " +

@@ -49,6 +49,9 @@ struct dpmm_ctx {
   double *d_log_pi = nullptr, *d_log_pisub = nullptr, *d_tmp = nullptr;
   double *d_mu = nullptr, *d_sigma = nullptr, *d_log_theta = nullptr, *d_logdet = nullptr;
   float* d_packed = nullptr;
+  // one split/merge round's read-back: device buffer and its pinned copy (grown with the items)
+  unsigned char* d_rb = nullptr;
+  unsigned char* h_rb = nullptr;
   double* d_scratch = nullptr;  // NIW_SCRATCH(d) per workgroup slot
   int scratch_slots = 0;
   int* d_err = nullptr;

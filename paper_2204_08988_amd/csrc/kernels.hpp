@@ -142,6 +142,10 @@ hipError_t launch_logml_gauss(int n_items, const LogmlItem* items, int d, NiwPri
 hipError_t launch_merge_decide(int n_pairs, const LogmlItem* pairs, const long long* counts, const double* lml_cluster,
                                const double* lml_pair, double alpha, bool paper_form, uint64_t seed, uint32_t t,
                                unsigned char* accept, hipStream_t s);
+// [error flag, 8 bytes][counts 2K int64][3K log marginals float64][P merge decisions] in one buffer
+size_t readback_bytes(int K, int P);
+hipError_t launch_pack_readback(int K, int P, const long long* counts, const double* lml, const unsigned char* mflag,
+                                const int* err, unsigned char* out, hipStream_t s);
 hipError_t launch_logml_mult(int n_items, const LogmlItem* items, int V, const double* beta,
                              double beta_sum, double lgamma_beta_sum, const double* lgamma_beta,
                              const long long* counts, const long long* sums, double* out, hipStream_t s);

@@ -171,6 +171,26 @@ __global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const L
 // item pairs[p] = (2 k1, 2 k1 + 1, 2 k2, 2 k2 + 1) with union marginal
 // lml_pair[p]; lml_cluster[3 k] is cluster k's marginal.  accept[p] = 1 when
 // log u < log H_merge with u the merge uniform of (k1, k2).
+// Read-back of one split/merge round in a single buffer (one copy to the
+// host instead of four): [int error flag, padded to 8 bytes][counts, 2K
+// int64][log marginals of the 3K cluster / sub-cluster items, float64][P merge
+// decisions, bytes].
+__global__ void k_pack_readback(int K, int P, const long long* __restrict__ counts, const double* __restrict__ lml,
+                                const unsigned char* __restrict__ mflag, const int* __restrict__ err,
+                                unsigned char* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *reinterpret_cast<long long*>(out) = (long long)*err;
+  long long* oc = reinterpret_cast<long long*>(out + 8);
+  double* ol = reinterpret_cast<double*>(out + 8 + 16 * (size_t)K);
+  unsigned char* om = out + 8 + 40 * (size_t)K;
+  if (i < 2 * K)
+    oc[i] = counts[i];
+  else if (i < 5 * K)
+    ol[i - 2 * K] = lml[i - 2 * K];
+  else if (i < 5 * K + P)
+    om[i - 5 * K] = mflag[i - 5 * K];
+}
+
 __global__ void k_merge_decide(int n_pairs, const LogmlItem* __restrict__ pairs, const long long* __restrict__ counts,
                                const double* __restrict__ lml_cluster, const double* __restrict__ lml_pair,
                                double alpha, int paper_form, uint64_t seed, uint32_t t,
@@ -301,6 +321,15 @@ hipError_t launch_merge_decide(int n_pairs, const LogmlItem* pairs, const long l
   if (n_pairs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_merge_decide, dim3((n_pairs + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, n_pairs, pairs, counts,
                      lml_cluster, lml_pair, alpha, paper_form ? 1 : 0, seed, t, accept);
+  return hipGetLastError();
+}
+
+size_t readback_bytes(int K, int P) { return 8 + 40 * (size_t)K + (size_t)P; }
+
+hipError_t launch_pack_readback(int K, int P, const long long* counts, const double* lml, const unsigned char* mflag,
+                                const int* err, unsigned char* out, hipStream_t s) {
+  const int n = 5 * K + P;
+  hipLaunchKernelGGL(k_pack_readback, dim3((n + 255) / 256), dim3(256), 0, s, K, P, counts, lml, mflag, err, out);
   return hipGetLastError();
 }
 
