@@ -437,8 +437,10 @@ __global__ __launch_bounds__(128) void k_niw_draw_wave(int K, int d, int k_max, 
                                                        double* __restrict__ sigma_out, float* __restrict__ packed,
                                                        double* __restrict__ logdet_out, int* __restrict__ err) {
   constexpr int LD = D + 1;
+  constexpr int ED = D + D * (D + 1) / 2;
   __shared__ double sm[D * LD];  // Bartlett factor A, then F, then G
-  __shared__ double col[D];      // Cholesky column broadcast
+  __shared__ double sst[ED];     // the component's summed statistics (wave 0)
+  static_assert(D % 4 == 0, "Sigma is formed four columns at a time");
   __shared__ double rdiag[D];    // 1 / A[j][j], then 1 / G[j][j]
   __shared__ double seps[D];     // the mean's normals
   const int e = blockIdx.x;
@@ -482,32 +484,32 @@ __global__ __launch_bounds__(128) void k_niw_draw_wave(int K, int d, int k_max, 
   if (wave == 0) {
     const double* M0 = moments + (size_t)s0 * E;
     const double* M1 = s1 >= 0 ? moments + (size_t)s1 * E : M0;
-    double si = 0.0, mi = 0.0;
-    if (live) {
-      si = M0[lane] + (s1 >= 0 ? M1[lane] : 0.0);
-      mi = prior.m[lane];
+    // one round of loads: the summed statistics into LDS, the prior's row into r
+#pragma unroll
+    for (int i = 0; i < (ED + 63) / 64; ++i) {
+      const int q = lane + 64 * i;
+      if (q < E) sst[q] = M0[q] + (s1 >= 0 ? M1[q] : 0.0);
     }
+#pragma unroll
+    for (int j = 0; j < D; ++j) r[j] = (live && j < d) ? prior.psi[lane * d + j] : 0.0;
+    const double mi = live ? prior.m[lane] : 0.0;
+    wave_sync();
+    const double si = live ? sst[lane] : 0.0;
     const double mni = (prior.kappa * mi + si) / kn;
     const double xi = n > 0.0 ? si / n : 0.0;
     const double cm = prior.kappa * n / kn;
-    // row of Psi_n = Psi + C + (kappa n / kappa_n)(xbar - m)(xbar - m)^T; the
-    // loads of a group of 16 columns are issued together
+    // row of Psi_n = Psi + C + (kappa n / kappa_n)(xbar - m)(xbar - m)^T
 #pragma unroll
-    for (int j0 = 0; j0 < D; j0 += 16) {
-      issue_fence();
-#pragma unroll
-      for (int j = j0; j < j0 + 16; ++j) {
-        const double xj = readlane_d(xi, j), mj = readlane_d(mi, j);
-        const bool in = live && j < d;
-        const int a = lane < j ? lane : j, b = lane < j ? j : lane;
-        const int ti = in ? d + tri_index(a, b, d) : 0;
-        const double S = M0[ti] + (s1 >= 0 ? M1[ti] : 0.0);
-        const double ps = prior.psi[in ? lane * d + j : 0];
-        const double v = n > 0.0 ? ps + ((S - n * xi * xj) + cm * (xi - mi) * (xj - mj)) : ps;
-        r[j] = in ? v : (j == lane ? 1.0 : 0.0);
-      }
+    for (int j = 0; j < D; ++j) {
+      const double xj = readlane_d(xi, j), mj = readlane_d(mi, j);
+      const bool in = live && j < d;
+      const int a = lane < j ? lane : j, b = lane < j ? j : lane;
+      const int ti = in ? d + tri_index(a, b, d) : 0;
+      const double ps = r[j];
+      const double v = n > 0.0 ? ps + ((sst[ti] - n * xi * xj) + cm * (xi - mi) * (xj - mj)) : ps;
+      r[j] = in ? v : (j == lane ? 1.0 : 0.0);
     }
-    if (!wave_cholesky<D>(r, lane, diag, col) && lane == 0) atomicOr(err, 1);
+    if (!wave_cholesky<D>(r, lane, diag) && lane == 0) atomicOr(err, 1);
     __syncthreads();
     // F = L A^-T, row by row: F[i][j] *= 1 / A[j][j], then F[i][q] -= F[i][j] A[q][j] (q > j)
 #pragma unroll
@@ -532,29 +534,37 @@ __global__ __launch_bounds__(128) void k_niw_draw_wave(int K, int d, int k_max, 
       for (int q = 0; q < D; ++q) sm[lane * LD + q] = r[q];
     }
     wave_sync();
+    // (the row of Sigma stays in registers for its Cholesky factorisation)
     double* sig = sigma_out + (size_t)e * d * d;
-    for (int j = 0; j < d; j += 4) {
+    double sg[D];
+#pragma unroll
+    for (int j = 0; j < D; j += 4) {
       issue_fence();
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      const int j1 = j + 1 < D ? j + 1 : j, j2 = j + 2 < D ? j + 2 : j, j3 = j + 3 < D ? j + 3 : j;
+      if (j < d) {
 #pragma unroll
-      for (int q = 0; q < D; ++q) {
-        a0 = fma(r[q], sm[j * LD + q], a0);
-        a1 = fma(r[q], sm[j1 * LD + q], a1);
-        a2 = fma(r[q], sm[j2 * LD + q], a2);
-        a3 = fma(r[q], sm[j3 * LD + q], a3);
+        for (int q = 0; q < D; ++q) {
+          a0 = fma(r[q], sm[j * LD + q], a0);
+          a1 = fma(r[q], sm[(j + 1) * LD + q], a1);
+          a2 = fma(r[q], sm[(j + 2) * LD + q], a2);
+          a3 = fma(r[q], sm[(j + 3) * LD + q], a3);
+        }
+        if (live) {
+          sig[lane * d + j] = a0;
+          if (j + 1 < d) sig[lane * d + j + 1] = a1;
+          if (j + 2 < d) sig[lane * d + j + 2] = a2;
+          if (j + 3 < d) sig[lane * d + j + 3] = a3;
+        }
       }
-      if (live) {
-        sig[lane * d + j] = a0;
-        if (j + 1 < d) sig[lane * d + j + 1] = a1;
-        if (j + 2 < d) sig[lane * d + j + 2] = a2;
-        if (j + 3 < d) sig[lane * d + j + 3] = a3;
-      }
+      sg[j] = a0;
+      sg[j + 1] = a1;
+      sg[j + 2] = a2;
+      sg[j + 3] = a3;
     }
     // the scoring record: Sigma = G G^T, W = G^-1, log|Sigma|
 #pragma unroll
-    for (int j = 0; j < D; ++j) r[j] = (live && j < d) ? sig[lane * d + j] : (j == lane ? 1.0 : 0.0);
-    if (!wave_cholesky<D>(r, lane, diag, col) && lane == 0) atomicOr(err, 2);
+    for (int j = 0; j < D; ++j) r[j] = (live && j < d) ? sg[j] : (j == lane ? 1.0 : 0.0);
+    if (!wave_cholesky<D>(r, lane, diag) && lane == 0) atomicOr(err, 2);
     wave_sync();
     if (lane < D) {
 #pragma unroll

@@ -100,62 +100,70 @@ __global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, 
 
 // One wave per item, D >= d rows padded with an identity block (whose
 // pivots are 1 and add nothing to log|Psi_n|).  Lane i builds row i of Psi_n
-// (entries k <= i; the loads of 16 columns at a time are issued together) and
-// factors it with the wave Cholesky (pivots by v_readlane, columns broadcast
-// through a per-wave LDS buffer): no workgroup barrier.
+// (entries k <= i) from the item's statistics, staged in the wave's LDS
+// buffer in one round of loads, and factors it with the wave Cholesky (pivots
+// and column entries by v_readlane): no workgroup barrier.
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const LogmlItem* __restrict__ items, int d,
                                                             NiwPriorDev prior, double logdet_psi,
                                                             const long long* __restrict__ counts,
                                                             const double* __restrict__ moments,
                                                             double* __restrict__ out, int* __restrict__ err) {
-  __shared__ double cols[BLOCK / 64][D];
+  constexpr int ED = D + D * (D + 1) / 2;
+  __shared__ double ssum[BLOCK / 64][ED];  // per wave: the item's summed statistics
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int it = blockIdx.x * (BLOCK / 64) + wave;
   if (it >= n_items) return;
   const int E = d + d * (d + 1) / 2;
   const LogmlItem item = items[it];
+  const bool live = lane < d;
+  // every load of the item in one round: its counts, the sum of its segments'
+  // statistics (summed in segment order into the wave's LDS buffer) and the
+  // prior's row of Psi (entries k <= lane)
+  const double* Mq[4];
+  double nq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    Mq[q] = moments + (size_t)(item.seg[q] >= 0 ? item.seg[q] : 0) * E;
+    nq[q] = item.seg[q] >= 0 ? (double)counts[item.seg[q]] : 0.0;
+  }
+  double* sm = ssum[wave];
+#pragma unroll
+  for (int i = 0; i < (ED + 63) / 64; ++i) {
+    const int e = lane + 64 * i;
+    if (e < E) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (item.seg[q] >= 0) v += Mq[q][e];
+      sm[e] = v;
+    }
+  }
+  double r[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) r[k] = (k < d && live && k <= lane) ? prior.psi[lane * d + k] : 0.0;
   double n = 0.0;
-  for (int q = 0; q < 4; ++q)
-    if (item.seg[q] >= 0) n += (double)counts[item.seg[q]];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) n += nq[q];
   if (n == 0.0) {
     if (lane == 0) out[it] = 0.0;
     return;
   }
   const double kn = prior.kappa + n, nun = prior.nu + n, cm = prior.kappa * n / kn;
-  const bool live = lane < d;
-  // the item's segments (unused slots read segment 0 with weight 0)
-  const double* Mq[4];
-  double wq[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    wq[q] = item.seg[q] >= 0 ? 1.0 : 0.0;
-    Mq[q] = moments + (size_t)(item.seg[q] >= 0 ? item.seg[q] : 0) * E;
-  }
-  double si = 0.0;
-  for (int q = 0; q < 4; ++q)
-    if (item.seg[q] >= 0 && live) si += Mq[q][lane];
+  wave_sync();
+  const double si = live ? sm[lane] : 0.0;
   const double xi = si / n;
   const double dmi = live ? xi - prior.m[lane] : 0.0;
-  double r[D];
 #pragma unroll
-  for (int k0 = 0; k0 < D; k0 += 16) {
-    issue_fence();
-#pragma unroll
-    for (int k = k0; k < k0 + 16 && k < D; ++k) {
-      const double xk = readlane_d(xi, k), dmk = readlane_d(dmi, k);
-      const bool in = k < d && live && k <= lane;
-      const int tk = in ? d + k * d - (k * (k - 1)) / 2 + (lane - k) : 0;  // packed (k, lane), k <= lane
-      double S = 0.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (wq[q] != 0.0) S += Mq[q][tk];
-      const double v = prior.psi[in ? lane * d + k : 0] + (S - n * xi * xk) + cm * dmi * dmk;
-      r[k] = in ? v : (k == lane ? 1.0 : 0.0);
-    }
+  for (int k = 0; k < D; ++k) {
+    const double xk = readlane_d(xi, k), dmk = readlane_d(dmi, k);
+    const bool in = k < d && live && k <= lane;
+    const int tk = in ? d + k * d - (k * (k - 1)) / 2 + (lane - k) : 0;  // packed (k, lane), k <= lane
+    const double v = r[k] + (sm[tk] - n * xi * xk) + cm * dmi * dmk;
+    r[k] = in ? v : (k == lane ? 1.0 : 0.0);
   }
   double mydiag;
-  const bool ok = wave_cholesky<D>(r, lane, mydiag, cols[wave]);
+  const bool ok = wave_cholesky<D>(r, lane, mydiag);
   // log|Psi_n| = 2 sum log L_ii; log Gamma_d(nu_n / 2) - log Gamma_d(nu / 2)
   const double ld = 2.0 * wave_sum(live ? log(mydiag) : 0.0);
   const double lg = wave_sum(live ? lgamma(0.5 * nun - 0.5 * lane) - lgamma(0.5 * prior.nu - 0.5 * lane) : 0.0);
@@ -166,11 +174,6 @@ __global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const L
   }
 }
 
-// Merge test of every listed pair (Sec. 4.1 eq. sample_merges; with
-// paper_form = 0 the reciprocal of the split ratio of Sec. 2.3): pair p is the
-// item pairs[p] = (2 k1, 2 k1 + 1, 2 k2, 2 k2 + 1) with union marginal
-// lml_pair[p]; lml_cluster[3 k] is cluster k's marginal.  accept[p] = 1 when
-// log u < log H_merge with u the merge uniform of (k1, k2).
 // Read-back of one split/merge round in a single buffer (one copy to the
 // host instead of four): [int error flag, padded to 8 bytes][counts, 2K
 // int64][log marginals of the 3K cluster / sub-cluster items, float64][P merge
@@ -191,6 +194,11 @@ __global__ void k_pack_readback(int K, int P, const long long* __restrict__ coun
     om[i - 5 * K] = mflag[i - 5 * K];
 }
 
+// Merge test of every listed pair (Sec. 4.1 eq. sample_merges; with
+// paper_form = 0 the reciprocal of the split ratio of Sec. 2.3): pair p is the
+// item pairs[p] = (2 k1, 2 k1 + 1, 2 k2, 2 k2 + 1) with union marginal
+// lml_pair[p]; lml_cluster[3 k] is cluster k's marginal.  accept[p] = 1 when
+// log u < log H_merge with u the merge uniform of (k1, k2).
 __global__ void k_merge_decide(int n_pairs, const LogmlItem* __restrict__ pairs, const long long* __restrict__ counts,
                                const double* __restrict__ lml_cluster, const double* __restrict__ lml_pair,
                                double alpha, int paper_form, uint64_t seed, uint32_t t,

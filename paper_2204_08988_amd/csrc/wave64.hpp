@@ -1,6 +1,6 @@
 // Wave-level (64-lane) float64 helpers for kernels that give one wave to one
 // small matrix: lane i owns row i, uniform values travel by v_readlane, and
-// broadcast rows or columns through LDS with no workgroup barrier.
+// broadcast rows go through LDS with no workgroup barrier.
 #pragma once
 #include "common.hpp"
 
@@ -44,14 +44,16 @@ __device__ __forceinline__ double rsqrt_refined(double s) {
 }
 
 // Right-looking Cholesky of the matrix whose row `lane` is r (D x D): the
-// pivot comes by v_readlane, the scaled column j is broadcast through `col`
-// (LDS, D doubles) for the trailing update a_ik -= a_ij a_kj.  Afterwards r is
-// row `lane` of L (zero above the diagonal) and diag its pivot.  A pivot that
-// is not positive and finite is replaced by 1 and reported by the
-// (wave-uniform) return value.  Entries right of the diagonal are scratch
-// during the loop and are cleared at the end.
+// pivot and the entries L_kj of the scaled column j come by v_readlane (into
+// scalar registers, used directly as FMA operands) for the trailing update
+// a_ik -= a_ij a_kj, so a step waits on no memory and the next pivot depends
+// only on one read and one FMA.  Afterwards r is row `lane` of L (zero above
+// the diagonal) and diag its pivot.  A pivot that is not positive and finite
+// is replaced by 1 and reported by the (wave-uniform) return value.  Entries
+// right of the diagonal are scratch during the loop and are cleared at the
+// end.
 template <int D>
-__device__ __forceinline__ bool wave_cholesky(double (&r)[D], int lane, double& diag, double* col) {
+__device__ __forceinline__ bool wave_cholesky(double (&r)[D], int lane, double& diag) {
   bool ok = true;
   diag = 1.0;
 #pragma unroll
@@ -64,14 +66,8 @@ __device__ __forceinline__ bool wave_cholesky(double (&r)[D], int lane, double& 
     const double inv = rsqrt_refined(s), ljj = s * inv;
     if (lane == j) diag = ljj;
     r[j] = lane == j ? ljj : r[j] * inv;
-    if (j + 1 < D) {
-      // (a wave's LDS operations complete in order: the next step's write
-      // cannot overtake these reads)
-      if (lane < D) col[lane] = r[j];
-      wave_sync();
 #pragma unroll
-      for (int k = j + 1; k < D; ++k) r[k] = fma(-r[j], col[k], r[k]);
-    }
+    for (int k = j + 1; k < D; ++k) r[k] = fma(-r[j], readlane_d(r[j], k), r[k]);
   }
 #pragma unroll
   for (int j = 0; j < D; ++j)
