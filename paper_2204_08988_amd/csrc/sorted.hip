@@ -648,25 +648,6 @@ size_t sub_stats_lds(int d, int TR, bool generic) {
 }
 
 
-// FP32 score c - 1/2 |W (x - mu)|^2 of a row held in LDS under the record p
-// (wave-uniform: its loads are scalar); the centred row lives in registers.
-template <int D>
-__device__ __forceinline__ float score_lds(const float* __restrict__ p, const float* __restrict__ xr) {
-  float dx[D];
-#pragma unroll
-  for (int j = 0; j < D; ++j) dx[j] = xr[j] - p[4 + j];
-  const float* w = p + 4 + D;
-  float q = 0.0f;
-#pragma unroll
-  for (int r = 0; r < D; ++r) {
-    float y = 0.0f;
-#pragma unroll
-    for (int c = 0; c <= r; ++c) y = fmaf(w[r * (r + 1) / 2 + c], dx[c], y);
-    q = fmaf(y, y, q);
-  }
-  return fmaf(-0.5f, q, p[0]);
-}
-
 constexpr int BIG_THREADS = 512;  // 8 waves: 0-3 own the left segment, 4-7 the right
 constexpr int BIG_ROWS = 256;     // sorted rows per tile
 
@@ -836,13 +817,12 @@ size_t sub_labels_mfma_lds(int d) {
   return (size_t)(2 * S + 2 * d) * sizeof(float);
 }
 
-// Sub-labels (d = 64, SAMPLE) and statistics for d in {64, 128} over the
-// cluster-sorted order, with sum x x^T on the FP64 matrix cores.  A workgroup
-// of 8 waves walks a contiguous range of tiles of BIG_ROWS sorted rows:
-//   (1) the tile's rows are gathered into LDS (coalesced row reads);
-//   (2) with SAMPLE, thread r < BIG_ROWS draws row r's sub-label from the
-//       FP32 scores of the two sub-clusters of its cluster (wave-uniform
-//       parameters: scalar loads); otherwise the sub-label is read;
+// Statistics for d in {64, 128} over the cluster-sorted order (the sub-labels
+// are drawn before, by k_sub_labels_mfma), with sum x x^T on the FP64 matrix
+// cores.  A workgroup of 8 waves walks a contiguous range of tiles of BIG_ROWS
+// sorted rows:
+//   (1) the tile's rows are gathered into LDS (16-byte row pieces);
+//   (2) thread r < BIG_ROWS reads row r's sub-label;
 //   (3) rows are grouped by segment (run of a cluster, sub-label);
 //   (4) per segment, four rows at a time, v_mfma_f64_16x16x4_f64 adds
 //       X_I^T X_J to the upper 16 x 16 blocks (I, J) of sum x x^T: the left
@@ -851,20 +831,17 @@ size_t sub_labels_mfma_lds(int d) {
 //       sums a quarter of sum x in FP64 on the vector ALUs.
 // Each wave carries its segment of the current cluster across tiles and
 // flushes it with global atomics when the cluster changes or the range ends.
-template <int D, bool SAMPLE>
+template <int D>
 __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __restrict__ x, long long n_sorted,
                                                                int tpb, const int* __restrict__ perm,
                                                                const int* __restrict__ z,
                                                                const int* __restrict__ zrow,
-                                                               unsigned char* __restrict__ zsub,
-                                                               const float* __restrict__ packed, int k_max,
-                                                               uint32_t t, uint64_t seed,
+                                                               const unsigned char* __restrict__ zsub,
                                                                long long* __restrict__ counts,
                                                                double* __restrict__ moments) {
   constexpr int LD = D + 1;  // odd row stride
   constexpr int NB = D / 16, NT = NB * (NB + 1) / 2, TPW = (NT + 3) / 4;
   constexpr int E = D + D * (D + 1) / 2;
-  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
   constexpr int DW = D / 4;  // dimensions of sum x per wave
   extern __shared__ float xs[];  // [BIG_ROWS][LD]
   __shared__ int order[BIG_ROWS], rk[BIG_ROWS], buf[BIG_THREADS];
@@ -935,54 +912,27 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
     {
       // D / 4 lanes read a row in 16-byte pieces; all of a thread's loads are in
       // flight before the first LDS store
-      // (in two batches where the sub-label registers leave less room)
-      constexpr int C4 = D / 4, RPP = BIG_THREADS / C4, NP = BIG_ROWS / RPP, NBAT = SAMPLE ? 2 : 1;
+      constexpr int C4 = D / 4, RPP = BIG_THREADS / C4, NP = BIG_ROWS / RPP;
       const int c4 = tid % C4, r0 = tid / C4;
+      float4 v[NP];
 #pragma unroll
-      for (int bt = 0; bt < NBAT; ++bt) {
-        float4 v[NP / NBAT];
+      for (int j = 0; j < NP; ++j) {
+        const int r = r0 + j * RPP;
+        v[j] = r < rows ? reinterpret_cast<const float4*>(x + (size_t)order[r] * D)[c4]
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
 #pragma unroll
-        for (int j = 0; j < NP / NBAT; ++j) {
-          const int r = r0 + (bt * (NP / NBAT) + j) * RPP;
-          v[j] = r < rows ? reinterpret_cast<const float4*>(x + (size_t)order[r] * D)[c4]
-                          : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int j = 0; j < NP / NBAT; ++j) {
-          float* dst = xs + (r0 + (bt * (NP / NBAT) + j) * RPP) * LD + 4 * c4;
-          dst[0] = v[j].x;
-          dst[1] = v[j].y;
-          dst[2] = v[j].z;
-          dst[3] = v[j].w;
-        }
+      for (int j = 0; j < NP; ++j) {
+        float* dst = xs + (r0 + j * RPP) * LD + 4 * c4;
+        dst[0] = v[j].x;
+        dst[1] = v[j].y;
+        dst[2] = v[j].z;
+        dst[3] = v[j].w;
       }
     }
     __syncthreads();
     // ---- (2) sub-label of row tid
-    int zs = 0;
-    if (SAMPLE) {
-      float delta = 0.0f;
-      unsigned long long pending = __ballot(valid);
-      while (pending) {
-        const int lane0 = __ffsll((long long)pending) - 1;
-        const int kk = __builtin_amdgcn_readfirstlane(__shfl(k, lane0));
-        const bool mine = valid && k == kk;
-        if (mine) {
-          const float* ps = packed + (size_t)(k_max + 2 * kk) * S;
-          float sc[2];
-#pragma clang loop unroll(disable)
-          for (int h = 0; h < 2; ++h) sc[h] = score_lds<D>(ps + h * S, xs + tid * LD);
-          delta = sc[0] - sc[1];
-        }
-        pending &= ~__ballot(mine);
-      }
-      if (valid) {
-        zs = sub_label_draw(delta, seed, t, (uint32_t)my_i);
-        zsub[my_i] = (unsigned char)zs;
-      }
-    } else if (valid) {
-      zs = zsub[my_i] ? 1 : 0;
-    }
+    const int zs = valid && zsub[my_i] ? 1 : 0;
     // ---- (3) group rows by segment: run of the cluster (rows are sorted by
     // z), then sub-label
     const int flag = (valid && (tid == 0 || rk[tid] != rk[tid - 1])) ? 1 : 0;
@@ -1115,23 +1065,29 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
   hipError_t e;
   if (n == 0) return hipSuccess;
   if (d == 64 || d == 128) {
-    // d = 128 draws the sub-labels in their own pass (registers), then counts
-    if (sample && d == 128) {
-      // two workgroups per CU (the staged records take 66 KB), each on a contiguous range of rows
+    // the sub-labels first (their own pass), then the statistics
+    if (sample) {
+      // the sub-labels in their own pass on the FP32 matrix cores; at d = 128 two workgroups
+      // per CU (the staged records take 66 KB), each on a contiguous range of rows
       static bool lattr = false;
-      const size_t llds = sub_labels_mfma_lds(128);
+      const size_t llds = sub_labels_mfma_lds(d);
       if (!lattr) {
         e = hipFuncSetAttribute((const void*)k_sub_labels_mfma<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)llds);
+                                (int)sub_labels_mfma_lds(128));
         if (e != hipSuccess) return e;
         lattr = true;
       }
       const long long chunks = (n + SUBL_BLOCK - 1) / SUBL_BLOCK;
-      const long long gl = chunks < 512 ? chunks : 512;
+      const long long cap = d == 128 ? 512 : 1024;
+      const long long gl = chunks < cap ? chunks : cap;
       const long long lper = ((chunks + gl - 1) / gl) * SUBL_BLOCK;
       const unsigned lg = (unsigned)((n + lper - 1) / lper);
-      hipLaunchKernelGGL(k_sub_labels_mfma<128>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, perm, z, zrow, zsub,
-                         packed, k_max, t, seed);
+      if (d == 128)
+        hipLaunchKernelGGL(k_sub_labels_mfma<128>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, perm, z, zrow,
+                           zsub, packed, k_max, t, seed);
+      else
+        hipLaunchKernelGGL(k_sub_labels_mfma<64>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, perm, z, zrow,
+                           zsub, packed, k_max, t, seed);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const long long tiles = (n + BIG_ROWS - 1) / BIG_ROWS;
@@ -1142,23 +1098,19 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
     const size_t lds = (size_t)BIG_ROWS * (d + 1) * sizeof(float);  // above 64 KB: raise the limit once
     static bool attr_set = false;
     if (!attr_set) {
-      const void* fns[3] = {(const void*)k_sub_stats_big<64, true>, (const void*)k_sub_stats_big<64, false>,
-                            (const void*)k_sub_stats_big<128, false>};
+      const void* fns[2] = {(const void*)k_sub_stats_big<64>, (const void*)k_sub_stats_big<128>};
       for (const void* f : fns) {
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 144 * 1024);
         if (e != hipSuccess) return e;
       }
       attr_set = true;
     }
-    if (d == 64 && sample)
-      hipLaunchKernelGGL((k_sub_stats_big<64, true>), dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z,
-                         zrow, zsub, packed, k_max, t, seed, counts, moments);
-    else if (d == 64)
-      hipLaunchKernelGGL((k_sub_stats_big<64, false>), dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z,
-                         zrow, zsub, packed, k_max, t, seed, counts, moments);
+    if (d == 64)
+      hipLaunchKernelGGL(k_sub_stats_big<64>, dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z, zrow, zsub,
+                         counts, moments);
     else
-      hipLaunchKernelGGL((k_sub_stats_big<128, false>), dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z,
-                         zrow, zsub, packed, k_max, t, seed, counts, moments);
+      hipLaunchKernelGGL(k_sub_stats_big<128>, dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z, zrow, zsub,
+                         counts, moments);
     return hipGetLastError();
   }
   if (d == 8 || d == 16 || d == 32) {
