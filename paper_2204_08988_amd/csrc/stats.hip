@@ -169,6 +169,11 @@ __global__ __launch_bounds__(BLOCK) void k_stats_gauss_sorted(const float* __res
   }
 }
 
+// Count sums of the multinomial segments in LDS (uint32 partial sums).  A wave
+// takes 64 consecutive rows: lane r reads row r's label, then the lanes span
+// the words of one row at a time (a coalesced load through a buffer descriptor
+// that covers only rows below n, eight rows in flight) and add them to the
+// row's segment, distinct addresses within each LDS instruction.
 __global__ __launch_bounds__(BLOCK) void k_stats_mult_lds(const int* __restrict__ x, long long n, int V,
                                                           const int* __restrict__ z,
                                                           const unsigned char* __restrict__ zsub, int K,
@@ -179,18 +184,32 @@ __global__ __launch_bounds__(BLOCK) void k_stats_mult_lds(const int* __restrict_
   unsigned int* cnt = acc + 2 * K * V;  // [2K]
   for (int idx = threadIdx.x; idx < 2 * K * V + 2 * K; idx += BLOCK) lds_u[idx] = 0u;
   __syncthreads();
-  const long long stride_pts = (long long)gridDim.x * BLOCK;
-  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride_pts) {
-    const int zi = z[i];
-    const int zs = zsub[i];
-    if ((unsigned)zi >= (unsigned)K || zs > 1) continue;
-    const int s = 2 * zi + zs;
-    atomicAdd(&cnt[s], 1u);
-    unsigned int* a = acc + s * V;
-    const int* xi = x + i * V;
-    for (int v = 0; v < V; ++v) {
-      const int c = xi[v];
-      if (c) atomicAdd(&a[v], (unsigned int)c);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long long wstep = (long long)gridDim.x * (BLOCK / 64) * 64;
+  for (long long base = ((long long)blockIdx.x * (BLOCK / 64) + wave) * 64; base < n; base += wstep) {
+    const long long i = base + lane;
+    int seg = -1;
+    if (i < n) {
+      const int zi = z[i], zs = zsub[i];
+      if ((unsigned)zi < (unsigned)K && zs <= 1) seg = 2 * zi + zs;
+    }
+    if (seg >= 0) atomicAdd(&cnt[seg], 1u);
+    const long long rows = n - base < 64 ? n - base : 64;
+    const __amdgpu_buffer_rsrc_t rx =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(x + base * V), (short)0, (int)(rows * V * 4), 0x00020000);
+    for (int c0 = 0; c0 < V; c0 += 64) {
+      const int c = c0 + lane;
+      for (int r0 = 0; r0 < 64; r0 += 8) {
+        int val[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) val[j] = __builtin_amdgcn_raw_buffer_load_b32(rx, ((r0 + j) * V + c) * 4, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int sj = __builtin_amdgcn_readlane(seg, r0 + j);
+          if (sj >= 0 && c < V && val[j]) atomicAdd(&acc[sj * V + c], (unsigned int)val[j]);
+        }
+      }
     }
   }
   __syncthreads();

@@ -238,7 +238,7 @@ def _mult_points(params, n, seed):
     return x.astype(np.int32)
 
 
-@pytest.mark.parametrize("V,K,n", [(100, 50, 4000), (7, 3, 3001), (40, 9, 2000), (128, 2, 1500)])
+@pytest.mark.parametrize("V,K,n", [(100, 50, 4000), (7, 3, 3001), (40, 9, 2000), (128, 2, 1500), (33, 70, 6000)])
 def test_mult_loglik_labels_stats(V, K, n):
     torch = _torch()
     from paper_2204_08988_amd.sampler import Sampler
