@@ -487,8 +487,10 @@ __global__ __launch_bounds__(128) void k_niw_draw_wave(int K, int d, int k_max, 
     // one round of loads: the summed statistics into LDS, the prior's row into r
 #pragma unroll
     for (int i = 0; i < (ED + 63) / 64; ++i) {
-      const int q = lane + 64 * i;
-      if (q < E) sst[q] = M0[q] + (s1 >= 0 ? M1[q] : 0.0);
+      // unconditional loads (M1 is M0 when there is no second segment), then selected
+      const int q = lane + 64 * i, qc = q < E ? q : 0;
+      const double a0 = M0[qc], a1 = M1[qc];
+      if (q < E) sst[q] = a0 + (s1 >= 0 ? a1 : 0.0);
     }
 #pragma unroll
     for (int j = 0; j < D; ++j) r[j] = (live && j < d) ? prior.psi[lane * d + j] : 0.0;

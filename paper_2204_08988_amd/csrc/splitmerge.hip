@@ -120,24 +120,29 @@ __global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const L
   // every load of the item in one round: its counts, the sum of its segments'
   // statistics (summed in segment order into the wave's LDS buffer) and the
   // prior's row of Psi (entries k <= lane)
+  // (absent segments read segment 0 and add +0.0: unconditional loads, no
+  // branches, so that they are all in flight together)
   const double* Mq[4];
+  bool hq[4];
   double nq[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    Mq[q] = moments + (size_t)(item.seg[q] >= 0 ? item.seg[q] : 0) * E;
-    nq[q] = item.seg[q] >= 0 ? (double)counts[item.seg[q]] : 0.0;
+    hq[q] = item.seg[q] >= 0;
+    Mq[q] = moments + (size_t)(hq[q] ? item.seg[q] : 0) * E;
+    const long long c = counts[hq[q] ? item.seg[q] : 0];
+    nq[q] = hq[q] ? (double)c : 0.0;
   }
   double* sm = ssum[wave];
 #pragma unroll
   for (int i = 0; i < (ED + 63) / 64; ++i) {
-    const int e = lane + 64 * i;
-    if (e < E) {
-      double v = 0.0;
+    const int e = lane + 64 * i, ec = e < E ? e : 0;
+    double m[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (item.seg[q] >= 0) v += Mq[q][e];
-      sm[e] = v;
-    }
+    for (int q = 0; q < 4; ++q) m[q] = Mq[q][ec];
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v += hq[q] ? m[q] : 0.0;
+    if (e < E) sm[e] = v;
   }
   double r[D];
 #pragma unroll
