@@ -21,6 +21,11 @@ using namespace wave64;
 
 namespace {
 
+// log Gamma as one shared (not inlined) copy: the kernels below call it several
+// times each, and their code is fetched once per wave
+__device__ __attribute__((noinline)) double lgamma_d(double v) { return lgamma(v); }
+
+
 constexpr int BLOCK = 256;
 
 __device__ __forceinline__ int tri_index(int a, int b, int d) {
@@ -87,7 +92,7 @@ __global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, 
   for (int i = tid; i < d; i += BLOCK) {
     ld += log(P[i * d + i]);
     // log Gamma_d(nu_n / 2) - log Gamma_d(nu / 2), term j = i + 1
-    lg += lgamma(0.5 * nun - 0.5 * i) - lgamma(0.5 * prior.nu - 0.5 * i);
+    lg += lgamma_d(0.5 * nun - 0.5 * i) - lgamma_d(0.5 * prior.nu - 0.5 * i);
   }
   ld = 2.0 * reduce_sum(ld, red);
   lg = reduce_sum(lg, red);
@@ -171,7 +176,7 @@ __global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const L
   const bool ok = wave_cholesky<D>(r, lane, mydiag);
   // log|Psi_n| = 2 sum log L_ii; log Gamma_d(nu_n / 2) - log Gamma_d(nu / 2)
   const double ld = 2.0 * wave_sum(live ? log(mydiag) : 0.0);
-  const double lg = wave_sum(live ? lgamma(0.5 * nun - 0.5 * lane) - lgamma(0.5 * prior.nu - 0.5 * lane) : 0.0);
+  const double lg = wave_sum(live ? lgamma_d(0.5 * nun - 0.5 * lane) - lgamma_d(0.5 * prior.nu - 0.5 * lane) : 0.0);
   if (lane == 0) {
     if (!ok) atomicOr(err, 4);
     out[it] = -0.5 * n * d * 1.1447298858494002 + lg + 0.5 * prior.nu * logdet_psi - 0.5 * nun * ld +
@@ -214,11 +219,11 @@ __global__ void k_merge_decide(int n_pairs, const LogmlItem* __restrict__ pairs,
   const int k1 = it.seg[0] >> 1, k2 = it.seg[2] >> 1;
   const double n1 = (double)(counts[2 * k1] + counts[2 * k1 + 1]);
   const double n2 = (double)(counts[2 * k2] + counts[2 * k2 + 1]);
-  double lh = lgamma(n1 + n2) - log(alpha) - lgamma(n1) - lgamma(n2) + lml_pair[p] - lml_cluster[3 * k1] -
+  double lh = lgamma_d(n1 + n2) - log(alpha) - lgamma_d(n1) - lgamma_d(n2) + lml_pair[p] - lml_cluster[3 * k1] -
               lml_cluster[3 * k2];
   if (paper_form)
-    lh += lgamma(alpha) - lgamma(alpha + n1 + n2) + lgamma(0.5 * alpha + n1) + lgamma(0.5 * alpha + n2) -
-          2.0 * lgamma(0.5 * alpha);
+    lh += lgamma_d(alpha) - lgamma_d(alpha + n1 + n2) + lgamma_d(0.5 * alpha + n1) + lgamma_d(0.5 * alpha + n2) -
+          2.0 * lgamma_d(0.5 * alpha);
   const double u = uniform_d(rng_block(seed, t, merge_entity(k1, k2), TAG_MERGE, 0).x);
   accept[p] = log(u) < lh ? 1 : 0;
 }
@@ -243,12 +248,12 @@ __global__ void k_logml_mult(int n_items, const LogmlItem* __restrict__ items, i
     long long c = 0;
     for (int q = 0; q < 4; ++q)
       if (item.seg[q] >= 0) c += sums[(size_t)item.seg[q] * V + v];
-    acc += lgamma(beta[v] + (double)c) - lgamma_beta[v];
+    acc += lgamma_d(beta[v] + (double)c) - lgamma_beta[v];
     tot += (double)c;
   }
   acc = reduce_sum(acc, red);
   tot = reduce_sum(tot, red);
-  if (threadIdx.x == 0) out[it] = lgamma_beta_sum - lgamma(beta_sum + tot) + acc;
+  if (threadIdx.x == 0) out[it] = lgamma_beta_sum - lgamma_d(beta_sum + tot) + acc;
 }
 
 __global__ void k_relabel(long long n, const RelabelEntry* __restrict__ table, int n_entries, uint32_t t,
