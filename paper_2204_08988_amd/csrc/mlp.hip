@@ -45,18 +45,43 @@ __global__ __launch_bounds__(BLOCK) void k_gemm_nt(const __bf16* __restrict__ A,
   const int row = m0 + (lane & 31), col = n0 + (lane & 31), kh = 8 * (lane >> 5);
   f32x16 acc = {0};
   const bf16x8 zero = {};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    bf16x8 a = row < M ? *reinterpret_cast<const bf16x8*>(A + (size_t)row * lda + k0 + kh) : zero;
-    bf16x8 b = col < N ? *reinterpret_cast<const bf16x8*>(Bt + (size_t)col * ldb + k0 + kh) : zero;
-    if (k0 + 16 > K) {
+  // rows past M (columns past N) read row M - 1 (N - 1) and are zeroed: the loads
+  // carry no branch, so the unrolled loop keeps several in flight
+  const bool va = row < M, vb = col < N;
+  const __bf16* pa = A + (size_t)(va ? row : M - 1) * lda + kh;
+  const __bf16* pb = Bt + (size_t)(vb ? col : N - 1) * ldb + kh;
+  const int kfull = K & ~15, nblk = kfull / 16;
+  if (nblk > 0) {
+    // four blocks of K in flight: ring slot j holds block i + j; the prefetch
+    // index is clamped to the last full block (a harmless reload at the end)
+    constexpr int PD = 4;
+    bf16x8 ra[PD], rb[PD];
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (k0 + kh + q >= K) {
-          a[q] = (__bf16)0.0f;
-          b[q] = (__bf16)0.0f;
-        }
+    for (int j = 0; j < PD; ++j) {
+      const int kb = 16 * (j < nblk ? j : nblk - 1);
+      ra[j] = *reinterpret_cast<const bf16x8*>(pa + kb);
+      rb[j] = *reinterpret_cast<const bf16x8*>(pb + kb);
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    for (int i = 0; i < nblk; i += PD) {
+#pragma unroll
+      for (int j = 0; j < PD; ++j) {
+        if (i + j < nblk) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va ? ra[j] : zero, vb ? rb[j] : zero, acc, 0, 0, 0);
+        const int nx = i + j + PD < nblk ? i + j + PD : nblk - 1;
+        ra[j] = *reinterpret_cast<const bf16x8*>(pa + 16 * nx);
+        rb[j] = *reinterpret_cast<const bf16x8*>(pb + 16 * nx);
+      }
+    }
+  }
+  if (kfull < K) {
+    bf16x8 a = *reinterpret_cast<const bf16x8*>(pa + kfull);
+    bf16x8 b = *reinterpret_cast<const bf16x8*>(pb + kfull);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (kfull + kh + q >= K) {
+        a[q] = (__bf16)0.0f;
+        b[q] = (__bf16)0.0f;
+      }
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va ? a : zero, vb ? b : zero, acc, 0, 0, 0);
   }
   if (col >= N) return;
 #pragma unroll
