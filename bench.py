@@ -269,8 +269,8 @@ def learned_ab(args):
     out.update({k: v for k, v in runs[0].items() if k != "seed"})
     sp = [r["speedup_wall"] for r in runs if r["speedup_wall"] is not None]
     out["seeds"] = [{k: v for k, v in r.items() if k not in ("plain", "learned")} |
-                    {f: {k: r[f][k] for k in ("time_to_plateau_s", "iters_to_plateau", "final_K", "nmi",
-                                                "learned_accepted", "train_s")} for f in ("plain", "learned")}
+                    {f: {k: r[f][k] for k in ("time_to_plateau_s", "iters_to_plateau", "final_K", "final_logpost",
+                                                "nmi", "learned_accepted", "train_s")} for f in ("plain", "learned")}
                     for r in runs]
     out["median_speedup_wall"] = float(np.median(sp)) if sp else None
     print(json.dumps(out), flush=True)
