@@ -14,6 +14,8 @@
 // s = 2 z + zsub, and every lane accumulates a 2x2 block of sum x x^T (or two
 // entries of sum x) in float64 registers over each segment's rows, with one
 // global atomic per entry, segment and tile.
+#include <utility>
+
 #include "kernels.hpp"
 #include "score.hpp"
 
@@ -817,6 +819,53 @@ size_t sub_labels_mfma_lds(int d) {
   return (size_t)(2 * S + 2 * d) * sizeof(float);
 }
 
+// Upper 16 x 16 block u (row-major over I <= J) of an NB x NB block grid.
+constexpr int blk_i(int u, int nb) {
+  int a = 0;
+  while (a < nb && u >= nb - a) {
+    u -= nb - a;
+    ++a;
+  }
+  return a;
+}
+constexpr int blk_j(int u, int nb) { return u - (blk_i(u, nb) * nb - blk_i(u, nb) * (blk_i(u, nb) - 1) / 2) + blk_i(u, nb); }
+
+// The accumulator updates of one four-row step for wave quarter WQ: block
+// u = WQ + 4 j of accumulator j, its (I, J) fixed at compile time so that the
+// operands are plain registers.
+template <int U, int NB>
+constexpr int BLK_I = blk_i(U, NB) < NB ? blk_i(U, NB) : NB - 1;
+template <int U, int NB>
+constexpr int BLK_J = blk_i(U, NB) < NB ? blk_j(U, NB) : NB - 1;
+
+template <int NB, int WQ, int TPW, int... J>
+__device__ __forceinline__ void big_mfmas(f64x4 (&acc)[TPW], const double (&xv)[NB], std::integer_sequence<int, J...>) {
+  constexpr int NT = NB * (NB + 1) / 2;
+  ((WQ + 4 * J < NT
+        ? (void)(acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[BLK_I<WQ + 4 * J, NB>], xv[BLK_J<WQ + 4 * J, NB>],
+                                                               acc[J], 0, 0, 0))
+        : (void)0),
+   ...);
+}
+
+// Rows [st, st + cnt) of a tile's order list, four at a time, into the
+// accumulators of wave quarter WQ (upper blocks WQ, WQ + 4, ...): each step
+// reads the row's D / 16 column blocks once and feeds every block from them
+// (a lane past the segment reads the tile's zero row).
+template <int D, int WQ, int TPW>
+__device__ __forceinline__ void big_rows(f64x4 (&acc)[TPW], const float* __restrict__ xs,
+                                         const int* __restrict__ order, int st, int cnt, int lane, int zero_row) {
+  constexpr int LD = D + 1, NB = D / 16, NT = NB * (NB + 1) / 2;
+  for (int g = 0; g < cnt; g += 4) {
+    const int p = g + (lane >> 4);
+    const int ro = (p < cnt ? order[st + p] : zero_row) * LD + (lane & 15);
+    double xv[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) xv[b] = (double)xs[ro + 16 * b];
+    big_mfmas<NB, WQ>(acc, xv, std::make_integer_sequence<int, TPW>{});
+  }
+}
+
 // Statistics for d in {64, 128} over the cluster-sorted order (the sub-labels
 // are drawn before, by k_sub_labels_mfma), with sum x x^T on the FP64 matrix
 // cores.  A workgroup of 8 waves walks a contiguous range of tiles of BIG_ROWS
@@ -843,7 +892,7 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
   constexpr int NB = D / 16, NT = NB * (NB + 1) / 2, TPW = (NT + 3) / 4;
   constexpr int E = D + D * (D + 1) / 2;
   constexpr int DW = D / 4;  // dimensions of sum x per wave
-  extern __shared__ float xs[];  // [BIG_ROWS][LD]
+  extern __shared__ float xs[];  // [BIG_ROWS + 1][LD], the last row zero
   __shared__ int order[BIG_ROWS], rk[BIG_ROWS], buf[BIG_THREADS];
   __shared__ int lcount[2 * BIG_ROWS], lstart[2 * BIG_ROWS], lseg[2 * BIG_ROWS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -891,6 +940,8 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
     if (wq == 0 && lane == 0) atomicAdd((unsigned long long*)&counts[seg], (unsigned long long)cnt_seg);
   };
   zero_acc();
+  // row BIG_ROWS of the tile buffer stays zero (read by lanes past a segment)
+  for (int c = tid; c < LD; c += BIG_THREADS) xs[BIG_ROWS * LD + c] = 0.0f;
   const long long tiles = (n_sorted + BIG_ROWS - 1) / BIG_ROWS;
   const long long tb = (long long)blockIdx.x * tpb;
   const long long te = tb + tpb < tiles ? tb + tpb : tiles;
@@ -969,19 +1020,19 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
       }
       cnt_seg += cnt;
       const int st = lstart[q];
-      for (int g = 0; g < cnt; g += 4) {
-        // unconditional LDS reads (a lane past the segment reads row 0 and zeroes its
-        // A operand), so that the reads of a step overlap and need no branches
-        const int p = g + (lane >> 4);
-        const bool ok = p < cnt;
-        const int ro = order[st + (ok ? p : 0)] * LD + (lane & 15);
-#pragma unroll
-        for (int j = 0; j < TPW; ++j) {
-          if (bI[j] < 0) continue;
-          const float fa = xs[ro + 16 * bI[j]], fb = xs[ro + 16 * bJ[j]];
-          const double av = ok ? (double)fa : 0.0, bv = (double)fb;
-          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[j], 0, 0, 0);
-        }
+      // (the quarter as a compile-time constant: its blocks' operands come from registers)
+      switch (wq) {
+        case 0:
+          big_rows<D, 0>(acc, xs, order, st, cnt, lane, BIG_ROWS);
+          break;
+        case 1:
+          big_rows<D, 1>(acc, xs, order, st, cnt, lane, BIG_ROWS);
+          break;
+        case 2:
+          big_rows<D, 2>(acc, xs, order, st, cnt, lane, BIG_ROWS);
+          break;
+        default:
+          big_rows<D, 3>(acc, xs, order, st, cnt, lane, BIG_ROWS);
       }
       if (lane < DW) {
         // four independent partial sums, each in row order, added at the end
@@ -1095,7 +1146,7 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
     const long long g = tiles < gmax ? tiles : gmax;
     const int tpb = (int)((tiles + g - 1) / g);
     const unsigned grid = (unsigned)((tiles + tpb - 1) / tpb);
-    const size_t lds = (size_t)BIG_ROWS * (d + 1) * sizeof(float);  // above 64 KB: raise the limit once
+    const size_t lds = (size_t)(BIG_ROWS + 1) * (d + 1) * sizeof(float);  // above 64 KB: raise the limit once
     static bool attr_set = false;
     if (!attr_set) {
       const void* fns[2] = {(const void*)k_sub_stats_big<64>, (const void*)k_sub_stats_big<128>};
