@@ -853,9 +853,9 @@ __device__ __forceinline__ void big_mfmas(f64x4 (&acc)[TPW], const double (&xv)[
 // reads the row's D / 16 column blocks once and feeds every block from them
 // (a lane past the segment reads the tile's zero row).
 template <int D, int WQ, int TPW>
-__device__ __forceinline__ void big_rows(f64x4 (&acc)[TPW], const float* __restrict__ xs,
+__device__ __forceinline__ void big_rows(f64x4 (&acc)[TPW], double (&sx)[D / 64], const float* __restrict__ xs,
                                          const int* __restrict__ order, int st, int cnt, int lane, int zero_row) {
-  constexpr int LD = D + 1, NB = D / 16, NT = NB * (NB + 1) / 2;
+  constexpr int LD = D + 1, NB = D / 16;
   for (int g = 0; g < cnt; g += 4) {
     const int p = g + (lane >> 4);
     const int ro = (p < cnt ? order[st + p] : zero_row) * LD + (lane & 15);
@@ -863,6 +863,10 @@ __device__ __forceinline__ void big_rows(f64x4 (&acc)[TPW], const float* __restr
 #pragma unroll
     for (int b = 0; b < NB; ++b) xv[b] = (double)xs[ro + 16 * b];
     big_mfmas<NB, WQ>(acc, xv, std::make_integer_sequence<int, TPW>{});
+    // sum x over the quarter's column blocks WQ, WQ + 4, ...: lane l adds
+    // column 16 b + l % 16 of row g + l / 16
+#pragma unroll
+    for (int j = 0; j < D / 64; ++j) sx[j] += xv[WQ + 4 * j];
   }
 }
 
@@ -876,8 +880,8 @@ __device__ __forceinline__ void big_rows(f64x4 (&acc)[TPW], const float* __restr
 //   (4) per segment, four rows at a time, v_mfma_f64_16x16x4_f64 adds
 //       X_I^T X_J to the upper 16 x 16 blocks (I, J) of sum x x^T: the left
 //       segment belongs to waves 0-3, the right to waves 4-7, and a wave owns
-//       blocks w, w + 4, ... (FP32 inputs are exact in FP64); each wave also
-//       sums a quarter of sum x in FP64 on the vector ALUs.
+//       blocks w, w + 4, ... (FP32 inputs are exact in FP64); from the same
+//       registers it also sums x over column blocks w, w + 4, ... in FP64.
 // Each wave carries its segment of the current cluster across tiles and
 // flushes it with global atomics when the cluster changes or the range ends.
 template <int D>
@@ -891,7 +895,7 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
   constexpr int LD = D + 1;  // odd row stride
   constexpr int NB = D / 16, NT = NB * (NB + 1) / 2, TPW = (NT + 3) / 4;
   constexpr int E = D + D * (D + 1) / 2;
-  constexpr int DW = D / 4;  // dimensions of sum x per wave
+  constexpr int SB = D / 64;  // column blocks of sum x per wave
   extern __shared__ float xs[];  // [BIG_ROWS + 1][LD], the last row zero
   __shared__ int order[BIG_ROWS], rk[BIG_ROWS], buf[BIG_THREADS];
   __shared__ int lcount[2 * BIG_ROWS], lstart[2 * BIG_ROWS], lseg[2 * BIG_ROWS];
@@ -913,13 +917,14 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
     }
   }
   f64x4 acc[TPW];
-  double sx = 0.0;
+  double sx[SB];
   long long cnt_seg = 0;
   int cur_k = -1;
   auto zero_acc = [&]() {
 #pragma unroll
     for (int j = 0; j < TPW; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
-    sx = 0.0;
+#pragma unroll
+    for (int j = 0; j < SB; ++j) sx[j] = 0.0;
     cnt_seg = 0;
   };
   auto flush = [&]() {
@@ -936,7 +941,14 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
         if (a <= b) atomicAdd(&M[D + a * D - (a * (a - 1)) / 2 + (b - a)], acc[j][e]);
       }
     }
-    if (lane < DW) atomicAdd(&M[wq * DW + lane], sx);
+#pragma unroll
+    for (int j = 0; j < SB; ++j) {
+      // the four row groups (lanes l, l + 16, l + 32, l + 48) combined
+      double v = sx[j];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (lane < 16) atomicAdd(&M[16 * (wq + 4 * j) + lane], v);
+    }
     if (wq == 0 && lane == 0) atomicAdd((unsigned long long*)&counts[seg], (unsigned long long)cnt_seg);
   };
   zero_acc();
@@ -1023,28 +1035,16 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
       // (the quarter as a compile-time constant: its blocks' operands come from registers)
       switch (wq) {
         case 0:
-          big_rows<D, 0>(acc, xs, order, st, cnt, lane, BIG_ROWS);
+          big_rows<D, 0>(acc, sx, xs, order, st, cnt, lane, BIG_ROWS);
           break;
         case 1:
-          big_rows<D, 1>(acc, xs, order, st, cnt, lane, BIG_ROWS);
+          big_rows<D, 1>(acc, sx, xs, order, st, cnt, lane, BIG_ROWS);
           break;
         case 2:
-          big_rows<D, 2>(acc, xs, order, st, cnt, lane, BIG_ROWS);
+          big_rows<D, 2>(acc, sx, xs, order, st, cnt, lane, BIG_ROWS);
           break;
         default:
-          big_rows<D, 3>(acc, xs, order, st, cnt, lane, BIG_ROWS);
-      }
-      if (lane < DW) {
-        // four independent partial sums, each in row order, added at the end
-        const int dim = wq * DW + lane;
-        double s4[4] = {0.0, 0.0, 0.0, 0.0};
-        int p = 0;
-        for (; p + 4 <= cnt; p += 4) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) s4[u] += (double)xs[order[st + p + u] * LD + dim];
-        }
-        for (; p < cnt; ++p) s4[0] += (double)xs[order[st + p] * LD + dim];
-        sx += (s4[0] + s4[1]) + (s4[2] + s4[3]);
+          big_rows<D, 3>(acc, sx, xs, order, st, cnt, lane, BIG_ROWS);
       }
     }
   }
