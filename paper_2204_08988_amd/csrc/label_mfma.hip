@@ -525,6 +525,178 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma_dma(const float* __r
   }
 }
 
+constexpr int BLOCK_W32 = 512;  // threads of k_label_gauss_mfma_w32: 8 waves of 32 points
+constexpr bool W32_AT_64 = true;
+
+// d = 64, 128 with half the registers per wave: the staging is that of
+// k_label_gauss_mfma_dma (a cluster's non-zero whitener tiles, mean and
+// constant copied straight into one of two static LDS buffers while the
+// previous cluster is scored from the other, one barrier per cluster), but a
+// wave scores a single 32-point tile: lanes l and l + 32 hold the two halves
+// of the K slice of point l % 32, so a lane keeps d / 2 FP32 coordinates and
+// one 16-register accumulator.  Two waves then share a SIMD and one wave's
+// centring and squared norms on the vector ALUs overlap the other's
+// matrix-core tiles.  A workgroup step covers 256 points, as for the other
+// label kernels (the per-workgroup histogram blocks are the same).  Points
+// whose top-2 gap leaves any doubt are appended to `flagged` (z = -1, not in
+// the histogram) for the candidate pass and k_rescore_flagged.
+template <int D, bool X3, bool CANDS>
+__global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float* __restrict__ x, long long n,
+                                                                   long long per_block, const float* __restrict__ packed,
+                                                                   const bf16x8* __restrict__ whi,
+                                                                   const bf16x8* __restrict__ wlo, int K, uint32_t t,
+                                                                   uint64_t seed, int* __restrict__ z,
+                                                                   int* __restrict__ hist, int* __restrict__ tot,
+                                                                   int* __restrict__ flagged, int* __restrict__ cand,
+                                                                   int* __restrict__ n_flagged) {
+  using TT = TriTiles<D>;
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  constexpr int MT = TT::MT, KS = TT::KS, NF = MT * KS * 64;  // fragments per cluster in global memory
+  constexpr int NFZ = TT::NT * 64;                              // fragments per cluster staged (non-zero tiles)
+  constexpr int NJ = (NFZ + BLOCK_W32 - 1) / BLOCK_W32;
+  constexpr float REL = X3 ? BF16X3_TOL_REL : BF16_TOL_REL;
+  constexpr int NB = X3 ? 2 : 1;  // fragment tables per cluster (hi, lo)
+  constexpr int MUS = D + 4;      // mu[D], c
+  constexpr int CHUNK = BLOCK_W32 / 2;
+  static_assert(D < BLOCK_W32 && CHUNK == BLOCK && NFZ % 64 == 0, "staging layout, histogram blocks");
+  __shared__ __align__(16) bf16x8 s_w0[NB * NFZ], s_w1[NB * NFZ];
+  __shared__ __align__(16) float s_mu0[MUS], s_mu1[MUS];
+  extern __shared__ int h[];  // K counters
+  for (int k = threadIdx.x; k < K; k += BLOCK_W32) h[k] = 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  const int wbase = threadIdx.x & ~63;
+  // main pass: the workgroup's points; candidate pass: the deferred slots, grid-strided
+  const long long nf = CANDS ? (long long)*n_flagged : 0;
+  const long long begin = CANDS ? (long long)blockIdx.x * CHUNK : (long long)blockIdx.x * per_block;
+  const long long end = CANDS ? nf : (begin + per_block < n ? begin + per_block : n);
+  const long long step = CANDS ? (long long)gridDim.x * CHUNK : CHUNK;
+  // copies of cluster k into (dw, dmu): fragment f of the staged table is tile f / 64 in
+  // (row block, ks) order, lane f % 64; each wave fills 64 consecutive entries
+  auto stage = [&](bf16x8* dw, float* dmu, int k) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int f = j * BLOCK_W32 + threadIdx.x;
+      if (f < NFZ) {
+        const int tt = f >> 6;
+        int mt = 0, o = 0;
+#pragma unroll
+        for (int m = 1; m < MT; ++m)
+          if (tt >= TT::off(m)) mt = m, o = TT::off(m);
+        const size_t g = (size_t)k * NF + (size_t)(mt * KS + tt - o) * 64 + (f & 63);
+        __builtin_amdgcn_global_load_lds((const void*)(whi + g), (lds_void*)(dw + j * BLOCK_W32 + wbase), 16, 0, 0);
+        if (X3)
+          __builtin_amdgcn_global_load_lds((const void*)(wlo + g), (lds_void*)(dw + NFZ + j * BLOCK_W32 + wbase), 16,
+                                           0, 0);
+      }
+    }
+    if (threadIdx.x <= D) {
+      const float* rec = packed + (size_t)k * S;
+      __builtin_amdgcn_global_load_lds((const void*)(threadIdx.x < D ? rec + 4 + threadIdx.x : rec),
+                                       (lds_void*)(dmu + wbase), 4, 0, 0);
+    }
+  };
+  if (begin < end) stage(s_w0, s_mu0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int buf = 0;
+  // every wave runs the same number of chunks and clusters: one barrier per cluster
+  for (long long chunk = begin; chunk < end; chunk += step) {
+    const long long r = chunk + wave * 32 + col;
+    const bool ok = r < end;
+    const long long p = ok ? (CANDS ? (long long)flagged[r] : r) : 0;
+    // the lane's half of the point's coordinates: 8 per K slice of 16 (a lane
+    // past the end reads row 0 and keeps zeros)
+    float xv[KS][8];
+    const float4* xr = reinterpret_cast<const float4*>(x + p * D) + 2 * half;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const float4 v0 = xr[4 * ks], v1 = xr[4 * ks + 1];
+      xv[ks][0] = ok ? v0.x : 0.0f;
+      xv[ks][1] = ok ? v0.y : 0.0f;
+      xv[ks][2] = ok ? v0.z : 0.0f;
+      xv[ks][3] = ok ? v0.w : 0.0f;
+      xv[ks][4] = ok ? v1.x : 0.0f;
+      xv[ks][5] = ok ? v1.y : 0.0f;
+      xv[ks][6] = ok ? v1.z : 0.0f;
+      xv[ks][7] = ok ? v1.w : 0.0f;
+    }
+    const bool more = chunk + step < end;
+    Top2U t2;
+    Cands cd;
+    if (CANDS)
+      cd.init();
+    else
+      t2.init();
+    // score cluster k from (cw, cmu) while cluster kn is copied into (nw, nmu)
+    auto cluster = [&](const bf16x8* cw, const float* cmu, bf16x8* nw, float* nmu, int k, bool next, int kn) {
+      if (next) stage(nw, nmu, kn);
+      const bf16x8* cwl = cw + (NB - 1) * NFZ;
+      bf16x8 b[KS], bl[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float dv = xv[ks][q] - cmu[16 * ks + 8 * half + q];
+          b[ks][q] = (__bf16)dv;
+          if (X3) bl[ks][q] = (__bf16)(dv - (float)b[ks][q]);
+        }
+      float q0 = 0.0f, q1 = 0.0f;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f32x16 acc = {0};
+#pragma unroll
+        for (int ks = 0; ks < TT::tiles(mt); ++ks) {
+          const int tile = TT::off(mt) + ks;
+          const bf16x8 a = cw[tile * 64 + lane];
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[ks], acc, 0, 0, 0);
+          if (X3) {
+            const bf16x8 al = cwl[tile * 64 + lane];
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b[ks], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl[ks], acc, 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 16; e += 2) {
+          q0 = fmaf(acc[e], acc[e], q0);
+          q1 = fmaf(acc[e + 1], acc[e + 1], q1);
+        }
+      }
+      // lane l holds rows 4 (l / 32) + ... of every 8: the other half has the rest
+      float qm = q0 + q1;
+      qm += __shfl_xor(qm, 32);
+      const float l = fmaf(-0.5f, qm, cmu[D]);
+      if (CANDS)
+        cd.push(l, qm, REL, k);
+      else
+        t2.push(l, qm, REL, k);
+      // this wave's copies into the other buffer have landed; after the barrier all have
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    };
+    for (int k = 0; k < K; ++k) {
+      const bool next = k + 1 < K || more;
+      const int kn = k + 1 < K ? k + 1 : 0;
+      if (buf == 0)
+        cluster(s_w0, s_mu0, s_w1, s_mu1, k, next, kn);
+      else
+        cluster(s_w1, s_mu1, s_w0, s_mu0, k, next, kn);
+      buf ^= 1;
+    }
+    // lanes 0-31 own the points (lanes 32-63 hold the same state)
+    if (CANDS)
+      finish_cands(ok && half == 0, r, p, cd, REL, K, per_block, t, seed, z, hist, tot, cand);
+    else
+      finish_main(ok && half == 0, r, t2, z, h, flagged, n_flagged, lane);
+  }
+  if (CANDS) return;
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += BLOCK_W32) {
+    hist[(size_t)blockIdx.x * K + k] = h[k];
+    if (h[k]) atomicAdd(&tot[k], h[k]);
+  }
+}
+
 // d = 64: the cluster's whitener fragments (and mu, c) are staged in LDS once
 // per workgroup and shared by its four waves, double-buffered: cluster k + 1 is
 // fetched into registers while cluster k computes (at d = 64 the prefetch fits
@@ -860,14 +1032,24 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
 #define DPMM_MFMA_LDS(KER, DD, XX, CC, L)                                                                 \
   hipLaunchKernelGGL((KER<DD, XX, CC>), dim3(Gp), dim3(BLOCK), L, s, x, n, per_block, packed, hi, lo, K, t, seed, \
                      z, hist, tot, flagged, cand, n_flagged)
+#define DPMM_MFMA_W32(DD, XX, CC)                                                                             \
+  hipLaunchKernelGGL((k_label_gauss_mfma_w32<DD, XX, CC>), dim3(Gp), dim3(BLOCK_W32), lh, s, x, n, per_block, packed, \
+                     hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
       if (d == 128) {
         // the candidate pass scores in bf16x3 whatever the main pass's form
         if (cands)
-          DPMM_MFMA_LDS(k_label_gauss_mfma_dma, 128, true, true, lh);
+          DPMM_MFMA_W32(128, true, true);
         else if (x3)
-          DPMM_MFMA_LDS(k_label_gauss_mfma_dma, 128, true, false, lh);
+          DPMM_MFMA_W32(128, true, false);
         else
-          DPMM_MFMA_LDS(k_label_gauss_mfma_dma, 128, false, false, lh);
+          DPMM_MFMA_W32(128, false, false);
+      } else if (W32_AT_64) {
+        if (cands)
+          DPMM_MFMA_W32(64, true, true);
+        else if (x3)
+          DPMM_MFMA_W32(64, true, false);
+        else
+          DPMM_MFMA_W32(64, false, false);
       } else {
         const int NF = (d / 32) * (d / 16) * 64;
         const size_t lds = 2 * ((size_t)(x3 || cands ? 2 : 1) * NF * sizeof(bf16x8) + (d + 4) * sizeof(float)) + lh;
@@ -879,6 +1061,7 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
           DPMM_MFMA_LDS(k_label_gauss_mfma_lds, 64, false, false, lds);
       }
 #undef DPMM_MFMA_LDS
+#undef DPMM_MFMA_W32
     } else if (d == 32) {
       // [CG][NB][NF] fragments (64 KB), [CG][d + 4] means and constants, the histogram;
       // the candidate pass scores in bf16x3
