@@ -31,10 +31,14 @@ SEED = 1
 ALPHA = 10.0
 PEAK_FP32_VALU = 78.6e12   # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (non-packed FP32)
 PEAK_BF16_MFMA = 2.5e15    # dense BF16 matrix-core peak
-# HBM bytes per launch of the sorted sub-label/statistics kernel at this
-# workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a device copy of
-# known size (profiles/traffic_gauss_d32_n1e6.md); None once the kernel changes
-MEASURED_TRAFFIC = {"k_sub_stats_w<32,true>": 162.5e6, "k_label_gauss_mfma32<false,false>": 133.3e6}
+PEAK_FP32_MFMA = 157.3e12  # dense FP32 matrix-core peak
+PEAK_FP64_MFMA = 78.6e12   # dense FP64 matrix-core peak
+# HBM bytes per step of the cluster-draw kernel and of the sub-label +
+# statistics kernels at this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# scaled by a device copy of known size (profiles/traffic_gauss_d32_n1e6.md);
+# None once a kernel changes
+MEASURED_TRAFFIC = {"k_label_gauss_mfma32<false,false>": 133.3e6,
+                    "k_sub_labels_mfma<32>+k_sub_stats_w<32,false>": 304.8e6}
 
 
 def flops_per_eval(d):
@@ -357,20 +361,29 @@ def main():
                       "kernel": f"k_label_gauss_mfma32<{'true' if args.precision == 'bf16x3' else 'false'}> "
                                 "(BF16 matrix-core cluster draw)"}
     label_roof["algorithmic_flops_per_eval"] = flops_per_eval(d)
-    # sub-label draw + statistics over the cluster-sorted order: two FP32
-    # sub-cluster scores (VALU) and the FP64 moments (sum x, upper triangle of
-    # x x^T; FP64 matrix cores).  Both units peak at 78.6 TFLOP/s on this chip,
-    # so their summed flops over that peak bound the kernel from below.
-    stats_flops = 2 * flops_per_eval(d) + d + d * (d + 1)
-    stats_roof = {"bound": "alu", "achieved": n * stats_flops / stats_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                  "unit": "TFLOP/s", "frac": n * stats_flops / stats_s / PEAK_FP32_VALU,
-                  "kernel": "k_sub_stats_w<32,true> (sub-label draw and FP64 statistics, sorted order)",
+    # sub-label draw + statistics over the cluster-sorted order, a phase of
+    # three kernels: the two FP32 sub-cluster scores on the FP32 matrix cores
+    # (k_sub_labels_mfma), then the FP64 moments (sum x, upper triangle of
+    # x x^T) on the FP64 matrix cores (k_sub_stats_w, k_sub_stats_fix).  The
+    # kernels run one after the other, so the phase takes at least the sum of
+    # the two parts' times at their units' peaks; "peak" is the phase's flops
+    # over that time.
+    score_flops, moment_flops = 2 * flops_per_eval(d), d + d * (d + 1)
+    stats_flops = score_flops + moment_flops
+    t_min = n * (score_flops / PEAK_FP32_MFMA + moment_flops / PEAK_FP64_MFMA)
+    stats_roof = {"bound": "mfma", "achieved": n * stats_flops / stats_s / 1e12,
+                  "peak": n * stats_flops / t_min / 1e12, "unit": "TFLOP/s", "frac": t_min / stats_s,
+                  "kernel": "sub-label + statistics phase: k_sub_labels_mfma<32>, k_sub_stats_w<32,false>, "
+                            "k_sub_stats_fix",
                   "algorithmic_flops_per_point": stats_flops,
-                  "hbm_bytes_per_point": 4 * d + 4 + 4 + 1}
-    stats_roof["traffic"] = MEASURED_TRAFFIC.get("k_sub_stats_w<32,true>")
+                  "hbm_bytes_per_point": 2 * (4 * d + 4 + 4 + 1)}
+    stats_roof["traffic"] = MEASURED_TRAFFIC.get("k_sub_labels_mfma<32>+k_sub_stats_w<32,false>")
     label_roof["traffic"] = (MEASURED_TRAFFIC.get("k_label_gauss_mfma32<false,false>")
                              if args.precision == "bf16" else None)
-    roof, other = (stats_roof, label_roof) if stats_s > label_s else (label_roof, stats_roof)
+    # the dominant single kernel is the cluster draw (the statistics phase is
+    # split over three kernels, the largest of them shorter than the draw); its
+    # phase time, used here, also holds the empty candidate pass and re-score
+    roof, other = label_roof, stats_roof
     out = {
         "metric": "point-cluster evals/s in label step; iters/s; time-to-plateau learned vs plain",
         "value": r["value"],

@@ -354,184 +354,15 @@ struct TriTiles {
   static constexpr int NT = off(MT);
 };
 
-// d = 128: the whitener fragments of a cluster (only the tiles on or
-// below the diagonal), its mean and its constant are copied from global memory
-// straight into LDS (global_load_lds, no registers), into one of two
-// statically allocated buffers, while the workgroup's four waves score their
-// points against the previous cluster from the other: one barrier per cluster.
-// The matrix cores execute 1.25 d^2 instead of 2 d^2 flops per point-cluster
-// at d = 128.  Points whose top-2 gap leaves any doubt are not drawn here:
-// they are appended to `flagged` (z = -1, not in the histogram) for the
-// candidate pass and k_rescore_flagged.
-template <int D, bool X3, bool CANDS>
-__global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma_dma(const float* __restrict__ x, long long n,
-                                                                long long per_block, const float* __restrict__ packed,
-                                                                const bf16x8* __restrict__ whi,
-                                                                const bf16x8* __restrict__ wlo, int K, uint32_t t,
-                                                                uint64_t seed, int* __restrict__ z, int* __restrict__ hist,
-                                                                int* __restrict__ tot, int* __restrict__ flagged,
-                                                                int* __restrict__ cand, int* __restrict__ n_flagged) {
-  using TT = TriTiles<D>;
-  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
-  constexpr int MT = TT::MT, KS = TT::KS, NF = MT * KS * 64;  // fragments per cluster in global memory
-  constexpr int NFZ = TT::NT * 64;  // fragments per cluster staged: the non-zero tiles (20 of 32 at d = 128)
-  constexpr int NJ = (NFZ + BLOCK - 1) / BLOCK;
-  constexpr float REL = X3 ? BF16X3_TOL_REL : BF16_TOL_REL;
-  constexpr int NB = X3 ? 2 : 1;  // fragment tables per cluster (hi, lo)
-  constexpr int MUS = D + 4;      // mu[D], c
-  static_assert(D < BLOCK, "staging layout");
-  // two staging buffers as distinct objects, so that the reads of one need no
-  // wait for the copies in flight into the other
-  __shared__ __align__(16) bf16x8 s_w0[NB * NFZ], s_w1[NB * NFZ];
-  __shared__ __align__(16) float s_mu0[MUS], s_mu1[MUS];
-  extern __shared__ int h[];  // K counters
-  for (int k = threadIdx.x; k < K; k += BLOCK) h[k] = 0;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int half = lane >> 5, col = lane & 31;
-  const int wbase = threadIdx.x & ~63;
-  // main pass: the workgroup's points; candidate pass: the deferred slots, grid-strided
-  const long long nf = CANDS ? (long long)*n_flagged : 0;
-  const long long begin = CANDS ? (long long)blockIdx.x * BLOCK : (long long)blockIdx.x * per_block;
-  const long long end = CANDS ? nf : (begin + per_block < n ? begin + per_block : n);
-  const long long step = CANDS ? (long long)gridDim.x * BLOCK : BLOCK;
-  // copies of cluster k into (dw, dmu): fragment f of the staged table is tile f / 64 in
-  // (row block, ks) order, lane f % 64; each wave fills 64 consecutive entries
-  auto stage = [&](bf16x8* dw, float* dmu, int k) {
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int f = j * BLOCK + threadIdx.x;
-      if (f < NFZ) {
-        const int tt = f >> 6;
-        int mt = 0, o = 0;
-#pragma unroll
-        for (int m = 1; m < MT; ++m)
-          if (tt >= TT::off(m)) mt = m, o = TT::off(m);
-        const size_t g = (size_t)k * NF + (size_t)(mt * KS + tt - o) * 64 + (f & 63);
-        __builtin_amdgcn_global_load_lds((const void*)(whi + g), (lds_void*)(dw + j * BLOCK + wbase), 16, 0, 0);
-        if (X3)
-          __builtin_amdgcn_global_load_lds((const void*)(wlo + g), (lds_void*)(dw + NFZ + j * BLOCK + wbase), 16, 0,
-                                           0);
-      }
-    }
-    if (threadIdx.x <= D) {
-      const float* rec = packed + (size_t)k * S;
-      __builtin_amdgcn_global_load_lds((const void*)(threadIdx.x < D ? rec + 4 + threadIdx.x : rec),
-                                       (lds_void*)(dmu + wbase), 4, 0, 0);
-    }
-  };
-  const bool any = begin < end;
-  if (any) stage(s_w0, s_mu0, 0);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  int buf = 0;
-  // every wave runs the same number of chunks and clusters: one barrier per cluster
-  for (long long chunk = begin; chunk < end; chunk += step) {
-    const long long base = chunk + wave * 64;
-    const long long rA = base + col, rB = base + 32 + col;
-    const long long pA = rA < end ? (CANDS ? (long long)flagged[rA] : rA) : 0;
-    const long long pB = rB < end ? (CANDS ? (long long)flagged[rB] : rB) : 0;
-    float xa[KS][8], xb[KS][8];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int j = 16 * ks + 8 * half + q;
-        xa[ks][q] = rA < end ? x[pA * D + j] : 0.0f;
-        xb[ks][q] = rB < end ? x[pB * D + j] : 0.0f;
-      }
-    const bool more = chunk + step < end;
-    Top2U t2;
-    Cands cd;
-    if (CANDS)
-      cd.init();
-    else
-      t2.init();
-    // score cluster k from (cw, cmu) while cluster kn is copied into (nw, nmu)
-    auto cluster = [&](const bf16x8* cw, const float* cmu, bf16x8* nw, float* nmu, int k, bool next, int kn) {
-      if (next) stage(nw, nmu, kn);
-      const bf16x8* cwl = cw + (NB - 1) * NFZ;
-      bf16x8 ba[KS], bb[KS], bal[KS], bbl[KS];
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const float mu = cmu[16 * ks + 8 * half + q];
-          const float da = xa[ks][q] - mu, db = xb[ks][q] - mu;
-          ba[ks][q] = (__bf16)da;
-          bb[ks][q] = (__bf16)db;
-          if (X3) {
-            bal[ks][q] = (__bf16)(da - (float)ba[ks][q]);
-            bbl[ks][q] = (__bf16)(db - (float)bb[ks][q]);
-          }
-        }
-      float qa = 0.0f, qb = 0.0f;
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        f32x16 acca = {0}, accb = {0};
-#pragma unroll
-        for (int ks = 0; ks < TT::tiles(mt); ++ks) {
-          const int tile = TT::off(mt) + ks;
-          const bf16x8 a = cw[tile * 64 + lane];
-          acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, ba[ks], acca, 0, 0, 0);
-          accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb[ks], accb, 0, 0, 0);
-          if (X3) {
-            const bf16x8 al = cwl[tile * 64 + lane];
-            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, ba[ks], acca, 0, 0, 0);
-            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bb[ks], accb, 0, 0, 0);
-            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bal[ks], acca, 0, 0, 0);
-            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbl[ks], accb, 0, 0, 0);
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          qa = fmaf(acca[r], acca[r], qa);
-          qb = fmaf(accb[r], accb[r], qb);
-        }
-      }
-      qa += __shfl_xor(qa, 32);
-      qb += __shfl_xor(qb, 32);
-      const float qm = half ? qb : qa;
-      const float l = fmaf(-0.5f, qm, cmu[D]);
-      if (CANDS)
-        cd.push(l, qm, REL, k);
-      else
-        t2.push(l, qm, REL, k);
-      // this wave's copies into the other buffer have landed; after the barrier all have
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-    };
-    for (int k = 0; k < K; ++k) {
-      // the next cluster (or the next chunk's first) is copied while this one computes
-      const bool next = k + 1 < K || more;
-      const int kn = k + 1 < K ? k + 1 : 0;
-      if (buf == 0)
-        cluster(s_w0, s_mu0, s_w1, s_mu1, k, next, kn);
-      else
-        cluster(s_w1, s_mu1, s_w0, s_mu0, k, next, kn);
-      buf ^= 1;
-    }
-    const long long r = base + lane;
-    if (CANDS)
-      finish_cands(r < end, r, r < end ? (long long)flagged[r] : 0, cd, REL, K, per_block, t, seed, z, hist, tot,
-                   cand);
-    else
-      finish_main(r < end, r, t2, z, h, flagged, n_flagged, lane);
-  }
-  if (CANDS) return;
-  __syncthreads();
-  for (int k = threadIdx.x; k < K; k += BLOCK) {
-    hist[(size_t)blockIdx.x * K + k] = h[k];
-    if (h[k]) atomicAdd(&tot[k], h[k]);
-  }
-}
-
 constexpr int BLOCK_W32 = 512;  // threads of k_label_gauss_mfma_w32: 8 waves of 32 points
-constexpr bool W32_AT_64 = true;
 
-// d = 64, 128 with half the registers per wave: the staging is that of
-// k_label_gauss_mfma_dma (a cluster's non-zero whitener tiles, mean and
-// constant copied straight into one of two static LDS buffers while the
-// previous cluster is scored from the other, one barrier per cluster), but a
+// d = 64, 128: a cluster's non-zero whitener tiles (only those on or below
+// the diagonal), its mean and its constant are copied from global memory
+// straight into LDS (global_load_lds, no registers) into one of two
+// statically allocated buffers, while the workgroup scores its points against
+// the previous clusters from the other (two clusters per buffer and barrier in
+// BF16, one in bf16x3, whose tables are twice as large); the matrix cores
+// execute 1.25 d^2 instead of 2 d^2 flops per point-cluster at d = 128.  A
 // wave scores a single 32-point tile: lanes l and l + 32 hold the two halves
 // of the K slice of point l % 32, so a lane keeps d / 2 FP32 coordinates and
 // one 16-register accumulator.  Two waves then share a SIMD and one wave's
@@ -558,9 +389,10 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
   constexpr int NB = X3 ? 2 : 1;  // fragment tables per cluster (hi, lo)
   constexpr int MUS = D + 4;      // mu[D], c
   constexpr int CHUNK = BLOCK_W32 / 2;
+  constexpr int CPB = X3 ? 1 : 2;  // clusters per staging buffer (per barrier)
   static_assert(D < BLOCK_W32 && CHUNK == BLOCK && NFZ % 64 == 0, "staging layout, histogram blocks");
-  __shared__ __align__(16) bf16x8 s_w0[NB * NFZ], s_w1[NB * NFZ];
-  __shared__ __align__(16) float s_mu0[MUS], s_mu1[MUS];
+  __shared__ __align__(16) bf16x8 s_w0[CPB * NB * NFZ], s_w1[CPB * NB * NFZ];
+  __shared__ __align__(16) float s_mu0[CPB * MUS], s_mu1[CPB * MUS];
   extern __shared__ int h[];  // K counters
   for (int k = threadIdx.x; k < K; k += BLOCK_W32) h[k] = 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -571,36 +403,44 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
   const long long begin = CANDS ? (long long)blockIdx.x * CHUNK : (long long)blockIdx.x * per_block;
   const long long end = CANDS ? nf : (begin + per_block < n ? begin + per_block : n);
   const long long step = CANDS ? (long long)gridDim.x * CHUNK : CHUNK;
-  // copies of cluster k into (dw, dmu): fragment f of the staged table is tile f / 64 in
-  // (row block, ks) order, lane f % 64; each wave fills 64 consecutive entries
-  auto stage = [&](bf16x8* dw, float* dmu, int k) {
+  // copies of clusters k0 ... k0 + nk - 1 into slots 0 ... nk - 1 of (dw, dmu): fragment
+  // f of a slot's table is tile f / 64 in (row block, ks) order, lane f % 64; each wave
+  // fills 64 consecutive entries
+  auto stage = [&](bf16x8* dws, float* dmus, int k0, int nk) {
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int f = j * BLOCK_W32 + threadIdx.x;
-      if (f < NFZ) {
-        const int tt = f >> 6;
-        int mt = 0, o = 0;
+    for (int c = 0; c < CPB; ++c) {
+      if (c >= nk) break;
+      const int k = k0 + c;
+      bf16x8* dw = dws + c * NB * NFZ;
+      float* dmu = dmus + c * MUS;
 #pragma unroll
-        for (int m = 1; m < MT; ++m)
-          if (tt >= TT::off(m)) mt = m, o = TT::off(m);
-        const size_t g = (size_t)k * NF + (size_t)(mt * KS + tt - o) * 64 + (f & 63);
-        __builtin_amdgcn_global_load_lds((const void*)(whi + g), (lds_void*)(dw + j * BLOCK_W32 + wbase), 16, 0, 0);
-        if (X3)
-          __builtin_amdgcn_global_load_lds((const void*)(wlo + g), (lds_void*)(dw + NFZ + j * BLOCK_W32 + wbase), 16,
-                                           0, 0);
+      for (int j = 0; j < NJ; ++j) {
+        const int f = j * BLOCK_W32 + threadIdx.x;
+        if (f < NFZ) {
+          const int tt = f >> 6;
+          int mt = 0, o = 0;
+#pragma unroll
+          for (int m = 1; m < MT; ++m)
+            if (tt >= TT::off(m)) mt = m, o = TT::off(m);
+          const size_t g = (size_t)k * NF + (size_t)(mt * KS + tt - o) * 64 + (f & 63);
+          __builtin_amdgcn_global_load_lds((const void*)(whi + g), (lds_void*)(dw + j * BLOCK_W32 + wbase), 16, 0, 0);
+          if (X3)
+            __builtin_amdgcn_global_load_lds((const void*)(wlo + g), (lds_void*)(dw + NFZ + j * BLOCK_W32 + wbase), 16,
+                                             0, 0);
+        }
+      }
+      if (threadIdx.x <= D) {
+        const float* rec = packed + (size_t)k * S;
+        __builtin_amdgcn_global_load_lds((const void*)(threadIdx.x < D ? rec + 4 + threadIdx.x : rec),
+                                         (lds_void*)(dmu + wbase), 4, 0, 0);
       }
     }
-    if (threadIdx.x <= D) {
-      const float* rec = packed + (size_t)k * S;
-      __builtin_amdgcn_global_load_lds((const void*)(threadIdx.x < D ? rec + 4 + threadIdx.x : rec),
-                                       (lds_void*)(dmu + wbase), 4, 0, 0);
-    }
   };
-  if (begin < end) stage(s_w0, s_mu0, 0);
+  if (begin < end) stage(s_w0, s_mu0, 0, K < CPB ? K : CPB);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int buf = 0;
-  // every wave runs the same number of chunks and clusters: one barrier per cluster
+  // every wave runs the same number of chunks and clusters: one barrier per CPB clusters
   for (long long chunk = begin; chunk < end; chunk += step) {
     const long long r = chunk + wave * 32 + col;
     const bool ok = r < end;
@@ -628,9 +468,9 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
       cd.init();
     else
       t2.init();
-    // score cluster k from (cw, cmu) while cluster kn is copied into (nw, nmu)
-    auto cluster = [&](const bf16x8* cw, const float* cmu, bf16x8* nw, float* nmu, int k, bool next, int kn) {
-      if (next) stage(nw, nmu, kn);
+    // score cluster k from (cw, cmu)
+    auto score = [&](const bf16x8* cw, const float* cmu, int k) __attribute__((always_inline)) {
+      float q0 = 0.0f, q1 = 0.0f;
       const bf16x8* cwl = cw + (NB - 1) * NFZ;
       bf16x8 b[KS], bl[KS];
 #pragma unroll
@@ -641,7 +481,6 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
           b[ks][q] = (__bf16)dv;
           if (X3) bl[ks][q] = (__bf16)(dv - (float)b[ks][q]);
         }
-      float q0 = 0.0f, q1 = 0.0f;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         f32x16 acc = {0};
@@ -670,17 +509,29 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
         cd.push(l, qm, REL, k);
       else
         t2.push(l, qm, REL, k);
+    };
+    // score clusters k0 ... k0 + nk - 1 from (cw, cmu) while the next group (kn, nkn)
+    // is copied into (nw, nmu)
+    auto group = [&](const bf16x8* cw, const float* cmu, bf16x8* nw, float* nmu, int k0, int nk, bool next, int kn,
+                     int nkn) __attribute__((always_inline)) {
+      if (next) stage(nw, nmu, kn, nkn);
+#pragma unroll
+      for (int c = 0; c < CPB; ++c)
+        if (c < nk) score(cw + c * NB * NFZ, cmu + c * MUS, k0 + c);
       // this wave's copies into the other buffer have landed; after the barrier all have
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     };
-    for (int k = 0; k < K; ++k) {
-      const bool next = k + 1 < K || more;
-      const int kn = k + 1 < K ? k + 1 : 0;
+    for (int k = 0; k < K; k += CPB) {
+      const int nk = K - k < CPB ? K - k : CPB;
+      const bool last = k + CPB >= K;
+      const bool next = !last || more;
+      const int kn = last ? 0 : k + CPB;
+      const int nkn = last ? (K < CPB ? K : CPB) : (K - kn < CPB ? K - kn : CPB);
       if (buf == 0)
-        cluster(s_w0, s_mu0, s_w1, s_mu1, k, next, kn);
+        group(s_w0, s_mu0, s_w1, s_mu1, k, nk, next, kn, nkn);
       else
-        cluster(s_w1, s_mu1, s_w0, s_mu0, k, next, kn);
+        group(s_w1, s_mu1, s_w0, s_mu0, k, nk, next, kn, nkn);
       buf ^= 1;
     }
     // lanes 0-31 own the points (lanes 32-63 hold the same state)
@@ -692,163 +543,6 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
   if (CANDS) return;
   __syncthreads();
   for (int k = threadIdx.x; k < K; k += BLOCK_W32) {
-    hist[(size_t)blockIdx.x * K + k] = h[k];
-    if (h[k]) atomicAdd(&tot[k], h[k]);
-  }
-}
-
-// d = 64: the cluster's whitener fragments (and mu, c) are staged in LDS once
-// per workgroup and shared by its four waves, double-buffered: cluster k + 1 is
-// fetched into registers while cluster k computes (at d = 64 the prefetch fits
-// in three waves per SIMD; copies straight into LDS cost registers here); MFMA
-// tiles entirely above the diagonal of W (16 ks > 32 mt + 31) are skipped.  Points whose top-2 gap
-// leaves any doubt are not drawn here: they are appended to `flagged` (z = -1,
-// not in the histogram) and drawn by k_rescore_flagged in FP32.
-template <int D, bool X3, bool CANDS>
-__global__ __launch_bounds__(BLOCK) void k_label_gauss_mfma_lds(const float* __restrict__ x, long long n,
-                                                                long long per_block, const float* __restrict__ packed,
-                                                                const bf16x8* __restrict__ whi,
-                                                                const bf16x8* __restrict__ wlo, int K, uint32_t t,
-                                                                uint64_t seed, int* __restrict__ z, int* __restrict__ hist,
-                                                                int* __restrict__ tot, int* __restrict__ flagged,
-                                                                int* __restrict__ cand, int* __restrict__ n_flagged) {
-  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
-  constexpr int MT = D / 32, KS = D / 16, NF = MT * KS * 64;
-  constexpr float REL = X3 ? BF16X3_TOL_REL : BF16_TOL_REL;
-  constexpr int PF = NF / BLOCK;  // fragments each thread stages per cluster
-  constexpr int NB = X3 ? 2 : 1;  // fragment tables per cluster (hi, lo)
-  constexpr int MUS = D + 4;      // mu[D], c
-  static_assert(NF % BLOCK == 0 && D < BLOCK, "staging layout");
-  // two staging buffers: [buf][NB][NF] fragments, then [buf][MUS] floats, then the histogram
-  extern __shared__ __align__(16) unsigned char smem[];
-  bf16x8* s_w = reinterpret_cast<bf16x8*>(smem);
-  float* s_mu = reinterpret_cast<float*>(s_w + 2 * NB * NF);
-  int* h = reinterpret_cast<int*>(s_mu + 2 * MUS);
-  for (int k = threadIdx.x; k < K; k += BLOCK) h[k] = 0;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int half = lane >> 5, col = lane & 31;
-  // main pass: the workgroup's points; candidate pass: the deferred slots, grid-strided
-  const long long nf = CANDS ? (long long)*n_flagged : 0;
-  const long long begin = CANDS ? (long long)blockIdx.x * BLOCK : (long long)blockIdx.x * per_block;
-  const long long end = CANDS ? nf : (begin + per_block < n ? begin + per_block : n);
-  const long long step = CANDS ? (long long)gridDim.x * BLOCK : BLOCK;
-  // staging of cluster k into buffer b: global -> registers (pf*), registers -> LDS
-  bf16x8 pf[NB][PF];
-  float pfmu = 0.0f;
-  auto fetch = [&](int k) {
-#pragma unroll
-    for (int j = 0; j < PF; ++j) {
-      pf[0][j] = whi[(size_t)k * NF + threadIdx.x + j * BLOCK];
-      if (X3) pf[NB - 1][j] = wlo[(size_t)k * NF + threadIdx.x + j * BLOCK];
-    }
-    const float* rec = packed + (size_t)k * S;
-    pfmu = threadIdx.x < D ? rec[4 + threadIdx.x] : (threadIdx.x == D ? rec[0] : 0.0f);
-  };
-  auto store = [&](int b) {
-#pragma unroll
-    for (int j = 0; j < PF; ++j) {
-      s_w[(b * NB) * NF + threadIdx.x + j * BLOCK] = pf[0][j];
-      if (X3) s_w[(b * NB + NB - 1) * NF + threadIdx.x + j * BLOCK] = pf[NB - 1][j];
-    }
-    if (threadIdx.x <= D) s_mu[b * MUS + threadIdx.x] = pfmu;
-  };
-  const bool any = begin < end;
-  if (any) {
-    fetch(0);
-    store(0);
-  }
-  __syncthreads();
-  int buf = 0;
-  // every wave runs the same number of chunks and clusters: one barrier per cluster
-  for (long long chunk = begin; chunk < end; chunk += step) {
-    const long long base = chunk + wave * 64;
-    const long long rA = base + col, rB = base + 32 + col;
-    const long long pA = rA < end ? (CANDS ? (long long)flagged[rA] : rA) : 0;
-    const long long pB = rB < end ? (CANDS ? (long long)flagged[rB] : rB) : 0;
-    float xa[KS][8], xb[KS][8];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int j = 16 * ks + 8 * half + q;
-        xa[ks][q] = rA < end ? x[pA * D + j] : 0.0f;
-        xb[ks][q] = rB < end ? x[pB * D + j] : 0.0f;
-      }
-    const bool more = chunk + step < end;
-    Top2U t2;
-    Cands cd;
-    if (CANDS)
-      cd.init();
-    else
-      t2.init();
-    for (int k = 0; k < K; ++k) {
-      // the next cluster (or the next chunk's first) is fetched while this one computes
-      const bool next = k + 1 < K || more;
-      if (next) fetch(k + 1 < K ? k + 1 : 0);
-      const bf16x8* cw = s_w + (buf * NB) * NF;
-      const bf16x8* cwl = s_w + (buf * NB + NB - 1) * NF;
-      const float* cmu = s_mu + buf * MUS;
-      bf16x8 ba[KS], bb[KS], bal[KS], bbl[KS];
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const float mu = cmu[16 * ks + 8 * half + q];
-          const float da = xa[ks][q] - mu, db = xb[ks][q] - mu;
-          ba[ks][q] = (__bf16)da;
-          bb[ks][q] = (__bf16)db;
-          if (X3) {
-            bal[ks][q] = (__bf16)(da - (float)ba[ks][q]);
-            bbl[ks][q] = (__bf16)(db - (float)bb[ks][q]);
-          }
-        }
-      float qa = 0.0f, qb = 0.0f;
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        f32x16 acca = {0}, accb = {0};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          if (16 * ks > 32 * mt + 31) continue;  // W is lower triangular: an all-zero tile
-          const bf16x8 a = cw[(mt * KS + ks) * 64 + lane];
-          acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, ba[ks], acca, 0, 0, 0);
-          accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb[ks], accb, 0, 0, 0);
-          if (X3) {
-            const bf16x8 al = cwl[(mt * KS + ks) * 64 + lane];
-            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, ba[ks], acca, 0, 0, 0);
-            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bb[ks], accb, 0, 0, 0);
-            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bal[ks], acca, 0, 0, 0);
-            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbl[ks], accb, 0, 0, 0);
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          qa = fmaf(acca[r], acca[r], qa);
-          qb = fmaf(accb[r], accb[r], qb);
-        }
-      }
-      qa += __shfl_xor(qa, 32);
-      qb += __shfl_xor(qb, 32);
-      const float qm = half ? qb : qa;
-      const float l = fmaf(-0.5f, qm, cmu[D]);
-      if (CANDS)
-        cd.push(l, qm, REL, k);
-      else
-        t2.push(l, qm, REL, k);
-      // the other buffer was last read before the previous barrier
-      if (next) store(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
-    }
-    const long long r = base + lane;
-    if (CANDS)
-      finish_cands(r < end, r, r < end ? (long long)flagged[r] : 0, cd, REL, K, per_block, t, seed, z, hist, tot,
-                   cand);
-    else
-      finish_main(r < end, r, t2, z, h, flagged, n_flagged, lane);
-  }
-  if (CANDS) return;
-  __syncthreads();
-  for (int k = threadIdx.x; k < K; k += BLOCK) {
     hist[(size_t)blockIdx.x * K + k] = h[k];
     if (h[k]) atomicAdd(&tot[k], h[k]);
   }
@@ -1027,40 +721,26 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
     const bool cands = pass == 1;
     const int Gp = cands ? (d == 32 ? (G < 256 ? G : 256) : (G < 512 ? G : 512)) : G;
     if (d == 64 || d == 128) {
-      // d = 128: static staging buffers, only the histogram is dynamic; d = 64: two staging
-      // buffers of [NB][NF] fragments and [d + 4] floats, then the histogram
-#define DPMM_MFMA_LDS(KER, DD, XX, CC, L)                                                                 \
-  hipLaunchKernelGGL((KER<DD, XX, CC>), dim3(Gp), dim3(BLOCK), L, s, x, n, per_block, packed, hi, lo, K, t, seed, \
-                     z, hist, tot, flagged, cand, n_flagged)
+      // static staging buffers; only the histogram is dynamic
 #define DPMM_MFMA_W32(DD, XX, CC)                                                                             \
   hipLaunchKernelGGL((k_label_gauss_mfma_w32<DD, XX, CC>), dim3(Gp), dim3(BLOCK_W32), lh, s, x, n, per_block, packed, \
                      hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
+      // the candidate pass scores in bf16x3 whatever the main pass's form
       if (d == 128) {
-        // the candidate pass scores in bf16x3 whatever the main pass's form
         if (cands)
           DPMM_MFMA_W32(128, true, true);
         else if (x3)
           DPMM_MFMA_W32(128, true, false);
         else
           DPMM_MFMA_W32(128, false, false);
-      } else if (W32_AT_64) {
+      } else {
         if (cands)
           DPMM_MFMA_W32(64, true, true);
         else if (x3)
           DPMM_MFMA_W32(64, true, false);
         else
           DPMM_MFMA_W32(64, false, false);
-      } else {
-        const int NF = (d / 32) * (d / 16) * 64;
-        const size_t lds = 2 * ((size_t)(x3 || cands ? 2 : 1) * NF * sizeof(bf16x8) + (d + 4) * sizeof(float)) + lh;
-        if (cands)
-          DPMM_MFMA_LDS(k_label_gauss_mfma_lds, 64, true, true, lds);
-        else if (x3)
-          DPMM_MFMA_LDS(k_label_gauss_mfma_lds, 64, true, false, lds);
-        else
-          DPMM_MFMA_LDS(k_label_gauss_mfma_lds, 64, false, false, lds);
       }
-#undef DPMM_MFMA_LDS
 #undef DPMM_MFMA_W32
     } else if (d == 32) {
       // [CG][NB][NF] fragments (64 KB), [CG][d + 4] means and constants, the histogram;

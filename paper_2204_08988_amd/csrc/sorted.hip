@@ -668,7 +668,7 @@ __device__ __forceinline__ int block_inclusive_scan_big(int v, int* buf) {
   return r;
 }
 
-// Sub-label draw of sorted rows on the FP32 matrix cores (d = 128), Sec. 4.1
+// Sub-label draw of sorted rows on the FP32 matrix cores (d = 32, 64, 128), Sec. 4.1
 // step (f): the scores of the two sub-clusters of the row's cluster, from
 // Y = W_h (x - mu_h) with v_mfma_f32_32x32x2_f32 (A = W_h, B = the centred
 // rows).  A workgroup walks a contiguous range of sorted rows; the two records
@@ -682,13 +682,13 @@ __device__ __forceinline__ int block_inclusive_scan_big(int v, int* buf) {
 constexpr int SUBL_BLOCK = 256;
 
 template <int D>
-__global__ __launch_bounds__(SUBL_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sub_labels_mfma(
+__global__ __launch_bounds__(SUBL_BLOCK) __attribute__((amdgpu_waves_per_eu(2, D <= 32 ? 3 : 2))) void k_sub_labels_mfma(
     const float* __restrict__ x, long long n_sorted, long long per_block, const int* __restrict__ perm,
     const int* __restrict__ z, const int* __restrict__ zrow, unsigned char* __restrict__ zsub,
     const float* __restrict__ packed, int k_max, uint32_t t, uint64_t seed) {
   constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
   constexpr int MT = D / 32, HALF = D / 2, QTR = D / 4;
-  static_assert(D % 64 == 0 && D <= SUBL_BLOCK, "layout");
+  static_assert(D % 32 == 0 && D <= SUBL_BLOCK, "layout");
   typedef float f32x16 __attribute__((ext_vector_type(16)));
   extern __shared__ __align__(16) float s_rec[];  // records of sub-clusters 0 and 1, then W_1 (mu_0 - mu_1), mu_0 - mu_1
   float* s_corr = s_rec + 2 * S;
@@ -1115,11 +1115,11 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
                              const int* ctot, double* part, hipStream_t s) {
   hipError_t e;
   if (n == 0) return hipSuccess;
-  if (d == 64 || d == 128) {
-    // the sub-labels first (their own pass), then the statistics
-    if (sample) {
-      // the sub-labels in their own pass on the FP32 matrix cores; at d = 128 two workgroups
-      // per CU (the staged records take 66 KB), each on a contiguous range of rows
+  if (sample && (d == 32 || d == 64 || d == 128)) {
+    // the sub-labels in their own pass on the FP32 matrix cores, then the statistics; at
+    // d = 128 two workgroups per CU (the staged records take 66 KB), each on a contiguous
+    // range of rows
+    {
       static bool lattr = false;
       const size_t llds = sub_labels_mfma_lds(d);
       if (!lattr) {
@@ -1129,18 +1129,25 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
         lattr = true;
       }
       const long long chunks = (n + SUBL_BLOCK - 1) / SUBL_BLOCK;
-      const long long cap = d == 128 ? 512 : 1024;
+      // d = 32: three waves per SIMD, all workgroups resident at once
+      const long long cap = d == 128 ? 512 : (d == 64 ? 1024 : 768);
       const long long gl = chunks < cap ? chunks : cap;
       const long long lper = ((chunks + gl - 1) / gl) * SUBL_BLOCK;
       const unsigned lg = (unsigned)((n + lper - 1) / lper);
       if (d == 128)
         hipLaunchKernelGGL(k_sub_labels_mfma<128>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, perm, z, zrow,
                            zsub, packed, k_max, t, seed);
-      else
+      else if (d == 64)
         hipLaunchKernelGGL(k_sub_labels_mfma<64>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, perm, z, zrow,
+                           zsub, packed, k_max, t, seed);
+      else
+        hipLaunchKernelGGL(k_sub_labels_mfma<32>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, perm, z, zrow,
                            zsub, packed, k_max, t, seed);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    sample = false;
+  }
+  if (d == 64 || d == 128) {
     const long long tiles = (n + BIG_ROWS - 1) / BIG_ROWS;
     const long long gmax = d == 128 ? 256 : 512;
     const long long g = tiles < gmax ? tiles : gmax;
