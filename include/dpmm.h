@@ -121,6 +121,11 @@ typedef struct {
   int32_t learned_kind;     /* learned move of dpmm_step: 0 none, 1 split, 2 merge */
   int32_t learned_accepted; /* 1 if it was accepted */
   float ms_learned;         /* its device-side time span, milliseconds */
+  float ms_label_kernel;    /* the main cluster-draw kernel alone (Gaussian
+                               matrix-core path: start and end events taken by
+                               its own dispatch, without the candidate pass and
+                               the FP32 re-score of deferred points); ms_labels
+                               on the other paths */
 } dpmm_iter_info;
 
 /* What one learned move did (dpmm_learned_move). */

@@ -46,6 +46,7 @@ class IterInfo(ctypes.Structure):
         ("ms_labels", ctypes.c_float), ("ms_sort", ctypes.c_float), ("ms_stats", ctypes.c_float),
         ("ms_splitmerge", ctypes.c_float), ("learned_kind", ctypes.c_int32),
         ("learned_accepted", ctypes.c_int32), ("ms_learned", ctypes.c_float),
+        ("ms_label_kernel", ctypes.c_float),
     ]
 
     def as_dict(self):

@@ -399,7 +399,7 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_flag, sizeof(int), hipHostMallocDefault);
   if (e == hipSuccess && ensure_items(c, (size_t)std::max(3 * km, 256)) != DPMM_OK) e = hipErrorOutOfMemory;
   if (e == hipSuccess) e = hipMemset(c->d_packed, 0, 3 * (size_t)km * c->stride * sizeof(float));
-  for (int i = 0; i < 7 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev[i]);
+  for (int i = 0; i < 9 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev[i]);
   if (e != hipSuccess) {
     g_create_error = std::string("device setup failed: ") + hipGetErrorString(e);
     dpmm_destroy(ctx.release());
@@ -646,8 +646,10 @@ dpmm_status label_phase(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int
       DPMM_HIP(ctx, launch_label_gauss_mfma(ctx->d, ctx->cfg.precision == DPMM_BF16X3, (const float*)x, n, *G, *per,
                                             ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->K, t, ctx->cfg.seed, z,
                                             ctx->d_hist, ctx->d_tot, ctx->d_perm, ctx->d_cand, ctx->d_nflag,
-                                            ctx->stream),
+                                            ctx->stream, ctx->label_timing ? ctx->ev[7] : nullptr,
+                                            ctx->label_timing ? ctx->ev[8] : nullptr),
                "matrix-core label kernel");
+      ctx->label_kernel_timed = ctx->label_timing && n > 0;
       return DPMM_OK;
     }
     DPMM_HIP(ctx, launch_label_gauss_z(ctx->d, (const float*)x, n, *G, *per, ctx->d_packed, ctx->K, t, ctx->cfg.seed, z,
@@ -896,7 +898,11 @@ dpmm_status dpmm_step(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32
   DPMM_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream), "event");
   int G = 0;
   long long per = 0;
-  DPMM_TRY(label_phase(ctx, x, n, t, z, zsub, &G, &per));
+  ctx->label_timing = true;
+  ctx->label_kernel_timed = false;
+  const dpmm_status lp = label_phase(ctx, x, n, t, z, zsub, &G, &per);
+  ctx->label_timing = false;
+  DPMM_TRY(lp);
   DPMM_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream), "event");
   // the sorted path records ev[3] between its sort and its statistics kernel
   ctx->timing = ctx->sorted_path();
@@ -927,6 +933,8 @@ dpmm_status dpmm_step(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int32
     hipEventElapsedTime(&info->ms_sort, ctx->ev[2], ctx->ev[3]);
     hipEventElapsedTime(&info->ms_stats, ctx->ev[3], ctx->ev[4]);
     hipEventElapsedTime(&info->ms_splitmerge, ctx->ev[4], ctx->ev[5]);
+    info->ms_label_kernel = info->ms_labels;
+    if (ctx->label_kernel_timed) hipEventElapsedTime(&info->ms_label_kernel, ctx->ev[7], ctx->ev[8]);
   }
   return DPMM_OK;
 }

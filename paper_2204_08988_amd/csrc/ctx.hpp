@@ -77,8 +77,11 @@ struct dpmm_ctx {
   uint16_t *d_whi = nullptr, *d_wlo = nullptr;
   int* d_nflag = nullptr;  // count of the points deferred to FP32 (matrix-core label kernels)
   int* d_cand = nullptr;   // [perm_cap][RESCORE_CAND] their candidate clusters
-  hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[9] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool timing = false;  // record ev[3] between the sort and the statistics kernel
+  // record ev[7], ev[8] around the main cluster-draw kernel (matrix-core path);
+  // label_kernel_timed tells whether the last label phase did
+  bool label_timing = false, label_kernel_timed = false;
   // learned split proposal (cfg.learned = m > 0 principal axes, F = 2m features)
   int lm = 0, F = 0, Fp = 0, n_mlp = 0;
   float *d_p = nullptr, *d_g = nullptr, *d_am = nullptr, *d_av = nullptr;  // FP32 master weights, gradient, Adam

@@ -119,7 +119,8 @@ hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void*
 hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, int G, long long per_block,
                                    const float* packed, const void* whi, const void* wlo, int K, uint32_t t,
                                    uint64_t seed, int* z, int* hist, int* tot, int* flagged, int* cand,
-                                   int* n_flagged, hipStream_t s);
+                                   int* n_flagged, hipStream_t s, hipEvent_t ev_main0 = nullptr,
+                                   hipEvent_t ev_main1 = nullptr);
 hipError_t launch_loglik_gauss(int d, const float* x, long long n, const float* packed, int K, int k_max,
                                float* out, hipStream_t s);
 hipError_t launch_label_mult(int V, const int* x, long long n, const float* packed, int K, int k_max,

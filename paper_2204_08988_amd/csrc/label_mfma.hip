@@ -17,6 +17,8 @@
 // deferred to k_rescore_flagged, which re-scores it in FP32 on the vector ALUs
 // and draws it exactly as the FP32 kernel draws it; otherwise no other cluster
 // can win and the leader is the label.
+#include <hip/hip_ext.h>
+
 #include <climits>
 
 #include "kernels.hpp"
@@ -696,7 +698,7 @@ hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void*
 hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, int G, long long per_block,
                                    const float* packed, const void* whi, const void* wlo, int K, uint32_t t,
                                    uint64_t seed, int* z, int* hist, int* tot, int* flagged, int* cand,
-                                   int* n_flagged, hipStream_t s) {
+                                   int* n_flagged, hipStream_t s, hipEvent_t ev_main0, hipEvent_t ev_main1) {
   if (n == 0) return hipSuccess;
   hipError_t e = launch_zero64(tot, (size_t)(K + 1) / 2 + 1, s);
   if (e != hipSuccess) return e;
@@ -720,11 +722,14 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
   for (int pass = 0; pass < 2; ++pass) {
     const bool cands = pass == 1;
     const int Gp = cands ? (d == 32 ? (G < 256 ? G : 256) : (G < 512 ? G : 512)) : G;
+    // optional events taken by the main pass's own dispatch (its start and end
+    // time stamps, for timing it alone without extra queue packets)
+    hipEvent_t e0 = cands ? nullptr : ev_main0, e1 = cands ? nullptr : ev_main1;
     if (d == 64 || d == 128) {
       // static staging buffers; only the histogram is dynamic
-#define DPMM_MFMA_W32(DD, XX, CC)                                                                             \
-  hipLaunchKernelGGL((k_label_gauss_mfma_w32<DD, XX, CC>), dim3(Gp), dim3(BLOCK_W32), lh, s, x, n, per_block, packed, \
-                     hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
+#define DPMM_MFMA_W32(DD, XX, CC)                                                                            \
+  hipExtLaunchKernelGGL((k_label_gauss_mfma_w32<DD, XX, CC>), dim3(Gp), dim3(BLOCK_W32), lh, s, e0, e1, 0, x, n, \
+                        per_block, packed, hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
       // the candidate pass scores in bf16x3 whatever the main pass's form
       if (d == 128) {
         if (cands)
@@ -746,9 +751,9 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
       // [CG][NB][NF] fragments (64 KB), [CG][d + 4] means and constants, the histogram;
       // the candidate pass scores in bf16x3
       const size_t lds = (size_t)65536 + (size_t)(x3 || cands ? 16 : 32) * (d + 4) * sizeof(float) + lh;
-#define DPMM_MFMA32(XX, CC)                                                                                 \
-  hipLaunchKernelGGL((k_label_gauss_mfma32<XX, CC>), dim3(Gp), dim3(BLOCK32), lds, s, x, n, per_block, packed, hi, \
-                     lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
+#define DPMM_MFMA32(XX, CC)                                                                                  \
+  hipExtLaunchKernelGGL((k_label_gauss_mfma32<XX, CC>), dim3(Gp), dim3(BLOCK32), lds, s, e0, e1, 0, x, n, per_block, \
+                        packed, hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
       if (cands)
         DPMM_MFMA32(true, true);
       else if (x3)
