@@ -471,7 +471,7 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
     else
       t2.init();
     // score cluster k from (cw, cmu)
-    auto score = [&](const bf16x8* cw, const float* cmu, int k) __attribute__((always_inline)) {
+    auto score = [&](const bf16x8* cw, const float* cmu, int k) {
       float q0 = 0.0f, q1 = 0.0f;
       const bf16x8* cwl = cw + (NB - 1) * NFZ;
       bf16x8 b[KS], bl[KS];
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
     // score clusters k0 ... k0 + nk - 1 from (cw, cmu) while the next group (kn, nkn)
     // is copied into (nw, nmu)
     auto group = [&](const bf16x8* cw, const float* cmu, bf16x8* nw, float* nmu, int k0, int nk, bool next, int kn,
-                     int nkn) __attribute__((always_inline)) {
+                     int nkn) {
       if (next) stage(nw, nmu, kn, nkn);
 #pragma unroll
       for (int c = 0; c < CPB; ++c)
