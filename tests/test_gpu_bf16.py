@@ -31,8 +31,8 @@ def _wishart_params(K, d, seed, mean_scale=5.0):
 
 @pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
 @pytest.mark.parametrize("d,K,n,scale", [(32, 20, 20000, 5.0), (32, 3, 4097, 5.0), (64, 8, 6000, 5.0),
-                                         (64, 1, 333, 5.0), (128, 6, 3000, 5.0), (128, 1, 257, 5.0),
-                                         (128, 5, 2000, 0.4)])
+                                         (64, 7, 5000, 5.0), (64, 1, 333, 5.0), (128, 6, 3000, 5.0),
+                                         (128, 1, 257, 5.0), (128, 5, 2000, 0.4)])
 def test_bf16_labels_meet_fp32_rule(precision, d, K, n, scale):
     import torch
     from paper_2204_08988_amd.sampler import Sampler
