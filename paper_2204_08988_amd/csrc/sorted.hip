@@ -1128,11 +1128,11 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
         if (e != hipSuccess) return e;
         lattr = true;
       }
-      const long long chunks = (n + SUBL_BLOCK - 1) / SUBL_BLOCK;
-      // d = 32: three waves per SIMD, all workgroups resident at once
+      // d = 32: three waves per SIMD, all workgroups resident at once; each workgroup takes
+      // a range of whole waves' rows (64), so that the ranges differ by at most one wave
       const long long cap = d == 128 ? 512 : (d == 64 ? 1024 : 768);
-      const long long gl = chunks < cap ? chunks : cap;
-      const long long lper = ((chunks + gl - 1) / gl) * SUBL_BLOCK;
+      long long lper = (n + cap - 1) / cap;
+      lper = ((lper + 63) / 64) * 64;
       const unsigned lg = (unsigned)((n + lper - 1) / lper);
       if (d == 128)
         hipLaunchKernelGGL(k_sub_labels_mfma<128>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, perm, z, zrow,
