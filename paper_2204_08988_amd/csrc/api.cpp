@@ -344,7 +344,7 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
   ok = ok && chk(c->alloc(&c->d_counts, 2 * (size_t)km));
   ok = ok && chk(c->alloc(&c->d_log_pi, (size_t)km + 1));
   ok = ok && chk(c->alloc(&c->d_log_pisub, 2 * (size_t)km));
-  ok = ok && chk(c->alloc(&c->d_tmp, (size_t)km + 1));
+  ok = ok && chk(c->alloc(&c->d_tmp, (size_t)3 * km + 1));  // the K + 1 + 2K log-gamma draws of k_weights
   ok = ok && chk(c->alloc(&c->d_logdet, 3 * (size_t)km));
   ok = ok && chk(c->alloc(&c->d_packed, 3 * (size_t)km * c->stride));
   ok = ok && chk(c->alloc(&c->d_err, 1));

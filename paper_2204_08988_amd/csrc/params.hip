@@ -59,29 +59,39 @@ __device__ __forceinline__ int tri_index(int a, int b, int d) {
 
 }  // namespace
 
+// Every log-gamma draw of the step on a thread of its own (the K + 1 of the
+// cluster weights, then the 2K of the sub-cluster weights, into tmp), then the
+// normalisations; tmp holds at least 3K + 1 doubles.
 __global__ void k_weights(int K, double alpha, const long long* __restrict__ counts, uint64_t seed,
                           uint32_t t, double* __restrict__ log_pi, double* __restrict__ log_pisub,
                           double* __restrict__ tmp) {
   __shared__ double red[256];
   const int tid = threadIdx.x;
   double mx = -INFINITY;
-  for (int j = tid; j <= K; j += blockDim.x) {
-    const double shape = j < K ? (double)(counts[2 * j] + counts[2 * j + 1]) : alpha;
-    const double lg = log_gamma_draw(seed, t, (uint32_t)j, TAG_WEIGHTS, 0, shape);
-    tmp[j] = lg;
-    mx = fmax(mx, lg);
+  for (int q = tid; q <= 3 * K; q += blockDim.x) {
+    double lg;
+    if (q <= K) {
+      const double shape = q < K ? (double)(counts[2 * q] + counts[2 * q + 1]) : alpha;
+      lg = log_gamma_draw(seed, t, (uint32_t)q, TAG_WEIGHTS, 0, shape);
+      mx = fmax(mx, lg);
+    } else {
+      const int r = q - (K + 1), k = r >> 1, h = r & 1;
+      lg = log_gamma_draw(seed, t, (uint32_t)k, TAG_SUBWEIGHTS, (uint32_t)h, (double)counts[2 * k + h] + 0.5 * alpha);
+    }
+    tmp[q] = lg;
   }
+  // the draws are read by other threads below: release them to the device
+  // scope before the reduction's barriers and acquire after
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   mx = block_reduce_max(mx, red);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   double s = 0.0;
   for (int j = tid; j <= K; j += blockDim.x) s += exp(tmp[j] - mx);
   s = block_reduce_sum(s, red);
   const double lse = mx + log(s);
   for (int j = tid; j < K; j += blockDim.x) log_pi[j] = tmp[j] - lse;
   for (int k = tid; k < K; k += blockDim.x) {
-    const double a0 = (double)counts[2 * k] + 0.5 * alpha;
-    const double a1 = (double)counts[2 * k + 1] + 0.5 * alpha;
-    const double l0 = log_gamma_draw(seed, t, (uint32_t)k, TAG_SUBWEIGHTS, 0, a0);
-    const double l1 = log_gamma_draw(seed, t, (uint32_t)k, TAG_SUBWEIGHTS, 1, a1);
+    const double l0 = tmp[K + 1 + 2 * k], l1 = tmp[K + 2 + 2 * k];
     const double m = fmax(l0, l1);
     const double l = m + log(exp(l0 - m) + exp(l1 - m));
     log_pisub[2 * k] = l0 - l;
