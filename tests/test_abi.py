@@ -108,3 +108,30 @@ def test_null_arguments():
     assert L.dpmm_learned_move(None, None, 0, 1, None, None, None, None) == -1
     assert L.dpmm_mlp_train(None, None, 0, None, None, 1, 1, 1e-3, None) == -1
     assert L.dpmm_set_features(None, None, 0, None, 0, -1, None, None, 0, None) == -1
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every field offset and the size of the three ABI structs, as a C
+    compiler lays them out from include/dpmm.h, equal the ctypes binding's."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"dpmm_config": _lib.Config, "dpmm_iter_info": _lib.IterInfo, "dpmm_learned_info": _lib.LearnedInfo}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "dpmm.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
