@@ -362,8 +362,9 @@ constexpr int BLOCK_W32 = 512;  // threads of k_label_gauss_mfma_w32: 8 waves of
 // the diagonal), its mean and its constant are copied from global memory
 // straight into LDS (global_load_lds, no registers) into one of two
 // statically allocated buffers, while the workgroup scores its points against
-// the previous clusters from the other (two clusters per buffer and barrier in
-// BF16, one in bf16x3, whose tables are twice as large); the matrix cores
+// the previous clusters from the other (in BF16 four clusters per buffer and
+// barrier at d = 64, two at d = 128; one in bf16x3, whose tables are twice as
+// large); the matrix cores
 // execute 1.25 d^2 instead of 2 d^2 flops per point-cluster at d = 128.  A
 // wave scores a single 32-point tile: lanes l and l + 32 hold the two halves
 // of the K slice of point l % 32, so a lane keeps d / 2 FP32 coordinates and
@@ -391,7 +392,7 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
   constexpr int NB = X3 ? 2 : 1;  // fragment tables per cluster (hi, lo)
   constexpr int MUS = D + 4;      // mu[D], c
   constexpr int CHUNK = BLOCK_W32 / 2;
-  constexpr int CPB = X3 ? 1 : 2;  // clusters per staging buffer (per barrier)
+  constexpr int CPB = X3 ? 1 : (D == 64 ? 4 : 2);  // clusters per staging buffer (per barrier)
   static_assert(D < BLOCK_W32 && CHUNK == BLOCK && NFZ % 64 == 0, "staging layout, histogram blocks");
   __shared__ __align__(16) bf16x8 s_w0[CPB * NB * NFZ], s_w1[CPB * NB * NFZ];
   __shared__ __align__(16) float s_mu0[CPB * MUS], s_mu1[CPB * MUS];
