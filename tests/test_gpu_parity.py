@@ -23,7 +23,7 @@ def _gauss_sampler(d, k_max, seed, **kw):
 
 GAUSS_CASES = [(1, 1, 777), (2, 6, 10000), (3, 4, 5000), (8, 12, 4099), (5, 7, 2049),
                (16, 9, 2000), (32, 20, 3001), (2, 70, 1500), (12, 3, 1300), (8, 300, 5000),
-               (64, 5, 700), (33, 4, 900), (128, 3, 300), (128, 6, 140000)]
+               (64, 5, 700), (33, 4, 900), (128, 3, 300), (128, 6, 140000), (32, 20, 200003)]
 
 
 def _check_stats(got, x, z, zs, K, d):
