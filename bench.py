@@ -38,7 +38,7 @@ PEAK_FP64_MFMA = 78.6e12   # dense FP64 matrix-core peak
 # scaled by a device copy of known size (profiles/traffic_gauss_d32_n1e6.md);
 # None once a kernel changes
 MEASURED_TRAFFIC = {"k_label_gauss_mfma32<false,false>": 133.3e6,
-                    "k_sub_labels_mfma<32>+k_sub_stats_w<32,false>": 304.6e6}
+                    "k_sub_labels_mfma<32>+k_sub_stats_w<32,false>": 304.7e6}
 
 
 def flops_per_eval(d):
