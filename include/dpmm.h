@@ -14,7 +14,9 @@
  *     parameters, statistics, scratch) and frees it in dpmm_destroy.
  *   - Layout: x is point-major (row-major) N x d float32 (Gaussian) or
  *     N x V int32 counts (multinomial); z is int32[N] with clusters 0..K-1;
- *     zsub is uint8[N] with 0 = left (l), 1 = right (r) sub-cluster.
+ *     zsub is uint8[N] with 0 = left (l), 1 = right (r) sub-cluster.  Every
+ *     call taking n accepts 0 <= n < 2^31 (device point indices are int32)
+ *     and returns DPMM_E_SHAPE otherwise.
  *   - Streams: every call enqueues on the stream given to dpmm_create and
  *     returns; calls that must read device results back (dpmm_split_merge,
  *     dpmm_step, the dpmm_get_* calls) synchronise that stream.
@@ -293,6 +295,18 @@ dpmm_status dpmm_learned_move(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t 
  * qualifies (loss = NaN). */
 dpmm_status dpmm_mlp_train(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub,
                            int32_t steps, int32_t batch, float lr, double* loss);
+
+/* The rows dpmm_mlp_train draws its batches from, all of them: the points of
+ * every cluster with age >= burn_out and two non-empty sub-clusters, in
+ * increasing index order; feats device float[n_rows][F] their set features
+ * under their own cluster's frame, y device float[n_rows] their targets (1
+ * for sub-label l, flipped per cluster so that side l has the larger mean
+ * first principal coordinate), idx device int32[n_rows] their point
+ * indices.  Each output may be NULL (all NULL: count only); capacity is the
+ * rows each non-NULL output holds (DPMM_E_SHAPE if below n_rows).  n_rows:
+ * host.  Needs current statistics (DPMM_E_STATE otherwise). */
+dpmm_status dpmm_mlp_training_set(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub,
+                                  float* feats, float* y, int32_t* idx, int64_t capacity, int64_t* n_rows);
 
 #ifdef __cplusplus
 }

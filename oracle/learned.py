@@ -189,12 +189,13 @@ def move(model, x, state, theta, m, t):
     return state, info
 
 
-def training_set(model, x, state, m):
+def training_set(model, x, state, m, with_rows=False):
     """Features and targets from the sampler's own sub-labels: points of every
     cluster with age >= burn_out and both sub-clusters non-empty; target 1 for
     sub-label l, flipped per cluster so that the l side has the larger mean
-    first principal coordinate."""
-    X, Y = [], []
+    first principal coordinate.  Rows come cluster by cluster (each in index
+    order); with_rows also returns their point indices."""
+    X, Y, R = [], [], []
     for k in range(state.K):
         if state.age[k] < model.burn_out:
             continue
@@ -208,6 +209,9 @@ def training_set(model, x, state, m):
             y = 1.0 - y
         X.append(f)
         Y.append(y)
+        R.append(C)
     if not X:
-        return np.zeros((0, 2 * m)), np.zeros(0)
-    return np.concatenate(X), np.concatenate(Y)
+        out = (np.zeros((0, 2 * m)), np.zeros(0), np.zeros(0, dtype=np.int64))
+    else:
+        out = (np.concatenate(X), np.concatenate(Y), np.concatenate(R))
+    return out if with_rows else out[:2]

@@ -24,7 +24,7 @@ EXPORTS = [
     "dpmm_get_stats", "dpmm_loglik", "dpmm_sample_labels", "dpmm_suffstats", "dpmm_sample_params",
     "dpmm_split_merge", "dpmm_step", "dpmm_mlp_n_params", "dpmm_mlp_set_weights", "dpmm_mlp_get_weights",
     "dpmm_mlp_forward", "dpmm_mlp_grad", "dpmm_mlp_adam_step", "dpmm_set_features", "dpmm_learned_move",
-    "dpmm_mlp_train",
+    "dpmm_mlp_train", "dpmm_mlp_training_set",
 ]
 
 
@@ -105,6 +105,7 @@ def lib():
         "dpmm_set_features": ([vp, vp, i64, vp, i32, i32, vp, vp, i64, ctypes.POINTER(i64)], i32),
         "dpmm_learned_move": ([vp, vp, i64, u32, vp, vp, vp, ctypes.POINTER(LearnedInfo)], i32),
         "dpmm_mlp_train": ([vp, vp, i64, vp, vp, i32, i32, ctypes.c_float, dp], i32),
+        "dpmm_mlp_training_set": ([vp, vp, i64, vp, vp, vp, vp, vp, i64, ctypes.POINTER(i64)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

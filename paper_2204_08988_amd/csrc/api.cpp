@@ -53,7 +53,9 @@ namespace dpmm::host {
 
 dpmm_status check_n(dpmm_ctx* ctx, const void* x, int64_t n) {
   if (!x && n > 0) return ctx->fail(DPMM_E_ARG, "x is NULL");
-  if (n < 0 || n > (int64_t)0xFFFFFFFFLL) return ctx->fail(DPMM_E_SHAPE, "n must lie in [0, 2^32)");
+  // point indices are int32 on the device (the cluster-sorted permutation, the
+  // deferred-draw list, the learned proposal's selection)
+  if (n < 0 || n > (int64_t)0x7FFFFFFFLL) return ctx->fail(DPMM_E_SHAPE, "n must lie in [0, 2^31)");
   return DPMM_OK;
 }
 
@@ -81,13 +83,27 @@ dpmm_status ensure_perm(dpmm_ctx* ctx, int64_t n) {
   }
   DPMM_HIP(ctx, hipMalloc(&ctx->d_perm, (size_t)n * sizeof(int)), "allocate permutation");
   DPMM_HIP(ctx, hipMalloc(&ctx->d_zsort, (size_t)n * sizeof(int)), "allocate sorted labels");
-  if (!ctx->d_part && sub_stats_part_doubles(ctx->d) > 0)
-    DPMM_HIP(ctx, hipMalloc(&ctx->d_part, sub_stats_part_doubles(ctx->d) * sizeof(double)),
-             "allocate partial statistics");
   // candidate lists of the points the matrix-core label kernels defer
   if (ctx->d_nflag)
     DPMM_HIP(ctx, hipMalloc(&ctx->d_cand, (size_t)n * RESCORE_CAND * sizeof(int)), "allocate candidate lists");
   ctx->perm_cap = n;
+  return ensure_part(ctx, n);
+}
+
+// partial-slot buffer of the sorted-order statistics kernels, sized for any
+// number of rows (allocated once)
+dpmm_status ensure_part(dpmm_ctx* ctx, int64_t n) {
+  const size_t need = sub_stats_part_doubles(ctx->d, n);
+  if (need <= ctx->part_cap) return DPMM_OK;
+  const size_t cap = std::max(need, sub_stats_part_doubles_max(ctx->d));
+  if (ctx->d_part) {
+    DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    hipFree(ctx->d_part);
+    ctx->d_part = nullptr;
+    ctx->part_cap = 0;
+  }
+  DPMM_HIP(ctx, hipMalloc(&ctx->d_part, cap * sizeof(double)), "allocate partial statistics");
+  ctx->part_cap = cap;
   return DPMM_OK;
 }
 
@@ -95,6 +111,7 @@ dpmm_status ensure_perm(dpmm_ctx* ctx, int64_t n) {
 dpmm_status sorted_pass(dpmm_ctx* ctx, const void* x, int64_t n, bool labels_done_hist, bool sample, uint32_t t,
                         const int32_t* z, uint8_t* zsub, int G, long long per_block) {
   DPMM_TRY(ensure_perm(ctx, n));
+  DPMM_TRY(ensure_part(ctx, n));
   DPMM_HIP(ctx, launch_sort_by_z(z, n, ctx->K, G, per_block, labels_done_hist, ctx->d_hist, ctx->d_tot, ctx->d_offs,
                                  ctx->d_perm, ctx->d_zsort, ctx->stream), "sort by cluster");
   if (ctx->timing) DPMM_HIP(ctx, hipEventRecord(ctx->ev[3], ctx->stream), "event");
@@ -108,14 +125,17 @@ dpmm_status sorted_pass(dpmm_ctx* ctx, const void* x, int64_t n, bool labels_don
 
 dpmm_status launch_stats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub) {
   hipError_t e;
-  if (ctx->sorted_path()) {
+  // Gaussian: per-lane accumulators for d <= 4 while they fit in LDS, else
+  // the cluster-sorted kernels (both take their sums in a fixed order)
+  if (ctx->gaussian() && (ctx->sorted_path() || !stats_small_lanes(ctx->d, ctx->K))) {
     int G;
     long long per;
     sorted_plan(n, ctx->K, ctx->hist_cap, &G, &per);
     return sorted_pass(ctx, x, n, false, false, 0, z, const_cast<uint8_t*>(zsub), G, per);
   }
   if (ctx->gaussian())
-    e = launch_stats_gauss(ctx->d, (const float*)x, n, z, zsub, ctx->K, ctx->d_counts, ctx->d_moments, ctx->stream);
+    e = launch_stats_gauss(ctx->d, (const float*)x, n, z, zsub, ctx->K, ctx->d_counts, ctx->d_moments, ctx->d_spart,
+                           ctx->stream);
   else
     e = launch_stats_mult(ctx->d, (const int*)x, n, z, zsub, ctx->K, ctx->d_counts, ctx->d_sums, ctx->stream);
   DPMM_HIP(ctx, e, "statistics kernel");
@@ -363,11 +383,17 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
       // low parts: the bf16x3 form, and the candidate pass of either matrix-core form
       ok = ok && chk(c->alloc(&c->d_wlo, (size_t)km * d * d));
     }
-    if (d >= SORTED_MIN_D) {
-      c->hist_cap = 2048LL * km;
-      ok = ok && chk(c->alloc(&c->d_hist, (size_t)c->hist_cap));
-      ok = ok && chk(c->alloc(&c->d_offs, (size_t)c->hist_cap));
-      ok = ok && chk(c->alloc(&c->d_tot, (size_t)km + 2));
+    // counting sort by cluster: the label path for d >= 5, the statistics of
+    // any d once K outgrows the small-d kernel's LDS accumulators
+    c->hist_cap = 2048LL * km;
+    ok = ok && chk(c->alloc(&c->d_hist, (size_t)c->hist_cap));
+    ok = ok && chk(c->alloc(&c->d_offs, (size_t)c->hist_cap));
+    ok = ok && chk(c->alloc(&c->d_tot, (size_t)km + 2));
+    ok = ok && chk(c->alloc(&c->d_cspan, 2));
+    if (d <= 4) {
+      size_t sp = 0;
+      for (int k = 1; k <= km; ++k) sp = std::max(sp, stats_small_part_doubles(d, k));
+      ok = ok && chk(c->alloc(&c->d_spart, std::max<size_t>(sp, 1)));
     }
   } else {
     ok = ok && chk(c->alloc(&c->d_beta, (size_t)d));

@@ -70,7 +70,10 @@ struct dpmm_ctx {
   // cluster-sorted path (Gaussian, d >= dpmm::SORTED_MIN_D)
   int *d_hist = nullptr, *d_offs = nullptr, *d_tot = nullptr, *d_perm = nullptr;
   int* d_zsort = nullptr;  // [perm_cap] the cluster of each row of the sorted order
-  double* d_part = nullptr;  // partial statistics slots of the d <= 32 statistics kernel
+  double* d_part = nullptr;  // partial statistics slots of the sorted-order statistics kernels
+  size_t part_cap = 0;       // doubles in d_part
+  double* d_spart = nullptr; // per-workgroup rows of the d <= 4 statistics kernel
+  int* d_cspan = nullptr;    // {0, n} of a partition's one cluster (learned split statistics)
   long long hist_cap = 0, perm_cap = 0;
   bool labels_gave_stats = false;
   // BF16 whitener fragments of the cluster components (precision != FP32)
@@ -97,6 +100,7 @@ struct dpmm_ctx {
   float* d_frames = nullptr;  // [k_max][d + m d + m]
   int *d_flip = nullptr, *d_elig = nullptr;
   double* d_lsums = nullptr;     // proposal sums [4], loss [1]
+  double* d_red = nullptr;       // rows of the fixed-order reductions (MLP_RED_DOUBLES)
   double* d_setpart = nullptr;   // set-statistics partials [SET_STATS_BLOCKS][2][E + 1]
   int* d_selcnt = nullptr;       // selection block counts [SELECT_BLOCKS + 1]
   int* d_sel = nullptr;          // selected point indices [sel_cap]
@@ -141,6 +145,7 @@ inline int tri_index(int a, int b, int d) { return a * d - (a * (a - 1)) / 2 + (
 dpmm_status check_n(dpmm_ctx* ctx, const void* x, int64_t n);
 NiwPriorDev prior_dev(dpmm_ctx* ctx);
 dpmm_status launch_stats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub);
+dpmm_status ensure_part(dpmm_ctx* ctx, int64_t n);
 // log marginal likelihoods of segment unions, read back (synchronises);
 // *flag_out (optional) receives the device error flag
 dpmm_status logml(dpmm_ctx* ctx, const std::vector<LogmlItem>& items, std::vector<double>& out,

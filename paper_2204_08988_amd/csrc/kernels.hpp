@@ -54,21 +54,26 @@ hipError_t launch_gemm_nt(const void* A, int lda, const void* Bt, int ldb, int M
                           bool relu, const void* mask, int ldm, float* out32, int ld32, bool accumulate, void* out16,
                           int ld16, void* out16t, int ld16t, hipStream_t s);
 hipError_t launch_out_layer(const float* H2, int n, const float* w3, const float* b3, float* o, hipStream_t s);
+// red: float64 row buffers of the fixed-order reductions below, MLP_RED_DOUBLES
+constexpr size_t MLP_RED_DOUBLES = (size_t)1024 * (MLP_HIDDEN + 2);
+// gw3, gb3 adjacent (gb3 = gw3 + 128); adds the block sums in block order
 hipError_t launch_out_backward(const float* o, const float* y, const float* H2, int n, int npad, const float* w3,
-                               void* D2, void* D2t, float* gw3, float* gb3, double* loss, hipStream_t s);
-hipError_t launch_colsum(const void* A, int lda, int n, int ncol, float* out, hipStream_t s);
+                               void* D2, void* D2t, float* gw3, float* gb3, double* loss, double* red, hipStream_t s);
+hipError_t launch_colsum(const void* A, int lda, int n, int ncol, float* out, double* red, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
                        int step, hipStream_t s);
 hipError_t launch_refresh_weights(const float* p, int F, int Fp, void* w1t, void* w2t, void* w2, hipStream_t s);
-// rows whose idx is outside [0, npts) are zero / skipped by the set kernels
+// rows whose idx is outside [0, npts) are zero / skipped by the set kernels;
+// the frame (and flip) of row q is cl[q], or cl[idx[q]] with cl_by_point
+// (cl = z: the row's own cluster), or 0 without cl
 hipError_t launch_features(const float* x, int d, long long npts, const int* idx, const int* cl, int n,
                            const float* frames, int m, int F, int Fp, void* X16, void* X16t, int npad, float* X32,
-                           hipStream_t s);
+                           hipStream_t s, bool cl_by_point = false);
 hipError_t launch_convert(const float* X32, int n, int F, int Fp, void* X16, void* X16t, int npad, hipStream_t s);
 hipError_t launch_targets(const int* idx, const int* cl, int n, const unsigned char* zsub, const int* flip, float* y,
-                          hipStream_t s);
+                          hipStream_t s, bool cl_by_point = false);
 hipError_t launch_proposal(const float* o, long long npts, const int* idx, int n, int merge_k1, const int* z,
-                           uint64_t seed, uint32_t t, unsigned char* side, double* sums, hipStream_t s);
+                           uint64_t seed, uint32_t t, unsigned char* side, double* sums, double* red, hipStream_t s);
 hipError_t launch_apply_split(long long npts, const int* idx, int n, const unsigned char* side, int k_new,
                               uint64_t seed, uint32_t t, int* z, unsigned char* zsub, hipStream_t s);
 // stable selection of {i : z_i in {k1, k2}} (elig == nullptr) or {i : elig[z_i]};
@@ -94,22 +99,24 @@ hipError_t launch_label_gauss_z(int d, const float* x, long long n, int G, long 
 hipError_t sorted_plan(long long n, int K, long long hist_cap, int* G, long long* per_block);
 hipError_t launch_sort_by_z(const int* z, long long n, int K, int G, long long per_block, bool have_hist, int* hist,
                             int* tot, int* offs, int* perm, int* zsort, hipStream_t s);
-// waves of the d <= 32 statistics kernel; in slot mode (cstart = the clusters'
-// first sorted rows, ctot their sizes, part = sub_stats_part_doubles(d)
-// doubles) every cluster's statistics are written, with no atomics
+// waves of the d <= 32 statistics kernel.  In slot mode (cstart = the
+// clusters' first sorted rows, ctot their sizes, part =
+// sub_stats_part_doubles(d, n) doubles) every cluster's statistics are
+// written, with no float atomics: the sums are taken in a fixed order
 constexpr int SUBW_WAVES = 2048;
-bool sub_stats_slot_mode(int d);
-size_t sub_stats_part_doubles(int d);
+size_t sub_stats_part_doubles(int d, long long n);
+size_t sub_stats_part_doubles_max(int d);  // over every n
 hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, const int* perm, const int* z,
                             const int* zrow, unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t,
                             uint64_t seed, long long* counts, double* moments, const int* cstart, const int* ctot,
                             double* part, hipStream_t s);
 // statistics of a listed set of cluster k1's points split by side[i] into
-// segments slot, slot + 1 (slot >= 2 k1; d in {8, 16, 32, 64, 128})
+// segments slot, slot + 1 (slot >= 2 k1; d in {8, 16, 32, 64, 128});
+// cspan: device int[2] = {0, nsel}; part: sub_stats_part_doubles(d, nsel)
 bool partition_stats_supported(int d);
 hipError_t launch_partition_stats(int d, const float* x, long long npts, const int* idx, long long nsel,
                                   const int* z, int k1, int K, const unsigned char* side, int slot,
-                                  long long* counts, double* moments, hipStream_t s);
+                                  long long* counts, double* moments, const int* cspan, double* part, hipStream_t s);
 // BF16 matrix-core cluster draw (d in {32, 64}) and its whitener fragments
 bool mfma_supported(int d);
 hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void* whi, void* wlo, hipStream_t s);
@@ -127,8 +134,15 @@ hipError_t launch_label_mult(int V, const int* x, long long n, const float* pack
                              uint32_t t, uint64_t seed, int* z, unsigned char* zsub, hipStream_t s);
 hipError_t launch_loglik_mult(int V, const int* x, long long n, const float* packed, int K, int k_max,
                               float* out, hipStream_t s);
+// Gaussian statistics for d <= 4 (when stats_small_lanes(d, K) > 0): part
+// holds stats_small_part_doubles(d, K) doubles of per-workgroup rows
+constexpr int STATS_SMALL_LANES = 65536;
+int stats_small_lanes(int d, int K);
+size_t stats_small_part_doubles(int d, int K);
 hipError_t launch_stats_gauss(int d, const float* x, long long n, const int* z, const unsigned char* zsub,
-                              int K, long long* counts, double* moments, hipStream_t s);
+                              int K, long long* counts, double* moments, double* part, hipStream_t s);
+// device p[0] = a, p[1] = b
+hipError_t launch_set_pair(int* p, int a, int b, hipStream_t s);
 hipError_t launch_stats_mult(int V, const int* x, long long n, const int* z, const unsigned char* zsub,
                              int K, long long* counts, long long* sums, hipStream_t s);
 

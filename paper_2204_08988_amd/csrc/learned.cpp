@@ -138,11 +138,11 @@ dpmm_status backward_chunk(dpmm_ctx* ctx, int c, const float* y) {
   hipStream_t s = ctx->stream;
   float* g = ctx->d_g;
   DPMM_HIP(ctx, launch_out_backward(ctx->d_o, y, ctx->d_h2, c, MLP_CHUNK, ctx->d_p + of.w3, ctx->d_d2, ctx->d_d2t,
-                                    g + of.w3, g + of.b3, ctx->d_lsums + 4, s), "output backward kernel");
+                                    g + of.w3, g + of.b3, ctx->d_lsums + 4, ctx->d_red, s), "output backward kernel");
   DPMM_HIP(ctx, launch_gemm_nt(ctx->d_d2, H, ctx->d_w2, H, c, H, H, nullptr, false, ctx->d_h1, H, nullptr, 0, false,
                                ctx->d_d1, H, ctx->d_d1t, MLP_CHUNK, s), "layer 2 backward kernel");
-  DPMM_HIP(ctx, launch_colsum(ctx->d_d2, H, c, H, g + of.b2, s), "bias gradient kernel");
-  DPMM_HIP(ctx, launch_colsum(ctx->d_d1, H, c, H, g + of.b1, s), "bias gradient kernel");
+  DPMM_HIP(ctx, launch_colsum(ctx->d_d2, H, c, H, g + of.b2, ctx->d_red, s), "bias gradient kernel");
+  DPMM_HIP(ctx, launch_colsum(ctx->d_d1, H, c, H, g + of.b1, ctx->d_red, s), "bias gradient kernel");
   DPMM_HIP(ctx, launch_gemm_nt(ctx->d_h1t, MLP_CHUNK, ctx->d_d2t, MLP_CHUNK, H, H, c, nullptr, false, nullptr, 0,
                                g + of.W2, H, true, nullptr, 0, nullptr, 0, s), "W2 gradient kernel");
   DPMM_HIP(ctx, launch_gemm_nt(ctx->d_x16t, MLP_CHUNK, ctx->d_d1t, MLP_CHUNK, ctx->F, H, c, nullptr, false, nullptr,
@@ -297,6 +297,7 @@ dpmm_status learned_alloc(dpmm_ctx* ctx) {
   A(&c->d_flip, km);
   A(&c->d_elig, km);
   A(&c->d_lsums, 8);
+  A(&c->d_red, MLP_RED_DOUBLES);
   A(&c->d_setpart, (size_t)SET_STATS_BLOCKS * 2 * (1 + c->E));
   A(&c->d_selcnt, SELECT_BLOCKS + 1);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_frame, frame_size(c) * sizeof(float), hipHostMallocDefault);
@@ -380,7 +381,7 @@ dpmm_status learned_move(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, in
                                   ctx->F, ctx->Fp, ctx->d_x16, nullptr, 0, nullptr, s), "features kernel");
     DPMM_TRY(forward_chunk(ctx, c, false, ctx->d_o));
     DPMM_HIP(ctx, launch_proposal(ctx->d_o, n, ctx->d_sel + off, c, split ? -1 : k1, z, seed, t, side, ctx->d_lsums,
-                                  s), "proposal kernel");
+                                  ctx->d_red, s), "proposal kernel");
   }
   std::vector<LogmlItem> items;
   int a_off = 0;  // segment of side A (side == 1) within slot, slot + 1
@@ -388,10 +389,13 @@ dpmm_status learned_move(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, in
     const int slot = 2 * K;
     // the sorted-order kernels keep side h in segment slot + h; the generic one puts side A first
     a_off = partition_stats_supported(ctx->d) ? 1 : 0;
-    if (partition_stats_supported(ctx->d))
+    if (partition_stats_supported(ctx->d)) {
+      DPMM_TRY(ensure_part(ctx, nC));
+      DPMM_HIP(ctx, launch_set_pair(ctx->d_cspan, 0, (int)nC, s), "span kernel");
       DPMM_HIP(ctx, launch_partition_stats(ctx->d, (const float*)x, n, ctx->d_sel, nC, z, k1, K, side, slot,
-                                           ctx->d_counts, ctx->d_moments, s), "partition statistics kernels");
-    else
+                                           ctx->d_counts, ctx->d_moments, ctx->d_cspan, ctx->d_part, s),
+               "partition statistics kernels");
+    } else
       DPMM_HIP(ctx, launch_set_stats((const float*)x, ctx->d, n, ctx->d_sel, (int)nC, side, ctx->d_setpart, slot,
                                      ctx->d_counts, ctx->d_moments, s), "partition statistics kernels");
     DPMM_HIP(ctx, hipMemcpyAsync(back->side_cnt, ctx->d_counts + slot, 2 * sizeof(long long), hipMemcpyDeviceToHost,
@@ -591,17 +595,16 @@ dpmm_status dpmm_learned_move(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t 
   return learned_move(ctx, x, n, t, z, zsub, side_out, info);
 }
 
-dpmm_status dpmm_mlp_train(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub,
-                           int32_t steps, int32_t batch, float lr, double* loss) {
-  if (!ctx) return DPMM_E_ARG;
-  DPMM_TRY(need_learned(ctx));
-  DPMM_TRY(check_n(ctx, x, n));
-  if (n > 0 && (!z || !zsub)) return ctx->fail(DPMM_E_ARG, "z / zsub is NULL");
-  if (steps < 0) return ctx->fail(DPMM_E_ARG, "steps must be >= 0");
-  if (batch < 1 || batch > MLP_CHUNK) return ctx->fail(DPMM_E_ARG, "batch must lie in [1, 65536]");
-  if (!(lr > 0.0f) || !std::isfinite(lr)) return ctx->fail(DPMM_E_ARG, "lr must be > 0");
-  if (!ctx->have_stats) return ctx->fail(DPMM_E_STATE, "no statistics yet");
-  if (loss) *loss = NAN;
+}  // extern "C"
+
+namespace {
+
+// The training rows of the sampler's own sub-labels: frames and target flips
+// of every cluster with age >= burn_out and two non-empty sub-clusters go to
+// d_frames / d_flip, and the stable list of their points to d_sel; *n_sel is
+// their number (0: nothing qualifies).
+dpmm_status training_rows(dpmm_ctx* ctx, int64_t n, const int32_t* z, int* n_sel) {
+  *n_sel = 0;
   const int K = ctx->K, d = ctx->d, E = ctx->E, fs = frame_size(ctx);
   std::vector<int> slots(2 * (size_t)K);
   std::iota(slots.begin(), slots.end(), 0);
@@ -646,8 +649,7 @@ dpmm_status dpmm_mlp_train(dpmm_ctx* ctx, const void* x, int64_t n, const int32_
   }
   for (char o : ok)
     if (!o) return ctx->fail(DPMM_E_NUMERIC, "the eigen-iteration of a cluster covariance did not converge");
-  const int n_elig_clusters = (int)todo.size();
-  if (n_elig_clusters == 0 || steps == 0) return DPMM_OK;
+  if (todo.empty()) return DPMM_OK;
   hipStream_t s = ctx->stream;
   DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_frames, frames.data(), frames.size() * sizeof(float), hipMemcpyHostToDevice, s),
            "copy frames");
@@ -655,11 +657,61 @@ dpmm_status dpmm_mlp_train(dpmm_ctx* ctx, const void* x, int64_t n, const int32_
   DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_flip, flip.data(), K * sizeof(int), hipMemcpyHostToDevice, s), "copy");
   DPMM_TRY(ensure_sel(ctx, n));
   DPMM_HIP(ctx, launch_select(z, n, -1, -1, ctx->d_elig, K, ctx->d_selcnt, ctx->d_sel, s), "selection kernels");
-  int n_sel = 0;
-  DPMM_HIP(ctx, hipMemcpyAsync(&n_sel, ctx->d_selcnt + SELECT_BLOCKS, sizeof(int), hipMemcpyDeviceToHost, s),
-           "copy count");
+  DPMM_HIP(ctx, hipMemcpyAsync(&ctx->h_back->sel_count, ctx->d_selcnt + SELECT_BLOCKS, sizeof(int),
+                               hipMemcpyDeviceToHost, s), "copy count");
   DPMM_HIP(ctx, hipStreamSynchronize(s), "synchronise");  // also keeps the host tables alive until copied
+  *n_sel = ctx->h_back->sel_count;
+  return DPMM_OK;
+}
+
+dpmm_status training_args(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub) {
+  DPMM_TRY(need_learned(ctx));
+  DPMM_TRY(check_n(ctx, x, n));
+  if (n > 0 && (!z || !zsub)) return ctx->fail(DPMM_E_ARG, "z / zsub is NULL");
+  if (!ctx->have_stats) return ctx->fail(DPMM_E_STATE, "no statistics yet");
+  return DPMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dpmm_status dpmm_mlp_training_set(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub,
+                                  float* feats, float* y, int32_t* idx, int64_t capacity, int64_t* n_rows) {
+  if (!ctx) return DPMM_E_ARG;
+  DPMM_TRY(training_args(ctx, x, n, z, zsub));
+  if (!n_rows) return ctx->fail(DPMM_E_ARG, "n_rows is NULL");
+  int n_sel = 0;
+  DPMM_TRY(training_rows(ctx, n, z, &n_sel));
+  *n_rows = n_sel;
+  if (n_sel == 0 || (!feats && !y && !idx)) return DPMM_OK;
+  if (capacity < n_sel) return ctx->fail(DPMM_E_SHAPE, "capacity is below the number of training rows");
+  hipStream_t s = ctx->stream;
+  if (feats)
+    DPMM_HIP(ctx, launch_features((const float*)x, ctx->d, n, ctx->d_sel, z, n_sel, ctx->d_frames, ctx->lm, ctx->F,
+                                  ctx->Fp, nullptr, nullptr, 0, feats, s, true), "features kernel");
+  if (y) DPMM_HIP(ctx, launch_targets(ctx->d_sel, z, n_sel, zsub, ctx->d_flip, y, s, true), "targets kernel");
+  if (idx)
+    DPMM_HIP(ctx, hipMemcpyAsync(idx, ctx->d_sel, (size_t)n_sel * sizeof(int), hipMemcpyDeviceToDevice, s),
+             "copy indices");
+  DPMM_HIP(ctx, hipStreamSynchronize(s), "synchronise");
+  return DPMM_OK;
+}
+
+dpmm_status dpmm_mlp_train(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub,
+                           int32_t steps, int32_t batch, float lr, double* loss) {
+  if (!ctx) return DPMM_E_ARG;
+  DPMM_TRY(training_args(ctx, x, n, z, zsub));
+  if (steps < 0) return ctx->fail(DPMM_E_ARG, "steps must be >= 0");
+  if (batch < 1 || batch > MLP_CHUNK) return ctx->fail(DPMM_E_ARG, "batch must lie in [1, 65536]");
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return ctx->fail(DPMM_E_ARG, "lr must be > 0");
+  if (loss) *loss = NAN;
+  if (steps == 0) return DPMM_OK;
+  int n_sel = 0;
+  DPMM_TRY(training_rows(ctx, n, z, &n_sel));
   if (n_sel == 0) return DPMM_OK;
+  hipStream_t s = ctx->stream;
+  const int d = ctx->d;
   DPMM_TRY(ensure_weights(ctx));
   for (int st = 0; st < steps; ++st) {
     DPMM_HIP(ctx, launch_batch_pick(ctx->d_sel, n_sel, batch, ctx->cfg.seed, ctx->train_counter++, z, ctx->d_bidx,

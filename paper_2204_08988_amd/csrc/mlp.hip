@@ -116,13 +116,13 @@ constexpr int OB_ROWS = 64;
 
 // Loss gradient through the output layer for OB_ROWS rows per block, one
 // thread per hidden unit: d_o = sigmoid(o) - y (BCE with logits);
-// D2 = (d_o w3^T) . [H2 > 0] as BF16 row-major and transposed; gw3, gb3 and the
-// loss sum(softplus(o) - y o) accumulate per block, then by one atomic.
+// D2 = (d_o w3^T) . [H2 > 0] as BF16 row-major and transposed; the block's
+// sums of gw3, gb3 and the loss sum(softplus(o) - y o) go to its row
+// red[block][H + 2] (k_add_rows adds the rows in block order).
 __global__ __launch_bounds__(H) void k_out_backward(const float* __restrict__ o, const float* __restrict__ y,
                                                     const float* __restrict__ H2, int n, int npad,
                                                     const float* __restrict__ w3, __bf16* __restrict__ D2,
-                                                    __bf16* __restrict__ D2t, float* __restrict__ gw3,
-                                                    float* __restrict__ gb3, double* __restrict__ loss) {
+                                                    __bf16* __restrict__ D2t, double* __restrict__ red) {
   const int j = threadIdx.x;
   const int r0 = blockIdx.x * OB_ROWS;
   const int r1 = r0 + OB_ROWS < n ? r0 + OB_ROWS : n;
@@ -144,20 +144,36 @@ __global__ __launch_bounds__(H) void k_out_backward(const float* __restrict__ o,
       lacc += sp - (double)y[r] * od;
     }
   }
-  atomicAdd(&gw3[j], gacc);
+  double* row = red + (size_t)blockIdx.x * (H + 2);
+  row[j] = gacc;
   if (j == 0) {
-    atomicAdd(gb3, bacc);
-    atomicAdd(loss, lacc);
+    row[H] = bacc;
+    row[H + 1] = lacc;
   }
 }
 
-// out[c] += sum_i A[i][c] over BF16 rows
-__global__ void k_colsum(const __bf16* __restrict__ A, int lda, int n, int ncol, float* __restrict__ out) {
+// Column sums of BF16 rows: block b sums rows b, b + G, ... of column c into
+// red[b][ncol].
+__global__ void k_colsum(const __bf16* __restrict__ A, int lda, int n, int ncol, double* __restrict__ red) {
   const int c = threadIdx.x;
   if (c >= ncol) return;
   float s = 0.0f;
   for (int i = blockIdx.x; i < n; i += gridDim.x) s += (float)A[(size_t)i * lda + c];
-  atomicAdd(&out[c], s);
+  red[(size_t)blockIdx.x * ncol + c] = s;
+}
+
+// out_c += sum over rows b < G of red[b][c] (in row order), for c < ncol;
+// columns c >= nf go to the float64 outputs outd[c - nf] (the loss sum).
+__global__ void k_add_rows(const double* __restrict__ red, int G, int ncol, int nf, float* __restrict__ outf,
+                           double* __restrict__ outd) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  double s = 0.0;
+  for (int b = 0; b < G; ++b) s += red[(size_t)b * ncol + c];
+  if (c < nf)
+    outf[c] += (float)s;
+  else
+    outd[c - nf] += s;
 }
 
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
@@ -197,13 +213,14 @@ __global__ void k_refresh_weights(const float* __restrict__ p, int F, int Fp, __
 // not name one of the npts points).  Outputs (each optional): X16 BF16
 // [n][Fp], X16t BF16 [Fp][npad], X32 FP32 [n][F].
 __global__ void k_features(const float* __restrict__ x, int d, long long npts, const int* __restrict__ idx,
-                           const int* __restrict__ cl, int n, const float* __restrict__ frames, int m, int F, int Fp,
-                           __bf16* __restrict__ X16, __bf16* __restrict__ X16t, int npad, float* __restrict__ X32) {
+                           const int* __restrict__ cl, int cl_by_point, int n, const float* __restrict__ frames, int m,
+                           int F, int Fp, __bf16* __restrict__ X16, __bf16* __restrict__ X16t, int npad,
+                           float* __restrict__ X32) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const int fs = d + m * d + m;
-  const float* fr = frames + (size_t)(cl ? cl[q] : 0) * fs;
   const bool valid = (unsigned long long)idx[q] < (unsigned long long)npts;  // rows past a short selection
+  const float* fr = frames + (size_t)(cl ? cl[cl_by_point ? (valid ? idx[q] : 0) : q] : 0) * fs;
   const float* xi = x + (size_t)(valid ? idx[q] : 0) * d;
   for (int f = 0; f < Fp; ++f) {
     float v = 0.0f;
@@ -232,24 +249,26 @@ __global__ void k_convert(const float* __restrict__ X32, int n, int F, int Fp, _
   }
 }
 
-// Training targets: 1 for sub-label l, flipped per cluster (flip[cl[q]]).
-__global__ void k_targets(const int* __restrict__ idx, const int* __restrict__ cl, int n,
+// Training targets: 1 for sub-label l, flipped per cluster (flip[cl[q]], or
+// flip[cl[idx[q]]] when cl is indexed by point).
+__global__ void k_targets(const int* __restrict__ idx, const int* __restrict__ cl, int cl_by_point, int n,
                           const unsigned char* __restrict__ zsub, const int* __restrict__ flip, float* __restrict__ y) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const int lft = zsub[idx[q]] == 0 ? 1 : 0;
-  y[q] = (float)(lft ^ flip[cl[q]]);
+  y[q] = (float)(lft ^ flip[cl[cl_by_point ? idx[q] : q]]);
 }
 
 // Proposal over rows idx[0..n): b = clip(sigmoid(o)); side A is
 // u(i, t, TAG_BERN) < b (split) or z_i == merge_k1 (merge).  side[i] = 1 on
-// side A, else 0; sums[0..3] += sum_A log b, sum_A log(1-b), sum_B log b,
-// sum_B log(1-b).
+// side A, else 0; the block's sums of log b and log(1-b) over side A and over
+// side B (a fixed tree) go to red[block][4] (k_add_rows adds the rows in
+// block order).
 __global__ __launch_bounds__(BLOCK) void k_proposal(const float* __restrict__ o, long long npts,
                                                     const int* __restrict__ idx, int n, int merge_k1,
                                                     const int* __restrict__ z, uint64_t seed, uint32_t t,
-                                                    unsigned char* __restrict__ side, double* __restrict__ sums) {
-  __shared__ double red[4][BLOCK];
+                                                    unsigned char* __restrict__ side, double* __restrict__ red) {
+  __shared__ double sh[4][BLOCK];
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (q < n && (unsigned long long)idx[q] < (unsigned long long)npts) {
@@ -262,14 +281,14 @@ __global__ __launch_bounds__(BLOCK) void k_proposal(const float* __restrict__ o,
     v[a ? 0 : 2] = lb;
     v[a ? 1 : 3] = l1b;
   }
-  for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = v[c];
+  for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = v[c];
   __syncthreads();
   for (int s = BLOCK / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s)
-      for (int c = 0; c < 4; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+      for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x < 4) atomicAdd(&sums[threadIdx.x], red[threadIdx.x][0]);
+  if (threadIdx.x < 4) red[(size_t)blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // Accepted learned split: side-A points of the set go to cluster k_new, every
@@ -477,16 +496,27 @@ hipError_t launch_out_layer(const float* H2, int n, const float* w3, const float
 }
 
 hipError_t launch_out_backward(const float* o, const float* y, const float* H2, int n, int npad, const float* w3,
-                               void* D2, void* D2t, float* gw3, float* gb3, double* loss, hipStream_t s) {
+                               void* D2, void* D2t, float* gw3, float* gb3, double* loss, double* red,
+                               hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_out_backward, dim3(cdiv(n, OB_ROWS)), dim3(H), 0, s, o, y, H2, n, npad, w3, (__bf16*)D2,
-                     (__bf16*)D2t, gw3, gb3, loss);
+  if (n > MLP_CHUNK || gb3 != gw3 + H) return hipErrorInvalidValue;  // red holds MLP_CHUNK / OB_ROWS rows
+  const int G = cdiv(n, OB_ROWS);
+  hipLaunchKernelGGL(k_out_backward, dim3(G), dim3(H), 0, s, o, y, H2, n, npad, w3, (__bf16*)D2, (__bf16*)D2t, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // gw3 and gb3 are adjacent in the parameter vector: columns 0 .. H of the rows, then the loss
+  hipLaunchKernelGGL(k_add_rows, dim3(1), dim3(H + 64), 0, s, red, G, H + 2, H + 1, gw3, loss);
   return hipGetLastError();
 }
 
-hipError_t launch_colsum(const void* A, int lda, int n, int ncol, float* out, hipStream_t s) {
+hipError_t launch_colsum(const void* A, int lda, int n, int ncol, float* out, double* red, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_colsum, dim3(n < 1024 ? n : 1024), dim3(H), 0, s, (const __bf16*)A, lda, n, ncol, out);
+  if (ncol > H) return hipErrorInvalidValue;
+  const int G = n < 1024 ? n : 1024;
+  hipLaunchKernelGGL(k_colsum, dim3(G), dim3(H), 0, s, (const __bf16*)A, lda, n, ncol, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_add_rows, dim3(1), dim3(H), 0, s, red, G, ncol, ncol, out, nullptr);
   return hipGetLastError();
 }
 
@@ -506,10 +536,10 @@ hipError_t launch_refresh_weights(const float* p, int F, int Fp, void* w1t, void
 
 hipError_t launch_features(const float* x, int d, long long npts, const int* idx, const int* cl, int n,
                            const float* frames, int m, int F, int Fp, void* X16, void* X16t, int npad, float* X32,
-                           hipStream_t s) {
+                           hipStream_t s, bool cl_by_point) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_features, dim3(cdiv(n, BLOCK)), dim3(BLOCK), 0, s, x, d, npts, idx, cl, n, frames, m, F, Fp,
-                     (__bf16*)X16, (__bf16*)X16t, npad, X32);
+  hipLaunchKernelGGL(k_features, dim3(cdiv(n, BLOCK)), dim3(BLOCK), 0, s, x, d, npts, idx, cl, cl_by_point ? 1 : 0, n,
+                     frames, m, F, Fp, (__bf16*)X16, (__bf16*)X16t, npad, X32);
   return hipGetLastError();
 }
 
@@ -521,17 +551,22 @@ hipError_t launch_convert(const float* X32, int n, int F, int Fp, void* X16, voi
 }
 
 hipError_t launch_targets(const int* idx, const int* cl, int n, const unsigned char* zsub, const int* flip, float* y,
-                          hipStream_t s) {
+                          hipStream_t s, bool cl_by_point) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_targets, dim3(cdiv(n, BLOCK)), dim3(BLOCK), 0, s, idx, cl, n, zsub, flip, y);
+  hipLaunchKernelGGL(k_targets, dim3(cdiv(n, BLOCK)), dim3(BLOCK), 0, s, idx, cl, cl_by_point ? 1 : 0, n, zsub, flip,
+                     y);
   return hipGetLastError();
 }
 
 hipError_t launch_proposal(const float* o, long long npts, const int* idx, int n, int merge_k1, const int* z,
-                           uint64_t seed, uint32_t t, unsigned char* side, double* sums, hipStream_t s) {
+                           uint64_t seed, uint32_t t, unsigned char* side, double* sums, double* red, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_proposal, dim3(cdiv(n, BLOCK)), dim3(BLOCK), 0, s, o, npts, idx, n, merge_k1, z, seed, t, side,
-                     sums);
+  if (n > MLP_CHUNK) return hipErrorInvalidValue;  // red holds MLP_CHUNK / BLOCK rows
+  const int G = cdiv(n, BLOCK);
+  hipLaunchKernelGGL(k_proposal, dim3(G), dim3(BLOCK), 0, s, o, npts, idx, n, merge_k1, z, seed, t, side, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_add_rows, dim3(1), dim3(64), 0, s, red, G, 4, 0, nullptr, sums);
   return hipGetLastError();
 }
 

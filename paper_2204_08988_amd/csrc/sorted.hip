@@ -94,20 +94,65 @@ __global__ __launch_bounds__(BLOCK) void k_scan_hist(const int* __restrict__ his
   }
 }
 
+// Stable scatter: within block b the rows of a cluster keep their index
+// order, so the sorted order (and every float64 sum taken over it) does not
+// depend on timing.  Wave w owns the contiguous quarter [begin + w q, begin +
+// (w + 1) q) of the block's range (q = per_block / 4, a multiple of 64): it
+// counts its rows per cluster (LDS integer atomics, exact), its cursor for
+// cluster k is the block's offset plus the counts of the waves before it, and
+// it then walks its quarter 64 rows at a time, ranking the lanes of each
+// cluster by their position in the wave (ballot).
 __global__ __launch_bounds__(BLOCK) void k_scatter_z(const int* __restrict__ z, long long n, long long per_block,
                                                      int K, const int* __restrict__ offs, int* __restrict__ perm,
                                                      int* __restrict__ zsort) {
-  extern __shared__ int cur[];
-  for (int k = threadIdx.x; k < K; k += BLOCK) cur[k] = offs[(size_t)blockIdx.x * K + k];
+  extern __shared__ int cur[];  // [4][K]
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int q = threadIdx.x; q < 4 * K; q += BLOCK) cur[q] = 0;
   __syncthreads();
   const long long begin = (long long)blockIdx.x * per_block;
   const long long end = begin + per_block < n ? begin + per_block : n;
-  for (long long i = begin + threadIdx.x; i < end; i += BLOCK) {
+  const long long quarter = per_block / 4;
+  const long long wb = begin + w * quarter;
+  const long long we = wb + quarter < end ? wb + quarter : end;
+  int* mine = cur + w * K;
+  for (long long i = wb + lane; i < we; i += 64) {
     const int zi = z[i];
-    if ((unsigned)zi < (unsigned)K) {
-      const int pos = atomicAdd(&cur[zi], 1);
-      perm[pos] = (int)i;
-      zsort[pos] = zi;
+    if ((unsigned)zi < (unsigned)K) atomicAdd(&mine[zi], 1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += BLOCK) {
+    int run = offs[(size_t)blockIdx.x * K + k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = cur[u * K + k];
+      cur[u * K + k] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (long long c0 = wb; c0 < we; c0 += 64) {
+    const long long i = c0 + lane;
+    const int zi = i < we ? z[i] : -1;
+    const bool v = (unsigned)zi < (unsigned)K;
+    unsigned long long pend = __ballot(v);
+    while (pend) {
+      const int l0 = __ffsll((long long)pend) - 1;
+      const int kk = __builtin_amdgcn_readlane(zi, l0);
+      const bool mk = v && zi == kk;
+      const unsigned long long m = __ballot(mk);
+      const int base = mine[kk];
+      if (mk) {
+        const int pos = base + __popcll(m & below);
+        perm[pos] = (int)i;
+        zsort[pos] = zi;
+      }
+      // every lane has read the cursor before it moves; the next reads see it
+      if (lane == l0) mine[kk] = base + __popcll(m);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      pend &= ~m;
     }
   }
 }
@@ -123,15 +168,21 @@ __host__ __device__ constexpr int items_per_lane(int D) {
 // (else read it).  Workgroup g walks the tiles [g tpw, (g + 1) tpw) of TR
 // sorted rows each (TR <= BLOCK: one row per lane).  Clusters are contiguous
 // in sorted order, so the lanes keep float64 accumulators of the current
-// cluster's two segments across tiles and flush them with global atomics only
-// when the cluster changes or the range ends.
+// cluster's two segments across tiles; each segment keeps the rows' sorted
+// order.  Slot mode (part != nullptr, cstart / ctot indexed by cluster -
+// kbase): a cluster inside the workgroup's rows is written to its final
+// place, the first and last clusters that reach beyond them to partial slots
+// 2 g, 2 g + 1 that k_sub_stats_fix adds in a fixed order.  Otherwise the
+// sums are added with global atomics when the cluster changes.
 template <int D, bool SAMPLE>
 __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x, int d, int TR, int tpw,
                                                      long long n_sorted, const int* __restrict__ perm,
                                                      const int* __restrict__ z, unsigned char* __restrict__ zsub,
                                                      const float* __restrict__ packed, int k_max, uint32_t t,
                                                      uint64_t seed, long long* __restrict__ counts,
-                                                     double* __restrict__ moments) {
+                                                     double* __restrict__ moments, const int* __restrict__ cstart,
+                                                     const int* __restrict__ ctot, int kbase,
+                                                     double* __restrict__ part) {
   constexpr int IPT = items_per_lane(D);
   extern __shared__ float lds[];
   const int tid = threadIdx.x;
@@ -142,9 +193,10 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
   int* order = rk + TR;                                    // [TR] (generic d) row of each sorted slot
   int* lcount = order + TR;                                // [2 TR]
   int* lstart = lcount + 2 * TR;                           // [2 TR]
-  int* lseg = lstart + 2 * TR;                             // [2 TR]
-  int* buf = lseg + 2 * TR;                                // [BLOCK]
-  float* dxc = reinterpret_cast<float*>(buf + BLOCK);      // [d][BLOCK] (generic d only)
+  int* rinfo = lstart + 2 * TR;                            // [2 TR]: run start row, right rows before it
+  int* buf = rinfo + 2 * TR;                               // [BLOCK]
+  int* rcl = buf + BLOCK;                                  // [TR] cluster of each run
+  float* dxc = reinterpret_cast<float*>(rcl + TR);         // [d][BLOCK] (generic d, SAMPLE only)
   const int S = gauss_rec_stride(d);
   const int E = d + d * (d + 1) / 2;
   // this lane's 2x2 work items: blocks (I, J), I <= J, of sum x x^T over the
@@ -171,11 +223,16 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
       iJ[j] = -2;
     }
   }
+  const long long tiles = (n_sorted + TR - 1) / TR;
+  const long long tile_beg = (long long)blockIdx.x * tpw;
+  const long long tile_end = tile_beg + tpw < tiles ? tile_beg + tpw : tiles;
+  const long long r_begin = tile_beg * TR;
+  const long long r_end = tile_end * TR < n_sorted ? tile_end * TR : n_sorted;
   // running sums of the current cluster's left (accL) and right (accR)
   // segments; indexed statically so they stay in registers
   double accL[IPT][4], accR[IPT][4];
   long long cntL = 0, cntR = 0;
-  int cur_k = -1;
+  int cur_k = -1, k_first = -1;
   auto zero_acc = [&]() {
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
@@ -184,32 +241,63 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
     }
     cntL = cntR = 0;
   };
-  auto flush_one = [&](double (&acc)[IPT][4], long long cnt, int seg) {
-    if (cnt == 0) return;
-    double* M = moments + (size_t)seg * E;
+  // atomic: added to M / C; else stored to M and C (or the slot's count Cd)
+  auto flush_one = [&](double (&acc)[IPT][4], long long cnt, double* M, long long* C, double* Cd, bool atomic) {
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
       const int I = iI[j], J = iJ[j];
       if (I < 0) continue;
       if (J == -2) {
-        if (2 * I < d) atomicAdd(&M[2 * I], acc[j][0]);
-        if (2 * I + 1 < d) atomicAdd(&M[2 * I + 1], acc[j][1]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          if (2 * I + u < d) {
+            if (atomic)
+              atomicAdd(&M[2 * I + u], acc[j][u]);
+            else
+              M[2 * I + u] = acc[j][u];
+          }
       } else {
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
           for (int v = 0; v < 2; ++v) {
             const int a = 2 * I + u, b = 2 * J + v;
-            if (a < d && b < d && a <= b) atomicAdd(&M[d + a * d - (a * (a - 1)) / 2 + (b - a)], acc[j][2 * u + v]);
+            if (a < d && b < d && a <= b) {
+              double* dst = &M[d + a * d - (a * (a - 1)) / 2 + (b - a)];
+              if (atomic)
+                atomicAdd(dst, acc[j][2 * u + v]);
+              else
+                *dst = acc[j][2 * u + v];
+            }
           }
       }
     }
-    if (tid == 0) atomicAdd((unsigned long long*)&counts[seg], (unsigned long long)cnt);
+    if (tid == 0) {
+      if (atomic)
+        atomicAdd((unsigned long long*)C, (unsigned long long)cnt);
+      else if (C)
+        *C = cnt;
+      else
+        *Cd = (double)cnt;
+    }
   };
   auto flush = [&]() {
     if (cur_k < 0) return;
-    flush_one(accL, cntL, 2 * cur_k);
-    flush_one(accR, cntR, 2 * cur_k + 1);
+    const int sL = 2 * cur_k, sR = sL + 1;
+    if (!part) {
+      if (cntL) flush_one(accL, cntL, moments + (size_t)sL * E, counts + sL, nullptr, true);
+      if (cntR) flush_one(accR, cntR, moments + (size_t)sR * E, counts + sR, nullptr, true);
+      return;
+    }
+    const long long cs = cstart[cur_k - kbase], ce = cs + ctot[cur_k - kbase];
+    if (cs >= r_begin && ce <= r_end) {
+      flush_one(accL, cntL, moments + (size_t)sL * E, counts + sL, nullptr, false);
+      flush_one(accR, cntR, moments + (size_t)sR * E, counts + sR, nullptr, false);
+    } else {
+      double* P = part + (size_t)(2 * blockIdx.x + (cur_k == k_first ? 0 : 1)) * 2 * (E + 1);
+      flush_one(accL, cntL, P + 1, nullptr, P, false);
+      flush_one(accR, cntR, P + (E + 1) + 1, nullptr, P + (E + 1), false);
+    }
   };
   auto accumulate = [&](double (&acc)[IPT][4], int st, int cnt) {
 #pragma unroll 4
@@ -234,9 +322,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
     }
   };
   zero_acc();
-  const long long tiles = (n_sorted + TR - 1) / TR;
-  const long long tile_end = ((long long)blockIdx.x + 1) * tpw < tiles ? ((long long)blockIdx.x + 1) * tpw : tiles;
-  for (long long tile = (long long)blockIdx.x * tpw; tile < tile_end; ++tile) {
+  for (long long tile = tile_beg; tile < tile_end; ++tile) {
     const long long tile0 = tile * TR;
     const int rows = (int)((n_sorted - tile0) < TR ? (n_sorted - tile0) : TR);
     const int r = tid;
@@ -294,30 +380,34 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
       zs = zsub[i] ? 1 : 0;
     }
     __syncthreads();
-    // ---- group rows by segment: run id of the cluster (rows are sorted by
-    // z), local id 2 run + zsub
+    // ---- group rows by segment: run of the cluster (rows are sorted by z),
+    // then the sub-label; one scan gives the run of each row (high half) and
+    // the right rows up to it (low half)
     const int flag = (valid && (r == 0 || rk[r] != rk[r - 1])) ? 1 : 0;
-    const int incl = block_inclusive_scan(flag, buf);
-    const int nl = 2 * buf[BLOCK - 1];
-    int lid = 0;
-    if (valid) {
-      lid = 2 * (incl - 1) + zs;
-      atomicAdd(&lcount[lid], 1);
-      lseg[lid] = 2 * k + zs;
+    const int sc = block_inclusive_scan((flag << 16) | zs, buf);
+    const int run = (sc >> 16) - 1, ones_ex = (sc & 0xFFFF) - zs;
+    const int nruns = buf[BLOCK - 1] >> 16;
+    const int lid = 2 * run + zs;
+    if (flag) {
+      rinfo[2 * run] = r;
+      rinfo[2 * run + 1] = ones_ex;
+      rcl[run] = k;
     }
+    if (valid) atomicAdd(&lcount[lid], 1);  // integer counts: exact in any order
     __syncthreads();
     if (tid == 0) {
       int a = 0;
-      for (int q = 0; q < nl; ++q) {
+      for (int q = 0; q < 2 * nruns; ++q) {
         lstart[q] = a;
         a += lcount[q];
       }
     }
     __syncthreads();
-    // slot within the segment (any order; the sums are float64): the high
-    // half of lcount serves as the cursor, the low half keeps the count
+    // slot within the segment: the row's rank among the run's rows of the same
+    // sub-label, so each segment keeps the sorted order
     if (valid) {
-      const int pos = lstart[lid] + atomicAdd(&lcount[lid], 0x10000) / 0x10000;
+      const int ones_run = ones_ex - rinfo[2 * run + 1];
+      const int pos = lstart[lid] + (zs ? ones_run : (r - rinfo[2 * run]) - ones_run);
       if constexpr (D > 0) {
         float* xr = xs + (size_t)pos * ld;
 #pragma unroll
@@ -328,27 +418,20 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
       }
     }
     __syncthreads();
-    for (int q = tid; q < nl; q += BLOCK) lcount[q] &= 0xFFFF;
-    __syncthreads();
-    // ---- phase B: accumulate each segment's rows into the running sums
-    for (int q = 0; q < nl; ++q) {
-      const int cnt = lcount[q];
-      if (cnt == 0) continue;
-      const int seg = lseg[q];
-      const int kq = seg >> 1, h = seg & 1;
+    // ---- phase B: every run in order into the running sums
+    for (int j = 0; j < nruns; ++j) {
+      const int kq = rcl[j];
       if (kq != cur_k) {
         flush();
         zero_acc();
+        if (cur_k < 0) k_first = kq;
         cur_k = kq;
       }
-      const int st = lstart[q];
-      if (h == 0) {
-        cntL += cnt;
-        accumulate(accL, st, cnt);
-      } else {
-        cntR += cnt;
-        accumulate(accR, st, cnt);
-      }
+      const int cl = lcount[2 * j], cr = lcount[2 * j + 1];
+      cntL += cl;
+      cntR += cr;
+      accumulate(accL, lstart[2 * j], cl);
+      accumulate(accR, lstart[2 * j + 1], cr);
     }
     __syncthreads();
   }
@@ -378,7 +461,8 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
                                                        const float* __restrict__ packed, int K, int k_max, uint32_t t,
                                                        uint64_t seed, long long* __restrict__ counts,
                                                        double* __restrict__ moments, const int* __restrict__ cstart,
-                                                       const int* __restrict__ ctot, double* __restrict__ part) {
+                                                       const int* __restrict__ ctot, int kbase,
+                                                       double* __restrict__ part) {
   constexpr int NB = (D + 15) / 16;  // 16-wide blocks of dimensions
   constexpr int NBLK = NB * (NB + 1) / 2;
   constexpr int LDW = D + 1;  // odd row stride
@@ -454,7 +538,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
       if (nR) flush_one(cR, sR, nR, moments + (size_t)(2 * cur_k + 1) * E, &counts[2 * cur_k + 1], nullptr, true);
       return;
     }
-    const long long cs = cstart[cur_k], ce = cs + ctot[cur_k];
+    const long long cs = cstart[cur_k - kbase], ce = cs + ctot[cur_k - kbase];
     if (cs >= w_begin && ce <= w_end) {
       // the whole cluster is this wave's: final values, both segments
       flush_one(cL, sL, nL, moments + (size_t)(2 * cur_k) * E, &counts[2 * cur_k], nullptr, false);
@@ -579,18 +663,21 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
   flush();
 }
 
-// Slot mode of k_sub_stats_w: the counts and moments of every cluster whose
-// rows span several waves are the sums of those waves' partial slots (2 g for
-// the wave's first cluster, 2 g + 1 for its last); empty clusters get zeros;
-// a cluster inside one wave was written by it.  Grid (entries / FIX_EN, K):
-// FIX_PH phases of threads take every FIX_PH-th slot of FIX_EN entries, and
-// their sums are added in a fixed order (the result does not depend on timing).
+// Slot mode of the sorted-order statistics kernels: the counts and moments of
+// every cluster whose rows span several row ranges (rpw rows each: a wave of
+// k_sub_stats_w, a workgroup of the other kernels) are the sums of those
+// ranges' partial slots (2 g for the range's first cluster, 2 g + 1 for its
+// last); empty clusters get zeros; a cluster inside one range was written by
+// it.  Grid (entries / FIX_EN, clusters): cluster kbase + blockIdx.y, whose
+// start and size are cstart / ctot[blockIdx.y].  FIX_PH phases of threads take
+// every FIX_PH-th slot of FIX_EN entries, and their sums are added in a fixed
+// order (the result does not depend on timing).
 constexpr int FIX_PH = 16, FIX_EN = 16;
 __global__ __launch_bounds__(FIX_PH * FIX_EN) void k_sub_stats_fix(int E, long long rpw, const int* __restrict__ cstart,
                                                                  const int* __restrict__ ctot,
                                                                  const double* __restrict__ part,
                                                                  long long* __restrict__ counts,
-                                                                 double* __restrict__ moments) {
+                                                                 double* __restrict__ moments, int kbase) {
   __shared__ double red[FIX_PH][FIX_EN];
   const int k = blockIdx.y;
   const int W = 2 * (E + 1);
@@ -598,7 +685,7 @@ __global__ __launch_bounds__(FIX_PH * FIX_EN) void k_sub_stats_fix(int E, long l
   const int e = blockIdx.x * FIX_EN + el;
   const long long cs = cstart[k], cnt = ctot[k];
   const long long ga = cnt > 0 ? cs / rpw : 0, gb = cnt > 0 ? (cs + cnt - 1) / rpw : -1;
-  if (cnt > 0 && ga == gb) return;  // written by the wave that holds it (uniform over the block)
+  if (cnt > 0 && ga == gb) return;  // written by the range that holds it (uniform over the block)
   double v = 0.0;
   if (e < W) {
 #pragma unroll 4
@@ -611,10 +698,11 @@ __global__ __launch_bounds__(FIX_PH * FIX_EN) void k_sub_stats_fix(int E, long l
   double sum = 0.0;
   for (int q = 0; q < FIX_PH; ++q) sum += red[q][el];
   const int h = e / (E + 1), f = e - h * (E + 1);
+  const size_t seg = 2 * ((size_t)k + kbase) + h;
   if (f == 0)
-    counts[2 * k + h] = (long long)sum;  // a sum of integer counts below 2^53: exact
+    counts[seg] = (long long)sum;  // a sum of integer counts below 2^53: exact
   else
-    moments[(size_t)(2 * k + h) * E + (f - 1)] = sum;
+    moments[seg * E + (f - 1)] = sum;
 }
 
 namespace {
@@ -644,7 +732,7 @@ int tile_rows(int d) {
 
 size_t sub_stats_lds(int d, int TR, bool generic) {
   const int dp = (d + 1) & ~1;
-  size_t b = (size_t)TR * (dp + 1) * sizeof(float) + (size_t)(2 * TR + 6 * TR + BLOCK) * sizeof(int);
+  size_t b = (size_t)TR * (dp + 1) * sizeof(float) + (size_t)(9 * TR + BLOCK) * sizeof(int);
   if (generic) b += (size_t)d * BLOCK * sizeof(float);
   return b;
 }
@@ -876,14 +964,20 @@ __device__ __forceinline__ void big_rows(f64x4 (&acc)[TPW], double (&sx)[D / 64]
 // sorted rows:
 //   (1) the tile's rows are gathered into LDS (16-byte row pieces);
 //   (2) thread r < BIG_ROWS reads row r's sub-label;
-//   (3) rows are grouped by segment (run of a cluster, sub-label);
+//   (3) rows are grouped by segment (run of a cluster, sub-label), each
+//       segment keeping the rows' sorted order (ranks from one block scan);
 //   (4) per segment, four rows at a time, v_mfma_f64_16x16x4_f64 adds
 //       X_I^T X_J to the upper 16 x 16 blocks (I, J) of sum x x^T: the left
 //       segment belongs to waves 0-3, the right to waves 4-7, and a wave owns
 //       blocks w, w + 4, ... (FP32 inputs are exact in FP64); from the same
 //       registers it also sums x over column blocks w, w + 4, ... in FP64.
-// Each wave carries its segment of the current cluster across tiles and
-// flushes it with global atomics when the cluster changes or the range ends.
+// Each wave carries its segment of the current cluster across tiles.  Slot
+// mode (part != nullptr): a cluster that lies inside the workgroup's rows is
+// written to its final place, the workgroup's first and last clusters that
+// reach beyond them to partial slots 2 g and 2 g + 1 ([2][1 + E] each) that
+// k_sub_stats_fix adds in a fixed order: no float atomics, so the sums do not
+// depend on timing.  cstart / ctot are indexed by cluster - kbase.  Otherwise
+// the segments are added to counts / moments with atomics.
 template <int D>
 __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __restrict__ x, long long n_sorted,
                                                                int tpb, const int* __restrict__ perm,
@@ -891,14 +985,18 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
                                                                const int* __restrict__ zrow,
                                                                const unsigned char* __restrict__ zsub,
                                                                long long* __restrict__ counts,
-                                                               double* __restrict__ moments) {
+                                                               double* __restrict__ moments,
+                                                               const int* __restrict__ cstart,
+                                                               const int* __restrict__ ctot, int kbase,
+                                                               double* __restrict__ part) {
   constexpr int LD = D + 1;  // odd row stride
   constexpr int NB = D / 16, NT = NB * (NB + 1) / 2, TPW = (NT + 3) / 4;
   constexpr int E = D + D * (D + 1) / 2;
   constexpr int SB = D / 64;  // column blocks of sum x per wave
   extern __shared__ float xs[];  // [BIG_ROWS + 1][LD], the last row zero
   __shared__ int order[BIG_ROWS], rk[BIG_ROWS], buf[BIG_THREADS];
-  __shared__ int lcount[2 * BIG_ROWS], lstart[2 * BIG_ROWS], lseg[2 * BIG_ROWS];
+  __shared__ int lcount[2 * BIG_ROWS], lstart[2 * BIG_ROWS];
+  __shared__ int rstart[BIG_ROWS], ostart[BIG_ROWS], rcl[BIG_ROWS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int side = wave >> 2, wq = wave & 3;  // segment (0 left, 1 right), quarter
   int bI[TPW], bJ[TPW];
@@ -916,10 +1014,15 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
       bJ[j] = a + u;
     }
   }
+  const long long tiles = (n_sorted + BIG_ROWS - 1) / BIG_ROWS;
+  const long long tb = (long long)blockIdx.x * tpb;
+  const long long te = tb + tpb < tiles ? tb + tpb : tiles;
+  const long long r_begin = tb * BIG_ROWS;
+  const long long r_end = te * BIG_ROWS < n_sorted ? te * BIG_ROWS : n_sorted;
   f64x4 acc[TPW];
   double sx[SB];
   long long cnt_seg = 0;
-  int cur_k = -1;
+  int cur_k = -1, k_first = -1;
   auto zero_acc = [&]() {
 #pragma unroll
     for (int j = 0; j < TPW; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -928,9 +1031,23 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
     cnt_seg = 0;
   };
   auto flush = [&]() {
-    if (cur_k < 0 || cnt_seg == 0) return;
+    if (cur_k < 0) return;
     const int seg = 2 * cur_k + side;
+    bool atomic = part == nullptr;
     double* M = moments + (size_t)seg * E;
+    long long* C = counts + seg;
+    double* Cd = nullptr;
+    if (atomic) {
+      if (cnt_seg == 0) return;
+    } else {
+      const long long cs = cstart[cur_k - kbase], ce = cs + ctot[cur_k - kbase];
+      if (!(cs >= r_begin && ce <= r_end)) {
+        double* P = part + ((size_t)(2 * blockIdx.x + (cur_k == k_first ? 0 : 1)) * 2 + side) * (E + 1);
+        Cd = P;
+        M = P + 1;
+        C = nullptr;
+      }
+    }
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       if (bI[j] < 0) continue;
@@ -938,7 +1055,13 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
       for (int e = 0; e < 4; ++e) {
         // accumulator element e of lane l is row l / 16 + 4 e, column l % 16
         const int a = 16 * bI[j] + (lane >> 4) + 4 * e, b = 16 * bJ[j] + (lane & 15);
-        if (a <= b) atomicAdd(&M[D + a * D - (a * (a - 1)) / 2 + (b - a)], acc[j][e]);
+        if (a <= b) {
+          double* dst = &M[D + a * D - (a * (a - 1)) / 2 + (b - a)];
+          if (atomic)
+            atomicAdd(dst, acc[j][e]);
+          else
+            *dst = acc[j][e];
+        }
       }
     }
 #pragma unroll
@@ -947,16 +1070,25 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
       double v = sx[j];
       v += __shfl_xor(v, 16);
       v += __shfl_xor(v, 32);
-      if (lane < 16) atomicAdd(&M[16 * (wq + 4 * j) + lane], v);
+      if (lane < 16) {
+        if (atomic)
+          atomicAdd(&M[16 * (wq + 4 * j) + lane], v);
+        else
+          M[16 * (wq + 4 * j) + lane] = v;
+      }
     }
-    if (wq == 0 && lane == 0) atomicAdd((unsigned long long*)&counts[seg], (unsigned long long)cnt_seg);
+    if (wq == 0 && lane == 0) {
+      if (atomic)
+        atomicAdd((unsigned long long*)C, (unsigned long long)cnt_seg);
+      else if (C)
+        *C = cnt_seg;
+      else
+        *Cd = (double)cnt_seg;
+    }
   };
   zero_acc();
   // row BIG_ROWS of the tile buffer stays zero (read by lanes past a segment)
   for (int c = tid; c < LD; c += BIG_THREADS) xs[BIG_ROWS * LD + c] = 0.0f;
-  const long long tiles = (n_sorted + BIG_ROWS - 1) / BIG_ROWS;
-  const long long tb = (long long)blockIdx.x * tpb;
-  const long long te = tb + tpb < tiles ? tb + tpb : tiles;
   for (long long tile = tb; tile < te; ++tile) {
     const long long base = tile * BIG_ROWS;
     const int rows = (int)(n_sorted - base < BIG_ROWS ? n_sorted - base : BIG_ROWS);
@@ -993,43 +1125,50 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
         dst[3] = v[j].w;
       }
     }
-    __syncthreads();
     // ---- (2) sub-label of row tid
     const int zs = valid && zsub[my_i] ? 1 : 0;
     // ---- (3) group rows by segment: run of the cluster (rows are sorted by
-    // z), then sub-label
+    // z), then sub-label.  One scan gives the run of each row (high half) and
+    // the right rows up to it (low half; both counts are <= BIG_ROWS)
     const int flag = (valid && (tid == 0 || rk[tid] != rk[tid - 1])) ? 1 : 0;
-    const int incl = block_inclusive_scan_big(flag, buf);
-    const int nl = 2 * buf[BIG_THREADS - 1];
-    int lid = 0;
-    if (valid) {
-      lid = 2 * (incl - 1) + zs;
-      atomicAdd(&lcount[lid], 1);
-      lseg[lid] = 2 * k + zs;
+    const int sc = block_inclusive_scan_big((flag << 16) | zs, buf);
+    const int run = (sc >> 16) - 1, ones_ex = (sc & 0xFFFF) - zs;
+    const int nruns = buf[BIG_THREADS - 1] >> 16;
+    if (flag) {
+      rstart[run] = tid;
+      ostart[run] = ones_ex;
+      rcl[run] = k;
     }
+    const int lid = 2 * run + zs;
+    if (valid) atomicAdd(&lcount[lid], 1);  // integer counts: exact in any order
     __syncthreads();
     if (tid == 0) {
       int a = 0;
-      for (int q = 0; q < nl; ++q) {
+      for (int q = 0; q < 2 * nruns; ++q) {
         lstart[q] = a;
         a += lcount[q];
       }
     }
     __syncthreads();
-    if (valid) order[lstart[lid] + atomicAdd(&lcount[lid], 0x10000) / 0x10000] = tid;
+    if (valid) {
+      // rank among the run's rows of the same sub-label, in sorted order
+      const int ones_run = ones_ex - ostart[run];
+      const int rank = zs ? ones_run : (tid - rstart[run]) - ones_run;
+      order[lstart[lid] + rank] = tid;
+    }
     __syncthreads();
-    for (int q = tid; q < nl; q += BIG_THREADS) lcount[q] &= 0xFFFF;
-    __syncthreads();
-    // ---- (4) this wave's segments: runs q with sub-label `side`
-    for (int q = side; q < nl; q += 2) {
-      const int cnt = lcount[q];
-      if (cnt == 0) continue;
-      const int kq = lseg[q] >> 1;
+    // ---- (4) every run, in order; this wave's side of it
+    for (int j = 0; j < nruns; ++j) {
+      const int kq = rcl[j];
       if (kq != cur_k) {
         flush();
         zero_acc();
+        if (cur_k < 0) k_first = kq;
         cur_k = kq;
       }
+      const int q = 2 * j + side;
+      const int cnt = lcount[q];
+      if (cnt == 0) continue;
       cnt_seg += cnt;
       const int st = lstart[q];
       // (the quarter as a compile-time constant: its blocks' operands come from registers)
@@ -1051,20 +1190,40 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
   flush();
 }
 
+// workgroups of the generic statistics kernel: about four per CU, fewer
+// above d = 64 (each range's partial slots hold 2 (1 + E) doubles per side)
+long long generic_groups(int d, long long n) {
+  const int TR = tile_rows(d);
+  const long long tiles = (n + TR - 1) / TR;
+  const long long cap = d <= 64 ? 1024 : 256;
+  const long long g = tiles < cap ? tiles : cap;
+  const long long tpw = g > 0 ? (tiles + g - 1) / g : 1;
+  return tiles > 0 ? (tiles + tpw - 1) / tpw : 0;
+}
+
 template <bool SAMPLE>
 hipError_t launch_sub_stats_t(int d, const float* x, long long n, const int* perm, const int* z, unsigned char* zsub,
                               const float* packed, int k_max, uint32_t t, uint64_t seed, long long* counts,
-                              double* moments, hipStream_t s) {
+                              double* moments, const int* cstart, const int* ctot, int kbase, int ncl, double* part,
+                              hipStream_t s) {
   const int TR = tile_rows(d);
-  // contiguous tile ranges, about four workgroups per CU
+  static bool attr_set = false;
+  if (!attr_set) {  // above d = 64 the per-lane centred columns take more than 64 KB
+    hipError_t e = hipFuncSetAttribute((const void*)k_sub_stats<0, SAMPLE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  // contiguous tile ranges
   const long long tiles = (n + TR - 1) / TR;
-  long long g = tiles < 1024 ? tiles : 1024;
+  const long long g = generic_groups(d, n);
   const int tpw = (int)((tiles + g - 1) / g);
   const unsigned grid = (unsigned)((tiles + tpw - 1) / tpw);
 #define DPMM_SUB_CASE(DD)                                                                                 \
   case DD:                                                                                                \
     hipLaunchKernelGGL((k_sub_stats<DD, SAMPLE>), dim3(grid), dim3(BLOCK), sub_stats_lds(d, TR, false), s, x, d, \
-                       TR, tpw, n, perm, z, zsub, packed, k_max, t, seed, counts, moments);              \
+                       TR, tpw, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, cstart, ctot, kbase,   \
+                       part);                                                                             \
     break;
   switch (d) {
     DPMM_SUB_CASE(8)
@@ -1073,9 +1232,15 @@ hipError_t launch_sub_stats_t(int d, const float* x, long long n, const int* per
     DPMM_SUB_CASE(64)
     default:
       hipLaunchKernelGGL((k_sub_stats<0, SAMPLE>), dim3(grid), dim3(BLOCK), sub_stats_lds(d, TR, SAMPLE), s, x, d,
-                         TR, tpw, n, perm, z, zsub, packed, k_max, t, seed, counts, moments);
+                         TR, tpw, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, cstart, ctot, kbase,
+                         part);
   }
 #undef DPMM_SUB_CASE
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !part) return e;
+  const int E = d + d * (d + 1) / 2;
+  hipLaunchKernelGGL(k_sub_stats_fix, dim3((2 * (E + 1) + FIX_EN - 1) / FIX_EN, ncl), dim3(FIX_PH * FIX_EN),
+                     0, s, E, (long long)tpw * TR, cstart, ctot, part, counts, moments, kbase);
   return hipGetLastError();
 }
 
@@ -1100,21 +1265,42 @@ hipError_t launch_sort_by_z(const int* z, long long n, int K, int G, long long p
   }
   hipLaunchKernelGGL(k_scan_hist, dim3(K), dim3(BLOCK), 0, s, hist, G, K, tot, offs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scatter_z, dim3(G), dim3(BLOCK), (size_t)K * sizeof(int), s, z, n, per_block, K, offs, perm,
+  // per_block is a multiple of BLOCK: each wave's quarter is whole 64-row chunks
+  if (per_block % BLOCK != 0 || 4 * (size_t)K * sizeof(int) > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scatter_z, dim3(G), dim3(BLOCK), 4 * (size_t)K * sizeof(int), s, z, n, per_block, K, offs, perm,
                      zsort);
   return hipGetLastError();
 }
 
 namespace {
 
-// The statistics kernels over rows perm[0, n) (point indices below npts),
-// accumulating into counts / moments (which the caller has zeroed).
+// rows per wave of k_sub_stats_w (whole 64-row chunks, at most SUBW_WAVES waves)
+long long subw_rpw(long long n) {
+  long long rpw = (n + SUBW_WAVES - 1) / SUBW_WAVES;
+  return ((rpw + 63) / 64) * 64;
+}
+
+// tiles per workgroup of k_sub_stats_big (at most 512 workgroups at d = 64, 256 at d = 128)
+int big_tpb(int d, long long n) {
+  const long long tiles = (n + BIG_ROWS - 1) / BIG_ROWS;
+  const long long gmax = d == 128 ? 256 : 512;
+  const long long g = tiles < gmax ? tiles : gmax;
+  return g > 0 ? (int)((tiles + g - 1) / g) : 1;
+}
+
+// The statistics kernels over rows perm[0, n) (point indices below npts).
+// Slot mode (part != nullptr): cstart / ctot give the sorted start and size
+// of clusters kbase ... kbase + ncl - 1 (indexed from 0), every one of their
+// entries is written and nothing is added with atomics; otherwise the kernels
+// add into counts / moments (which the caller has zeroed).
 hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts, long long n, const int* perm,
                              const int* z, const int* zrow, unsigned char* zsub, const float* packed, int K, int k_max,
                              uint32_t t, uint64_t seed, long long* counts, double* moments, const int* cstart,
-                             const int* ctot, double* part, hipStream_t s) {
+                             const int* ctot, int kbase, int ncl, double* part, hipStream_t s) {
   hipError_t e;
   if (n == 0) return hipSuccess;
+  const int E = d + d * (d + 1) / 2;
+  const dim3 fix_grid((2 * (E + 1) + FIX_EN - 1) / FIX_EN, ncl);
   if (sample && (d == 32 || d == 64 || d == 128)) {
     // the sub-labels in their own pass on the FP32 matrix cores, then the statistics; at
     // d = 128 two workgroups per CU (the staged records take 66 KB), each on a contiguous
@@ -1149,9 +1335,7 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
   }
   if (d == 64 || d == 128) {
     const long long tiles = (n + BIG_ROWS - 1) / BIG_ROWS;
-    const long long gmax = d == 128 ? 256 : 512;
-    const long long g = tiles < gmax ? tiles : gmax;
-    const int tpb = (int)((tiles + g - 1) / g);
+    const int tpb = big_tpb(d, n);
     const unsigned grid = (unsigned)((tiles + tpb - 1) / tpb);
     const size_t lds = (size_t)(BIG_ROWS + 1) * (d + 1) * sizeof(float);  // above 64 KB: raise the limit once
     static bool attr_set = false;
@@ -1165,17 +1349,18 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
     }
     if (d == 64)
       hipLaunchKernelGGL(k_sub_stats_big<64>, dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z, zrow, zsub,
-                         counts, moments);
+                         counts, moments, cstart, ctot, kbase, part);
     else
       hipLaunchKernelGGL(k_sub_stats_big<128>, dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z, zrow, zsub,
-                         counts, moments);
+                         counts, moments, cstart, ctot, kbase, part);
+    if ((e = hipGetLastError()) != hipSuccess || !part) return e;
+    hipLaunchKernelGGL(k_sub_stats_fix, fix_grid, dim3(FIX_PH * FIX_EN), 0, s, E, (long long)tpb * BIG_ROWS, cstart,
+                       ctot, part, counts, moments, kbase);
     return hipGetLastError();
   }
   if (d == 8 || d == 16 || d == 32) {
     // about eight waves per CU, each on a contiguous range of whole 64-row chunks
-    const long long waves = SUBW_WAVES;
-    long long rpw = (n + waves - 1) / waves;
-    rpw = ((rpw + 63) / 64) * 64;
+    const long long rpw = subw_rpw(n);
     const long long nw = (n + rpw - 1) / rpw;
     const unsigned grid = (unsigned)((nw + 3) / 4);
     const size_t lds = (size_t)4 * 64 * (d + 1) * sizeof(float);
@@ -1183,10 +1368,10 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
   case DD:                                                                                                      \
     if (sample)                                                                                                 \
       hipLaunchKernelGGL((k_sub_stats_w<DD, true>), dim3(grid), dim3(BLOCK), lds, s, x, npts, n, rpw, perm, z,  \
-                         zrow, zsub, packed, K, k_max, t, seed, counts, moments, cstart, ctot, part);           \
+                         zrow, zsub, packed, K, k_max, t, seed, counts, moments, cstart, ctot, kbase, part);    \
     else                                                                                                        \
       hipLaunchKernelGGL((k_sub_stats_w<DD, false>), dim3(grid), dim3(BLOCK), lds, s, x, npts, n, rpw, perm, z, \
-                         zrow, zsub, packed, K, k_max, t, seed, counts, moments, cstart, ctot, part);           \
+                         zrow, zsub, packed, K, k_max, t, seed, counts, moments, cstart, ctot, kbase, part);    \
     break;
     switch (d) {
       DPMM_SUBW_CASE(8)
@@ -1194,26 +1379,46 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
       DPMM_SUBW_CASE(32)
     }
 #undef DPMM_SUBW_CASE
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (part) {
-      const int E = d + d * (d + 1) / 2;
-      hipLaunchKernelGGL(k_sub_stats_fix, dim3((2 * (E + 1) + FIX_EN - 1) / FIX_EN, K), dim3(FIX_PH * FIX_EN), 0, s, E,
-                         rpw, cstart, ctot, part, counts, moments);
-      return hipGetLastError();
-    }
-    return hipSuccess;
+    if ((e = hipGetLastError()) != hipSuccess || !part) return e;
+    hipLaunchKernelGGL(k_sub_stats_fix, fix_grid, dim3(FIX_PH * FIX_EN), 0, s, E, rpw, cstart, ctot, part, counts,
+                       moments, kbase);
+    return hipGetLastError();
   }
-  return sample ? launch_sub_stats_t<true>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, s)
-                : launch_sub_stats_t<false>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, s);
+  return sample ? launch_sub_stats_t<true>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, cstart,
+                                           ctot, kbase, ncl, part, s)
+                : launch_sub_stats_t<false>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, cstart,
+                                            ctot, kbase, ncl, part, s);
 }
 
 }  // namespace
 
-bool sub_stats_slot_mode(int d) { return d == 8 || d == 16 || d == 32; }
-
-size_t sub_stats_part_doubles(int d) {
+size_t sub_stats_part_doubles(int d, long long n) {
   const int E = d + d * (d + 1) / 2;
-  return sub_stats_slot_mode(d) ? (size_t)2 * SUBW_WAVES * 2 * (E + 1) : 0;
+  long long ranges;
+  if (n <= 0) return 0;
+  if (d == 8 || d == 16 || d == 32) {
+    const long long rpw = subw_rpw(n);
+    ranges = (n + rpw - 1) / rpw;
+  } else if (d == 64 || d == 128) {
+    const long long tiles = (n + BIG_ROWS - 1) / BIG_ROWS;
+    const int tpb = big_tpb(d, n);
+    ranges = (tiles + tpb - 1) / tpb;
+  } else {
+    ranges = generic_groups(d, n);
+  }
+  return (size_t)2 * ranges * 2 * (E + 1);
+}
+
+size_t sub_stats_part_doubles_max(int d) {
+  const int E = d + d * (d + 1) / 2;
+  long long ranges;
+  if (d == 8 || d == 16 || d == 32)
+    ranges = SUBW_WAVES;
+  else if (d == 64 || d == 128)
+    ranges = d == 128 ? 256 : 512;
+  else
+    ranges = d <= 64 ? 1024 : 256;
+  return (size_t)2 * ranges * 2 * (E + 1);
 }
 
 hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, const int* perm, const int* z,
@@ -1221,15 +1426,15 @@ hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, con
                             uint64_t seed, long long* counts, double* moments, const int* cstart, const int* ctot,
                             double* part, hipStream_t s) {
   const int E = d + d * (d + 1) / 2;
-  if (n > 0 && part && sub_stats_slot_mode(d))  // every cluster's entries are written: no zeroing
+  if (n > 0 && part)  // slot mode: every cluster's entries are written, no zeroing
     return sub_stats_kernels(d, sample, x, n, n, perm, z, zrow, zsub, packed, K, k_max, t, seed, counts, moments,
-                             cstart, ctot, part, s);
+                             cstart, ctot, 0, K, part, s);
   hipError_t e = launch_zero64(counts, (size_t)2 * K, s);
   if (e != hipSuccess) return e;
   e = launch_zero64(moments, (size_t)2 * K * E, s);
   if (e != hipSuccess) return e;
   return sub_stats_kernels(d, sample, x, n, n, perm, z, zrow, zsub, packed, K, k_max, t, seed, counts, moments,
-                           nullptr, nullptr, nullptr, s);
+                           nullptr, nullptr, 0, K, nullptr, s);
 }
 
 bool partition_stats_supported(int d) { return d == 8 || d == 16 || d == 32 || d == 64 || d == 128; }
@@ -1238,19 +1443,23 @@ bool partition_stats_supported(int d) { return d == 8 || d == 16 || d == 32 || d
 // plays the sub-label, so the sorted-order kernels leave the statistics of
 // side h in segment 2 k1 + h of the arrays they are given.  Shifting the base
 // pointers by slot - 2 k1 segments puts them in counts[slot + h] and
-// moments[(slot + h) E] and touches nothing else.
+// moments[(slot + h) E] and touches nothing else.  cspan: device int[2] =
+// {0, nsel} (the one cluster's sorted start and size); part: partial slots
+// (sub_stats_part_doubles(d, nsel) doubles), summed in a fixed order.
 hipError_t launch_partition_stats(int d, const float* x, long long npts, const int* idx, long long nsel,
                                   const int* z, int k1, int K, const unsigned char* side, int slot,
-                                  long long* counts, double* moments, hipStream_t s) {
-  if (!partition_stats_supported(d) || k1 < 0 || k1 >= K || slot < 2 * k1) return hipErrorInvalidValue;
+                                  long long* counts, double* moments, const int* cspan, double* part, hipStream_t s) {
+  if (!partition_stats_supported(d) || k1 < 0 || k1 >= K || slot < 2 * k1 || !cspan || !part)
+    return hipErrorInvalidValue;
   const int E = d + d * (d + 1) / 2;
-  hipError_t e = launch_zero64(counts + slot, 2, s);
-  if (e != hipSuccess) return e;
-  e = launch_zero64(moments + (size_t)slot * E, (size_t)2 * E, s);
-  if (e != hipSuccess) return e;
   const long long shift = (long long)slot - 2 * k1;
+  if (nsel == 0) {
+    hipError_t e = launch_zero64(counts + slot, 2, s);
+    if (e != hipSuccess) return e;
+    return launch_zero64(moments + (size_t)slot * E, (size_t)2 * E, s);
+  }
   return sub_stats_kernels(d, false, x, npts, nsel, idx, z, nullptr, const_cast<unsigned char*>(side), nullptr, K, 0,
-                           0, 0, counts + shift, moments + shift * E, nullptr, nullptr, nullptr, s);
+                           0, 0, counts + shift, moments + shift * E, cspan, cspan + 1, k1, 1, part, s);
 }
 
 }  // namespace dpmm

@@ -50,6 +50,13 @@ __global__ void k_zero64(unsigned long long* p, size_t n) {
     p[i] = 0ull;
 }
 
+__global__ void k_set_pair(int* p, int a, int b) {
+  if (threadIdx.x == 0) {
+    p[0] = a;
+    p[1] = b;
+  }
+}
+
 __global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, int d, NiwPriorDev prior,
                               double logdet_psi, const long long* __restrict__ counts,
                               const double* __restrict__ moments, double* __restrict__ scratch,
@@ -289,6 +296,11 @@ int grid_for(long long n) {
 }
 
 }  // namespace
+
+hipError_t launch_set_pair(int* p, int a, int b, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_pair, dim3(1), dim3(64), 0, s, p, a, b);
+  return hipGetLastError();
+}
 
 hipError_t launch_zero64(void* p, size_t n_words, hipStream_t s) {
   if (n_words == 0) return hipSuccess;

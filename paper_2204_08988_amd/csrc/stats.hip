@@ -5,15 +5,14 @@
 // n, sum x (d) and the upper triangle of sum x x^T (d(d+1)/2, row-major),
 // stored as [2K][d + d(d+1)/2] doubles plus a separate int64 count array.
 // A product of two float32 values is exact in float64, so the only rounding
-// is that of the float64 sums.
+// is that of the float64 sums, and every sum here is taken in a fixed order:
+// the same input gives the same bits whatever the timing of the waves.
 //
-// Two Gaussian kernels:
-//   small d  : lanes over points, per-workgroup LDS accumulators updated with
-//              LDS atomics, flushed to global memory once per workgroup;
-//   any d    : per chunk of up to 8192 points a local counting sort by segment in
-//              LDS, then lanes over statistic entries accumulate each
-//              segment's run from LDS tiles of 64 rows, one global atomic per
-//              entry and segment and chunk.
+// Gaussian, d <= 4 (d >= 5 and the large-K case take the cluster-sorted
+// kernels): each lane owns float64 accumulators of every segment in LDS and
+// adds its own points (a fixed grid-stride assignment); the workgroup then
+// adds its lanes by a fixed tree and writes one partial row, and a second
+// kernel adds the rows in workgroup order.
 // Multinomial: lanes over points, uint32 LDS accumulators (at most 65536
 // points per workgroup, so count entries below 65536 cannot overflow), int64
 // flush; all integer, so the result is exact and independent of the order.
@@ -24,149 +23,78 @@ namespace dpmm {
 namespace {
 
 constexpr int BLOCK = 256;
-constexpr int CHUNK_MAX = 8192;
 constexpr int LDS_MAX = 160 * 1024;
-constexpr int TILE = 64;
 constexpr int LDS_BUDGET = 64 * 1024;
 
-__device__ __forceinline__ int tri_index(int a, int b, int d) {
-  return a * d - (a * (a - 1)) / 2 + (b - a);
-}
-
-template <int D>
-__global__ __launch_bounds__(BLOCK) void k_stats_gauss_lds(const float* __restrict__ x, long long n,
-                                                           const int* __restrict__ z,
-                                                           const unsigned char* __restrict__ zsub, int K,
-                                                           long long* __restrict__ counts,
-                                                           double* __restrict__ moments) {
-  constexpr int E = D + D * (D + 1) / 2;
-  extern __shared__ double lds_d[];
-  double* acc = lds_d;                                        // [2K][E]
-  unsigned int* cnt = reinterpret_cast<unsigned int*>(acc + 2 * K * E);  // [2K]
-  for (int idx = threadIdx.x; idx < 2 * K * E; idx += BLOCK) acc[idx] = 0.0;
-  for (int idx = threadIdx.x; idx < 2 * K; idx += BLOCK) cnt[idx] = 0u;
-  __syncthreads();
-  const long long stride_pts = (long long)gridDim.x * BLOCK;
-  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride_pts) {
-    const int zi = z[i];
-    const int zs = zsub[i];
-    if ((unsigned)zi >= (unsigned)K || zs > 1) continue;  // labels outside the table are ignored
-    const int s = 2 * zi + zs;
-    float xv[D];
+// Per-lane float64 accumulators [2K][1 + E][L] (entry-major, so the lanes of
+// one access hit distinct banks); lane l of workgroup g adds the points
+// i = (g L + l) + j G L in increasing j, eight loads in flight.  Then a fixed
+// tree over the lanes, and the workgroup's row part[g][2K (1 + E)] (entry 0 of
+// a segment is its count).
+template <int D, int L>
+__global__ __launch_bounds__(L) void k_stats_small(const float* __restrict__ x, long long n,
+                                                   const int* __restrict__ z, const unsigned char* __restrict__ zsub,
+                                                   int K, double* __restrict__ part) {
+  constexpr int E1 = 1 + D + D * (D + 1) / 2;
+  constexpr int U = 8;
+  extern __shared__ double acc[];
+  const int NE = 2 * K * E1;
+  const int lane = threadIdx.x;
+  for (int e = 0; e < NE; ++e) acc[(size_t)e * L + lane] = 0.0;
+  const long long stride = (long long)gridDim.x * L;
+  for (long long i0 = (long long)blockIdx.x * L + lane; i0 < n; i0 += U * stride) {
+    int seg[U];
+    float xv[U][D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) xv[j] = x[i * D + j];
-    atomicAdd(&cnt[s], 1u);
-    double* a = acc + s * E;
+    for (int u = 0; u < U; ++u) {
+      const long long i = i0 + u * stride;
+      seg[u] = -1;
 #pragma unroll
-    for (int j = 0; j < D; ++j) atomicAdd(&a[j], (double)xv[j]);
+      for (int j = 0; j < D; ++j) xv[u][j] = 0.0f;
+      if (i < n) {
+        const int zi = z[i], zs = zsub[i];
+        if ((unsigned)zi < (unsigned)K && zs <= 1) seg[u] = 2 * zi + zs;
 #pragma unroll
-    for (int p = 0; p < D; ++p)
+        for (int j = 0; j < D; ++j) xv[u][j] = x[i * D + j];
+      }
+    }
 #pragma unroll
-      for (int q = p; q < D; ++q) atomicAdd(&a[D + tri_index(p, q, D)], (double)xv[p] * (double)xv[q]);
+    for (int u = 0; u < U; ++u) {
+      if (seg[u] < 0) continue;
+      double* a = acc + (size_t)seg[u] * E1 * L + lane;
+      a[0] += 1.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) a[(size_t)(1 + j) * L] += (double)xv[u][j];
+      int e = 1 + D;
+#pragma unroll
+      for (int p = 0; p < D; ++p)
+#pragma unroll
+        for (int q = p; q < D; ++q, ++e) a[(size_t)e * L] += (double)xv[u][p] * (double)xv[u][q];
+    }
+  }
+#pragma unroll
+  for (int h = L / 2; h > 0; h >>= 1) {
+    __syncthreads();
+    if (lane < h)
+      for (int e = 0; e < NE; ++e) acc[(size_t)e * L + lane] += acc[(size_t)e * L + lane + h];
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < 2 * K * E; idx += BLOCK)
-    if (acc[idx] != 0.0) atomicAdd(&moments[idx], acc[idx]);
-  for (int idx = threadIdx.x; idx < 2 * K; idx += BLOCK)
-    if (cnt[idx]) atomicAdd((unsigned long long*)&counts[idx], (unsigned long long)cnt[idx]);
+  for (int e = lane; e < NE; e += L) part[(size_t)blockIdx.x * NE + e] = acc[(size_t)e * L];
 }
 
-// Entries per lane for d <= 128: (128 + 128*129/2) / 256 rounded up.
-constexpr int EPT = 33;
-
-__global__ __launch_bounds__(BLOCK) void k_stats_gauss_sorted(const float* __restrict__ x, long long n, int d,
-                                                              int chunk, const int* __restrict__ z,
-                                                              const unsigned char* __restrict__ zsub, int K,
-                                                              long long* __restrict__ counts,
-                                                              double* __restrict__ moments) {
-  extern __shared__ int lds_i[];
-  const int G = 2 * K;
-  int* cnt = lds_i;            // [G]
-  int* off = cnt + G;          // [G]
-  int* cur = off + G;          // [G]
-  int* perm = cur + G;         // [CHUNK]
-  float* xs = reinterpret_cast<float*>(perm + chunk);  // [TILE][d]
-  const int E = d + d * (d + 1) / 2;
-  const int tid = threadIdx.x;
-  // decode this lane's entries: e < d -> sum x_a; else upper-triangle (a, b)
-  short ea[EPT], eb[EPT];
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) {
-    const int e = tid + j * BLOCK;
-    ea[j] = -1;
-    eb[j] = -1;
-    if (e < d) {
-      ea[j] = (short)e;
-    } else if (e < E) {
-      int u = e - d, a = 0;
-      while (u >= d - a) {
-        u -= d - a;
-        ++a;
-      }
-      ea[j] = (short)a;
-      eb[j] = (short)(a + u);
-    }
-  }
-  for (long long base = (long long)blockIdx.x * chunk; base < n; base += (long long)gridDim.x * chunk) {
-    const int m = (int)((n - base) < chunk ? (n - base) : chunk);
-    for (int g = tid; g < G; g += BLOCK) cnt[g] = 0;
-    __syncthreads();
-    for (int p = tid; p < m; p += BLOCK) {
-      const int zi = z[base + p], zs = zsub[base + p];
-      if ((unsigned)zi < (unsigned)K && zs <= 1) atomicAdd(&cnt[2 * zi + zs], 1);
-    }
-    __syncthreads();
-    if (tid == 0) {
-      int acc = 0;
-      for (int g = 0; g < G; ++g) {
-        off[g] = acc;
-        cur[g] = acc;
-        acc += cnt[g];
-      }
-    }
-    __syncthreads();
-    for (int p = tid; p < m; p += BLOCK) {
-      const int zi = z[base + p], zs = zsub[base + p];
-      if ((unsigned)zi < (unsigned)K && zs <= 1) perm[atomicAdd(&cur[2 * zi + zs], 1)] = p;
-    }
-    __syncthreads();
-    for (int s = 0; s < G; ++s) {
-      const int cs = cnt[s];
-      if (cs == 0) continue;
-      double acc[EPT];
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) acc[j] = 0.0;
-      const int beg = off[s];
-      for (int r0 = 0; r0 < cs; r0 += TILE) {
-        const int tn = (cs - r0) < TILE ? (cs - r0) : TILE;
-        for (int idx = tid; idx < tn * d; idx += BLOCK) {
-          const int pr = idx / d, col = idx - pr * d;
-          xs[idx] = x[(base + perm[beg + r0 + pr]) * d + col];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-          const int a = ea[j], b = eb[j];
-          if (a < 0) continue;
-          double sacc = 0.0;
-          if (b < 0) {
-            for (int p = 0; p < tn; ++p) sacc += (double)xs[p * d + a];
-          } else {
-            for (int p = 0; p < tn; ++p) sacc += (double)xs[p * d + a] * (double)xs[p * d + b];
-          }
-          acc[j] += sacc;
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        const int e = tid + j * BLOCK;
-        if (e < E) atomicAdd(&moments[(size_t)s * E + e], acc[j]);
-      }
-      if (tid == 0) atomicAdd((unsigned long long*)&counts[s], (unsigned long long)cs);
-    }
-    __syncthreads();
-  }
+// counts[s] and moments[s][.] from the G partial rows, added in row order.
+__global__ void k_stats_small_reduce(const double* __restrict__ part, int G, int K, int E,
+                                     long long* __restrict__ counts, double* __restrict__ moments) {
+  const int NE = 2 * K * (E + 1);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NE) return;
+  double sum = 0.0;
+  for (int g = 0; g < G; ++g) sum += part[(size_t)g * NE + e];
+  const int sgm = e / (E + 1), f = e - sgm * (E + 1);
+  if (f == 0)
+    counts[sgm] = (long long)sum;  // a sum of integer counts below 2^53: exact
+  else
+    moments[(size_t)sgm * E + (f - 1)] = sum;
 }
 
 // Count sums of the multinomial segments in LDS (uint32 partial sums).  A wave
@@ -248,39 +176,67 @@ int stats_grid(long long n, long long per_block) {
 
 }  // namespace
 
+int stats_small_lanes(int d, int K) {
+  if (d < 1 || d > 4 || K < 1) return 0;
+  const size_t ne = (size_t)2 * K * (1 + d + d * (d + 1) / 2);
+  for (int L = 256; L >= 64; L /= 2)
+    if (ne * L * sizeof(double) <= (size_t)LDS_MAX) return L;
+  return 0;
+}
+
+size_t stats_small_part_doubles(int d, int K) {
+  const int L = stats_small_lanes(d, K);
+  if (!L) return 0;
+  return (size_t)(STATS_SMALL_LANES / L) * 2 * K * (1 + d + d * (d + 1) / 2);
+}
+
 hipError_t launch_stats_gauss(int d, const float* x, long long n, const int* z, const unsigned char* zsub,
-                              int K, long long* counts, double* moments, hipStream_t s) {
+                              int K, long long* counts, double* moments, double* part, hipStream_t s) {
   const int E = d + d * (d + 1) / 2;
-  hipError_t err = launch_zero64(counts, (size_t)2 * K, s);
-  if (err != hipSuccess) return err;
-  err = launch_zero64(moments, (size_t)2 * K * E, s);
-  if (err != hipSuccess) return err;
-  if (n == 0) return hipSuccess;
-  const size_t lds_small = (size_t)2 * K * E * sizeof(double) + (size_t)2 * K * sizeof(unsigned);
-  if (d <= 4 && lds_small <= LDS_BUDGET) {
-    const int g = stats_grid(n, (long long)BLOCK * 16);
-#define DPMM_STATS_CASE(DD)                                                                          \
-  case DD:                                                                                           \
-    hipLaunchKernelGGL(k_stats_gauss_lds<DD>, dim3(g), dim3(BLOCK), lds_small, s, x, n, z, zsub, K,  \
-                       counts, moments);                                                             \
-    break;
-    switch (d) {
-      DPMM_STATS_CASE(1)
-      DPMM_STATS_CASE(2)
-      DPMM_STATS_CASE(3)
-      DPMM_STATS_CASE(4)
-    }
-#undef DPMM_STATS_CASE
-    return hipGetLastError();
+  const int L = stats_small_lanes(d, K);
+  if (!L || !part) return hipErrorInvalidValue;
+  if (n == 0) {
+    hipError_t err = launch_zero64(counts, (size_t)2 * K, s);
+    if (err != hipSuccess) return err;
+    return launch_zero64(moments, (size_t)2 * K * E, s);
   }
-  // chunk of points sorted in LDS: as large as CHUNK_MAX allows within the LDS limit
-  const long long fixed = (long long)3 * 2 * K * sizeof(int) + (long long)TILE * d * sizeof(float);
-  long long chunk = (LDS_MAX - fixed) / (long long)sizeof(int);
-  chunk = chunk > CHUNK_MAX ? CHUNK_MAX : (chunk / BLOCK) * BLOCK;
-  if (chunk < BLOCK) return hipErrorInvalidValue;
-  const size_t lds = (size_t)fixed + (size_t)chunk * sizeof(int);
-  hipLaunchKernelGGL(k_stats_gauss_sorted, dim3(stats_grid(n, chunk)), dim3(BLOCK), lds, s, x, n, d, (int)chunk,
-                     z, zsub, K, counts, moments);
+  // STATS_SMALL_LANES lanes in all: one resident workgroup per CU at L = 256
+  const int G = STATS_SMALL_LANES / L;
+  const size_t lds = (size_t)2 * K * (E + 1) * L * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    const void* fns[] = {
+        (const void*)k_stats_small<1, 256>, (const void*)k_stats_small<1, 128>, (const void*)k_stats_small<1, 64>,
+        (const void*)k_stats_small<2, 256>, (const void*)k_stats_small<2, 128>, (const void*)k_stats_small<2, 64>,
+        (const void*)k_stats_small<3, 256>, (const void*)k_stats_small<3, 128>, (const void*)k_stats_small<3, 64>,
+        (const void*)k_stats_small<4, 256>, (const void*)k_stats_small<4, 128>, (const void*)k_stats_small<4, 64>};
+    for (const void* f : fns) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_MAX);
+      if (e != hipSuccess) return e;
+    }
+    attr_set = true;
+  }
+#define DPMM_SMALL_CASE(DD)                                                                                        \
+  case DD:                                                                                                         \
+    if (L == 256)                                                                                                  \
+      hipLaunchKernelGGL((k_stats_small<DD, 256>), dim3(G), dim3(256), lds, s, x, n, z, zsub, K, part);            \
+    else if (L == 128)                                                                                             \
+      hipLaunchKernelGGL((k_stats_small<DD, 128>), dim3(G), dim3(128), lds, s, x, n, z, zsub, K, part);            \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_stats_small<DD, 64>), dim3(G), dim3(64), lds, s, x, n, z, zsub, K, part);              \
+    break;
+  switch (d) {
+    DPMM_SMALL_CASE(1)
+    DPMM_SMALL_CASE(2)
+    DPMM_SMALL_CASE(3)
+    DPMM_SMALL_CASE(4)
+  }
+#undef DPMM_SMALL_CASE
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const int NE = 2 * K * (E + 1);
+  hipLaunchKernelGGL(k_stats_small_reduce, dim3((NE + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, part, G, K, E, counts,
+                     moments);
   return hipGetLastError();
 }
 

@@ -239,3 +239,19 @@ class Sampler:
         self._check(self._L.dpmm_mlp_train(self._ctx, _tptr(x), x.shape[0], _tptr(z), _tptr(zsub), int(steps),
                                            int(batch), float(lr), ctypes.byref(loss)))
         return loss.value
+
+    def mlp_training_set(self, x, z, zsub):
+        """(features float32 [rows][F], targets float32 [rows], point indices
+        int32 [rows]) of the rows mlp_train draws its batches from."""
+        n_rows = ctypes.c_int64()
+        self._check(self._L.dpmm_mlp_training_set(self._ctx, _tptr(x), x.shape[0], _tptr(z), _tptr(zsub), None, None,
+                                                  None, 0, ctypes.byref(n_rows)))
+        r = n_rows.value
+        F = 2 * self.learned
+        feats = self.torch.empty((r, F), dtype=self.torch.float32, device=x.device)
+        y = self.torch.empty(r, dtype=self.torch.float32, device=x.device)
+        idx = self.torch.empty(r, dtype=self.torch.int32, device=x.device)
+        if r:
+            self._check(self._L.dpmm_mlp_training_set(self._ctx, _tptr(x), x.shape[0], _tptr(z), _tptr(zsub),
+                                                      _tptr(feats), _tptr(y), _tptr(idx), r, ctypes.byref(n_rows)))
+        return feats, y, idx

@@ -30,7 +30,8 @@ def _wishart_params(K, d, seed, mean_scale=5.0):
 
 
 @pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
-@pytest.mark.parametrize("d,K,n,scale", [(32, 20, 20000, 5.0), (32, 3, 4097, 5.0), (64, 8, 6000, 5.0),
+@pytest.mark.parametrize("d,K,n,scale", [(32, 20, 20000, 5.0), (32, 3, 4097, 5.0), (32, 40, 8000, 5.0),
+                                         (64, 8, 6000, 5.0),
                                          (64, 7, 5000, 5.0), (64, 1, 333, 5.0), (128, 6, 3000, 5.0),
                                          (128, 1, 257, 5.0), (128, 5, 2000, 0.4)])
 def test_bf16_labels_meet_fp32_rule(precision, d, K, n, scale):
@@ -54,6 +55,49 @@ def test_bf16_labels_meet_fp32_rule(precision, d, K, n, scale):
         # the sorted statistics pass used the label pass's histograms
         counts = S.get_stats()[:, :, 0].sum(axis=1)
         assert np.array_equal(counts, np.bincount(z.cpu().numpy(), minlength=K))
+    S.close()
+
+
+def _cond_params(K, d, seed, cond, mean_scale):
+    """Covariances Q diag(lambda) Q^T, eigenvalues log-uniform in
+    [cond^-1/2, cond^1/2] with both ends present (condition number `cond`)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    mu = g.normal(0, mean_scale, size=(K, 3, d))
+    mu[:, 1:] = mu[:, :1] + g.normal(0, 0.3, size=(K, 2, d))
+    sigma = np.empty((K, 3, d, d))
+    for k in range(K):
+        for c in range(3):
+            q, _ = np.linalg.qr(g.standard_normal((d, d)))
+            lam = np.exp(g.uniform(-0.5, 0.5, size=d) * np.log(cond))
+            lam[0], lam[1] = np.sqrt(cond), 1.0 / np.sqrt(cond)
+            sigma[k, c] = (q * lam) @ q.T
+            sigma[k, c] = 0.5 * (sigma[k, c] + sigma[k, c].T)
+    return sampler.Params(np.log(g.dirichlet(np.ones(K))), np.log(g.dirichlet(np.ones(2), size=K)), mu=mu,
+                          sigma=sigma)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("d,K,n", [(32, 10, 6000), (64, 6, 4000), (128, 4, 2000)])
+def test_bf16_ill_conditioned_covariances(precision, d, K, n):
+    """Condition number 1e6: whitener rows span three orders of magnitude, so
+    the BF16 rounding of the centred points is amplified along the weak
+    directions; the labels must still meet the FP32 comparison rule."""
+    import torch
+    from paper_2204_08988_amd.sampler import Sampler
+    seed = 4200 + d + K
+    params = _cond_params(K, d, seed, 1e6, 3.0)
+    x = pu.gauss_points(params, n, seed + 1)
+    S = Sampler("gaussian", d, K + 2, 2.0, seed, m=np.zeros(d), psi=np.eye(d), precision=precision)
+    S.set_params(params.log_pi, params.log_pisub, pu.comp_array(params))
+    xt = torch.from_numpy(x).cuda()
+    model = sampler.Model("gaussian", 2.0, niw.NIWPrior(1.0, np.zeros(d), d + 3, np.eye(d)), seed=seed)
+    lc, ls = sampler.loglik(model, x.astype(np.float64), params)
+    Mc, Ms = pu.gauss_scale(x, params)
+    for t in (2, 7):
+        z, zs = S.sample_labels(xt, t)
+        bad_c, bad_s, tie_c, tie_s = pu.label_mismatches(seed, t, z.cpu().numpy(), zs.cpu().numpy(), lc, ls, Mc, Ms)
+        assert bad_c.size == 0, (bad_c[:10], tie_c)
+        assert bad_s.size == 0, (bad_s[:10], tie_s)
     S.close()
 
 

@@ -21,9 +21,12 @@ def _gauss_sampler(d, k_max, seed, **kw):
                    m=np.zeros(d), psi=np.eye(d), **kw)
 
 
+# the last two put more than 2^21 points through the d <= 4 label kernel, whose
+# 8192 x 256 lanes then each take two or more points of the grid-stride loop
 GAUSS_CASES = [(1, 1, 777), (2, 6, 10000), (3, 4, 5000), (8, 12, 4099), (5, 7, 2049),
                (16, 9, 2000), (32, 20, 3001), (2, 70, 1500), (12, 3, 1300), (8, 300, 5000),
-               (64, 5, 700), (33, 4, 900), (128, 3, 300), (128, 6, 140000), (32, 20, 200003)]
+               (64, 5, 700), (33, 4, 900), (128, 3, 300), (128, 6, 140000), (32, 20, 200003),
+               (2, 6, 2_500_001), (3, 5, 2_300_000)]
 
 
 def _check_stats(got, x, z, zs, K, d):
@@ -192,7 +195,7 @@ def test_gauss_log_marginals_across_dimensions(d):
 def test_gauss_chain_matches_oracle_then_converges():
     torch = _torch()
     from paper_2204_08988_amd import datagen
-    x, lab = datagen.workload("gauss_d2", 1, n=3000)
+    x, lab = datagen.workload("gauss_d2", 1)  # the configuration's N = 10 000
     d = 2
     m = x.mean(0).astype(np.float64)
     seed = 1
