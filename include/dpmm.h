@@ -200,6 +200,23 @@ dpmm_status dpmm_sample_labels(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t
 dpmm_status dpmm_suffstats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z,
                            const uint8_t* zsub);
 
+/* dpmm_suffstats without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid it).  The same kernels and the same results as dpmm_suffstats
+ * (bit for bit), but their scratch (sort tables, permutation, partial sums)
+ * comes from a static device array of DPMM_STATIC_SCRATCH_MIB MiB that each
+ * GPU holds for the life of the process.  A call needs, at the context's
+ * current K: nothing for the multinomial family; 8 (2 K (2 + d + d(d+1)/2))
+ * 65536 / L bytes (L = 256, 128 or 64 lanes, the most whose accumulators fit
+ * in LDS) for the Gaussian family with d <= 4; else about 8 n bytes for the
+ * sort plus the partial sums (2 ranges x 2 (1 + d + d(d+1)/2) doubles, at
+ * most 2048 ranges).  A call that needs more than the array returns
+ * DPMM_E_CAPACITY (its message gives the size) before touching the device.
+ * All calls on one GPU share the array: calls that overlap on one GPU race. */
+#define DPMM_STATIC_SCRATCH_MIB 128
+dpmm_status dpmm_suffstats_static(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z,
+                                  const uint8_t* zsub);
+
 /* Steps (a)-(d) of Sec. 4.1 from the context's statistics, in float64 on the
  * device: (pi_1..pi_K, rest) ~ Dir(N_1..N_K, alpha); (pi-bar_kl, pi-bar_kr) ~
  * Dir(N_kl + alpha/2, N_kr + alpha/2); component parameters from their

@@ -24,7 +24,7 @@ EXPORTS = [
     "dpmm_get_stats", "dpmm_loglik", "dpmm_sample_labels", "dpmm_suffstats", "dpmm_sample_params",
     "dpmm_split_merge", "dpmm_step", "dpmm_mlp_n_params", "dpmm_mlp_set_weights", "dpmm_mlp_get_weights",
     "dpmm_mlp_forward", "dpmm_mlp_grad", "dpmm_mlp_adam_step", "dpmm_set_features", "dpmm_learned_move",
-    "dpmm_mlp_train", "dpmm_mlp_training_set",
+    "dpmm_mlp_train", "dpmm_mlp_training_set", "dpmm_suffstats_static",
 ]
 
 
@@ -93,6 +93,7 @@ def lib():
         "dpmm_loglik": ([vp, vp, i64, vp], i32),
         "dpmm_sample_labels": ([vp, vp, i64, u32, vp, vp], i32),
         "dpmm_suffstats": ([vp, vp, i64, vp, vp], i32),
+        "dpmm_suffstats_static": ([vp, vp, i64, vp, vp], i32),
         "dpmm_sample_params": ([vp, u32], i32),
         "dpmm_split_merge": ([vp, vp, i64, u32, vp, vp, ctypes.POINTER(IterInfo)], i32),
         "dpmm_step": ([vp, vp, i64, u32, vp, vp, ctypes.POINTER(IterInfo)], i32),

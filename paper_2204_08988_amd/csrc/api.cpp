@@ -107,40 +107,64 @@ dpmm_status ensure_part(dpmm_ctx* ctx, int64_t n) {
   return DPMM_OK;
 }
 
-// statistics over the cluster-sorted order; with sample = true also draws zsub
-dpmm_status sorted_pass(dpmm_ctx* ctx, const void* x, int64_t n, bool labels_done_hist, bool sample, uint32_t t,
-                        const int32_t* z, uint8_t* zsub, int G, long long per_block) {
-  DPMM_TRY(ensure_perm(ctx, n));
-  DPMM_TRY(ensure_part(ctx, n));
-  DPMM_HIP(ctx, launch_sort_by_z(z, n, ctx->K, G, per_block, labels_done_hist, ctx->d_hist, ctx->d_tot, ctx->d_offs,
-                                 ctx->d_perm, ctx->d_zsort, ctx->stream), "sort by cluster");
+// statistics over the cluster-sorted order with the given scratch; with
+// sample = true also draws zsub
+dpmm_status sorted_pass_with(dpmm_ctx* ctx, const void* x, int64_t n, bool labels_done_hist, bool sample, uint32_t t,
+                             const int32_t* z, uint8_t* zsub, int G, long long per_block, const StatsBufs& b) {
+  DPMM_HIP(ctx, launch_sort_by_z(z, n, ctx->K, G, per_block, labels_done_hist, b.hist, b.tot, b.offs, b.perm, b.zsort,
+                                 ctx->stream), "sort by cluster");
   if (ctx->timing) DPMM_HIP(ctx, hipEventRecord(ctx->ev[3], ctx->stream), "event");
-  DPMM_HIP(ctx, launch_sub_stats(ctx->d, sample, (const float*)x, n, ctx->d_perm, z, ctx->d_zsort, zsub, ctx->d_packed,
-                                 ctx->K, ctx->cfg.k_max, t, ctx->cfg.seed, ctx->d_counts, ctx->d_moments, ctx->d_offs,
-                                 ctx->d_tot, ctx->d_part, ctx->stream),
+  DPMM_HIP(ctx, launch_sub_stats(ctx->d, sample, (const float*)x, n, b.perm, z, b.zsort, zsub, ctx->d_packed, ctx->K,
+                                 ctx->cfg.k_max, t, ctx->cfg.seed, ctx->d_counts, ctx->d_moments, b.offs, b.tot, b.part,
+                                 ctx->stream),
            "sub-label / statistics kernel");
   ctx->have_stats = true;
   return DPMM_OK;
 }
 
-dpmm_status launch_stats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub) {
+StatsBufs ctx_bufs(dpmm_ctx* ctx) {
+  return StatsBufs{ctx->d_hist, ctx->d_offs, ctx->d_tot, ctx->d_perm, ctx->d_zsort, ctx->d_part, ctx->d_spart};
+}
+
+// statistics over the cluster-sorted order; with sample = true also draws zsub
+dpmm_status sorted_pass(dpmm_ctx* ctx, const void* x, int64_t n, bool labels_done_hist, bool sample, uint32_t t,
+                        const int32_t* z, uint8_t* zsub, int G, long long per_block) {
+  DPMM_TRY(ensure_perm(ctx, n));
+  DPMM_TRY(ensure_part(ctx, n));
+  return sorted_pass_with(ctx, x, n, labels_done_hist, sample, t, z, zsub, G, per_block, ctx_bufs(ctx));
+}
+
+bool stats_sorted(const dpmm_ctx* ctx) {
+  return ctx->gaussian() && (ctx->sorted_path() || !stats_small_lanes(ctx->d, ctx->K));
+}
+
+dpmm_status stats_with(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub,
+                       const StatsBufs& b) {
   hipError_t e;
   // Gaussian: per-lane accumulators for d <= 4 while they fit in LDS, else
   // the cluster-sorted kernels (both take their sums in a fixed order)
-  if (ctx->gaussian() && (ctx->sorted_path() || !stats_small_lanes(ctx->d, ctx->K))) {
+  if (stats_sorted(ctx)) {
     int G;
     long long per;
     sorted_plan(n, ctx->K, ctx->hist_cap, &G, &per);
-    return sorted_pass(ctx, x, n, false, false, 0, z, const_cast<uint8_t*>(zsub), G, per);
+    return sorted_pass_with(ctx, x, n, false, false, 0, z, const_cast<uint8_t*>(zsub), G, per, b);
   }
   if (ctx->gaussian())
-    e = launch_stats_gauss(ctx->d, (const float*)x, n, z, zsub, ctx->K, ctx->d_counts, ctx->d_moments, ctx->d_spart,
+    e = launch_stats_gauss(ctx->d, (const float*)x, n, z, zsub, ctx->K, ctx->d_counts, ctx->d_moments, b.spart,
                            ctx->stream);
   else
     e = launch_stats_mult(ctx->d, (const int*)x, n, z, zsub, ctx->K, ctx->d_counts, ctx->d_sums, ctx->stream);
   DPMM_HIP(ctx, e, "statistics kernel");
   ctx->have_stats = true;
   return DPMM_OK;
+}
+
+dpmm_status launch_stats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub) {
+  if (stats_sorted(ctx)) {
+    DPMM_TRY(ensure_perm(ctx, n));
+    DPMM_TRY(ensure_part(ctx, n));
+  }
+  return stats_with(ctx, x, n, z, zsub, ctx_bufs(ctx));
 }
 
 // capacity of the item lists and their pinned staging (synchronises when it grows)
@@ -357,6 +381,11 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
   ctx->stream = (hipStream_t)hip_stream;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return bad(DPMM_E_DEVICE, "no HIP device");
+  if (hipGetDevice(&ctx->device) != hipSuccess) return bad(DPMM_E_DEVICE, "no current HIP device");
+  if (static_scratch_init(ctx.get()) != DPMM_OK) {
+    g_create_error = ctx->err;
+    return DPMM_E_DEVICE;
+  }
   const int km = cfg->k_max;
   dpmm_ctx* c = ctx.get();
   auto chk = [&](hipError_t e) { return e == hipSuccess; };

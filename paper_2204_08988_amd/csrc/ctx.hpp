@@ -34,6 +34,7 @@ struct dpmm_ctx {
   std::vector<double> m, psi, beta, lgamma_beta;
   double logdet_psi = 0.0, beta_sum = 0.0, lgamma_beta_sum = 0.0;
   hipStream_t stream = nullptr;
+  int device = 0;  // the HIP device current at dpmm_create
   int K = 0;
   std::vector<int> age;
   bool have_params = false;
@@ -141,11 +142,25 @@ struct dpmm_ctx {
 
 namespace dpmm::host {
 
+// device scratch of the statistics kernels: sort tables (hist, offs [G][K],
+// tot [K + 2]), permutation and sorted labels [n], partial slots of the
+// sorted-order kernels, per-workgroup rows of the d <= 4 kernel
+struct StatsBufs {
+  int *hist, *offs, *tot, *perm, *zsort;
+  double *part, *spart;
+};
+
 inline int tri_index(int a, int b, int d) { return a * d - (a * (a - 1)) / 2 + (b - a); }
 dpmm_status check_n(dpmm_ctx* ctx, const void* x, int64_t n);
 NiwPriorDev prior_dev(dpmm_ctx* ctx);
 dpmm_status launch_stats(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub);
 dpmm_status ensure_part(dpmm_ctx* ctx, int64_t n);
+// the statistics with the scratch b; whether they take the cluster-sorted kernels
+dpmm_status stats_with(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub,
+                       const StatsBufs& b);
+bool stats_sorted(const dpmm_ctx* ctx);
+// static_scratch.cpp: resolve this device's static scratch (dpmm_create)
+dpmm_status static_scratch_init(dpmm_ctx* ctx);
 // log marginal likelihoods of segment unions, read back (synchronises);
 // *flag_out (optional) receives the device error flag
 dpmm_status logml(dpmm_ctx* ctx, const std::vector<LogmlItem>& items, std::vector<double>& out,
