@@ -1,19 +1,29 @@
 """Throughput of the DPMM sub-cluster sampler hot path on one MI355X.
 
 A step is one full sampler iteration through the C ABI (dpmm_step: FP64
-parameter draws, the label/sub-label kernel, the statistics kernel, split /
-merge bookkeeping and relabelling) over the whole data set, resident in HBM.
+parameter draws, the cluster draw, the sort by cluster, the sub-label draw and
+the statistics, split / merge bookkeeping and relabelling) over the whole data
+set, resident in HBM before the clock starts.
 
-Workload: the Gaussian precision-form configuration, N = 1e6 points, d = 32,
-20 true clusters (means N(0, 25 I), covariances Wishart(d + 2, I/d), weights
-Dirichlet(1)).  `value` is the BF16 matrix-core form by default; the FP32 and
-bf16x3 forms are timed beside it.  Before the warm-up each chain is run until
-its cluster count has settled, so the timed steps score the converged K.
+Headline workload: the largest configuration, gauss_d128 -- N = 1e7 points,
+d = 128, 100 true clusters (means N(0, 9 I), covariances Wishart(d + 2, I/d),
+weights Dirichlet(1)), cluster scoring in BF16 on the matrix cores with the
+FP32 guard, sub-labels FP32, statistics and parameters FP64.  The chain
+starts at its converged state (the generating labels, random sub-labels,
+every cluster old enough to split or merge); the warm-up steps let the
+sub-clusters settle and every timed step is a full iteration.
 
-Prints one JSON line: metric (point-cluster evaluations per second: N (K + 2)
-scores per step), iterations per second, the label kernel's roofline figures
-from HIP events recorded on the sampler's stream, and the FP64 oracle's rate
-on a bounded sample on the host cores (rank 0, one GPU only).
+Prints one JSON line: `value` = point-cluster evaluations per second over the
+whole step (N (K + 2) scores per iteration), iterations per second, the
+roofline of the dominant kernel (the d = 128 BF16 cluster draw, timed by HIP
+events around its own dispatch on the sampler's stream), the other
+configurations (gauss_d32, mult_v100, the d = 2 label step at N = 1e8, the
+d = 2 chain at N = 1e4) as extra keys, and the FP64 oracle's label step on a
+bounded sample on the host cores (all cores and one core).
+
+Other modes: --label-step WORKLOAD (label step at a workload's generating
+mixture), --learned-ab (time to the log-posterior plateau, learned proposal
+vs plain, over several seeds).
 """
 import argparse
 import json
@@ -26,19 +36,19 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "gauss_d32"
 SEED = 1
 ALPHA = 10.0
+PEAK_HBM = 8.0e12          # bytes/s
 PEAK_FP32_VALU = 78.6e12   # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (non-packed FP32)
 PEAK_BF16_MFMA = 2.5e15    # dense BF16 matrix-core peak
 PEAK_FP32_MFMA = 157.3e12  # dense FP32 matrix-core peak
 PEAK_FP64_MFMA = 78.6e12   # dense FP64 matrix-core peak
-# HBM bytes per step of the cluster-draw kernel and of the sub-label +
-# statistics kernels at this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# scaled by a device copy of known size (profiles/traffic_gauss_d32_n1e6.md);
-# None once a kernel changes
-MEASURED_TRAFFIC = {"k_label_gauss_mfma32<false,false>": 133.3e6,
-                    "k_sub_labels_mfma<32>+k_sub_stats_w<32,false>": 304.7e6}
+HEADLINE = "gauss_d128"
+HEADLINE_KERNEL = "k_label_gauss_mfma_w32<128,false,false>"
+# HBM bytes per launch of the headline kernel at the headline workload, from
+# rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a copy of known size; None
+# until they are taken for the current kernel
+MEASURED_TRAFFIC = {HEADLINE_KERNEL: None}
 
 
 def flops_per_eval(d):
@@ -46,61 +56,41 @@ def flops_per_eval(d):
     return d * (d + 1) + 2 * d
 
 
-def cpu_baseline(x, z, zs, K, d, budget_s=12.0):
-    """Time the FP64 oracle's full iteration on a bounded sample of the data."""
-    from oracle import niw, sampler
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
-    n_s = 50_000
-    xs = x[:n_s].astype(np.float64)
-    model = sampler.Model("gaussian", ALPHA, niw.NIWPrior(1.0, x.mean(0).astype(np.float64), d + 3.0, np.eye(d)),
-                          seed=SEED, burn_out=5)
-    zz = z[:n_s].astype(np.int64)
-    zzs = zs[:n_s].astype(np.int64)
-    used = np.unique(zz)
-    remap = np.full(K, -1)
-    remap[used] = np.arange(used.size)
-    state = sampler.State(int(used.size), remap[zz], zzs, np.full(used.size, 100, dtype=np.int64))
-    evals = 0
-    t0 = time.perf_counter()
-    t = 10_000
-    while True:
-        k_now = state.K
-        state, info = sampler.step(model, xs, state, t)
-        evals += n_s * (k_now + 2)
-        t += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    el = time.perf_counter() - t0
-    return {"value": evals / el, "unit": "point-cluster evals/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"full FP64 oracle iterations on the first {n_s} points of the workload "
-                      f"({t - 10_000} iterations, {el:.1f} s)"}
-
-
-def run_form(torch, x, n, d, m, precision, steps, warmup, k_true):
-    """Converge the chain, then time `steps` full iterations of one precision form."""
+def _sampler(family, d, k_max, m, precision="fp32", burn_out=5, learned=0, seed=SEED):
     from paper_2204_08988_amd.sampler import Sampler
-    S = Sampler("gaussian", d, 128, ALPHA, SEED, kappa=1.0, nu=d + 3.0, m=m, psi=np.eye(d), burn_out=5,
-                precision=precision)
-    z, zs = S.init_labels(n)
+    if family == "gaussian":
+        return Sampler("gaussian", d, k_max, ALPHA, seed, kappa=1.0, nu=d + 3.0, m=m, psi=np.eye(d),
+                       burn_out=burn_out, precision=precision, learned=learned)
+    return Sampler("multinomial", d, k_max, ALPHA, seed, beta=np.ones(d), burn_out=burn_out)
+
+
+def converged_chain(torch, name, n, precision, steps, warmup, seed=SEED):
+    """Full iterations from the converged state of a workload: labels = the
+    generating labels, sub-labels random, ages at burn_out.  Returns the
+    timing record and the final labels."""
+    from paper_2204_08988_amd import datagen
+    spec = datagen.WORKLOADS[name]
+    gauss = isinstance(spec, datagen.GaussianSpec)
+    x_np, labels = datagen.workload(name, seed, n)
+    n, d = x_np.shape
+    labels = np.unique(labels, return_inverse=True)[1]  # the occupied clusters, renumbered
+    K = int(labels.max()) + 1
+    m = x_np.mean(0).astype(np.float64) if gauss else None
+    x = torch.from_numpy(x_np).cuda()
+    del x_np
+    burn = 5
+    S = _sampler("gaussian" if gauss else "multinomial", d, 2 * K + 16, m, precision, burn_out=burn, seed=seed)
+    z = torch.from_numpy(labels.astype(np.int32)).cuda()
+    zs = torch.from_numpy((np.random.Generator(np.random.PCG64(seed + 7)).integers(0, 2, n)).astype(np.uint8)).cuda()
+    S.set_state(K, [burn] * K)
     t = 1
-    ks = []
-    for _ in range(400):
-        info = S.step(x, t, z, zs)
-        t += 1
-        ks.append(info["K"])
-        if len(ks) > 30 and len(set(ks[-15:])) == 1 and info["K"] >= k_true // 2:
-            break
     for _ in range(warmup):
         S.step(x, t, z, zs)
         t += 1
     torch.cuda.synchronize()
-    evals = 0
     ms = {"params": 0.0, "labels": 0.0, "sort": 0.0, "stats": 0.0, "splitmerge": 0.0}
     kernel_ms = 0.0
+    evals = 0
     k_sum = 0
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -112,102 +102,221 @@ def run_form(torch, x, n, d, m, precision, steps, warmup, k_true):
             ms[key] += info["ms_" + key]
         kernel_ms += info["ms_label_kernel"]
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    k_mean = k_sum / steps
-    res = {
-        "precision": precision,
-        "value": evals / elapsed,
-        "ms_per_step": 1e3 * elapsed / steps,
-        "iters_per_s": steps / elapsed,
-        "k_mean": k_mean,
-        "phase_ms": {key: v / steps for key, v in ms.items()},
-        "label_kernel_ms": kernel_ms / steps,
-        "stats_kernel_ms": ms["stats"] / steps,
-        "label_evals_per_s": n * k_mean / (ms["labels"] / steps / 1e3),
-    }
-    return S, z, zs, res
+    el = time.perf_counter() - t0
+    from paper_2204_08988_amd import _lib
+    rec = {"n": n, "d": d, "k_true": K, "k_mean": k_sum / steps, "value": evals / el, "ms_per_step": 1e3 * el / steps,
+           "iters_per_s": steps / el, "phase_ms": {k: v / steps for k, v in ms.items()},
+           "label_kernel_ms": kernel_ms / steps,
+           "label_evals_per_s": n * (k_sum / steps) / (ms["labels"] / steps / 1e3),
+           "nmi": _lib.nmi(labels, z.cpu().numpy())}
+    S.close()
+    del x
+    torch.cuda.empty_cache()
+    return rec
 
 
-AB_WORKLOAD = "gauss_d64"
+def mfma_roofline(rec, d, kernel):
+    """The BF16 cluster draw: algorithmic flops N K (d(d+1) + 2d) per launch
+    over the launch's own duration."""
+    flops = rec["n"] * rec["k_mean"] * flops_per_eval(d)
+    s = rec["label_kernel_ms"] / 1e3
+    return {"bound": "mfma", "achieved": flops / s / 1e12, "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
+            "frac": flops / s / PEAK_BF16_MFMA, "traffic": MEASURED_TRAFFIC.get(kernel), "kernel": kernel,
+            "kernel_ms": rec["label_kernel_ms"], "algorithmic_flops_per_eval": flops_per_eval(d),
+            "evals_per_launch": rec["n"] * rec["k_mean"]}
 
 
-def label_step(args):
+def label_step_run(torch, name, n, precision, steps, warmup):
     """Label-step throughput at a workload's true mixture: the statistics come
     from the generating labels, nothing splits or merges (burn_out beyond the
     run), and each timed iteration redraws the parameters and the labels."""
-    import torch
     from paper_2204_08988_amd import datagen
-    from paper_2204_08988_amd.sampler import Sampler
-    name = args.label_step
     spec = datagen.WORKLOADS[name]
     gauss = isinstance(spec, datagen.GaussianSpec)
-    n = int(float(args.n)) if args.n else None
     x_np, labels = datagen.workload(name, 5, n)
     n, d = x_np.shape
+    labels = np.unique(labels, return_inverse=True)[1]  # the occupied clusters, renumbered
     K = int(labels.max()) + 1
     x = torch.from_numpy(x_np).cuda()
     del x_np
-    prec = args.precision if gauss and d in (32, 64, 128) else "fp32"  # matrix-core forms: d = 32, 64, 128
-    if gauss:
-        S = Sampler("gaussian", d, max(2 * K, 16), ALPHA, SEED, kappa=1.0, nu=d + 3.0, m=np.zeros(d), psi=np.eye(d),
-                    burn_out=10 ** 9, precision=prec)
-    else:
-        S = Sampler("multinomial", d, max(2 * K, 16), ALPHA, SEED, beta=np.ones(d), burn_out=10 ** 9)
+    prec = precision if gauss and d in (32, 64, 128) else "fp32"
+    S = _sampler("gaussian" if gauss else "multinomial", d, max(2 * K, 16), np.zeros(d), prec, burn_out=10 ** 9)
     z = torch.from_numpy(labels.astype(np.int32)).cuda()
     zs = torch.from_numpy((np.arange(n) % 2).astype(np.uint8)).cuda()
     S.set_state(K, [0] * K)
     S.suffstats(x, z, zs)
     ms = {"params": 0.0, "labels": 0.0, "sort": 0.0, "stats": 0.0, "splitmerge": 0.0}
     kernel_ms = 0.0
-    for t in range(1, args.warmup + 1):
+    for t in range(1, warmup + 1):
         S.step(x, t, z, zs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for t in range(args.warmup + 1, args.warmup + args.steps + 1):
+    for t in range(warmup + 1, warmup + steps + 1):
         info = S.step(x, t, z, zs)
         for key in ms:
             ms[key] += info["ms_" + key]
         kernel_ms += info["ms_label_kernel"]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    ms = {k: v / args.steps for k, v in ms.items()}
-    kernel_ms /= args.steps
-    lab_s = ms["labels"] / 1e3
-    evals = n * K / lab_s  # the whole cluster-draw phase
-    # the roofline of the main cluster-draw kernel alone (events around its launch)
+    S.close()
+    del x
+    torch.cuda.empty_cache()
+    ms = {k: v / steps for k, v in ms.items()}
+    kernel_ms /= steps
     ker_s = kernel_ms / 1e3
     fpe = flops_per_eval(d) if gauss else 2 * d  # multinomial: sum_v x_v log theta_kv
     flops = n * K * fpe / ker_s
     fused = d <= 4 or not gauss  # these label kernels also draw the sub-labels
     bpp = 4 * d + 4 + (1 if fused else 0)  # x read, z (and zsub) written
     hbm = bpp * n / ker_s
-    if prec == "fp32":
+    if not gauss:  # on the FP32 matrix cores; HBM-bound at this shape
+        roof = {"bound": "hbm", "achieved": hbm / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": hbm / PEAK_HBM,
+                "mfma_fp32_frac": flops / PEAK_FP32_MFMA}
+    elif d <= 4:
+        roof = {"bound": "hbm", "achieved": hbm / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": hbm / PEAK_HBM,
+                "valu_fp32_frac": flops / PEAK_FP32_VALU}
+    elif prec == "fp32":
         roof = {"bound": "alu", "achieved": flops / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
                 "frac": flops / PEAK_FP32_VALU}
     else:
         roof = {"bound": "mfma", "achieved": flops / 1e12, "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
                 "frac": flops / PEAK_BF16_MFMA}
-    roof.update({"kernel_ms": kernel_ms, "hbm_achieved_GBs": hbm / 1e9, "hbm_frac": hbm / 8e12,
-                 "algorithmic_flops_per_eval": fpe, "hbm_bytes_per_point": bpp})
-    out = {"metric": "point-cluster evals/s in label step", "value": evals, "unit": "point-cluster evals/s",
-           "higher_is_better": True, "dtype": prec if gauss else "fp32 (int32 counts)",
-           "data": "synthetic",
-           "config": {"workload": f"{name}: N={n}, d={d}, {spec.k} true clusters at the generating mixture "
-                                  "(statistics from the true labels, no split or merge)", "n": n, "d": d, "K": K},
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "phase_ms": ms,
-           "label_kernel": roof}
+    roof.update({"kernel_ms": kernel_ms, "hbm_GBs": hbm / 1e9, "algorithmic_flops_per_eval": fpe,
+                 "hbm_bytes_per_point": bpp})
+    return {"workload": f"{name}: N={n}, d={d}, {K} true clusters at the generating mixture (statistics from the "
+                        "true labels, no split or merge)", "n": n, "d": d, "K": K, "dtype": prec,
+            "label_evals_per_s": n * K / (ms["labels"] / 1e3), "ms_per_step": 1e3 * el / steps, "phase_ms": ms,
+            "label_kernel": roof}
+
+
+def chain_from_one(torch, name, n, iters, precision="fp32"):
+    """Iterations per second of a chain from K = 1 (every iteration timed)."""
+    from paper_2204_08988_amd import datagen, _lib
+    x_np, labels = datagen.workload(name, SEED, n)
+    n, d = x_np.shape
+    S = _sampler("gaussian", d, 64, x_np.mean(0).astype(np.float64), precision, burn_out=5)
+    x = torch.from_numpy(x_np).cuda()
+    z, zs = S.init_labels(n)
+    S.step(x, 1, z, zs)  # first call: lazy buffers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(2, iters + 2):
+        info = S.step(x, t, z, zs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {"workload": f"{name}: N={n}, d={d}, chain from K=1", "iters": iters, "iters_per_s": iters / el,
+           "final_K": info["K"], "nmi": _lib.nmi(labels, z.cpu().numpy())}
+    S.close()
+    return out
+
+
+def cpu_baseline(name, n_sample, budget_s):
+    """The FP64 oracle's label step (component log-likelihoods of the K true
+    clusters and their 2K sub-clusters, Gumbel-max and logistic draws) on the
+    first n_sample points of the workload, with all host cores and with one."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import niw, sampler
+    from paper_2204_08988_amd import datagen
+    x, labels = datagen.workload(name, SEED, n_sample)
+    x = x.astype(np.float64)
+    d = x.shape[1]
+    used, z = np.unique(labels, return_inverse=True)  # the clusters the sample holds
+    K = used.size
+    model = sampler.Model("gaussian", ALPHA, niw.NIWPrior(1.0, x.mean(0), d + 3.0, np.eye(d)), seed=SEED)
+    zs = (np.arange(x.shape[0]) % 2).astype(np.int64)
+    stats = sampler.suffstats(model, x, z.astype(np.int64), zs, K)
+    params = sampler.sample_params(model, stats, 1)
+
+    def rate(nrows, limit_s):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            sampler.sample_labels(model, x[:nrows], params, 2 + reps)
+            reps += 1
+            if time.perf_counter() - t0 > limit_s:
+                break
+        el = time.perf_counter() - t0
+        return nrows * (K + 2) * reps / el, reps, el
+
+    cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    v_all, r_all, e_all = rate(x.shape[0], 0.6 * budget_s)
+    with threadpool_limits(limits=1):
+        n1 = max(1000, x.shape[0] // 8)
+        v_one, r_one, e_one = rate(n1, 0.4 * budget_s)
+    return {"value": v_all, "unit": "point-cluster evals/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"FP64 oracle label step (K + 2 = {K + 2} components scored and drawn per point) on the first "
+                      f"{x.shape[0]} points of {name}: {r_all} repetitions in {e_all:.1f} s",
+            "value_1core": v_one,
+            "sample_1core": f"the same on {n1} points with BLAS limited to one thread: {r_one} repetitions in "
+                            f"{e_one:.1f} s"}
+
+
+def headline(args):
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    rec = converged_chain(torch, HEADLINE, None, args.precision, args.steps, args.warmup)
+    d = rec["d"]
+    kernel = HEADLINE_KERNEL if args.precision == "bf16" else f"cluster draw ({args.precision})"
+    out = {
+        "metric": "point-cluster evals/s in label step; iters/s; time-to-plateau learned vs plain",
+        "value": rec["value"],
+        "unit": "point-cluster evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": rec["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"{HEADLINE}: Gaussian DPMM, N={rec['n']}, d={d}, {rec['k_true']} true clusters, "
+                               "means N(0,9I), covariances Wishart(d+2, I/d), weights Dir(1); converged state "
+                               f"(generating labels); cluster scoring {args.precision} with the FP32 guard, "
+                               "sub-labels FP32, statistics and parameters FP64",
+                   "n": rec["n"], "d": d, "k_mean": rec["k_mean"], "alpha": ALPHA, "parallelism": "single GPU"},
+        "iters_per_s": rec["iters_per_s"],
+        "phase_ms": rec["phase_ms"],
+        "label_kernel_ms": rec["label_kernel_ms"],
+        "label_evals_per_s": rec["label_evals_per_s"],
+        "nmi": rec["nmi"],
+        "roofline": mfma_roofline(rec, d, kernel),
+    }
+    if not args.headline_only:
+        extra = {}
+        r2 = converged_chain(torch, "gauss_d32", None, "bf16", max(args.steps, 20), args.warmup)
+        r2["roofline"] = mfma_roofline(r2, 32, "k_label_gauss_mfma32<false,false>")
+        extra["gauss_d32"] = r2
+        extra["mult_v100"] = label_step_run(torch, "mult_v100", None, "fp32", 20, 3)
+        extra["mult_v100_chain"] = converged_chain(torch, "mult_v100", None, "fp32", 20, 3)
+        extra["gauss_d2_label_step_n1e8"] = label_step_run(torch, "gauss_d2", 100_000_000, "fp32", 10, 3)
+        extra["gauss_d2_chain_n1e4"] = chain_from_one(torch, "gauss_d2", None, 100)
+        out["configs"] = extra
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(HEADLINE, 20_000, 24.0)
     print(json.dumps(out), flush=True)
 
 
-def run_chain(torch, x, n, d, m, iters, learned, train_every, train_until, train_steps, batch, lr, seed=SEED):
+def label_step(args):
+    import torch
+    res = label_step_run(torch, args.label_step, int(float(args.n)) if args.n else None, args.precision, args.steps,
+                         args.warmup)
+    out = {"metric": "point-cluster evals/s in label step", "value": res["label_evals_per_s"],
+           "unit": "point-cluster evals/s", "higher_is_better": True, "data": "synthetic",
+           "steps": args.steps, "warmup": args.warmup, **res}
+    print(json.dumps(out), flush=True)
+
+
+# ----------------------------------------------------------------------------- learned vs plain
+
+AB_WORKLOAD = "gauss_d64"
+
+
+def run_chain(torch, x, n, d, m, iters, learned, train_every, train_until, train_steps, batch, lr, seed):
     """One chain from K = 1 with the BF16 form: per iteration (t, seconds since
     the start, K, log posterior).  The learned chain trains every `train_every`
-    iterations up to iteration `train_until` (the growth phase, while clusters
-    still hold several components and their sub-labels carry a signal); its
-    training time is inside the clock."""
-    from paper_2204_08988_amd.sampler import Sampler
-    S = Sampler("gaussian", d, 512, ALPHA, seed, kappa=1.0, nu=d + 3.0, m=m, psi=np.eye(d), burn_out=5,
-                precision="bf16", learned=learned)
+    iterations up to iteration `train_until`; its training time is inside the
+    clock."""
+    S = _sampler("gaussian", d, 512, m, "bf16", burn_out=5, learned=learned, seed=seed)
     z, zs = S.init_labels(n)
     torch.cuda.synchronize()
     rec, tries, acc, t_train = [], 0, 0, 0.0
@@ -225,43 +334,50 @@ def run_chain(torch, x, n, d, m, iters, learned, train_every, train_until, train
     return S, z, rec, {"learned_moves": tries, "learned_accepted": acc, "train_s": t_train}
 
 
+def plateau_time(rec, level, rel, window=5):
+    """First (iteration, seconds) at which the `window`-iteration moving average
+    of the log posterior enters level - rel |level|; None if it never does."""
+    lp = np.array([r[3] for r in rec])
+    thr = level - rel * abs(level)
+    for j in range(window - 1, lp.size):
+        if lp[j - window + 1: j + 1].mean() >= thr:
+            return rec[j][0], rec[j][1]
+    return None
+
+
 def ab_one(args, torch, x, n, d, m, labels, seed):
-    """Both chains under one seed; the plateau is that seed's plain chain's."""
-    from oracle import nmi as nmi_mod
+    """Both chains under one seed; the plateau is that seed's plain chain's:
+    P* = median log posterior over its last 20% iterations; a chain reaches it
+    when its 5-iteration moving average enters P* - rel |P*| (rel = 1e-4, and
+    1e-5 and 1e-3 for the sensitivity).  A chain that never does has speed-up 0."""
+    from paper_2204_08988_amd import _lib
     chains = {}
     for form, learned in (("plain", 0), ("learned", args.ab_axes)):
         S, z, rec, extra = run_chain(torch, x, n, d, m, args.ab_iters, learned, args.ab_train_every,
                                      args.ab_train_until, args.ab_train_steps, args.ab_batch, args.ab_lr, seed)
-        chains[form] = (rec, extra, nmi_mod.nmi(labels, z.cpu().numpy()), S.K)
+        chains[form] = (rec, extra, _lib.nmi(labels, z.cpu().numpy()), S.K)
         S.close()
-    # the plateau: mean log posterior of the plain chain's last quarter; a chain
-    # has reached it once within max(3 standard deviations of that tail, 1e-5 of
-    # the level) -- converged chains can settle in modes a few hundred nats
-    # apart (one cluster more or less), far below 1e-5 of the level
-    tail = np.array([r[3] for r in chains["plain"][0][-max(1, args.ab_iters // 4):]])
-    level = float(tail.mean())
-    tol = max(3.0 * float(tail.std()), 1e-5 * abs(level))
-    out = {"seed": seed, "plateau_logpost": level, "plateau_tol": tol}
+    tail = np.array([r[3] for r in chains["plain"][0][-max(1, args.ab_iters // 5):]])
+    level = float(np.median(tail))
+    out = {"seed": seed, "plateau_logpost": level}
+    for rel in (1e-5, 1e-4, 1e-3):
+        hits = {f: plateau_time(chains[f][0], level, rel) for f in chains}
+        p, l = hits["plain"], hits["learned"]
+        sp = None if p is None else (0.0 if l is None else p[1] / l[1])
+        out[f"speedup_wall@{rel:g}"] = sp
+        out[f"plain_to_plateau@{rel:g}"] = p
+        out[f"learned_to_plateau@{rel:g}"] = l
     for form, (rec, extra, nmi, K) in chains.items():
-        hit = next((r for r in rec if r[3] >= level - tol), None)
-        out[form] = {"time_to_plateau_s": None if hit is None else hit[1],
-                     "iters_to_plateau": None if hit is None else hit[0],
-                     "total_s": rec[-1][1], "final_K": K, "final_logpost": rec[-1][3], "nmi": nmi,
+        out[form] = {"total_s": rec[-1][1], "final_K": K, "final_logpost": rec[-1][3], "nmi": nmi,
                      "trace": [[r[0], round(r[1], 4), r[2], r[3]] for r in rec if r[0] % 5 == 0], **extra}
-    p, l = out["plain"], out["learned"]
-    out["speedup_wall"] = (p["time_to_plateau_s"] / l["time_to_plateau_s"]
-                           if p["time_to_plateau_s"] and l["time_to_plateau_s"] else None)
-    out["speedup_iters"] = (p["iters_to_plateau"] / l["iters_to_plateau"]
-                            if p["iters_to_plateau"] and l["iters_to_plateau"] else None)
-    out["nmi_diff"] = l["nmi"] - p["nmi"]
+    out["nmi_diff"] = out["learned"]["nmi"] - out["plain"]["nmi"]
     return out
 
 
 def learned_ab(args):
     """Time to the plain chain's log-posterior plateau, learned vs plain, for
-    each of --ab-seeds seeds (the chains' trajectories, and so the time to a
-    plateau, vary with the seed); the first seed's result is reported at the
-    top level, every seed's under `seeds`, with the median wall-clock speed-up."""
+    each of --ab-seeds seeds; the median wall-clock speed-up over the seeds
+    (a learned chain that never reaches the plateau counts as 0)."""
     import torch
     from paper_2204_08988_amd import datagen
     spec = datagen.WORKLOADS[AB_WORKLOAD]
@@ -269,33 +385,36 @@ def learned_ab(args):
     n, d = x_np.shape
     m = x_np.mean(0).astype(np.float64)
     x = torch.from_numpy(x_np).cuda()
-    runs = [ab_one(args, torch, x, n, d, m, labels, SEED + i) for i in range(args.ab_seeds)]
+    runs = []
+    for i in range(args.ab_seeds):
+        runs.append(ab_one(args, torch, x, n, d, m, labels, SEED + i))
+        print(json.dumps({"seed_done": SEED + i, "speedup_wall@0.0001": runs[-1]["speedup_wall@0.0001"]}),
+              file=sys.stderr, flush=True)
     out = {"metric": "time-to-plateau learned vs plain", "unit": "s", "higher_is_better": False,
            "workload": f"{AB_WORKLOAD}: Gaussian DPMM, N={n}, d={d}, {spec.k} true clusters, means N(0,4I), "
                        "covariances Wishart(d+2, I/d), weights Dir(1); start K=1; BF16 cluster scoring",
+           "plateau_rule": "P* = median log posterior of the plain chain's last 20% iterations; reached when the "
+                           "5-iteration moving average enters P* - rel |P*|; never reached = speed-up 0",
            "learned_config": {"axes": args.ab_axes, "features": 2 * args.ab_axes, "hidden": [128, 128],
                               "train_every": args.ab_train_every, "train_until": args.ab_train_until,
-                              "train_steps": args.ab_train_steps,
-                              "batch": args.ab_batch, "lr": args.ab_lr}}
-    out.update({k: v for k, v in runs[0].items() if k != "seed"})
-    sp = [r["speedup_wall"] for r in runs if r["speedup_wall"] is not None]
-    out["seeds"] = [{k: v for k, v in r.items() if k not in ("plain", "learned")} |
-                    {f: {k: r[f][k] for k in ("time_to_plateau_s", "iters_to_plateau", "final_K", "final_logpost",
-                                                "nmi", "learned_accepted", "train_s")} for f in ("plain", "learned")}
-                    for r in runs]
-    out["median_speedup_wall"] = float(np.median(sp)) if sp else None
+                              "train_steps": args.ab_train_steps, "batch": args.ab_batch, "lr": args.ab_lr},
+           "seeds": runs}
+    for rel in (1e-5, 1e-4, 1e-3):
+        sp = [r[f"speedup_wall@{rel:g}"] for r in runs if r[f"speedup_wall@{rel:g}"] is not None]
+        out[f"median_speedup_wall@{rel:g}"] = float(np.median(sp)) if sp else None
+    out["median_nmi_diff"] = float(np.median([r["nmi_diff"] for r in runs]))
     print(json.dumps(out), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "bf16x3"],
-                    help="form reported as `value` (the other forms are reported beside it)")
+                    help="cluster scoring of the headline workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", action="store_true", help="time only the --precision form")
+    ap.add_argument("--headline-only", action="store_true", help="skip the other configurations")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a device buffer of BYTES five times (calibrates HBM byte counters)")
     ap.add_argument("--label-step", metavar="WORKLOAD",
@@ -305,7 +424,7 @@ def main():
                     help="instead of the throughput line: time to the plain chain's log-posterior plateau, "
                          "learned proposal vs plain, on the learned-proposal workload")
     ap.add_argument("--ab-iters", type=int, default=200)
-    ap.add_argument("--ab-seeds", type=int, default=1, help="seeds of the learned-vs-plain comparison")
+    ap.add_argument("--ab-seeds", type=int, default=5, help="seeds of the learned-vs-plain comparison")
     ap.add_argument("--ab-axes", type=int, default=8)
     ap.add_argument("--ab-train-every", type=int, default=10)
     ap.add_argument("--ab-train-until", type=int, default=60)
@@ -313,12 +432,9 @@ def main():
     ap.add_argument("--ab-batch", type=int, default=4096)
     ap.add_argument("--ab-lr", type=float, default=1e-3)
     args = ap.parse_args()
-    if args.gpus == 1 and args.learned_ab:
-        learned_ab(args)
-        return
-    if args.gpus == 1 and args.label_step:
-        label_step(args)
-        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
     if args.copy_probe:
         import torch
         a = torch.empty(args.copy_probe // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -328,102 +444,13 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
         return
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(--gpus must be 1)", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2204_08988_amd import datagen
-    from oracle import nmi as nmi_mod
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    spec = datagen.WORKLOADS[WORKLOAD]
-    x_np, labels = datagen.workload(WORKLOAD, SEED)
-    n, d = x_np.shape
-    m = x_np.mean(0).astype(np.float64)
-    x = torch.from_numpy(x_np).cuda()
-    forms = [args.precision] if args.only else [args.precision] + [f for f in ("fp32", "bf16", "bf16x3")
-                                                                     if f != args.precision]
-    results = {}
-    main_state = None
-    for f in forms:
-        S, z, zs, res = run_form(torch, x, n, d, m, f, args.steps, args.warmup, spec.k)
-        res["nmi"] = nmi_mod.nmi(labels, z.cpu().numpy())
-        results[f] = res
-        if f == args.precision:
-            main_state = (z.cpu().numpy(), zs.cpu().numpy(), S.K)
-        S.close()
-    r = results[args.precision]
-    label_s = r["label_kernel_ms"] / 1e3
-    stats_s = r["stats_kernel_ms"] / 1e3
-    algo_label = n * r["k_mean"] * flops_per_eval(d)  # the cluster draw scores K clusters per point
-    if args.precision == "fp32":
-        label_roof = {"bound": "alu", "achieved": algo_label / label_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                      "unit": "TFLOP/s", "frac": algo_label / label_s / PEAK_FP32_VALU,
-                      "kernel": "k_label_gauss_z<32> (FP32 VALU cluster draw)"}
-    else:
-        label_roof = {"bound": "mfma", "achieved": algo_label / label_s / 1e12, "peak": PEAK_BF16_MFMA / 1e12,
-                      "unit": "TFLOP/s", "frac": algo_label / label_s / PEAK_BF16_MFMA,
-                      "kernel": f"k_label_gauss_mfma32<{'true' if args.precision == 'bf16x3' else 'false'}> "
-                                "(BF16 matrix-core cluster draw)"}
-    label_roof["algorithmic_flops_per_eval"] = flops_per_eval(d)
-    # sub-label draw + statistics over the cluster-sorted order, a phase of
-    # three kernels: the two FP32 sub-cluster scores on the FP32 matrix cores
-    # (k_sub_labels_mfma), then the FP64 moments (sum x, upper triangle of
-    # x x^T) on the FP64 matrix cores (k_sub_stats_w, k_sub_stats_fix).  The
-    # kernels run one after the other, so the phase takes at least the sum of
-    # the two parts' times at their units' peaks; "peak" is the phase's flops
-    # over that time.
-    score_flops, moment_flops = 2 * flops_per_eval(d), d + d * (d + 1)
-    stats_flops = score_flops + moment_flops
-    t_min = n * (score_flops / PEAK_FP32_MFMA + moment_flops / PEAK_FP64_MFMA)
-    stats_roof = {"bound": "mfma", "achieved": n * stats_flops / stats_s / 1e12,
-                  "peak": n * stats_flops / t_min / 1e12, "unit": "TFLOP/s", "frac": t_min / stats_s,
-                  "kernel": "sub-label + statistics phase: k_sub_labels_mfma<32>, k_sub_stats_w<32,false>, "
-                            "k_sub_stats_fix",
-                  "algorithmic_flops_per_point": stats_flops,
-                  "hbm_bytes_per_point": 2 * (4 * d + 4 + 4 + 1)}
-    stats_roof["traffic"] = MEASURED_TRAFFIC.get("k_sub_labels_mfma<32>+k_sub_stats_w<32,false>")
-    label_roof["traffic"] = (MEASURED_TRAFFIC.get("k_label_gauss_mfma32<false,false>")
-                             if args.precision == "bf16" else None)
-    # the dominant single kernel is the cluster draw (the statistics phase is
-    # split over three kernels, the largest of them shorter than the draw),
-    # timed alone by events right around its launch on the sampler's stream
-    label_roof["kernel_ms"] = r["label_kernel_ms"]
-    roof, other = label_roof, stats_roof
-    out = {
-        "metric": "point-cluster evals/s in label step; iters/s; time-to-plateau learned vs plain",
-        "value": r["value"],
-        "unit": "point-cluster evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": r["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": args.precision,
-        "data": "synthetic",
-        "config": {"workload": f"{WORKLOAD}: Gaussian DPMM, N={n}, d={d}, {spec.k} true clusters, "
-                               "means N(0,25I), covariances Wishart(d+2, I/d), weights Dir(1); "
-                               f"cluster scoring {args.precision}, sub-labels FP32, statistics and "
-                               "parameters FP64", "n": n, "d": d, "k_mean": r["k_mean"],
-                   "alpha": ALPHA, "parallelism": "single GPU"},
-        "iters_per_s": r["iters_per_s"],
-        "phase_ms": r["phase_ms"],
-        "label_kernel_ms": r["label_kernel_ms"],
-        "label_evals_per_s": r["label_evals_per_s"],
-        "nmi": r["nmi"],
-        "forms": {f: {k: v for k, v in res.items() if k != "precision"} for f, res in results.items()
-                  if f != args.precision},
-        "roofline": roof,
-        "roofline_other_kernel": other,
-    }
-    if not args.no_cpu_baseline:
-        z_np, zs_np, K = main_state
-        out["cpu_baseline"] = cpu_baseline(x_np, z_np, zs_np, K, d)
-    print(json.dumps(out), flush=True)
+    if args.learned_ab:
+        learned_ab(args)
+        return
+    if args.label_step:
+        label_step(args)
+        return
+    headline(args)
 
 
 if __name__ == "__main__":

@@ -325,6 +325,53 @@ dpmm_status dpmm_mlp_train(dpmm_ctx* ctx, const void* x, int64_t n, const int32_
 dpmm_status dpmm_mlp_training_set(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z, const uint8_t* zsub,
                                   float* feats, float* y, int32_t* idx, int64_t capacity, int64_t* n_rows);
 
+/* ---- User-level run (the paper's fit interface, Sec. 3.4) ---- */
+
+/* Normalised mutual information of two labelings a, b (host int32[n]) with
+ * the arithmetic-mean normalisation I(a; b) / ((H(a) + H(b)) / 2), the
+ * accuracy measure of Sec. 5; 1 when both are constant.  Host code: needs no
+ * context and no device. */
+dpmm_status dpmm_nmi(const int32_t* a, const int32_t* b, int64_t n, double* out);
+
+/* Options of dpmm_fit. */
+typedef struct {
+  uint32_t t0;         /* the first iteration's number (>= 1); a run resumed
+                          from a checkpoint of iteration t passes t + 1 */
+  int32_t iters;       /* iterations to run (>= 0) */
+  int32_t train_every; /* learned proposal: train the network on the sampler's
+                          sub-labels after every iteration t with
+                          t % train_every == 0 and t <= train_until (0: never) */
+  int32_t train_until;
+  int32_t train_steps; /* dpmm_mlp_train arguments */
+  int32_t train_batch;
+  float train_lr;
+  int32_t reserved;
+} dpmm_fit_options;
+
+/* Run iterations t0 ... t0 + iters - 1 of the sampler (dpmm_step each, plus
+ * the training schedule of opt), the user-level run of Sec. 3.4 (a fixed
+ * iteration count, the state in z / zsub).  trace: host dpmm_iter_info[iters]
+ * (optional), seconds: host double[iters] wall-clock time of each iteration
+ * (optional).  Stops at the first failing iteration and returns its status. */
+dpmm_status dpmm_fit(dpmm_ctx* ctx, const void* x, int64_t n, const dpmm_fit_options* opt, int32_t* z, uint8_t* zsub,
+                     dpmm_iter_info* trace, double* seconds);
+
+/* Checkpoint files (the save-model option of Sec. 3.4): the state after
+ * iteration t -- K, the cluster ages, z and zsub (device int32[n] / uint8[n]),
+ * and with the learned proposal the network's weights, Adam moments and
+ * counters -- with the configuration it was written under.  Every draw of a
+ * later iteration is a function of (seed, iteration, entity) and of this
+ * state, so a run resumed from a checkpoint of iteration t at t + 1 repeats
+ * the uninterrupted run bit for bit.  The file is written to path + ".tmp"
+ * and renamed.  Loading checks the configuration (family, d, seed, alpha,
+ * prior, forms) and n against the context (DPMM_E_ARG / DPMM_E_SHAPE
+ * otherwise), writes z / zsub, sets K and the ages (as dpmm_set_state) and
+ * returns t. */
+dpmm_status dpmm_save_checkpoint(dpmm_ctx* ctx, const char* path, int64_t n, uint32_t t, const int32_t* z,
+                                 const uint8_t* zsub);
+dpmm_status dpmm_load_checkpoint(dpmm_ctx* ctx, const char* path, int64_t n, uint32_t* t, int32_t* z,
+                                 uint8_t* zsub);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,8 @@ EXPORTS = [
     "dpmm_get_stats", "dpmm_loglik", "dpmm_sample_labels", "dpmm_suffstats", "dpmm_sample_params",
     "dpmm_split_merge", "dpmm_step", "dpmm_mlp_n_params", "dpmm_mlp_set_weights", "dpmm_mlp_get_weights",
     "dpmm_mlp_forward", "dpmm_mlp_grad", "dpmm_mlp_adam_step", "dpmm_set_features", "dpmm_learned_move",
-    "dpmm_mlp_train", "dpmm_mlp_training_set", "dpmm_suffstats_static",
+    "dpmm_mlp_train", "dpmm_mlp_training_set", "dpmm_suffstats_static", "dpmm_nmi", "dpmm_fit",
+    "dpmm_save_checkpoint", "dpmm_load_checkpoint",
 ]
 
 
@@ -65,6 +66,14 @@ class LearnedInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class FitOptions(ctypes.Structure):
+    _fields_ = [
+        ("t0", ctypes.c_uint32), ("iters", ctypes.c_int32), ("train_every", ctypes.c_int32),
+        ("train_until", ctypes.c_int32), ("train_steps", ctypes.c_int32), ("train_batch", ctypes.c_int32),
+        ("train_lr", ctypes.c_float), ("reserved", ctypes.c_int32),
+    ]
+
+
 _lib = None
 
 
@@ -94,6 +103,10 @@ def lib():
         "dpmm_sample_labels": ([vp, vp, i64, u32, vp, vp], i32),
         "dpmm_suffstats": ([vp, vp, i64, vp, vp], i32),
         "dpmm_suffstats_static": ([vp, vp, i64, vp, vp], i32),
+        "dpmm_nmi": ([vp, vp, i64, dp], i32),
+        "dpmm_fit": ([vp, vp, i64, ctypes.POINTER(FitOptions), vp, vp, ctypes.POINTER(IterInfo), dp], i32),
+        "dpmm_save_checkpoint": ([vp, ctypes.c_char_p, i64, u32, vp, vp], i32),
+        "dpmm_load_checkpoint": ([vp, ctypes.c_char_p, i64, ctypes.POINTER(u32), vp, vp], i32),
         "dpmm_sample_params": ([vp, u32], i32),
         "dpmm_split_merge": ([vp, vp, i64, u32, vp, vp, ctypes.POINTER(IterInfo)], i32),
         "dpmm_step": ([vp, vp, i64, u32, vp, vp, ctypes.POINTER(IterInfo)], i32),
@@ -120,3 +133,18 @@ class DpmmError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{STATUS.get(status, status)}: {message}")
         self.status = status
+
+
+def nmi(a, b):
+    """Normalised mutual information of two host labelings (dpmm_nmi)."""
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.int32).ravel()
+    b = np.ascontiguousarray(b, dtype=np.int32).ravel()
+    if a.size != b.size:
+        raise ValueError("label vectors differ in length")
+    out = ctypes.c_double()
+    s = lib().dpmm_nmi(a.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p), a.size,
+                       ctypes.byref(out))
+    if s != DPMM_OK:
+        raise DpmmError(s, "dpmm_nmi")
+    return out.value

@@ -3,7 +3,9 @@
 Usage: python -m paper_2204_08988_amd.build   (or build() from Python)
 Every source under csrc/ is compiled to an object in _build/ (in parallel)
 and linked into paper_2204_08988_amd/libdpmm.so, which the Python binding
-loads.  Always recompiles: the call is the "does it build" check.
+loads; cli/dpmm_fit.cpp becomes the command-line tool
+paper_2204_08988_amd/dpmm_fit.  Always recompiles: the call is the "does it
+build" check.
 """
 import concurrent.futures
 import os
@@ -65,7 +67,26 @@ def build(verbose=False, jobs=8):
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")
+    build_cli(verbose)
     return LIB
+
+
+CLI_SRC = os.path.join(HERE, "cli", "dpmm_fit.cpp")
+CLI = os.path.join(HERE, "dpmm_fit")
+
+
+def build_cli(verbose=False):
+    """The command-line run (cli/dpmm_fit.cpp), linked against libdpmm.so next to it."""
+    tmp = CLI + ".tmp"
+    cmd = [hipcc(), "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), CLI_SRC, "-L", HERE, "-ldpmm",
+           "-Wl,-rpath,$ORIGIN", "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"CLI build failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    os.replace(tmp, CLI)
+    if verbose:
+        print(f"built {CLI}")
+    return CLI
 
 
 if __name__ == "__main__":

@@ -183,6 +183,30 @@ class Sampler:
                                       ctypes.byref(info)))
         return info.as_dict()
 
+    def fit(self, x, t0, iters, z, zsub, train_every=0, train_until=0, train_steps=20, train_batch=4096,
+            train_lr=1e-3):
+        """Iterations t0 ... t0 + iters - 1 (dpmm_fit): per-iteration info
+        dicts and wall-clock seconds."""
+        opt = _lib.FitOptions(int(t0), int(iters), int(train_every), int(train_until), int(train_steps),
+                              int(train_batch), float(train_lr), 0)
+        trace = (_lib.IterInfo * max(int(iters), 1))()
+        secs = np.zeros(max(int(iters), 1))
+        self._check(self._L.dpmm_fit(self._ctx, _tptr(x), x.shape[0], ctypes.byref(opt), _tptr(z), _tptr(zsub),
+                                     trace, _dptr(secs)))
+        return [trace[j].as_dict() for j in range(int(iters))], secs[:int(iters)]
+
+    def save_checkpoint(self, path, t, z, zsub):
+        self._check(self._L.dpmm_save_checkpoint(self._ctx, str(path).encode(), z.shape[0], int(t), _tptr(z),
+                                                 _tptr(zsub)))
+
+    def load_checkpoint(self, path, z, zsub):
+        """Labels into z / zsub, K and ages into the context; returns the
+        checkpoint's iteration t."""
+        t = ctypes.c_uint32()
+        self._check(self._L.dpmm_load_checkpoint(self._ctx, str(path).encode(), z.shape[0], ctypes.byref(t),
+                                                 _tptr(z), _tptr(zsub)))
+        return int(t.value)
+
     # ------------------------------------------------------------------ learned proposal
     @property
     def n_mlp_params(self):

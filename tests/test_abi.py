@@ -118,7 +118,8 @@ def test_struct_layouts_match_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    structs = {"dpmm_config": _lib.Config, "dpmm_iter_info": _lib.IterInfo, "dpmm_learned_info": _lib.LearnedInfo}
+    structs = {"dpmm_config": _lib.Config, "dpmm_iter_info": _lib.IterInfo, "dpmm_learned_info": _lib.LearnedInfo,
+               "dpmm_fit_options": _lib.FitOptions}
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "dpmm.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
