@@ -92,12 +92,15 @@ def converged_chain(torch, name, n, precision, steps, warmup, seed=SEED):
     kernel_ms = 0.0
     evals = 0
     k_sum = 0
+    moves = [0, 0]
     t0 = time.perf_counter()
     for _ in range(steps):
         info = S.step(x, t, z, zs)
         t += 1
         evals += n * (info["K"] + 2)
         k_sum += info["K"]
+        moves[0] += info["splits"]
+        moves[1] += info["merges"]
         for key in ms:
             ms[key] += info["ms_" + key]
         kernel_ms += info["ms_label_kernel"]
@@ -108,6 +111,7 @@ def converged_chain(torch, name, n, precision, steps, warmup, seed=SEED):
            "iters_per_s": steps / el, "phase_ms": {k: v / steps for k, v in ms.items()},
            "label_kernel_ms": kernel_ms / steps,
            "label_evals_per_s": n * (k_sum / steps) / (ms["labels"] / steps / 1e3),
+           "splits": moves[0], "merges": moves[1],
            "nmi": _lib.nmi(labels, z.cpu().numpy())}
     S.close()
     del x

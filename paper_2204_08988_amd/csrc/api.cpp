@@ -175,11 +175,13 @@ dpmm_status ensure_items(dpmm_ctx* ctx, size_t count) {
   hipFree(ctx->d_items);
   hipFree(ctx->d_logml);
   hipFree(ctx->d_mflag);
+  hipFree(ctx->d_plist);
   hipHostFree(ctx->h_items);
   hipHostFree(ctx->h_lml);
   hipHostFree(ctx->h_mflag);
   hipFree(ctx->d_rb);
   hipHostFree(ctx->h_rb);
+  ctx->d_plist = nullptr;
   ctx->d_rb = nullptr;
   ctx->h_rb = nullptr;
   ctx->d_items = nullptr;
@@ -192,6 +194,7 @@ dpmm_status ensure_items(dpmm_ctx* ctx, size_t count) {
   DPMM_HIP(ctx, hipMalloc(&ctx->d_items, cap * sizeof(LogmlItem)), "allocate items");
   DPMM_HIP(ctx, hipMalloc(&ctx->d_logml, cap * sizeof(double)), "allocate items");
   DPMM_HIP(ctx, hipMalloc(&ctx->d_mflag, cap), "allocate items");
+  DPMM_HIP(ctx, hipMalloc(&ctx->d_plist, cap * sizeof(int)), "allocate items");
   DPMM_HIP(ctx, hipHostMalloc((void**)&ctx->h_items, cap * sizeof(LogmlItem), hipHostMallocDefault), "pin items");
   DPMM_HIP(ctx, hipHostMalloc((void**)&ctx->h_lml, cap * sizeof(double), hipHostMallocDefault), "pin items");
   DPMM_HIP(ctx, hipHostMalloc((void**)&ctx->h_mflag, cap, hipHostMallocDefault), "pin items");
@@ -202,22 +205,35 @@ dpmm_status ensure_items(dpmm_ctx* ctx, size_t count) {
   return DPMM_OK;
 }
 
-// enqueue the log marginal likelihoods of items (copied through pinned staging)
-dpmm_status logml_launch(dpmm_ctx* ctx, const LogmlItem* items, size_t count) {
+// copy items to d_items (through pinned staging)
+dpmm_status logml_upload(dpmm_ctx* ctx, const LogmlItem* items, size_t count) {
   DPMM_TRY(ensure_items(ctx, count));
   if (count == 0) return DPMM_OK;
   std::memcpy(ctx->h_items, items, count * sizeof(LogmlItem));
   DPMM_HIP(ctx, hipMemcpyAsync(ctx->d_items, ctx->h_items, count * sizeof(LogmlItem), hipMemcpyHostToDevice,
                                ctx->stream), "copy items");
+  return DPMM_OK;
+}
+
+// the log marginal likelihoods of the uploaded items [first, first + count)
+// into d_logml[first ...]
+dpmm_status logml_range(dpmm_ctx* ctx, size_t first, size_t count) {
+  if (count == 0) return DPMM_OK;
   hipError_t e;
   if (ctx->gaussian())
-    e = launch_logml_gauss((int)count, ctx->d_items, ctx->d, prior_dev(ctx), ctx->logdet_psi, ctx->d_counts,
-                           ctx->d_moments, ctx->d_scratch, ctx->d_logml, ctx->d_err, ctx->stream);
+    e = launch_logml_gauss((int)count, ctx->d_items + first, ctx->d, prior_dev(ctx), ctx->logdet_psi, ctx->d_counts,
+                           ctx->d_moments, ctx->d_scratch, ctx->d_logml + first, ctx->d_err, ctx->stream);
   else
-    e = launch_logml_mult((int)count, ctx->d_items, ctx->d, ctx->d_beta, ctx->beta_sum, ctx->lgamma_beta_sum,
-                          ctx->d_lgamma_beta, ctx->d_counts, ctx->d_sums, ctx->d_logml, ctx->stream);
+    e = launch_logml_mult((int)count, ctx->d_items + first, ctx->d, ctx->d_beta, ctx->beta_sum, ctx->lgamma_beta_sum,
+                          ctx->d_lgamma_beta, ctx->d_counts, ctx->d_sums, ctx->d_logml + first, ctx->stream);
   DPMM_HIP(ctx, e, "log marginal likelihood kernel");
   return DPMM_OK;
+}
+
+// enqueue the log marginal likelihoods of items (copied through pinned staging)
+dpmm_status logml_launch(dpmm_ctx* ctx, const LogmlItem* items, size_t count) {
+  DPMM_TRY(logml_upload(ctx, items, count));
+  return logml_range(ctx, 0, count);
 }
 
 // log marginal likelihoods of a list of segment unions (device), read back
@@ -363,6 +379,12 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
       for (int j = 0; j < d; ++j)
         if (ctx->psi[i * d + j] != ctx->psi[j * d + i]) return bad(DPMM_E_NUMERIC, "psi is not symmetric");
     if (!host_cholesky_logdet(ctx->psi, d, &ctx->logdet_psi)) return bad(DPMM_E_NUMERIC, "psi is not positive definite");
+    // Gershgorin: the largest absolute row sum bounds lambda_max(Psi) (the merge bound)
+    for (int i = 0; i < d; ++i) {
+      double r = 0.0;
+      for (int j = 0; j < d; ++j) r += std::fabs(ctx->psi[i * d + j]);
+      ctx->lam_psi = std::max(ctx->lam_psi, r);
+    }
     ctx->E = d + d * (d + 1) / 2;
     ctx->stride = gauss_rec_stride(d);
   } else {
@@ -398,6 +420,7 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
   ok = ok && chk(c->alloc(&c->d_packed, 3 * (size_t)km * c->stride));
   ok = ok && chk(c->alloc(&c->d_err, 1));
   ok = ok && chk(c->alloc(&c->d_table, 4 * (size_t)km));
+  ok = ok && chk(c->alloc(&c->d_pcount, 2));
   if (c->gaussian()) {
     ok = ok && chk(c->alloc(&c->d_m, (size_t)d));
     ok = ok && chk(c->alloc(&c->d_psi, (size_t)d * d));
@@ -480,6 +503,7 @@ void dpmm_destroy(dpmm_ctx* ctx) {
   hipFree(ctx->d_items);
   hipFree(ctx->d_logml);
   hipFree(ctx->d_mflag);
+  hipFree(ctx->d_plist);
   hipHostFree(ctx->h_items);
   hipHostFree(ctx->h_lml);
   hipHostFree(ctx->h_mflag);
@@ -809,14 +833,35 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t
           items.push_back(LogmlItem{{2 * k1, 2 * k1 + 1, 2 * k2, 2 * k2 + 1}});
         }
     }
-    // one launch for every marginal, the merge tests on the device, one
-    // read-back: counts, the 3K cluster / sub-cluster marginals, the pair
-    // decisions and the error flag
-    DPMM_TRY(logml_launch(ctx, items.data(), items.size()));
-    DPMM_HIP(ctx, launch_merge_decide((int)pairs.size(), ctx->d_items + 3 * K, ctx->d_counts, ctx->d_logml,
-                                      ctx->d_logml + 3 * K, alpha, ctx->cfg.merge_form == DPMM_MERGE_PAPER, seed, t,
-                                      ctx->d_mflag, ctx->stream), "merge test kernel");
     const int P = (int)pairs.size();
+    const bool paper_form = ctx->cfg.merge_form == DPMM_MERGE_PAPER;
+    // the merge tests on the device, one read-back: counts, the 3K cluster /
+    // sub-cluster marginals, the pair decisions and the error flag
+    if (ctx->gaussian() && P > 0 && ctx->d <= MERGE_BOUND_MAX_D) {
+      // Gaussian, small d: the bound items log|Psi / 2 + C_k| after the pairs;
+      // the merge bound rejects most pairs, and only the others get the union's
+      // Cholesky.  (Above MERGE_BOUND_MAX_D the bound is too loose to pay for
+      // its K extra factorisations on ill-conditioned covariances.)
+      for (int k = 0; k < K; ++k) items.push_back(LogmlItem{{2 * k, 2 * k + 1, -1, LOGML_BOUND}});
+      DPMM_TRY(logml_upload(ctx, items.data(), items.size()));
+      DPMM_TRY(logml_range(ctx, 0, 3 * (size_t)K));
+      DPMM_TRY(logml_range(ctx, 3 * (size_t)K + P, (size_t)K));
+      DPMM_HIP(ctx, launch_merge_prune(P, ctx->d_items + 3 * K, ctx->d, prior_dev(ctx), ctx->logdet_psi, ctx->lam_psi,
+                                       ctx->d_counts, ctx->d_moments, ctx->d_logml, ctx->d_logml + 3 * K + P, alpha,
+                                       paper_form, seed, t, ctx->d_mflag, ctx->d_plist, ctx->d_pcount, ctx->stream),
+               "merge bound kernel");
+      DPMM_HIP(ctx, launch_logml_gauss(P, ctx->d_items, ctx->d, prior_dev(ctx), ctx->logdet_psi, ctx->d_counts,
+                                       ctx->d_moments, ctx->d_scratch, ctx->d_logml, ctx->d_err, ctx->stream,
+                                       ctx->d_plist, ctx->d_pcount, 3 * K),
+               "log marginal likelihood kernel");
+      DPMM_HIP(ctx, launch_merge_decide(P, ctx->d_items + 3 * K, ctx->d_counts, ctx->d_logml, ctx->d_logml + 3 * K,
+                                        alpha, paper_form, seed, t, ctx->d_mflag, ctx->stream, ctx->d_plist,
+                                        ctx->d_pcount), "merge test kernel");
+    } else {
+      DPMM_TRY(logml_launch(ctx, items.data(), items.size()));
+      DPMM_HIP(ctx, launch_merge_decide(P, ctx->d_items + 3 * K, ctx->d_counts, ctx->d_logml, ctx->d_logml + 3 * K,
+                                        alpha, paper_form, seed, t, ctx->d_mflag, ctx->stream), "merge test kernel");
+    }
     DPMM_HIP(ctx, launch_pack_readback(K, P, ctx->d_counts, ctx->d_logml, ctx->d_mflag, ctx->d_err, ctx->d_rb,
                                        ctx->stream), "read-back kernel");
     DPMM_HIP(ctx, hipMemcpyAsync(ctx->h_rb, ctx->d_rb, readback_bytes(K, P), hipMemcpyDeviceToHost, ctx->stream),

@@ -61,6 +61,9 @@ struct dpmm_ctx {
   LogmlItem* d_items = nullptr;
   double* d_logml = nullptr;
   unsigned char* d_mflag = nullptr;
+  int* d_plist = nullptr;   // pairs the merge bound leaves for the exact test
+  int* d_pcount = nullptr;  // their number
+  double lam_psi = 0.0;     // an upper bound on lambda_max(Psi) (Gershgorin)
   LogmlItem* h_items = nullptr;
   double* h_lml = nullptr;
   unsigned char* h_mflag = nullptr;

@@ -148,15 +148,33 @@ hipError_t launch_stats_mult(int V, const int* x, long long n, const int* z, con
 
 // ---- split / merge (splitmerge.hip)
 struct LogmlItem {
-  int seg[4];  // up to four sub-cluster segments summed; -1 = unused
+  int seg[4];  // up to four sub-cluster segments summed; -1 = unused; seg[3] = LOGML_BOUND: see below
 };
+// a Gaussian item whose seg[3] is LOGML_BOUND yields log|Psi / 2 + C| (C the
+// scatter of its segments about their mean) instead of the log marginal: the
+// per-cluster term of the merge bound
+constexpr int LOGML_BOUND = -3;
+// the merge bound is used up to this d: it relies on Minkowski's inequality
+// |X + Y|^(1/d) >= |X|^(1/d) + |Y|^(1/d), whose gap grows with d when the two
+// clusters' covariances are ill-conditioned in different directions
+constexpr int MERGE_BOUND_MAX_D = 16;
+// list mode (list != nullptr): the items list_base + list[q] for q < *list_count
+// (n_items bounds the grid)
 hipError_t launch_logml_gauss(int n_items, const LogmlItem* items, int d, NiwPriorDev prior,
                               double logdet_psi, const long long* counts, const double* moments,
-                              double* scratch, double* out, int* err, hipStream_t s);
-// accept[p] = merge test of pair item pairs[p] (see k_merge_decide)
+                              double* scratch, double* out, int* err, hipStream_t s, const int* list = nullptr,
+                              const int* list_count = nullptr, int list_base = 0);
+// the merge bound: accept[p] = 0 for the pairs it rejects, the others listed
+// (list, *list_count) for their log marginal and k_merge_decide
+hipError_t launch_merge_prune(int n_pairs, const LogmlItem* pairs, int d, NiwPriorDev prior, double logdet_psi,
+                              double lam_psi, const long long* counts, const double* moments, const double* lml_cluster,
+                              const double* logdet_half, double alpha, bool paper_form, uint64_t seed, uint32_t t,
+                              unsigned char* accept, int* list, int* list_count, hipStream_t s);
+// accept[p] = merge test of pair item pairs[p] (see k_merge_decide); list mode as above
 hipError_t launch_merge_decide(int n_pairs, const LogmlItem* pairs, const long long* counts, const double* lml_cluster,
                                const double* lml_pair, double alpha, bool paper_form, uint64_t seed, uint32_t t,
-                               unsigned char* accept, hipStream_t s);
+                               unsigned char* accept, hipStream_t s, const int* list = nullptr,
+                               const int* list_count = nullptr);
 // [error flag, 8 bytes][counts 2K int64][3K log marginals float64][P merge decisions] in one buffer
 size_t readback_bytes(int K, int P);
 hipError_t launch_pack_readback(int K, int P, const long long* counts, const double* lml, const unsigned char* mflag,

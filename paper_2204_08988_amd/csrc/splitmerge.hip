@@ -57,18 +57,28 @@ __global__ void k_set_pair(int* p, int a, int b) {
   }
 }
 
+// Item it of a launch: it itself, or in list mode (list != nullptr) the
+// base + list[q]-th item for q < *list_count (the survivors of the merge bound).
+__device__ __forceinline__ int logml_item(int q, int n_items, const int* list, const int* list_count, int base) {
+  if (!list) return q < n_items ? q : -1;
+  return q < *list_count ? base + list[q] : -1;
+}
+
 __global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, int d, NiwPriorDev prior,
                               double logdet_psi, const long long* __restrict__ counts,
                               const double* __restrict__ moments, double* __restrict__ scratch,
-                              double* __restrict__ out, int* __restrict__ err) {
+                              double* __restrict__ out, int* __restrict__ err, const int* __restrict__ list,
+                              const int* __restrict__ list_count, int list_base) {
   extern __shared__ double lds_p[];
   __shared__ double red[BLOCK];
   __shared__ int flag;
-  const int it = blockIdx.x;
-  if (it >= n_items) return;
+  const int it = logml_item(blockIdx.x, n_items, list, list_count, list_base);
+  if (it < 0) return;
   const int tid = threadIdx.x;
   const int E = d + d * (d + 1) / 2;
   const LogmlItem item = items[it];
+  // bound item: log|Psi / 2 + C| of the union's scatter C (for the merge bound)
+  const bool bound = item.seg[3] == LOGML_BOUND;
   double n = 0.0;
   for (int q = 0; q < 4; ++q)
     if (item.seg[q] >= 0) n += (double)counts[item.seg[q]];
@@ -76,8 +86,9 @@ __global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, 
     if (tid == 0) out[it] = 0.0;
     return;
   }
-  double* P = d <= LOGML_LDS_MAX_D ? lds_p : scratch + (size_t)it * d * d;
+  double* P = d <= LOGML_LDS_MAX_D ? lds_p : scratch + (size_t)blockIdx.x * d * d;
   const double kn = prior.kappa + n, nun = prior.nu + n;
+  const double wpsi = bound ? 0.5 : 1.0, wmean = bound ? 0.0 : prior.kappa * n / kn;
   for (int idx = tid; idx < d * d; idx += BLOCK) {
     const int i = idx / d, j = idx % d;
     const int a = i < j ? i : j, b = i < j ? j : i;
@@ -91,7 +102,7 @@ __global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, 
       sj += M[j];
     }
     const double xi = si / n, xj = sj / n;
-    P[idx] = prior.psi[idx] + (S - n * xi * xj) + (prior.kappa * n / kn) * (xi - prior.m[i]) * (xj - prior.m[j]);
+    P[idx] = wpsi * prior.psi[idx] + (S - n * xi * xj) + wmean * (xi - prior.m[i]) * (xj - prior.m[j]);
   }
   __syncthreads();
   const bool ok = wg_cholesky(P, d, &flag);
@@ -105,8 +116,9 @@ __global__ void k_logml_gauss(int n_items, const LogmlItem* __restrict__ items, 
   lg = reduce_sum(lg, red);
   if (tid == 0) {
     if (!ok) atomicOr(err, 4);
-    out[it] = -0.5 * n * d * 1.1447298858494002 + lg + 0.5 * prior.nu * logdet_psi - 0.5 * nun * ld +
-              0.5 * d * (log(prior.kappa) - log(kn));
+    out[it] = bound ? ld
+                    : -0.5 * n * d * 1.1447298858494002 + lg + 0.5 * prior.nu * logdet_psi - 0.5 * nun * ld +
+                          0.5 * d * (log(prior.kappa) - log(kn));
   }
 }
 
@@ -120,14 +132,17 @@ __global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const L
                                                             NiwPriorDev prior, double logdet_psi,
                                                             const long long* __restrict__ counts,
                                                             const double* __restrict__ moments,
-                                                            double* __restrict__ out, int* __restrict__ err) {
+                                                            double* __restrict__ out, int* __restrict__ err,
+                                                            const int* __restrict__ list,
+                                                            const int* __restrict__ list_count, int list_base) {
   constexpr int ED = D + D * (D + 1) / 2;
   __shared__ double ssum[BLOCK / 64][ED];  // per wave: the item's summed statistics
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int it = blockIdx.x * (BLOCK / 64) + wave;
-  if (it >= n_items) return;
+  const int it = logml_item(blockIdx.x * (BLOCK / 64) + wave, n_items, list, list_count, list_base);
+  if (it < 0) return;
   const int E = d + d * (d + 1) / 2;
   const LogmlItem item = items[it];
+  const bool bound = item.seg[3] == LOGML_BOUND;  // log|Psi / 2 + C| (merge bound)
   const bool live = lane < d;
   // every load of the item in one round: its counts, the sum of its segments'
   // statistics (summed in segment order into the wave's LDS buffer) and the
@@ -157,8 +172,9 @@ __global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const L
     if (e < E) sm[e] = v;
   }
   double r[D];
+  const double wpsi = bound ? 0.5 : 1.0;
 #pragma unroll
-  for (int k = 0; k < D; ++k) r[k] = (k < d && live && k <= lane) ? prior.psi[lane * d + k] : 0.0;
+  for (int k = 0; k < D; ++k) r[k] = (k < d && live && k <= lane) ? wpsi * prior.psi[lane * d + k] : 0.0;
   double n = 0.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) n += nq[q];
@@ -166,7 +182,7 @@ __global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const L
     if (lane == 0) out[it] = 0.0;
     return;
   }
-  const double kn = prior.kappa + n, nun = prior.nu + n, cm = prior.kappa * n / kn;
+  const double kn = prior.kappa + n, nun = prior.nu + n, cm = bound ? 0.0 : prior.kappa * n / kn;
   wave_sync();
   const double si = live ? sm[lane] : 0.0;
   const double xi = si / n;
@@ -186,8 +202,150 @@ __global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const L
   const double lg = wave_sum(live ? lgamma_d(0.5 * nun - 0.5 * lane) - lgamma_d(0.5 * prior.nu - 0.5 * lane) : 0.0);
   if (lane == 0) {
     if (!ok) atomicOr(err, 4);
-    out[it] = -0.5 * n * d * 1.1447298858494002 + lg + 0.5 * prior.nu * logdet_psi - 0.5 * nun * ld +
-              0.5 * d * (log(prior.kappa) - log(kn));
+    out[it] = bound ? ld
+                    : -0.5 * n * d * 1.1447298858494002 + lg + 0.5 * prior.nu * logdet_psi - 0.5 * nun * ld +
+                          0.5 * d * (log(prior.kappa) - log(kn));
+  }
+}
+
+// 64 < d <= 128: one workgroup per item, Psi_n held in registers as the
+// 136 lower 8 x 8 tiles of a 128 x 128 matrix (d padded with an identity
+// block, whose pivots are 1), one tile per thread of the first 136.  Step j of
+// the right-looking Cholesky: the pivot's owner publishes L_jj, the owners of
+// column j scale it and publish it, and every thread updates its tile from
+// the published column -- two barriers per step, a 1 KB column buffer in LDS,
+// no strided LDS access.
+constexpr int TILE_T = 136;  // 16 * 17 / 2 lower tiles of 8 x 8
+
+__global__ __launch_bounds__(BLOCK) void k_logml_gauss_tile(int n_items, const LogmlItem* __restrict__ items, int d,
+                                                            NiwPriorDev prior, double logdet_psi,
+                                                            const long long* __restrict__ counts,
+                                                            const double* __restrict__ moments,
+                                                            double* __restrict__ out, int* __restrict__ err,
+                                                            const int* __restrict__ list,
+                                                            const int* __restrict__ list_count, int list_base) {
+  constexpr int DP = 128, T = 8;
+  __shared__ double xbar[DP], col[DP], red[BLOCK];
+  __shared__ double piv;
+  __shared__ int bad;
+  const int it = logml_item(blockIdx.x, n_items, list, list_count, list_base);
+  if (it < 0) return;
+  const int tid = threadIdx.x;
+  const int E = d + d * (d + 1) / 2;
+  const LogmlItem item = items[it];
+  const bool bound = item.seg[3] == LOGML_BOUND;  // log|Psi / 2 + C| (merge bound)
+  double n = 0.0;
+  for (int q = 0; q < 4; ++q)
+    if (item.seg[q] >= 0) n += (double)counts[item.seg[q]];
+  if (n == 0.0) {
+    if (tid == 0) out[it] = 0.0;
+    return;
+  }
+  const double kn = prior.kappa + n, nun = prior.nu + n;
+  const double wpsi = bound ? 0.5 : 1.0, wmean = bound ? 0.0 : prior.kappa * n / kn;
+  if (tid < DP) {
+    double si = 0.0;
+    if (tid < d)
+      for (int q = 0; q < 4; ++q)
+        if (item.seg[q] >= 0) si += moments[(size_t)item.seg[q] * E + tid];
+    xbar[tid] = si / n;
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  // this thread's tile (TR, TC), TR >= TC
+  int TR = 0, TC = 0;
+  {
+    int u = tid < TILE_T ? tid : 0;
+    while (u > TR) {
+      u -= TR + 1;
+      ++TR;
+    }
+    TC = u;
+  }
+  const bool owner = tid < TILE_T;
+  double a[T][T];
+#pragma unroll
+  for (int r = 0; r < T; ++r)
+#pragma unroll
+    for (int c = 0; c < T; ++c) {
+      const int i = T * TR + r, k = T * TC + c;
+      double v = 0.0;
+      if (owner && k <= i) {
+        if (i < d) {
+          const int lo = k, hi = i;  // k <= i: packed upper-triangle entry (k, i)
+          double S = 0.0;
+          for (int q = 0; q < 4; ++q)
+            if (item.seg[q] >= 0) S += moments[(size_t)item.seg[q] * E + d + tri_index(lo, hi, d)];
+          const double xi = xbar[i], xk = xbar[k];
+          v = wpsi * prior.psi[i * d + k] + (S - n * xi * xk) + wmean * (xi - prior.m[i]) * (xk - prior.m[k]);
+        } else {
+          v = i == k ? 1.0 : 0.0;  // the identity padding
+        }
+      }
+      a[r][c] = v;
+    }
+  double ld = 0.0;  // sum of log L_jj over this thread's pivots
+  for (int j = 0; j < DP; ++j) {
+    const int jt = j >> 3, jr = j & 7;
+    // the pivot
+    if (owner && TR == jt && TC == jt) {
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < T; ++r) s = r == jr ? a[r][r] : s;
+      if (!(s > 0.0) || !isfinite(s)) {
+        bad = 1;
+        s = 1.0;
+      }
+      const double l = sqrt(s);
+      piv = l;
+      ld += log(l);
+    }
+    __syncthreads();
+    // column j below the pivot: scaled by 1 / L_jj, kept and published
+    if (owner && TC == jt && TR >= jt) {
+      const double inv = 1.0 / piv;
+#pragma unroll
+      for (int r = 0; r < T; ++r) {
+        const int i = T * TR + r;
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < T; ++c) v = c == jr ? a[r][c] : v;
+        v *= inv;
+#pragma unroll
+        for (int c = 0; c < T; ++c)
+          if (c == jr && i > j) a[r][c] = v;
+        if (i > j) col[i] = v;
+      }
+    }
+    __syncthreads();
+    // trailing update of the tile: a_ik -= L_ij L_kj for j < k <= i
+    if (owner && TC >= jt) {
+      double ci[T], ck[T];
+#pragma unroll
+      for (int r = 0; r < T; ++r) ci[r] = col[T * TR + r];
+#pragma unroll
+      for (int c = 0; c < T; ++c) ck[c] = col[T * TC + c];
+#pragma unroll
+      for (int r = 0; r < T; ++r)
+#pragma unroll
+        for (int c = 0; c < T; ++c) {
+          const int i = T * TR + r, k = T * TC + c;
+          if (k > j && k <= i) a[r][c] = fma(-ci[r], ck[c], a[r][c]);
+        }
+    }
+    // the next step's column writes wait for its first barrier: every thread
+    // has read this column by then
+  }
+  // log|Psi_n| = 2 sum log L_jj; log Gamma_d(nu_n / 2) - log Gamma_d(nu / 2)
+  double lg = 0.0;
+  for (int i = tid; i < d; i += BLOCK) lg += lgamma_d(0.5 * nun - 0.5 * i) - lgamma_d(0.5 * prior.nu - 0.5 * i);
+  const double ldet = 2.0 * reduce_sum(ld, red);
+  lg = reduce_sum(lg, red);
+  if (tid == 0) {
+    if (bad) atomicOr(err, 4);
+    out[it] = bound ? ldet
+                    : -0.5 * n * d * 1.1447298858494002 + lg + 0.5 * prior.nu * logdet_psi - 0.5 * nun * ldet +
+                          0.5 * d * (log(prior.kappa) - log(kn));
   }
 }
 
@@ -216,12 +374,86 @@ __global__ void k_pack_readback(int K, int P, const long long* __restrict__ coun
 // item pairs[p] = (2 k1, 2 k1 + 1, 2 k2, 2 k2 + 1) with union marginal
 // lml_pair[p]; lml_cluster[3 k] is cluster k's marginal.  accept[p] = 1 when
 // log u < log H_merge with u the merge uniform of (k1, k2).
+// log Gamma_d(a) - log Gamma_d(b) = sum_{j < d} lgamma(a - j/2) - lgamma(b - j/2)
+__device__ double lmultigamma_diff(double a, double b, int d) {
+  double s = 0.0;
+  for (int j = 0; j < d; ++j) s += lgamma_d(a - 0.5 * j) - lgamma_d(b - 0.5 * j);
+  return s;
+}
+
+// The merge bound (Gaussian family): for the pair (k1, k2) with union U,
+//   Psi_n(U) >= X + Y + b b^T,  X = Psi/2 + C1, Y = Psi/2 + C2 (scatters about
+//   the clusters' means), b = sqrt(n1 n2 / n) (xbar1 - xbar2);
+//   log|X + Y| >= d log(|X|^(1/d) + |Y|^(1/d)) (Minkowski's determinant inequality),
+//   b^T (X + Y)^-1 b >= |b|^2 / (lambda_max(Psi) + tr C1 + tr C2),
+// give a lower bound LB on log|Psi_n(U)|, so an upper bound on the NIW
+// marginal of U and on log H_merge.  A pair whose bound (plus a rounding
+// margin) lies below log u is rejected here: exactly the decision its full
+// ratio would give.  Every other pair is listed for its log marginal and
+// k_merge_decide.  logdet_half[k] = log|Psi/2 + C_k|; lam_psi >= lambda_max(Psi).
+__global__ void k_merge_prune(int n_pairs, const LogmlItem* __restrict__ pairs, int d, NiwPriorDev prior,
+                              double logdet_psi, double lam_psi, const long long* __restrict__ counts,
+                              const double* __restrict__ moments, const double* __restrict__ lml_cluster,
+                              const double* __restrict__ logdet_half, double alpha, int paper_form, uint64_t seed,
+                              uint32_t t, unsigned char* __restrict__ accept, int* __restrict__ list,
+                              int* __restrict__ list_count) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  const LogmlItem it = pairs[p];
+  const int k1 = it.seg[0] >> 1, k2 = it.seg[2] >> 1;
+  const int E = d + d * (d + 1) / 2;
+  const double n1 = (double)(counts[2 * k1] + counts[2 * k1 + 1]);
+  const double n2 = (double)(counts[2 * k2] + counts[2 * k2 + 1]);
+  const double n = n1 + n2;
+  const double* A0 = moments + (size_t)(2 * k1) * E;
+  const double* A1 = A0 + E;
+  const double* B0 = moments + (size_t)(2 * k2) * E;
+  const double* B1 = B0 + E;
+  // tr C_k = sum_i S_ii - |s|^2 / n_k, and |xbar1 - xbar2|^2
+  double tr1 = 0.0, tr2 = 0.0, ss1 = 0.0, ss2 = 0.0, dx2 = 0.0;
+  for (int i = 0; i < d; ++i) {
+    const int di = d + tri_index(i, i, d);
+    const double s1 = A0[i] + A1[i], s2 = B0[i] + B1[i];
+    tr1 += A0[di] + A1[di];
+    tr2 += B0[di] + B1[di];
+    ss1 += s1 * s1;
+    ss2 += s2 * s2;
+    const double dd = s1 / n1 - s2 / n2;
+    dx2 += dd * dd;
+  }
+  tr1 = fmax(tr1 - ss1 / n1, 0.0);
+  tr2 = fmax(tr2 - ss2 / n2, 0.0);
+  const double a = logdet_half[k1] / d, c = logdet_half[k2] / d;
+  const double lb = d * (fmax(a, c) + log1p(exp(-fabs(a - c)))) + log1p(n1 * n2 / n * dx2 / (lam_psi + tr1 + tr2));
+  const double nun = prior.nu + n, kn = prior.kappa + n;
+  const double lmg = lmultigamma_diff(0.5 * nun, 0.5 * prior.nu, d);
+  const double ub_u = -0.5 * n * d * 1.1447298858494002 + lmg + 0.5 * prior.nu * logdet_psi - 0.5 * nun * lb +
+                      0.5 * d * (log(prior.kappa) - log(kn));
+  double g = lgamma_d(n) - log(alpha) - lgamma_d(n1) - lgamma_d(n2);
+  if (paper_form)
+    g += lgamma_d(alpha) - lgamma_d(alpha + n) + lgamma_d(0.5 * alpha + n1) + lgamma_d(0.5 * alpha + n2) -
+         2.0 * lgamma_d(0.5 * alpha);
+  const double l1 = lml_cluster[3 * k1], l2 = lml_cluster[3 * k2];
+  const double ub = g + ub_u - l1 - l2;
+  // float64 rounding of the terms above (and of the Cholesky factorisations behind them)
+  const double margin = 1e-9 * (fabs(g) + fabs(lmg) + 0.5 * nun * fabs(lb) + 0.5 * n * d * 1.15 + fabs(l1) + fabs(l2) +
+                                0.5 * prior.nu * fabs(logdet_psi)) + 1e-6;
+  const double u = uniform_d(rng_block(seed, t, merge_entity(k1, k2), TAG_MERGE, 0).x);
+  if (ub + margin < log(u)) {
+    accept[p] = 0;
+  } else {
+    list[atomicAdd(list_count, 1)] = p;  // the order of the list does not matter: one result per pair
+  }
+}
+
 __global__ void k_merge_decide(int n_pairs, const LogmlItem* __restrict__ pairs, const long long* __restrict__ counts,
                                const double* __restrict__ lml_cluster, const double* __restrict__ lml_pair,
                                double alpha, int paper_form, uint64_t seed, uint32_t t,
-                               unsigned char* __restrict__ accept) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_pairs) return;
+                               unsigned char* __restrict__ accept, const int* __restrict__ list,
+                               const int* __restrict__ list_count) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = list ? (q < *list_count ? list[q] : -1) : (q < n_pairs ? q : -1);
+  if (p < 0) return;
   const LogmlItem it = pairs[p];
   const int k1 = it.seg[0] >> 1, k2 = it.seg[2] >> 1;
   const double n1 = (double)(counts[2 * k1] + counts[2 * k1 + 1]);
@@ -312,27 +544,43 @@ hipError_t launch_zero64(void* p, size_t n_words, hipStream_t s) {
 
 hipError_t launch_logml_gauss(int n_items, const LogmlItem* items, int d, NiwPriorDev prior, double logdet_psi,
                               const long long* counts, const double* moments, double* scratch, double* out,
-                              int* err, hipStream_t s) {
+                              int* err, hipStream_t s, const int* list, const int* list_count, int list_base) {
   if (n_items == 0) return hipSuccess;
   const dim3 wg((n_items + BLOCK / 64 - 1) / (BLOCK / 64));
+#define DPMM_LOGML_WAVE(DD)                                                                                         \
+  hipLaunchKernelGGL(k_logml_gauss_wave<DD>, wg, dim3(BLOCK), 0, s, n_items, items, d, prior, logdet_psi, counts, \
+                     moments, out, err, list, list_count, list_base);                                             \
+  return hipGetLastError();
   if (d <= 16) {
-    hipLaunchKernelGGL(k_logml_gauss_wave<16>, wg, dim3(BLOCK), 0, s, n_items, items, d, prior, logdet_psi, counts,
-                       moments, out, err);
-    return hipGetLastError();
+    DPMM_LOGML_WAVE(16)
   }
   if (d <= 32) {
-    hipLaunchKernelGGL(k_logml_gauss_wave<32>, wg, dim3(BLOCK), 0, s, n_items, items, d, prior, logdet_psi, counts,
-                       moments, out, err);
-    return hipGetLastError();
+    DPMM_LOGML_WAVE(32)
   }
   if (d <= 64) {
-    hipLaunchKernelGGL(k_logml_gauss_wave<64>, wg, dim3(BLOCK), 0, s, n_items, items, d, prior, logdet_psi, counts,
-                       moments, out, err);
+    DPMM_LOGML_WAVE(64)
+  }
+#undef DPMM_LOGML_WAVE
+  if (d <= 128) {
+    hipLaunchKernelGGL(k_logml_gauss_tile, dim3(n_items), dim3(BLOCK), 0, s, n_items, items, d, prior, logdet_psi,
+                       counts, moments, out, err, list, list_count, list_base);
     return hipGetLastError();
   }
   const size_t lds = d <= LOGML_LDS_MAX_D ? (size_t)d * d * sizeof(double) : 0;
   hipLaunchKernelGGL(k_logml_gauss, dim3(n_items), dim3(BLOCK), lds, s, n_items, items, d, prior, logdet_psi,
-                     counts, moments, scratch, out, err);
+                     counts, moments, scratch, out, err, list, list_count, list_base);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_prune(int n_pairs, const LogmlItem* pairs, int d, NiwPriorDev prior, double logdet_psi,
+                              double lam_psi, const long long* counts, const double* moments, const double* lml_cluster,
+                              const double* logdet_half, double alpha, bool paper_form, uint64_t seed, uint32_t t,
+                              unsigned char* accept, int* list, int* list_count, hipStream_t s) {
+  hipError_t e = launch_zero64(list_count, 1, s);
+  if (e != hipSuccess || n_pairs == 0) return e;
+  hipLaunchKernelGGL(k_merge_prune, dim3((n_pairs + 63) / 64), dim3(64), 0, s, n_pairs, pairs, d, prior, logdet_psi,
+                     lam_psi, counts, moments, lml_cluster, logdet_half, alpha, paper_form ? 1 : 0, seed, t, accept,
+                     list, list_count);
   return hipGetLastError();
 }
 
@@ -347,10 +595,10 @@ hipError_t launch_logml_mult(int n_items, const LogmlItem* items, int V, const d
 
 hipError_t launch_merge_decide(int n_pairs, const LogmlItem* pairs, const long long* counts, const double* lml_cluster,
                                const double* lml_pair, double alpha, bool paper_form, uint64_t seed, uint32_t t,
-                               unsigned char* accept, hipStream_t s) {
+                               unsigned char* accept, hipStream_t s, const int* list, const int* list_count) {
   if (n_pairs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_merge_decide, dim3((n_pairs + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, n_pairs, pairs, counts,
-                     lml_cluster, lml_pair, alpha, paper_form ? 1 : 0, seed, t, accept);
+                     lml_cluster, lml_pair, alpha, paper_form ? 1 : 0, seed, t, accept, list, list_count);
   return hipGetLastError();
 }
 

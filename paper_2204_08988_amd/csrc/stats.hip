@@ -28,9 +28,10 @@ constexpr int LDS_BUDGET = 64 * 1024;
 
 // Per-lane float64 accumulators [2K][1 + E][L] (entry-major, so the lanes of
 // one access hit distinct banks); lane l of workgroup g adds the points
-// i = (g L + l) + j G L in increasing j, eight loads in flight.  Then a fixed
-// tree over the lanes, and the workgroup's row part[g][2K (1 + E)] (entry 0 of
-// a segment is its count).
+// i = (g L + l) + j G L in increasing j.  The next U points' loads are issued
+// before the current U are added (one workgroup per CU leaves few waves to
+// hide the memory latency).  Then a fixed tree over the lanes, and the
+// workgroup's row part[g][2K (1 + E)] (entry 0 of a segment is its count).
 template <int D, int L>
 __global__ __launch_bounds__(L) void k_stats_small(const float* __restrict__ x, long long n,
                                                    const int* __restrict__ z, const unsigned char* __restrict__ zsub,
@@ -42,9 +43,9 @@ __global__ __launch_bounds__(L) void k_stats_small(const float* __restrict__ x, 
   const int lane = threadIdx.x;
   for (int e = 0; e < NE; ++e) acc[(size_t)e * L + lane] = 0.0;
   const long long stride = (long long)gridDim.x * L;
-  for (long long i0 = (long long)blockIdx.x * L + lane; i0 < n; i0 += U * stride) {
-    int seg[U];
-    float xv[U][D];
+  int seg[U];
+  float xv[U][D];
+  auto load = [&](long long i0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const long long i = i0 + u * stride;
@@ -58,18 +59,31 @@ __global__ __launch_bounds__(L) void k_stats_small(const float* __restrict__ x, 
         for (int j = 0; j < D; ++j) xv[u][j] = x[i * D + j];
       }
     }
+  };
+  long long i0 = (long long)blockIdx.x * L + lane;
+  if (i0 < n) load(i0);
+  for (; i0 < n; i0 += U * stride) {
+    int cs[U];
+    float cx[U][D];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (seg[u] < 0) continue;
-      double* a = acc + (size_t)seg[u] * E1 * L + lane;
+      cs[u] = seg[u];
+#pragma unroll
+      for (int j = 0; j < D; ++j) cx[u][j] = xv[u][j];
+    }
+    if (i0 + U * stride < n) load(i0 + U * stride);  // in flight while the current points are added
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (cs[u] < 0) continue;
+      double* a = acc + (size_t)cs[u] * E1 * L + lane;
       a[0] += 1.0;
 #pragma unroll
-      for (int j = 0; j < D; ++j) a[(size_t)(1 + j) * L] += (double)xv[u][j];
+      for (int j = 0; j < D; ++j) a[(size_t)(1 + j) * L] += (double)cx[u][j];
       int e = 1 + D;
 #pragma unroll
       for (int p = 0; p < D; ++p)
 #pragma unroll
-        for (int q = p; q < D; ++q, ++e) a[(size_t)e * L] += (double)xv[u][p] * (double)xv[u][q];
+        for (int q = p; q < D; ++q, ++e) a[(size_t)e * L] += (double)cx[u][p] * (double)cx[u][q];
     }
   }
 #pragma unroll

@@ -296,3 +296,39 @@ def test_mult_params_and_split_merge():
     assert gi["K"] == refs.K and gi["merges"] == info.merges and gi["splits"] == info.splits
     assert np.array_equal(zt.cpu().numpy(), refs.z) and np.array_equal(zst.cpu().numpy(), refs.zsub)
     S.close()
+
+
+@pytest.mark.parametrize("d,K,n", [(2, 12, 3000), (20, 9, 4000), (64, 8, 3000), (128, 6, 2500)])
+def test_gauss_merges_with_the_merge_bound(d, K, n):
+    """Many clusters over three true groups: the fragments of one group are
+    merge candidates, the rest are pruned by the merge bound.  The GPU's split /
+    merge phase must take exactly the oracle's decisions (the oracle computes
+    every pair's ratio in full)."""
+    torch = _torch()
+    g = np.random.Generator(np.random.PCG64(600 + d))
+    grp = g.integers(0, 3, n)
+    centres = g.normal(0, 6.0, size=(3, d))
+    x = (centres[grp] + g.standard_normal((n, d))).astype(np.float32)
+    # clusters: random fragments of the groups (each cluster within one group)
+    z = np.where(grp == 0, g.integers(0, K // 3, n), np.where(grp == 1, K // 3 + g.integers(0, K // 3, n),
+                                                                 2 * (K // 3) + g.integers(0, K - 2 * (K // 3), n)))
+    zs = g.integers(0, 2, n)
+    seed, t = 17 + d, 3
+    prior = niw.NIWPrior(1.0, np.zeros(d), d + 3.0, np.eye(d))
+    for form in ("paper", "inverse_split"):
+        model = sampler.Model("gaussian", 1.0, prior, seed=seed, burn_out=1, merge_form=form)
+        state = sampler.State(K, z.copy(), zs.copy(), np.full(K, 2))
+        st0, stats = sampler.drop_empty(model, x, state)
+        ref, info = sampler.split_merge(model, st0, stats, t)
+        S = _gauss_sampler(d, 2 * K, seed, alpha=1.0, burn_out=1, merge_form=form)
+        zt = torch.from_numpy(z.astype(np.int32)).cuda()
+        zst = torch.from_numpy(zs.astype(np.uint8)).cuda()
+        xt = torch.from_numpy(x).cuda()
+        S.set_state(K, [2] * K)
+        S.suffstats(xt, zt, zst)
+        gi = S.split_merge(xt, t, zt, zst)
+        assert (gi["K"], gi["splits"], gi["merges"]) == (ref.K, info.splits, info.merges)
+        assert np.array_equal(zt.cpu().numpy(), ref.z) and np.array_equal(zst.cpu().numpy(), ref.zsub)
+        if form == "paper":
+            assert info.merges >= 1
+        S.close()
