@@ -25,5 +25,6 @@ sampler   one sampler iteration and its parts (weights, params, labels,
 partitions  exact posterior over set partitions and Neal's Algorithm 3, used
           to check the whole chain on tiny inputs.
 mlp       float64 MLP forward/backward for the learned split proposal.
+poisson   Poisson components with a Gamma prior (marginal, draws, log-likelihood).
 nmi       normalised mutual information.
 """

@@ -39,12 +39,12 @@ from dataclasses import dataclass, field
 import numpy as np
 from scipy.special import gammaln, logsumexp
 
-from . import dirmult, niw, rng
+from . import dirmult, niw, poisson, rng
 
 
 @dataclass
 class Model:
-    family: str            # "gaussian" or "multinomial"
+    family: str            # "gaussian", "multinomial" or "poisson"
     alpha: float
     prior: object          # niw.NIWPrior or dirmult.DirPrior
     seed: int
@@ -65,7 +65,7 @@ class Stats:
     """Per sub-cluster statistics; a cluster's statistics are the sum of its two.
 
     Gaussian: n[K,2], s[K,2,d] = sum x, S[K,2,d,d] = sum x x^T.
-    Multinomial: n[K,2] point counts, s[K,2,V] summed counts (S unused).
+    Multinomial and Poisson: n[K,2] point counts, s[K,2,V] summed counts (S unused).
     """
     n: np.ndarray
     s: np.ndarray
@@ -149,6 +149,8 @@ def suffstats(model, x, z, zsub, K):
 def log_marginal(model, n, s, S):
     if model.family == "gaussian":
         return niw.log_marginal(model.prior, n, s, S)
+    if model.family == "poisson":
+        return poisson.log_marginal(model.prior, n, s)
     return dirmult.log_marginal(model.prior, s) if n > 0 else 0.0
 
 
@@ -192,7 +194,10 @@ def sample_params(model, stats, t):
     for k in range(K):
         comps = [stats.cluster(k), stats.sub(k, 0), stats.sub(k, 1)]
         for c, (n, s, _) in enumerate(comps):
-            lt[k, c] = dirmult.sample_log_theta(model.prior, s, model.seed, t, 3 * k + c)
+            if model.family == "poisson":  # log lambda (rates) in place of log theta
+                lt[k, c] = poisson.sample_log_lambda(model.prior, n, s, model.seed, t, 3 * k + c)
+            else:
+                lt[k, c] = dirmult.sample_log_theta(model.prior, s, model.seed, t, 3 * k + c)
     return Params(log_pi, log_pisub, log_theta=lt)
 
 
@@ -203,6 +208,8 @@ def sample_params(model, stats, t):
 def component_loglik(model, x, params, k, c):
     if model.family == "gaussian":
         return niw.logpdf(x, params.mu[k, c], params.sigma[k, c])
+    if model.family == "poisson":
+        return poisson.loglik(x, params.log_theta[k, c])
     return dirmult.loglik(x, params.log_theta[k, c])
 
 

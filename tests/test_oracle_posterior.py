@@ -5,8 +5,8 @@ proposal's training set, each against a quantity computed another way.
   + sum_k [lgamma(N_k) + log f(C_k)] is checked against the Chinese-restaurant
   seating product (points arrive one at a time: an occupied table c with
   probability n_c / (alpha + i), a new one with alpha / (alpha + i)) times the
-  marginal likelihoods, for every partition of N = 5 points, NIW and
-  Dirichlet-multinomial; and its differences between partitions against the
+  marginal likelihoods, for every partition of N = 5 points, NIW,
+  Dirichlet-multinomial and Gamma-Poisson; and its differences between partitions against the
   log-ratios of the enumerated exact posterior (Sec. 2.2 model, pi and the
   component parameters integrated out).
 * compact() on a deletion in the middle of the cluster range: the surviving
@@ -17,7 +17,7 @@ proposal's training set, each against a quantity computed another way.
 import numpy as np
 import pytest
 
-from oracle import dirmult, learned, niw, partitions, sampler
+from oracle import dirmult, learned, niw, partitions, poisson, sampler
 
 
 def _crp_log_prior(z, alpha):
@@ -41,7 +41,16 @@ MX = np.array([[3, 0, 1], [2, 1, 0], [0, 4, 1], [0, 3, 2], [1, 1, 5]])
 MPRIOR = dirmult.DirPrior([0.5, 1.0, 2.0])
 
 
+PPRIOR = poisson.GammaPrior([1.5, 0.5, 2.0], [1.0, 0.3, 2.0])
+
+
 def _family(name):
+    if name == "poisson":
+        model = sampler.Model("poisson", 1.7, PPRIOR, seed=1, burn_out=0)
+
+        def lm(rows):
+            return poisson.log_marginal(PPRIOR, len(rows), MX[rows].sum(0))
+        return model, MX, lm
     if name == "gaussian":
         model = sampler.Model("gaussian", 1.7, GPRIOR, seed=1, burn_out=0)
 
@@ -56,7 +65,7 @@ def _family(name):
     return model, MX, lm
 
 
-@pytest.mark.parametrize("family", ["gaussian", "multinomial"])
+@pytest.mark.parametrize("family", ["gaussian", "multinomial", "poisson"])
 def test_log_posterior_is_crp_seating_times_marginals(family):
     model, x, lm = _family(family)
     zsub = np.array([0, 1, 0, 1, 1])
@@ -68,7 +77,7 @@ def test_log_posterior_is_crp_seating_times_marginals(family):
         assert abs(lp - ref) <= 1e-11 * (1 + abs(ref)), part
 
 
-@pytest.mark.parametrize("family", ["gaussian", "multinomial"])
+@pytest.mark.parametrize("family", ["gaussian", "multinomial", "poisson"])
 def test_log_posterior_differences_match_enumerated_posterior(family):
     model, x, lm = _family(family)
     ex = partitions.exact_posterior(x, model.alpha, lm)
