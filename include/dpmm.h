@@ -13,7 +13,7 @@
  *     memory, e.g. torch tensors).  The context owns everything else (packed
  *     parameters, statistics, scratch) and frees it in dpmm_destroy.
  *   - Layout: x is point-major (row-major) N x d float32 (Gaussian) or
- *     N x V int32 counts (multinomial); z is int32[N] with clusters 0..K-1;
+ *     N x V int32 counts (multinomial, Poisson); z is int32[N] with clusters 0..K-1;
  *     zsub is uint8[N] with 0 = left (l), 1 = right (r) sub-cluster.  Every
  *     call taking n accepts 0 <= n < 2^31 (device point indices are int32)
  *     and returns DPMM_E_SHAPE otherwise.
@@ -65,15 +65,18 @@ enum {
   DPMM_E_STATE = -7     /* call out of order (no parameters / statistics yet) */
 };
 
-enum { DPMM_GAUSSIAN = 0, DPMM_MULTINOMIAL = 1 };
+enum { DPMM_GAUSSIAN = 0, DPMM_MULTINOMIAL = 1, DPMM_POISSON = 2 };
 enum { DPMM_FP32 = 0, DPMM_BF16 = 1, DPMM_BF16X3 = 2 };
 enum { DPMM_MERGE_PAPER = 0, DPMM_MERGE_INVERSE_SPLIT = 1 };
 
 /* Model and capacity (Sec. 2.2 model; NIW prior of Sec. 2.2 Example;
- * Dirichlet prior for multinomial components, Sec. 2.1). */
+ * Dirichlet prior for multinomial components, Sec. 2.1).  DPMM_POISSON is a
+ * further exponential family on the same template (Sec. 3.4 names Poisson as
+ * the example of one): a component is a product of independent Poisson
+ * counts with rates lambda_v ~ Gamma(gamma_shape_v, gamma_rate_v). */
 typedef struct {
-  int32_t family;     /* DPMM_GAUSSIAN or DPMM_MULTINOMIAL */
-  int32_t d;          /* data dimension d (Gaussian) or vocabulary size V */
+  int32_t family;     /* DPMM_GAUSSIAN, DPMM_MULTINOMIAL or DPMM_POISSON */
+  int32_t d;          /* data dimension d (Gaussian, Poisson) or vocabulary size V */
   int32_t k_max;      /* capacity in clusters, 1 <= k_max <= 4096 */
   int32_t burn_out;   /* a cluster younger than this many iterations may not
                          split or merge (>= 0) */
@@ -100,6 +103,8 @@ typedef struct {
                          family only.  F = 2m network inputs.  When on,
                          dpmm_step makes one learned move after the split /
                          merge phase */
+  const double* gamma_shape; /* host [d]: Gamma prior shapes, > 0 (Poisson; copied) */
+  const double* gamma_rate;  /* host [d]: Gamma prior rates, > 0 (Poisson; copied) */
 } dpmm_config;
 
 /* What one iteration did (filled by dpmm_split_merge and dpmm_step). */
@@ -166,7 +171,8 @@ dpmm_status dpmm_get_state(dpmm_ctx* ctx, int32_t* K, int32_t* age);
  *   log_pisub host double[K][2]    log sub-cluster weights (l, r)
  *   comp      host double[K][3][P] component c = 0 (cluster), 1 (sub l),
  *             2 (sub r) of cluster k; Gaussian P = d + d*d: mean (d) then
- *             covariance Sigma (d*d row-major SPD); multinomial P = V: log theta.
+ *             covariance Sigma (d*d row-major SPD); multinomial P = V: log theta;
+ *             Poisson P = d: log lambda (log rates).
  * dpmm_set_params packs the float32 scoring tables on the device (Cholesky
  * of Sigma in float64, whitener W = L^-1, constant log w - 1/2 log|Sigma|
  * - d/2 log 2 pi); a covariance that is not positive definite gives
@@ -177,7 +183,7 @@ dpmm_status dpmm_get_params(dpmm_ctx* ctx, double* log_pi, double* log_pisub, do
 
 /* Sufficient statistics per sub-cluster (Sec. 4.4 statistics update).
  * Gaussian: host double[K][2][1 + d + d*d] = (n, sum x, sum x x^T row-major).
- * Multinomial: host int64[K][2][1 + V] = (n, summed counts).
+ * Multinomial and Poisson: host int64[K][2][1 + V] = (n, summed counts).
  * A cluster's statistics are the sum of its two sub-clusters'. */
 dpmm_status dpmm_set_stats(dpmm_ctx* ctx, int32_t K, const void* stats);
 dpmm_status dpmm_get_stats(dpmm_ctx* ctx, void* stats);
@@ -185,8 +191,9 @@ dpmm_status dpmm_get_stats(dpmm_ctx* ctx, void* stats);
 /* Weighted component log-likelihoods under the current packed parameters:
  * out device float[n][3K]: out[i][k] = log pi_k + log f(x_i; theta_k) for
  * k < K, out[i][K + 2k + h] = log pi-bar_kh + log f(x_i; theta-bar_kh).
- * Multinomial log-likelihoods omit the multinomial coefficient (the same for
- * every component).  Sec. 4.1 eqs. sample_labels / sample_sub_labels. */
+ * Multinomial log-likelihoods omit the multinomial coefficient and Poisson
+ * ones the factor prod 1 / x_v! (the same for every component).  Sec. 4.1
+ * eqs. sample_labels / sample_sub_labels. */
 dpmm_status dpmm_loglik(dpmm_ctx* ctx, const void* x, int64_t n, float* out);
 
 /* Steps (e) and (f) of Sec. 4.1: z_i = argmax_k (log pi_k + log f(x_i; theta_k)
@@ -220,7 +227,8 @@ dpmm_status dpmm_suffstats_static(dpmm_ctx* ctx, const void* x, int64_t n, const
 /* Steps (a)-(d) of Sec. 4.1 from the context's statistics, in float64 on the
  * device: (pi_1..pi_K, rest) ~ Dir(N_1..N_K, alpha); (pi-bar_kl, pi-bar_kr) ~
  * Dir(N_kl + alpha/2, N_kr + alpha/2); component parameters from their
- * conjugate posteriors (NIW by Bartlett's construction; Dirichlet).  Then the
+ * conjugate posteriors (NIW by Bartlett's construction; Dirichlet; Gamma
+ * rates Gamma(a_v + c_v, b_v + n)).  Then the
  * float32 scoring tables are packed.  Every cluster must be non-empty
  * (DPMM_E_STATE otherwise). */
 dpmm_status dpmm_sample_params(dpmm_ctx* ctx, uint32_t t);

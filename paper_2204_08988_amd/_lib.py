@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libdpmm.so")
 DPMM_OK = 0
 STATUS = {0: "DPMM_OK", -1: "DPMM_E_ARG", -2: "DPMM_E_SHAPE", -3: "DPMM_E_CAPACITY",
           -4: "DPMM_E_NUMERIC", -5: "DPMM_E_DEVICE", -6: "DPMM_E_OOM", -7: "DPMM_E_STATE"}
-GAUSSIAN, MULTINOMIAL = 0, 1
+GAUSSIAN, MULTINOMIAL, POISSON = 0, 1, 2
 FP32, BF16, BF16X3 = 0, 1, 2
 MERGE_PAPER, MERGE_INVERSE_SPLIT = 0, 1
 
@@ -36,7 +36,8 @@ class Config(ctypes.Structure):
         ("nu", ctypes.c_double), ("m", ctypes.POINTER(ctypes.c_double)),
         ("psi", ctypes.POINTER(ctypes.c_double)), ("beta", ctypes.POINTER(ctypes.c_double)),
         ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32), ("merge_form", ctypes.c_int32),
-        ("learned", ctypes.c_int32),
+        ("learned", ctypes.c_int32), ("gamma_shape", ctypes.POINTER(ctypes.c_double)),
+        ("gamma_rate", ctypes.POINTER(ctypes.c_double)),
     ]
 
 

@@ -1,12 +1,12 @@
 // dpmm_fit: the command-line run of the sampler (the paper's command-line
 // interface, Sec. 3.4) over the C ABI of libdpmm.so.
 //
-//   dpmm_fit --model_path=X.npy [--params_path=P.json] [--prior_type=Gaussian|Multinomial]
+//   dpmm_fit --model_path=X.npy [--params_path=P.json] [--prior_type=Gaussian|Multinomial|Poisson]
 //            [--gt_path=LABELS.npy] [--result_path=R.json] [--checkpoint_path=C.ckpt]
 //            [--resume_path=C.ckpt] [--check_config]
 //
 // X.npy: N x d float32/float64 (Gaussian) or N x V integer counts
-// (Multinomial), C order.  P.json: the configuration object (keys as in
+// (Multinomial, Poisson), C order.  P.json: the configuration object (keys as in
 // paper_2204_08988_amd/fit.py: prior_type, alpha, iterations, burn_out,
 // seed, k_max, precision, merge_form, hyper_params, learned, train_*).  The
 // result JSON holds the labels, the weights, the NMI against the ground
@@ -267,7 +267,7 @@ struct Config {
   int train_every = 10, train_until = 60, train_steps = 20, train_batch = 4096;
   double train_lr = 1e-3;
   double kappa = 1.0, nu = -1.0;
-  std::vector<double> m, psi, beta;  // empty: data mean, identity, ones
+  std::vector<double> m, psi, beta, shape, rate;  // empty: data mean, identity, ones
 };
 
 Config parse_config(const Json& j, const std::string& prior_override) {
@@ -294,8 +294,8 @@ Config parse_config(const Json& j, const std::string& prior_override) {
     return v->str;
   };
   c.prior_type = prior_override.empty() ? str("prior_type", c.prior_type) : prior_override;
-  if (c.prior_type != "Gaussian" && c.prior_type != "Multinomial")
-    throw std::runtime_error("prior_type must be Gaussian or Multinomial");
+  if (c.prior_type != "Gaussian" && c.prior_type != "Multinomial" && c.prior_type != "Poisson")
+    throw std::runtime_error("prior_type must be Gaussian, Multinomial or Poisson");
   c.alpha = num("alpha", c.alpha);
   c.iterations = (int)num("iterations", c.iterations);
   c.burn_out = (int)num("burn_out", c.burn_out);
@@ -325,6 +325,8 @@ Config parse_config(const Json& j, const std::string& prior_override) {
     if (const Json* v = hp->get("m")) vec(*v, c.m);
     if (const Json* v = hp->get("psi")) vec(*v, c.psi);
     if (const Json* v = hp->get("alpha")) vec(*v, c.beta);
+    if (const Json* v = hp->get("shape")) vec(*v, c.shape);
+    if (const Json* v = hp->get("rate")) vec(*v, c.rate);
   }
   return c;
 }
@@ -382,7 +384,8 @@ int run(int argc, char** argv) {
   else
     xi = npy_as<int32_t>(xa);
   xa.data.clear();
-  std::vector<double> m = c.m, psi = c.psi, beta = c.beta;
+  const bool pois = c.prior_type == "Poisson";
+  std::vector<double> m = c.m, psi = c.psi, beta = c.beta, shape = c.shape, rate = c.rate;
   if (gauss) {
     if (m.empty()) {
       m.assign(d, 0.0);
@@ -395,12 +398,16 @@ int run(int argc, char** argv) {
       for (int j = 0; j < d; ++j) psi[(size_t)j * d + j] = 1.0;
     }
     if ((int)m.size() != d || (int)psi.size() != d * d) throw std::runtime_error("hyper_params m / psi sizes");
+  } else if (pois) {
+    if (shape.empty()) shape.assign(d, 1.0);
+    if (rate.empty()) rate.assign(d, 1.0);
+    if ((int)shape.size() != d || (int)rate.size() != d) throw std::runtime_error("hyper_params shape / rate sizes");
   } else {
     if (beta.empty()) beta.assign(d, 1.0);
     if ((int)beta.size() != d) throw std::runtime_error("hyper_params alpha (Dirichlet) size");
   }
   dpmm_config cfg{};
-  cfg.family = gauss ? DPMM_GAUSSIAN : DPMM_MULTINOMIAL;
+  cfg.family = gauss ? DPMM_GAUSSIAN : (pois ? DPMM_POISSON : DPMM_MULTINOMIAL);
   cfg.d = d;
   cfg.k_max = c.k_max;
   cfg.burn_out = c.burn_out;
@@ -409,7 +416,9 @@ int run(int argc, char** argv) {
   cfg.nu = c.nu > 0 ? c.nu : d + 3.0;
   cfg.m = gauss ? m.data() : nullptr;
   cfg.psi = gauss ? psi.data() : nullptr;
-  cfg.beta = gauss ? nullptr : beta.data();
+  cfg.beta = gauss || pois ? nullptr : beta.data();
+  cfg.gamma_shape = pois ? shape.data() : nullptr;
+  cfg.gamma_rate = pois ? rate.data() : nullptr;
   cfg.seed = c.seed;
   cfg.precision = c.precision == "bf16" ? DPMM_BF16 : (c.precision == "bf16x3" ? DPMM_BF16X3 : DPMM_FP32);
   cfg.merge_form = c.merge_form == "inverse_split" ? DPMM_MERGE_INVERSE_SPLIT : DPMM_MERGE_PAPER;

@@ -223,6 +223,9 @@ dpmm_status logml_range(dpmm_ctx* ctx, size_t first, size_t count) {
   if (ctx->gaussian())
     e = launch_logml_gauss((int)count, ctx->d_items + first, ctx->d, prior_dev(ctx), ctx->logdet_psi, ctx->d_counts,
                            ctx->d_moments, ctx->d_scratch, ctx->d_logml + first, ctx->d_err, ctx->stream);
+  else if (ctx->poisson())
+    e = launch_logml_pois((int)count, ctx->d_items + first, ctx->d, ctx->d_gshape, ctx->d_grate, ctx->pois_const,
+                          ctx->d_counts, ctx->d_sums, ctx->d_logml + first, ctx->stream);
   else
     e = launch_logml_mult((int)count, ctx->d_items + first, ctx->d, ctx->d_beta, ctx->beta_sum, ctx->lgamma_beta_sum,
                           ctx->d_lgamma_beta, ctx->d_counts, ctx->d_sums, ctx->d_logml + first, ctx->stream);
@@ -301,7 +304,7 @@ dpmm_status pack_params(dpmm_ctx* ctx) {
                        ctx->d_logdet, ctx->d_err);
   } else {
     hipLaunchKernelGGL(k_pack_mult, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->cfg.k_max,
-                       ctx->d_log_pi, ctx->d_log_pisub, ctx->d_log_theta, ctx->d_packed);
+                       ctx->d_log_pi, ctx->d_log_pisub, ctx->d_log_theta, ctx->d_packed, ctx->poisson() ? 1 : 0);
   }
   DPMM_HIP(ctx, hipGetLastError(), "pack kernel");
   if (ctx->d_whi)
@@ -344,11 +347,14 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     return s;
   };
   if (!cfg) return bad(DPMM_E_ARG, "cfg is NULL");
-  if (cfg->family != DPMM_GAUSSIAN && cfg->family != DPMM_MULTINOMIAL) return bad(DPMM_E_ARG, "unknown family");
+  if (cfg->family != DPMM_GAUSSIAN && cfg->family != DPMM_MULTINOMIAL && cfg->family != DPMM_POISSON)
+    return bad(DPMM_E_ARG, "unknown family");
   if (cfg->family == DPMM_GAUSSIAN && (cfg->d < 1 || cfg->d > 128))
     return bad(DPMM_E_ARG, "Gaussian dimension must lie in [1, 128]");
   if (cfg->family == DPMM_MULTINOMIAL && (cfg->d < 1 || cfg->d > 128))
     return bad(DPMM_E_ARG, "vocabulary size must lie in [1, 128]");
+  if (cfg->family == DPMM_POISSON && (cfg->d < 1 || cfg->d > 128))
+    return bad(DPMM_E_ARG, "Poisson dimension must lie in [1, 128]");
   if (cfg->k_max < 1 || cfg->k_max > 4096) return bad(DPMM_E_ARG, "k_max must lie in [1, 4096]");
   if (cfg->burn_out < 0) return bad(DPMM_E_ARG, "burn_out must be >= 0");
   if (!(cfg->alpha > 0.0) || !std::isfinite(cfg->alpha)) return bad(DPMM_E_ARG, "alpha must be > 0");
@@ -387,6 +393,18 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     }
     ctx->E = d + d * (d + 1) / 2;
     ctx->stride = gauss_rec_stride(d);
+  } else if (cfg->family == DPMM_POISSON) {
+    if (!cfg->gamma_shape || !cfg->gamma_rate) return bad(DPMM_E_ARG, "gamma_shape and gamma_rate are required");
+    ctx->gshape.assign(cfg->gamma_shape, cfg->gamma_shape + d);
+    ctx->grate.assign(cfg->gamma_rate, cfg->gamma_rate + d);
+    for (int v = 0; v < d; ++v) {
+      const double a = ctx->gshape[v], b = ctx->grate[v];
+      if (!(a > 0.0) || !std::isfinite(a) || !(b > 0.0) || !std::isfinite(b))
+        return bad(DPMM_E_ARG, "the Gamma prior needs shape > 0 and rate > 0");
+      ctx->pois_const += a * std::log(b) - std::lgamma(a);
+    }
+    ctx->E = 0;
+    ctx->stride = mult_rec_stride(d);
   } else {
     if (!cfg->beta) return bad(DPMM_E_ARG, "beta is required");
     ctx->beta.assign(cfg->beta, cfg->beta + d);
@@ -399,7 +417,7 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     ctx->E = 0;
     ctx->stride = mult_rec_stride(d);
   }
-  ctx->cfg.m = ctx->cfg.psi = ctx->cfg.beta = nullptr;
+  ctx->cfg.m = ctx->cfg.psi = ctx->cfg.beta = ctx->cfg.gamma_shape = ctx->cfg.gamma_rate = nullptr;
   ctx->stream = (hipStream_t)hip_stream;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return bad(DPMM_E_DEVICE, "no HIP device");
@@ -448,8 +466,13 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
       ok = ok && chk(c->alloc(&c->d_spart, std::max<size_t>(sp, 1)));
     }
   } else {
-    ok = ok && chk(c->alloc(&c->d_beta, (size_t)d));
-    ok = ok && chk(c->alloc(&c->d_lgamma_beta, (size_t)d));
+    if (c->poisson()) {
+      ok = ok && chk(c->alloc(&c->d_gshape, (size_t)d));
+      ok = ok && chk(c->alloc(&c->d_grate, (size_t)d));
+    } else {
+      ok = ok && chk(c->alloc(&c->d_beta, (size_t)d));
+      ok = ok && chk(c->alloc(&c->d_lgamma_beta, (size_t)d));
+    }
     ok = ok && chk(c->alloc(&c->d_sums, 2 * (size_t)km * d));
     ok = ok && chk(c->alloc(&c->d_log_theta, 3 * (size_t)km * d));
   }
@@ -467,6 +490,9 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
   if (c->gaussian()) {
     e = hipMemcpy(c->d_m, c->m.data(), d * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_psi, c->psi.data(), (size_t)d * d * sizeof(double), hipMemcpyHostToDevice);
+  } else if (c->poisson()) {
+    e = hipMemcpy(c->d_gshape, c->gshape.data(), d * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_grate, c->grate.data(), d * sizeof(double), hipMemcpyHostToDevice);
   } else {
     e = hipMemcpy(c->d_beta, c->beta.data(), d * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -793,8 +819,12 @@ dpmm_status dpmm_sample_params(dpmm_ctx* ctx, uint32_t t) {
     ctx->have_params = true;
     return DPMM_OK;
   }
-  hipLaunchKernelGGL(k_dir_draw, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->d_beta, ctx->d_sums,
-                     ctx->cfg.seed, t, ctx->d_log_theta);
+  if (ctx->poisson())
+    hipLaunchKernelGGL(k_pois_draw, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->d_gshape, ctx->d_grate,
+                       ctx->d_counts, ctx->d_sums, ctx->cfg.seed, t, ctx->d_log_theta);
+  else
+    hipLaunchKernelGGL(k_dir_draw, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->d_beta, ctx->d_sums,
+                       ctx->cfg.seed, t, ctx->d_log_theta);
   DPMM_HIP(ctx, hipGetLastError(), "posterior draw kernel");
   return pack_params(ctx);
 }

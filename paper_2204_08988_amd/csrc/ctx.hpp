@@ -31,7 +31,8 @@ struct DevBuf {
 
 struct dpmm_ctx {
   dpmm_config cfg{};
-  std::vector<double> m, psi, beta, lgamma_beta;
+  std::vector<double> m, psi, beta, lgamma_beta, gshape, grate;
+  double pois_const = 0.0;  // sum_v (a_v log b_v - lgamma(a_v)) of the Gamma prior
   double logdet_psi = 0.0, beta_sum = 0.0, lgamma_beta_sum = 0.0;
   hipStream_t stream = nullptr;
   int device = 0;  // the HIP device current at dpmm_create
@@ -44,6 +45,7 @@ struct dpmm_ctx {
   std::vector<DevBuf> bufs;
   // device tables
   double *d_m = nullptr, *d_psi = nullptr, *d_beta = nullptr, *d_lgamma_beta = nullptr;
+  double *d_gshape = nullptr, *d_grate = nullptr;  // Poisson: Gamma prior
   long long* d_counts = nullptr;  // [2 k_max]
   double* d_moments = nullptr;    // Gaussian [2 k_max][E]
   long long* d_sums = nullptr;    // multinomial [2 k_max][V]
@@ -133,6 +135,7 @@ struct dpmm_ctx {
     return hipSuccess;
   }
   bool gaussian() const { return cfg.family == DPMM_GAUSSIAN; }
+  bool poisson() const { return cfg.family == DPMM_POISSON; }
   bool sorted_path() const { return gaussian() && d >= dpmm::SORTED_MIN_D; }
 };
 

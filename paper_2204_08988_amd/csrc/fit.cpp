@@ -99,6 +99,8 @@ double prior_sum(const dpmm_ctx* ctx) {
   for (double v : ctx->m) s += v;
   for (double v : ctx->psi) s += v;
   for (double v : ctx->beta) s += v;
+  for (double v : ctx->gshape) s += v;
+  for (double v : ctx->grate) s += 2.0 * v;
   return s;
 }
 

@@ -39,7 +39,9 @@ __global__ void k_pack_gauss(int K, int d, int k_max, const double* log_pi, cons
                              const double* mu, const double* sigma, double* scratch, float* packed,
                              double* logdet_out, int* err);
 __global__ void k_pack_mult(int K, int V, int k_max, const double* log_pi, const double* log_pisub,
-                            const double* log_theta, float* packed);
+                            const double* log_theta, float* packed, int poisson);
+__global__ void k_pois_draw(int K, int V, const double* shape, const double* rate, const long long* counts,
+                            const long long* sums, uint64_t seed, uint32_t t, double* log_lambda);
 
 // ---- learned split proposal (mlp.hip)
 constexpr int MLP_HIDDEN = 128;
@@ -182,6 +184,10 @@ hipError_t launch_pack_readback(int K, int P, const long long* counts, const dou
 hipError_t launch_logml_mult(int n_items, const LogmlItem* items, int V, const double* beta,
                              double beta_sum, double lgamma_beta_sum, const double* lgamma_beta,
                              const long long* counts, const long long* sums, double* out, hipStream_t s);
+// Gamma-Poisson log marginal: pconst = sum_v (a_v log b_v - lgamma(a_v))
+hipError_t launch_logml_pois(int n_items, const LogmlItem* items, int V, const double* shape, const double* rate,
+                             double pconst, const long long* counts, const long long* sums, double* out,
+                             hipStream_t s);
 
 // relabel table entry for old segment s = 2 z + zsub
 struct RelabelEntry {

@@ -646,6 +646,25 @@ __global__ void k_dir_draw(int K, int V, const double* __restrict__ beta,
   for (int v = threadIdx.x; v < V; v += blockDim.x) out[v] -= lse;
 }
 
+// Poisson family, one workgroup per component: log lambda_v for lambda_v ~
+// Gamma(a_v + c_v, b_v + n) (shape, rate), the Gamma(a_v + c_v, 1) variate of
+// draw v of (3k + c, TAG_DIRTHETA) divided by the rate.
+__global__ void k_pois_draw(int K, int V, const double* __restrict__ shape, const double* __restrict__ rate,
+                            const long long* __restrict__ counts, const long long* __restrict__ sums, uint64_t seed,
+                            uint32_t t, double* __restrict__ log_lambda) {
+  const int e = blockIdx.x;
+  if (e >= 3 * K) return;
+  const int k = e / 3, c = e % 3;
+  const int s0 = c == 0 ? 2 * k : 2 * k + (c - 1);
+  const int s1 = c == 0 ? 2 * k + 1 : -1;
+  const double n = (double)counts[s0] + (s1 >= 0 ? (double)counts[s1] : 0.0);
+  double* out = log_lambda + (size_t)e * V;
+  for (int v = threadIdx.x; v < V; v += blockDim.x) {
+    const double cnt = (double)sums[(size_t)s0 * V + v] + (s1 >= 0 ? (double)sums[(size_t)s1 * V + v] : 0.0);
+    out[v] = log_gamma_draw(seed, t, (uint32_t)e, TAG_DIRTHETA, (uint32_t)v, shape[v] + cnt) - log(rate[v] + n);
+  }
+}
+
 // Pack component e = 3k + c from its float64 (mu, Sigma): record slot k
 // (cluster) or k_max + 2k + h (sub-cluster).
 __global__ void k_pack_gauss(int K, int d, int k_max, const double* __restrict__ log_pi,
@@ -668,16 +687,25 @@ __global__ void k_pack_gauss(int K, int d, int k_max, const double* __restrict__
               logdet_out + e, err, &flag, red);
 }
 
+// Count families: record = (log w, log theta) (multinomial) or (log w - sum
+// lambda, log lambda) (Poisson, poisson != 0): the score c + sum_v x_v rec_v
+// is the component's log-likelihood without its per-point factor.
 __global__ void k_pack_mult(int K, int V, int k_max, const double* __restrict__ log_pi,
                             const double* __restrict__ log_pisub, const double* __restrict__ log_theta,
-                            float* __restrict__ packed) {
+                            float* __restrict__ packed, int poisson) {
+  __shared__ double red[256];
   const int e = blockIdx.x;
   if (e >= 3 * K) return;
   const int k = e / 3, c = e % 3;
   const int stride = mult_rec_stride(V);
   const int slot = c == 0 ? k : k_max + 2 * k + (c - 1);
   float* rec = packed + (size_t)slot * stride;
-  const double lw = c == 0 ? log_pi[k] : log_pisub[2 * k + (c - 1)];
+  double lw = c == 0 ? log_pi[k] : log_pisub[2 * k + (c - 1)];
+  if (poisson) {
+    double s = 0.0;
+    for (int v = threadIdx.x; v < V; v += blockDim.x) s += exp(log_theta[(size_t)e * V + v]);
+    lw -= block_reduce_sum(s, red);
+  }
   if (threadIdx.x == 0) {
     rec[0] = (float)lw;
     rec[1] = rec[2] = rec[3] = 0.0f;

@@ -495,6 +495,35 @@ __global__ void k_logml_mult(int n_items, const LogmlItem* __restrict__ items, i
   if (threadIdx.x == 0) out[it] = lgamma_beta_sum - lgamma_d(beta_sum + tot) + acc;
 }
 
+// Gamma-Poisson: sum_v [a_v log b_v - lgamma(a_v) + lgamma(a_v + c_v) -
+// (a_v + c_v) log(b_v + n)] (the per-point 1 / x! factors left out: they
+// cancel in every ratio); pconst holds the first two terms summed.
+__global__ void k_logml_pois(int n_items, const LogmlItem* __restrict__ items, int V, const double* __restrict__ shape,
+                             const double* __restrict__ rate, double pconst, const long long* __restrict__ counts,
+                             const long long* __restrict__ sums, double* __restrict__ out) {
+  __shared__ double red[BLOCK];
+  const int it = blockIdx.x;
+  if (it >= n_items) return;
+  const LogmlItem item = items[it];
+  long long npts = 0;
+  for (int q = 0; q < 4; ++q)
+    if (item.seg[q] >= 0) npts += counts[item.seg[q]];
+  if (npts == 0) {
+    if (threadIdx.x == 0) out[it] = 0.0;
+    return;
+  }
+  double acc = 0.0;
+  for (int v = threadIdx.x; v < V; v += BLOCK) {
+    long long c = 0;
+    for (int q = 0; q < 4; ++q)
+      if (item.seg[q] >= 0) c += sums[(size_t)item.seg[q] * V + v];
+    const double ac = shape[v] + (double)c;
+    acc += lgamma_d(ac) - ac * log(rate[v] + (double)npts);
+  }
+  acc = reduce_sum(acc, red);
+  if (threadIdx.x == 0) out[it] = pconst + acc;
+}
+
 __global__ void k_relabel(long long n, const RelabelEntry* __restrict__ table, int n_entries, uint32_t t,
                           uint64_t seed, int* __restrict__ z, unsigned char* __restrict__ zsub) {
   for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK) {
@@ -590,6 +619,15 @@ hipError_t launch_logml_mult(int n_items, const LogmlItem* items, int V, const d
   if (n_items == 0) return hipSuccess;
   hipLaunchKernelGGL(k_logml_mult, dim3(n_items), dim3(BLOCK), 0, s, n_items, items, V, beta, beta_sum,
                      lgamma_beta_sum, lgamma_beta, counts, sums, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_logml_pois(int n_items, const LogmlItem* items, int V, const double* shape, const double* rate,
+                             double pconst, const long long* counts, const long long* sums, double* out,
+                             hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_logml_pois, dim3(n_items), dim3(BLOCK), 0, s, n_items, items, V, shape, rate, pconst, counts,
+                     sums, out);
   return hipGetLastError();
 }
 

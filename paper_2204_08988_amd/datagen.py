@@ -18,6 +18,10 @@ gauss_d128    N=1e7, d=128, 100 Gaussians, means N(0, 9 I), covariances
               Wishart(d+2, I/d), weights Dirichlet(1).
 gauss_d64     N=2e6, d=64, 200 overlapping Gaussians, means N(0, 4 I),
               covariances Wishart(d+2, I/d), weights Dirichlet(1).
+pois_d20      N=1e6 count vectors, d=20 independent Poisson counts, 20
+              clusters with rates Gamma(1, scale 10) per cluster and
+              coordinate, equal weights (the Poisson family, an exponential
+              family of the kind Sec. 3.4 names).
 """
 from dataclasses import dataclass
 
@@ -46,12 +50,22 @@ class MultinomialSpec:
     total_hi: int
 
 
+@dataclass
+class PoissonSpec:
+    n: int
+    d: int
+    k: int
+    rate_shape: float   # rates ~ Gamma(rate_shape, scale rate_scale)
+    rate_scale: float
+
+
 WORKLOADS = {
     "gauss_d2": GaussianSpec(10_000, 2, 6, "uniform", 10.0, 4.0, 1.0, "equal"),
     "gauss_d32": GaussianSpec(1_000_000, 32, 20, "normal", 5.0, 34.0, 1.0 / 32, "dirichlet1"),
     "mult_v100": MultinomialSpec(1_000_000, 100, 50, 0.1, 50, 200),
     "gauss_d128": GaussianSpec(10_000_000, 128, 100, "normal", 3.0, 130.0, 1.0 / 128, "dirichlet1"),
     "gauss_d64": GaussianSpec(2_000_000, 64, 200, "normal", 2.0, 66.0, 1.0 / 64, "dirichlet1"),
+    "pois_d20": PoissonSpec(1_000_000, 20, 20, 1.0, 10.0),
 }
 
 
@@ -110,8 +124,21 @@ def multinomial_data(spec, seed, n=None):
     return x, labels.astype(np.int32)
 
 
+def poisson_data(spec, seed, n=None):
+    """Counts x[n, d] (int32, independent Poisson per coordinate) and the true labels."""
+    n = spec.n if n is None else int(n)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rates = rng.gamma(spec.rate_shape, spec.rate_scale, size=(spec.k, spec.d))
+    rng2 = np.random.Generator(np.random.PCG64(seed + 1))
+    labels = rng2.integers(0, spec.k, size=n)
+    x = rng2.poisson(rates[labels]).astype(np.int32)
+    return x, labels.astype(np.int32)
+
+
 def workload(name, seed, n=None):
     spec = WORKLOADS[name]
     if isinstance(spec, GaussianSpec):
         return gaussian_data(spec, seed, n)
+    if isinstance(spec, PoissonSpec):
+        return poisson_data(spec, seed, n)
     return multinomial_data(spec, seed, n)

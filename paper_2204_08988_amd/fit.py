@@ -7,7 +7,7 @@ parameter draw dpmm_sample_params, the NMI dpmm_nmi, the checkpoints
 dpmm_save_checkpoint / dpmm_load_checkpoint.
 
 Configuration keys (JSON object; every key optional except as noted):
-  prior_type     "Gaussian" (default) or "Multinomial"
+  prior_type     "Gaussian" (default), "Multinomial" or "Poisson"
   alpha          DP concentration (default 10)
   iterations     iterations to run (default 100)
   burn_out       iterations a new cluster waits before it may split or merge (default 15)
@@ -16,7 +16,8 @@ Configuration keys (JSON object; every key optional except as noted):
   precision      "fp32" (default), "bf16", "bf16x3" (Gaussian d = 32, 64, 128)
   merge_form     "paper" (default) or "inverse_split"
   hyper_params   Gaussian: {"kappa": 1, "m": data mean, "nu": d + 3, "psi": identity};
-                 Multinomial: {"alpha": [1, ...]} (the Dirichlet prior, length V)
+                 Multinomial: {"alpha": [1, ...]} (the Dirichlet prior, length V);
+                 Poisson: {"shape": [1, ...], "rate": [1, ...]} (the Gamma prior, length d)
   learned        principal axes of the learned split proposal (0 = off); with
                  train_every, train_until, train_steps, train_batch, train_lr
 """
@@ -43,8 +44,8 @@ def load_config(config):
     unknown = set(cfg) - set(DEFAULTS) - {"hyper_params"}
     if unknown:
         raise ValueError(f"unknown configuration keys: {sorted(unknown)}")
-    if cfg["prior_type"] not in ("Gaussian", "Multinomial"):
-        raise ValueError("prior_type must be Gaussian or Multinomial")
+    if cfg["prior_type"] not in ("Gaussian", "Multinomial", "Poisson"):
+        raise ValueError("prior_type must be Gaussian, Multinomial or Poisson")
     return cfg
 
 
@@ -58,6 +59,11 @@ def make_sampler(cfg, x):
         return Sampler("gaussian", d, cfg["k_max"], cfg["alpha"], cfg["seed"], kappa=float(hp.get("kappa", 1.0)),
                        nu=float(hp.get("nu", d + 3.0)), m=m, psi=psi, burn_out=cfg["burn_out"],
                        merge_form=cfg["merge_form"], precision=cfg["precision"], learned=cfg["learned"])
+    if cfg["prior_type"] == "Poisson":
+        return Sampler("poisson", d, cfg["k_max"], cfg["alpha"], cfg["seed"],
+                       gamma_shape=np.asarray(hp.get("shape", np.ones(d)), dtype=np.float64),
+                       gamma_rate=np.asarray(hp.get("rate", np.ones(d)), dtype=np.float64), burn_out=cfg["burn_out"],
+                       merge_form=cfg["merge_form"])
     beta = np.asarray(hp.get("alpha", np.ones(d)), dtype=np.float64)
     return Sampler("multinomial", d, cfg["k_max"], cfg["alpha"], cfg["seed"], beta=beta, burn_out=cfg["burn_out"],
                    merge_form=cfg["merge_form"])
@@ -65,7 +71,7 @@ def make_sampler(cfg, x):
 
 def fit(x, config=None, gt=None, result_path=None, checkpoint_path=None, resume_path=None):
     """Fit a DPMM to x (numpy N x d float32 for Gaussian, N x V int32 counts
-    for Multinomial) on the current GPU.  resume_path: continue from a
+    for Multinomial and Poisson) on the current GPU.  resume_path: continue from a
     checkpoint (the configuration and data must match the run that wrote
     it); checkpoint_path: save the final state there.  Returns the result
     dict (also written as JSON to result_path when given)."""

@@ -29,14 +29,15 @@ class Sampler:
     """One sampler context on the current HIP device and torch stream."""
 
     def __init__(self, family, d, k_max, alpha, seed, kappa=1.0, nu=None, m=None, psi=None,
-                 beta=None, burn_out=15, merge_form="paper", precision="fp32", learned=0, stream=None):
+                 beta=None, burn_out=15, merge_form="paper", precision="fp32", learned=0, stream=None,
+                 gamma_shape=None, gamma_rate=None):
         import torch
         self.torch = torch
         L = _lib.lib()
         self.family = family
         self.d = int(d)
         cfg = _lib.Config()
-        cfg.family = _lib.GAUSSIAN if family == "gaussian" else _lib.MULTINOMIAL
+        cfg.family = {"gaussian": _lib.GAUSSIAN, "multinomial": _lib.MULTINOMIAL, "poisson": _lib.POISSON}[family]
         cfg.d = self.d
         cfg.k_max = int(k_max)
         cfg.burn_out = int(burn_out)
@@ -49,6 +50,11 @@ class Sampler:
             psi = np.ascontiguousarray(np.eye(self.d) if psi is None else psi, dtype=np.float64)
             self._keep += [m, psi]
             cfg.m, cfg.psi = _dptr(m), _dptr(psi)
+        elif family == "poisson":
+            a = np.ascontiguousarray(np.ones(self.d) if gamma_shape is None else gamma_shape, dtype=np.float64)
+            b = np.ascontiguousarray(np.ones(self.d) if gamma_rate is None else gamma_rate, dtype=np.float64)
+            self._keep += [a, b]
+            cfg.gamma_shape, cfg.gamma_rate = _dptr(a), _dptr(b)
         else:
             beta = np.ascontiguousarray(np.ones(self.d) if beta is None else beta, dtype=np.float64)
             self._keep.append(beta)

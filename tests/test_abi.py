@@ -49,6 +49,11 @@ def _cfg(**kw):
     if beta is not None:
         keep.append(beta)
         cfg.beta = beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for name in ("gamma_shape", "gamma_rate"):
+        arr = kw.pop(name, None)
+        if arr is not None:
+            keep.append(arr)
+            setattr(cfg, name, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     cfg.seed = 1
     cfg.precision = kw.pop("precision", _lib.FP32)
     cfg.merge_form = kw.pop("merge_form", _lib.MERGE_PAPER)
@@ -80,6 +85,12 @@ def _cfg(**kw):
     (dict(psi=np.array([[1.0, 0.5], [0.4, 1.0]])), -4),
     (dict(family=_lib.MULTINOMIAL, d=4), -1),
     (dict(family=_lib.MULTINOMIAL, d=3, beta=np.array([1.0, 0.0, 1.0])), -1),
+    (dict(family=_lib.POISSON, d=3), -1),
+    (dict(family=_lib.POISSON, d=3, gamma_shape=np.ones(3)), -1),
+    (dict(family=_lib.POISSON, d=2, gamma_shape=np.array([1.0, 0.0]), gamma_rate=np.ones(2)), -1),
+    (dict(family=_lib.POISSON, d=2, gamma_shape=np.ones(2), gamma_rate=np.array([1.0, float("inf")])), -1),
+    (dict(family=_lib.POISSON, d=129, gamma_shape=np.ones(129), gamma_rate=np.ones(129)), -1),
+    (dict(learned=1, family=_lib.POISSON, d=4, gamma_shape=np.ones(4), gamma_rate=np.ones(4)), -1),
 ])
 def test_create_rejects_bad_config_before_device(kw, status):
     L = _lib.lib()
