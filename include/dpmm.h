@@ -13,7 +13,9 @@
  *     memory, e.g. torch tensors).  The context owns everything else (packed
  *     parameters, statistics, scratch) and frees it in dpmm_destroy.
  *   - Layout: x is point-major (row-major) N x d float32 (Gaussian) or
- *     N x V int32 counts (multinomial, Poisson); z is int32[N] with clusters 0..K-1;
+ *     N x V int32 counts (multinomial, Poisson); for a context created with
+ *     sparse = 1, x is instead a host pointer to a dpmm_csr that describes
+ *     the counts in compressed sparse rows; z is int32[N] with clusters 0..K-1;
  *     zsub is uint8[N] with 0 = left (l), 1 = right (r) sub-cluster.  Every
  *     call taking n accepts 0 <= n < 2^31 (device point indices are int32)
  *     and returns DPMM_E_SHAPE otherwise.
@@ -69,6 +71,25 @@ enum { DPMM_GAUSSIAN = 0, DPMM_MULTINOMIAL = 1, DPMM_POISSON = 2 };
 enum { DPMM_FP32 = 0, DPMM_BF16 = 1, DPMM_BF16X3 = 2 };
 enum { DPMM_MERGE_PAPER = 0, DPMM_MERGE_INVERSE_SPLIT = 1 };
 
+/* Count data in compressed sparse rows (contexts created with sparse = 1):
+ * the shape of bag-of-words data with a large vocabulary, such as the
+ * 20newsgroups documents of Sec. 5 (N = 11314, V = 20000).  The struct is
+ * host memory read during the call; the three arrays are device memory owned
+ * by the caller.  Row i is entries row_ptr[i] .. row_ptr[i+1] - 1 of col /
+ * val: word col[e] in [0, V) with count val[e] >= 0; the columns of a row
+ * need not be sorted, and a repeated column adds its counts.  row_ptr has
+ * n + 1 entries, non-decreasing, within [0, nnz].  The kernels check every
+ * entry: a row range outside [0, nnz], a column outside [0, V) or a negative
+ * count is skipped (the row's labels stay as they were) and makes the next
+ * call that synchronises (dpmm_split_merge, dpmm_step, the dpmm_get_* calls)
+ * return DPMM_E_ARG. */
+typedef struct {
+  const int64_t* row_ptr; /* device [n + 1] */
+  const int32_t* col;     /* device [nnz] */
+  const int32_t* val;     /* device [nnz] */
+  int64_t nnz;            /* number of stored entries, >= 0 */
+} dpmm_csr;
+
 /* Model and capacity (Sec. 2.2 model; NIW prior of Sec. 2.2 Example;
  * Dirichlet prior for multinomial components, Sec. 2.1).  DPMM_POISSON is a
  * further exponential family on the same template (Sec. 3.4 names Poisson as
@@ -76,7 +97,9 @@ enum { DPMM_MERGE_PAPER = 0, DPMM_MERGE_INVERSE_SPLIT = 1 };
  * counts with rates lambda_v ~ Gamma(gamma_shape_v, gamma_rate_v). */
 typedef struct {
   int32_t family;     /* DPMM_GAUSSIAN, DPMM_MULTINOMIAL or DPMM_POISSON */
-  int32_t d;          /* data dimension d (Gaussian, Poisson) or vocabulary size V */
+  int32_t d;          /* data dimension d (Gaussian, Poisson) or vocabulary
+                         size V: 1 <= d <= 128 for dense data, 1 <= d <= 2^20
+                         with sparse = 1 */
   int32_t k_max;      /* capacity in clusters, 1 <= k_max <= 4096 */
   int32_t burn_out;   /* a cluster younger than this many iterations may not
                          split or merge (>= 0) */
@@ -105,6 +128,8 @@ typedef struct {
                          merge phase */
   const double* gamma_shape; /* host [d]: Gamma prior shapes, > 0 (Poisson; copied) */
   const double* gamma_rate;  /* host [d]: Gamma prior rates, > 0 (Poisson; copied) */
+  int32_t sparse;     /* 0: dense x; 1: x is a dpmm_csr (multinomial and
+                         Poisson families only) */
 } dpmm_config;
 
 /* What one iteration did (filled by dpmm_split_merge and dpmm_step). */

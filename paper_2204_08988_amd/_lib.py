@@ -37,8 +37,14 @@ class Config(ctypes.Structure):
         ("psi", ctypes.POINTER(ctypes.c_double)), ("beta", ctypes.POINTER(ctypes.c_double)),
         ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32), ("merge_form", ctypes.c_int32),
         ("learned", ctypes.c_int32), ("gamma_shape", ctypes.POINTER(ctypes.c_double)),
-        ("gamma_rate", ctypes.POINTER(ctypes.c_double)),
+        ("gamma_rate", ctypes.POINTER(ctypes.c_double)), ("sparse", ctypes.c_int32),
     ]
+
+
+class CSR(ctypes.Structure):
+    """dpmm_csr: count rows in compressed sparse rows (device arrays)."""
+    _fields_ = [("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("nnz", ctypes.c_int64)]
 
 
 class IterInfo(ctypes.Structure):

@@ -53,10 +53,36 @@ namespace dpmm::host {
 
 dpmm_status check_n(dpmm_ctx* ctx, const void* x, int64_t n) {
   if (!x && n > 0) return ctx->fail(DPMM_E_ARG, "x is NULL");
+  if (ctx->sparse() && x) {
+    const dpmm_csr* c = static_cast<const dpmm_csr*>(x);
+    if (c->nnz < 0) return ctx->fail(DPMM_E_SHAPE, "nnz must be >= 0");
+    if (n > 0 && !c->row_ptr) return ctx->fail(DPMM_E_ARG, "row_ptr is NULL");
+    if (c->nnz > 0 && (!c->col || !c->val)) return ctx->fail(DPMM_E_ARG, "col / val is NULL");
+  }
   // point indices are int32 on the device (the cluster-sorted permutation, the
   // deferred-draw list, the learned proposal's selection)
   if (n < 0 || n > (int64_t)0x7FFFFFFFLL) return ctx->fail(DPMM_E_SHAPE, "n must lie in [0, 2^31)");
   return DPMM_OK;
+}
+
+SparseRows sparse_rows(const void* x) {
+  const dpmm_csr* c = static_cast<const dpmm_csr*>(x);
+  SparseRows r;
+  r.row_ptr = reinterpret_cast<const long long*>(c->row_ptr);
+  r.col = c->col;
+  r.val = c->val;
+  r.nnz = c->nnz;
+  return r;
+}
+
+// the status of a non-zero device error flag (and the flag cleared)
+dpmm_status flag_fail(dpmm_ctx* ctx, int flag) {
+  DPMM_HIP(ctx, hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream), "clear flag");
+  if (flag & ERR_SPARSE_INPUT)
+    return ctx->fail(DPMM_E_ARG, "sparse rows: a row range outside [0, nnz], a column outside [0, V) or a "
+                                 "negative count");
+  return ctx->fail(DPMM_E_NUMERIC, "a float64 Cholesky factorisation met a non-positive pivot (flag " +
+                                       std::to_string(flag) + ")");
 }
 
 NiwPriorDev prior_dev(dpmm_ctx* ctx) {
@@ -152,6 +178,9 @@ dpmm_status stats_with(dpmm_ctx* ctx, const void* x, int64_t n, const int32_t* z
   if (ctx->gaussian())
     e = launch_stats_gauss(ctx->d, (const float*)x, n, z, zsub, ctx->K, ctx->d_counts, ctx->d_moments, b.spart,
                            ctx->stream);
+  else if (ctx->sparse())
+    e = launch_stats_csr(sparse_rows(x), n, ctx->d, z, zsub, ctx->K, ctx->d_counts, ctx->d_sums, ctx->d_err,
+                         ctx->stream);
   else
     e = launch_stats_mult(ctx->d, (const int*)x, n, z, zsub, ctx->K, ctx->d_counts, ctx->d_sums, ctx->stream);
   DPMM_HIP(ctx, e, "statistics kernel");
@@ -269,11 +298,7 @@ dpmm_status check_device_error(dpmm_ctx* ctx) {
   int flag = 0;
   DPMM_HIP(ctx, hipMemcpyAsync(&flag, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "copy flag");
   DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
-  if (flag) {
-    DPMM_HIP(ctx, hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream), "clear flag");
-    return ctx->fail(DPMM_E_NUMERIC, "a float64 Cholesky factorisation met a non-positive pivot (flag " +
-                                         std::to_string(flag) + ")");
-  }
+  if (flag) return flag_fail(ctx, flag);
   return DPMM_OK;
 }
 
@@ -307,6 +332,9 @@ dpmm_status pack_params(dpmm_ctx* ctx) {
                        ctx->d_log_pi, ctx->d_log_pisub, ctx->d_log_theta, ctx->d_packed, ctx->poisson() ? 1 : 0);
   }
   DPMM_HIP(ctx, hipGetLastError(), "pack kernel");
+  if (ctx->sparse())
+    DPMM_HIP(ctx, launch_pack_csr(K, ctx->d, ctx->cfg.k_max, ctx->d_packed, ctx->d_tcl, ctx->d_tsub, ctx->d_cw,
+                                  ctx->stream), "sparse table pack kernel");
   if (ctx->d_whi)
     DPMM_HIP(ctx, launch_pack_wfrag(K, ctx->d, ctx->cfg.k_max, ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->stream),
              "fragment pack kernel");
@@ -351,10 +379,14 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     return bad(DPMM_E_ARG, "unknown family");
   if (cfg->family == DPMM_GAUSSIAN && (cfg->d < 1 || cfg->d > 128))
     return bad(DPMM_E_ARG, "Gaussian dimension must lie in [1, 128]");
-  if (cfg->family == DPMM_MULTINOMIAL && (cfg->d < 1 || cfg->d > 128))
-    return bad(DPMM_E_ARG, "vocabulary size must lie in [1, 128]");
-  if (cfg->family == DPMM_POISSON && (cfg->d < 1 || cfg->d > 128))
-    return bad(DPMM_E_ARG, "Poisson dimension must lie in [1, 128]");
+  if (cfg->sparse != 0 && cfg->sparse != 1) return bad(DPMM_E_ARG, "sparse must be 0 or 1");
+  if (cfg->sparse && cfg->family == DPMM_GAUSSIAN)
+    return bad(DPMM_E_ARG, "sparse rows need the multinomial or Poisson family");
+  const int max_v = cfg->sparse ? (1 << 20) : 128;
+  if (cfg->family == DPMM_MULTINOMIAL && (cfg->d < 1 || cfg->d > max_v))
+    return bad(DPMM_E_ARG, cfg->sparse ? "vocabulary size must lie in [1, 2^20]" : "vocabulary size must lie in [1, 128]");
+  if (cfg->family == DPMM_POISSON && (cfg->d < 1 || cfg->d > max_v))
+    return bad(DPMM_E_ARG, cfg->sparse ? "Poisson dimension must lie in [1, 2^20]" : "Poisson dimension must lie in [1, 128]");
   if (cfg->k_max < 1 || cfg->k_max > 4096) return bad(DPMM_E_ARG, "k_max must lie in [1, 4096]");
   if (cfg->burn_out < 0) return bad(DPMM_E_ARG, "burn_out must be >= 0");
   if (!(cfg->alpha > 0.0) || !std::isfinite(cfg->alpha)) return bad(DPMM_E_ARG, "alpha must be > 0");
@@ -475,6 +507,11 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     }
     ok = ok && chk(c->alloc(&c->d_sums, 2 * (size_t)km * d));
     ok = ok && chk(c->alloc(&c->d_log_theta, 3 * (size_t)km * d));
+    if (c->sparse()) {
+      ok = ok && chk(c->alloc(&c->d_tcl, (size_t)km * d));
+      ok = ok && chk(c->alloc(&c->d_tsub, 2 * (size_t)km * d));
+      ok = ok && chk(c->alloc(&c->d_cw, 3 * (size_t)km));
+    }
   }
   // every failure below releases what was allocated through dpmm_destroy
   if (!ok) {
@@ -638,6 +675,7 @@ dpmm_status dpmm_get_params(dpmm_ctx* ctx, double* log_pi, double* log_pisub, do
                                  ctx->stream), "copy");
     DPMM_HIP(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
   }
+  if (ctx->sparse()) DPMM_TRY(check_device_error(ctx));  // range checks of the sparse rows
   return DPMM_OK;
 }
 
@@ -720,6 +758,7 @@ dpmm_status dpmm_get_stats(dpmm_ctx* ctx, void* stats) {
       for (int v = 0; v < d; ++v) s[g * R + 1 + v] = sums[(size_t)g * d + v];
     }
   }
+  if (ctx->sparse()) DPMM_TRY(check_device_error(ctx));  // range checks of the sparse rows
   return DPMM_OK;
 }
 
@@ -728,9 +767,13 @@ dpmm_status dpmm_loglik(dpmm_ctx* ctx, const void* x, int64_t n, float* out) {
   DPMM_TRY(check_n(ctx, x, n));
   if (!out && n > 0) return ctx->fail(DPMM_E_ARG, "out is NULL");
   if (!ctx->have_params) return ctx->fail(DPMM_E_STATE, "no parameters yet");
-  hipError_t e = ctx->gaussian()
-                     ? launch_loglik_gauss(ctx->d, (const float*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max, out, ctx->stream)
-                     : launch_loglik_mult(ctx->d, (const int*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max, out, ctx->stream);
+  hipError_t e =
+      ctx->gaussian()
+          ? launch_loglik_gauss(ctx->d, (const float*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max, out, ctx->stream)
+      : ctx->sparse()
+          ? launch_loglik_csr(sparse_rows(x), n, ctx->d, ctx->d_tcl, ctx->d_tsub, ctx->d_cw, ctx->K, out, ctx->d_err,
+                              ctx->stream)
+          : launch_loglik_mult(ctx->d, (const int*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max, out, ctx->stream);
   DPMM_HIP(ctx, e, "log-likelihood kernel");
   return DPMM_OK;
 }
@@ -761,10 +804,13 @@ dpmm_status label_phase(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int
                                        ctx->d_hist, ctx->d_tot, ctx->stream), "label kernel");
     return DPMM_OK;
   }
-  hipError_t e = ctx->gaussian() ? launch_label_gauss(ctx->d, (const float*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max,
-                                                      t, ctx->cfg.seed, z, zsub, ctx->stream)
-                                 : launch_label_mult(ctx->d, (const int*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max, t,
-                                                     ctx->cfg.seed, z, zsub, ctx->stream);
+  hipError_t e =
+      ctx->gaussian() ? launch_label_gauss(ctx->d, (const float*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max, t,
+                                           ctx->cfg.seed, z, zsub, ctx->stream)
+      : ctx->sparse() ? launch_label_csr(sparse_rows(x), n, ctx->d, ctx->d_tcl, ctx->d_tsub, ctx->d_cw, ctx->K, t,
+                                         ctx->cfg.seed, z, zsub, ctx->d_err, ctx->stream)
+                      : launch_label_mult(ctx->d, (const int*)x, n, ctx->d_packed, ctx->K, ctx->cfg.k_max, t,
+                                          ctx->cfg.seed, z, zsub, ctx->stream);
   DPMM_HIP(ctx, e, "label kernel");
   return DPMM_OK;
 }
@@ -904,11 +950,7 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t
     lml.assign(rb_lml, rb_lml + 3 * (size_t)K);
     merge_ok.assign(rb_m, rb_m + P);
     const int flag = (int)*reinterpret_cast<const long long*>(ctx->h_rb);
-    if (flag) {
-      DPMM_HIP(ctx, hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream), "clear flag");
-      return ctx->fail(DPMM_E_NUMERIC, "a float64 Cholesky factorisation met a non-positive pivot (flag " +
-                                           std::to_string(flag) + ")");
-    }
+    if (flag) return flag_fail(ctx, flag);
     // delete empty clusters (stable), then start over with the new K
     int kept = 0;
     std::vector<int> newidx(K, -1);
@@ -998,10 +1040,7 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t
                                  ctx->stream), "copy counts");
     int flag = 0;
     DPMM_TRY(logml(ctx, fitems, lml_cluster, &flag));
-    if (flag) {
-      DPMM_HIP(ctx, hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream), "clear flag");
-      return ctx->fail(DPMM_E_NUMERIC, "a float64 Cholesky factorisation met a non-positive pivot");
-    }
+    if (flag) return flag_fail(ctx, flag);
   }
   local.K = ctx->K;
   local.logpost = log_posterior(ctx, cnt, lml_cluster);

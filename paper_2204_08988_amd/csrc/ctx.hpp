@@ -46,6 +46,8 @@ struct dpmm_ctx {
   // device tables
   double *d_m = nullptr, *d_psi = nullptr, *d_beta = nullptr, *d_lgamma_beta = nullptr;
   double *d_gshape = nullptr, *d_grate = nullptr;  // Poisson: Gamma prior
+  // sparse rows: word-major scoring tables [V][K], [V][2K] and the 3K constants
+  float *d_tcl = nullptr, *d_tsub = nullptr, *d_cw = nullptr;
   long long* d_counts = nullptr;  // [2 k_max]
   double* d_moments = nullptr;    // Gaussian [2 k_max][E]
   long long* d_sums = nullptr;    // multinomial [2 k_max][V]
@@ -136,6 +138,7 @@ struct dpmm_ctx {
   }
   bool gaussian() const { return cfg.family == DPMM_GAUSSIAN; }
   bool poisson() const { return cfg.family == DPMM_POISSON; }
+  bool sparse() const { return cfg.sparse != 0; }
   bool sorted_path() const { return gaussian() && d >= dpmm::SORTED_MIN_D; }
 };
 
@@ -172,6 +175,8 @@ dpmm_status static_scratch_init(dpmm_ctx* ctx);
 dpmm_status logml(dpmm_ctx* ctx, const std::vector<LogmlItem>& items, std::vector<double>& out,
                   int* flag_out = nullptr);
 dpmm_status check_device_error(dpmm_ctx* ctx);
+dpmm_status flag_fail(dpmm_ctx* ctx, int flag);
+SparseRows sparse_rows(const void* x);
 dpmm_status ensure_items(dpmm_ctx* ctx, size_t count);
 dpmm_status apply_relabel(dpmm_ctx* ctx, const std::vector<RelabelEntry>& table, int64_t n, uint32_t t, int32_t* z,
                           uint8_t* zsub);

@@ -132,6 +132,25 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
                                    hipEvent_t ev_main1 = nullptr);
 hipError_t launch_loglik_gauss(int d, const float* x, long long n, const float* packed, int K, int k_max,
                                float* out, hipStream_t s);
+// ---- count data in compressed sparse rows (label_csr.hip)
+// bit of the device error flag: an entry of the sparse rows was out of range
+constexpr int ERR_SPARSE_INPUT = 8;
+struct SparseRows {
+  const long long* row_ptr;  // device [n + 1]
+  const int* col;            // device [nnz]
+  const int* val;            // device [nnz]
+  long long nnz;
+};
+hipError_t launch_pack_csr(int K, int V, int k_max, const float* packed, float* tcl, float* tsub, float* cw,
+                           hipStream_t s);
+hipError_t launch_label_csr(const SparseRows& x, long long n, int V, const float* tcl, const float* tsub,
+                            const float* cw, int K, uint32_t t, uint64_t seed, int* z, unsigned char* zsub, int* err,
+                            hipStream_t s);
+hipError_t launch_loglik_csr(const SparseRows& x, long long n, int V, const float* tcl, const float* tsub,
+                             const float* cw, int K, float* out, int* err, hipStream_t s);
+hipError_t launch_stats_csr(const SparseRows& x, long long n, int V, const int* z, const unsigned char* zsub, int K,
+                            long long* counts, long long* sums, int* err, hipStream_t s);
+
 hipError_t launch_label_mult(int V, const int* x, long long n, const float* packed, int K, int k_max,
                              uint32_t t, uint64_t seed, int* z, unsigned char* zsub, hipStream_t s);
 hipError_t launch_loglik_mult(int V, const int* x, long long n, const float* packed, int K, int k_max,

@@ -410,10 +410,7 @@ dpmm_status learned_move(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, in
   std::vector<double> lml;
   int flag = 0;
   DPMM_TRY(logml(ctx, items, lml, &flag));  // synchronises
-  if (flag) {
-    DPMM_HIP(ctx, hipMemsetAsync(ctx->d_err, 0, sizeof(int), s), "clear flag");
-    return ctx->fail(DPMM_E_NUMERIC, "a float64 Cholesky factorisation met a non-positive pivot");
-  }
+  if (flag) return flag_fail(ctx, flag);
   DPMM_TRY(check_selected(ctx, nC));
   const long long nA = split ? back->side_cnt[a_off] : cnt[2 * k1] + cnt[2 * k1 + 1];
   const long long nB = split ? back->side_cnt[1 - a_off] : cnt[2 * k2] + cnt[2 * k2 + 1];

@@ -25,12 +25,43 @@ def _stream(torch):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+class SparseCounts:
+    """Count rows in compressed sparse rows on the device: row_ptr int64
+    [n + 1], col int32 [nnz] (words in [0, V)), val int32 [nnz] (counts).
+    The data argument of a Sampler created with sparse=True."""
+
+    def __init__(self, row_ptr, col, val, V):
+        import torch
+        self.row_ptr = row_ptr.to(device="cuda", dtype=torch.int64).contiguous()
+        self.col = col.to(device="cuda", dtype=torch.int32).contiguous()
+        self.val = val.to(device="cuda", dtype=torch.int32).contiguous()
+        self.shape = (self.row_ptr.shape[0] - 1, int(V))
+        self.device = self.row_ptr.device
+        self._desc = _lib.CSR(self.row_ptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr(),
+                              self.col.shape[0])
+
+    @classmethod
+    def from_numpy(cls, indptr, indices, data, V):
+        import torch
+        return cls(torch.from_numpy(np.ascontiguousarray(indptr, dtype=np.int64)),
+                   torch.from_numpy(np.ascontiguousarray(indices, dtype=np.int32)),
+                   torch.from_numpy(np.ascontiguousarray(data, dtype=np.int32)), V)
+
+    def ptr(self):
+        return ctypes.cast(ctypes.pointer(self._desc), ctypes.c_void_p)
+
+
+def _xptr(x):
+    """The data argument: a device tensor's address or a dpmm_csr descriptor."""
+    return x.ptr() if isinstance(x, SparseCounts) else _tptr(x)
+
+
 class Sampler:
     """One sampler context on the current HIP device and torch stream."""
 
     def __init__(self, family, d, k_max, alpha, seed, kappa=1.0, nu=None, m=None, psi=None,
                  beta=None, burn_out=15, merge_form="paper", precision="fp32", learned=0, stream=None,
-                 gamma_shape=None, gamma_rate=None):
+                 gamma_shape=None, gamma_rate=None, sparse=False):
         import torch
         self.torch = torch
         L = _lib.lib()
@@ -63,6 +94,7 @@ class Sampler:
         cfg.precision = {"fp32": _lib.FP32, "bf16": _lib.BF16, "bf16x3": _lib.BF16X3}[precision]
         cfg.merge_form = {"paper": _lib.MERGE_PAPER, "inverse_split": _lib.MERGE_INVERSE_SPLIT}[merge_form]
         cfg.learned = int(learned)
+        cfg.sparse = 1 if sparse else 0
         self.learned = int(learned)
         self._L = L
         self._ctx = ctypes.c_void_p()
@@ -159,7 +191,7 @@ class Sampler:
     def loglik(self, x):
         n = x.shape[0]
         out = self.torch.empty((n, 3 * self.K), dtype=self.torch.float32, device=x.device)
-        self._check(self._L.dpmm_loglik(self._ctx, _tptr(x), n, _tptr(out)))
+        self._check(self._L.dpmm_loglik(self._ctx, _xptr(x), n, _tptr(out)))
         return out
 
     def sample_labels(self, x, t, z=None, zsub=None):
@@ -168,24 +200,24 @@ class Sampler:
             z = self.torch.empty(n, dtype=self.torch.int32, device=x.device)
         if zsub is None:
             zsub = self.torch.empty(n, dtype=self.torch.uint8, device=x.device)
-        self._check(self._L.dpmm_sample_labels(self._ctx, _tptr(x), n, int(t), _tptr(z), _tptr(zsub)))
+        self._check(self._L.dpmm_sample_labels(self._ctx, _xptr(x), n, int(t), _tptr(z), _tptr(zsub)))
         return z, zsub
 
     def suffstats(self, x, z, zsub):
-        self._check(self._L.dpmm_suffstats(self._ctx, _tptr(x), x.shape[0], _tptr(z), _tptr(zsub)))
+        self._check(self._L.dpmm_suffstats(self._ctx, _xptr(x), x.shape[0], _tptr(z), _tptr(zsub)))
 
     def sample_params(self, t):
         self._check(self._L.dpmm_sample_params(self._ctx, int(t)))
 
     def split_merge(self, x, t, z, zsub):
         info = _lib.IterInfo()
-        self._check(self._L.dpmm_split_merge(self._ctx, _tptr(x), x.shape[0], int(t), _tptr(z), _tptr(zsub),
+        self._check(self._L.dpmm_split_merge(self._ctx, _xptr(x), x.shape[0], int(t), _tptr(z), _tptr(zsub),
                                              ctypes.byref(info)))
         return info.as_dict()
 
     def step(self, x, t, z, zsub):
         info = _lib.IterInfo()
-        self._check(self._L.dpmm_step(self._ctx, _tptr(x), x.shape[0], int(t), _tptr(z), _tptr(zsub),
+        self._check(self._L.dpmm_step(self._ctx, _xptr(x), x.shape[0], int(t), _tptr(z), _tptr(zsub),
                                       ctypes.byref(info)))
         return info.as_dict()
 
@@ -197,7 +229,7 @@ class Sampler:
                               int(train_batch), float(train_lr), 0)
         trace = (_lib.IterInfo * max(int(iters), 1))()
         secs = np.zeros(max(int(iters), 1))
-        self._check(self._L.dpmm_fit(self._ctx, _tptr(x), x.shape[0], ctypes.byref(opt), _tptr(z), _tptr(zsub),
+        self._check(self._L.dpmm_fit(self._ctx, _xptr(x), x.shape[0], ctypes.byref(opt), _tptr(z), _tptr(zsub),
                                      trace, _dptr(secs)))
         return [trace[j].as_dict() for j in range(int(iters))], secs[:int(iters)]
 

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def _cfg(**kw):
     d = kw.pop("d", 2)
     m = np.zeros(d)
-    psi = np.eye(d)
+    psi = np.eye(d) if d <= 1024 else None  # a Gaussian prior is not read past d = 128
     cfg = _lib.Config()
     cfg.family = kw.pop("family", _lib.GAUSSIAN)
     cfg.d = d
@@ -58,6 +58,7 @@ def _cfg(**kw):
     cfg.precision = kw.pop("precision", _lib.FP32)
     cfg.merge_form = kw.pop("merge_form", _lib.MERGE_PAPER)
     cfg.learned = kw.pop("learned", 0)
+    cfg.sparse = kw.pop("sparse", 0)
     assert not kw
     return cfg, keep
 
@@ -91,6 +92,13 @@ def _cfg(**kw):
     (dict(family=_lib.POISSON, d=2, gamma_shape=np.ones(2), gamma_rate=np.array([1.0, float("inf")])), -1),
     (dict(family=_lib.POISSON, d=129, gamma_shape=np.ones(129), gamma_rate=np.ones(129)), -1),
     (dict(learned=1, family=_lib.POISSON, d=4, gamma_shape=np.ones(4), gamma_rate=np.ones(4)), -1),
+    (dict(sparse=2, family=_lib.MULTINOMIAL, d=4, beta=np.ones(4)), -1),
+    (dict(sparse=1), -1),  # Gaussian
+    (dict(sparse=1, family=_lib.MULTINOMIAL, d=2 ** 20 + 1, beta=np.ones(2 ** 20 + 1)), -1),
+    (dict(sparse=1, family=_lib.POISSON, d=2 ** 20 + 1, gamma_shape=np.ones(2 ** 20 + 1),
+          gamma_rate=np.ones(2 ** 20 + 1)), -1),
+    (dict(sparse=1, family=_lib.MULTINOMIAL, d=300, beta=np.ones(300), precision=1), -1),
+    (dict(family=_lib.MULTINOMIAL, d=300, beta=np.ones(300)), -1),  # dense rows: V <= 128
 ])
 def test_create_rejects_bad_config_before_device(kw, status):
     L = _lib.lib()
@@ -130,7 +138,7 @@ def test_struct_layouts_match_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = {"dpmm_config": _lib.Config, "dpmm_iter_info": _lib.IterInfo, "dpmm_learned_info": _lib.LearnedInfo,
-               "dpmm_fit_options": _lib.FitOptions}
+               "dpmm_fit_options": _lib.FitOptions, "dpmm_csr": _lib.CSR}
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "dpmm.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
