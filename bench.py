@@ -18,7 +18,8 @@ whole step (N (K + 2) scores per iteration), iterations per second, the
 roofline of the dominant kernel (the d = 128 BF16 cluster draw, timed by HIP
 events around its own dispatch on the sampler's stream), the other
 configurations (gauss_d32, mult_v100, the d = 2 label step at N = 1e8, the
-d = 2 chain at N = 1e4) as extra keys, and the FP64 oracle's label step on a
+d = 2 chain at N = 1e4, the sparse-row multinomial of the 20newsgroups shape:
+its chain at N = 11 314 and its label step at N = 2e5) as extra keys, and the FP64 oracle's label step on a
 bounded sample on the host cores (all cores and one core).
 
 Other modes: --label-step WORKLOAD (label step at a workload's generating
@@ -44,7 +45,7 @@ PEAK_BF16_MFMA = 2.5e15    # dense BF16 matrix-core peak
 PEAK_FP32_MFMA = 157.3e12  # dense FP32 matrix-core peak
 PEAK_FP64_MFMA = 78.6e12   # dense FP64 matrix-core peak
 HEADLINE = "gauss_d128"
-HEADLINE_KERNEL = "k_label_gauss_mfma_w32<128,false,false>"
+HEADLINE_KERNEL = "k_label_gauss_mfma_cs<128>"
 # HBM bytes per launch of the headline kernel at the headline workload, from
 # rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a copy of known size; None
 # until they are taken for the current kernel
@@ -193,6 +194,64 @@ def label_step_run(torch, name, n, precision, steps, warmup):
             "label_kernel": roof}
 
 
+def sparse_run(torch, n, steps, warmup, chain):
+    """The sparse-row multinomial on the 20newsgroups-shaped stand-in
+    (news_v20k, V = 20 000, 20 topics).  chain=True: full iterations from the
+    converged state (generating labels, every cluster old enough to move);
+    chain=False: the label step at the generating mixture (statistics from
+    the true labels, no split or merge).  The label phase is one kernel
+    (k_label_csr); its HBM roofline counts the rows once: row pointers (8 B a
+    row), entries (4 B word + 4 B count) and the labels written (5 B a row)."""
+    from paper_2204_08988_amd import datagen, _lib
+    from paper_2204_08988_amd.sampler import Sampler, SparseCounts
+    xh, labels = datagen.workload("news_v20k", SEED, n)
+    n, V = xh.shape
+    nnz = int(xh.indices.size)
+    x = SparseCounts.from_numpy(xh.indptr, xh.indices, xh.data, V)
+    del xh
+    labels = np.unique(labels, return_inverse=True)[1]
+    K = int(labels.max()) + 1
+    burn = 5 if chain else 10 ** 9
+    S = Sampler("multinomial", V, 2 * K + 16, ALPHA, SEED, beta=np.full(V, 0.1), burn_out=burn, sparse=True)
+    z = torch.from_numpy(labels.astype(np.int32)).cuda()
+    zs = torch.from_numpy((np.random.Generator(np.random.PCG64(SEED + 7)).integers(0, 2, n)).astype(np.uint8)).cuda()
+    S.set_state(K, [burn if chain else 0] * K)
+    if not chain:
+        S.suffstats(x, z, zs)
+    t = 1
+    for _ in range(warmup):
+        S.step(x, t, z, zs)
+        t += 1
+    torch.cuda.synchronize()
+    ms = {"params": 0.0, "labels": 0.0, "sort": 0.0, "stats": 0.0, "splitmerge": 0.0}
+    k_sum = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = S.step(x, t, z, zs)
+        t += 1
+        k_sum += info["K"]
+        for key in ms:
+            ms[key] += info["ms_" + key]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = {k: v / steps for k, v in ms.items()}
+    bytes_launch = 8 * (n + 1) + 8 * nnz + 5 * n
+    ker_s = ms["labels"] / 1e3
+    rec = {"workload": f"news_v20k: sparse rows (CSR), N={n} documents, V={V}, {K} topics, nnz={nnz}; "
+                       + ("converged chain" if chain else "label step at the generating mixture"),
+           "n": n, "V": V, "nnz": nnz, "k_true": K, "k_mean": k_sum / steps, "ms_per_step": 1e3 * el / steps,
+           "iters_per_s": steps / el, "phase_ms": ms,
+           "label_evals_per_s": n * (k_sum / steps) / ker_s,
+           "label_kernel": {"bound": "hbm", "kernel": "k_label_csr", "kernel_ms": ms["labels"],
+                            "achieved": bytes_launch / ker_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                            "frac": bytes_launch / ker_s / PEAK_HBM, "algorithmic_bytes_per_launch": bytes_launch},
+           "nmi": _lib.nmi(labels, z.cpu().numpy())}
+    S.close()
+    del x
+    torch.cuda.empty_cache()
+    return rec
+
+
 def chain_from_one(torch, name, n, iters, precision="fp32"):
     """Iterations per second of a chain from K = 1 (every iteration timed)."""
     from paper_2204_08988_amd import datagen, _lib
@@ -294,6 +353,8 @@ def headline(args):
         extra["mult_v100_chain"] = converged_chain(torch, "mult_v100", None, "fp32", 20, 3)
         extra["gauss_d2_label_step_n1e8"] = label_step_run(torch, "gauss_d2", 100_000_000, "fp32", 10, 3)
         extra["gauss_d2_chain_n1e4"] = chain_from_one(torch, "gauss_d2", None, 100)
+        extra["news_v20k_chain"] = sparse_run(torch, None, 50, 5, True)
+        extra["news_v20k_label_step_n2e5"] = sparse_run(torch, 200_000, 20, 3, False)
         out["configs"] = extra
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(HEADLINE, 20_000, 24.0)
@@ -421,6 +482,8 @@ def main():
     ap.add_argument("--headline-only", action="store_true", help="skip the other configurations")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a device buffer of BYTES five times (calibrates HBM byte counters)")
+    ap.add_argument("--sparse", action="store_true",
+                    help="instead of the throughput line: the sparse-row (news_v20k) chain and label step only")
     ap.add_argument("--label-step", metavar="WORKLOAD",
                     help="instead of the throughput line: label-step throughput at WORKLOAD's true mixture")
     ap.add_argument("--n", default=None, help="points for --label-step (default: the workload's N)")
@@ -453,6 +516,13 @@ def main():
         return
     if args.label_step:
         label_step(args)
+        return
+    if args.sparse:
+        import torch
+        out = {"news_v20k_chain": sparse_run(torch, int(float(args.n)) if args.n else None, args.steps, args.warmup,
+                                             True),
+               "news_v20k_label_step_n2e5": sparse_run(torch, 200_000, args.steps, args.warmup, False)}
+        print(json.dumps(out), flush=True)
         return
     headline(args)
 

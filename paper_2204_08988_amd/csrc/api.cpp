@@ -507,8 +507,10 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     }
     ok = ok && chk(c->alloc(&c->d_sums, 2 * (size_t)km * d));
     ok = ok && chk(c->alloc(&c->d_log_theta, 3 * (size_t)km * d));
+    if (d > DIR_CHUNK && !c->poisson())
+      ok = ok && chk(c->alloc(&c->d_dpart, 2 * (size_t)3 * km * ((d + DIR_CHUNK - 1) / DIR_CHUNK)));
     if (c->sparse()) {
-      ok = ok && chk(c->alloc(&c->d_tcl, (size_t)km * d));
+      ok = ok && chk(c->alloc(&c->d_tcl, (size_t)((km + 3) & ~3) * d));
       ok = ok && chk(c->alloc(&c->d_tsub, 2 * (size_t)km * d));
       ok = ok && chk(c->alloc(&c->d_cw, 3 * (size_t)km));
     }
@@ -865,12 +867,19 @@ dpmm_status dpmm_sample_params(dpmm_ctx* ctx, uint32_t t) {
     ctx->have_params = true;
     return DPMM_OK;
   }
-  if (ctx->poisson())
-    hipLaunchKernelGGL(k_pois_draw, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->d_gshape, ctx->d_grate,
-                       ctx->d_counts, ctx->d_sums, ctx->cfg.seed, t, ctx->d_log_theta);
-  else
+  const int nch = (ctx->d + DIR_CHUNK - 1) / DIR_CHUNK;
+  if (ctx->poisson()) {
+    hipLaunchKernelGGL(k_pois_draw, dim3(std::min(nch * 8, 256), 3 * K), dim3(256), 0, ctx->stream, K, ctx->d,
+                       ctx->d_gshape, ctx->d_grate, ctx->d_counts, ctx->d_sums, ctx->cfg.seed, t, ctx->d_log_theta);
+  } else if (nch > 1) {
+    hipLaunchKernelGGL(k_dir_draw_chunk, dim3(nch, 3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->d_beta,
+                       ctx->d_sums, ctx->cfg.seed, t, ctx->d_log_theta, ctx->d_dpart);
+    hipLaunchKernelGGL(k_dir_norm, dim3(nch, 3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->d_dpart,
+                       ctx->d_log_theta);
+  } else {
     hipLaunchKernelGGL(k_dir_draw, dim3(3 * K), dim3(256), 0, ctx->stream, K, ctx->d, ctx->d_beta, ctx->d_sums,
                        ctx->cfg.seed, t, ctx->d_log_theta);
+  }
   DPMM_HIP(ctx, hipGetLastError(), "posterior draw kernel");
   return pack_params(ctx);
 }

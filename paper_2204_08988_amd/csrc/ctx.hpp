@@ -48,6 +48,7 @@ struct dpmm_ctx {
   double *d_gshape = nullptr, *d_grate = nullptr;  // Poisson: Gamma prior
   // sparse rows: word-major scoring tables [V][K], [V][2K] and the 3K constants
   float *d_tcl = nullptr, *d_tsub = nullptr, *d_cw = nullptr;
+  double* d_dpart = nullptr;  // per-chunk (max, sum) of the chunked Dirichlet draw
   long long* d_counts = nullptr;  // [2 k_max]
   double* d_moments = nullptr;    // Gaussian [2 k_max][E]
   long long* d_sums = nullptr;    // multinomial [2 k_max][V]

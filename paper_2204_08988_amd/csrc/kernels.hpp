@@ -42,6 +42,11 @@ __global__ void k_pack_mult(int K, int V, int k_max, const double* log_pi, const
                             const double* log_theta, float* packed, int poisson);
 __global__ void k_pois_draw(int K, int V, const double* shape, const double* rate, const long long* counts,
                             const long long* sums, uint64_t seed, uint32_t t, double* log_lambda);
+// the Dirichlet draw over word chunks (vocabularies above DIR_CHUNK words)
+constexpr int DIR_CHUNK = 2048;
+__global__ void k_dir_draw_chunk(int K, int V, const double* beta, const long long* sums, uint64_t seed, uint32_t t,
+                                 double* log_theta, double* part);
+__global__ void k_dir_norm(int K, int V, const double* part, double* log_theta);
 
 // ---- learned split proposal (mlp.hip)
 constexpr int MLP_HIDDEN = 128;

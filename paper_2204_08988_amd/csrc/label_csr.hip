@@ -6,16 +6,17 @@
 // with T = log theta (multinomial; c = log w) or log lambda (Poisson;
 // c = log w - sum_v lambda_v).  With a vocabulary in the tens of thousands
 // and a hundred or so distinct words per row, a row touches a few hundred
-// table rows, so the tables are laid out word-major: tcl[v][K] holds the K
-// cluster values of word v and tsub[v][2K] the sub-cluster values (l, r of
-// cluster 0, l, r of cluster 1, ...).  A nonzero then reads K consecutive
-// floats, which the lanes of one group load together.
+// table rows, so the tables are laid out word-major: tcl[v][KS] holds the K
+// cluster values of word v (KS = K rounded up to 4, the pad zero) and
+// tsub[v][2K] the sub-cluster values (l, r of cluster 0, l, r of cluster 1,
+// ...).  A nonzero then reads K consecutive floats, 16 bytes per lane.
 //
 // One wave per row.  The row's nonzeros are loaded 64 at a time (one per
-// lane) and broadcast to groups of KP lanes (KP the power of two >= K, at
-// most 64): group g takes nonzeros g, g + G, ... of the batch (G = 64 / KP),
-// lane j of the group accumulates cluster j; the G partial sums are then
-// added across groups.  More than 64 clusters run in chunks of 64.  The
+// lane) and broadcast to groups of QP lanes (QP the power of two >= KS / 4,
+// at most 64): group g takes nonzeros g, g + G, ... of the batch (G = 64 /
+// QP), lane q of the group accumulates clusters 4q .. 4q + 3; the G partial
+// sums are then added across groups.  More than 256 clusters run in chunks
+// of 256.  The
 // scores go to the wave's slice of LDS; the top-2 screen, the exact
 // Gumbel-max over the clusters within the Gumbel range (the winner of
 // max_k l_k + g_k, smaller k on ties) and the sub-label draw follow as in the
@@ -74,22 +75,24 @@ __device__ __forceinline__ void load_batch(const int* __restrict__ col, const in
 __global__ __launch_bounds__(BLOCK) void k_label_csr(const long long* __restrict__ rp, const int* __restrict__ col,
                                                      const int* __restrict__ val, long long nnz, long long n, int V,
                                                      const float* __restrict__ tcl, const float* __restrict__ tsub,
-                                                     const float* __restrict__ cw, int K, int lg_kp, uint32_t t,
+                                                     const float* __restrict__ cw, int K, int lg_qp, uint32_t t,
                                                      uint64_t seed, int* __restrict__ z,
                                                      unsigned char* __restrict__ zsub, int* __restrict__ err) {
   extern __shared__ float sc_all[];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   float* sc = sc_all + (size_t)w * K;
-  const int KP = 1 << lg_kp, G = 64 >> lg_kp;
-  const int g = lane >> lg_kp, jl = lane & (KP - 1);
-  const int NC = (K + 63) >> 6;
+  const int Q = (K + 3) >> 2;  // float4 per table row
+  const int QP = 1 << lg_qp, G = 64 >> lg_qp;
+  const int g = lane >> lg_qp, ql = lane & (QP - 1);
+  const int NC = (Q + 63) >> 6;
+  const float4* t4 = reinterpret_cast<const float4*>(tcl);
   for (long long i = (long long)blockIdx.x * WAVES + w; i < n; i += (long long)gridDim.x * WAVES) {
     long long e0, e1;
     if (!row_range(rp, i, nnz, e0, e1, err)) continue;
     // cluster scores into LDS
     for (int c = 0; c < NC; ++c) {
-      const int j = 64 * c + jl;
-      float acc = 0.0f;
+      const int q = 64 * c + ql;
+      float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       for (long long b = e0; b < e1; b += 64) {
         const int m = (int)min(64LL, e1 - b);
         int cl;
@@ -100,11 +103,28 @@ __global__ __launch_bounds__(BLOCK) void k_label_csr(const long long* __restrict
           const int u = u0 + g;  // < 64: u0 <= 64 - G
           const int cc = __shfl(cl, u);
           const float vv = __shfl(vl, u);
-          if (j < K) acc = fmaf(vv, tcl[(size_t)cc * K + j], acc);
+          if (q < Q) {
+            const float4 tv = t4[(size_t)cc * Q + q];
+            acc.x = fmaf(vv, tv.x, acc.x);
+            acc.y = fmaf(vv, tv.y, acc.y);
+            acc.z = fmaf(vv, tv.z, acc.z);
+            acc.w = fmaf(vv, tv.w, acc.w);
+          }
         }
       }
-      for (int off = KP; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
-      if (g == 0 && j < K) sc[j] = cw[j] + acc;
+      for (int off = QP; off < 64; off <<= 1) {
+        acc.x += __shfl_xor(acc.x, off);
+        acc.y += __shfl_xor(acc.y, off);
+        acc.z += __shfl_xor(acc.z, off);
+        acc.w += __shfl_xor(acc.w, off);
+      }
+      if (g == 0 && q < Q) {
+        const int k = 4 * q;
+        sc[k] = cw[k] + acc.x;
+        if (k + 1 < K) sc[k + 1] = cw[k + 1] + acc.y;
+        if (k + 2 < K) sc[k + 2] = cw[k + 2] + acc.z;
+        if (k + 3 < K) sc[k + 3] = cw[k + 3] + acc.w;
+      }
     }
     wave_lds_sync();
     // top-2 screen (arg: the smallest k of the maximum)
@@ -169,9 +189,9 @@ __global__ __launch_bounds__(BLOCK) void k_label_csr(const long long* __restrict
       float vl;
       load_batch(col, val, b, m, V, lane, cl, vl, err);
       if (lane < m) {
-        const float* r = ts + (size_t)cl * 2 * K;
-        al = fmaf(vl, r[0], al);
-        ar = fmaf(vl, r[1], ar);
+        const float2 r = *reinterpret_cast<const float2*>(ts + (size_t)cl * 2 * K);
+        al = fmaf(vl, r.x, al);
+        ar = fmaf(vl, r.y, ar);
       }
     }
     al = wave_sum(al);
@@ -191,6 +211,7 @@ __global__ __launch_bounds__(BLOCK) void k_loglik_csr(const long long* __restric
                                                       const float* __restrict__ cw, int K, float* __restrict__ out,
                                                       int* __restrict__ err) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int KS = (K + 3) & ~3;
   for (long long i = (long long)blockIdx.x * WAVES + w; i < n; i += (long long)gridDim.x * WAVES) {
     long long e0, e1;
     if (!row_range(rp, i, nnz, e0, e1, err)) continue;
@@ -204,7 +225,7 @@ __global__ __launch_bounds__(BLOCK) void k_loglik_csr(const long long* __restric
           continue;
         }
         if (j < K)
-          acc = fmaf((float)v, tcl[(size_t)c * K + j], acc);
+          acc = fmaf((float)v, tcl[(size_t)c * KS + j], acc);
         else if (j < 3 * K)
           acc = fmaf((float)v, tsub[(size_t)c * 2 * K + (j - K)], acc);
       }
@@ -253,12 +274,14 @@ __global__ void k_zero_u64(unsigned long long* __restrict__ p, size_t n) {
 // Word-major tables from the component records of k_pack_mult (slot k for
 // cluster k, k_max + 2k + h for its sub-clusters; value 0 the constant c,
 // values 4 .. 4 + V - 1 the log parameters): a 64 x 64 tile of (component,
-// word) per workgroup, transposed through LDS.
+// word) per workgroup, transposed through LDS; the pad of each tcl row is
+// zeroed.
 __global__ __launch_bounds__(BLOCK) void k_pack_csr(int K, int V, int k_max, const float* __restrict__ packed,
                                                     float* __restrict__ tcl, float* __restrict__ tsub,
                                                     float* __restrict__ cw) {
   __shared__ float tile[64][65];
   const int S = mult_rec_stride(V);
+  const int KS = (K + 3) & ~3;
   const int v0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   const int lane = threadIdx.x & 63, r0 = threadIdx.x >> 6;
   auto slot = [&](int j) { return j < K ? j : k_max + (j - K); };
@@ -271,9 +294,11 @@ __global__ __launch_bounds__(BLOCK) void k_pack_csr(int K, int V, int k_max, con
   __syncthreads();
   for (int r = r0; r < 64; r += WAVES) {
     const int v = v0 + r, j = j0 + lane;
-    if (v >= V || j >= 3 * K) continue;
+    if (v >= V) continue;
+    if (blockIdx.y == 0 && lane < KS - K) tcl[(size_t)v * KS + K + lane] = 0.0f;
+    if (j >= 3 * K) continue;
     if (j < K)
-      tcl[(size_t)v * K + j] = tile[lane][r];
+      tcl[(size_t)v * KS + j] = tile[lane][r];
     else
       tsub[(size_t)v * 2 * K + (j - K)] = tile[lane][r];
   }
@@ -299,8 +324,9 @@ hipError_t launch_label_csr(const SparseRows& x, long long n, int V, const float
                             const float* cw, int K, uint32_t t, uint64_t seed, int* z, unsigned char* zsub, int* err,
                             hipStream_t s) {
   if (n == 0) return hipSuccess;
+  const int Q = (K + 3) / 4;
   int lg = 0;
-  while ((1 << lg) < K && lg < 6) ++lg;
+  while ((1 << lg) < Q && lg < 6) ++lg;
   const size_t lds = (size_t)WAVES * K * sizeof(float);
   hipLaunchKernelGGL(k_label_csr, dim3(waves_grid(n)), dim3(BLOCK), lds, s, x.row_ptr, x.col, x.val, x.nnz, n, V, tcl,
                      tsub, cw, K, lg, t, seed, z, zsub, err);

@@ -358,7 +358,9 @@ struct TriTiles {
 
 constexpr int BLOCK_W32 = 512;  // threads of k_label_gauss_mfma_w32: 8 waves of 32 points
 
-// d = 64, 128: a cluster's non-zero whitener tiles (only those on or below
+// d = 64, 128 in bf16x3, and the candidate pass of either form (the BF16
+// main pass is k_label_gauss_mfma_cs below): a cluster's non-zero whitener
+// tiles (only those on or below
 // the diagonal), its mean and its constant are copied from global memory
 // straight into LDS (global_load_lds, no registers) into one of two
 // statically allocated buffers, while the workgroup scores its points against
@@ -551,6 +553,208 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
   }
 }
 
+constexpr int BLOCK_CS = 512;  // threads of k_label_gauss_mfma_cs: 8 waves, two per SIMD
+constexpr int CS_PTS = 256;    // points per workgroup step: 8 tiles of 32
+
+// Two partial top-2 states over disjoint cluster sets combined: the same state
+// as one sequential pass over both (maximum bounds, the smallest cluster index
+// among equal maxima, the second largest bound of the union).
+__device__ __forceinline__ void top2_merge(Top2U& a, float u1, float u2, float lo, int k1) {
+  const bool take = u1 > a.u1 || (u1 == a.u1 && k1 < a.k1);
+  const float s2 = fmaxf(fminf(a.u1, u1), fmaxf(a.u2, u2));
+  a.k1 = take ? k1 : a.k1;
+  a.u1 = fmaxf(a.u1, u1);
+  a.u2 = s2;
+  a.lo_max = fmaxf(a.lo_max, lo);
+}
+
+// Main pass for d = 64, 128 in BF16, cluster-stationary: the workgroup's 256
+// rows are copied once per step into LDS (rows padded by four floats, so the
+// sixteen-byte reads of 32 rows fall on distinct banks), and each of the eight
+// waves takes every eighth cluster, holding that cluster's whitener fragments
+// (its non-zero tiles only), its mean half and its constant in registers while
+// it sweeps the eight 32-point tiles.  The whitener then crosses LDS not at
+// all and the rows once per tile and cluster: 16 KB per tile and cluster at
+// d = 128, against 36 KB for k_label_gauss_mfma_w32, whose per-tile fragment
+// reads alone would take the LDS's whole bandwidth at the matrix cores' rate.
+// Within a step the waves never wait for each other, so the two waves of a
+// SIMD drift apart and one's matrix-core tiles overlap the other's centring
+// and norms.  Each lane keeps the partial top-2 of the points of its half's
+// tiles (tiles 2j + half, point 32 t + lane % 32) over its wave's clusters;
+// the eight partial states are merged through LDS at the end of the step.
+// The scores equal those of k_label_gauss_mfma_w32 bit for bit (the same BF16
+// operands, MFMA order and FP32 sums) and so do the merged states, so the
+// labels and the deferred points are the same.
+template <int D>
+__global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_cs(const float* __restrict__ x, long long n,
+                                                                     long long per_block,
+                                                                     const float* __restrict__ packed,
+                                                                     const bf16x8* __restrict__ whi, int K,
+                                                                     int* __restrict__ z, int* __restrict__ hist,
+                                                                     int* __restrict__ tot, int* __restrict__ flagged,
+                                                                     int* __restrict__ n_flagged) {
+  using TT = TriTiles<D>;
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  constexpr int MT = TT::MT, KS = TT::KS, NF = MT * KS * 64, NT = TT::NT;
+  constexpr int XS = D + 4;             // LDS row stride in floats
+  constexpr int TILES = CS_PTS / 32;
+  constexpr int PARTS = D / 64;         // 64-float pieces of a row (one wave copy each)
+  constexpr int NW = BLOCK_CS / 64;
+  constexpr float REL = BF16_TOL_REL;
+  static_assert(CS_PTS == BLOCK && D % 64 == 0 && NW * CS_PTS * 4 <= CS_PTS * XS, "step, row copies, states");
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* xs = reinterpret_cast<float*>(smem);              // [CS_PTS][XS] rows, then the partial states
+  int* h = reinterpret_cast<int*>(xs + CS_PTS * XS);       // [K] counters
+  for (int k = threadIdx.x; k < K; k += BLOCK_CS) h[k] = 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  const long long begin = (long long)blockIdx.x * per_block;
+  const long long end = begin + per_block < n ? begin + per_block : n;
+  for (long long chunk = begin; chunk < end; chunk += CS_PTS) {
+    const int rows = end - chunk < CS_PTS ? (int)(end - chunk) : CS_PTS;
+    __syncthreads();  // the previous step's merge is done with xs
+    // rows past the end copy row `chunk` (their scores are never used)
+    for (int e = wave; e < CS_PTS * PARTS; e += NW) {
+      const int r = e / PARTS, part = e - r * PARTS;
+      const float* src = x + (chunk + (r < rows ? r : 0)) * D + part * 64 + lane;
+      __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(xs + r * XS + part * 64), 4, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    Top2U st[TILES / 2];
+#pragma unroll
+    for (int j = 0; j < TILES / 2; ++j) st[j].init();
+    // cluster k's non-zero fragment tiles [f0, f1), this lane's mean half, its constant
+    bf16x8 a[NT];
+    float mu[KS][8];
+    float ck = 0.0f;
+    auto load_frags = [&](int k, int f0, int f1) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < TT::tiles(mt); ++ks)
+          if (TT::off(mt) + ks >= f0 && TT::off(mt) + ks < f1)
+            a[TT::off(mt) + ks] = whi[(size_t)k * NF + (size_t)(mt * KS + ks) * 64 + lane];
+    };
+    auto load_mu = [&](int k) {
+      const float* rec = packed + (size_t)k * S;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const float4 u0 = *reinterpret_cast<const float4*>(rec + 4 + 16 * ks + 8 * half);
+        const float4 u1 = *reinterpret_cast<const float4*>(rec + 4 + 16 * ks + 8 * half + 4);
+        mu[ks][0] = u0.x;
+        mu[ks][1] = u0.y;
+        mu[ks][2] = u0.z;
+        mu[ks][3] = u0.w;
+        mu[ks][4] = u1.x;
+        mu[ks][5] = u1.y;
+        mu[ks][6] = u1.z;
+        mu[ks][7] = u1.w;
+      }
+    };
+    for (int k = wave; k < K; k += NW) {
+      load_frags(k, 0, NT);
+      load_mu(k);
+      ck = packed[(size_t)k * S];
+#pragma unroll
+      for (int t = 0; t < TILES; ++t) {
+        // tile t's B operand, k-slice by k-slice just before the row block that
+        // first needs it (this lane's half of row 32 t + col, centred and
+        // rounded), so that each slice's centring overlaps the previous row
+        // block's matrix-core tiles; the wave's priority is raised while it
+        // issues them.
+        const float* xr = xs + (t * 32 + col) * XS + 8 * half;
+        bf16x8 b[KS];
+        auto center = [&](int ks) {
+          const float4 v0 = *reinterpret_cast<const float4*>(xr + 16 * ks);
+          const float4 v1 = *reinterpret_cast<const float4*>(xr + 16 * ks + 4);
+          b[ks][0] = (__bf16)(v0.x - mu[ks][0]);
+          b[ks][1] = (__bf16)(v0.y - mu[ks][1]);
+          b[ks][2] = (__bf16)(v0.z - mu[ks][2]);
+          b[ks][3] = (__bf16)(v0.w - mu[ks][3]);
+          b[ks][4] = (__bf16)(v1.x - mu[ks][4]);
+          b[ks][5] = (__bf16)(v1.y - mu[ks][5]);
+          b[ks][6] = (__bf16)(v1.z - mu[ks][6]);
+          b[ks][7] = (__bf16)(v1.w - mu[ks][7]);
+        };
+        float q0 = 0.0f, q1 = 0.0f;
+        f32x16 acc;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+          for (int ks = (mt == 0 ? 0 : TT::tiles(mt - 1)); ks < TT::tiles(mt); ++ks) center(ks);
+          if (mt > 0) {
+#pragma unroll
+            for (int e = 0; e < 16; e += 2) {
+              q0 = fmaf(acc[e], acc[e], q0);
+              q1 = fmaf(acc[e + 1], acc[e + 1], q1);
+            }
+          }
+          acc = f32x16{0};
+          __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+          for (int ks = 0; ks < TT::tiles(mt); ++ks)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[TT::off(mt) + ks], b[ks], acc, 0, 0, 0);
+          __builtin_amdgcn_s_setprio(0);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; e += 2) {
+          q0 = fmaf(acc[e], acc[e], q0);
+          q1 = fmaf(acc[e + 1], acc[e + 1], q1);
+        }
+        // the two coordinate halves of the point: lanes l and l + 32 swap their
+        // sums (v_permlane32_swap: no LDS round trip) and add them
+        float qm = q0 + q1;
+        {
+          const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(qm), __float_as_uint(qm), false, false);
+          qm = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+        }
+        const float l = fmaf(-0.5f, qm, ck);
+        // the owning half's state, updated without a branch
+        Top2U& sj = st[t >> 1];
+        Top2U nx = sj;
+        nx.push(l, qm, REL, k);
+        const bool own = (t & 1) == half;
+        sj.u1 = own ? nx.u1 : sj.u1;
+        sj.u2 = own ? nx.u2 : sj.u2;
+        sj.lo_max = own ? nx.lo_max : sj.lo_max;
+        sj.k1 = own ? nx.k1 : sj.k1;
+        __builtin_amdgcn_sched_barrier(0);  // one tile at a time: no hoisting of the next tile's operands
+      }
+    }
+    __syncthreads();  // every wave is done with the rows
+    // partial states [wave][point]: u1, u2, lo_max, k1
+    float* ps = xs;
+#pragma unroll
+    for (int j = 0; j < TILES / 2; ++j) {
+      const int p = (2 * j + half) * 32 + col;
+      float* o = ps + ((size_t)wave * CS_PTS + p) * 4;
+      o[0] = st[j].u1;
+      o[1] = st[j].u2;
+      o[2] = st[j].lo_max;
+      o[3] = __int_as_float(st[j].k1);
+    }
+    __syncthreads();
+    if (threadIdx.x < CS_PTS) {
+      Top2U m;
+      m.init();
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const float* o = ps + ((size_t)w * CS_PTS + threadIdx.x) * 4;
+        top2_merge(m, o[0], o[1], o[2], __float_as_int(o[3]));
+      }
+      finish_main(threadIdx.x < rows, chunk + threadIdx.x, m, z, h, flagged, n_flagged, lane);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += BLOCK_CS) {
+    hist[(size_t)blockIdx.x * K + k] = h[k];
+    if (h[k]) atomicAdd(&tot[k], h[k]);
+  }
+}
+
+size_t label_cs_lds(int d, int K) { return ((size_t)CS_PTS * (d + 4)) * sizeof(float) + (size_t)K * sizeof(int); }
+
 constexpr int RS_BLOCK = 256;
 
 __device__ __forceinline__ int wave_min_i(int v) {
@@ -709,9 +913,10 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
   e = launch_zero64(n_flagged, 1, s);
   if (e != hipSuccess) return e;
   static bool attr_set = false;
-  if (!attr_set) {  // d = 32: more than 64 KB of dynamic LDS (160 KB per CU on gfx950)
-    const void* fns[3] = {(const void*)k_label_gauss_mfma32<true, false>, (const void*)k_label_gauss_mfma32<false, false>,
-                          (const void*)k_label_gauss_mfma32<true, true>};
+  if (!attr_set) {  // d = 32 and the cluster-stationary kernels: more than 64 KB of dynamic LDS (160 KB per CU)
+    const void* fns[5] = {(const void*)k_label_gauss_mfma32<true, false>, (const void*)k_label_gauss_mfma32<false, false>,
+                          (const void*)k_label_gauss_mfma32<true, true>, (const void*)k_label_gauss_mfma_cs<128>,
+                          (const void*)k_label_gauss_mfma_cs<64>};
     for (const void* f : fns) {
       e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       if (e != hipSuccess) return e;
@@ -726,7 +931,16 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
     // optional events taken by the main pass's own dispatch (its start and end
     // time stamps, for timing it alone without extra queue packets)
     hipEvent_t e0 = cands ? nullptr : ev_main0, e1 = cands ? nullptr : ev_main1;
-    if (d == 64 || d == 128) {
+    if ((d == 64 || d == 128) && !cands && !x3) {
+      // BF16 main pass, cluster-stationary: the rows in LDS, the whitener in registers
+      const size_t lcs = label_cs_lds(d, K);
+      if (d == 128)
+        hipExtLaunchKernelGGL((k_label_gauss_mfma_cs<128>), dim3(Gp), dim3(BLOCK_CS), lcs, s, e0, e1, 0, x, n,
+                              per_block, packed, hi, K, z, hist, tot, flagged, n_flagged);
+      else
+        hipExtLaunchKernelGGL((k_label_gauss_mfma_cs<64>), dim3(Gp), dim3(BLOCK_CS), lcs, s, e0, e1, 0, x, n,
+                              per_block, packed, hi, K, z, hist, tot, flagged, n_flagged);
+    } else if (d == 64 || d == 128) {
       // static staging buffers; only the histogram is dynamic
 #define DPMM_MFMA_W32(DD, XX, CC)                                                                            \
   hipExtLaunchKernelGGL((k_label_gauss_mfma_w32<DD, XX, CC>), dim3(Gp), dim3(BLOCK_W32), lh, s, e0, e1, 0, x, n, \

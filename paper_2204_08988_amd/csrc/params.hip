@@ -646,20 +646,65 @@ __global__ void k_dir_draw(int K, int V, const double* __restrict__ beta,
   for (int v = threadIdx.x; v < V; v += blockDim.x) out[v] -= lse;
 }
 
-// Poisson family, one workgroup per component: log lambda_v for lambda_v ~
-// Gamma(a_v + c_v, b_v + n) (shape, rate), the Gamma(a_v + c_v, 1) variate of
-// draw v of (3k + c, TAG_DIRTHETA) divided by the rate.
+// The Dirichlet draw of a large vocabulary over a grid of (word chunk,
+// component): the chunk's log-Gamma variates, and the chunk's maximum and
+// sum of exp(variate - maximum) into part[e][chunk]; k_dir_norm then
+// subtracts each component's log-sum-exp, taken over the chunks in order.
+__global__ void k_dir_draw_chunk(int K, int V, const double* __restrict__ beta, const long long* __restrict__ sums,
+                                 uint64_t seed, uint32_t t, double* __restrict__ log_theta, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int e = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  if (e >= 3 * K) return;
+  const int k = e / 3, c = e % 3;
+  const int s0 = c == 0 ? 2 * k : 2 * k + (c - 1);
+  const int s1 = c == 0 ? 2 * k + 1 : -1;
+  double* out = log_theta + (size_t)e * V;
+  const int v0 = ch * DIR_CHUNK, v1 = min(V, v0 + DIR_CHUNK);
+  double mx = -INFINITY;
+  for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+    const double cnt = (double)sums[(size_t)s0 * V + v] + (s1 >= 0 ? (double)sums[(size_t)s1 * V + v] : 0.0);
+    const double lg = log_gamma_draw(seed, t, (uint32_t)e, TAG_DIRTHETA, (uint32_t)v, beta[v] + cnt);
+    out[v] = lg;
+    mx = fmax(mx, lg);
+  }
+  mx = block_reduce_max(mx, red);
+  double sm = 0.0;
+  for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) sm += exp(out[v] - mx);
+  sm = block_reduce_sum(sm, red);
+  if (threadIdx.x == 0) {
+    part[((size_t)e * nch + ch) * 2] = mx;
+    part[((size_t)e * nch + ch) * 2 + 1] = sm;
+  }
+}
+
+__global__ void k_dir_norm(int K, int V, const double* __restrict__ part, double* __restrict__ log_theta) {
+  const int e = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  if (e >= 3 * K) return;
+  const double* p = part + (size_t)e * nch * 2;
+  double mx = -INFINITY;
+  for (int j = 0; j < nch; ++j) mx = fmax(mx, p[2 * j]);
+  double sm = 0.0;
+  for (int j = 0; j < nch; ++j) sm += p[2 * j + 1] * exp(p[2 * j] - mx);
+  const double lse = mx + log(sm);
+  double* out = log_theta + (size_t)e * V;
+  const int v1 = min(V, (ch + 1) * DIR_CHUNK);
+  for (int v = ch * DIR_CHUNK + threadIdx.x; v < v1; v += blockDim.x) out[v] -= lse;
+}
+
+// Poisson family, a grid of (word chunk, component): log lambda_v for
+// lambda_v ~ Gamma(a_v + c_v, b_v + n) (shape, rate), the Gamma(a_v + c_v, 1)
+// variate of draw v of (3k + c, TAG_DIRTHETA) divided by the rate.
 __global__ void k_pois_draw(int K, int V, const double* __restrict__ shape, const double* __restrict__ rate,
                             const long long* __restrict__ counts, const long long* __restrict__ sums, uint64_t seed,
                             uint32_t t, double* __restrict__ log_lambda) {
-  const int e = blockIdx.x;
+  const int e = blockIdx.y;
   if (e >= 3 * K) return;
   const int k = e / 3, c = e % 3;
   const int s0 = c == 0 ? 2 * k : 2 * k + (c - 1);
   const int s1 = c == 0 ? 2 * k + 1 : -1;
   const double n = (double)counts[s0] + (s1 >= 0 ? (double)counts[s1] : 0.0);
   double* out = log_lambda + (size_t)e * V;
-  for (int v = threadIdx.x; v < V; v += blockDim.x) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x) {
     const double cnt = (double)sums[(size_t)s0 * V + v] + (s1 >= 0 ? (double)sums[(size_t)s1 * V + v] : 0.0);
     out[v] = log_gamma_draw(seed, t, (uint32_t)e, TAG_DIRTHETA, (uint32_t)v, shape[v] + cnt) - log(rate[v] + n);
   }

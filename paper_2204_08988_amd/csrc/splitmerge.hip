@@ -467,11 +467,15 @@ __global__ void k_merge_decide(int n_pairs, const LogmlItem* __restrict__ pairs,
   accept[p] = log(u) < lh ? 1 : 0;
 }
 
-__global__ void k_logml_mult(int n_items, const LogmlItem* __restrict__ items, int V,
-                             const double* __restrict__ beta, double beta_sum, double lgamma_beta_sum,
-                             const double* __restrict__ lgamma_beta, const long long* __restrict__ counts,
-                             const long long* __restrict__ sums, double* __restrict__ out) {
-  __shared__ double red[BLOCK];
+// NT threads per item: 1024 for a large vocabulary (the log-Gamma calls of an
+// item spread over 16 waves), BLOCK otherwise
+template <int NT>
+__global__ __launch_bounds__(NT) void k_logml_mult(int n_items, const LogmlItem* __restrict__ items, int V,
+                                                   const double* __restrict__ beta, double beta_sum,
+                                                   double lgamma_beta_sum, const double* __restrict__ lgamma_beta,
+                                                   const long long* __restrict__ counts,
+                                                   const long long* __restrict__ sums, double* __restrict__ out) {
+  __shared__ double red[NT];
   const int it = blockIdx.x;
   if (it >= n_items) return;
   const LogmlItem item = items[it];
@@ -483,10 +487,11 @@ __global__ void k_logml_mult(int n_items, const LogmlItem* __restrict__ items, i
     return;
   }
   double acc = 0.0, tot = 0.0;
-  for (int v = threadIdx.x; v < V; v += BLOCK) {
+  for (int v = threadIdx.x; v < V; v += NT) {
     long long c = 0;
     for (int q = 0; q < 4; ++q)
       if (item.seg[q] >= 0) c += sums[(size_t)item.seg[q] * V + v];
+    if (c == 0) continue;  // lgamma(beta_v) - lgamma(beta_v) = 0: most words of a large vocabulary
     acc += lgamma_d(beta[v] + (double)c) - lgamma_beta[v];
     tot += (double)c;
   }
@@ -617,8 +622,12 @@ hipError_t launch_logml_mult(int n_items, const LogmlItem* items, int V, const d
                              double lgamma_beta_sum, const double* lgamma_beta, const long long* counts,
                              const long long* sums, double* out, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_logml_mult, dim3(n_items), dim3(BLOCK), 0, s, n_items, items, V, beta, beta_sum,
-                     lgamma_beta_sum, lgamma_beta, counts, sums, out);
+  if (V > 4096)
+    hipLaunchKernelGGL(k_logml_mult<1024>, dim3(n_items), dim3(1024), 0, s, n_items, items, V, beta, beta_sum,
+                       lgamma_beta_sum, lgamma_beta, counts, sums, out);
+  else
+    hipLaunchKernelGGL(k_logml_mult<BLOCK>, dim3(n_items), dim3(BLOCK), 0, s, n_items, items, V, beta, beta_sum,
+                       lgamma_beta_sum, lgamma_beta, counts, sums, out);
   return hipGetLastError();
 }
 
