@@ -46,10 +46,12 @@ PEAK_FP32_MFMA = 157.3e12  # dense FP32 matrix-core peak
 PEAK_FP64_MFMA = 78.6e12   # dense FP64 matrix-core peak
 HEADLINE = "gauss_d128"
 HEADLINE_KERNEL = "k_label_gauss_mfma_cs<128>"
-# HBM bytes per launch of the headline kernel at the headline workload, from
-# rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a copy of known size; None
-# until they are taken for the current kernel
-MEASURED_TRAFFIC = {HEADLINE_KERNEL: None}
+# HBM bytes per launch of the headline kernel at the headline workload (N = 1e7,
+# d = 128, K = 100): rocprofv3 FETCH_SIZE 3.804e6 KiB x 2.0 + WRITE_SIZE 4.065e4
+# KiB x 1.0, the factors being what a 1 GiB device copy reads on the same
+# counters (FETCH_SIZE 0.5 GiB, WRITE_SIZE 1 GiB); set to None whenever the
+# kernel changes until the counters are taken again
+MEASURED_TRAFFIC = {HEADLINE_KERNEL: (3.804e6 * 2.0 + 4.065e4) * 1024}
 
 
 def flops_per_eval(d):
@@ -126,7 +128,8 @@ def mfma_roofline(rec, d, kernel):
     flops = rec["n"] * rec["k_mean"] * flops_per_eval(d)
     s = rec["label_kernel_ms"] / 1e3
     return {"bound": "mfma", "achieved": flops / s / 1e12, "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
-            "frac": flops / s / PEAK_BF16_MFMA, "traffic": MEASURED_TRAFFIC.get(kernel), "kernel": kernel,
+            "frac": flops / s / PEAK_BF16_MFMA, "traffic": MEASURED_TRAFFIC.get(kernel), "traffic_unit": "bytes per launch",
+            "algorithmic_bytes_per_launch": rec["n"] * (4 * d + 4), "kernel": kernel,
             "kernel_ms": rec["label_kernel_ms"], "algorithmic_flops_per_eval": flops_per_eval(d),
             "evals_per_launch": rec["n"] * rec["k_mean"]}
 
