@@ -207,26 +207,33 @@ __global__ __launch_bounds__(BLOCK) void k_logml_gauss_wave(int n_items, const L
                           0.5 * d * (log(prior.kappa) - log(kn));
   }
 }
-
 // 64 < d <= 128: one workgroup per item, Psi_n held in registers as the
 // 136 lower 8 x 8 tiles of a 128 x 128 matrix (d padded with an identity
-// block, whose pivots are 1), one tile per thread of the first 136.  Step j of
-// the right-looking Cholesky: the pivot's owner publishes L_jj, the owners of
-// column j scale it and publish it, and every thread updates its tile from
-// the published column -- two barriers per step, a 1 KB column buffer in LDS,
-// no strided LDS access.
+// block, whose pivots are 1), one tile per thread of the first 136.  Blocked
+// right-looking Cholesky, one 8-column panel per step: the diagonal tile's
+// owner factors it in registers and publishes L_jj (its own 8 x 8 buffer), the
+// owners of the tiles below solve against it and publish the panel, and every
+// trailing tile takes the rank-8 update from the published panel -- two
+// barriers per 8 columns, an 8 KB panel buffer in LDS read as contiguous 8-row
+// pieces.  A buffer is rewritten only after the barrier that follows its last
+// reads (L_jj: read before the panel barrier; the panel: read before the next
+// step's first barrier).  log|Psi_n| is
+// summed as one log per panel (the product of its 8 pivots).
 constexpr int TILE_T = 136;  // 16 * 17 / 2 lower tiles of 8 x 8
+constexpr int CHOL_T = 192;  // three waves cover the 136 tile owners
 
-__global__ __launch_bounds__(BLOCK) void k_logml_gauss_tile(int n_items, const LogmlItem* __restrict__ items, int d,
-                                                            NiwPriorDev prior, double logdet_psi,
-                                                            const long long* __restrict__ counts,
-                                                            const double* __restrict__ moments,
-                                                            double* __restrict__ out, int* __restrict__ err,
-                                                            const int* __restrict__ list,
-                                                            const int* __restrict__ list_count, int list_base) {
-  constexpr int DP = 128, T = 8;
-  __shared__ double xbar[DP], col[DP], red[BLOCK];
-  __shared__ double piv;
+__global__ __launch_bounds__(CHOL_T) void k_logml_gauss_tile(int n_items, const LogmlItem* __restrict__ items, int d,
+                                                             NiwPriorDev prior, double logdet_psi,
+                                                             const long long* __restrict__ counts,
+                                                             const double* __restrict__ moments,
+                                                             double* __restrict__ out, int* __restrict__ err,
+                                                             const int* __restrict__ list,
+                                                             const int* __restrict__ list_count, int list_base) {
+  constexpr int DP = 128, T = 8, NTL = DP / T;
+  __shared__ double xbar[DP];
+  __shared__ __align__(16) double pan[T][DP];  // pan[c][row] = L[row][8 jt + c] below the diagonal tile
+  __shared__ double dg[T][T];                 // dg[c][r] = L[8 jt + r][8 jt + c] of the diagonal tile
+  __shared__ double red[CHOL_T / 64];
   __shared__ int bad;
   const int it = logml_item(blockIdx.x, n_items, list, list_count, list_base);
   if (it < 0) return;
@@ -284,63 +291,94 @@ __global__ __launch_bounds__(BLOCK) void k_logml_gauss_tile(int n_items, const L
       }
       a[r][c] = v;
     }
-  double ld = 0.0;  // sum of log L_jj over this thread's pivots
-  for (int j = 0; j < DP; ++j) {
-    const int jt = j >> 3, jr = j & 7;
-    // the pivot
+  double ld = 0.0;  // sum of log L_jj over this thread's diagonal tiles
+  for (int jt = 0; jt < NTL; ++jt) {
+    // the diagonal tile, factored in registers (lower triangle; the upper part is never read)
     if (owner && TR == jt && TC == jt) {
-      double s = 0.0;
+      double prod = 1.0;
+      bool ok = true;
 #pragma unroll
-      for (int r = 0; r < T; ++r) s = r == jr ? a[r][r] : s;
-      if (!(s > 0.0) || !isfinite(s)) {
-        bad = 1;
-        s = 1.0;
+      for (int c = 0; c < T; ++c) {
+        double s = a[c][c];
+        if (!(s > 0.0) || !isfinite(s)) {
+          ok = false;
+          s = 1.0;
+        }
+        const double l = sqrt(s), inv = 1.0 / l;
+        prod *= l;
+        a[c][c] = l;
+#pragma unroll
+        for (int r = c + 1; r < T; ++r) a[r][c] *= inv;
+#pragma unroll
+        for (int c2 = c + 1; c2 < T; ++c2)
+#pragma unroll
+          for (int r = c2; r < T; ++r) a[r][c2] = fma(-a[r][c], a[c2][c], a[r][c2]);
       }
-      const double l = sqrt(s);
-      piv = l;
-      ld += log(l);
+      if (!ok) bad = 1;
+      ld += log(prod);
+#pragma unroll
+      for (int c = 0; c < T; ++c)
+#pragma unroll
+        for (int r = 0; r < T; ++r) dg[c][r] = r >= c ? a[r][c] : 0.0;
     }
     __syncthreads();
-    // column j below the pivot: scaled by 1 / L_jj, kept and published
-    if (owner && TC == jt && TR >= jt) {
-      const double inv = 1.0 / piv;
+    // the tiles below it: A_ij L_jj^-T, row by row forward substitution
+    if (owner && TC == jt && TR > jt) {
+      double L[T][T];
 #pragma unroll
-      for (int r = 0; r < T; ++r) {
-        const int i = T * TR + r;
-        double v = 0.0;
+      for (int c = 0; c < T; ++c)
 #pragma unroll
-        for (int c = 0; c < T; ++c) v = c == jr ? a[r][c] : v;
-        v *= inv;
+        for (int r = c; r < T; ++r) L[r][c] = dg[c][r];
+      double inv[T];
 #pragma unroll
-        for (int c = 0; c < T; ++c)
-          if (c == jr && i > j) a[r][c] = v;
-        if (i > j) col[i] = v;
-      }
-    }
-    __syncthreads();
-    // trailing update of the tile: a_ik -= L_ij L_kj for j < k <= i
-    if (owner && TC >= jt) {
-      double ci[T], ck[T];
-#pragma unroll
-      for (int r = 0; r < T; ++r) ci[r] = col[T * TR + r];
-#pragma unroll
-      for (int c = 0; c < T; ++c) ck[c] = col[T * TC + c];
+      for (int c = 0; c < T; ++c) inv[c] = 1.0 / L[c][c];
 #pragma unroll
       for (int r = 0; r < T; ++r)
 #pragma unroll
         for (int c = 0; c < T; ++c) {
-          const int i = T * TR + r, k = T * TC + c;
-          if (k > j && k <= i) a[r][c] = fma(-ci[r], ck[c], a[r][c]);
+          double v = a[r][c];
+#pragma unroll
+          for (int c2 = 0; c2 < c; ++c2) v = fma(-a[r][c2], L[c][c2], v);
+          a[r][c] = v * inv[c];
         }
+#pragma unroll
+      for (int c = 0; c < T; ++c)
+#pragma unroll
+        for (int r = 0; r < T; ++r) pan[c][T * TR + r] = a[r][c];
     }
-    // the next step's column writes wait for its first barrier: every thread
-    // has read this column by then
+    __syncthreads();
+    // the trailing tiles: A_ik -= L_i L_k^T over the panel's 8 columns
+    if (owner && TC > jt) {
+#pragma unroll
+      for (int c2 = 0; c2 < T; ++c2) {
+        double pr[T], pc[T];
+#pragma unroll
+        for (int r = 0; r < T; ++r) pr[r] = pan[c2][T * TR + r];
+#pragma unroll
+        for (int c = 0; c < T; ++c) pc[c] = pan[c2][T * TC + c];
+#pragma unroll
+        for (int r = 0; r < T; ++r)
+#pragma unroll
+          for (int c = 0; c < T; ++c) a[r][c] = fma(-pr[r], pc[c], a[r][c]);
+      }
+    }
   }
   // log|Psi_n| = 2 sum log L_jj; log Gamma_d(nu_n / 2) - log Gamma_d(nu / 2)
   double lg = 0.0;
-  for (int i = tid; i < d; i += BLOCK) lg += lgamma_d(0.5 * nun - 0.5 * i) - lgamma_d(0.5 * prior.nu - 0.5 * i);
-  const double ldet = 2.0 * reduce_sum(ld, red);
-  lg = reduce_sum(lg, red);
+  for (int i = tid; i < d; i += CHOL_T) lg += lgamma_d(0.5 * nun - 0.5 * i) - lgamma_d(0.5 * prior.nu - 0.5 * i);
+  auto block_sum = [&](double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < CHOL_T / 64; ++w) t += red[w];
+    return t;
+  };
+  const double ldet = 2.0 * block_sum(ld);
+  lg = block_sum(lg);
   if (tid == 0) {
     if (bad) atomicOr(err, 4);
     out[it] = bound ? ldet
@@ -596,7 +634,7 @@ hipError_t launch_logml_gauss(int n_items, const LogmlItem* items, int d, NiwPri
   }
 #undef DPMM_LOGML_WAVE
   if (d <= 128) {
-    hipLaunchKernelGGL(k_logml_gauss_tile, dim3(n_items), dim3(BLOCK), 0, s, n_items, items, d, prior, logdet_psi,
+    hipLaunchKernelGGL(k_logml_gauss_tile, dim3(n_items), dim3(CHOL_T), 0, s, n_items, items, d, prior, logdet_psi,
                        counts, moments, out, err, list, list_count, list_base);
     return hipGetLastError();
   }
