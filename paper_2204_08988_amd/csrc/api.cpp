@@ -336,7 +336,8 @@ dpmm_status pack_params(dpmm_ctx* ctx) {
     DPMM_HIP(ctx, launch_pack_csr(K, ctx->d, ctx->cfg.k_max, ctx->d_packed, ctx->d_tcl, ctx->d_tsub, ctx->d_cw,
                                   ctx->stream), "sparse table pack kernel");
   if (ctx->d_whi)
-    DPMM_HIP(ctx, launch_pack_wfrag(K, ctx->d, ctx->cfg.k_max, ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->stream),
+    DPMM_HIP(ctx, launch_pack_wfrag(K, ctx->d, ctx->cfg.k_max, ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->d_wbias,
+                                    ctx->stream),
              "fragment pack kernel");
   ctx->have_params = true;
   return DPMM_OK;
@@ -484,6 +485,7 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
       ok = ok && chk(c->alloc(&c->d_nflag, 2));
       // low parts: the bf16x3 form, and the candidate pass of either matrix-core form
       ok = ok && chk(c->alloc(&c->d_wlo, (size_t)km * d * d));
+      if (wbias_floats(d, km)) ok = ok && chk(c->alloc(&c->d_wbias, wbias_floats(d, km)));
     }
     // counting sort by cluster: the label path for d >= 5, the statistics of
     // any d once K outgrows the small-d kernel's LDS accumulators
@@ -794,7 +796,8 @@ dpmm_status label_phase(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int
     DPMM_TRY(ensure_perm(ctx, n));
     if (ctx->d_whi) {
       DPMM_HIP(ctx, launch_label_gauss_mfma(ctx->d, ctx->cfg.precision == DPMM_BF16X3, (const float*)x, n, *G, *per,
-                                            ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->K, t, ctx->cfg.seed, z,
+                                            ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->d_wbias, ctx->K,
+                                            ctx->cfg.k_max, t, ctx->cfg.seed, z,
                                             ctx->d_hist, ctx->d_tot, ctx->d_perm, ctx->d_cand, ctx->d_nflag,
                                             ctx->stream, ctx->label_timing ? ctx->ev[7] : nullptr,
                                             ctx->label_timing ? ctx->ev[8] : nullptr),
@@ -862,7 +865,8 @@ dpmm_status dpmm_sample_params(dpmm_ctx* ctx, uint32_t t) {
                                   ctx->d_scratch, ctx->d_packed, ctx->d_logdet, ctx->d_err, ctx->stream),
              "posterior draw kernel");
     if (ctx->d_whi)
-      DPMM_HIP(ctx, launch_pack_wfrag(K, ctx->d, ctx->cfg.k_max, ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->stream),
+      DPMM_HIP(ctx, launch_pack_wfrag(K, ctx->d, ctx->cfg.k_max, ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->d_wbias,
+                                    ctx->stream),
                "fragment pack kernel");
     ctx->have_params = true;
     return DPMM_OK;

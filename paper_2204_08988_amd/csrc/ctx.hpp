@@ -87,6 +87,8 @@ struct dpmm_ctx {
   bool labels_gave_stats = false;
   // BF16 whitener fragments of the cluster components (precision != FP32)
   uint16_t *d_whi = nullptr, *d_wlo = nullptr;
+  // offsets, constants and the common centre of the uncentred BF16 main pass (d = 64, 128)
+  float* d_wbias = nullptr;
   int* d_nflag = nullptr;  // count of the points deferred to FP32 (matrix-core label kernels)
   int* d_cand = nullptr;   // [perm_cap][RESCORE_CAND] their candidate clusters
   hipEvent_t ev[9] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};

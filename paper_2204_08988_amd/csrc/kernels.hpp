@@ -126,14 +126,19 @@ hipError_t launch_partition_stats(int d, const float* x, long long npts, const i
                                   long long* counts, double* moments, const int* cspan, double* part, hipStream_t s);
 // BF16 matrix-core cluster draw (d in {32, 64}) and its whitener fragments
 bool mfma_supported(int d);
-hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void* whi, void* wlo, hipStream_t s);
+// wbias (d = 64, 128; may be null): [k_max][d] offsets beta = -W (mu - c) in the
+// accumulator layout, [k_max][4] constants, [d] the common centre c, for the
+// uncentred BF16 main pass; wbias_floats(d, k_max) floats (0 for other d)
+size_t wbias_floats(int d, int k_max);
+hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void* whi, void* wlo, float* wbias,
+                             hipStream_t s);
 // flagged: int[n] (the points whose draw is deferred to FP32); cand:
 // int[n][RESCORE_CAND], each deferred point's candidate clusters (-1: empty
 // slot, -2 in slot 0: all clusters); n_flagged: one device int
 hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, int G, long long per_block,
-                                   const float* packed, const void* whi, const void* wlo, int K, uint32_t t,
-                                   uint64_t seed, int* z, int* hist, int* tot, int* flagged, int* cand,
-                                   int* n_flagged, hipStream_t s, hipEvent_t ev_main0 = nullptr,
+                                   const float* packed, const void* whi, const void* wlo, const float* wbias, int K,
+                                   int k_max, uint32_t t, uint64_t seed, int* z, int* hist, int* tot, int* flagged,
+                                   int* cand, int* n_flagged, hipStream_t s, hipEvent_t ev_main0 = nullptr,
                                    hipEvent_t ev_main1 = nullptr);
 hipError_t launch_loglik_gauss(int d, const float* x, long long n, const float* packed, int K, int k_max,
                                float* out, hipStream_t s);

@@ -12,6 +12,12 @@
 // BF16X3 adds the two cross terms of the hi/lo split, W_hi dx_lo + W_lo dx_hi,
 // for about 16 mantissa bits.
 //
+// The BF16 main pass at d = 64, 128 (k_label_gauss_mfma_uc) centres the points
+// once on a centre common to all clusters and starts each cluster's
+// accumulators at W_k (c - mu_k), so that the rows are rounded to BF16 once per
+// step instead of once per cluster; each of its scores carries an interval
+// that bounds the BF16 and FP32 rounding errors.
+//
 // Precision guard: if the runner-up is within the Gumbel range of the leader,
 // widened by an allowance for the BF16 rounding of both scores, the point is
 // deferred to k_rescore_flagged, which re-scores it in FP32 on the vector ALUs
@@ -112,8 +118,11 @@ struct Top2U {
     k1 = 0;
   }
   __device__ __forceinline__ void push(float l, float q, float rel, int kk) {
-    lo_max = fmaxf(lo_max, fmaf(-rel, q, l));
-    const float u = fmaf(rel, q, l);
+    push_bounds(fmaf(-rel, q, l), fmaf(rel, q, l), kk);
+  }
+  // a score known to lie in [lo, u]
+  __device__ __forceinline__ void push_bounds(float lo, float u, int kk) {
+    lo_max = fmaxf(lo_max, lo);
     const bool gt1 = u > u1, gt2 = u > u2;
     u2 = gt1 ? u1 : (gt2 ? u : u2);
     u1 = gt1 ? u : u1;
@@ -359,7 +368,7 @@ struct TriTiles {
 constexpr int BLOCK_W32 = 512;  // threads of k_label_gauss_mfma_w32: 8 waves of 32 points
 
 // d = 64, 128 in bf16x3, and the candidate pass of either form (the BF16
-// main pass is k_label_gauss_mfma_cs below): a cluster's non-zero whitener
+// main pass is k_label_gauss_mfma_uc below): a cluster's non-zero whitener
 // tiles (only those on or below
 // the diagonal), its mean and its constant are copied from global memory
 // straight into LDS (global_load_lds, no registers) into one of two
@@ -553,7 +562,7 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
   }
 }
 
-constexpr int BLOCK_CS = 512;  // threads of k_label_gauss_mfma_cs: 8 waves, two per SIMD
+constexpr int BLOCK_CS = 512;  // threads of k_label_gauss_mfma_uc: 8 waves, two per SIMD
 constexpr int CS_PTS = 256;    // points per workgroup step: 8 tiles of 32
 
 // Two partial top-2 states over disjoint cluster sets combined: the same state
@@ -568,121 +577,144 @@ __device__ __forceinline__ void top2_merge(Top2U& a, float u1, float u2, float l
   a.lo_max = fmaxf(a.lo_max, lo);
 }
 
-// Main pass for d = 64, 128 in BF16, cluster-stationary: the workgroup's 256
-// rows are copied once per step into LDS (rows padded by four floats, so the
-// sixteen-byte reads of 32 rows fall on distinct banks), and each of the eight
-// waves takes every eighth cluster, holding that cluster's whitener fragments
-// (its non-zero tiles only), its mean half and its constant in registers while
-// it sweeps the eight 32-point tiles.  The whitener then crosses LDS not at
-// all and the rows once per tile and cluster: 16 KB per tile and cluster at
-// d = 128, against 36 KB for k_label_gauss_mfma_w32, whose per-tile fragment
-// reads alone would take the LDS's whole bandwidth at the matrix cores' rate.
-// Within a step the waves never wait for each other, so the two waves of a
-// SIMD drift apart and one's matrix-core tiles overlap the other's centring
-// and norms.  Each lane keeps the partial top-2 of the points of its half's
-// tiles (tiles 2j + half, point 32 t + lane % 32) over its wave's clusters;
-// the eight partial states are merged through LDS at the end of the step.
-// The scores equal those of k_label_gauss_mfma_w32 bit for bit (the same BF16
-// operands, MFMA order and FP32 sums) and so do the merged states, so the
-// labels and the deferred points are the same.
+
+// Bounds on the score of the uncentred form below.  l = c_k - q / 2 is the
+// score of the FP32 record (W, mu, c_k), q = ||y||^2, y = W (x - mu).  With
+// x' = x - c (c a centre common to all clusters) and beta = -W (mu - c),
+// y = W x' + beta; the matrix cores form Y = bf16(W) bf16(x') + beta with exact
+// products and FP32 sums.  Each rounding to BF16 is within 2^-8 relative, so
+//   |Y_j - y_j| <= g sum_i |W_ji| |x'_i| + g2 sum_i |W_ji| (|x'_i| + |mu_i - c_i|)
+// with g = 2^-7 (plus a margin) for the two BF16 roundings and g2 = 2^-14 for
+// the FP32 sums and roundings of both this form and the FP32 draw it stands
+// for ((3d + 5) 2^-24 at most, d <= 128).  By Cauchy-Schwarz
+//   E = ||Y - y|| <= (g + g2) ||W||_F ||x'|| + g2 ||W||_F ||mu - c||.
+// The computed s = sqrt(q_bf16) is within 2^-16 s of ||Y||, so with
+// E' = E + 2^-16 s the exact q lies in [max(0, s - E')^2, (s + E')^2]: the
+// score lies in [c_k - (s + E')^2 / 2, c_k - max(0, s - E')^2 / 2].
+constexpr float UC_GAMMA = 1.02f / 128.0f;
+constexpr float UC_GAMMA2 = 1.0f / 16384.0f;
+constexpr float UC_EPSS = 1.0f / 65536.0f;
+
+// Main pass for d = 64, 128 in BF16, cluster-stationary and uncentred: the
+// workgroup's 256 rows are centred once per step on the common centre c,
+// rounded to BF16 and stored in LDS (rows padded by 16 bytes, so that the
+// sixteen-byte reads of 32 rows fall on distinct banks), with each row's norm
+// ||x'||.  Each of the eight waves takes every eighth cluster and holds its
+// whitener fragments (non-zero tiles only) and its offset beta = -W (mu - c),
+// in the accumulator layout, in registers while it sweeps the eight 32-point
+// tiles: a row block's accumulators start at beta (the matrix cores add it),
+// so a tile costs its MFMAs, its B operands read from LDS and the squared
+// norms, and none of the per-cluster centring and rounding of the rows.  Each
+// score comes with its own interval (above) in place of the allowance of the
+// centred kernels: a point is drawn here only if a single cluster can win the
+// FP32 draw, so the labels are those of the FP32 draw.
+// The partial top-2 states of the waves are merged through LDS at the end of
+// the step (top2_merge).
 template <int D>
-__global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_cs(const float* __restrict__ x, long long n,
+__global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float* __restrict__ x, long long n,
                                                                      long long per_block,
-                                                                     const float* __restrict__ packed,
-                                                                     const bf16x8* __restrict__ whi, int K,
+                                                                     const bf16x8* __restrict__ whi,
+                                                                     const float* __restrict__ wbias, int K, int k_max,
                                                                      int* __restrict__ z, int* __restrict__ hist,
                                                                      int* __restrict__ tot, int* __restrict__ flagged,
                                                                      int* __restrict__ n_flagged) {
   using TT = TriTiles<D>;
-  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
   constexpr int MT = TT::MT, KS = TT::KS, NF = MT * KS * 64, NT = TT::NT;
-  constexpr int XS = D + 4;             // LDS row stride in floats
+  constexpr int RB = D / 8 + 1;  // LDS row stride in 16-byte units
   constexpr int TILES = CS_PTS / 32;
-  constexpr int PARTS = D / 64;         // 64-float pieces of a row (one wave copy each)
   constexpr int NW = BLOCK_CS / 64;
-  constexpr float REL = BF16_TOL_REL;
-  static_assert(CS_PTS == BLOCK && D % 64 == 0 && NW * CS_PTS * 4 <= CS_PTS * XS, "step, row copies, states");
+  constexpr int P4 = D / 4;       // float4 pieces of a row
+  constexpr int RPI = 64 / P4;    // rows per wave and staging pass
+  constexpr int ITER = 32 / RPI;  // staging passes for the wave's 32 rows
+  static_assert(CS_PTS == BLOCK && D % 64 == 0 && NW * 32 == CS_PTS, "step, row copies");
+  static_assert(NW * CS_PTS * 4 * sizeof(float) <= CS_PTS * RB * 16, "partial states alias the rows");
+  typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
   extern __shared__ __align__(16) unsigned char smem[];
-  float* xs = reinterpret_cast<float*>(smem);              // [CS_PTS][XS] rows, then the partial states
-  int* h = reinterpret_cast<int*>(xs + CS_PTS * XS);       // [K] counters
+  bf16x8* xb = reinterpret_cast<bf16x8*>(smem);                 // [CS_PTS][RB] centred BF16 rows
+  float* rxs = reinterpret_cast<float*>(smem + CS_PTS * RB * 16);  // [CS_PTS] ||x'||
+  int* h = reinterpret_cast<int*>(rxs + CS_PTS);                  // [K] counters
+  const float4* cst = reinterpret_cast<const float4*>(wbias + (size_t)k_max * D);  // (c_k, (g + g2) ||W||_F, g2 ||W||_F ||mu - c||, 0)
+  const float* centre = wbias + (size_t)k_max * (D + 4);
   for (int k = threadIdx.x; k < K; k += BLOCK_CS) h[k] = 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int half = lane >> 5, col = lane & 31;
+  const int sub = lane / P4, part = lane % P4;
+  const float4 c4 = *reinterpret_cast<const float4*>(centre + 4 * part);
   const long long begin = (long long)blockIdx.x * per_block;
   const long long end = begin + per_block < n ? begin + per_block : n;
   for (long long chunk = begin; chunk < end; chunk += CS_PTS) {
     const int rows = end - chunk < CS_PTS ? (int)(end - chunk) : CS_PTS;
-    __syncthreads();  // the previous step's merge is done with xs
-    // rows past the end copy row `chunk` (their scores are never used)
-    for (int e = wave; e < CS_PTS * PARTS; e += NW) {
-      const int r = e / PARTS, part = e - r * PARTS;
-      const float* src = x + (chunk + (r < rows ? r : 0)) * D + part * 64 + lane;
-      __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(xs + r * XS + part * 64), 4, 0, 0);
+    __syncthreads();  // the previous step's merge is done with the rows' space
+    // the wave's 32 rows: x' = x - c rounded to BF16, and ||x'|| (rows past the end are zero)
+    {
+      float4 v[ITER];
+#pragma unroll
+      for (int it = 0; it < ITER; ++it) {
+        const int r = wave * 32 + it * RPI + sub;
+        v[it] = r < rows ? *reinterpret_cast<const float4*>(x + (chunk + r) * D + 4 * part) : c4;
+      }
+      float ss[ITER];
+#pragma unroll
+      for (int it = 0; it < ITER; ++it) {
+        const int r = wave * 32 + it * RPI + sub;
+        const float d0 = v[it].x - c4.x, d1 = v[it].y - c4.y, d2 = v[it].z - c4.z, d3 = v[it].w - c4.w;
+        ss[it] = fmaf(d3, d3, fmaf(d2, d2, fmaf(d1, d1, d0 * d0)));
+        bf16x4 b4;
+        b4[0] = (__bf16)d0;
+        b4[1] = (__bf16)d1;
+        b4[2] = (__bf16)d2;
+        b4[3] = (__bf16)d3;
+        reinterpret_cast<bf16x4*>(xb + r * RB)[part] = b4;
+      }
+#pragma unroll
+      for (int o = P4 / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) ss[it] += __shfl_xor(ss[it], o);
+      if (part == 0)
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) rxs[wave * 32 + it * RPI + sub] = __builtin_amdgcn_sqrtf(ss[it]);
     }
-    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    float rxv[TILES];
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) rxv[t] = rxs[t * 32 + col];
     Top2U st[TILES / 2];
 #pragma unroll
     for (int j = 0; j < TILES / 2; ++j) st[j].init();
-    // cluster k's non-zero fragment tiles [f0, f1), this lane's mean half, its constant
-    bf16x8 a[NT];
-    float mu[KS][8];
-    float ck = 0.0f;
-    auto load_frags = [&](int k, int f0, int f1) {
+    for (int k = wave; k < K; k += NW) {
+      const int ku = __builtin_amdgcn_readfirstlane(k);
+      bf16x8 a[NT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int ks = 0; ks < TT::tiles(mt); ++ks)
-          if (TT::off(mt) + ks >= f0 && TT::off(mt) + ks < f1)
-            a[TT::off(mt) + ks] = whi[(size_t)k * NF + (size_t)(mt * KS + ks) * 64 + lane];
-    };
-    auto load_mu = [&](int k) {
-      const float* rec = packed + (size_t)k * S;
+          a[TT::off(mt) + ks] = whi[(size_t)ku * NF + (size_t)(mt * KS + ks) * 64 + lane];
+      // beta in the accumulator layout: element r of row block mt is output row
+      // 32 mt + 8 (r / 4) + 4 half + r % 4
+      f32x16 bs[MT];
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const float4 u0 = *reinterpret_cast<const float4*>(rec + 4 + 16 * ks + 8 * half);
-        const float4 u1 = *reinterpret_cast<const float4*>(rec + 4 + 16 * ks + 8 * half + 4);
-        mu[ks][0] = u0.x;
-        mu[ks][1] = u0.y;
-        mu[ks][2] = u0.z;
-        mu[ks][3] = u0.w;
-        mu[ks][4] = u1.x;
-        mu[ks][5] = u1.y;
-        mu[ks][6] = u1.z;
-        mu[ks][7] = u1.w;
+      for (int mt = 0; mt < MT; ++mt) {
+        const float4* bp = reinterpret_cast<const float4*>(wbias + ((size_t)ku * MT + mt) * 32 + half * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 u = bp[q];
+          bs[mt][4 * q] = u.x;
+          bs[mt][4 * q + 1] = u.y;
+          bs[mt][4 * q + 2] = u.z;
+          bs[mt][4 * q + 3] = u.w;
+        }
       }
-    };
-    for (int k = wave; k < K; k += NW) {
-      load_frags(k, 0, NT);
-      load_mu(k);
-      ck = packed[(size_t)k * S];
+      const float4 kc = cst[ku];
 #pragma unroll
       for (int t = 0; t < TILES; ++t) {
-        // tile t's B operand, k-slice by k-slice just before the row block that
-        // first needs it (this lane's half of row 32 t + col, centred and
-        // rounded), so that each slice's centring overlaps the previous row
-        // block's matrix-core tiles; the wave's priority is raised while it
-        // issues them.
-        const float* xr = xs + (t * 32 + col) * XS + 8 * half;
+        const bf16x8* xr = xb + (t * 32 + col) * RB + half;
         bf16x8 b[KS];
-        auto center = [&](int ks) {
-          const float4 v0 = *reinterpret_cast<const float4*>(xr + 16 * ks);
-          const float4 v1 = *reinterpret_cast<const float4*>(xr + 16 * ks + 4);
-          b[ks][0] = (__bf16)(v0.x - mu[ks][0]);
-          b[ks][1] = (__bf16)(v0.y - mu[ks][1]);
-          b[ks][2] = (__bf16)(v0.z - mu[ks][2]);
-          b[ks][3] = (__bf16)(v0.w - mu[ks][3]);
-          b[ks][4] = (__bf16)(v1.x - mu[ks][4]);
-          b[ks][5] = (__bf16)(v1.y - mu[ks][5]);
-          b[ks][6] = (__bf16)(v1.z - mu[ks][6]);
-          b[ks][7] = (__bf16)(v1.w - mu[ks][7]);
-        };
         float q0 = 0.0f, q1 = 0.0f;
         f32x16 acc;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
-          for (int ks = (mt == 0 ? 0 : TT::tiles(mt - 1)); ks < TT::tiles(mt); ++ks) center(ks);
+          for (int ks = (mt == 0 ? 0 : TT::tiles(mt - 1)); ks < TT::tiles(mt); ++ks) b[ks] = xr[2 * ks];
           if (mt > 0) {
 #pragma unroll
             for (int e = 0; e < 16; e += 2) {
@@ -690,7 +722,7 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_cs(const float
               q1 = fmaf(acc[e + 1], acc[e + 1], q1);
             }
           }
-          acc = f32x16{0};
+          acc = bs[mt];
           __builtin_amdgcn_s_setprio(1);
 #pragma unroll
           for (int ks = 0; ks < TT::tiles(mt); ++ks)
@@ -702,29 +734,29 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_cs(const float
           q0 = fmaf(acc[e], acc[e], q0);
           q1 = fmaf(acc[e + 1], acc[e + 1], q1);
         }
-        // the two coordinate halves of the point: lanes l and l + 32 swap their
-        // sums (v_permlane32_swap: no LDS round trip) and add them
         float qm = q0 + q1;
         {
           const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(qm), __float_as_uint(qm), false, false);
           qm = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
         }
-        const float l = fmaf(-0.5f, qm, ck);
-        // the owning half's state, updated without a branch
+        const float sq = __builtin_amdgcn_sqrtf(qm);
+        const float e = fmaf(UC_EPSS, sq, fmaf(kc.y, rxv[t], kc.z));
+        const float sp = sq + e, sm = sq - e;
+        const float lo = fmaf(-0.5f * sp, sp, kc.x);
+        const float up = sm > 0.0f ? fmaf(-0.5f * sm, sm, kc.x) : kc.x;
         Top2U& sj = st[t >> 1];
         Top2U nx = sj;
-        nx.push(l, qm, REL, k);
+        nx.push_bounds(lo, up, k);
         const bool own = (t & 1) == half;
         sj.u1 = own ? nx.u1 : sj.u1;
         sj.u2 = own ? nx.u2 : sj.u2;
         sj.lo_max = own ? nx.lo_max : sj.lo_max;
         sj.k1 = own ? nx.k1 : sj.k1;
-        __builtin_amdgcn_sched_barrier(0);  // one tile at a time: no hoisting of the next tile's operands
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     __syncthreads();  // every wave is done with the rows
-    // partial states [wave][point]: u1, u2, lo_max, k1
-    float* ps = xs;
+    float* ps = reinterpret_cast<float*>(smem);  // partial states [wave][point]: u1, u2, lo_max, k1
 #pragma unroll
     for (int j = 0; j < TILES / 2; ++j) {
       const int p = (2 * j + half) * 32 + col;
@@ -753,7 +785,9 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_cs(const float
   }
 }
 
-size_t label_cs_lds(int d, int K) { return ((size_t)CS_PTS * (d + 4)) * sizeof(float) + (size_t)K * sizeof(int); }
+size_t label_uc_lds(int d, int K) {
+  return (size_t)CS_PTS * (d / 8 + 1) * 16 + (size_t)CS_PTS * sizeof(float) + (size_t)K * sizeof(int);
+}
 
 constexpr int RS_BLOCK = 256;
 
@@ -891,19 +925,96 @@ __global__ void k_pack_wfrag(int K, int d, int k_max, const float* __restrict__ 
   }
 }
 
+// The common centre of the uncentred main pass: the mean of the K cluster
+// means (any centre keeps the draw exact; one near the data keeps ||x'|| and
+// so the error bounds small).
+__global__ void k_pack_centre(int K, int d, const float* __restrict__ packed, float* __restrict__ centre) {
+  const int S = gauss_rec_stride(d);
+  for (int j = threadIdx.x; j < d; j += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) s += (double)packed[(size_t)k * S + 4 + j];
+    centre[j] = (float)(s / K);
+  }
+}
+
+// Cluster k's offset beta = -W (mu - c) in the accumulator layout of
+// k_label_gauss_mfma_uc ([k][row block][lane half][16]) and its constants
+// (c_k, (g + g2) ||W||_F, g2 ||W||_F ||mu - c||, 0), rounded up; float64 sums
+// of the record's float32 values.  One thread per output row.
+template <int D>
+__global__ __launch_bounds__(D) void k_pack_bias(int K, int k_max, const float* __restrict__ packed,
+                                                 float* __restrict__ wbias) {
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  constexpr int MT = D / 32, NWV = D / 64;
+  __shared__ double dm[D], red[2][NWV];
+  const int k = blockIdx.x, j = threadIdx.x;
+  if (k >= K) return;
+  const float* rec = packed + (size_t)k * S;
+  const float* centre = wbias + (size_t)k_max * (D + 4);
+  dm[j] = (double)rec[4 + j] - (double)centre[j];
+  __syncthreads();
+  const float* w = rec + 4 + D + j * (j + 1) / 2;
+  double b = 0.0, wn = 0.0;
+  for (int i = 0; i <= j; ++i) {
+    const double wji = (double)w[i];
+    b = fma(wji, dm[i], b);
+    wn = fma(wji, wji, wn);
+  }
+  const int mt = j >> 5, jj = j & 31;
+  const int hh = (jj >> 2) & 1, r = ((jj >> 3) << 2) | (jj & 3);
+  wbias[((size_t)k * MT + mt) * 32 + hh * 16 + r] = (float)(-b);
+  double m2 = dm[j] * dm[j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    wn += __shfl_xor(wn, o);
+    m2 += __shfl_xor(m2, o);
+  }
+  if ((j & 63) == 0) {
+    red[0][j >> 6] = wn;
+    red[1][j >> 6] = m2;
+  }
+  __syncthreads();
+  if (j == 0) {
+    double wf = 0.0, mm = 0.0;
+    for (int v = 0; v < NWV; ++v) {
+      wf += red[0][v];
+      mm += red[1][v];
+    }
+    const double f = sqrt(wf) * (1.0 + 1e-6);
+    float4 c;
+    c.x = rec[0];
+    c.y = (float)(((double)UC_GAMMA + (double)UC_GAMMA2) * f);
+    c.z = (float)((double)UC_GAMMA2 * f * sqrt(mm) * (1.0 + 1e-6));
+    c.w = 0.0f;
+    reinterpret_cast<float4*>(wbias + (size_t)k_max * D)[k] = c;
+  }
+}
+
 }  // namespace
+
+size_t wbias_floats(int d, int k_max) { return (d == 64 || d == 128) ? (size_t)k_max * (d + 4) + d : 0; }
 
 bool mfma_supported(int d) { return d == 32 || d == 64 || d == 128; }
 
-hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void* whi, void* wlo, hipStream_t s) {
+hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void* whi, void* wlo, float* wbias,
+                             hipStream_t s) {
+  if (K <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_pack_wfrag, dim3(K), dim3(256), 0, s, K, d, k_max, packed, (__bf16*)whi, (__bf16*)wlo);
+  if (wbias && (d == 64 || d == 128)) {
+    hipLaunchKernelGGL(k_pack_centre, dim3(1), dim3(128), 0, s, K, d, packed, wbias + (size_t)k_max * (d + 4));
+    if (d == 128)
+      hipLaunchKernelGGL(k_pack_bias<128>, dim3(K), dim3(128), 0, s, K, k_max, packed, wbias);
+    else
+      hipLaunchKernelGGL(k_pack_bias<64>, dim3(K), dim3(64), 0, s, K, k_max, packed, wbias);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, int G, long long per_block,
-                                   const float* packed, const void* whi, const void* wlo, int K, uint32_t t,
-                                   uint64_t seed, int* z, int* hist, int* tot, int* flagged, int* cand,
-                                   int* n_flagged, hipStream_t s, hipEvent_t ev_main0, hipEvent_t ev_main1) {
+                                   const float* packed, const void* whi, const void* wlo, const float* wbias, int K,
+                                   int k_max, uint32_t t, uint64_t seed, int* z, int* hist, int* tot, int* flagged,
+                                   int* cand, int* n_flagged, hipStream_t s, hipEvent_t ev_main0,
+                                   hipEvent_t ev_main1) {
   if (n == 0) return hipSuccess;
   hipError_t e = launch_zero64(tot, (size_t)(K + 1) / 2 + 1, s);
   if (e != hipSuccess) return e;
@@ -913,10 +1024,10 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
   e = launch_zero64(n_flagged, 1, s);
   if (e != hipSuccess) return e;
   static bool attr_set = false;
-  if (!attr_set) {  // d = 32 and the cluster-stationary kernels: more than 64 KB of dynamic LDS (160 KB per CU)
+  if (!attr_set) {  // d = 32 and the uncentred kernels: more than 64 KB of dynamic LDS (160 KB per CU)
     const void* fns[5] = {(const void*)k_label_gauss_mfma32<true, false>, (const void*)k_label_gauss_mfma32<false, false>,
-                          (const void*)k_label_gauss_mfma32<true, true>, (const void*)k_label_gauss_mfma_cs<128>,
-                          (const void*)k_label_gauss_mfma_cs<64>};
+                          (const void*)k_label_gauss_mfma32<true, true>, (const void*)k_label_gauss_mfma_uc<128>,
+                          (const void*)k_label_gauss_mfma_uc<64>};
     for (const void* f : fns) {
       e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       if (e != hipSuccess) return e;
@@ -931,15 +1042,15 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
     // optional events taken by the main pass's own dispatch (its start and end
     // time stamps, for timing it alone without extra queue packets)
     hipEvent_t e0 = cands ? nullptr : ev_main0, e1 = cands ? nullptr : ev_main1;
-    if ((d == 64 || d == 128) && !cands && !x3) {
-      // BF16 main pass, cluster-stationary: the rows in LDS, the whitener in registers
-      const size_t lcs = label_cs_lds(d, K);
+    if ((d == 64 || d == 128) && !cands && !x3 && wbias) {
+      // BF16 main pass, uncentred: the rows centred once on the common centre
+      const size_t luc = label_uc_lds(d, K);
       if (d == 128)
-        hipExtLaunchKernelGGL((k_label_gauss_mfma_cs<128>), dim3(Gp), dim3(BLOCK_CS), lcs, s, e0, e1, 0, x, n,
-                              per_block, packed, hi, K, z, hist, tot, flagged, n_flagged);
+        hipExtLaunchKernelGGL((k_label_gauss_mfma_uc<128>), dim3(Gp), dim3(BLOCK_CS), luc, s, e0, e1, 0, x, n,
+                              per_block, hi, wbias, K, k_max, z, hist, tot, flagged, n_flagged);
       else
-        hipExtLaunchKernelGGL((k_label_gauss_mfma_cs<64>), dim3(Gp), dim3(BLOCK_CS), lcs, s, e0, e1, 0, x, n,
-                              per_block, packed, hi, K, z, hist, tot, flagged, n_flagged);
+        hipExtLaunchKernelGGL((k_label_gauss_mfma_uc<64>), dim3(Gp), dim3(BLOCK_CS), luc, s, e0, e1, 0, x, n,
+                              per_block, hi, wbias, K, k_max, z, hist, tot, flagged, n_flagged);
     } else if (d == 64 || d == 128) {
       // static staging buffers; only the histogram is dynamic
 #define DPMM_MFMA_W32(DD, XX, CC)                                                                            \

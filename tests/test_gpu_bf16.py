@@ -145,6 +145,43 @@ def test_bf16_deferred_candidate_lists(precision, d, K, n, scale):
     S.close()
 
 
+@pytest.mark.parametrize("d,K,n,shift", [(64, 6, 4000, "common"), (128, 5, 2000, "common"),
+                                         (64, 6, 4000, "split"), (128, 6, 2000, "split")])
+def test_bf16_labels_far_from_origin(d, K, n, shift):
+    """The BF16 main pass at d = 64, 128 scores the rows centred on one common
+    centre (the mean of the cluster means) instead of on each cluster's mean,
+    with a per-score error bound that grows with ||x - c||.  Data offset by
+    1000 in every coordinate ("common"), or clusters in two groups 400 apart
+    ("split": the centre lies between them, far from every point), must still
+    meet the FP32 comparison rule."""
+    import torch
+    from paper_2204_08988_amd.sampler import Sampler
+    seed = 4300 + d + K
+    params = _wishart_params(K, d, seed, mean_scale=5.0)
+    off = np.zeros((K, 1, d))
+    if shift == "common":
+        off[:] = 1000.0
+    else:
+        off[: K // 2] = 200.0
+        off[K // 2:] = -200.0
+    params = sampler.Params(params.log_pi, params.log_pisub, mu=params.mu + off, sigma=params.sigma)
+    x = pu.gauss_points(params, n, seed + 1)
+    S = Sampler("gaussian", d, K + 2, 2.0, seed, m=np.zeros(d), psi=np.eye(d), precision="bf16")
+    S.set_params(params.log_pi, params.log_pisub, pu.comp_array(params))
+    xt = torch.from_numpy(x).cuda()
+    model = sampler.Model("gaussian", 2.0, niw.NIWPrior(1.0, np.zeros(d), d + 3, np.eye(d)), seed=seed)
+    lc, ls = sampler.loglik(model, x.astype(np.float64), params)
+    Mc, Ms = pu.gauss_scale(x, params)
+    for t in (2, 6):
+        z, zs = S.sample_labels(xt, t)
+        bad_c, bad_s, tie_c, tie_s = pu.label_mismatches(seed, t, z.cpu().numpy(), zs.cpu().numpy(), lc, ls, Mc, Ms)
+        assert bad_c.size == 0, (bad_c[:10], tie_c)
+        assert bad_s.size == 0, (bad_s[:10], tie_s)
+        counts = S.get_stats()[:, :, 0].sum(axis=1)
+        assert np.array_equal(counts, np.bincount(z.cpu().numpy(), minlength=K))
+    S.close()
+
+
 def test_bf16_chain_recovers_clusters():
     import torch
     from paper_2204_08988_amd import datagen
