@@ -102,9 +102,15 @@ dpmm_status ensure_perm(dpmm_ctx* ctx, int64_t n) {
     hipFree(ctx->d_perm);
     hipFree(ctx->d_zsort);
     hipFree(ctx->d_cand);
+    hipFree(ctx->d_sflag);
+    hipFree(ctx->d_perm_c);
+    hipFree(ctx->d_zrow_c);
     ctx->d_perm = nullptr;
     ctx->d_zsort = nullptr;
     ctx->d_cand = nullptr;
+    ctx->d_sflag = nullptr;
+    ctx->d_perm_c = nullptr;
+    ctx->d_zrow_c = nullptr;
     ctx->perm_cap = 0;
   }
   DPMM_HIP(ctx, hipMalloc(&ctx->d_perm, (size_t)n * sizeof(int)), "allocate permutation");
@@ -112,6 +118,11 @@ dpmm_status ensure_perm(dpmm_ctx* ctx, int64_t n) {
   // candidate lists of the points the matrix-core label kernels defer
   if (ctx->d_nflag)
     DPMM_HIP(ctx, hipMalloc(&ctx->d_cand, (size_t)n * RESCORE_CAND * sizeof(int)), "allocate candidate lists");
+  if (ctx->d_shi) {  // the bf16x3 sub-label pass: flags and the undecided rows' list
+    DPMM_HIP(ctx, hipMalloc(&ctx->d_sflag, (size_t)n), "allocate sub-label flags");
+    DPMM_HIP(ctx, hipMalloc(&ctx->d_perm_c, (size_t)n * sizeof(int)), "allocate sub-label list");
+    DPMM_HIP(ctx, hipMalloc(&ctx->d_zrow_c, (size_t)n * sizeof(int)), "allocate sub-label list");
+  }
   ctx->perm_cap = n;
   return ensure_part(ctx, n);
 }
@@ -140,9 +151,12 @@ dpmm_status sorted_pass_with(dpmm_ctx* ctx, const void* x, int64_t n, bool label
   DPMM_HIP(ctx, launch_sort_by_z(z, n, ctx->K, G, per_block, labels_done_hist, b.hist, b.tot, b.offs, b.perm, b.zsort,
                                  ctx->stream), "sort by cluster");
   if (ctx->timing) DPMM_HIP(ctx, hipEventRecord(ctx->ev[3], ctx->stream), "event");
+  // BF16 tables at d = 64, 128: the sub-labels in bf16x3 first, the FP32 kernel on the rows left
+  SubX3 x3{ctx->d_shi, ctx->d_slo, ctx->d_sflag, ctx->d_scnt, ctx->d_soffs, ctx->d_perm_c, ctx->d_zrow_c};
+  const bool use_x3 = sample && ctx->d_shi && ctx->d_sflag && b.perm == ctx->d_perm;
   DPMM_HIP(ctx, launch_sub_stats(ctx->d, sample, (const float*)x, n, b.perm, z, b.zsort, zsub, ctx->d_packed, ctx->K,
                                  ctx->cfg.k_max, t, ctx->cfg.seed, ctx->d_counts, ctx->d_moments, b.offs, b.tot, b.part,
-                                 ctx->stream),
+                                 ctx->stream, use_x3 ? &x3 : nullptr),
            "sub-label / statistics kernel");
   ctx->have_stats = true;
   return DPMM_OK;
@@ -337,7 +351,7 @@ dpmm_status pack_params(dpmm_ctx* ctx) {
                                   ctx->stream), "sparse table pack kernel");
   if (ctx->d_whi)
     DPMM_HIP(ctx, launch_pack_wfrag(K, ctx->d, ctx->cfg.k_max, ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->d_wbias,
-                                    ctx->stream),
+                                    ctx->d_shi, ctx->d_slo, ctx->stream),
              "fragment pack kernel");
   ctx->have_params = true;
   return DPMM_OK;
@@ -486,6 +500,12 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
       // low parts: the bf16x3 form, and the candidate pass of either matrix-core form
       ok = ok && chk(c->alloc(&c->d_wlo, (size_t)km * d * d));
       if (wbias_floats(d, km)) ok = ok && chk(c->alloc(&c->d_wbias, wbias_floats(d, km)));
+      if (d == 64 || d == 128) {
+        ok = ok && chk(c->alloc(&c->d_shi, (size_t)2 * km * d * d));
+        ok = ok && chk(c->alloc(&c->d_slo, (size_t)2 * km * d * d));
+        ok = ok && chk(c->alloc(&c->d_scnt, (size_t)SUBX_GROUPS));
+        ok = ok && chk(c->alloc(&c->d_soffs, (size_t)SUBX_GROUPS + 1));
+      }
     }
     // counting sort by cluster: the label path for d >= 5, the statistics of
     // any d once K outgrows the small-d kernel's LDS accumulators
@@ -563,6 +583,9 @@ void dpmm_destroy(dpmm_ctx* ctx) {
   if (ctx->d_zsort) hipFree(ctx->d_zsort);
   if (ctx->d_part) hipFree(ctx->d_part);
   if (ctx->d_cand) hipFree(ctx->d_cand);
+  if (ctx->d_sflag) hipFree(ctx->d_sflag);
+  if (ctx->d_perm_c) hipFree(ctx->d_perm_c);
+  if (ctx->d_zrow_c) hipFree(ctx->d_zrow_c);
   if (ctx->d_sel) hipFree(ctx->d_sel);
   if (ctx->d_side) hipFree(ctx->d_side);
   if (ctx->h_frame) hipHostFree(ctx->h_frame);
@@ -866,7 +889,7 @@ dpmm_status dpmm_sample_params(dpmm_ctx* ctx, uint32_t t) {
              "posterior draw kernel");
     if (ctx->d_whi)
       DPMM_HIP(ctx, launch_pack_wfrag(K, ctx->d, ctx->cfg.k_max, ctx->d_packed, ctx->d_whi, ctx->d_wlo, ctx->d_wbias,
-                                    ctx->stream),
+                                    ctx->d_shi, ctx->d_slo, ctx->stream),
                "fragment pack kernel");
     ctx->have_params = true;
     return DPMM_OK;

@@ -89,6 +89,13 @@ struct dpmm_ctx {
   uint16_t *d_whi = nullptr, *d_wlo = nullptr;
   // offsets, constants and the common centre of the uncentred BF16 main pass (d = 64, 128)
   float* d_wbias = nullptr;
+  // BF16 fragments of the sub-cluster whiteners and the buffers of the bf16x3
+  // sub-label pass (d = 64, 128): per-workgroup counts and offsets, and per
+  // sorted row (sized with the permutation) the undecided flags and list
+  uint16_t *d_shi = nullptr, *d_slo = nullptr;
+  int *d_scnt = nullptr, *d_soffs = nullptr;
+  unsigned char* d_sflag = nullptr;
+  int *d_perm_c = nullptr, *d_zrow_c = nullptr;
   int* d_nflag = nullptr;  // count of the points deferred to FP32 (matrix-core label kernels)
   int* d_cand = nullptr;   // [perm_cap][RESCORE_CAND] their candidate clusters
   hipEvent_t ev[9] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};

@@ -113,10 +113,12 @@ hipError_t launch_sort_by_z(const int* z, long long n, int K, int G, long long p
 constexpr int SUBW_WAVES = 2048;
 size_t sub_stats_part_doubles(int d, long long n);
 size_t sub_stats_part_doubles_max(int d);  // over every n
+struct SubX3;
+// x3 (may be null; d = 64, 128 with sample): the bf16x3 sub-label pass and its buffers
 hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, const int* perm, const int* z,
                             const int* zrow, unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t,
                             uint64_t seed, long long* counts, double* moments, const int* cstart, const int* ctot,
-                            double* part, hipStream_t s);
+                            double* part, hipStream_t s, const SubX3* x3 = nullptr);
 // statistics of a listed set of cluster k1's points split by side[i] into
 // segments slot, slot + 1 (slot >= 2 k1; d in {8, 16, 32, 64, 128});
 // cspan: device int[2] = {0, nsel}; part: sub_stats_part_doubles(d, nsel)
@@ -130,8 +132,25 @@ bool mfma_supported(int d);
 // accumulator layout, [k_max][4] constants, [d] the common centre c, for the
 // uncentred BF16 main pass; wbias_floats(d, k_max) floats (0 for other d)
 size_t wbias_floats(int d, int k_max);
+// shi, slo (may be null): the same fragment tables for the 2K sub-clusters
 hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void* whi, void* wlo, float* wbias,
-                             hipStream_t s);
+                             void* shi, void* slo, hipStream_t s);
+// bf16x3 sub-label pass over cluster-sorted rows (d = 64, 128) in front of the
+// FP32 one: the rows it cannot decide are listed, in sorted order, in
+// perm_c / zrow_c, their number in offs[SUBX_GROUPS]
+constexpr int SUBX_GROUPS = 1024;
+struct SubX3 {
+  const void* hi;       // [2 k_max][d / 32][d / 16][64][8] BF16 fragments of the sub-cluster whiteners
+  const void* lo;       // their low parts
+  unsigned char* flag;  // [n] per sorted row
+  int* cnt;             // [SUBX_GROUPS]
+  int* offs;            // [SUBX_GROUPS + 1]
+  int* perm_c;          // [n]
+  int* zrow_c;          // [n]
+};
+hipError_t launch_sub_labels_x3(int d, const float* x, long long n, const int* perm, const int* z, const int* zrow,
+                                unsigned char* zsub, const float* packed, int k_max, uint32_t t, uint64_t seed,
+                                const SubX3& b, hipStream_t s);
 // flagged: int[n] (the points whose draw is deferred to FP32); cand:
 // int[n][RESCORE_CAND], each deferred point's candidate clusters (-1: empty
 // slot, -2 in slot 0: all clusters); n_flagged: one device int

@@ -647,11 +647,16 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
     __syncthreads();  // the previous step's merge is done with the rows' space
     // the wave's 32 rows: x' = x - c rounded to BF16, and ||x'|| (rows past the end are zero)
     {
+      // the rows are read once: non-temporal loads, so that they do not evict
+      // the whitener tables from L2
+      typedef float f32x4 __attribute__((ext_vector_type(4)));
       float4 v[ITER];
 #pragma unroll
       for (int it = 0; it < ITER; ++it) {
         const int r = wave * 32 + it * RPI + sub;
-        v[it] = r < rows ? *reinterpret_cast<const float4*>(x + (chunk + r) * D + 4 * part) : c4;
+        const f32x4 u = r < rows ? __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(x + (chunk + r) * D + 4 * part))
+                                 : f32x4{c4.x, c4.y, c4.z, c4.w};
+        v[it] = make_float4(u.x, u.y, u.z, u.w);
       }
       float ss[ITER];
 #pragma unroll
@@ -905,14 +910,14 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rescore_flagged(const float* __res
   }
 }
 
-// Fragment table of cluster k's whitener: element (mt, ks, lane, q) =
+// Fragment table of record rec0 + k's whitener: element (mt, ks, lane, q) =
 // W[32 mt + lane % 32][16 ks + 8 (lane / 32) + q] (zero above the diagonal).
-__global__ void k_pack_wfrag(int K, int d, int k_max, const float* __restrict__ packed, __bf16* __restrict__ whi,
+__global__ void k_pack_wfrag(int K, int d, int rec0, const float* __restrict__ packed, __bf16* __restrict__ whi,
                              __bf16* __restrict__ wlo) {
   const int k = blockIdx.x;
   if (k >= K) return;
   const int S = gauss_rec_stride(d);
-  const float* w = packed + (size_t)k * S + 4 + d;
+  const float* w = packed + (size_t)(rec0 + k) * S + 4 + d;
   const int KS = d / 16;
   for (int idx = threadIdx.x; idx < d * d; idx += blockDim.x) {
     const int q = idx & 7, lane = (idx >> 3) & 63, f = idx >> 9;
@@ -922,6 +927,243 @@ __global__ void k_pack_wfrag(int K, int d, int k_max, const float* __restrict__ 
     const __bf16 hi = (__bf16)v;
     whi[(size_t)k * d * d + idx] = hi;
     if (wlo) wlo[(size_t)k * d * d + idx] = (__bf16)(v - (float)hi);
+  }
+}
+
+// Sub-label draw of cluster-sorted rows in bf16x3 on the BF16 matrix cores
+// (d = 64, 128), Sec. 4.1 step (f), in front of the FP32 kernel
+// k_sub_labels_mfma: the same scores (rows centred on sub-cluster 0's mean,
+// sub-cluster 1's accumulators started at W_1 (mu_0 - mu_1)) from the hi/lo
+// BF16 parts of W_h and of the centred rows, three products each (W_hi x_hi +
+// W_hi x_lo + W_lo x_hi), for about 16 mantissa bits at a sixteenth of the FP32
+// matrix cores' time.  The score difference delta = l_0 - l_1 then carries the
+// allowance rel (q_0 + q_1) + TOL_ABS of the bf16x3 form against the FP32 one;
+// a row is drawn here when the logistic draw gives the same sub-label at both
+// ends of that interval (the draw is monotone in delta), else it is flagged for
+// the FP32 kernel, which draws it as it draws every row in the FP32 form.
+// A workgroup of eight waves walks a contiguous range of sorted rows; the
+// hi/lo fragments of the current cluster's two sub-clusters (non-zero tiles)
+// are staged in LDS whenever the cluster changes; a wave scores 64 rows (two
+// 32-row tiles that share each fragment read), a lane holding the hi and lo
+// BF16 parts of half the coordinates of one row of each tile.
+constexpr int SUBX_BLOCK = 512;
+
+__device__ __forceinline__ int logistic_pick(float delta, float u) {
+  if (delta > LOGISTIC_MAX_F) return 0;
+  if (delta < -LOGISTIC_MAX_F) return 1;
+  return u > 1.0f / (1.0f + expf(delta)) ? 0 : 1;
+}
+
+template <int D>
+__global__ __launch_bounds__(SUBX_BLOCK, 1) void k_sub_labels_x3(
+    const float* __restrict__ x, long long n_sorted, long long per_block, const int* __restrict__ perm,
+    const int* __restrict__ z, const int* __restrict__ zrow, unsigned char* __restrict__ zsub,
+    const float* __restrict__ packed, const bf16x8* __restrict__ shi, const bf16x8* __restrict__ slo, int k_max,
+    uint32_t t, uint64_t seed, unsigned char* __restrict__ flag, int* __restrict__ cnt) {
+  using TT = TriTiles<D>;
+  constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
+  constexpr int MT = TT::MT, KS = TT::KS, NF = MT * KS * 64, NT = TT::NT;
+  constexpr int NFZ = NT * 64;  // staged fragments per sub-cluster and part
+  extern __shared__ __align__(16) unsigned char smem[];
+  bf16x8* s_fr = reinterpret_cast<bf16x8*>(smem);  // [sub][hi, lo][NFZ]
+  float* s_mu0 = reinterpret_cast<float*>(s_fr + 4 * NFZ);
+  float* s_dmu = s_mu0 + D;
+  float* s_corr = s_dmu + D;  // W_1 (mu_0 - mu_1)
+  float* s_c = s_corr + D;    // c_0, c_1
+  int* s_cnt = reinterpret_cast<int*>(s_c + 4);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, col = lane & 31;
+  if (threadIdx.x == 0) *s_cnt = 0;
+  const long long begin = (long long)blockIdx.x * per_block;
+  const long long end = begin + per_block < n_sorted ? begin + per_block : n_sorted;
+  auto kof = [&](long long g) { return __builtin_amdgcn_readfirstlane(zrow ? zrow[g] : z[perm[g]]); };
+  int staged = -1, nflag = 0;
+  for (long long chunk = begin; chunk < end; chunk += SUBX_BLOCK) {
+    const long long cend = chunk + SUBX_BLOCK < end ? chunk + SUBX_BLOCK : end;
+    const long long base = chunk + wave * 64;
+    const long long rA = base + col, rB = base + 32 + col;
+    const bool vA = rA < cend, vB = rB < cend;
+    const long long iA = vA ? perm[rA] : 0, iB = vB ? perm[rB] : 0;
+    const int kA = vA ? (zrow ? zrow[rA] : z[iA]) : -1, kB = vB ? (zrow ? zrow[rB] : z[iB]) : -1;
+    const int kmine = h ? kB : kA;
+    float delta = 0.0f, allow = 0.0f;
+    int cur = kof(chunk);
+    const int last = kof(cend - 1);
+    for (;;) {
+      if (cur != staged) {
+        __syncthreads();  // every wave is done with the previous tables
+        for (int f = threadIdx.x; f < 4 * NFZ; f += SUBX_BLOCK) {
+          const int part = f / NFZ, g = f - part * NFZ;  // part = 2 sub + (lo)
+          const int tt = g >> 6;
+          int mt = 0, o = 0;
+#pragma unroll
+          for (int m = 1; m < MT; ++m)
+            if (tt >= TT::off(m)) mt = m, o = TT::off(m);
+          const size_t src = (size_t)(2 * cur + (part >> 1)) * NF + (size_t)(mt * KS + tt - o) * 64 + (g & 63);
+          s_fr[f] = (part & 1) ? slo[src] : shi[src];
+        }
+        const float* r0 = packed + (size_t)(k_max + 2 * cur) * S;
+        const float* r1 = r0 + S;
+        if (threadIdx.x < D) {
+          s_mu0[threadIdx.x] = r0[4 + threadIdx.x];
+          s_dmu[threadIdx.x] = r0[4 + threadIdx.x] - r1[4 + threadIdx.x];
+        }
+        if (threadIdx.x == 0) {
+          s_c[0] = r0[0];
+          s_c[1] = r1[0];
+        }
+        __syncthreads();
+        if (threadIdx.x < D) {
+          const int i = threadIdx.x;
+          const float* w1 = r1 + 4 + D + i * (i + 1) / 2;
+          float c = 0.0f;
+          for (int k = 0; k <= i; ++k) c = fmaf(w1[k], s_dmu[k], c);
+          s_corr[i] = c;
+        }
+        __syncthreads();
+        staged = cur;
+      }
+      if (__ballot(kA == cur || kB == cur)) {
+        // this lane's half of rows A and B (k = 16 ks + 8 h + q), centred on mu_0, hi and lo parts
+        bf16x8 ah[KS], al[KS], bh[KS], bl[KS];
+        const float4* pa = reinterpret_cast<const float4*>(x + (size_t)iA * D + 8 * h);
+        const float4* pb = reinterpret_cast<const float4*>(x + (size_t)iB * D + 8 * h);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const float4 a0 = vA ? pa[4 * ks] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float4 a1 = vA ? pa[4 * ks + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float4 b0 = vB ? pb[4 * ks] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float4 b1 = vB ? pb[4 * ks + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float va[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+          const float vb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const float m = s_mu0[16 * ks + 8 * h + q];
+            const float da = va[q] - m, db = vb[q] - m;
+            ah[ks][q] = (__bf16)da;
+            al[ks][q] = (__bf16)(da - (float)ah[ks][q]);
+            bh[ks][q] = (__bf16)db;
+            bl[ks][q] = (__bf16)(db - (float)bh[ks][q]);
+          }
+        }
+        float sc[2], qq[2];
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+          const bf16x8* fh = s_fr + (2 * sub) * NFZ;
+          const bf16x8* fl = fh + NFZ;
+          float qa = 0.0f, qb = 0.0f;
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            f32x16 acca, accb;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const float c0 = sub ? s_corr[32 * mt + 8 * (r >> 2) + 4 * h + (r & 3)] : 0.0f;
+              acca[r] = c0;
+              accb[r] = c0;
+            }
+#pragma unroll
+            for (int ks = 0; ks < TT::tiles(mt); ++ks) {
+              const int tile = TT::off(mt) + ks;
+              const bf16x8 wh = fh[tile * 64 + lane], wl = fl[tile * 64 + lane];
+              acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, ah[ks], acca, 0, 0, 0);
+              accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, bh[ks], accb, 0, 0, 0);
+              acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, al[ks], acca, 0, 0, 0);
+              accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, bl[ks], accb, 0, 0, 0);
+              acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, ah[ks], acca, 0, 0, 0);
+              accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, bh[ks], accb, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              qa = fmaf(acca[r], acca[r], qa);
+              qb = fmaf(accb[r], accb[r], qb);
+            }
+          }
+          qa += __shfl_xor(qa, 32);
+          qb += __shfl_xor(qb, 32);
+          qq[sub] = h ? qb : qa;
+          sc[sub] = fmaf(-0.5f, qq[sub], s_c[sub]);
+        }
+        if (kmine == cur) {
+          delta = sc[0] - sc[1];
+          allow = fmaf(BF16X3_TOL_REL, qq[0] + qq[1], TOL_ABS);
+        }
+      }
+      if (cur == last) break;
+      long long lo = chunk, hi = cend - 1;
+      while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if (kof(mid) > cur)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      cur = kof(lo);
+    }
+    const long long rme = base + lane;
+    if (rme < cend) {
+      const int i = (int)(h ? iB : iA);
+      const float u = uniform_f(rng_block(seed, t, (uint32_t)i, TAG_LOGISTIC, 0).x);
+      const int s0 = logistic_pick(delta - allow, u), s1 = logistic_pick(delta + allow, u);
+      if (s0 == s1) zsub[i] = (unsigned char)s0;
+      flag[rme] = s0 != s1;
+      nflag += s0 != s1;
+    }
+  }
+  // the workgroup's count of flagged rows
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nflag += __shfl_xor(nflag, o);
+  if (lane == 0 && nflag) atomicAdd(s_cnt, nflag);
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[blockIdx.x] = *s_cnt;
+}
+
+// Exclusive prefix of the G workgroup counts (G <= SUBX_GROUPS): offs[g]; the total in offs[SUBX_GROUPS].
+__global__ __launch_bounds__(1024) void k_subx_scan(const int* __restrict__ cnt, int G, int* __restrict__ offs) {
+  __shared__ int buf[1024];
+  const int tid = threadIdx.x;
+  buf[tid] = tid < G ? cnt[tid] : 0;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = tid >= o ? buf[tid - o] : 0;
+    __syncthreads();
+    buf[tid] += v;
+    __syncthreads();
+  }
+  if (tid < G) offs[tid] = buf[tid] - cnt[tid];
+  if (tid == 0) offs[SUBX_GROUPS] = buf[1023];
+}
+
+// The flagged rows of workgroup g's range, in sorted order, at offs[g]: their
+// point indices and clusters (the FP32 kernel's row list).
+__global__ __launch_bounds__(256) void k_subx_scatter(long long n_sorted, long long per_block,
+                                                      const unsigned char* __restrict__ flag,
+                                                      const int* __restrict__ perm, const int* __restrict__ z,
+                                                      const int* __restrict__ zrow, const int* __restrict__ offs,
+                                                      int* __restrict__ perm_c, int* __restrict__ zrow_c) {
+  __shared__ int wsum[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long begin = (long long)blockIdx.x * per_block;
+  const long long end = begin + per_block < n_sorted ? begin + per_block : n_sorted;
+  int at = offs[blockIdx.x];
+  for (long long c = begin; c < end; c += 256) {
+    const long long g = c + threadIdx.x;
+    const bool f = g < end && flag[g];
+    const unsigned long long m = __ballot(f);
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      before += w < wave ? wsum[w] : 0;
+      tot += wsum[w];
+    }
+    if (f) {
+      const int o = at + before + __popcll(m & ((1ull << lane) - 1ull));
+      const int p = perm[g];
+      perm_c[o] = p;
+      zrow_c[o] = zrow ? zrow[g] : z[p];
+    }
+    at += tot;
+    __syncthreads();
   }
 }
 
@@ -994,12 +1236,54 @@ __global__ __launch_bounds__(D) void k_pack_bias(int K, int k_max, const float* 
 
 size_t wbias_floats(int d, int k_max) { return (d == 64 || d == 128) ? (size_t)k_max * (d + 4) + d : 0; }
 
+size_t sub_labels_x3_lds(int d) {
+  const int nt = d == 128 ? 20 : 6;
+  return (size_t)4 * nt * 64 * 16 + (size_t)(3 * d + 4) * sizeof(float) + 16;
+}
+
+hipError_t launch_sub_labels_x3(int d, const float* x, long long n, const int* perm, const int* z, const int* zrow,
+                                unsigned char* zsub, const float* packed, int k_max, uint32_t t, uint64_t seed,
+                                const SubX3& b, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_sub_labels_x3<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)sub_labels_x3_lds(128));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  // one workgroup per CU (eight waves of 64 rows), each on a contiguous range of whole waves' rows
+  const long long cap = SUBX_GROUPS;
+  long long per = (n + cap - 1) / cap;
+  per = ((per + 63) / 64) * 64;
+  const unsigned G = (unsigned)((n + per - 1) / per);
+  const size_t lds = sub_labels_x3_lds(d);
+  const bf16x8* hi = (const bf16x8*)b.hi;
+  const bf16x8* lo = (const bf16x8*)b.lo;
+  if (d == 128)
+    hipLaunchKernelGGL(k_sub_labels_x3<128>, dim3(G), dim3(SUBX_BLOCK), lds, s, x, n, per, perm, z, zrow, zsub, packed,
+                       hi, lo, k_max, t, seed, b.flag, b.cnt);
+  else if (d == 64)
+    hipLaunchKernelGGL(k_sub_labels_x3<64>, dim3(G), dim3(SUBX_BLOCK), lds, s, x, n, per, perm, z, zrow, zsub, packed,
+                       hi, lo, k_max, t, seed, b.flag, b.cnt);
+  else
+    return hipErrorInvalidValue;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_subx_scan, dim3(1), dim3(1024), 0, s, b.cnt, (int)G, b.offs);
+  hipLaunchKernelGGL(k_subx_scatter, dim3(G), dim3(256), 0, s, n, per, b.flag, perm, z, zrow, b.offs, b.perm_c,
+                     b.zrow_c);
+  return hipGetLastError();
+}
+
 bool mfma_supported(int d) { return d == 32 || d == 64 || d == 128; }
 
 hipError_t launch_pack_wfrag(int K, int d, int k_max, const float* packed, void* whi, void* wlo, float* wbias,
-                             hipStream_t s) {
+                             void* shi, void* slo, hipStream_t s) {
   if (K <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pack_wfrag, dim3(K), dim3(256), 0, s, K, d, k_max, packed, (__bf16*)whi, (__bf16*)wlo);
+  hipLaunchKernelGGL(k_pack_wfrag, dim3(K), dim3(256), 0, s, K, d, 0, packed, (__bf16*)whi, (__bf16*)wlo);
+  // the sub-clusters' records follow the clusters' (slot k_max + 2 k + h)
+  if (shi) hipLaunchKernelGGL(k_pack_wfrag, dim3(2 * K), dim3(256), 0, s, 2 * K, d, k_max, packed, (__bf16*)shi, (__bf16*)slo);
   if (wbias && (d == 64 || d == 128)) {
     hipLaunchKernelGGL(k_pack_centre, dim3(1), dim3(128), 0, s, K, d, packed, wbias + (size_t)k_max * (d + 4));
     if (d == 128)

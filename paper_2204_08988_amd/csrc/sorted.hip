@@ -766,16 +766,22 @@ __device__ __forceinline__ int block_inclusive_scan_big(int v, int* buf) {
 // once on mu_0; sub-cluster 1 starts its accumulators at W_1 (mu_0 - mu_1), so
 // that both products read the same centred rows.  Row blocks of W above the
 // diagonal are skipped (k <= 32 mt + 31 for output rows 32 mt ... 32 mt + 31)
-// and the entries above the diagonal inside a block are read as zero.
+// and the entries above the diagonal inside a block are read as zero.  With
+// n_dev the rows are the list of n_dev[0] rows that the bf16x3 pass left
+// undecided (n_sorted then only bounds the grid).
 constexpr int SUBL_BLOCK = 256;
 
 template <int D>
 __global__ __launch_bounds__(SUBL_BLOCK) __attribute__((amdgpu_waves_per_eu(2, D <= 32 ? 3 : 2))) void k_sub_labels_mfma(
     const float* __restrict__ x, long long n_sorted, long long per_block, const int* __restrict__ perm,
     const int* __restrict__ z, const int* __restrict__ zrow, unsigned char* __restrict__ zsub,
-    const float* __restrict__ packed, int k_max, uint32_t t, uint64_t seed) {
+    const float* __restrict__ packed, int k_max, uint32_t t, uint64_t seed, const int* __restrict__ n_dev) {
   constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
   constexpr int MT = D / 32, HALF = D / 2, QTR = D / 4;
+  if (n_dev) {  // a row list whose length is on the device: split it evenly over the grid
+    n_sorted = *n_dev;
+    per_block = ((n_sorted + gridDim.x - 1) / gridDim.x + 63) / 64 * 64;
+  }
   static_assert(D % 32 == 0 && D <= SUBL_BLOCK, "layout");
   typedef float f32x16 __attribute__((ext_vector_type(16)));
   extern __shared__ __align__(16) float s_rec[];  // records of sub-clusters 0 and 1, then W_1 (mu_0 - mu_1), mu_0 - mu_1
@@ -1296,7 +1302,8 @@ int big_tpb(int d, long long n) {
 hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts, long long n, const int* perm,
                              const int* z, const int* zrow, unsigned char* zsub, const float* packed, int K, int k_max,
                              uint32_t t, uint64_t seed, long long* counts, double* moments, const int* cstart,
-                             const int* ctot, int kbase, int ncl, double* part, hipStream_t s) {
+                             const int* ctot, int kbase, int ncl, double* part, hipStream_t s,
+                             const SubX3* x3 = nullptr) {
   hipError_t e;
   if (n == 0) return hipSuccess;
   const int E = d + d * (d + 1) / 2;
@@ -1320,15 +1327,29 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
       long long lper = (n + cap - 1) / cap;
       lper = ((lper + 63) / 64) * 64;
       const unsigned lg = (unsigned)((n + lper - 1) / lper);
+      // with BF16 tables (d = 64, 128) a bf16x3 pass draws most rows first and this
+      // kernel only the list it leaves
+      const int* lperm = perm;
+      const int* lz = z;
+      const int* lzrow = zrow;
+      const int* ndev = nullptr;
+      if (x3 && (d == 64 || d == 128)) {
+        e = launch_sub_labels_x3(d, x, n, perm, z, zrow, zsub, packed, k_max, t, seed, *x3, s);
+        if (e != hipSuccess) return e;
+        lperm = x3->perm_c;
+        lz = nullptr;
+        lzrow = x3->zrow_c;
+        ndev = x3->offs + SUBX_GROUPS;
+      }
       if (d == 128)
-        hipLaunchKernelGGL(k_sub_labels_mfma<128>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, perm, z, zrow,
-                           zsub, packed, k_max, t, seed);
+        hipLaunchKernelGGL(k_sub_labels_mfma<128>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, lperm, lz, lzrow,
+                           zsub, packed, k_max, t, seed, ndev);
       else if (d == 64)
-        hipLaunchKernelGGL(k_sub_labels_mfma<64>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, perm, z, zrow,
-                           zsub, packed, k_max, t, seed);
+        hipLaunchKernelGGL(k_sub_labels_mfma<64>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, lperm, lz, lzrow,
+                           zsub, packed, k_max, t, seed, ndev);
       else
-        hipLaunchKernelGGL(k_sub_labels_mfma<32>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, perm, z, zrow,
-                           zsub, packed, k_max, t, seed);
+        hipLaunchKernelGGL(k_sub_labels_mfma<32>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, lperm, lz, lzrow,
+                           zsub, packed, k_max, t, seed, ndev);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     sample = false;
@@ -1424,17 +1445,17 @@ size_t sub_stats_part_doubles_max(int d) {
 hipError_t launch_sub_stats(int d, bool sample, const float* x, long long n, const int* perm, const int* z,
                             const int* zrow, unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t,
                             uint64_t seed, long long* counts, double* moments, const int* cstart, const int* ctot,
-                            double* part, hipStream_t s) {
+                            double* part, hipStream_t s, const SubX3* x3) {
   const int E = d + d * (d + 1) / 2;
   if (n > 0 && part)  // slot mode: every cluster's entries are written, no zeroing
     return sub_stats_kernels(d, sample, x, n, n, perm, z, zrow, zsub, packed, K, k_max, t, seed, counts, moments,
-                             cstart, ctot, 0, K, part, s);
+                             cstart, ctot, 0, K, part, s, x3);
   hipError_t e = launch_zero64(counts, (size_t)2 * K, s);
   if (e != hipSuccess) return e;
   e = launch_zero64(moments, (size_t)2 * K * E, s);
   if (e != hipSuccess) return e;
   return sub_stats_kernels(d, sample, x, n, n, perm, z, zrow, zsub, packed, K, k_max, t, seed, counts, moments,
-                           nullptr, nullptr, 0, K, nullptr, s);
+                           nullptr, nullptr, 0, K, nullptr, s, x3);
 }
 
 bool partition_stats_supported(int d) { return d == 8 || d == 16 || d == 32 || d == 64 || d == 128; }
