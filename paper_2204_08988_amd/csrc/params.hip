@@ -249,9 +249,10 @@ constexpr int NIW_BIG_THREADS = 512;
 // k_niw_draw for 64 < d <= NIW_BIG_MAX_D: one workgroup of 512 threads per
 // component with one d x d float64 matrix resident in LDS (row stride d + 1),
 // reused in place by every stage: Psi_n -> L = chol(Psi_n) -> F = L A^-T (the
-// columns of the Bartlett factor A come from the component's global scratch,
-// one column ahead) -> Sigma = F F^T (4 x 4 register tiles) -> G = chol(Sigma)
-// -> W = G^-1.  Same random draws and outputs as k_niw_draw.
+// Bartlett factor A from the component's global scratch, eight columns at a
+// time) -> Sigma = F F^T (4 x 4 register tiles) -> G = chol(Sigma) -> W = G^-1,
+// the factorisations, the solve and the inverse in eight-column panels (two
+// barriers per panel).  Same random draws and outputs as k_niw_draw.
 __global__ __launch_bounds__(NIW_BIG_THREADS) void k_niw_draw_lds(
     int K, int d, int k_max, NiwPriorDev prior, const long long* __restrict__ counts,
     const double* __restrict__ moments, const double* __restrict__ log_pi, const double* __restrict__ log_pisub,
@@ -259,6 +260,7 @@ __global__ __launch_bounds__(NIW_BIG_THREADS) void k_niw_draw_lds(
     double* __restrict__ scratch, float* __restrict__ packed, double* __restrict__ logdet_out, int* __restrict__ err) {
   extern __shared__ double M[];  // [d][d + 1]
   __shared__ double colbuf[2][NIW_BIG_MAX_D], eps[NIW_BIG_MAX_D], red[NIW_BIG_THREADS];
+  __shared__ double apan[PNL * NIW_BIG_MAX_D];  // a panel of A's columns, then the inverse's products
   __shared__ int flag;
   __shared__ double sh_n;
   const int e = blockIdx.x;
@@ -312,27 +314,11 @@ __global__ __launch_bounds__(NIW_BIG_THREADS) void k_niw_draw_lds(
   for (int q = tid; q < d; q += nt) eps[q] = normal_draw(seed, t, (uint32_t)e, TAG_NIW, (uint32_t)(nq_off + d + q));
   __threadfence_block();
   __syncthreads();
-  if (!wg_cholesky(M, d, &flag, ld)) {
+  if (!wg_cholesky_panel(M, d, ld, &flag)) {
     if (tid == 0) atomicOr(err, 1);
   }
-  // F = L A^-T in place: column j of F is final after dividing by A_jj, then
-  // F[:, q] -= F[:, j] A[q][j] for q > j; column j + 1 of A is read while step j runs
-  if (tid < d) colbuf[0][tid] = At[tid];
-  __syncthreads();
-  for (int j = 0; j < d; ++j) {
-    const double* cur = colbuf[j & 1];
-    double* nxt = colbuf[(j + 1) & 1];
-    const double pre = (j + 1 < d && tid < d) ? At[(size_t)(j + 1) * d + tid] : 0.0;
-    const double inv = 1.0 / cur[j];
-    for (int r = tid; r < d; r += nt) M[r * ld + j] *= inv;
-    __syncthreads();
-    for (int r = ty; r < d; r += nty) {
-      const double frj = M[r * ld + j];
-      for (int q = j + 1 + tx; q < d; q += 32) M[r * ld + q] -= frj * cur[q];
-    }
-    if (j + 1 < d && tid < d) nxt[tid] = pre;  // last read in step j - 1
-    __syncthreads();
-  }
+  // F = L A^-T in place (panels of eight columns of A staged in LDS)
+  wg_right_solve_lt_panel(M, d, ld, At, apan, colbuf[0]);
   // mu = m_n + F eps / sqrt(kappa_n)
   const double rs = 1.0 / sqrt(kn);
   for (int r = tid; r < d; r += nt) {
@@ -404,13 +390,13 @@ __global__ __launch_bounds__(NIW_BIG_THREADS) void k_niw_draw_lds(
   }
   __syncthreads();
   // G = chol(Sigma), log|Sigma|, W = G^-1, the float32 record
-  if (!wg_cholesky(M, d, &flag, ld)) {
+  if (!wg_cholesky_panel(M, d, ld, &flag)) {
     if (tid == 0) atomicOr(err, 2);
   }
   double lds = 0.0;
   for (int i = tid; i < d; i += nt) lds += log(M[i * ld + i]);
   lds = 2.0 * block_reduce_sum(lds, red);
-  wg_lower_inverse_inplace(M, d, ld, colbuf[0]);
+  wg_lower_inverse_panel(M, d, ld, apan);
   const double lw = c == 0 ? log_pi[k] : log_pisub[2 * k + (c - 1)];
   float* rec = packed + (size_t)record_slot(k, c, k_max) * gauss_rec_stride(d);
   const int stride = gauss_rec_stride(d);
