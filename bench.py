@@ -8,7 +8,8 @@ set, resident in HBM before the clock starts.
 Headline workload: the largest configuration, gauss_d128 -- N = 1e7 points,
 d = 128, 100 true clusters (means N(0, 9 I), covariances Wishart(d + 2, I/d),
 weights Dirichlet(1)), cluster scoring in BF16 on the matrix cores with the
-FP32 guard, sub-labels FP32, statistics and parameters FP64.  The chain
+FP32 guard, sub-labels in bf16x3 with FP32 on the rows it leaves undecided
+(the same sub-labels as the FP32 pass), statistics and parameters FP64.  The chain
 starts at its converged state (the generating labels, random sub-labels,
 every cluster old enough to split or merge); the warm-up steps let the
 sub-clusters settle and every timed step is a full iteration.
@@ -338,7 +339,7 @@ def headline(args):
         "config": {"workload": f"{HEADLINE}: Gaussian DPMM, N={rec['n']}, d={d}, {rec['k_true']} true clusters, "
                                "means N(0,9I), covariances Wishart(d+2, I/d), weights Dir(1); converged state "
                                f"(generating labels); cluster scoring {args.precision} with the FP32 guard, "
-                               "sub-labels FP32, statistics and parameters FP64",
+                               "sub-labels bf16x3 with the FP32 guard, statistics and parameters FP64",
                    "n": rec["n"], "d": d, "k_mean": rec["k_mean"], "alpha": ALPHA, "parallelism": "single GPU"},
         "iters_per_s": rec["iters_per_s"],
         "phase_ms": rec["phase_ms"],
