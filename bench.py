@@ -25,7 +25,8 @@ bounded sample on the host cores (all cores and one core).
 
 Other modes: --label-step WORKLOAD (label step at a workload's generating
 mixture), --learned-ab (time to the log-posterior plateau, learned proposal
-vs plain, over several seeds).
+vs plain, over several seeds), --width-compare (the K-wide cluster draw
+against the 3K-wide whitening form at the headline shape).
 """
 import argparse
 import json
@@ -135,16 +136,20 @@ def mfma_roofline(rec, d, kernel):
             "evals_per_launch": rec["n"] * rec["k_mean"]}
 
 
-def label_step_run(torch, name, n, precision, steps, warmup):
+def label_step_run(torch, name, n, precision, steps, warmup, thirds=False):
     """Label-step throughput at a workload's true mixture: the statistics come
     from the generating labels, nothing splits or merges (burn_out beyond the
-    run), and each timed iteration redraws the parameters and the labels."""
+    run), and each timed iteration redraws the parameters and the labels.
+    thirds: every true cluster split into three interleaved clusters (3K
+    components scored per point, the work of the 3K-wide whitening form)."""
     from paper_2204_08988_amd import datagen
     spec = datagen.WORKLOADS[name]
     gauss = isinstance(spec, datagen.GaussianSpec)
     x_np, labels = datagen.workload(name, 5, n)
     n, d = x_np.shape
     labels = np.unique(labels, return_inverse=True)[1]  # the occupied clusters, renumbered
+    if thirds:
+        labels = 3 * labels + np.arange(n) % 3
     K = int(labels.max()) + 1
     x = torch.from_numpy(x_np).cuda()
     del x_np
@@ -365,6 +370,28 @@ def headline(args):
     print(json.dumps(out), flush=True)
 
 
+def width_compare(args):
+    """The K-wide cluster draw (this build: K cluster components per point, the
+    sub-clusters in their own pass over the sorted rows) against the 3K-wide
+    form (every cluster and sub-cluster scored for every point), timed as the
+    same main-pass kernel over K and over 3K components at the headline shape."""
+    import torch
+    n = int(float(args.n)) if args.n else None
+    kw = label_step_run(torch, HEADLINE, n, "bf16", args.steps, args.warmup)
+    w3 = label_step_run(torch, HEADLINE, n, "bf16", args.steps, args.warmup, thirds=True)
+    d, N, K = kw["d"], kw["n"], kw["K"]
+    exe = 1.25 * d * d  # executed MFMA flops per point-component (zero tiles above the diagonal skipped)
+    alg = N * (K + 2) * flops_per_eval(d)
+    rec = {"metric": "whitening form: K-wide + sub-cluster pass vs 3K-wide", "workload": kw["workload"],
+           "algorithmic_flops_per_step": alg,
+           "k_wide": {"components": K, "cluster_draw_ms": kw["label_kernel"]["kernel_ms"],
+                      "executed_flops_cluster_draw": N * K * exe,
+                      "executed_flops_sub_labels_bf16x3": N * 2 * 3 * exe},
+           "three_k_wide": {"components": 3 * K, "cluster_draw_ms": w3["label_kernel"]["kernel_ms"],
+                            "executed_flops": N * 3 * K * exe}}
+    print(json.dumps(rec), flush=True)
+
+
 def label_step(args):
     import torch
     res = label_step_run(torch, args.label_step, int(float(args.n)) if args.n else None, args.precision, args.steps,
@@ -488,6 +515,9 @@ def main():
                     help="only copy a device buffer of BYTES five times (calibrates HBM byte counters)")
     ap.add_argument("--sparse", action="store_true",
                     help="instead of the throughput line: the sparse-row (news_v20k) chain and label step only")
+    ap.add_argument("--width-compare", action="store_true",
+                    help="instead of the throughput line: the K-wide cluster draw against the 3K-wide form at the "
+                         "headline shape")
     ap.add_argument("--label-step", metavar="WORKLOAD",
                     help="instead of the throughput line: label-step throughput at WORKLOAD's true mixture")
     ap.add_argument("--n", default=None, help="points for --label-step (default: the workload's N)")
@@ -520,6 +550,9 @@ def main():
         return
     if args.label_step:
         label_step(args)
+        return
+    if args.width_compare:
+        width_compare(args)
         return
     if args.sparse:
         import torch
