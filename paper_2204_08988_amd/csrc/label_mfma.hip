@@ -596,12 +596,13 @@ constexpr float UC_GAMMA2 = 1.0f / 16384.0f;
 constexpr float UC_EPSS = 1.0f / 65536.0f;
 
 // Main pass for d = 64, 128 in BF16, cluster-stationary and uncentred: the
-// workgroup's 256 rows are centred once per step on the common centre c,
+// workgroup's rows, PTS (512, or 256 when the LDS counters of a large K leave no
+// room) per step, are centred once per step on the common centre c,
 // rounded to BF16 and stored in LDS (rows padded by 16 bytes, so that the
 // sixteen-byte reads of 32 rows fall on distinct banks), with each row's norm
 // ||x'||.  Each of the eight waves takes every eighth cluster and holds its
 // whitener fragments (non-zero tiles only) and its offset beta = -W (mu - c),
-// in the accumulator layout, in registers while it sweeps the eight 32-point
+// in the accumulator layout, in registers while it sweeps the step's 32-point
 // tiles: a row block's accumulators start at beta (the matrix cores add it),
 // so a tile costs its MFMAs, its B operands read from LDS and the squared
 // norms, and none of the per-cluster centring and rounding of the rows.  Each
@@ -610,7 +611,7 @@ constexpr float UC_EPSS = 1.0f / 65536.0f;
 // FP32 draw, so the labels are those of the FP32 draw.
 // The partial top-2 states of the waves are merged through LDS at the end of
 // the step (top2_merge).
-template <int D>
+template <int D, int PTS>
 __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float* __restrict__ x, long long n,
                                                                      long long per_block,
                                                                      const bf16x8* __restrict__ whi,
@@ -621,18 +622,19 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
   using TT = TriTiles<D>;
   constexpr int MT = TT::MT, KS = TT::KS, NF = MT * KS * 64, NT = TT::NT;
   constexpr int RB = D / 8 + 1;  // LDS row stride in 16-byte units
-  constexpr int TILES = CS_PTS / 32;
+  constexpr int TILES = PTS / 32;
   constexpr int NW = BLOCK_CS / 64;
   constexpr int P4 = D / 4;       // float4 pieces of a row
   constexpr int RPI = 64 / P4;    // rows per wave and staging pass
-  constexpr int ITER = 32 / RPI;  // staging passes for the wave's 32 rows
-  static_assert(CS_PTS == BLOCK && D % 64 == 0 && NW * 32 == CS_PTS, "step, row copies");
-  static_assert(NW * CS_PTS * 4 * sizeof(float) <= CS_PTS * RB * 16, "partial states alias the rows");
+  constexpr int WROWS = PTS / NW;  // rows staged per wave
+  constexpr int ITER = WROWS / RPI;  // staging passes for the wave's rows
+  static_assert(D % 64 == 0 && PTS % (32 * NW) == 0 && PTS <= BLOCK_CS, "step, row copies");
+  static_assert(NW * PTS * 4 * sizeof(float) <= PTS * RB * 16, "partial states alias the rows");
   typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
   extern __shared__ __align__(16) unsigned char smem[];
-  bf16x8* xb = reinterpret_cast<bf16x8*>(smem);                 // [CS_PTS][RB] centred BF16 rows
-  float* rxs = reinterpret_cast<float*>(smem + CS_PTS * RB * 16);  // [CS_PTS] ||x'||
-  int* h = reinterpret_cast<int*>(rxs + CS_PTS);                  // [K] counters
+  bf16x8* xb = reinterpret_cast<bf16x8*>(smem);                 // [PTS][RB] centred BF16 rows
+  float* rxs = reinterpret_cast<float*>(smem + PTS * RB * 16);  // [PTS] ||x'||
+  int* h = reinterpret_cast<int*>(rxs + PTS);                  // [K] counters
   const float4* cst = reinterpret_cast<const float4*>(wbias + (size_t)k_max * D);  // (c_k, (g + g2) ||W||_F, g2 ||W||_F ||mu - c||, 0)
   const float* centre = wbias + (size_t)k_max * (D + 4);
   for (int k = threadIdx.x; k < K; k += BLOCK_CS) h[k] = 0;
@@ -642,8 +644,8 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
   const float4 c4 = *reinterpret_cast<const float4*>(centre + 4 * part);
   const long long begin = (long long)blockIdx.x * per_block;
   const long long end = begin + per_block < n ? begin + per_block : n;
-  for (long long chunk = begin; chunk < end; chunk += CS_PTS) {
-    const int rows = end - chunk < CS_PTS ? (int)(end - chunk) : CS_PTS;
+  for (long long chunk = begin; chunk < end; chunk += PTS) {
+    const int rows = end - chunk < PTS ? (int)(end - chunk) : PTS;
     __syncthreads();  // the previous step's merge is done with the rows' space
     // the wave's 32 rows: x' = x - c rounded to BF16, and ||x'|| (rows past the end are zero)
     {
@@ -653,7 +655,7 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
       float4 v[ITER];
 #pragma unroll
       for (int it = 0; it < ITER; ++it) {
-        const int r = wave * 32 + it * RPI + sub;
+        const int r = wave * WROWS + it * RPI + sub;
         const f32x4 u = r < rows ? __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(x + (chunk + r) * D + 4 * part))
                                  : f32x4{c4.x, c4.y, c4.z, c4.w};
         v[it] = make_float4(u.x, u.y, u.z, u.w);
@@ -661,7 +663,7 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
       float ss[ITER];
 #pragma unroll
       for (int it = 0; it < ITER; ++it) {
-        const int r = wave * 32 + it * RPI + sub;
+        const int r = wave * WROWS + it * RPI + sub;
         const float d0 = v[it].x - c4.x, d1 = v[it].y - c4.y, d2 = v[it].z - c4.z, d3 = v[it].w - c4.w;
         ss[it] = fmaf(d3, d3, fmaf(d2, d2, fmaf(d1, d1, d0 * d0)));
         bf16x4 b4;
@@ -677,12 +679,10 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
         for (int it = 0; it < ITER; ++it) ss[it] += __shfl_xor(ss[it], o);
       if (part == 0)
 #pragma unroll
-        for (int it = 0; it < ITER; ++it) rxs[wave * 32 + it * RPI + sub] = __builtin_amdgcn_sqrtf(ss[it]);
+        for (int it = 0; it < ITER; ++it) rxs[wave * WROWS + it * RPI + sub] = __builtin_amdgcn_sqrtf(ss[it]);
     }
     __syncthreads();
-    float rxv[TILES];
-#pragma unroll
-    for (int t = 0; t < TILES; ++t) rxv[t] = rxs[t * 32 + col];
+
     Top2U st[TILES / 2];
 #pragma unroll
     for (int j = 0; j < TILES / 2; ++j) st[j].init();
@@ -745,7 +745,7 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
           qm = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
         }
         const float sq = __builtin_amdgcn_sqrtf(qm);
-        const float e = fmaf(UC_EPSS, sq, fmaf(kc.y, rxv[t], kc.z));
+        const float e = fmaf(UC_EPSS, sq, fmaf(kc.y, rxs[t * 32 + col], kc.z));
         const float sp = sq + e, sm = sq - e;
         const float lo = fmaf(-0.5f * sp, sp, kc.x);
         const float up = sm > 0.0f ? fmaf(-0.5f * sm, sm, kc.x) : kc.x;
@@ -765,19 +765,19 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
 #pragma unroll
     for (int j = 0; j < TILES / 2; ++j) {
       const int p = (2 * j + half) * 32 + col;
-      float* o = ps + ((size_t)wave * CS_PTS + p) * 4;
+      float* o = ps + ((size_t)wave * PTS + p) * 4;
       o[0] = st[j].u1;
       o[1] = st[j].u2;
       o[2] = st[j].lo_max;
       o[3] = __int_as_float(st[j].k1);
     }
     __syncthreads();
-    if (threadIdx.x < CS_PTS) {
+    if (threadIdx.x < PTS) {
       Top2U m;
       m.init();
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
-        const float* o = ps + ((size_t)w * CS_PTS + threadIdx.x) * 4;
+        const float* o = ps + ((size_t)w * PTS + threadIdx.x) * 4;
         top2_merge(m, o[0], o[1], o[2], __float_as_int(o[3]));
       }
       finish_main(threadIdx.x < rows, chunk + threadIdx.x, m, z, h, flagged, n_flagged, lane);
@@ -790,8 +790,8 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
   }
 }
 
-size_t label_uc_lds(int d, int K) {
-  return (size_t)CS_PTS * (d / 8 + 1) * 16 + (size_t)CS_PTS * sizeof(float) + (size_t)K * sizeof(int);
+size_t label_uc_lds(int d, int K, int pts) {
+  return (size_t)pts * (d / 8 + 1) * 16 + (size_t)pts * sizeof(float) + (size_t)K * sizeof(int);
 }
 
 constexpr int RS_BLOCK = 256;
@@ -1309,9 +1309,10 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
   if (e != hipSuccess) return e;
   static bool attr_set = false;
   if (!attr_set) {  // d = 32 and the uncentred kernels: more than 64 KB of dynamic LDS (160 KB per CU)
-    const void* fns[5] = {(const void*)k_label_gauss_mfma32<true, false>, (const void*)k_label_gauss_mfma32<false, false>,
-                          (const void*)k_label_gauss_mfma32<true, true>, (const void*)k_label_gauss_mfma_uc<128>,
-                          (const void*)k_label_gauss_mfma_uc<64>};
+    const void* fns[7] = {(const void*)k_label_gauss_mfma32<true, false>, (const void*)k_label_gauss_mfma32<false, false>,
+                          (const void*)k_label_gauss_mfma32<true, true>, (const void*)k_label_gauss_mfma_uc<128, 256>,
+                          (const void*)k_label_gauss_mfma_uc<64, 256>, (const void*)k_label_gauss_mfma_uc<128, 512>,
+                          (const void*)k_label_gauss_mfma_uc<64, 512>};
     for (const void* f : fns) {
       e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       if (e != hipSuccess) return e;
@@ -1327,14 +1328,26 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
     // time stamps, for timing it alone without extra queue packets)
     hipEvent_t e0 = cands ? nullptr : ev_main0, e1 = cands ? nullptr : ev_main1;
     if ((d == 64 || d == 128) && !cands && !x3 && wbias) {
-      // BF16 main pass, uncentred: the rows centred once on the common centre
-      const size_t luc = label_uc_lds(d, K);
-      if (d == 128)
-        hipExtLaunchKernelGGL((k_label_gauss_mfma_uc<128>), dim3(Gp), dim3(BLOCK_CS), luc, s, e0, e1, 0, x, n,
-                              per_block, hi, wbias, K, k_max, z, hist, tot, flagged, n_flagged);
-      else
-        hipExtLaunchKernelGGL((k_label_gauss_mfma_uc<64>), dim3(Gp), dim3(BLOCK_CS), luc, s, e0, e1, 0, x, n,
-                              per_block, hi, wbias, K, k_max, z, hist, tot, flagged, n_flagged);
+      // BF16 main pass, uncentred: the rows centred once on the common centre, 512 per
+      // step while they and the counters fit in LDS (fewer fragment fetches and merges
+      // per point), else 256
+      const bool big = label_uc_lds(d, K, 512) <= (size_t)160 * 1024;
+      const size_t luc = label_uc_lds(d, K, big ? 512 : 256);
+#define DPMM_UC(DD, PP)                                                                                       \
+  hipExtLaunchKernelGGL((k_label_gauss_mfma_uc<DD, PP>), dim3(Gp), dim3(BLOCK_CS), luc, s, e0, e1, 0, x, n, \
+                        per_block, hi, wbias, K, k_max, z, hist, tot, flagged, n_flagged)
+      if (d == 128) {
+        if (big)
+          DPMM_UC(128, 512);
+        else
+          DPMM_UC(128, 256);
+      } else {
+        if (big)
+          DPMM_UC(64, 512);
+        else
+          DPMM_UC(64, 256);
+      }
+#undef DPMM_UC
     } else if (d == 64 || d == 128) {
       // static staging buffers; only the histogram is dynamic
 #define DPMM_MFMA_W32(DD, XX, CC)                                                                            \
