@@ -47,13 +47,13 @@ PEAK_BF16_MFMA = 2.5e15    # dense BF16 matrix-core peak
 PEAK_FP32_MFMA = 157.3e12  # dense FP32 matrix-core peak
 PEAK_FP64_MFMA = 78.6e12   # dense FP64 matrix-core peak
 HEADLINE = "gauss_d128"
-HEADLINE_KERNEL = "k_label_gauss_mfma_uc<128>"
+HEADLINE_KERNEL = "k_label_gauss_mfma_uc<128, 512>"
 # HBM bytes per launch of the headline kernel at the headline workload (N = 1e7,
 # d = 128, K = 100) from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the
 # factors being what a 1 GiB device copy reads on the same counters (FETCH_SIZE
 # 0.5 GiB, WRITE_SIZE 1 GiB); empty whenever the kernel changes until the
 # counters are taken again
-MEASURED_TRAFFIC = {HEADLINE_KERNEL: (3.1328e6 * 2.0 + 1.7743e5) * 1024}
+MEASURED_TRAFFIC = {HEADLINE_KERNEL: (2.5404e6 * 2.0 + 9.1454e4) * 1024}
 
 
 def flops_per_eval(d):

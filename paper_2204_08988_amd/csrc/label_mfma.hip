@@ -591,6 +591,8 @@ __device__ __forceinline__ void top2_merge(Top2U& a, float u1, float u2, float l
 // The computed s = sqrt(q_bf16) is within 2^-16 s of ||Y||, so with
 // E' = E + 2^-16 s the exact q lies in [max(0, s - E')^2, (s + E')^2]: the
 // score lies in [c_k - (s + E')^2 / 2, c_k - max(0, s - E')^2 / 2].
+constexpr int UC_BUF_DWORD3 = 0x00020000;  // raw buffer descriptor word 3 (gfx9 family)
+constexpr int UC_NT = 2;                    // cache policy of the row loads: non-temporal
 constexpr float UC_GAMMA = 1.02f / 128.0f;
 constexpr float UC_GAMMA2 = 1.0f / 16384.0f;
 constexpr float UC_EPSS = 1.0f / 65536.0f;
@@ -647,39 +649,50 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
   for (long long chunk = begin; chunk < end; chunk += PTS) {
     const int rows = end - chunk < PTS ? (int)(end - chunk) : PTS;
     __syncthreads();  // the previous step's merge is done with the rows' space
-    // the wave's 32 rows: x' = x - c rounded to BF16, and ||x'|| (rows past the end are zero)
+    // the wave's rows: x' = x - c rounded to BF16, and ||x'|| (rows past the end
+    // are zero), sixteen loads in flight per batch
     {
       // the rows are read once: non-temporal loads, so that they do not evict
       // the whitener tables from L2
       typedef float f32x4 __attribute__((ext_vector_type(4)));
-      float4 v[ITER];
+      constexpr int SB = ITER < 16 ? ITER : 16;
+      static_assert(ITER % SB == 0, "staging batches");
+      // one buffer descriptor per step over its rows (loads past them return
+      // zero), one lane offset and a constant offset per row: no 64-bit
+      // address per load to keep live
+      const __amdgpu_buffer_rsrc_t rx =
+          __builtin_amdgcn_make_buffer_rsrc((void*)(x + chunk * D), (short)0, rows * D * 4, UC_BUF_DWORD3);
+      const int vo = ((wave * WROWS + sub) * D + 4 * part) * 4;
 #pragma unroll
-      for (int it = 0; it < ITER; ++it) {
-        const int r = wave * WROWS + it * RPI + sub;
-        const f32x4 u = r < rows ? __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(x + (chunk + r) * D + 4 * part))
-                                 : f32x4{c4.x, c4.y, c4.z, c4.w};
-        v[it] = make_float4(u.x, u.y, u.z, u.w);
+      for (int i0 = 0; i0 < ITER; i0 += SB) {
+        float4 v[SB];
+#pragma unroll
+        for (int j = 0; j < SB; ++j) {
+          const int r = wave * WROWS + (i0 + j) * RPI + sub;
+          const f32x4 u = __builtin_amdgcn_raw_buffer_load_b128(rx, vo, (i0 + j) * RPI * D * 4, UC_NT);
+          v[j] = r < rows ? make_float4(u.x, u.y, u.z, u.w) : c4;
+        }
+        float ss[SB];
+#pragma unroll
+        for (int j = 0; j < SB; ++j) {
+          const int r = wave * WROWS + (i0 + j) * RPI + sub;
+          const float d0 = v[j].x - c4.x, d1 = v[j].y - c4.y, d2 = v[j].z - c4.z, d3 = v[j].w - c4.w;
+          ss[j] = fmaf(d3, d3, fmaf(d2, d2, fmaf(d1, d1, d0 * d0)));
+          bf16x4 b4;
+          b4[0] = (__bf16)d0;
+          b4[1] = (__bf16)d1;
+          b4[2] = (__bf16)d2;
+          b4[3] = (__bf16)d3;
+          reinterpret_cast<bf16x4*>(xb + r * RB)[part] = b4;
+        }
+#pragma unroll
+        for (int o = P4 / 2; o > 0; o >>= 1)
+#pragma unroll
+          for (int j = 0; j < SB; ++j) ss[j] += __shfl_xor(ss[j], o);
+        if (part == 0)
+#pragma unroll
+          for (int j = 0; j < SB; ++j) rxs[wave * WROWS + (i0 + j) * RPI + sub] = __builtin_amdgcn_sqrtf(ss[j]);
       }
-      float ss[ITER];
-#pragma unroll
-      for (int it = 0; it < ITER; ++it) {
-        const int r = wave * WROWS + it * RPI + sub;
-        const float d0 = v[it].x - c4.x, d1 = v[it].y - c4.y, d2 = v[it].z - c4.z, d3 = v[it].w - c4.w;
-        ss[it] = fmaf(d3, d3, fmaf(d2, d2, fmaf(d1, d1, d0 * d0)));
-        bf16x4 b4;
-        b4[0] = (__bf16)d0;
-        b4[1] = (__bf16)d1;
-        b4[2] = (__bf16)d2;
-        b4[3] = (__bf16)d3;
-        reinterpret_cast<bf16x4*>(xb + r * RB)[part] = b4;
-      }
-#pragma unroll
-      for (int o = P4 / 2; o > 0; o >>= 1)
-#pragma unroll
-        for (int it = 0; it < ITER; ++it) ss[it] += __shfl_xor(ss[it], o);
-      if (part == 0)
-#pragma unroll
-        for (int it = 0; it < ITER; ++it) rxs[wave * WROWS + it * RPI + sub] = __builtin_amdgcn_sqrtf(ss[it]);
     }
     __syncthreads();
 
