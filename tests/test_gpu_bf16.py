@@ -182,6 +182,30 @@ def test_bf16_labels_far_from_origin(d, K, n, shift):
     S.close()
 
 
+@pytest.mark.parametrize("d,K,n,offset", [(64, 7, 6000, 0.0), (128, 6, 3000, 0.0), (128, 5, 2000, 300.0)])
+def test_bf16_draw_equals_fp32_draw(d, K, n, offset):
+    """The matrix-core forms promise the FP32 form's labels: a point is drawn
+    by the BF16 pass only where its interval leaves one cluster (one sub-label)
+    possible, the rest by the FP32 kernels.  Same seed, same parameters: the
+    labels and sub-labels of the BF16 and FP32 samplers are identical."""
+    import torch
+    from paper_2204_08988_amd.sampler import Sampler
+    seed = 4400 + d + K
+    params = _wishart_params(K, d, seed, mean_scale=1.5)
+    params = sampler.Params(params.log_pi, params.log_pisub, mu=params.mu + offset, sigma=params.sigma)
+    x = pu.gauss_points(params, n, seed + 1)
+    xt = torch.from_numpy(x).cuda()
+    out = {}
+    for prec in ("bf16", "fp32"):
+        S = Sampler("gaussian", d, K + 2, 2.0, seed, m=np.zeros(d), psi=np.eye(d), precision=prec)
+        S.set_params(params.log_pi, params.log_pisub, pu.comp_array(params))
+        out[prec] = [tuple(a.cpu().numpy() for a in S.sample_labels(xt, t)) for t in (2, 3)]
+        S.close()
+    for (zb, sb), (zf, sf) in zip(out["bf16"], out["fp32"]):
+        assert np.array_equal(zb, zf), np.nonzero(zb != zf)[0][:10]
+        assert np.array_equal(sb, sf), np.nonzero(sb != sf)[0][:10]
+
+
 def test_bf16_chain_recovers_clusters():
     import torch
     from paper_2204_08988_amd import datagen
