@@ -265,7 +265,8 @@ dpmm_status logml_range(dpmm_ctx* ctx, size_t first, size_t count) {
   hipError_t e;
   if (ctx->gaussian())
     e = launch_logml_gauss((int)count, ctx->d_items + first, ctx->d, prior_dev(ctx), ctx->logdet_psi, ctx->d_counts,
-                           ctx->d_moments, ctx->d_scratch, ctx->d_logml + first, ctx->d_err, ctx->stream);
+                           ctx->d_moments, ctx->d_scratch, ctx->d_logml + first, ctx->d_err, ctx->stream, nullptr,
+                           nullptr, 0, ctx->d_cmom, ctx->K);
   else if (ctx->poisson())
     e = launch_logml_pois((int)count, ctx->d_items + first, ctx->d, ctx->d_gshape, ctx->d_grate, ctx->pois_const,
                           ctx->d_counts, ctx->d_sums, ctx->d_logml + first, ctx->stream);
@@ -494,6 +495,7 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     ok = ok && chk(c->alloc(&c->d_sigma, 3 * (size_t)km * d * d));
     c->scratch_slots = std::max(3 * km, 256);
     ok = ok && chk(c->alloc(&c->d_scratch, (size_t)c->scratch_slots * NIW_SCRATCH(d)));
+    if (d > 64 && d <= 128) ok = ok && chk(c->alloc(&c->d_cmom, (size_t)km * (d * (d + 1) / 2)));
     if (cfg->precision != DPMM_FP32) {
       ok = ok && chk(c->alloc(&c->d_whi, (size_t)km * d * d));
       ok = ok && chk(c->alloc(&c->d_nflag, 2));

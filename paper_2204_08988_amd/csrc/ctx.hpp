@@ -89,6 +89,8 @@ struct dpmm_ctx {
   uint16_t *d_whi = nullptr, *d_wlo = nullptr;
   // offsets, constants and the common centre of the uncentred BF16 main pass (d = 64, 128)
   float* d_wbias = nullptr;
+  // the clusters' summed scatter matrices plus Psi / 2 for the log marginals at 64 < d <= 128
+  double* d_cmom = nullptr;
   // BF16 fragments of the sub-cluster whiteners and the buffers of the bf16x3
   // sub-label pass (d = 64, 128): per-workgroup counts and offsets, and per
   // sorted row (sized with the permutation) the undecided flags and list

@@ -210,10 +210,13 @@ constexpr int LOGML_BOUND = -3;
 constexpr int MERGE_BOUND_MAX_D = 16;
 // list mode (list != nullptr): the items list_base + list[q] for q < *list_count
 // (n_items bounds the grid)
+// cmom (may be null; 64 < d <= 128): K x d (d + 1) / 2 doubles of scratch for
+// the clusters' summed scatter matrices, rebuilt by the call
 hipError_t launch_logml_gauss(int n_items, const LogmlItem* items, int d, NiwPriorDev prior,
                               double logdet_psi, const long long* counts, const double* moments,
                               double* scratch, double* out, int* err, hipStream_t s, const int* list = nullptr,
-                              const int* list_count = nullptr, int list_base = 0);
+                              const int* list_count = nullptr, int list_base = 0, double* cmom = nullptr,
+                              int K = 0);
 // the merge bound: accept[p] = 0 for the pairs it rejects, the others listed
 // (list, *list_count) for their log marginal and k_merge_decide
 hipError_t launch_merge_prune(int n_pairs, const LogmlItem* pairs, int d, NiwPriorDev prior, double logdet_psi,

@@ -228,7 +228,8 @@ __global__ __launch_bounds__(CHOL_T) void k_logml_gauss_tile(int n_items, const 
                                                              const double* __restrict__ moments,
                                                              double* __restrict__ out, int* __restrict__ err,
                                                              const int* __restrict__ list,
-                                                             const int* __restrict__ list_count, int list_base) {
+                                                             const int* __restrict__ list_count, int list_base,
+                                                             const double* __restrict__ cmom, int K) {
   constexpr int DP = 128, T = 8, NTL = DP / T;
   __shared__ double xbar[DP];
   __shared__ __align__(16) double pan[T][DP];  // pan[c][row] = L[row][8 jt + c] below the diagonal tile
@@ -270,6 +271,17 @@ __global__ __launch_bounds__(CHOL_T) void k_logml_gauss_tile(int n_items, const 
     TC = u;
   }
   const bool owner = tid < TILE_T;
+  // whole clusters among the item's segments (2 k, 2 k + 1): their summed scatter
+  // with Psi / 2 comes precomputed in cmom[k] (one load instead of two or three)
+  auto whole = [&](int q) {
+    const int a0 = item.seg[q], a1 = item.seg[q + 1];
+    return (cmom && a0 >= 0 && (a0 & 1) == 0 && a1 == a0 + 1 && a0 / 2 < K) ? a0 / 2 : -1;
+  };
+  const int ca = whole(0), cb = item.seg[2] >= 0 ? whole(2) : -1;
+  // pair of whole clusters: Psi + S = cmom[ca] + cmom[cb]; one whole cluster: cmom[ca]
+  // plus Psi / 2 (a bound item wants Psi / 2: cmom[ca] alone)
+  const bool use_c = ca >= 0 && (item.seg[2] < 0 || cb >= 0);
+  const double wrest = bound ? 0.0 : 0.5;
   double a[T][T];
 #pragma unroll
   for (int r = 0; r < T; ++r)
@@ -280,11 +292,18 @@ __global__ __launch_bounds__(CHOL_T) void k_logml_gauss_tile(int n_items, const 
       if (owner && k <= i) {
         if (i < d) {
           const int lo = k, hi = i;  // k <= i: packed upper-triangle entry (k, i)
-          double S = 0.0;
-          for (int q = 0; q < 4; ++q)
-            if (item.seg[q] >= 0) S += moments[(size_t)item.seg[q] * E + d + tri_index(lo, hi, d)];
           const double xi = xbar[i], xk = xbar[k];
-          v = wpsi * prior.psi[i * d + k] + (S - n * xi * xk) + wmean * (xi - prior.m[i]) * (xk - prior.m[k]);
+          if (use_c) {
+            const size_t ti = (size_t)tri_index(lo, hi, d);
+            const double pc = cmom[(size_t)ca * (E - d) + ti] +
+                              (cb >= 0 ? cmom[(size_t)cb * (E - d) + ti] : wrest * prior.psi[i * d + k]);
+            v = (pc - n * xi * xk) + wmean * (xi - prior.m[i]) * (xk - prior.m[k]);
+          } else {
+            double S = 0.0;
+            for (int q = 0; q < 4; ++q)
+              if (item.seg[q] >= 0) S += moments[(size_t)item.seg[q] * E + d + tri_index(lo, hi, d)];
+            v = wpsi * prior.psi[i * d + k] + (S - n * xi * xk) + wmean * (xi - prior.m[i]) * (xk - prior.m[k]);
+          }
         } else {
           v = i == k ? 1.0 : 0.0;  // the identity padding
         }
@@ -614,9 +633,29 @@ hipError_t launch_zero64(void* p, size_t n_words, hipStream_t s) {
   return hipGetLastError();
 }
 
+// cmom[k] = Psi / 2 + S_2k + S_2k+1 (the packed upper triangle of cluster k's
+// scatter matrix plus half the prior's), for the tile kernel's whole-cluster items
+__global__ void k_cluster_scatter(int K, int d, NiwPriorDev prior, const double* __restrict__ moments,
+                                  double* __restrict__ cmom) {
+  const int E = d + d * (d + 1) / 2, P = E - d;
+  const int k = blockIdx.y;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < P; t += gridDim.x * blockDim.x) {
+    // t = tri_index(a, b, d), a <= b
+    int a = 0, rem = t;
+    while (rem >= d - a) {
+      rem -= d - a;
+      ++a;
+    }
+    const int b = a + rem;
+    cmom[(size_t)k * P + t] = 0.5 * prior.psi[a * d + b] + moments[(size_t)(2 * k) * E + d + t] +
+                              moments[(size_t)(2 * k + 1) * E + d + t];
+  }
+}
+
 hipError_t launch_logml_gauss(int n_items, const LogmlItem* items, int d, NiwPriorDev prior, double logdet_psi,
                               const long long* counts, const double* moments, double* scratch, double* out,
-                              int* err, hipStream_t s, const int* list, const int* list_count, int list_base) {
+                              int* err, hipStream_t s, const int* list, const int* list_count, int list_base,
+                              double* cmom, int K) {
   if (n_items == 0) return hipSuccess;
   const dim3 wg((n_items + BLOCK / 64 - 1) / (BLOCK / 64));
 #define DPMM_LOGML_WAVE(DD)                                                                                         \
@@ -634,8 +673,12 @@ hipError_t launch_logml_gauss(int n_items, const LogmlItem* items, int d, NiwPri
   }
 #undef DPMM_LOGML_WAVE
   if (d <= 128) {
+    if (cmom && K > 0) {
+      const int P = d * (d + 1) / 2;
+      hipLaunchKernelGGL(k_cluster_scatter, dim3((P + 255) / 256, K), dim3(256), 0, s, K, d, prior, moments, cmom);
+    }
     hipLaunchKernelGGL(k_logml_gauss_tile, dim3(n_items), dim3(CHOL_T), 0, s, n_items, items, d, prior, logdet_psi,
-                       counts, moments, out, err, list, list_count, list_base);
+                       counts, moments, out, err, list, list_count, list_base, cmom, cmom ? K : 0);
     return hipGetLastError();
   }
   const size_t lds = d <= LOGML_LDS_MAX_D ? (size_t)d * d * sizeof(double) : 0;
