@@ -495,7 +495,7 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
     ok = ok && chk(c->alloc(&c->d_sigma, 3 * (size_t)km * d * d));
     c->scratch_slots = std::max(3 * km, 256);
     ok = ok && chk(c->alloc(&c->d_scratch, (size_t)c->scratch_slots * NIW_SCRATCH(d)));
-    if (d > 64 && d <= 128) ok = ok && chk(c->alloc(&c->d_cmom, (size_t)km * (d * (d + 1) / 2)));
+    if (d > 64 && d <= 128) ok = ok && chk(c->alloc(&c->d_cmom, ((size_t)km + 1) * CMOM_TILE_ENTRIES));
     if (cfg->precision != DPMM_FP32) {
       ok = ok && chk(c->alloc(&c->d_whi, (size_t)km * d * d));
       ok = ok && chk(c->alloc(&c->d_nflag, 2));

@@ -210,8 +210,9 @@ constexpr int LOGML_BOUND = -3;
 constexpr int MERGE_BOUND_MAX_D = 16;
 // list mode (list != nullptr): the items list_base + list[q] for q < *list_count
 // (n_items bounds the grid)
-// cmom (may be null; 64 < d <= 128): K x d (d + 1) / 2 doubles of scratch for
-// the clusters' summed scatter matrices, rebuilt by the call
+// cmom (may be null; 64 < d <= 128): (K + 1) x CMOM_TILE_ENTRIES doubles of
+// scratch for the clusters' summed scatter matrices, rebuilt by the call
+constexpr int CMOM_TILE_ENTRIES = 136 * 64;
 hipError_t launch_logml_gauss(int n_items, const LogmlItem* items, int d, NiwPriorDev prior,
                               double logdet_psi, const long long* counts, const double* moments,
                               double* scratch, double* out, int* err, hipStream_t s, const int* list = nullptr,

@@ -272,16 +272,18 @@ __global__ __launch_bounds__(CHOL_T) void k_logml_gauss_tile(int n_items, const 
   }
   const bool owner = tid < TILE_T;
   // whole clusters among the item's segments (2 k, 2 k + 1): their summed scatter
-  // with Psi / 2 comes precomputed in cmom[k] (one load instead of two or three)
+  // with Psi / 2 comes precomputed in cmom[k], this thread's tile contiguous
   auto whole = [&](int q) {
     const int a0 = item.seg[q], a1 = item.seg[q + 1];
     return (cmom && a0 >= 0 && (a0 & 1) == 0 && a1 == a0 + 1 && a0 / 2 < K) ? a0 / 2 : -1;
   };
   const int ca = whole(0), cb = item.seg[2] >= 0 ? whole(2) : -1;
   // pair of whole clusters: Psi + S = cmom[ca] + cmom[cb]; one whole cluster: cmom[ca]
-  // plus Psi / 2 (a bound item wants Psi / 2: cmom[ca] alone)
+  // plus Psi / 2 (slot K); a bound item wants Psi / 2 + S: cmom[ca] alone
   const bool use_c = ca >= 0 && (item.seg[2] < 0 || cb >= 0);
-  const double wrest = bound ? 0.0 : 0.5;
+  const double* tca = use_c ? cmom + ((size_t)ca * TILE_T + (owner ? tid : 0)) * 64 : nullptr;
+  const double* tcb = use_c ? cmom + ((size_t)(cb >= 0 ? cb : K) * TILE_T + (owner ? tid : 0)) * 64 : nullptr;
+  const double wrest = (cb >= 0 || !bound) ? 1.0 : 0.0;
   double a[T][T];
 #pragma unroll
   for (int r = 0; r < T; ++r)
@@ -294,9 +296,7 @@ __global__ __launch_bounds__(CHOL_T) void k_logml_gauss_tile(int n_items, const 
           const int lo = k, hi = i;  // k <= i: packed upper-triangle entry (k, i)
           const double xi = xbar[i], xk = xbar[k];
           if (use_c) {
-            const size_t ti = (size_t)tri_index(lo, hi, d);
-            const double pc = cmom[(size_t)ca * (E - d) + ti] +
-                              (cb >= 0 ? cmom[(size_t)cb * (E - d) + ti] : wrest * prior.psi[i * d + k]);
+            const double pc = tca[T * r + c] + wrest * tcb[T * r + c];
             v = (pc - n * xi * xk) + wmean * (xi - prior.m[i]) * (xk - prior.m[k]);
           } else {
             double S = 0.0;
@@ -633,22 +633,30 @@ hipError_t launch_zero64(void* p, size_t n_words, hipStream_t s) {
   return hipGetLastError();
 }
 
-// cmom[k] = Psi / 2 + S_2k + S_2k+1 (the packed upper triangle of cluster k's
-// scatter matrix plus half the prior's), for the tile kernel's whole-cluster items
+// cmom[k] = Psi / 2 + S_2k + S_2k+1, cluster k's scatter matrix plus half the
+// prior's, in the tile kernel's register layout ([136 lower 8 x 8 tiles][8][8],
+// tile u held by thread u, zero outside the lower d x d triangle), and in slot K
+// Psi / 2 alone: a thread of the tile kernel reads its 64 entries contiguously.
 __global__ void k_cluster_scatter(int K, int d, NiwPriorDev prior, const double* __restrict__ moments,
                                   double* __restrict__ cmom) {
-  const int E = d + d * (d + 1) / 2, P = E - d;
-  const int k = blockIdx.y;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < P; t += gridDim.x * blockDim.x) {
-    // t = tri_index(a, b, d), a <= b
-    int a = 0, rem = t;
-    while (rem >= d - a) {
-      rem -= d - a;
-      ++a;
+  const int E = d + d * (d + 1) / 2;
+  const int k = blockIdx.y;  // K: Psi / 2 alone
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < CMOM_TILE_ENTRIES; e += gridDim.x * blockDim.x) {
+    int u = e >> 6, TR = 0;
+    while (u > TR) {
+      u -= TR + 1;
+      ++TR;
     }
-    const int b = a + rem;
-    cmom[(size_t)k * P + t] = 0.5 * prior.psi[a * d + b] + moments[(size_t)(2 * k) * E + d + t] +
-                              moments[(size_t)(2 * k + 1) * E + d + t];
+    const int i = 8 * TR + ((e >> 3) & 7), j = 8 * u + (e & 7);
+    double v = 0.0;
+    if (j <= i && i < d) {
+      v = 0.5 * prior.psi[i * d + j];
+      if (k < K) {
+        const int t = tri_index(j, i, d);
+        v += moments[(size_t)(2 * k) * E + d + t] + moments[(size_t)(2 * k + 1) * E + d + t];
+      }
+    }
+    cmom[(size_t)k * CMOM_TILE_ENTRIES + e] = v;
   }
 }
 
@@ -673,10 +681,9 @@ hipError_t launch_logml_gauss(int n_items, const LogmlItem* items, int d, NiwPri
   }
 #undef DPMM_LOGML_WAVE
   if (d <= 128) {
-    if (cmom && K > 0) {
-      const int P = d * (d + 1) / 2;
-      hipLaunchKernelGGL(k_cluster_scatter, dim3((P + 255) / 256, K), dim3(256), 0, s, K, d, prior, moments, cmom);
-    }
+    if (cmom && K > 0)
+      hipLaunchKernelGGL(k_cluster_scatter, dim3((CMOM_TILE_ENTRIES + 255) / 256, K + 1), dim3(256), 0, s, K, d, prior,
+                         moments, cmom);
     hipLaunchKernelGGL(k_logml_gauss_tile, dim3(n_items), dim3(CHOL_T), 0, s, n_items, items, d, prior, logdet_psi,
                        counts, moments, out, err, list, list_count, list_base, cmom, cmom ? K : 0);
     return hipGetLastError();
