@@ -598,8 +598,8 @@ constexpr float UC_GAMMA2 = 1.0f / 16384.0f;
 constexpr float UC_EPSS = 1.0f / 65536.0f;
 
 // Main pass for d = 64, 128 in BF16, cluster-stationary and uncentred: the
-// workgroup's rows, PTS (512, or 256 when the LDS counters of a large K leave no
-// room) per step, are centred once per step on the common centre c,
+// workgroup's rows, PTS per step (512: with the counters of up to 4096 clusters
+// they fit in LDS; 256 otherwise), are centred once per step on the common centre c,
 // rounded to BF16 and stored in LDS (rows padded by 16 bytes, so that the
 // sixteen-byte reads of 32 rows fall on distinct banks), with each row's norm
 // ||x'||.  Each of the eight waves takes every eighth cluster and holds its

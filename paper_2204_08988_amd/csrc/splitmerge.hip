@@ -343,23 +343,21 @@ __global__ __launch_bounds__(CHOL_T) void k_logml_gauss_tile(int n_items, const 
     __syncthreads();
     // the tiles below it: A_ij L_jj^-T, row by row forward substitution
     if (owner && TC == jt && TR > jt) {
-      double L[T][T];
+      // column by column: row c of L_jj (at most 8 values) is all a column needs
 #pragma unroll
-      for (int c = 0; c < T; ++c)
+      for (int c = 0; c < T; ++c) {
+        double lr[T];
 #pragma unroll
-        for (int r = c; r < T; ++r) L[r][c] = dg[c][r];
-      double inv[T];
+        for (int c2 = 0; c2 < c; ++c2) lr[c2] = dg[c2][c];
+        const double ic = 1.0 / dg[c][c];
 #pragma unroll
-      for (int c = 0; c < T; ++c) inv[c] = 1.0 / L[c][c];
-#pragma unroll
-      for (int r = 0; r < T; ++r)
-#pragma unroll
-        for (int c = 0; c < T; ++c) {
+        for (int r = 0; r < T; ++r) {
           double v = a[r][c];
 #pragma unroll
-          for (int c2 = 0; c2 < c; ++c2) v = fma(-a[r][c2], L[c][c2], v);
-          a[r][c] = v * inv[c];
+          for (int c2 = 0; c2 < c; ++c2) v = fma(-a[r][c2], lr[c2], v);
+          a[r][c] = v * ic;
         }
+      }
 #pragma unroll
       for (int c = 0; c < T; ++c)
 #pragma unroll
