@@ -29,20 +29,30 @@ using score::score_rec_dyn;
 constexpr int IPT_MAX = 9;  // 2x2 work items per lane for d <= 128
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
 
-__device__ __forceinline__ int block_inclusive_scan(int v, int* buf) {
-  const int tid = threadIdx.x;
+// Inclusive scan over a workgroup of `NT` threads (integer: exact in any
+// order), left in buf (NT ints) as well: shuffles within each wave, then the
+// preceding waves' totals (staged in buf's first entries); three barriers.
+template <int NT>
+__device__ __forceinline__ int block_inclusive_scan_n(int v, int* buf) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(v, o);
+    if (lane >= o) v += u;
+  }
+  if (lane == 63) buf[w] = v;
+  __syncthreads();
+  int add = 0;
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) add += q < w ? buf[q] : 0;
+  v += add;
+  __syncthreads();  // every wave has read the totals
   buf[tid] = v;
   __syncthreads();
-  for (int off = 1; off < BLOCK; off <<= 1) {
-    const int add = tid >= off ? buf[tid - off] : 0;
-    __syncthreads();
-    buf[tid] += add;
-    __syncthreads();
-  }
-  const int r = buf[tid];
-  __syncthreads();
-  return r;
+  return v;
 }
+
+__device__ __forceinline__ int block_inclusive_scan(int v, int* buf) { return block_inclusive_scan_n<BLOCK>(v, buf); }
 
 }  // namespace
 
@@ -741,20 +751,7 @@ size_t sub_stats_lds(int d, int TR, bool generic) {
 constexpr int BIG_THREADS = 512;  // 8 waves: 0-3 own the left segment, 4-7 the right
 constexpr int BIG_ROWS = 256;     // sorted rows per tile
 
-__device__ __forceinline__ int block_inclusive_scan_big(int v, int* buf) {
-  const int tid = threadIdx.x;
-  buf[tid] = v;
-  __syncthreads();
-  for (int off = 1; off < BIG_THREADS; off <<= 1) {
-    const int add = tid >= off ? buf[tid - off] : 0;
-    __syncthreads();
-    buf[tid] += add;
-    __syncthreads();
-  }
-  const int r = buf[tid];
-  __syncthreads();
-  return r;
-}
+__device__ __forceinline__ int block_inclusive_scan_big(int v, int* buf) { return block_inclusive_scan_n<BIG_THREADS>(v, buf); }
 
 // Sub-label draw of sorted rows on the FP32 matrix cores (d = 32, 64, 128), Sec. 4.1
 // step (f): the scores of the two sub-clusters of the row's cluster, from
