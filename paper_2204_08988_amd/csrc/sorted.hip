@@ -749,7 +749,9 @@ size_t sub_stats_lds(int d, int TR, bool generic) {
 
 
 constexpr int BIG_THREADS = 512;  // 8 waves: 0-3 own the left segment, 4-7 the right
-constexpr int BIG_ROWS = 256;     // sorted rows per tile
+// sorted rows per tile: 64 KB of FP32 rows, so that two tiles fit in LDS
+constexpr int big_rows_of(int d) { return 16384 / d; }
+typedef __attribute__((address_space(3))) void lds_void;
 
 __device__ __forceinline__ int block_inclusive_scan_big(int v, int* buf) { return block_inclusive_scan_n<BIG_THREADS>(v, buf); }
 
@@ -939,43 +941,92 @@ __device__ __forceinline__ void big_mfmas(f64x4 (&acc)[TPW], const double (&xv)[
    ...);
 }
 
+// Column held by lane i (of 16) for column block I in the statistics tile:
+// lane i reads its D / 16 columns as one contiguous piece of the row (one or
+// two 16-byte LDS reads), so block I is the column set {col(I, i)}.  At
+// d = 128 the two halves of a lane's piece are read in an order that depends
+// on bits 2 and 3 of i, so that any 8 or 16 consecutive lanes reading one row
+// hit distinct LDS banks.
+template <int D>
+__device__ __forceinline__ int big_col(int blk, int i) {
+  if constexpr (D == 128) {
+    const int s = ((i >> 2) ^ (i >> 3)) & 1;
+    return 8 * i + (blk ^ (4 * s));
+  } else {
+    return 4 * i + blk;
+  }
+}
+
 // Rows [st, st + cnt) of a tile's order list, four at a time, into the
 // accumulators of wave quarter WQ (upper blocks WQ, WQ + 4, ...): each step
-// reads the row's D / 16 column blocks once and feeds every block from them
-// (a lane past the segment reads the tile's zero row).
-template <int D, int WQ, int TPW>
+// reads the lane's piece of its row once and feeds every block from it (a
+// lane past the segment reads the zero row R).  rd0 / rd1: the lane's two
+// 16-byte offsets in a row (rd1 unused at d = 64).
+template <int D, int WQ, int R, int TPW>
 __device__ __forceinline__ void big_rows(f64x4 (&acc)[TPW], double (&sx)[D / 64], const float* __restrict__ xs,
-                                         const int* __restrict__ order, int st, int cnt, int lane, int zero_row) {
-  constexpr int LD = D + 1, NB = D / 16;
-  for (int g = 0; g < cnt; g += 4) {
-    const int p = g + (lane >> 4);
-    const int ro = (p < cnt ? order[st + p] : zero_row) * LD + (lane & 15);
+                                         const int* __restrict__ order, int st, int cnt, int lane, int rd0, int rd1) {
+  constexpr int NB = D / 16;
+  const int p = lane >> 4;
+  // software pipeline over two register sets: the row pieces of step g + 4 and
+  // the row index of step g + 8 are read while step g's matrix-core work runs
+  auto row_of = [&](int g) __attribute__((always_inline)) { return g + p < cnt ? order[st + g + p] : R; };
+  auto fetch = [&](int o, float4& a, float4& b) __attribute__((always_inline)) {
+    const float* rp = xs + o * D;
+    a = *reinterpret_cast<const float4*>(rp + rd0);
+    if constexpr (NB == 8) b = *reinterpret_cast<const float4*>(rp + rd1);
+  };
+  auto step = [&](const float4& a, const float4& b) __attribute__((always_inline)) {
     double xv[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) xv[b] = (double)xs[ro + 16 * b];
+    xv[0] = (double)a.x;
+    xv[1] = (double)a.y;
+    xv[2] = (double)a.z;
+    xv[3] = (double)a.w;
+    if constexpr (NB == 8) {
+      xv[4] = (double)b.x;
+      xv[5] = (double)b.y;
+      xv[6] = (double)b.z;
+      xv[7] = (double)b.w;
+    }
     big_mfmas<NB, WQ>(acc, xv, std::make_integer_sequence<int, TPW>{});
     // sum x over the quarter's column blocks WQ, WQ + 4, ...: lane l adds
-    // column 16 b + l % 16 of row g + l / 16
+    // column col(block, l % 16) of its row
 #pragma unroll
     for (int j = 0; j < D / 64; ++j) sx[j] += xv[WQ + 4 * j];
+  };
+  float4 a0, b0 = make_float4(0.f, 0.f, 0.f, 0.f), a1, b1 = make_float4(0.f, 0.f, 0.f, 0.f);
+  int o0 = row_of(0), o1 = cnt > 4 ? row_of(4) : R;
+  fetch(o0, a0, b0);
+  for (int g = 0; g < cnt; g += 8) {
+    if (g + 4 < cnt) fetch(o1, a1, b1);
+    if (g + 8 < cnt) o0 = row_of(g + 8);
+    step(a0, b0);
+    if (g + 4 >= cnt) break;
+    if (g + 8 < cnt) fetch(o0, a0, b0);
+    if (g + 12 < cnt) o1 = row_of(g + 12);
+    step(a1, b1);
   }
 }
 
 // Statistics for d in {64, 128} over the cluster-sorted order (the sub-labels
-// are drawn before, by k_sub_labels_mfma), with sum x x^T on the FP64 matrix
-// cores.  A workgroup of 8 waves walks a contiguous range of tiles of BIG_ROWS
-// sorted rows:
-//   (1) the tile's rows are gathered into LDS (16-byte row pieces);
-//   (2) thread r < BIG_ROWS reads row r's sub-label;
-//   (3) rows are grouped by segment (run of a cluster, sub-label), each
+// are drawn before, by the sub-label kernels), with sum x x^T on the FP64
+// matrix cores.  A workgroup of 8 waves walks a contiguous range of tiles of
+// big_rows_of(D) sorted rows (64 KB of rows each), two tiles' rows in LDS:
+//   (1) the next tile's rows are copied into the other LDS buffer by LDS DMA
+//       (global_load_lds, 16 bytes per lane, no registers) while this tile's
+//       matrix-core work runs; its point indices, clusters and sub-labels are
+//       loaded into registers at the same time;
+//   (2) rows are grouped by segment (run of a cluster, sub-label), each
 //       segment keeping the rows' sorted order (ranks from one block scan);
-//   (4) per segment, four rows at a time, v_mfma_f64_16x16x4_f64 adds
-//       X_I^T X_J to the upper 16 x 16 blocks (I, J) of sum x x^T: the left
-//       segment belongs to waves 0-3, the right to waves 4-7, and a wave owns
-//       blocks w, w + 4, ... (FP32 inputs are exact in FP64); from the same
-//       registers it also sums x over column blocks w, w + 4, ... in FP64.
-// Each wave carries its segment of the current cluster across tiles.  Slot
-// mode (part != nullptr): a cluster that lies inside the workgroup's rows is
+//   (3) per segment, four rows at a time, v_mfma_f64_16x16x4_f64 adds
+//       X_I^T X_J to the upper 16 x 16 blocks (I, J) of sum x x^T (column
+//       blocks as big_col gives them): the left segment belongs to waves 0-3,
+//       the right to waves 4-7, and a wave owns blocks w, w + 4, ... (FP32
+//       inputs are exact in FP64); from the same registers it also sums x over
+//       its column blocks in FP64.
+// The only barriers are those of the grouping, whose wait for all memory
+// operations also lands the next tile's DMA issued one tile earlier.  Each
+// wave carries its segment of the current cluster across tiles.  Slot mode
+// (part != nullptr): a cluster that lies inside the workgroup's rows is
 // written to its final place, the workgroup's first and last clusters that
 // reach beyond them to partial slots 2 g and 2 g + 1 ([2][1 + E] each) that
 // k_sub_stats_fix adds in a fixed order: no float atomics, so the sums do not
@@ -992,48 +1043,59 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
                                                                const int* __restrict__ cstart,
                                                                const int* __restrict__ ctot, int kbase,
                                                                double* __restrict__ part) {
-  constexpr int LD = D + 1;  // odd row stride
+  constexpr int R = big_rows_of(D);
   constexpr int NB = D / 16, NT = NB * (NB + 1) / 2, TPW = (NT + 3) / 4;
   constexpr int E = D + D * (D + 1) / 2;
-  constexpr int SB = D / 64;  // column blocks of sum x per wave
-  extern __shared__ float xs[];  // [BIG_ROWS + 1][LD], the last row zero
-  __shared__ int order[BIG_ROWS], rk[BIG_ROWS], buf[BIG_THREADS];
-  __shared__ int lcount[2 * BIG_ROWS], lstart[2 * BIG_ROWS];
-  __shared__ int rstart[BIG_ROWS], ostart[BIG_ROWS], rcl[BIG_ROWS];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int SB = D / 64;       // column blocks of sum x per wave
+  constexpr int C4 = D / 4;        // 16-byte pieces per row
+  constexpr int RPI = 64 / C4;     // rows per wave DMA instruction
+  constexpr int NI = R / RPI / 8;  // DMA instructions per wave and tile
+  static_assert(NI * RPI * 8 == R, "tile rows split evenly over the waves' DMA");
+  // rows of two tiles, each followed by a zero row (read by lanes past a
+  // segment).  Two arrays, and each tile's array fixed at compile time: the
+  // compiler then knows that the rows a tile reads are not the ones its DMA
+  // writes, and does not wait for the DMA before those reads.
+  __shared__ float xa[(R + 1) * D], xb[(R + 1) * D];
+  __shared__ int order[R], rk[R], buf[BIG_THREADS];
+  __shared__ int lcount[2 * R], lstart[2 * R];
+  __shared__ int rstart[R], ostart[R], rcl[R];
+  __shared__ int nperm[2][R];  // point indices of the tiles whose rows are in flight
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int side = wave >> 2, wq = wave & 3;  // segment (0 left, 1 right), quarter
-  int bI[TPW], bJ[TPW];
-#pragma unroll
-  for (int j = 0; j < TPW; ++j) {
-    int u = wq + 4 * j, a = 0;
-    bI[j] = -1;
-    bJ[j] = -1;
-    if (u < NT) {
-      while (u >= NB - a) {
-        u -= NB - a;
-        ++a;
-      }
-      bI[j] = a;
-      bJ[j] = a + u;
+  int rd0, rd1;
+  {
+    const int i = lane & 15;
+    if constexpr (D == 128) {
+      const int s = ((i >> 2) ^ (i >> 3)) & 1;
+      rd0 = 8 * i + 4 * s;
+      rd1 = 8 * i + 4 * (1 - s);
+    } else {
+      rd0 = 4 * i;
+      rd1 = rd0;
     }
   }
-  const long long tiles = (n_sorted + BIG_ROWS - 1) / BIG_ROWS;
+  const long long tiles = (n_sorted + R - 1) / R;
   const long long tb = (long long)blockIdx.x * tpb;
   const long long te = tb + tpb < tiles ? tb + tpb : tiles;
-  const long long r_begin = tb * BIG_ROWS;
-  const long long r_end = te * BIG_ROWS < n_sorted ? te * BIG_ROWS : n_sorted;
+  const int nt = (int)(te - tb);
+  const long long r_begin = tb * R;
+  const long long r_end = te * R < n_sorted ? te * R : n_sorted;
+  auto tile_rows = [&](int lt) __attribute__((always_inline)) -> int {
+    const long long b = (tb + lt) * R;
+    return (int)(n_sorted - b < R ? n_sorted - b : R);
+  };
   f64x4 acc[TPW];
   double sx[SB];
   long long cnt_seg = 0;
   int cur_k = -1, k_first = -1;
-  auto zero_acc = [&]() {
+  auto zero_acc = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int j = 0; j < TPW; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < SB; ++j) sx[j] = 0.0;
     cnt_seg = 0;
   };
-  auto flush = [&]() {
+  auto flush = [&]() __attribute__((always_inline)) {
     if (cur_k < 0) return;
     const int seg = 2 * cur_k + side;
     bool atomic = part == nullptr;
@@ -1053,18 +1115,27 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
     }
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
-      if (bI[j] < 0) continue;
+      // block (bI, bJ) of accumulator j: upper block wq + 4 j, row-major over I <= J
+      int u = wq + 4 * j, bI = 0;
+      if (u >= NT) continue;
+      while (u >= NB - bI) {
+        u -= NB - bI;
+        ++bI;
+      }
+      const int bJ = bI + u;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         // accumulator element e of lane l is row l / 16 + 4 e, column l % 16
-        const int a = 16 * bI[j] + (lane >> 4) + 4 * e, b = 16 * bJ[j] + (lane & 15);
-        if (a <= b) {
-          double* dst = &M[D + a * D - (a * (a - 1)) / 2 + (b - a)];
-          if (atomic)
-            atomicAdd(dst, acc[j][e]);
-          else
-            *dst = acc[j][e];
-        }
+        // of block (I, J): the pair of columns col(I, row), col(J, column)
+        const int ra = (lane >> 4) + 4 * e, rb = lane & 15;
+        if (bI == bJ && ra > rb) continue;  // a diagonal block holds both orders
+        const int c1 = big_col<D>(bI, ra), c2 = big_col<D>(bJ, rb);
+        const int a = c1 < c2 ? c1 : c2, b = c1 < c2 ? c2 : c1;
+        double* dst = &M[D + a * D - (a * (a - 1)) / 2 + (b - a)];
+        if (atomic)
+          atomicAdd(dst, acc[j][e]);
+        else
+          *dst = acc[j][e];
       }
     }
 #pragma unroll
@@ -1074,10 +1145,11 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
       v += __shfl_xor(v, 16);
       v += __shfl_xor(v, 32);
       if (lane < 16) {
+        double* dst = &M[big_col<D>(wq + 4 * j, lane)];
         if (atomic)
-          atomicAdd(&M[16 * (wq + 4 * j) + lane], v);
+          atomicAdd(dst, v);
         else
-          M[16 * (wq + 4 * j) + lane] = v;
+          *dst = v;
       }
     }
     if (wq == 0 && lane == 0) {
@@ -1089,60 +1161,68 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
         *Cd = (double)cnt_seg;
     }
   };
+  // LDS DMA of tile lt's rows into dst, the point indices from nperm[lt % 2]
+  auto issue_rows = [&](int lt, float* dst) __attribute__((always_inline)) {
+    const int rows = tile_rows(lt);
+    const int* np = nperm[lt & 1];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      // rows past the tile's end copy its first row (never read): no branches,
+      // so the compiler's count of loads in flight stays exact
+      const int r0 = (wave * NI + i) * RPI;
+      const int r = r0 + lane / C4;
+      __builtin_amdgcn_global_load_lds((const void*)(x + (size_t)np[r < rows ? r : 0] * D + 4 * (lane % C4)),
+                                       (lds_void*)(dst + r0 * D), 16, 0, 0);
+    }
+  };
   zero_acc();
-  // row BIG_ROWS of the tile buffer stays zero (read by lanes past a segment)
-  for (int c = tid; c < LD; c += BIG_THREADS) xs[BIG_ROWS * LD + c] = 0.0f;
-  for (long long tile = tb; tile < te; ++tile) {
-    const long long base = tile * BIG_ROWS;
-    const int rows = (int)(n_sorted - base < BIG_ROWS ? n_sorted - base : BIG_ROWS);
-    const bool valid = tid < rows;
-    __syncthreads();  // the previous tile's LDS reads are done
-    // ---- (1) gather the rows
-    int my_i = 0, k = -1;
-    if (valid) {
-      my_i = perm[base + tid];
-      k = zrow ? zrow[base + tid] : z[my_i];
-      rk[tid] = k;
-      order[tid] = my_i;
+  // (k, zb: cluster and sub-label of row tid of the tile being grouped, loaded a
+  // tile ahead and first used after the barrier that lands them)
+  int k = -1;
+  unsigned char zb = 0;
+  if (nt > 0) {
+    if (tid < tile_rows(0)) nperm[0][tid] = perm[r_begin + tid];
+    for (int c = tid; c < D; c += BIG_THREADS) {
+      xa[R * D + c] = 0.0f;
+      xb[R * D + c] = 0.0f;
     }
-    for (int q = tid; q < 2 * BIG_ROWS; q += BIG_THREADS) lcount[q] = 0;
     __syncthreads();
-    {
-      // D / 4 lanes read a row in 16-byte pieces; all of a thread's loads are in
-      // flight before the first LDS store
-      constexpr int C4 = D / 4, RPP = BIG_THREADS / C4, NP = BIG_ROWS / RPP;
-      const int c4 = tid % C4, r0 = tid / C4;
-      float4 v[NP];
-#pragma unroll
-      for (int j = 0; j < NP; ++j) {
-        const int r = r0 + j * RPP;
-        v[j] = r < rows ? reinterpret_cast<const float4*>(x + (size_t)order[r] * D)[c4]
-                        : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-#pragma unroll
-      for (int j = 0; j < NP; ++j) {
-        float* dst = xs + (r0 + j * RPP) * LD + 4 * c4;
-        dst[0] = v[j].x;
-        dst[1] = v[j].y;
-        dst[2] = v[j].z;
-        dst[3] = v[j].w;
-      }
-    }
-    // ---- (2) sub-label of row tid
-    const int zs = valid && zsub[my_i] ? 1 : 0;
-    // ---- (3) group rows by segment: run of the cluster (rows are sorted by
+    const int r = tid < tile_rows(0) ? tid : 0;
+    const int mi = nperm[0][r];
+    k = zrow ? zrow[r_begin + r] : z[mi];
+    zb = zsub[mi];
+    issue_rows(0, xa);
+    if (nt > 1 && tid < tile_rows(1)) nperm[1][tid] = perm[r_begin + R + tid];
+  }
+  // one tile; its rows in xa (B = 0) or xb (B = 1), the next tile's DMA into the other
+  auto tile_step = [&](auto bsel, auto wqc, int lt) __attribute__((always_inline)) {
+    constexpr int B = decltype(bsel)::value;
+    constexpr int WQ = decltype(wqc)::value;
+    const float* tx = B ? xb : xa;
+    float* nx = B ? xa : xb;
+    const int rows = tile_rows(lt);
+    const bool valid = tid < rows;
+    // tile lt's rows and metadata have landed (the barrier waits for every memory
+    // operation), the previous tile's LDS reads are done, nperm[(lt + 1) % 2] is visible
+    __syncthreads();
+    const int zs = zb ? 1 : 0;
+    if (valid) rk[tid] = k;
+    for (int q = tid; q < 2 * R; q += BIG_THREADS) lcount[q] = 0;
+    __syncthreads();
+    // ---- (2) group rows by segment: run of the cluster (rows are sorted by
     // z), then sub-label.  One scan gives the run of each row (high half) and
-    // the right rows up to it (low half; both counts are <= BIG_ROWS)
+    // the right rows up to it (low half; both counts are <= R)
+    const int zsv = valid ? zs : 0;
     const int flag = (valid && (tid == 0 || rk[tid] != rk[tid - 1])) ? 1 : 0;
-    const int sc = block_inclusive_scan_big((flag << 16) | zs, buf);
-    const int run = (sc >> 16) - 1, ones_ex = (sc & 0xFFFF) - zs;
-    const int nruns = buf[BIG_THREADS - 1] >> 16;
+    const int sc = block_inclusive_scan_big((flag << 16) | zsv, buf);
+    const int run = (sc >> 16) - 1, ones_ex = (sc & 0xFFFF) - zsv;
+    const int nruns = __builtin_amdgcn_readfirstlane(buf[BIG_THREADS - 1] >> 16);
     if (flag) {
       rstart[run] = tid;
       ostart[run] = ones_ex;
       rcl[run] = k;
     }
-    const int lid = 2 * run + zs;
+    const int lid = 2 * run + zsv;
     if (valid) atomicAdd(&lcount[lid], 1);  // integer counts: exact in any order
     __syncthreads();
     if (tid == 0) {
@@ -1156,13 +1236,25 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
     if (valid) {
       // rank among the run's rows of the same sub-label, in sorted order
       const int ones_run = ones_ex - ostart[run];
-      const int rank = zs ? ones_run : (tid - rstart[run]) - ones_run;
+      const int rank = zsv ? ones_run : (tid - rstart[run]) - ones_run;
       order[lstart[lid] + rank] = tid;
     }
     __syncthreads();
-    // ---- (4) every run, in order; this wave's side of it
+    // ---- (1) the next tile: metadata into registers, the indices of the tile
+    // after it, and its rows by DMA (the registers' first use is after the next
+    // barrier, so nothing here waits for the DMA)
+    int pn = -1;
+    if (lt + 1 < nt) {
+      const int r = tid < tile_rows(lt + 1) ? tid : 0;
+      const int mi = nperm[(lt + 1) & 1][r];
+      k = zrow ? zrow[(tb + lt + 1) * R + r] : z[mi];
+      zb = zsub[mi];
+      if (lt + 2 < nt) pn = perm[(tb + lt + 2) * R + (tid < tile_rows(lt + 2) ? tid : 0)];
+      issue_rows(lt + 1, nx);
+    }
+    // ---- (3) every run, in order; this wave's side of it
     for (int j = 0; j < nruns; ++j) {
-      const int kq = rcl[j];
+      const int kq = __builtin_amdgcn_readfirstlane(rcl[j]);
       if (kq != cur_k) {
         flush();
         zero_acc();
@@ -1170,25 +1262,35 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sub_stats_big(const float* __re
         cur_k = kq;
       }
       const int q = 2 * j + side;
-      const int cnt = lcount[q];
+      const int cnt = __builtin_amdgcn_readfirstlane(lcount[q]);
       if (cnt == 0) continue;
       cnt_seg += cnt;
-      const int st = lstart[q];
-      // (the quarter as a compile-time constant: its blocks' operands come from registers)
-      switch (wq) {
-        case 0:
-          big_rows<D, 0>(acc, sx, xs, order, st, cnt, lane, BIG_ROWS);
-          break;
-        case 1:
-          big_rows<D, 1>(acc, sx, xs, order, st, cnt, lane, BIG_ROWS);
-          break;
-        case 2:
-          big_rows<D, 2>(acc, sx, xs, order, st, cnt, lane, BIG_ROWS);
-          break;
-        default:
-          big_rows<D, 3>(acc, sx, xs, order, st, cnt, lane, BIG_ROWS);
-      }
+      const int st = __builtin_amdgcn_readfirstlane(lstart[q]);
+      big_rows<D, WQ, R>(acc, sx, tx, order, st, cnt, lane, rd0, rd1);
     }
+    // nperm[lt % 2] was last read before this tile's first barrier
+    if (pn >= 0 && tid < R) nperm[lt & 1][tid] = pn;
+  };
+  // the tile loop once per quarter (a compile-time constant, so that its
+  // blocks' operands are plain registers and the accumulators stay in place)
+  auto run = [&](auto wqc) __attribute__((always_inline)) {
+    for (int lt = 0; lt < nt; lt += 2) {
+      tile_step(std::integral_constant<int, 0>{}, wqc, lt);
+      if (lt + 1 < nt) tile_step(std::integral_constant<int, 1>{}, wqc, lt + 1);
+    }
+  };
+  switch (wq) {
+    case 0:
+      run(std::integral_constant<int, 0>{});
+      break;
+    case 1:
+      run(std::integral_constant<int, 1>{});
+      break;
+    case 2:
+      run(std::integral_constant<int, 2>{});
+      break;
+    default:
+      run(std::integral_constant<int, 3>{});
   }
   flush();
 }
@@ -1285,7 +1387,7 @@ long long subw_rpw(long long n) {
 
 // tiles per workgroup of k_sub_stats_big (at most 512 workgroups at d = 64, 256 at d = 128)
 int big_tpb(int d, long long n) {
-  const long long tiles = (n + BIG_ROWS - 1) / BIG_ROWS;
+  const long long tiles = (n + big_rows_of(d) - 1) / big_rows_of(d);
   const long long gmax = d == 128 ? 256 : 512;
   const long long g = tiles < gmax ? tiles : gmax;
   return g > 0 ? (int)((tiles + g - 1) / g) : 1;
@@ -1352,19 +1454,11 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
     sample = false;
   }
   if (d == 64 || d == 128) {
-    const long long tiles = (n + BIG_ROWS - 1) / BIG_ROWS;
+    const int R = big_rows_of(d);
+    const long long tiles = (n + R - 1) / R;
     const int tpb = big_tpb(d, n);
     const unsigned grid = (unsigned)((tiles + tpb - 1) / tpb);
-    const size_t lds = (size_t)(BIG_ROWS + 1) * (d + 1) * sizeof(float);  // above 64 KB: raise the limit once
-    static bool attr_set = false;
-    if (!attr_set) {
-      const void* fns[2] = {(const void*)k_sub_stats_big<64>, (const void*)k_sub_stats_big<128>};
-      for (const void* f : fns) {
-        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 144 * 1024);
-        if (e != hipSuccess) return e;
-      }
-      attr_set = true;
-    }
+    const size_t lds = 0;  // all of its LDS is static (two tiles' rows, 129 KB)
     if (d == 64)
       hipLaunchKernelGGL(k_sub_stats_big<64>, dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z, zrow, zsub,
                          counts, moments, cstart, ctot, kbase, part);
@@ -1372,7 +1466,7 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
       hipLaunchKernelGGL(k_sub_stats_big<128>, dim3(grid), dim3(BIG_THREADS), lds, s, x, n, tpb, perm, z, zrow, zsub,
                          counts, moments, cstart, ctot, kbase, part);
     if ((e = hipGetLastError()) != hipSuccess || !part) return e;
-    hipLaunchKernelGGL(k_sub_stats_fix, fix_grid, dim3(FIX_PH * FIX_EN), 0, s, E, (long long)tpb * BIG_ROWS, cstart,
+    hipLaunchKernelGGL(k_sub_stats_fix, fix_grid, dim3(FIX_PH * FIX_EN), 0, s, E, (long long)tpb * R, cstart,
                        ctot, part, counts, moments, kbase);
     return hipGetLastError();
   }
@@ -1418,7 +1512,7 @@ size_t sub_stats_part_doubles(int d, long long n) {
     const long long rpw = subw_rpw(n);
     ranges = (n + rpw - 1) / rpw;
   } else if (d == 64 || d == 128) {
-    const long long tiles = (n + BIG_ROWS - 1) / BIG_ROWS;
+    const long long tiles = (n + big_rows_of(d) - 1) / big_rows_of(d);
     const int tpb = big_tpb(d, n);
     ranges = (tiles + tpb - 1) / tpb;
   } else {
