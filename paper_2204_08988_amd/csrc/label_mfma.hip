@@ -727,7 +727,7 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
       for (int t = 0; t < TILES; ++t) {
         const bf16x8* xr = xb + (t * 32 + col) * RB + half;
         bf16x8 b[KS];
-        float q0 = 0.0f, q1 = 0.0f;
+        float q0 = 0.0f, q1 = 0.0f, q2 = 0.0f, q3 = 0.0f;
         f32x16 acc;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -735,24 +735,26 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
           for (int ks = (mt == 0 ? 0 : TT::tiles(mt - 1)); ks < TT::tiles(mt); ++ks) b[ks] = xr[2 * ks];
           if (mt > 0) {
 #pragma unroll
-            for (int e = 0; e < 16; e += 2) {
+            for (int e = 0; e < 16; e += 4) {
               q0 = fmaf(acc[e], acc[e], q0);
               q1 = fmaf(acc[e + 1], acc[e + 1], q1);
+              q2 = fmaf(acc[e + 2], acc[e + 2], q2);
+              q3 = fmaf(acc[e + 3], acc[e + 3], q3);
             }
           }
           acc = bs[mt];
-          __builtin_amdgcn_s_setprio(1);
 #pragma unroll
           for (int ks = 0; ks < TT::tiles(mt); ++ks)
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[TT::off(mt) + ks], b[ks], acc, 0, 0, 0);
-          __builtin_amdgcn_s_setprio(0);
         }
 #pragma unroll
-        for (int e = 0; e < 16; e += 2) {
+        for (int e = 0; e < 16; e += 4) {
           q0 = fmaf(acc[e], acc[e], q0);
           q1 = fmaf(acc[e + 1], acc[e + 1], q1);
+          q2 = fmaf(acc[e + 2], acc[e + 2], q2);
+          q3 = fmaf(acc[e + 3], acc[e + 3], q3);
         }
-        float qm = q0 + q1;
+        float qm = (q0 + q1) + (q2 + q3);
         {
           const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(qm), __float_as_uint(qm), false, false);
           qm = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
