@@ -29,7 +29,7 @@ namespace {
 
 using namespace score;
 
-template <int D, bool STAGED>
+template <int D, bool STAGED, int KM>
 __global__ __launch_bounds__(BLOCK) void k_label_gauss(const float* __restrict__ x, long long n,
                                                        const float* __restrict__ packed, int K, int k_max,
                                                        uint32_t t, uint64_t seed, int* __restrict__ z,
@@ -55,9 +55,20 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss(const float* __restrict__
     for (int j = 0; j < D; ++j) xv[j] = x[i * D + j];
     Top2 t2;
     t2.init();
-    for (int k = 0; k < K; ++k) t2.push(score_rec<D>(cl + (size_t)k * S, xv), k);
-    const int zi = lazy_gumbel_max(t2, K, (uint32_t)i, t, seed,
-                                   [&](int k) { return score_rec<D>(cl + (size_t)k * S, xv); });
+    int zi;
+    if constexpr (KM > 0) {
+      // K <= KM: the scores stay in registers for the draw
+      float lk[KM];
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        lk[k] = k < K ? score_rec<D>(cl + (size_t)k * S, xv) : -INFINITY;
+        if (k < K) t2.push(lk[k], k);
+      }
+      zi = lazy_gumbel_max_regs<KM>(lk, t2, K, (uint32_t)i, t, seed);
+    } else {
+      for (int k = 0; k < K; ++k) t2.push(score_rec<D>(cl + (size_t)k * S, xv), k);
+      zi = lazy_gumbel_max(t2, K, (uint32_t)i, t, seed, [&](int k) { return score_rec<D>(cl + (size_t)k * S, xv); });
+    }
     const float* ps = sub + (size_t)(2 * zi) * S;
     const float delta = score_rec<D>(ps, xv) - score_rec<D>(ps + S, xv);
     z[i] = zi;
@@ -184,14 +195,17 @@ hipError_t launch_label_gauss(int d, const float* x, long long n, const float* p
   // the 3K score records go to LDS when they fit in 48 KB
   const size_t rec_bytes = (size_t)3 * K * gauss_rec_stride(d) * sizeof(float);
   const bool staged = rec_bytes <= 48 * 1024;
-#define DPMM_LABEL_CASE(DD)                                                                          \
-  case DD:                                                                                           \
-    if (staged)                                                                                      \
-      hipLaunchKernelGGL((k_label_gauss<DD, true>), dim3(g), dim3(BLOCK), rec_bytes, s, x, n, packed, \
-                         K, k_max, t, seed, z, zsub);                                                \
-    else                                                                                             \
-      hipLaunchKernelGGL((k_label_gauss<DD, false>), dim3(g), dim3(BLOCK), 0, s, x, n, packed, K,    \
-                         k_max, t, seed, z, zsub);                                                   \
+#define DPMM_LABEL_CASE(DD)                                                                              \
+  case DD:                                                                                               \
+    if (staged && K <= 8)                                                                                \
+      hipLaunchKernelGGL((k_label_gauss<DD, true, 8>), dim3(g), dim3(BLOCK), rec_bytes, s, x, n, packed, \
+                         K, k_max, t, seed, z, zsub);                                                    \
+    else if (staged)                                                                                     \
+      hipLaunchKernelGGL((k_label_gauss<DD, true, 0>), dim3(g), dim3(BLOCK), rec_bytes, s, x, n, packed, \
+                         K, k_max, t, seed, z, zsub);                                                    \
+    else                                                                                                 \
+      hipLaunchKernelGGL((k_label_gauss<DD, false, 0>), dim3(g), dim3(BLOCK), 0, s, x, n, packed, K,     \
+                         k_max, t, seed, z, zsub);                                                       \
     break;
   switch (d) {
     DPMM_LABEL_CASE(1)

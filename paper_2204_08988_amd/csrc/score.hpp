@@ -108,6 +108,43 @@ __device__ __forceinline__ int lazy_gumbel_max(const Top2& t2, int K, uint32_t i
   return win;
 }
 
+// The same draw for K <= KM with the K scores already in registers: the
+// candidates are the clusters within G_max - G_min of the leader (any other
+// trails the leader's perturbed score whatever the noise); their Gumbel
+// blocks are taken in increasing block order, each computed at most once
+// per wave, and the winner is the largest l_k + g_k, the smaller k on ties.
+// Clusters that lazy_gumbel_max skips cannot win, so the label is the same.
+template <int KM>
+__device__ __forceinline__ int lazy_gumbel_max_regs(const float (&l)[KM], const Top2& t2, int K, uint32_t i,
+                                                    uint32_t t, uint64_t seed) {
+  if (!(t2.m2 > t2.m1 - RGAP)) return t2.arg;
+  const float floor = t2.m1 - RGAP;
+  float best = -INFINITY;
+  int win = t2.arg;
+#pragma unroll
+  for (int b = 0; b < (KM + 3) / 4; ++b) {
+    bool need = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (4 * b + j < K && l[4 * b + j] > floor) need = true;
+    if (need) {
+      const u32x4 blk = rng_block(seed, t, i, TAG_GUMBEL, (uint32_t)b);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 4 * b + j;
+        if (k < K && l[k] > floor) {
+          const float s = l[k] + gumbel_f(word_of(blk, j));
+          if (s > best) {
+            best = s;
+            win = k;
+          }
+        }
+      }
+    }
+  }
+  return win;
+}
+
 __device__ __forceinline__ unsigned char draw_sub(float delta, uint32_t i, uint32_t t, uint64_t seed) {
   return (unsigned char)sub_label_draw(delta, seed, t, i);
 }
