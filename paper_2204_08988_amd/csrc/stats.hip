@@ -9,10 +9,11 @@
 // the same input gives the same bits whatever the timing of the waves.
 //
 // Gaussian, d <= 4 (d >= 5 and the large-K case take the cluster-sorted
-// kernels): each lane owns float64 accumulators of every segment in LDS and
-// adds its own points (a fixed grid-stride assignment); the workgroup then
-// adds its lanes by a fixed tree and writes one partial row, and a second
-// kernel adds the rows in workgroup order.
+// kernels): each lane owns float64 accumulators of every segment (in
+// registers when d <= 2 and all segments' sums fit in 72 of them, in LDS
+// otherwise) and adds its own points (a fixed grid-stride assignment); the
+// workgroup then adds its lanes by a fixed tree and writes one partial row,
+// and a second kernel adds the rows in workgroup order.
 // Multinomial: lanes over points, uint32 LDS accumulators (at most 65536
 // points per workgroup, so count entries below 65536 cannot overflow), int64
 // flush; all integer, so the result is exact and independent of the order.
@@ -95,6 +96,103 @@ __global__ __launch_bounds__(L) void k_stats_small(const float* __restrict__ x, 
   __syncthreads();
   for (int e = lane; e < NE; e += L) part[(size_t)blockIdx.x * NE + e] = acc[(size_t)e * L];
 }
+
+// d <= 2 with at most REG_VALUES sums (2K (1 + E) <= 72): every lane keeps
+// the sums of all segments in float64 registers and adds each of its points
+// to its segment's (an add under the lane mask per segment: no data-dependent
+// addressing, no LDS traffic).  Lane l of workgroup g adds the points
+// i = (g L + l) + j G L in increasing j, the next U points' loads in flight
+// while the current ones are added; then the wave's lanes by a fixed xor tree,
+// the workgroup's waves in wave order, one partial row per workgroup.
+constexpr int REG_VALUES = 72;
+constexpr int REG_L = 256;
+constexpr int REG_G = 512;  // two workgroups per CU
+
+template <int D>
+__global__ __launch_bounds__(REG_L) void k_stats_regs(const float* __restrict__ x, long long n,
+                                                      const int* __restrict__ z,
+                                                      const unsigned char* __restrict__ zsub, int K,
+                                                      double* __restrict__ part) {
+  constexpr int E1 = 1 + D + D * (D + 1) / 2;
+  constexpr int SM = REG_VALUES / E1;  // segments held
+  constexpr int U = 4;
+  __shared__ double wsum[REG_L / 64][SM * E1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nseg = 2 * K;
+  double acc[SM][E1];
+#pragma unroll
+  for (int q = 0; q < SM; ++q)
+#pragma unroll
+    for (int e = 0; e < E1; ++e) acc[q][e] = 0.0;
+  const long long stride = (long long)gridDim.x * REG_L;
+  int seg[U];
+  float xv[U][D];
+  auto load = [&](long long i0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long i = i0 + u * stride;
+      seg[u] = -1;
+#pragma unroll
+      for (int j = 0; j < D; ++j) xv[u][j] = 0.0f;
+      if (i < n) {
+        const int zi = z[i], zs = zsub[i];
+        if ((unsigned)zi < (unsigned)K && zs <= 1) seg[u] = 2 * zi + zs;
+#pragma unroll
+        for (int j = 0; j < D; ++j) xv[u][j] = x[i * D + j];
+      }
+    }
+  };
+  long long i0 = (long long)blockIdx.x * REG_L + threadIdx.x;
+  if (i0 < n) load(i0);
+  for (; i0 < n; i0 += U * stride) {
+    int cs[U];
+    float cx[U][D];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      cs[u] = seg[u];
+#pragma unroll
+      for (int j = 0; j < D; ++j) cx[u][j] = xv[u][j];
+    }
+    if (i0 + U * stride < n) load(i0 + U * stride);  // in flight while the current points are added
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      double v[E1];
+      v[0] = 1.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) v[1 + j] = (double)cx[u][j];
+      int e = 1 + D;
+#pragma unroll
+      for (int p = 0; p < D; ++p)
+#pragma unroll
+        for (int q = p; q < D; ++q, ++e) v[e] = (double)cx[u][p] * (double)cx[u][q];
+#pragma unroll
+      for (int q = 0; q < SM; ++q)
+        if (q < nseg && cs[u] == q)
+#pragma unroll
+          for (int f = 0; f < E1; ++f) acc[q][f] += v[f];
+    }
+  }
+  // the wave's lanes by a fixed xor tree, then its waves in order
+#pragma unroll
+  for (int q = 0; q < SM; ++q)
+#pragma unroll
+    for (int f = 0; f < E1; ++f) {
+      double a = acc[q][f];
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) a += __shfl_xor(a, o);
+      if (lane == 0) wsum[wave][q * E1 + f] = a;
+    }
+  __syncthreads();
+  const int NE = nseg * E1;
+  for (int e = threadIdx.x; e < NE; e += REG_L) {
+    double a = wsum[0][e];
+#pragma unroll
+    for (int w = 1; w < REG_L / 64; ++w) a += wsum[w][e];
+    part[(size_t)blockIdx.x * NE + e] = a;
+  }
+}
+
+bool stats_regs_ok(int d, int K) { return (d == 1 || d == 2) && (size_t)2 * K * (1 + d + d * (d + 1) / 2) <= REG_VALUES; }
 
 // counts[s] and moments[s][.] from the G partial rows, added in row order.
 __global__ void k_stats_small_reduce(const double* __restrict__ part, int G, int K, int E,
@@ -201,7 +299,9 @@ int stats_small_lanes(int d, int K) {
 size_t stats_small_part_doubles(int d, int K) {
   const int L = stats_small_lanes(d, K);
   if (!L) return 0;
-  return (size_t)(STATS_SMALL_LANES / L) * 2 * K * (1 + d + d * (d + 1) / 2);
+  const size_t row = (size_t)2 * K * (1 + d + d * (d + 1) / 2);
+  const size_t lds_rows = (size_t)(STATS_SMALL_LANES / L);
+  return (stats_regs_ok(d, K) && REG_G > (int)lds_rows ? (size_t)REG_G : lds_rows) * row;
 }
 
 hipError_t launch_stats_gauss(int d, const float* x, long long n, const int* z, const unsigned char* zsub,
@@ -213,6 +313,18 @@ hipError_t launch_stats_gauss(int d, const float* x, long long n, const int* z, 
     hipError_t err = launch_zero64(counts, (size_t)2 * K, s);
     if (err != hipSuccess) return err;
     return launch_zero64(moments, (size_t)2 * K * E, s);
+  }
+  if (stats_regs_ok(d, K)) {
+    if (d == 1)
+      hipLaunchKernelGGL(k_stats_regs<1>, dim3(REG_G), dim3(REG_L), 0, s, x, n, z, zsub, K, part);
+    else
+      hipLaunchKernelGGL(k_stats_regs<2>, dim3(REG_G), dim3(REG_L), 0, s, x, n, z, zsub, K, part);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const int NE = 2 * K * (E + 1);
+    hipLaunchKernelGGL(k_stats_small_reduce, dim3((NE + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, part, REG_G, K, E,
+                       counts, moments);
+    return hipGetLastError();
   }
   // STATS_SMALL_LANES lanes in all: one resident workgroup per CU at L = 256
   const int G = STATS_SMALL_LANES / L;
