@@ -967,21 +967,20 @@ __device__ __forceinline__ void big_rows(f64x4 (&acc)[TPW], double (&sx)[D / 64]
                                          const int* __restrict__ order, int st, int cnt, int lane, int rd0, int rd1) {
   constexpr int NB = D / 16;
   const int p = lane >> 4;
-  // software pipeline over two register sets: the row pieces of step g + 4 and
-  // the row index of step g + 8 are read while step g's matrix-core work runs
-  auto row_of = [&](int g) __attribute__((always_inline)) { return g + p < cnt ? order[st + g + p] : R; };
-  auto fetch = [&](int o, float4& a, float4& b) __attribute__((always_inline)) {
-    const float* rp = xs + o * D;
-    a = *reinterpret_cast<const float4*>(rp + rd0);
-    if constexpr (NB == 8) b = *reinterpret_cast<const float4*>(rp + rd1);
-  };
-  auto step = [&](const float4& a, const float4& b) __attribute__((always_inline)) {
+  // (a two-step software pipeline of these reads measured the same: the other
+  // wave of the SIMD covers their latency, and while an LDS DMA is in flight
+  // the compiler waits for every LDS read before its first use anyway)
+  for (int g = 0; g < cnt; g += 4) {
+    const int q = g + p;
+    const float* rp = xs + (q < cnt ? order[st + q] : R) * D;
+    const float4 a = *reinterpret_cast<const float4*>(rp + rd0);
     double xv[NB];
     xv[0] = (double)a.x;
     xv[1] = (double)a.y;
     xv[2] = (double)a.z;
     xv[3] = (double)a.w;
     if constexpr (NB == 8) {
+      const float4 b = *reinterpret_cast<const float4*>(rp + rd1);
       xv[4] = (double)b.x;
       xv[5] = (double)b.y;
       xv[6] = (double)b.z;
@@ -992,18 +991,6 @@ __device__ __forceinline__ void big_rows(f64x4 (&acc)[TPW], double (&sx)[D / 64]
     // column col(block, l % 16) of its row
 #pragma unroll
     for (int j = 0; j < D / 64; ++j) sx[j] += xv[WQ + 4 * j];
-  };
-  float4 a0, b0 = make_float4(0.f, 0.f, 0.f, 0.f), a1, b1 = make_float4(0.f, 0.f, 0.f, 0.f);
-  int o0 = row_of(0), o1 = cnt > 4 ? row_of(4) : R;
-  fetch(o0, a0, b0);
-  for (int g = 0; g < cnt; g += 8) {
-    if (g + 4 < cnt) fetch(o1, a1, b1);
-    if (g + 8 < cnt) o0 = row_of(g + 8);
-    step(a0, b0);
-    if (g + 4 >= cnt) break;
-    if (g + 8 < cnt) fetch(o0, a0, b0);
-    if (g + 12 < cnt) o1 = row_of(g + 12);
-    step(a1, b1);
   }
 }
 
