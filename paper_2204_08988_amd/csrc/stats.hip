@@ -106,7 +106,7 @@ __global__ __launch_bounds__(L) void k_stats_small(const float* __restrict__ x, 
 // the workgroup's waves in wave order, one partial row per workgroup.
 constexpr int REG_VALUES = 72;
 constexpr int REG_L = 256;
-constexpr int REG_G = 512;  // two workgroups per CU
+constexpr int REG_G = 512;  // at most two workgroups per CU
 
 template <int D>
 __global__ __launch_bounds__(REG_L) void k_stats_regs(const float* __restrict__ x, long long n,
@@ -315,14 +315,17 @@ hipError_t launch_stats_gauss(int d, const float* x, long long n, const int* z, 
     return launch_zero64(moments, (size_t)2 * K * E, s);
   }
   if (stats_regs_ok(d, K)) {
+    // at least 16 points per lane before the grid grows (small n: few partial rows)
+    long long gl = (n + (long long)REG_L * 16 - 1) / ((long long)REG_L * 16);
+    const int G = (int)(gl < 1 ? 1 : (gl > REG_G ? REG_G : gl));
     if (d == 1)
-      hipLaunchKernelGGL(k_stats_regs<1>, dim3(REG_G), dim3(REG_L), 0, s, x, n, z, zsub, K, part);
+      hipLaunchKernelGGL(k_stats_regs<1>, dim3(G), dim3(REG_L), 0, s, x, n, z, zsub, K, part);
     else
-      hipLaunchKernelGGL(k_stats_regs<2>, dim3(REG_G), dim3(REG_L), 0, s, x, n, z, zsub, K, part);
+      hipLaunchKernelGGL(k_stats_regs<2>, dim3(G), dim3(REG_L), 0, s, x, n, z, zsub, K, part);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int NE = 2 * K * (E + 1);
-    hipLaunchKernelGGL(k_stats_small_reduce, dim3((NE + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, part, REG_G, K, E,
+    hipLaunchKernelGGL(k_stats_small_reduce, dim3((NE + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, part, G, K, E,
                        counts, moments);
     return hipGetLastError();
   }
