@@ -392,6 +392,52 @@ def width_compare(args):
     print(json.dumps(rec), flush=True)
 
 
+def yardstick(args):
+    """Library GEMM references (torch.matmul in BF16 with FP32 accumulation, served
+    by hipBLASLt on this stack), a ceiling reference only: (1) a large square
+    product, the BF16 rate library code reaches on this chip; (2) the K-wide
+    whitening product of the headline shape, N x d by d x Kd (the K whiteners side
+    by side), in row chunks: it writes the N x Kd product that the fused cluster
+    draw keeps in registers, and none of the norms or the draw."""
+    import torch
+
+    def timed(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    g = torch.Generator(device="cuda").manual_seed(7)
+    out = {"metric": "library BF16 GEMM references (hipBLASLt through torch.matmul)"}
+    s = 8192
+    a = torch.randn(s, s, device="cuda", dtype=torch.bfloat16, generator=g)
+    b = torch.randn(s, s, device="cuda", dtype=torch.bfloat16, generator=g)
+    c = torch.empty(s, s, device="cuda", dtype=torch.bfloat16)
+    ms = timed(lambda: torch.matmul(a, b, out=c), 20)
+    fl = 2.0 * s ** 3
+    out["square_8192"] = {"ms": ms, "tflops": fl / ms / 1e9, "frac_of_peak": fl / (ms * 1e-3) / PEAK_BF16_MFMA}
+    del a, b, c
+    d, K, N, m = 128, 100, 10_000_000, 1 << 18
+    xa = torch.randn(m, d, device="cuda", dtype=torch.bfloat16, generator=g)
+    w = torch.randn(d, K * d, device="cuda", dtype=torch.bfloat16, generator=g)
+    y = torch.empty(m, K * d, device="cuda", dtype=torch.bfloat16)
+    ms_chunk = timed(lambda: torch.matmul(xa, w, out=y), 5)
+    ms_step = ms_chunk * N / m
+    fl_step = 2.0 * N * d * K * d
+    out["whitening_k_wide_gauss_d128"] = {
+        "rows_per_chunk": m, "ms_per_chunk": ms_chunk, "ms_per_1e7_rows": ms_step,
+        "executed_tflops": fl_step / ms_step / 1e9, "frac_of_peak": fl_step / (ms_step * 1e-3) / PEAK_BF16_MFMA,
+        "product_bytes_written_per_1e7_rows": 2.0 * N * K * d}
+    print(json.dumps(out), flush=True)
+
+
 def label_step(args):
     import torch
     res = label_step_run(torch, args.label_step, int(float(args.n)) if args.n else None, args.precision, args.steps,
@@ -521,6 +567,8 @@ def main():
     ap.add_argument("--label-step", metavar="WORKLOAD",
                     help="instead of the throughput line: label-step throughput at WORKLOAD's true mixture")
     ap.add_argument("--n", default=None, help="points for --label-step (default: the workload's N)")
+    ap.add_argument("--yardstick", action="store_true",
+                    help="instead of the throughput line: library BF16 GEMM references (a ceiling reference only)")
     ap.add_argument("--learned-ab", action="store_true",
                     help="instead of the throughput line: time to the plain chain's log-posterior plateau, "
                          "learned proposal vs plain, on the learned-proposal workload")
@@ -553,6 +601,9 @@ def main():
         return
     if args.width_compare:
         width_compare(args)
+        return
+    if args.yardstick:
+        yardstick(args)
         return
     if args.sparse:
         import torch
