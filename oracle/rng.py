@@ -13,7 +13,11 @@ oracle and the GPU path see identical random numbers.
 
 Tags (the entity named after each tag):
     0  TAG_GUMBEL     point i      cluster-label Gumbels: block k//4, word k%4
-    1  TAG_LOGISTIC   point i      sub-label logistic: block 0, word 0
+    1  TAG_LOGISTIC   point i      sub-label logistic with K a multiple of 4:
+                                   block 0, word 0 (otherwise the logistic
+                                   takes the first word of the last Gumbel
+                                   block that no cluster uses: TAG_GUMBEL
+                                   block K//4, word K%4; see sub_label_word)
     2  TAG_SUBINIT    point i      fresh random sub-label: block 0, word 0, bit 0
     3  TAG_BERN       point i      learned-proposal Bernoulli: block 0, word 0
     16 TAG_WEIGHTS    cluster k    Gamma draw for Dir(N_1..N_K, alpha); the
@@ -68,6 +72,18 @@ def block(seed, t, entity, tag, blk):
     """Philox block for (entity, t, tag, blk); arrays broadcast."""
     k0, k1 = key_of(seed)
     return philox4x32(entity, t, tag, blk, k0, k1)
+
+
+def sub_label_word(seed, t, i, K):
+    """The word of point i's sub-label logistic at step t with K clusters.  The
+    Gumbels of clusters 0..K-1 take words 0..K-1 of blocks 0, 1, ... of
+    TAG_GUMBEL; when K is not a multiple of 4 the last of those blocks has a
+    word no cluster uses (K % 4), and the logistic takes it, so that a point
+    that draws both labels computes one block fewer; otherwise it takes word 0
+    of its own block (TAG_LOGISTIC)."""
+    if K % 4:
+        return block(seed, t, i, TAG_GUMBEL, K // 4)[K % 4]
+    return block(seed, t, i, TAG_LOGISTIC, 0)[0]
 
 
 def uniform(w):

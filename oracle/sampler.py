@@ -250,9 +250,11 @@ def gumbels(seed, t, N, K, point_offset=0, points=None):
     return g
 
 
-def logistics(seed, t, N, point_offset=0, points=None):
+def logistics(seed, t, N, K, point_offset=0, points=None):
+    """The sub-label logistics of the rows at step t with K clusters (the word
+    of rng.sub_label_word)."""
     i = _points(N, point_offset, points)
-    return rng.logistic(rng.block(seed, t, i, rng.TAG_LOGISTIC, 0)[0])
+    return rng.logistic(rng.sub_label_word(seed, t, i, K))
 
 
 def draw_labels(seed, t, lc, ls, point_offset=0, points=None):
@@ -264,7 +266,7 @@ def draw_labels(seed, t, lc, ls, point_offset=0, points=None):
     z = np.argmax(lc + g, axis=1)
     idx = np.arange(N)
     delta = ls[idx, z, 0] - ls[idx, z, 1]
-    L = logistics(seed, t, N, point_offset, points)
+    L = logistics(seed, t, N, K, point_offset, points)
     zsub = np.where(delta + L > 0, 0, 1)
     return z.astype(np.int64), zsub.astype(np.int64)
 

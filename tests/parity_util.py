@@ -110,7 +110,7 @@ def label_mismatches(seed, t, z_gpu, zs_gpu, lc, ls, Mc, Ms, points=None):
     tol = 1e-5 * (Mc[idx, a] + Mc[idx, b]) + 4 * 2.0 ** -24 * (np.abs(g[idx, a]) + np.abs(g[idx, b]) + 1)
     diff_c = z_gpu != z_o
     bad_c = np.nonzero(diff_c & (margin > tol))[0]
-    L = sampler.logistics(seed, t, N, points=points)
+    L = sampler.logistics(seed, t, N, K, points=points)
     same = ~diff_c
     gap = ls[idx, z_o, 0] - ls[idx, z_o, 1] + L
     tol_s = 1e-5 * (Ms[idx, z_o, 0] + Ms[idx, z_o, 1]) + 4 * 2.0 ** -24 * (np.abs(L) + 1)

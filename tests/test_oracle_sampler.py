@@ -43,8 +43,29 @@ def test_loglik_against_scipy_and_label_argmax():
         w = [rng.block(model.seed, 4, i, rng.TAG_GUMBEL, k // 4)[k % 4] for k in range(K)]
         pert = [lc[i, k] + float(rng.gumbel(np.uint32(w[k]))) for k in range(K)]
         assert z[i] == int(np.argmax(pert))
-        L = float(rng.logistic(rng.block(model.seed, 4, i, rng.TAG_LOGISTIC, 0)[0]))
+        # the logistic's word: the last Gumbel block's unused word when K % 4 != 0
+        wl = rng.block(model.seed, 4, i, rng.TAG_GUMBEL, K // 4)[K % 4] if K % 4 else \
+            rng.block(model.seed, 4, i, rng.TAG_LOGISTIC, 0)[0]
+        L = float(rng.logistic(np.uint32(wl)))
         assert zs[i] == (0 if ls[i, z[i], 0] - ls[i, z[i], 1] + L > 0 else 1)
+
+
+@pytest.mark.parametrize("K", [4, 5, 6, 7, 8])
+def test_sub_label_independent_of_cluster_draw(K):
+    """The sub-label's logistic shares the last Gumbel block when K % 4 != 0:
+    the joint frequencies of (z, sub-label) must still be the product of the
+    softmax and the sigmoid.  A logistic word that coincided with a cluster's
+    Gumbel word (an index off by one) would tie the two draws together."""
+    N = 150_000
+    logits = np.linspace(0.8, -0.6, K)
+    lc = np.tile(logits, (N, 1))
+    ls = np.zeros((N, K, 2))
+    ls[:, :, 0] = 0.4
+    z, zs = sampler.draw_labels(23, 5, lc, ls)
+    table = np.zeros((K, 2))
+    np.add.at(table, (z, zs), 1)
+    expect = np.outer(softmax(logits), [expit(0.4), 1.0 - expit(0.4)]) * N
+    assert stats.chisquare(table.ravel(), expect.ravel()).pvalue > 1e-3
 
 
 def test_label_frequencies_follow_softmax_and_sigmoid():
