@@ -98,16 +98,30 @@ __device__ __forceinline__ float logistic_f(uint32_t w) {
   return logf(u) - log1pf(-u);
 }
 
-// Sub-label draw (eq. sample_sub_labels) from the score gap delta = l_l - l_r:
-// l (0) iff delta + L > 0 for the logistic L = log u - log(1 - u) of point i's
-// word; since the logit is increasing this is u > 1 / (1 + e^delta), one exp
-// instead of two logs.  A gap beyond the logistic's range decides without a
-// draw.
-__device__ __forceinline__ int sub_label_draw(float delta, uint64_t seed, uint32_t t, uint32_t i) {
+// Word of point i's sub-label logistic at step t with K clusters: the word of
+// the last Gumbel block that no cluster uses (TAG_GUMBEL block K / 4, word
+// K % 4) when K is not a multiple of 4, so that a point drawing both labels
+// computes that block once; else word 0 of its own block (TAG_LOGISTIC).
+__device__ __forceinline__ uint32_t sub_label_word(uint64_t seed, uint32_t t, uint32_t i, int K) {
+  if (K & 3) return word_of(rng_block(seed, t, i, TAG_GUMBEL, (uint32_t)(K >> 2)), K & 3);
+  return rng_block(seed, t, i, TAG_LOGISTIC, 0).x;
+}
+
+// Sub-label draw (eq. sample_sub_labels) from the score gap delta = l_l - l_r
+// and the logistic's word w: l (0) iff delta + L > 0 for the logistic
+// L = log u - log(1 - u); since the logit is increasing this is
+// u > 1 / (1 + e^delta), one exp instead of two logs.
+__device__ __forceinline__ int sub_label_from_word(float delta, uint32_t w) {
+  const float u = uniform_f(w);
+  return u > 1.0f / (1.0f + expf(delta)) ? 0 : 1;
+}
+
+// The same with the word drawn here; a gap beyond the logistic's range
+// decides without a draw.
+__device__ __forceinline__ int sub_label_draw(float delta, uint64_t seed, uint32_t t, uint32_t i, int K) {
   if (delta > LOGISTIC_MAX_F) return 0;
   if (delta < -LOGISTIC_MAX_F) return 1;
-  const float u = uniform_f(rng_block(seed, t, i, TAG_LOGISTIC, 0).x);
-  return u > 1.0f / (1.0f + expf(delta)) ? 0 : 1;
+  return sub_label_from_word(delta, sub_label_word(seed, t, i, K));
 }
 
 __host__ __device__ __forceinline__ double box_muller_d(uint32_t w0, uint32_t w1) {

@@ -149,7 +149,7 @@ struct SubX3 {
   int* zrow_c;          // [n]
 };
 hipError_t launch_sub_labels_x3(int d, const float* x, long long n, const int* perm, const int* z, const int* zrow,
-                                unsigned char* zsub, const float* packed, int k_max, uint32_t t, uint64_t seed,
+                                unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t, uint64_t seed,
                                 const SubX3& b, hipStream_t s);
 // flagged: int[n] (the points whose draw is deferred to FP32); cand:
 // int[n][RESCORE_CAND], each deferred point's candidate clusters (-1: empty

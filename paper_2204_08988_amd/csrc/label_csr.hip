@@ -199,7 +199,7 @@ __global__ __launch_bounds__(BLOCK) void k_label_csr(const long long* __restrict
     if (lane == 0) {
       const float delta = (cw[K + 2 * zi] + al) - (cw[K + 2 * zi + 1] + ar);
       z[i] = zi;
-      zsub[i] = (unsigned char)sub_label_draw(delta, seed, t, (uint32_t)i);
+      zsub[i] = (unsigned char)sub_label_draw(delta, seed, t, (uint32_t)i, K);
     }
   }
 }

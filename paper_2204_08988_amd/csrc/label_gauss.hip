@@ -56,6 +56,9 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss(const float* __restrict__
     Top2 t2;
     t2.init();
     int zi;
+    // the sub-label's word: the unused word of Gumbel block K / 4 when K % 4 != 0
+    // (that block computed once, for every lane, and shared with the draw of z)
+    uint32_t wsub = 0;
     if constexpr (KM > 0) {
       // K <= KM: the scores stay in registers for the draw
       float lk[KM];
@@ -64,7 +67,9 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss(const float* __restrict__
         lk[k] = k < K ? score_rec<D>(cl + (size_t)k * S, xv) : -INFINITY;
         if (k < K) t2.push(lk[k], k);
       }
-      zi = lazy_gumbel_max_regs<KM>(lk, t2, K, (uint32_t)i, t, seed);
+      const u32x4 last = (K & 3) ? rng_block(seed, t, (uint32_t)i, TAG_GUMBEL, (uint32_t)(K >> 2)) : u32x4{0u, 0u, 0u, 0u};
+      wsub = word_of(last, K & 3);
+      zi = lazy_gumbel_max_regs<KM>(lk, t2, K, (uint32_t)i, t, seed, last);
     } else {
       for (int k = 0; k < K; ++k) t2.push(score_rec<D>(cl + (size_t)k * S, xv), k);
       zi = lazy_gumbel_max(t2, K, (uint32_t)i, t, seed, [&](int k) { return score_rec<D>(cl + (size_t)k * S, xv); });
@@ -72,7 +77,10 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss(const float* __restrict__
     const float* ps = sub + (size_t)(2 * zi) * S;
     const float delta = score_rec<D>(ps, xv) - score_rec<D>(ps + S, xv);
     z[i] = zi;
-    zsub[i] = draw_sub(delta, (uint32_t)i, t, seed);
+    if (KM > 0 && (K & 3))
+      zsub[i] = delta > LOGISTIC_MAX_F ? 0 : (delta < -LOGISTIC_MAX_F ? 1 : sub_label_from_word(delta, wsub));
+    else
+      zsub[i] = draw_sub(delta, (uint32_t)i, t, seed, K);
   }
 }
 
@@ -95,7 +103,7 @@ __global__ __launch_bounds__(BLOCK) void k_label_gauss_dyn(const float* __restri
     const float* ps = packed + (size_t)(k_max + 2 * zi) * S;
     const float delta = score_rec_dyn(ps, xi, dx, d) - score_rec_dyn(ps + S, xi, dx, d);
     z[i] = zi;
-    zsub[i] = draw_sub(delta, (uint32_t)i, t, seed);
+    zsub[i] = draw_sub(delta, (uint32_t)i, t, seed, K);
   }
 }
 

@@ -973,8 +973,8 @@ template <int D>
 __global__ __launch_bounds__(SUBX_BLOCK, 1) void k_sub_labels_x3(
     const float* __restrict__ x, long long n_sorted, long long per_block, const int* __restrict__ perm,
     const int* __restrict__ z, const int* __restrict__ zrow, unsigned char* __restrict__ zsub,
-    const float* __restrict__ packed, const bf16x8* __restrict__ shi, const bf16x8* __restrict__ slo, int k_max,
-    uint32_t t, uint64_t seed, unsigned char* __restrict__ flag, int* __restrict__ cnt) {
+    const float* __restrict__ packed, const bf16x8* __restrict__ shi, const bf16x8* __restrict__ slo, int K,
+    int k_max, uint32_t t, uint64_t seed, unsigned char* __restrict__ flag, int* __restrict__ cnt) {
   using TT = TriTiles<D>;
   constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
   constexpr int MT = TT::MT, KS = TT::KS, NF = MT * KS * 64, NT = TT::NT;
@@ -1116,7 +1116,7 @@ __global__ __launch_bounds__(SUBX_BLOCK, 1) void k_sub_labels_x3(
     const long long rme = base + lane;
     if (rme < cend) {
       const int i = (int)(h ? iB : iA);
-      const float u = uniform_f(rng_block(seed, t, (uint32_t)i, TAG_LOGISTIC, 0).x);
+      const float u = uniform_f(sub_label_word(seed, t, (uint32_t)i, K));
       const int s0 = logistic_pick(delta - allow, u), s1 = logistic_pick(delta + allow, u);
       if (s0 == s1) zsub[i] = (unsigned char)s0;
       flag[rme] = s0 != s1;
@@ -1257,7 +1257,7 @@ size_t sub_labels_x3_lds(int d) {
 }
 
 hipError_t launch_sub_labels_x3(int d, const float* x, long long n, const int* perm, const int* z, const int* zrow,
-                                unsigned char* zsub, const float* packed, int k_max, uint32_t t, uint64_t seed,
+                                unsigned char* zsub, const float* packed, int K, int k_max, uint32_t t, uint64_t seed,
                                 const SubX3& b, hipStream_t s) {
   if (n == 0) return hipSuccess;
   static bool attr = false;
@@ -1277,10 +1277,10 @@ hipError_t launch_sub_labels_x3(int d, const float* x, long long n, const int* p
   const bf16x8* lo = (const bf16x8*)b.lo;
   if (d == 128)
     hipLaunchKernelGGL(k_sub_labels_x3<128>, dim3(G), dim3(SUBX_BLOCK), lds, s, x, n, per, perm, z, zrow, zsub, packed,
-                       hi, lo, k_max, t, seed, b.flag, b.cnt);
+                       hi, lo, K, k_max, t, seed, b.flag, b.cnt);
   else if (d == 64)
     hipLaunchKernelGGL(k_sub_labels_x3<64>, dim3(G), dim3(SUBX_BLOCK), lds, s, x, n, per, perm, z, zrow, zsub, packed,
-                       hi, lo, k_max, t, seed, b.flag, b.cnt);
+                       hi, lo, K, k_max, t, seed, b.flag, b.cnt);
   else
     return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(BLOCK) void k_label_mult(const int* __restrict__ x,
     const float* ps = packed + (size_t)(k_max + 2 * zi) * S;
     const float delta = score_mult<VT>(ps, xv) - score_mult<VT>(ps + S, xv);
     unsigned char zs;
-    zs = sub_label_draw(delta, seed, t, (uint32_t)i);
+    zs = sub_label_draw(delta, seed, t, (uint32_t)i, K);
     z[i] = zi;
     zsub[i] = zs;
   }
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(BLOCK) void k_label_mult_mfma(const int* __restrict
       const float* ps = packed + (size_t)(k_max + 2 * zi) * S;
       const float delta = score_mult<2 * VH>(ps, xv) - score_mult<2 * VH>(ps + S, xv);
       z[i] = zi;
-      zsub[i] = (unsigned char)sub_label_draw(delta, seed, t, (uint32_t)i);
+      zsub[i] = (unsigned char)sub_label_draw(delta, seed, t, (uint32_t)i, K);
     }
   }
 }

@@ -114,11 +114,14 @@ __device__ __forceinline__ int lazy_gumbel_max(const Top2& t2, int K, uint32_t i
 // blocks are taken in increasing block order, each computed at most once
 // per wave, and the winner is the largest l_k + g_k, the smaller k on ties.
 // Clusters that lazy_gumbel_max skips cannot win, so the label is the same.
+// `last` is block K / 4 when K % 4 != 0, computed by the caller (its unused
+// word is the sub-label's), and is not computed again here.
 template <int KM>
 __device__ __forceinline__ int lazy_gumbel_max_regs(const float (&l)[KM], const Top2& t2, int K, uint32_t i,
-                                                    uint32_t t, uint64_t seed) {
+                                                    uint32_t t, uint64_t seed, const u32x4& last) {
   if (!(t2.m2 > t2.m1 - RGAP)) return t2.arg;
   const float floor = t2.m1 - RGAP;
+  const int bl = (K & 3) ? (K >> 2) : -1;
   float best = -INFINITY;
   int win = t2.arg;
 #pragma unroll
@@ -128,7 +131,7 @@ __device__ __forceinline__ int lazy_gumbel_max_regs(const float (&l)[KM], const 
     for (int j = 0; j < 4; ++j)
       if (4 * b + j < K && l[4 * b + j] > floor) need = true;
     if (need) {
-      const u32x4 blk = rng_block(seed, t, i, TAG_GUMBEL, (uint32_t)b);
+      const u32x4 blk = b == bl ? last : rng_block(seed, t, i, TAG_GUMBEL, (uint32_t)b);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = 4 * b + j;
@@ -145,8 +148,8 @@ __device__ __forceinline__ int lazy_gumbel_max_regs(const float (&l)[KM], const 
   return win;
 }
 
-__device__ __forceinline__ unsigned char draw_sub(float delta, uint32_t i, uint32_t t, uint64_t seed) {
-  return (unsigned char)sub_label_draw(delta, seed, t, i);
+__device__ __forceinline__ unsigned char draw_sub(float delta, uint32_t i, uint32_t t, uint64_t seed, int K) {
+  return (unsigned char)sub_label_draw(delta, seed, t, i, K);
 }
 
 }  // namespace score

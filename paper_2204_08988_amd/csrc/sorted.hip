@@ -188,7 +188,7 @@ template <int D, bool SAMPLE>
 __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x, int d, int TR, int tpw,
                                                      long long n_sorted, const int* __restrict__ perm,
                                                      const int* __restrict__ z, unsigned char* __restrict__ zsub,
-                                                     const float* __restrict__ packed, int k_max, uint32_t t,
+                                                     const float* __restrict__ packed, int K, int k_max, uint32_t t,
                                                      uint64_t seed, long long* __restrict__ counts,
                                                      double* __restrict__ moments, const int* __restrict__ cstart,
                                                      const int* __restrict__ ctot, int kbase,
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats(const float* __restrict__ x
         pending &= ~__ballot(mine);
       }
       if (valid) {
-        zs = sub_label_draw(delta, seed, t, (uint32_t)i);
+        zs = sub_label_draw(delta, seed, t, (uint32_t)i, K);
         zsub[i] = (unsigned char)zs;
       }
     } else if (valid) {
@@ -622,7 +622,7 @@ __global__ __launch_bounds__(BLOCK) void k_sub_stats_w(const float* __restrict__
         pend &= ~__ballot(mine);
       }
       if (valid) {
-        zs = sub_label_draw(delta, seed, t, (uint32_t)i);
+        zs = sub_label_draw(delta, seed, t, (uint32_t)i, K);
         zsub[i] = (unsigned char)zs;
       }
     } else if (valid) {
@@ -774,7 +774,7 @@ template <int D>
 __global__ __launch_bounds__(SUBL_BLOCK) __attribute__((amdgpu_waves_per_eu(2, D <= 32 ? 3 : 2))) void k_sub_labels_mfma(
     const float* __restrict__ x, long long n_sorted, long long per_block, const int* __restrict__ perm,
     const int* __restrict__ z, const int* __restrict__ zrow, unsigned char* __restrict__ zsub,
-    const float* __restrict__ packed, int k_max, uint32_t t, uint64_t seed, const int* __restrict__ n_dev) {
+    const float* __restrict__ packed, int K, int k_max, uint32_t t, uint64_t seed, const int* __restrict__ n_dev) {
   constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
   constexpr int MT = D / 32, HALF = D / 2, QTR = D / 4;
   if (n_dev) {  // a row list whose length is on the device: split it evenly over the grid
@@ -902,7 +902,7 @@ __global__ __launch_bounds__(SUBL_BLOCK) __attribute__((amdgpu_waves_per_eu(2, D
     const long long rme = base + lane;
     if (rme < cend) {
       const int i = (int)(h ? iB : iA);
-      zsub[i] = (unsigned char)sub_label_draw(delta, seed, t, (uint32_t)i);
+      zsub[i] = (unsigned char)sub_label_draw(delta, seed, t, (uint32_t)i, K);
     }
   }
 }
@@ -1295,7 +1295,7 @@ long long generic_groups(int d, long long n) {
 
 template <bool SAMPLE>
 hipError_t launch_sub_stats_t(int d, const float* x, long long n, const int* perm, const int* z, unsigned char* zsub,
-                              const float* packed, int k_max, uint32_t t, uint64_t seed, long long* counts,
+                              const float* packed, int K, int k_max, uint32_t t, uint64_t seed, long long* counts,
                               double* moments, const int* cstart, const int* ctot, int kbase, int ncl, double* part,
                               hipStream_t s) {
   const int TR = tile_rows(d);
@@ -1314,7 +1314,7 @@ hipError_t launch_sub_stats_t(int d, const float* x, long long n, const int* per
 #define DPMM_SUB_CASE(DD)                                                                                 \
   case DD:                                                                                                \
     hipLaunchKernelGGL((k_sub_stats<DD, SAMPLE>), dim3(grid), dim3(BLOCK), sub_stats_lds(d, TR, false), s, x, d, \
-                       TR, tpw, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, cstart, ctot, kbase,   \
+                       TR, tpw, n, perm, z, zsub, packed, K, k_max, t, seed, counts, moments, cstart, ctot, kbase,\
                        part);                                                                             \
     break;
   switch (d) {
@@ -1324,7 +1324,7 @@ hipError_t launch_sub_stats_t(int d, const float* x, long long n, const int* per
     DPMM_SUB_CASE(64)
     default:
       hipLaunchKernelGGL((k_sub_stats<0, SAMPLE>), dim3(grid), dim3(BLOCK), sub_stats_lds(d, TR, SAMPLE), s, x, d,
-                         TR, tpw, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, cstart, ctot, kbase,
+                         TR, tpw, n, perm, z, zsub, packed, K, k_max, t, seed, counts, moments, cstart, ctot, kbase,
                          part);
   }
 #undef DPMM_SUB_CASE
@@ -1420,7 +1420,7 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
       const int* lzrow = zrow;
       const int* ndev = nullptr;
       if (x3 && (d == 64 || d == 128)) {
-        e = launch_sub_labels_x3(d, x, n, perm, z, zrow, zsub, packed, k_max, t, seed, *x3, s);
+        e = launch_sub_labels_x3(d, x, n, perm, z, zrow, zsub, packed, K, k_max, t, seed, *x3, s);
         if (e != hipSuccess) return e;
         lperm = x3->perm_c;
         lz = nullptr;
@@ -1429,13 +1429,13 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
       }
       if (d == 128)
         hipLaunchKernelGGL(k_sub_labels_mfma<128>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, lperm, lz, lzrow,
-                           zsub, packed, k_max, t, seed, ndev);
+                           zsub, packed, K, k_max, t, seed, ndev);
       else if (d == 64)
         hipLaunchKernelGGL(k_sub_labels_mfma<64>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, lperm, lz, lzrow,
-                           zsub, packed, k_max, t, seed, ndev);
+                           zsub, packed, K, k_max, t, seed, ndev);
       else
         hipLaunchKernelGGL(k_sub_labels_mfma<32>, dim3(lg), dim3(SUBL_BLOCK), llds, s, x, n, lper, lperm, lz, lzrow,
-                           zsub, packed, k_max, t, seed, ndev);
+                           zsub, packed, K, k_max, t, seed, ndev);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     sample = false;
@@ -1483,10 +1483,10 @@ hipError_t sub_stats_kernels(int d, bool sample, const float* x, long long npts,
                        moments, kbase);
     return hipGetLastError();
   }
-  return sample ? launch_sub_stats_t<true>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, cstart,
-                                           ctot, kbase, ncl, part, s)
-                : launch_sub_stats_t<false>(d, x, n, perm, z, zsub, packed, k_max, t, seed, counts, moments, cstart,
-                                            ctot, kbase, ncl, part, s);
+  return sample ? launch_sub_stats_t<true>(d, x, n, perm, z, zsub, packed, K, k_max, t, seed, counts, moments,
+                                           cstart, ctot, kbase, ncl, part, s)
+                : launch_sub_stats_t<false>(d, x, n, perm, z, zsub, packed, K, k_max, t, seed, counts, moments,
+                                            cstart, ctot, kbase, ncl, part, s);
 }
 
 }  // namespace
