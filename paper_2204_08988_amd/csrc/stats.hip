@@ -13,7 +13,7 @@
 // registers when d <= 2 and all segments' sums fit in 72 of them, in LDS
 // otherwise) and adds its own points (a fixed grid-stride assignment); the
 // workgroup then adds its lanes by a fixed tree and writes one partial row,
-// and a second kernel adds the rows in workgroup order.
+// and a second kernel adds the rows by a fixed tree (one wave per entry).
 // Multinomial: lanes over points, uint32 LDS accumulators (at most 65536
 // points per workgroup, so count entries below 65536 cannot overflow), int64
 // flush; all integer, so the result is exact and independent of the order.
@@ -194,14 +194,20 @@ __global__ __launch_bounds__(REG_L) void k_stats_regs(const float* __restrict__ 
 
 bool stats_regs_ok(int d, int K) { return (d == 1 || d == 2) && (size_t)2 * K * (1 + d + d * (d + 1) / 2) <= REG_VALUES; }
 
-// counts[s] and moments[s][.] from the G partial rows, added in row order.
-__global__ void k_stats_small_reduce(const double* __restrict__ part, int G, int K, int E,
-                                     long long* __restrict__ counts, double* __restrict__ moments) {
+// counts[s] and moments[s][.] from the G partial rows: one wave per entry,
+// lane l adding rows l, l + 64, ... in order, then the lanes by a fixed xor
+// tree (the same bits whatever the timing).
+__global__ __launch_bounds__(64) void k_stats_small_reduce(const double* __restrict__ part, int G, int K, int E,
+                                                           long long* __restrict__ counts,
+                                                           double* __restrict__ moments) {
   const int NE = 2 * K * (E + 1);
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = blockIdx.x;
   if (e >= NE) return;
   double sum = 0.0;
-  for (int g = 0; g < G; ++g) sum += part[(size_t)g * NE + e];
+  for (int g = threadIdx.x; g < G; g += 64) sum += part[(size_t)g * NE + e];
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) sum += __shfl_xor(sum, o);
+  if (threadIdx.x != 0) return;
   const int sgm = e / (E + 1), f = e - sgm * (E + 1);
   if (f == 0)
     counts[sgm] = (long long)sum;  // a sum of integer counts below 2^53: exact
@@ -325,7 +331,7 @@ hipError_t launch_stats_gauss(int d, const float* x, long long n, const int* z, 
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int NE = 2 * K * (E + 1);
-    hipLaunchKernelGGL(k_stats_small_reduce, dim3((NE + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, part, G, K, E,
+    hipLaunchKernelGGL(k_stats_small_reduce, dim3(NE), dim3(64), 0, s, part, G, K, E,
                        counts, moments);
     return hipGetLastError();
   }
@@ -364,7 +370,7 @@ hipError_t launch_stats_gauss(int d, const float* x, long long n, const int* z, 
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int NE = 2 * K * (E + 1);
-  hipLaunchKernelGGL(k_stats_small_reduce, dim3((NE + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, part, G, K, E, counts,
+  hipLaunchKernelGGL(k_stats_small_reduce, dim3(NE), dim3(64), 0, s, part, G, K, E, counts,
                      moments);
   return hipGetLastError();
 }
