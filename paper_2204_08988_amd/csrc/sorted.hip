@@ -110,8 +110,10 @@ __global__ __launch_bounds__(BLOCK) void k_scan_hist(const int* __restrict__ his
 // (w + 1) q) of the block's range (q = per_block / 4, a multiple of 64): it
 // counts its rows per cluster (LDS integer atomics, exact), its cursor for
 // cluster k is the block's offset plus the counts of the waves before it, and
-// it then walks its quarter 64 rows at a time, ranking the lanes of each
-// cluster by their position in the wave (ballot).
+// it then walks its quarter 64 rows at a time.  The lanes holding the same
+// cluster are found with one ballot per bit of the cluster index (the lanes
+// that agree with this lane on every bit); a lane's rank among them is the
+// count of those below it, and the highest of them moves the cursor.
 __global__ __launch_bounds__(BLOCK) void k_scatter_z(const int* __restrict__ z, long long n, long long per_block,
                                                      int K, const int* __restrict__ offs, int* __restrict__ perm,
                                                      int* __restrict__ zsort) {
@@ -141,29 +143,32 @@ __global__ __launch_bounds__(BLOCK) void k_scatter_z(const int* __restrict__ z, 
   }
   __syncthreads();
   const unsigned long long below = (1ull << lane) - 1ull;
+  int nbits = 1;
+  while ((1 << nbits) < K) ++nbits;
   for (long long c0 = wb; c0 < we; c0 += 64) {
     const long long i = c0 + lane;
     const int zi = i < we ? z[i] : -1;
     const bool v = (unsigned)zi < (unsigned)K;
-    unsigned long long pend = __ballot(v);
-    while (pend) {
-      const int l0 = __ffsll((long long)pend) - 1;
-      const int kk = __builtin_amdgcn_readlane(zi, l0);
-      const bool mk = v && zi == kk;
-      const unsigned long long m = __ballot(mk);
-      const int base = mine[kk];
-      if (mk) {
-        const int pos = base + __popcll(m & below);
-        perm[pos] = (int)i;
-        zsort[pos] = zi;
-      }
-      // every lane has read the cursor before it moves; the next reads see it
-      if (lane == l0) mine[kk] = base + __popcll(m);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      pend &= ~m;
+    unsigned long long m = __ballot(v);
+    for (int b = 0; b < nbits; ++b) {
+      const unsigned long long on = __ballot(v && ((zi >> b) & 1));
+      m &= ((zi >> b) & 1) ? on : ~on;
     }
+    int base = 0;
+    if (v) base = mine[zi];
+    // every lane has read its cursor before any moves (wave order)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (v) {
+      const int pos = base + __popcll(m & below);
+      perm[pos] = (int)i;
+      zsort[pos] = zi;
+      if ((m >> lane) == 1ull) mine[zi] = base + __popcll(m);  // the highest lane of its cluster
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
