@@ -93,11 +93,6 @@ __device__ __forceinline__ float gumbel_f(uint32_t w) {
   return -LN2 * __builtin_amdgcn_logf(e);
 }
 
-__device__ __forceinline__ float logistic_f(uint32_t w) {
-  const float u = uniform_f(w);
-  return logf(u) - log1pf(-u);
-}
-
 // Word of point i's sub-label logistic at step t with K clusters: the word of
 // the last Gumbel block that no cluster uses (TAG_GUMBEL block K / 4, word
 // K % 4) when K is not a multiple of 4, so that a point drawing both labels
