@@ -28,8 +28,9 @@
  *     dpmm_last_error gives a message for the last failure on a context.
  *   - Random numbers: every draw is Philox4x32-10 (Salmon et al., SC'11) at
  *     counter (entity, t, tag, block) under key = seed (low word, high word).
- *     Tags: 0 cluster Gumbels of point i (block k/4, word k%4); 1 sub-label
- *     logistic of point i; 2 fresh sub-label bit of point i; 16 weight
+ *     Tags: 0 cluster Gumbels of point i (block k/4, word k%4); the
+ *     sub-label logistic of point i takes word K%4 of tag-0 block K/4 when
+ *     K % 4 != 0, else word 0 of tag 1; 2 fresh sub-label bit of point i; 16 weight
  *     Gammas (entity k, the alpha slot entity K); 17 sub-weight Gammas
  *     (entity k, draw h); 18 NIW draws and 19 Dirichlet draws of component
  *     3k + c; 20 split uniform (entity k); 21 merge uniform (entity
