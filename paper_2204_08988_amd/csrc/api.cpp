@@ -507,6 +507,8 @@ dpmm_status dpmm_create(const dpmm_config* cfg, void* hip_stream, dpmm_ctx** out
         ok = ok && chk(c->alloc(&c->d_slo, (size_t)2 * km * d * d));
         ok = ok && chk(c->alloc(&c->d_scnt, (size_t)SUBX_GROUPS));
         ok = ok && chk(c->alloc(&c->d_soffs, (size_t)SUBX_GROUPS + 1));
+        // the split candidate pass's per-group lists of up to CAND_SPLIT_CAP deferred points
+        ok = ok && chk(c->alloc(&c->d_cst, (size_t)CAND_SPLIT_CAP * CAND_SPLIT_NG * CAND_STATE));
       }
     }
     // counting sort by cluster: the label path for d >= 5, the statistics of
@@ -825,7 +827,7 @@ dpmm_status label_phase(dpmm_ctx* ctx, const void* x, int64_t n, uint32_t t, int
                                             ctx->cfg.k_max, t, ctx->cfg.seed, z,
                                             ctx->d_hist, ctx->d_tot, ctx->d_perm, ctx->d_cand, ctx->d_nflag,
                                             ctx->stream, ctx->label_timing ? ctx->ev[7] : nullptr,
-                                            ctx->label_timing ? ctx->ev[8] : nullptr),
+                                            ctx->label_timing ? ctx->ev[8] : nullptr, ctx->d_cst),
                "matrix-core label kernel");
       ctx->label_kernel_timed = ctx->label_timing && n > 0;
       return DPMM_OK;

@@ -100,6 +100,7 @@ struct dpmm_ctx {
   int *d_perm_c = nullptr, *d_zrow_c = nullptr;
   int* d_nflag = nullptr;  // count of the points deferred to FP32 (matrix-core label kernels)
   int* d_cand = nullptr;   // [perm_cap][RESCORE_CAND] their candidate clusters
+  float* d_cst = nullptr;  // [CAND_SPLIT_CAP][CAND_SPLIT_NG][CAND_STATE] split candidate pass lists (d = 64, 128)
   hipEvent_t ev[9] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool timing = false;  // record ev[3] between the sort and the statistics kernel
   // record ev[7], ev[8] around the main cluster-draw kernel (matrix-core path);

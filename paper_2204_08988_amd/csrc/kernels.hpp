@@ -8,6 +8,13 @@ namespace dpmm {
 // float64 workspaces of the per-component kernels live in LDS up to this d
 // candidate clusters kept per point by the matrix-core label kernels
 constexpr int RESCORE_CAND = 8;
+// candidate pass over few deferred points (d = 64, 128): the clusters split over
+// CAND_SPLIT_NG workgroups per point chunk, their lists merged per point; used
+// while at most CAND_SPLIT_CAP points are deferred.  CAND_STATE: floats of one
+// list (bounds, squared norms, clusters, lo_max, ev_max)
+constexpr int CAND_SPLIT_NG = 8;
+constexpr int CAND_SPLIT_CAP = 32768;
+constexpr int CAND_STATE = 3 * RESCORE_CAND + 2;
 constexpr int NIW_LDS_MAX_D = 64;
 // above that and up to this d the draw keeps one d x (d + 1) float64 matrix in LDS
 constexpr int NIW_BIG_MAX_D = 128;
@@ -158,7 +165,7 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
                                    const float* packed, const void* whi, const void* wlo, const float* wbias, int K,
                                    int k_max, uint32_t t, uint64_t seed, int* z, int* hist, int* tot, int* flagged,
                                    int* cand, int* n_flagged, hipStream_t s, hipEvent_t ev_main0 = nullptr,
-                                   hipEvent_t ev_main1 = nullptr);
+                                   hipEvent_t ev_main1 = nullptr, float* cst = nullptr);
 hipError_t launch_loglik_gauss(int d, const float* x, long long n, const float* packed, int K, int k_max,
                                float* out, hipStream_t s);
 // ---- count data in compressed sparse rows (label_csr.hip)

@@ -85,7 +85,10 @@ struct Cands {
   __device__ __forceinline__ float threshold() const { return lo_max - RGAP - TOL_ABS; }
   __device__ __forceinline__ void push(float l, float q, float rel, int kk) {
     lo_max = fmaxf(lo_max, fmaf(-rel, q, l));
-    const float uu = fmaf(rel, q, l);
+    push_u(fmaf(rel, q, l), q, kk);
+  }
+  // a bound uu (squared norm q, cluster kk) against the current lo_max
+  __device__ __forceinline__ void push_u(float uu, float q, int kk) {
     if (uu > threshold() && uu > u[NCAND - 1]) {
       ev_max = fmaxf(ev_max, u[NCAND - 1]);
       float cu = uu, cq = q;
@@ -201,6 +204,44 @@ __device__ __forceinline__ void finish_cands(bool valid, long long r, long long 
   }
   wave_count_add(sure, sure ? (p / per_block) * K + kb : 0, hist);
   wave_count_add(sure, sure ? kb : 0, tot);
+}
+
+// The split candidate pass's lists of deferred point r (one per cluster group)
+// merged in group order: lo_max and the evicted bound are the groups' maxima,
+// and every listed bound above the merged threshold enters one list (a bound a
+// group dropped lay below its own threshold, at most the merged one).  The
+// result holds every cluster that can win, as the single pass's list does, and
+// finish_cands draws or lists from it.  Lanes of a wave take consecutive points.
+__global__ __launch_bounds__(256) void k_cands_merge(const int* __restrict__ n_flagged, int ng, int cap,
+                                                     const float* __restrict__ cst, float rel, int K,
+                                                     long long per_block, uint32_t t, uint64_t seed,
+                                                     const int* __restrict__ flagged, int* __restrict__ z,
+                                                     int* __restrict__ hist, int* __restrict__ tot,
+                                                     int* __restrict__ cand) {
+  const long long nf = *n_flagged;
+  if (nf > cap) return;
+  const int lane = threadIdx.x & 63;
+  for (long long base = (long long)blockIdx.x * 256 + (threadIdx.x & ~63); base < nf;
+       base += (long long)gridDim.x * 256) {
+    const long long r = base + lane;
+    const bool valid = r < nf;
+    Cands m;
+    m.init();
+    if (valid) {
+      const float* o = cst + (size_t)r * ng * CAND_STATE;
+      for (int g = 0; g < ng; ++g) {
+        m.lo_max = fmaxf(m.lo_max, o[g * CAND_STATE + 3 * NCAND]);
+        m.ev_max = fmaxf(m.ev_max, o[g * CAND_STATE + 3 * NCAND + 1]);
+      }
+      for (int g = 0; g < ng; ++g)
+#pragma unroll
+        for (int j = 0; j < NCAND; ++j) {
+          const int kk = __float_as_int(o[g * CAND_STATE + 2 * NCAND + j]);
+          if (kk >= 0) m.push_u(o[g * CAND_STATE + j], o[g * CAND_STATE + NCAND + j], kk);
+        }
+    }
+    finish_cands(valid, r, valid ? (long long)flagged[r] : 0, m, rel, K, per_block, t, seed, z, hist, tot, cand);
+  }
 }
 
 constexpr int BLOCK32 = 512;  // threads per workgroup of the d = 32 kernel
@@ -393,7 +434,8 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
                                                                    uint64_t seed, int* __restrict__ z,
                                                                    int* __restrict__ hist, int* __restrict__ tot,
                                                                    int* __restrict__ flagged, int* __restrict__ cand,
-                                                                   int* __restrict__ n_flagged) {
+                                                                   int* __restrict__ n_flagged, int ng, int cap,
+                                                                   float* __restrict__ cst) {
   using TT = TriTiles<D>;
   constexpr int S = (4 + D + D * (D + 1) / 2 + 3) & ~3;
   constexpr int MT = TT::MT, KS = TT::KS, NF = MT * KS * 64;  // fragments per cluster in global memory
@@ -414,6 +456,14 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
   const int wbase = threadIdx.x & ~63;
   // main pass: the workgroup's points; candidate pass: the deferred slots, grid-strided
   const long long nf = CANDS ? (long long)*n_flagged : 0;
+  // candidate pass, split form (ng > 1): workgroup (chunk, g) scores clusters
+  // [g kg, (g + 1) kg) of its points and stores their lists; it runs only while at
+  // most cap points are deferred, and the single form only beyond that
+  if (CANDS && (ng > 1 ? nf > cap : (cap > 0 && nf <= cap))) return;
+  const int grp = CANDS ? (int)blockIdx.y : 0;
+  const int kg = (K + ng - 1) / ng;
+  const int kb0 = grp * kg < K ? grp * kg : K;
+  const int kb1 = kb0 + kg < K ? kb0 + kg : K;
   const long long begin = CANDS ? (long long)blockIdx.x * CHUNK : (long long)blockIdx.x * per_block;
   const long long end = CANDS ? nf : (begin + per_block < n ? begin + per_block : n);
   const long long step = CANDS ? (long long)gridDim.x * CHUNK : CHUNK;
@@ -450,7 +500,7 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
       }
     }
   };
-  if (begin < end) stage(s_w0, s_mu0, 0, K < CPB ? K : CPB);
+  if (begin < end && kb0 < kb1) stage(s_w0, s_mu0, kb0, kb1 - kb0 < CPB ? kb1 - kb0 : CPB);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int buf = 0;
@@ -536,12 +586,12 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     };
-    for (int k = 0; k < K; k += CPB) {
-      const int nk = K - k < CPB ? K - k : CPB;
-      const bool last = k + CPB >= K;
+    for (int k = kb0; k < kb1; k += CPB) {
+      const int nk = kb1 - k < CPB ? kb1 - k : CPB;
+      const bool last = k + CPB >= kb1;
       const bool next = !last || more;
-      const int kn = last ? 0 : k + CPB;
-      const int nkn = last ? (K < CPB ? K : CPB) : (K - kn < CPB ? K - kn : CPB);
+      const int kn = last ? kb0 : k + CPB;
+      const int nkn = last ? (kb1 - kb0 < CPB ? kb1 - kb0 : CPB) : (kb1 - kn < CPB ? kb1 - kn : CPB);
       if (buf == 0)
         group(s_w0, s_mu0, s_w1, s_mu1, k, nk, next, kn, nkn);
       else
@@ -549,10 +599,23 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
       buf ^= 1;
     }
     // lanes 0-31 own the points (lanes 32-63 hold the same state)
-    if (CANDS)
+    if (CANDS && ng > 1) {
+      if (ok && half == 0) {  // this group's list of point r (r < nf <= cap)
+        float* o = cst + ((size_t)r * ng + grp) * CAND_STATE;
+#pragma unroll
+        for (int j = 0; j < NCAND; ++j) {
+          o[j] = cd.u[j];
+          o[NCAND + j] = cd.q[j];
+          o[2 * NCAND + j] = __int_as_float(cd.k[j]);
+        }
+        o[3 * NCAND] = cd.lo_max;
+        o[3 * NCAND + 1] = cd.ev_max;
+      }
+    } else if (CANDS) {
       finish_cands(ok && half == 0, r, p, cd, REL, K, per_block, t, seed, z, hist, tot, cand);
-    else
+    } else {
       finish_main(ok && half == 0, r, t2, z, h, flagged, n_flagged, lane);
+    }
   }
   if (CANDS) return;
   __syncthreads();
@@ -1313,7 +1376,7 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
                                    const float* packed, const void* whi, const void* wlo, const float* wbias, int K,
                                    int k_max, uint32_t t, uint64_t seed, int* z, int* hist, int* tot, int* flagged,
                                    int* cand, int* n_flagged, hipStream_t s, hipEvent_t ev_main0,
-                                   hipEvent_t ev_main1) {
+                                   hipEvent_t ev_main1, float* cst) {
   if (n == 0) return hipSuccess;
   hipError_t e = launch_zero64(tot, (size_t)(K + 1) / 2 + 1, s);
   if (e != hipSuccess) return e;
@@ -1367,8 +1430,29 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
       // static staging buffers; only the histogram is dynamic
 #define DPMM_MFMA_W32(DD, XX, CC)                                                                            \
   hipExtLaunchKernelGGL((k_label_gauss_mfma_w32<DD, XX, CC>), dim3(Gp), dim3(BLOCK_W32), lh, s, e0, e1, 0, x, n, \
-                        per_block, packed, hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged)
-      // the candidate pass scores in bf16x3 whatever the main pass's form
+                        per_block, packed, hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged, 1,        \
+                        (CC) && cst ? CAND_SPLIT_CAP : 0, nullptr)
+      // the candidate pass scores in bf16x3 whatever the main pass's form; while
+      // few points are deferred its clusters are split over CAND_SPLIT_NG
+      // workgroups per point chunk and the lists merged (the single form below
+      // then returns at once)
+      if (cands && cst) {
+        const unsigned gx = (unsigned)((CAND_SPLIT_CAP + BLOCK_W32 / 2 - 1) / (BLOCK_W32 / 2) < Gp
+                                           ? (CAND_SPLIT_CAP + BLOCK_W32 / 2 - 1) / (BLOCK_W32 / 2)
+                                           : Gp);
+        if (d == 128)
+          hipLaunchKernelGGL((k_label_gauss_mfma_w32<128, true, true>), dim3(gx, CAND_SPLIT_NG), dim3(BLOCK_W32), lh, s,
+                             x, n, per_block, packed, hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged,
+                             CAND_SPLIT_NG, CAND_SPLIT_CAP, cst);
+        else
+          hipLaunchKernelGGL((k_label_gauss_mfma_w32<64, true, true>), dim3(gx, CAND_SPLIT_NG), dim3(BLOCK_W32), lh, s,
+                             x, n, per_block, packed, hi, lo, K, t, seed, z, hist, tot, flagged, cand, n_flagged,
+                             CAND_SPLIT_NG, CAND_SPLIT_CAP, cst);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_cands_merge, dim3(CAND_SPLIT_CAP / 256), dim3(256), 0, s, n_flagged, CAND_SPLIT_NG,
+                           CAND_SPLIT_CAP, cst, BF16X3_TOL_REL, K, per_block, t, seed, flagged, z, hist, tot, cand);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
       if (d == 128) {
         if (cands)
           DPMM_MFMA_W32(128, true, true);
