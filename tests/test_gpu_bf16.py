@@ -112,12 +112,15 @@ def _iso_params(K, d, seed, mean_scale):
 
 
 @pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
-@pytest.mark.parametrize("d,K,n,scale", [(32, 24, 6000, 0.65), (64, 16, 4000, 0.5), (128, 12, 2000, 0.38)])
+@pytest.mark.parametrize("d,K,n,scale", [(32, 24, 6000, 0.65), (64, 16, 4000, 0.5), (128, 12, 2000, 0.38),
+                                         (64, 16, 36000, 0.5)])
 def test_bf16_deferred_candidate_lists(precision, d, K, n, scale):
     """Overlapping mixtures: deferred points carry the clusters that can still
     win (at most 8) or, when more lie in the window, fall back to all K.  The
     oracle's FP64 scores show that both kinds occur here; every label must
-    still meet the FP32 comparison rule."""
+    still meet the FP32 comparison rule.  At d = 64, 128 the candidate pass
+    splits the clusters over groups while at most 32 768 points are deferred
+    and runs in one piece beyond; the n = 36 000 case defers more than that."""
     import torch
     from oracle import rng
     from paper_2204_08988_amd.sampler import Sampler
@@ -130,6 +133,8 @@ def test_bf16_deferred_candidate_lists(precision, d, K, n, scale):
     window = (lc > lc.max(axis=1, keepdims=True) - (rng.GUMBEL_MAX - rng.GUMBEL_MIN)).sum(axis=1)
     assert np.any((window >= 2) & (window <= 6)), np.bincount(window)
     assert np.any(window > 8), np.bincount(window)
+    if n > 32768:  # a second cluster within the window forces a deferral
+        assert int((window >= 2).sum()) > 32768, int((window >= 2).sum())
     S = Sampler("gaussian", d, K + 2, 2.0, seed, m=np.zeros(d), psi=np.eye(d), precision=precision)
     S.set_params(params.log_pi, params.log_pisub, pu.comp_array(params))
     xt = torch.from_numpy(x).cuda()
