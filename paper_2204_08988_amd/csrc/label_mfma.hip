@@ -688,6 +688,7 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
   constexpr int MT = TT::MT, KS = TT::KS, NF = MT * KS * 64, NT = TT::NT;
   constexpr int RB = D / 8 + 1;  // LDS row stride in 16-byte units
   constexpr int TILES = PTS / 32;
+  constexpr int UC_T2 = TILES / 2;  // first tile read from the second base
   constexpr int NW = BLOCK_CS / 64;
   constexpr int P4 = D / 4;       // float4 pieces of a row
   constexpr int RPI = 64 / P4;    // rows per wave and staging pass
@@ -762,6 +763,8 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
     Top2U st[TILES / 2];
 #pragma unroll
     for (int j = 0; j < TILES / 2; ++j) st[j].init();
+    typedef __attribute__((address_space(3))) const bf16x8 lds_bf16x8;
+    lds_bf16x8* xr_lo = (lds_bf16x8*)(xb + col * RB + half);
     for (int k = wave; k < K; k += NW) {
       const int ku = __builtin_amdgcn_readfirstlane(k);
       bf16x8 a[NT];
@@ -786,9 +789,18 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
         }
       }
       const float4 kc = cst[ku];
+      float qa;  // the lane's half of the squared norms of the even tile of a pair
+      // a second base for the second half of the tiles, opaque to the compiler,
+      // so that every B-operand read takes its offset as an immediate (at most
+      // 16 bits) instead of an address add of its own
+      lds_bf16x8* xr_hi;
 #pragma unroll
       for (int t = 0; t < TILES; ++t) {
-        const bf16x8* xr = xb + (t * 32 + col) * RB + half;
+        if (t == UC_T2) {
+          xr_hi = xr_lo + UC_T2 * 32 * RB;
+          asm volatile("" : "+v"(xr_hi));
+        }
+        lds_bf16x8* xr = (t < UC_T2 ? xr_lo + t * 32 * RB : xr_hi + (t - UC_T2) * 32 * RB);
         bf16x8 b[KS];
         float q0 = 0.0f, q1 = 0.0f, q2 = 0.0f, q3 = 0.0f;
         f32x16 acc;
@@ -817,24 +829,24 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
           q2 = fmaf(acc[e + 2], acc[e + 2], q2);
           q3 = fmaf(acc[e + 3], acc[e + 3], q3);
         }
-        float qm = (q0 + q1) + (q2 + q3);
-        {
-          const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(qm), __float_as_uint(qm), false, false);
-          qm = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+        // the lane's half of the squared norm of point t * 32 + col
+        const float qh = (q0 + q1) + (q2 + q3);
+        if ((t & 1) == 0) {
+          qa = qh;
+        } else {
+          // tiles t - 1 and t together: one swap of the upper half of the first
+          // tile's partial sums with the lower half of the second's leaves the
+          // full norm of tile t - 1 in lanes 0-31 and of tile t in lanes 32-63,
+          // so each half takes the bounds of its own tile's points only
+          const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(qa), __float_as_uint(qh), false, false);
+          const float qm = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+          const float sq = __builtin_amdgcn_sqrtf(qm);
+          const float e = fmaf(UC_EPSS, sq, fmaf(kc.y, rxs[(t - 1) * 32 + lane], kc.z));
+          const float sp = sq + e, sm = sq - e;
+          const float lo = fmaf(-0.5f * sp, sp, kc.x);
+          const float up = sm > 0.0f ? fmaf(-0.5f * sm, sm, kc.x) : kc.x;
+          st[t >> 1].push_bounds(lo, up, k);
         }
-        const float sq = __builtin_amdgcn_sqrtf(qm);
-        const float e = fmaf(UC_EPSS, sq, fmaf(kc.y, rxs[t * 32 + col], kc.z));
-        const float sp = sq + e, sm = sq - e;
-        const float lo = fmaf(-0.5f * sp, sp, kc.x);
-        const float up = sm > 0.0f ? fmaf(-0.5f * sm, sm, kc.x) : kc.x;
-        Top2U& sj = st[t >> 1];
-        Top2U nx = sj;
-        nx.push_bounds(lo, up, k);
-        const bool own = (t & 1) == half;
-        sj.u1 = own ? nx.u1 : sj.u1;
-        sj.u2 = own ? nx.u2 : sj.u2;
-        sj.lo_max = own ? nx.lo_max : sj.lo_max;
-        sj.k1 = own ? nx.k1 : sj.k1;
         __builtin_amdgcn_sched_barrier(0);
       }
     }
