@@ -707,11 +707,15 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int half = lane >> 5, col = lane & 31;
   const int sub = lane / P4, part = lane % P4;
-  const float4 c4 = *reinterpret_cast<const float4*>(centre + 4 * part);
   const long long begin = (long long)blockIdx.x * per_block;
   const long long end = begin + per_block < n ? begin + per_block : n;
   for (long long chunk = begin; chunk < end; chunk += PTS) {
     const int rows = end - chunk < PTS ? (int)(end - chunk) : PTS;
+    // the lane's slice of the centre, read again each step (an L2 hit) rather
+    // than held in registers across the cluster loop
+    const float* cp = centre + 4 * part;
+    asm volatile("" : "+v"(cp));
+    const float4 c4 = *reinterpret_cast<const float4*>(cp);
     __syncthreads();  // the previous step's merge is done with the rows' space
     // the wave's rows: x' = x - c rounded to BF16, and ||x'|| (rows past the end
     // are zero), sixteen loads in flight per batch
