@@ -47,7 +47,7 @@ PEAK_BF16_MFMA = 2.5e15    # dense BF16 matrix-core peak
 PEAK_FP32_MFMA = 157.3e12  # dense FP32 matrix-core peak
 PEAK_FP64_MFMA = 78.6e12   # dense FP64 matrix-core peak
 HEADLINE = "gauss_d128"
-HEADLINE_KERNEL = "k_label_gauss_mfma_uc<128, 512>"
+HEADLINE_KERNEL = "k_label_gauss_mfma_uc<128, 512, 8>"
 # HBM bytes per launch of the headline kernel at the headline workload (N = 1e7,
 # d = 128, K = 100) from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the
 # factors being what a 1 GiB device copy reads on the same counters (FETCH_SIZE

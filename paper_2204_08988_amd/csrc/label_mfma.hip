@@ -625,8 +625,6 @@ __global__ __launch_bounds__(BLOCK_W32) void k_label_gauss_mfma_w32(const float*
   }
 }
 
-constexpr int BLOCK_CS = 512;  // threads of k_label_gauss_mfma_uc: 8 waves, two per SIMD
-constexpr int CS_PTS = 256;    // points per workgroup step: 8 tiles of 32
 
 // Two partial top-2 states over disjoint cluster sets combined: the same state
 // as one sequential pass over both (maximum bounds, the smallest cluster index
@@ -661,11 +659,12 @@ constexpr float UC_GAMMA2 = 1.0f / 16384.0f;
 constexpr float UC_EPSS = 1.0f / 65536.0f;
 
 // Main pass for d = 64, 128 in BF16, cluster-stationary and uncentred: the
-// workgroup's rows, PTS per step (512: with the counters of up to 4096 clusters
-// they fit in LDS; 256 otherwise), are centred once per step on the common centre c,
+// workgroup's NWAVE waves (eight, or four with two workgroups per CU) take PTS
+// rows per step (512 with eight waves while they and the counters fit in LDS,
+// else 256), centred once per step on the common centre c,
 // rounded to BF16 and stored in LDS (rows padded by 16 bytes, so that the
 // sixteen-byte reads of 32 rows fall on distinct banks), with each row's norm
-// ||x'||.  Each of the eight waves takes every eighth cluster and holds its
+// ||x'||.  Each wave takes every NWAVE-th cluster and holds its
 // whitener fragments (non-zero tiles only) and its offset beta = -W (mu - c),
 // in the accumulator layout, in registers while it sweeps the step's 32-point
 // tiles: a row block's accumulators start at beta (the matrix cores add it),
@@ -676,8 +675,8 @@ constexpr float UC_EPSS = 1.0f / 65536.0f;
 // FP32 draw, so the labels are those of the FP32 draw.
 // The partial top-2 states of the waves are merged through LDS at the end of
 // the step (top2_merge).
-template <int D, int PTS>
-__global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float* __restrict__ x, long long n,
+template <int D, int PTS, int NWAVE>
+__global__ __launch_bounds__(64 * NWAVE, 8 / NWAVE) void k_label_gauss_mfma_uc(const float* __restrict__ x, long long n,
                                                                      long long per_block,
                                                                      const bf16x8* __restrict__ whi,
                                                                      const float* __restrict__ wbias, int K, int k_max,
@@ -689,12 +688,12 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
   constexpr int RB = D / 8 + 1;  // LDS row stride in 16-byte units
   constexpr int TILES = PTS / 32;
   constexpr int UC_T2 = TILES / 2;  // first tile read from the second base
-  constexpr int NW = BLOCK_CS / 64;
+  constexpr int NW = NWAVE, BLK = 64 * NWAVE;
   constexpr int P4 = D / 4;       // float4 pieces of a row
   constexpr int RPI = 64 / P4;    // rows per wave and staging pass
   constexpr int WROWS = PTS / NW;  // rows staged per wave
   constexpr int ITER = WROWS / RPI;  // staging passes for the wave's rows
-  static_assert(D % 64 == 0 && PTS % (32 * NW) == 0 && PTS <= BLOCK_CS, "step, row copies");
+  static_assert(D % 64 == 0 && PTS % (32 * NW) == 0 && PTS <= BLK, "step, row copies");
   static_assert(NW * PTS * 4 * sizeof(float) <= PTS * RB * 16, "partial states alias the rows");
   typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -703,7 +702,7 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
   int* h = reinterpret_cast<int*>(rxs + PTS);                  // [K] counters
   const float4* cst = reinterpret_cast<const float4*>(wbias + (size_t)k_max * D);  // (c_k, (g + g2) ||W||_F, g2 ||W||_F ||mu - c||, 0)
   const float* centre = wbias + (size_t)k_max * (D + 4);
-  for (int k = threadIdx.x; k < K; k += BLOCK_CS) h[k] = 0;
+  for (int k = threadIdx.x; k < K; k += BLK) h[k] = 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int half = lane >> 5, col = lane & 31;
   const int sub = lane / P4, part = lane % P4;
@@ -878,7 +877,7 @@ __global__ __launch_bounds__(BLOCK_CS, 1) void k_label_gauss_mfma_uc(const float
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < K; k += BLOCK_CS) {
+  for (int k = threadIdx.x; k < K; k += BLK) {
     hist[(size_t)blockIdx.x * K + k] = h[k];
     if (h[k]) atomicAdd(&tot[k], h[k]);
   }
@@ -1403,10 +1402,11 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
   if (e != hipSuccess) return e;
   static bool attr_set = false;
   if (!attr_set) {  // d = 32 and the uncentred kernels: more than 64 KB of dynamic LDS (160 KB per CU)
-    const void* fns[7] = {(const void*)k_label_gauss_mfma32<true, false>, (const void*)k_label_gauss_mfma32<false, false>,
-                          (const void*)k_label_gauss_mfma32<true, true>, (const void*)k_label_gauss_mfma_uc<128, 256>,
-                          (const void*)k_label_gauss_mfma_uc<64, 256>, (const void*)k_label_gauss_mfma_uc<128, 512>,
-                          (const void*)k_label_gauss_mfma_uc<64, 512>};
+    const void* fns[8] = {(const void*)k_label_gauss_mfma32<true, false>, (const void*)k_label_gauss_mfma32<false, false>,
+                          (const void*)k_label_gauss_mfma32<true, true>,
+                          (const void*)k_label_gauss_mfma_uc<64, 256, 4>, (const void*)k_label_gauss_mfma_uc<128, 512, 8>,
+                          (const void*)k_label_gauss_mfma_uc<64, 512, 8>, (const void*)k_label_gauss_mfma_uc<128, 256, 8>,
+                          (const void*)k_label_gauss_mfma_uc<64, 256, 8>};
     for (const void* f : fns) {
       e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       if (e != hipSuccess) return e;
@@ -1422,24 +1422,31 @@ hipError_t launch_label_gauss_mfma(int d, bool x3, const float* x, long long n, 
     // time stamps, for timing it alone without extra queue packets)
     hipEvent_t e0 = cands ? nullptr : ev_main0, e1 = cands ? nullptr : ev_main1;
     if ((d == 64 || d == 128) && !cands && !x3 && wbias) {
-      // BF16 main pass, uncentred: the rows centred once on the common centre, 512 per
-      // step while they and the counters fit in LDS (fewer fragment fetches and merges
-      // per point), else 256
-      const bool big = label_uc_lds(d, K, 512) <= (size_t)160 * 1024;
-      const size_t luc = label_uc_lds(d, K, big ? 512 : 256);
-#define DPMM_UC(DD, PP)                                                                                       \
-  hipExtLaunchKernelGGL((k_label_gauss_mfma_uc<DD, PP>), dim3(Gp), dim3(BLOCK_CS), luc, s, e0, e1, 0, x, n, \
+      // BF16 main pass, uncentred: the rows centred once on the common centre.  At
+      // d = 64, two workgroups of four waves per CU (256 rows per step each) while
+      // both fit in LDS, so that one copies its rows while the other runs its
+      // matrix-core work; at d = 128 (and for larger K at d = 64) one workgroup of
+      // eight waves, 512 rows per step while they and the counters fit in LDS
+      // (fewer fragment fetches and merges per point), else 256
+      const size_t l256 = label_uc_lds(d, K, 256), l512 = label_uc_lds(d, K, 512);
+      const bool two = d == 64 && 2 * l256 <= (size_t)160 * 1024;
+      const bool big = !two && l512 <= (size_t)160 * 1024;
+      const size_t luc = big ? l512 : l256;
+#define DPMM_UC(DD, PP, NWV)                                                                                     \
+  hipExtLaunchKernelGGL((k_label_gauss_mfma_uc<DD, PP, NWV>), dim3(Gp), dim3(64 * NWV), luc, s, e0, e1, 0, x, n, \
                         per_block, hi, wbias, K, k_max, z, hist, tot, flagged, n_flagged)
       if (d == 128) {
         if (big)
-          DPMM_UC(128, 512);
+          DPMM_UC(128, 512, 8);
         else
-          DPMM_UC(128, 256);
+          DPMM_UC(128, 256, 8);
       } else {
-        if (big)
-          DPMM_UC(64, 512);
+        if (two)
+          DPMM_UC(64, 256, 4);
+        else if (big)
+          DPMM_UC(64, 512, 8);
         else
-          DPMM_UC(64, 256);
+          DPMM_UC(64, 256, 8);
       }
 #undef DPMM_UC
     } else if (d == 64 || d == 128) {
